@@ -1,0 +1,447 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics, not by the oracle itself.
+
+Each test names the passage or the closed form that fixes the expected value. Independent routes are
+numpy/scipy dense linear algebra, closed-form Poisson eigenpairs, brute-force structure checks and the
+golden fixtures under tests/golden/.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from workloads import CSR, poisson2d, poisson3d, random_csr, tridiag1d, varcoef3d, convdiff3d
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------------------------- SpMV
+def test_spmv_matches_dense_product(oracle_lib):
+    O = oracle_lib
+    for seed in range(3):
+        A = random_csr(40, 6, seed)
+        x = np.random.default_rng(seed).standard_normal(A.n)
+        np.testing.assert_allclose(O.spmv(A, x), A.to_dense() @ x, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("N", [5, 9])
+def test_spmv_poisson_eigenvectors_2d_3d(oracle_lib, N):
+    """A v = lambda v for v_jk = sin(j pi x/(N+1)) sin(k pi y/(N+1)), lambda = 4 - 2cos - 2cos (3-D: 6 - sum)."""
+    O = oracle_lib
+    g = np.arange(1, N + 1) / (N + 1)
+    A2 = poisson2d(N)
+    for (j, k) in [(1, 1), (2, 3), (N, 1)]:
+        v = np.outer(np.sin(k * np.pi * g), np.sin(j * np.pi * g)).ravel()  # x fastest
+        lam = 4 - 2 * np.cos(j * np.pi / (N + 1)) - 2 * np.cos(k * np.pi / (N + 1))
+        np.testing.assert_allclose(O.spmv(A2, v), lam * v, atol=1e-13)
+    A3 = poisson3d(N)
+    for (i, j, k) in [(1, 1, 1), (2, 1, 3)]:
+        v = np.einsum("a,b,c->abc", np.sin(k * np.pi * g), np.sin(j * np.pi * g), np.sin(i * np.pi * g)).ravel()
+        lam = 6 - 2 * sum(np.cos(q * np.pi / (N + 1)) for q in (i, j, k))
+        np.testing.assert_allclose(O.spmv(A3, v), lam * v, atol=1e-13)
+
+
+# ------------------------------------------------------------------------------------ strength / RS
+def test_strength_threshold_hand_example(oracle_lib):
+    """Section 5.1: j strongly influences i iff |a_ij| >= theta max_{k != i} |a_ik| (theta = 0.25)."""
+    d = np.array([[4.0, -1.0, -0.25, 0.0], [-0.2, 3.0, -1.0, -0.1], [0.0, -0.5, 2.0, 0.0], [0.0, 0.0, 0.0, 1.0]])
+    srp, sci = oracle_lib.strength(CSR.from_dense(d), 0.25)
+    rows = [list(sci[srp[i]:srp[i + 1]]) for i in range(4)]
+    # row 0: max 1 -> thr 0.25: both -1 and -0.25 qualify (ties count); row 1: max 1 -> thr .25: only col 2
+    # row 2: only neighbour col 1; row 3: no off-diagonal -> empty
+    assert rows == [[1, 2], [2], [1], []]
+
+
+def test_rs_tridiag_golden(oracle_lib):
+    g = json.load(open(os.path.join(GOLD, "tridiag7_rs.json")))
+    A = tridiag1d(7)
+    assert list(oracle_lib.coarsen(A, g["theta"])) == g["cf"]
+    H = oracle_lib.Hierarchy(A, theta=g["theta"], max_levels=2, max_coarse=1)
+    L0 = H.level(0)
+    np.testing.assert_array_equal(L0.cf, g["cf"])
+    np.testing.assert_array_equal(L0.P.toarray(), np.array(g["P"]))
+    np.testing.assert_array_equal(H.level(1).A.to_dense(), np.array(g["Ac"]))
+
+
+def _strong_sets(O, A, theta):
+    srp, sci = O.strength(A, theta)
+    return [set(sci[srp[i]:srp[i + 1]].tolist()) for i in range(A.n)]
+
+
+@pytest.mark.parametrize("maker", [lambda: poisson2d(12), lambda: poisson3d(6), lambda: varcoef3d(6, 1.0, 2, 100.0)[0],
+                                   lambda: random_csr(60, 5, 7, symmetric=True)])
+def test_rs_first_pass_structure(oracle_lib, maker):
+    """Brute-force structural facts of the RS first pass: every F point with a strong connection has a
+    strong C point; for a symmetric strength graph no C point strongly depends on another C point."""
+    O = oracle_lib
+    A = maker()
+    cf = O.coarsen(A, 0.25)
+    S = _strong_sets(O, A, 0.25)
+    ST = [set() for _ in range(A.n)]
+    for i, s in enumerate(S):
+        for j in s:
+            ST[j].add(i)
+    for i in range(A.n):
+        if cf[i] == 0 and (S[i] or ST[i]):
+            assert any(cf[j] == 1 for j in S[i]), i
+    if all(S[i] == {j for j in range(A.n) if i in S[j]} for i in range(A.n)):
+        for i in range(A.n):
+            if cf[i] == 1:
+                assert not any(cf[j] == 1 for j in S[i])
+    assert 0 < cf.sum() < A.n
+
+
+def test_rs_tie_break_smallest_index(oracle_lib):
+    """Equal measures: the smallest index is chosen first. On a 5-point 3x3 grid the corner 0 and the
+    centre 4 both have measure... the centre has the largest measure (4) and becomes C first."""
+    cf = oracle_lib.coarsen(poisson2d(3), 0.25)
+    # centre 4 (measure 4) -> C, its 4 neighbours F; the corners then have measure 4 (two F neighbours):
+    # all corners become C in index order.
+    assert list(cf) == [1, 0, 1, 0, 1, 0, 1, 0, 1]
+
+
+# ------------------------------------------------------------------------------ interpolation / RAP
+@pytest.mark.parametrize("maker", [lambda: poisson2d(16), lambda: poisson3d(8), lambda: varcoef3d(8, 1.0, 2, 100.0)[0]])
+def test_classical_interp_preserves_constants(oracle_lib, maker):
+    """Classical interpolation reproduces constants on every row whose A-row sums to zero (the identity
+    sum_j w_ij = 1 follows from den_k = sum_{l in C_i} a_kl and a zero row sum)."""
+    A = maker()
+    H = oracle_lib.Hierarchy(A, max_levels=2, max_coarse=1)
+    L0 = H.level(0)
+    rowsum = A.to_scipy() @ np.ones(A.n)
+    p1 = L0.P @ np.ones(L0.P.shape[1])
+    zero_rows = np.abs(rowsum) < 1e-12 * np.abs(A.vals).max()
+    assert zero_rows.sum() > 0
+    np.testing.assert_allclose(p1[zero_rows], 1.0, atol=1e-14)
+    assert np.all(p1[L0.cf == 1] == 1.0)
+
+
+@pytest.mark.parametrize("maker", [lambda: poisson2d(20), lambda: poisson3d(8), lambda: convdiff3d(7, 3)[0]])
+def test_galerkin_matches_scipy_triple_product(oracle_lib, maker):
+    """Section 5: A_{k+1} = P^T A_k P. Compared with scipy's sparse triple product on every level."""
+    A = maker()
+    H = oracle_lib.Hierarchy(A, max_coarse=10)
+    assert H.levels >= 3
+    for l in range(H.levels - 1):
+        L = H.level(l)
+        Ac = H.level(l + 1).A
+        ref = (L.P.T @ L.A.to_scipy() @ L.P).toarray()
+        got = Ac.to_dense()
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+        # stored pattern covers every nonzero of the product
+        assert np.all((ref != 0) <= (got != 0) | (np.abs(ref) < 1e-15))
+
+
+def test_galerkin_symmetric_for_symmetric_A(oracle_lib):
+    H = oracle_lib.Hierarchy(varcoef3d(8, 1.0, 2, 100.0)[0], max_coarse=10)
+    for l in range(1, H.levels):
+        d = H.level(l).A.to_dense()
+        assert np.abs(d - d.T).max() <= 1e-14 * np.abs(d).max()
+
+
+# ------------------------------------------------------------------------------------------ ILU(0)
+def _split_ilu(A, w):
+    n = A.n
+    L, U = np.eye(n), np.zeros((n, n))
+    for i in range(n):
+        for k in range(A.rowptr[i], A.rowptr[i + 1]):
+            j = A.colind[k]
+            (L if j < i else U)[i, j] = w[k]
+    return L, U
+
+
+@pytest.mark.parametrize("maker", [lambda: poisson2d(8), lambda: convdiff3d(4, 3)[0], lambda: random_csr(30, 5, 3)])
+def test_ilu0_reproduces_A_on_pattern(oracle_lib, maker):
+    """ILU(0) (Chow & Saad, Section 1): (LU)_ij = a_ij at every position of A's pattern."""
+    A = maker()
+    L, U = _split_ilu(A, oracle_lib.ilu0(A))
+    LU = L @ U
+    Ad = A.to_dense()
+    mask = Ad != 0
+    np.testing.assert_allclose(LU[mask], Ad[mask], atol=1e-13)
+
+
+def test_ilu0_tridiagonal_is_exact_lu(oracle_lib):
+    """No fill for tridiagonal A, so ILU(0) = LU and the ILU-direct sweep solves A x = b exactly."""
+    A = tridiag1d(25)
+    L, U = _split_ilu(A, oracle_lib.ilu0(A))
+    np.testing.assert_allclose(L @ U, A.to_dense(), atol=1e-14)
+    b = np.random.default_rng(4).standard_normal(A.n)
+    x = oracle_lib.smooth(A, oracle_lib.ILU_DIRECT, 1, b, np.zeros(A.n))
+    np.testing.assert_allclose(x, np.linalg.solve(A.to_dense(), b), rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------------------- smoothers
+def _depth(A, lower=True):
+    """Number of levels of the dependency DAG of the strict triangle (brute force)."""
+    lev = np.zeros(A.n, int)
+    order = range(A.n) if lower else range(A.n - 1, -1, -1)
+    for i in order:
+        cols = A.colind[A.rowptr[i]:A.rowptr[i + 1]]
+        dep = cols[cols < i] if lower else cols[cols > i]
+        lev[i] = 1 + (lev[dep].max() if dep.size else 0)
+    return lev.max()
+
+
+def test_pgs_zero_inner_sweeps_is_jacobi(oracle_lib):
+    """Section 5.2: with zero inner sweeps polynomial GS is the Jacobi iteration x + D^{-1}(b - A x)."""
+    A = varcoef3d(5, 1.0, 2, 100.0)[0]
+    rng = np.random.default_rng(1)
+    b, x = rng.standard_normal(A.n), rng.standard_normal(A.n)
+    Ad = A.to_dense()
+    ref = x + (b - Ad @ x) / np.diag(Ad)
+    for kind in (oracle_lib.PGS_FWD, oracle_lib.PGS_BWD):
+        np.testing.assert_allclose(oracle_lib.smooth(A, kind, 1, b, x), ref, rtol=1e-13)
+
+
+def test_gs_direct_is_triangular_solve(oracle_lib):
+    A = convdiff3d(4, 3)[0]
+    rng = np.random.default_rng(2)
+    b, x = rng.standard_normal(A.n), rng.standard_normal(A.n)
+    Ad = A.to_dense()
+    r = b - Ad @ x
+    fw = x + sla.solve_triangular(np.tril(Ad), r, lower=True)
+    bw = x + sla.solve_triangular(np.triu(Ad), r, lower=False)
+    np.testing.assert_allclose(oracle_lib.smooth(A, oracle_lib.GS_FWD, 1, b, x), fw, rtol=1e-12)
+    np.testing.assert_allclose(oracle_lib.smooth(A, oracle_lib.GS_BWD, 1, b, x), bw, rtol=1e-12)
+
+
+def test_neumann_terminates_at_dependency_depth(oracle_lib):
+    """Section 5.2 / 5.3.2: D^{-1}L and U_s are nilpotent, so the Neumann series is finite. For the
+    8x8 5-point grid the lower triangle has depth 15: 15 terms reproduce the forward substitution,
+    14 terms do not. The same holds for ILU(0) with its L_s and U_s."""
+    O = oracle_lib
+    A = poisson2d(8)
+    assert _depth(A, True) == 15 and _depth(A, False) == 15
+    rng = np.random.default_rng(3)
+    b, x = rng.standard_normal(A.n), np.zeros(A.n)
+    ref = O.smooth(A, O.GS_FWD, 1, b, x)
+    e15 = np.abs(O.smooth(A, O.PGS_FWD, 15, b, x) - ref).max() / np.abs(ref).max()
+    e14 = np.abs(O.smooth(A, O.PGS_FWD, 14, b, x) - ref).max() / np.abs(ref).max()
+    assert e15 < 1e-15 and e14 > 1e-9
+    refb = O.smooth(A, O.GS_BWD, 1, b, x)
+    assert np.abs(O.smooth(A, O.PGS_BWD, 15, b, x) - refb).max() < 1e-15 * np.abs(refb).max() * 10
+    ref_ilu = O.smooth(A, O.ILU_DIRECT, 1, b, x)
+    e_ilu15 = np.abs(O.smooth(A, O.ILU_NEUMANN, 15, b, x) - ref_ilu).max() / np.abs(ref_ilu).max()
+    e_ilu14 = np.abs(O.smooth(A, O.ILU_NEUMANN, 14, b, x) - ref_ilu).max() / np.abs(ref_ilu).max()
+    assert e_ilu15 < 1e-14 and e_ilu14 > 1e-12
+
+
+def test_ilu_neumann_is_truncated_series(oracle_lib):
+    """Section 5.3.2, eq. (Neumann): with L = I + L_s and U = D_U (I + U_s) the t-term sweep applies
+    (sum_{j<t} (-U_s)^j) D_U^{-1} (sum_{j<t} (-L_s)^j) to the residual. Checked with dense powers."""
+    O = oracle_lib
+    A = convdiff3d(4, 3)[0]
+    L, U = _split_ilu(A, O.ilu0(A))
+    Ls = L - np.eye(A.n)
+    Du = np.diag(np.diag(U))
+    Us = np.linalg.solve(Du, U) - np.eye(A.n)
+    rng = np.random.default_rng(5)
+    b, x = rng.standard_normal(A.n), rng.standard_normal(A.n)
+    r = b - A.to_dense() @ x
+    for t in (1, 2, 3, 5):
+        NL = sum(np.linalg.matrix_power(-Ls, j) for j in range(t))
+        NU = sum(np.linalg.matrix_power(-Us, j) for j in range(t))
+        ref = x + NU @ np.linalg.solve(Du, NL @ r)
+        np.testing.assert_allclose(O.smooth(A, O.ILU_NEUMANN, t, b, x), ref, rtol=1e-11, atol=1e-12)
+
+
+def test_numerical_nilpotence_of_ilu_factor(oracle_lib):
+    """Section 5.3.2 (Figure 1's phenomenon): ||U_s^p|| decays long before p = n and is exactly zero
+    at p = dependency depth, on the ILU(0) factor of a nonsymmetric 3-D operator."""
+    A = convdiff3d(5, 3)[0]
+    L, U = _split_ilu(A, oracle_lib.ilu0(A))
+    Us = np.triu(U / np.diag(U)[:, None], 1)  # D_U^{-1} U = I + U_s
+    d = _depth(A, False)
+    assert d < A.n
+    norms = [np.linalg.norm(np.linalg.matrix_power(Us, p), 2) for p in (1, 4, 8, d - 1, d)]
+    assert norms[0] < 1.0 and norms[2] < 0.05 * norms[0]
+    assert norms[-2] > 0 and norms[-1] == 0.0
+
+
+# ----------------------------------------------------------------------------------------- V-cycle
+def test_one_level_hierarchy_is_direct_solve(oracle_lib):
+    A = poisson2d(6)  # n = 36 <= max_coarse
+    H = oracle_lib.Hierarchy(A)
+    assert H.levels == 1
+    b = np.random.default_rng(0).standard_normal(A.n)
+    np.testing.assert_allclose(H.vcycle(b), np.linalg.solve(A.to_dense(), b), rtol=1e-13)
+
+
+def _dense_op(f, n):
+    return np.stack([f(e) for e in np.eye(n)], axis=1)
+
+
+@pytest.mark.parametrize("smoother,tri", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_vcycle_linear_and_symmetric(oracle_lib, smoother, tri):
+    """The V-cycle is a linear operator; with forward pre- and backward post-smoothing (PGS) or the
+    ILU sweep (symmetric A gives U = D L^T) it is symmetric for symmetric A."""
+    O = oracle_lib
+    A = poisson2d(10)
+    H = O.Hierarchy(A, ilu_levels=1)
+    assert H.levels >= 2
+    M = _dense_op(lambda e: H.vcycle(e, smoother=smoother, tri_mode=tri, t=3), A.n)
+    assert np.abs(M - M.T).max() <= 1e-13 * np.abs(M).max()
+    rng = np.random.default_rng(6)
+    u, v = rng.standard_normal(A.n), rng.standard_normal(A.n)
+    lhs = H.vcycle(2.0 * u - 3.0 * v, smoother=smoother, tri_mode=tri, t=3)
+    np.testing.assert_allclose(lhs, M @ (2.0 * u - 3.0 * v), rtol=1e-12, atol=1e-14)
+
+
+def test_two_grid_coarse_correction_is_galerkin_projection(oracle_lib):
+    """With no smoothing and an exact coarse solve the V-cycle on two levels is P (P^T A P)^{-1} P^T,
+    the Galerkin coarse-grid correction (Section 5)."""
+    O = oracle_lib
+    A = poisson2d(9)
+    H = O.Hierarchy(A, max_levels=2)
+    assert H.levels == 2
+    P = H.level(0).P.toarray()
+    Ad = A.to_dense()
+    ref = P @ np.linalg.solve(P.T @ Ad @ P, P.T)
+    M = _dense_op(lambda e: H.vcycle(e, nu1=0, nu2=0), A.n)
+    np.testing.assert_allclose(M, ref, atol=1e-13)
+
+
+# ------------------------------------------------------------------------------------------- GMRES
+def test_gmres_terminates_at_number_of_distinct_eigenvalues(oracle_lib):
+    """4x4 5-point Poisson has 9 distinct eigenvalues: unpreconditioned GMRES with a generic b reaches
+    the exact solution at iteration 9 and not before (Krylov space dimension), for both T forms."""
+    O = oracle_lib
+    A = poisson2d(4)
+    b = np.random.default_rng(0).standard_normal(A.n)
+    H = O.Hierarchy(A)
+    for T in (O.T_NEUMANN, O.T_DIRECT):
+        r = H.solve(b, tol=1e-13, restart=16, precond=O.PRECOND_NONE, gmres_T=T)
+        assert r["iters"] == 9 and r["status"] == 0
+        assert r["hist"][7] > 1e-6 and r["hist"][8] < 1e-13
+        assert r["relres_true"] < 1e-13
+
+
+def test_gmres_ritz_values_are_poisson_eigenvalues(oracle_lib):
+    O = oracle_lib
+    A = poisson2d(4)
+    b = np.random.default_rng(1).standard_normal(A.n)
+    r = O.Hierarchy(A).solve(b, tol=1e-14, restart=16, max_iters=9, precond=O.PRECOND_NONE, capture=True)
+    k = r["k"]
+    assert k == 9
+    ritz = np.sort(np.linalg.eigvals(r["H"][:k, :k]).real)
+    c = np.cos(np.arange(1, 5) * np.pi / 5)
+    lam = np.unique(np.round(4 - 2 * (c[:, None] + c[None, :]), 12))
+    np.testing.assert_allclose(ritz, np.sort(lam), atol=1e-10)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5])
+def test_gmres_iterate_is_krylov_least_squares(oracle_lib, k):
+    """GMRES (Section 1): x_k minimises ||b - A x|| over x0 + K_k(A, r0). Dense least squares on an
+    orthonormal basis of the Krylov space (numpy QR + lstsq) gives the same x_k."""
+    O = oracle_lib
+    A = random_csr(30, 5, 11)
+    Ad = A.to_dense()
+    rng = np.random.default_rng(2)
+    b, x0 = rng.standard_normal(A.n), rng.standard_normal(A.n)
+    res = O.Hierarchy(A, max_coarse=100).solve(b, x0, tol=1e-15, restart=30, max_iters=k,
+                                               precond=O.PRECOND_NONE)
+    r0 = b - Ad @ x0
+    K = np.stack([np.linalg.matrix_power(Ad, j) @ r0 for j in range(k)], axis=1)
+    Q, _ = np.linalg.qr(K)
+    y, *_ = np.linalg.lstsq(Ad @ Q, r0, rcond=None)
+    np.testing.assert_allclose(res["x"], x0 + Q @ y, rtol=1e-10, atol=1e-12)
+
+
+def test_flexible_gmres_with_fixed_amg_minimises_over_MK(oracle_lib):
+    """Right preconditioning with a fixed linear M: x_k minimises the residual over x0 + M K_k(A M, r0)."""
+    O = oracle_lib
+    A = poisson2d(9)
+    Ad = A.to_dense()
+    H = O.Hierarchy(A)
+    M = _dense_op(lambda e: H.vcycle(e, t=2), A.n)
+    b = np.random.default_rng(3).standard_normal(A.n)
+    for k in (1, 2, 3):
+        res = H.solve(b, tol=1e-15, restart=30, max_iters=k, t=2)
+        AM = Ad @ M
+        K = np.stack([np.linalg.matrix_power(AM, j) @ b for j in range(k)], axis=1)
+        Q, _ = np.linalg.qr(K)
+        y, *_ = np.linalg.lstsq(AM @ Q, b, rcond=None)
+        np.testing.assert_allclose(res["x"], M @ Q @ y, rtol=1e-9, atol=1e-11)
+
+
+@pytest.mark.parametrize("T", [0, 1])
+@pytest.mark.parametrize("tol", [1e-8, 1e-12])
+def test_arnoldi_relation_and_orthogonality(oracle_lib, T, tol):
+    """A Z_k = V_{k+1} H_{k+1,k} (flexible Arnoldi, Section 1) to rounding, and the loss of orthogonality
+    ||I - V^T V||_F stays below O(eps) kappa(B), B = [r0, A Z_k] with unit columns (Section 3)."""
+    O = oracle_lib
+    A, b, _ = __import__("workloads").config_system("c1")
+    r = O.Hierarchy(A).solve(b, tol=tol, restart=30, t=2, gmres_T=T, capture=True)
+    V, Z, Hh, k = r["V"], r["Z"], r["H"], r["k"]
+    AZ = A.to_scipy() @ Z
+    assert np.linalg.norm(AZ - V @ Hh) / np.linalg.norm(AZ) < 1e-14
+    B = np.column_stack([b, AZ])
+    sv = np.linalg.svd(B / np.linalg.norm(B, axis=0), compute_uv=False)
+    kappa = sv[0] / sv[-1]
+    loo = O.loss_orth(V)
+    assert loo <= 10.0 * np.finfo(float).eps * kappa
+    # Section 3: beta(x) kappa(B) = O(1) -- the orthogonality loss grows as the backward error falls
+    assert r["nrbe"] * kappa < 100.0
+
+
+def test_T_neumann_matches_T_direct(oracle_lib):
+    """Section 1/3: the truncated T = I - L gives the same convergence history as (I + L)^{-1}."""
+    O = oracle_lib
+    A, b, _ = __import__("workloads").config_system("c1")
+    H = O.Hierarchy(A)
+    a = H.solve(b, t=2, gmres_T=O.T_NEUMANN)
+    c = H.solve(b, t=2, gmres_T=O.T_DIRECT)
+    assert a["iters"] == c["iters"]
+    np.testing.assert_allclose(a["hist"], c["hist"], rtol=1e-8)
+    np.testing.assert_allclose(a["x"], c["x"], rtol=1e-12, atol=1e-12 * np.abs(c["x"]).max())
+    assert a["relres_true"] <= 1e-8
+
+
+def test_lucky_breakdown_on_eigenvector(oracle_lib):
+    O = oracle_lib
+    N = 7
+    g = np.arange(1, N + 1) / (N + 1)
+    v = np.outer(np.sin(2 * np.pi * g), np.sin(np.pi * g)).ravel()
+    lam = 4 - 2 * np.cos(np.pi / (N + 1)) - 2 * np.cos(2 * np.pi / (N + 1))
+    r = O.Hierarchy(poisson2d(N)).solve(v, tol=1e-12, precond=O.PRECOND_NONE)
+    assert r["status"] == 0 and r["iters"] == 1
+    np.testing.assert_allclose(r["x"], v / lam, rtol=1e-13)
+
+
+def test_restarted_gmres_and_nrbe(oracle_lib):
+    """Small restart still converges on the true residual; the NRBE of Section 3 is
+    ||r|| / (||b|| + ||A||_inf ||x||)."""
+    O = oracle_lib
+    A, b, _ = __import__("workloads").config_system("c1")
+    r = O.Hierarchy(A).solve(b, tol=1e-8, restart=3, t=2)
+    assert r["status"] == 0 and r["cycles"] > 1 and r["relres_true"] <= 1e-8
+    Ad = A.to_dense()
+    res = np.linalg.norm(b - Ad @ r["x"])
+    nrbe = res / (np.linalg.norm(b) + np.abs(Ad).sum(1).max() * np.linalg.norm(r["x"]))
+    assert abs(r["nrbe"] - nrbe) <= 1e-6 * nrbe
+    assert abs(r["relres_true"] - res / np.linalg.norm(b)) <= 1e-6 * r["relres_true"]
+
+
+def test_not_converged_status_and_error_paths(oracle_lib):
+    O = oracle_lib
+    A, b, _ = __import__("workloads").config_system("c1")
+    H = O.Hierarchy(A)
+    r = H.solve(b, tol=1e-20, max_iters=2, t=2)
+    assert r["status"] == O.NOT_CONVERGED and r["iters"] == 2
+    bad = b.copy()
+    bad[3] = np.nan
+    with pytest.raises(O.OracleFailure) as e:
+        H.solve(bad)
+    assert e.value.code == O.E_NONFINITE
+    d = A.to_dense()
+    d[5, 5] = 0.0
+    with pytest.raises(O.OracleFailure) as e:
+        O.Hierarchy(CSR.from_dense(d))
+    assert e.value.code == O.E_ZERO_PIVOT
+    Z = CSR(A.n, A.rowptr, A.colind.copy(), A.vals)
+    Z.colind[[0, 1]] = Z.colind[[1, 0]]
+    with pytest.raises(O.OracleFailure) as e:
+        O.Hierarchy(Z)
+    assert e.value.code == O.E_INVALID
