@@ -1,0 +1,147 @@
+#!/usr/bin/env python3
+"""Benchmark: ms per low-sync GMRES + classical-AMG solve to relative residual 1e-8.
+
+Default workload: 3-D Poisson 7-point, 128^3 (2 097 152 rows, 14 581 760 nnz), b ~ N(0, 1) seed 1,
+RS-AMG theta = 0.25, hybrid V-cycle with ILU(0) on the finest level (3 Neumann terms per triangular
+solve) and polynomial GS elsewhere, GMRES(30), tol 1e-8, FP64. One step = one whole solve from x0 = 0
+with the matrix, hierarchy and right-hand side already resident in HBM; setup is timed separately.
+
+Prints one JSON line (rank 0). Only one GPU is used: --gpus above 1 exits with a message.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4n", "c4r", "c4rcm"])
+    ap.add_argument("--N", type=int, default=None)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--smoother", default="ilu0", choices=["ilu0", "pgs"])
+    ap.add_argument("--tri", default="neumann", choices=["neumann", "direct"])
+    ap.add_argument("--terms", type=int, default=3)
+    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--gmres-T", default="neumann", choices=["neumann", "direct"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--compare", action="store_true", help="also time the direct-triangular and FP32 variants")
+    return ap.parse_args()
+
+
+def _time_solves(torch, H, bt, xt, kw, steps, warmup):
+    for _ in range(warmup):
+        xt.zero_()
+        H.solve(bt, xt, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for _ in range(steps):
+        xt.zero_()
+        stats.append(H.solve(bt, xt, **kw))
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps, stats
+
+
+def cpu_baseline(A, b, kw, gpu_iters):
+    """The oracle (single-threaded FP64 C++) on the same system: setup excluded, full solve timed."""
+    import oracle
+
+    t0 = time.perf_counter()
+    G = oracle.Hierarchy(A)
+    setup_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    r = G.solve(b, tol=kw["tol"], restart=kw["restart"], smoother=kw["smoother"], tri_mode=kw["tri_mode"],
+                t=kw["inner_terms"], gmres_T=kw["gmres_T"])
+    solve_s = time.perf_counter() - t0
+    return {"value": solve_s * 1e3, "unit": "ms", "cores": 1, "kind": "oracle",
+            "sample": f"one full oracle solve of the same system ({r['iters']} iterations, relres "
+                      f"{r['relres_true']:.1e}; GPU {gpu_iters}); oracle setup {setup_s:.1f} s excluded"}
+
+
+def main():
+    args = _args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the solve phase is not sharded in this build "
+              "(see the multi-GPU design notes); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2112_14681_amd as namg
+    from workloads import config_system
+
+    A, b, meta = config_system(args.config, args.N)
+    prec = namg.FP64 if args.precision == "fp64" else namg.FP32_PRECOND
+    t0 = time.perf_counter()
+    H = namg.Hierarchy(A, device=0, precision=prec, ilu_levels=1)
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    info = H.info()
+    kw = dict(tol=1e-8, restart=args.restart, smoother=namg.SMOOTH_ILU0 if args.smoother == "ilu0" else namg.SMOOTH_PGS,
+              tri_mode=namg.TRI_NEUMANN if args.tri == "neumann" else namg.TRI_DIRECT, inner_terms=args.terms,
+              gmres_T=namg.T_NEUMANN if args.gmres_T == "neumann" else namg.T_DIRECT)
+    dev = torch.device("cuda:0")
+    bt = torch.from_numpy(b).to(dev)
+    xt = torch.zeros_like(bt)
+    ms, stats = _time_solves(torch, H, bt, xt, kw, args.steps, args.warmup)
+    st = stats[-1]
+    if st["status"] != namg.OK or st["relres_true"] > 1e-8:
+        print(f"solve did not reach 1e-8: {st}", file=sys.stderr)
+        sys.exit(1)
+    gbs = st["alg_bytes"] / (ms * 1e-3) / 1e9
+
+    out = {
+        "metric": "ms per GMRES+AMG solve to rel-res 1e-8 at 128^3; HBM GB/s; served p99",
+        "value": round(ms, 4),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == namg.FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{meta['name']}: " + {
+                "c1": "2-D Poisson 5-point", "c2": "3-D Poisson 7-point", "c3": "3-D -div(k grad p) lognormal k, z 1:100",
+                "c4n": "3-D upwind conv-diff natural order", "c4r": "3-D upwind conv-diff random order",
+                "c4rcm": "3-D upwind conv-diff RCM order"}[meta["name"]] + f" N={meta['N']}",
+            "n": A.n, "nnz": A.nnz, "smoother": args.smoother, "tri_mode": args.tri, "inner_terms": args.terms,
+            "restart": args.restart, "gmres_T": args.gmres_T, "precision": args.precision, "tol": 1e-8,
+            "levels": info["levels"], "op_complexity": round(info["op_complexity"], 3),
+        },
+        "iters": st["iters"],
+        "relres": st["relres_true"],
+        "setup_ms": round(setup_ms, 1),
+        "alg_GBps": round(gbs, 1),
+    }
+
+    if args.compare:
+        cmp = {}
+        for name, extra, prec2 in (("direct_tri", dict(tri_mode=namg.TRI_DIRECT), prec),
+                                   ("fp32_precond", {}, namg.FP32_PRECOND), ("fp64", {}, namg.FP64)):
+            H2 = H if prec2 == prec else namg.Hierarchy(A, device=0, precision=prec2, ilu_levels=1)
+            kw2 = dict(kw, **extra)
+            ms2, st2 = _time_solves(torch, H2, bt, xt, kw2, max(1, args.steps // 2), 1)
+            cmp[name] = {"ms": round(ms2, 3), "iters": st2[-1]["iters"], "relres": st2[-1]["relres_true"]}
+        out["compare"] = cmp
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(A, b, kw, st["iters"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

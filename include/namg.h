@@ -1,0 +1,154 @@
+/* namg — Neumann-series GMRES + classical AMG for AMD Instinct MI355X (gfx950).
+ *
+ * The solve phase of "Neumann Series in GMRES and Algebraic Multigrid Smoothers" (Thomas, Carr,
+ * Mullowney, Li, Swirydowicz; arXiv 2112.14681): Ax = b (Section 1) is solved by a restarted,
+ * right-preconditioned flexible low-synchronization MGS-GMRES whose correction matrix is applied as
+ * T = I - L (Section 4, Algorithm 1), preconditioned by one classical Ruge-Stueben AMG V-cycle
+ * (Section 5) whose polynomial Gauss-Seidel (Section 5.2) and ILU(0) (Section 5.3) smoothers replace
+ * the sparse triangular solves by truncated Neumann-series / Jacobi inner iterations.
+ *
+ * Conventions for every call:
+ *  - Return value: NAMG_OK (0), NAMG_NOT_CONVERGED (1, a status: outputs are valid) or a negative
+ *    error code. On error, namg_last_error() returns a message for the calling thread.
+ *  - Host arrays are borrowed for the duration of the call and copied where kept.
+ *  - "_dev" pointers are device pointers on the hierarchy's device, contiguous, float64, caller-owned.
+ *  - stream is a hipStream_t (NULL = the default stream). A hierarchy is used by one stream at a time.
+ *  - CSR: 0-based, int32 row pointers and column indices, columns strictly ascending per row, the
+ *    diagonal present and nonzero, finite values, nnz < 2^31.
+ */
+#ifndef NAMG_H
+#define NAMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NAMG_OK 0
+#define NAMG_NOT_CONVERGED 1
+#define NAMG_PENDING 2
+#define NAMG_E_INVALID (-1)    /* bad argument or malformed CSR */
+#define NAMG_E_ZERO_PIVOT (-2) /* zero diagonal in A, a coarse operator, an ILU pivot or the coarse LU */
+#define NAMG_E_NONFINITE (-3)  /* NaN/Inf in the input or during the solve */
+#define NAMG_E_NOMEM (-4)      /* device allocation failed (nothing leaked) */
+#define NAMG_E_HIP (-5)        /* other HIP runtime error */
+#define NAMG_E_BUDGET (-6)     /* serving: request larger than the whole HBM budget */
+#define NAMG_E_NODEVICE (-7)   /* the hierarchy was set up host-only (device = -1) */
+
+enum { NAMG_FP64 = 0, NAMG_FP32_PRECOND = 1 };        /* namg_setup_params.precision */
+enum { NAMG_SMOOTH_PGS = 0, NAMG_SMOOTH_ILU0 = 1 };   /* namg_solve_params.smoother  */
+enum { NAMG_TRI_NEUMANN = 0, NAMG_TRI_DIRECT = 1 };   /* namg_solve_params.tri_mode  */
+enum { NAMG_T_NEUMANN = 0, NAMG_T_DIRECT = 1 };       /* namg_solve_params.gmres_T   */
+
+#define NAMG_MAX_LEVELS 32
+#define NAMG_MAX_RESTART 128
+
+typedef struct namg_hier namg_hier; /* opaque; owns the host copy and all device memory of one hierarchy */
+
+typedef struct {
+  double theta;   /* strength threshold, 0 < theta <= 1 (Section 5.1); default 0.25 */
+  int max_levels; /* <= NAMG_MAX_LEVELS; default 25 */
+  int max_coarse; /* stop coarsening at <= max_coarse rows (dense direct solve); default 50 */
+  int precision;  /* NAMG_FP64, or NAMG_FP32_PRECOND: hierarchy values and the V-cycle in FP32,
+                     Arnoldi / Hessenberg / true residual in FP64 */
+  int ilu_levels; /* ILU(0) factors on levels l < ilu_levels (1 = finest only, the hybrid V-cycle of
+                     Section 6.2; -1 = every level but the coarsest; 0 = none); default 1 */
+  int device;     /* HIP device ordinal; -1 = host-only setup (for inspection; solves are refused) */
+} namg_setup_params;
+
+typedef struct {
+  double tol;      /* stop when ||b - A x||_2 / ||b||_2 <= tol (Section 4, eq. relres); default 1e-8 */
+  int restart;     /* m, 1..NAMG_MAX_RESTART; default 30 */
+  int max_iters;   /* total Arnoldi iterations over all cycles; default 1000 */
+  int smoother;    /* NAMG_SMOOTH_PGS (all levels) or NAMG_SMOOTH_ILU0 (ILU on the levels that carry
+                      factors, polynomial GS elsewhere) */
+  int tri_mode;    /* NAMG_TRI_NEUMANN (Jacobi/Neumann inner iterations) or NAMG_TRI_DIRECT (the
+                      direct-triangular comparators: GS and ILU by substitution) */
+  int inner_terms; /* t >= 1: Neumann terms per triangular solve (t = 1: Jacobi; t - 1 products with the
+                      strict triangle); default 2 */
+  int gmres_T;     /* NAMG_T_NEUMANN: T = I - L (Section 4); NAMG_T_DIRECT: T = (I + L)^{-1} */
+  int pre_sweeps, post_sweeps; /* smoothing sweeps nu1, nu2 per level; default 1, 1 */
+} namg_solve_params;
+
+typedef struct {
+  int status, iters, cycles, precond_apps;
+  double relres_true; /* ||b - A x|| / ||b|| recomputed in FP64 at the end */
+  double relres_est;  /* the last Givens estimate |g_{i+1}| / ||b|| */
+  double nrbe;        /* ||r|| / (||b|| + ||A||_inf ||x||), Section 3 */
+  double ms_total;    /* wall time of the call on the stream (hipEvent) */
+  double alg_bytes;   /* algorithmic HBM bytes moved by the solve's kernels */
+} namg_solve_stats;
+
+typedef struct {
+  int levels;
+  int32_t n[NAMG_MAX_LEVELS];
+  int64_t nnz[NAMG_MAX_LEVELS];
+  double op_complexity, grid_complexity;
+  int64_t device_bytes; /* device memory held by the hierarchy and its Krylov workspace */
+} namg_hierarchy_info;
+
+void namg_default_setup_params(namg_setup_params *p);
+void namg_default_solve_params(namg_solve_params *p);
+
+/* AMG setup (Section 5 and 5.1): per level the strength graph S (|a_ij| >= theta max_{k!=i}|a_ik|), the
+ * Ruge-Stueben first-pass C/F splitting, classical interpolation P, R = P^T and the Galerkin operator
+ * A_{l+1} = P^T A_l P; ILU(0) of the first ilu_levels levels (Section 5.3); the coarsest level's dense
+ * inverse. Runs on the host in FP64, then uploads (FP64 or FP32 copies) to p->device.
+ * rowptr/colind/vals: host CSR of A (n rows). *out receives a new handle (release with namg_destroy).
+ * Errors: NAMG_E_INVALID, NAMG_E_NONFINITE, NAMG_E_ZERO_PIVOT, NAMG_E_NOMEM, NAMG_E_HIP. */
+int namg_setup(int32_t n, const int32_t *rowptr, const int32_t *colind, const double *vals,
+               const namg_setup_params *p, namg_hier **out);
+
+/* Solve A x = b (Section 1) with low-synchronization flexible GMRES(m) (Section 4, Algorithm 1) and one
+ * V-cycle per preconditioner application. b_dev: n float64 (read). x_dev: n float64, the initial guess on
+ * entry and the solution on return (overwritten in place). st: optional statistics.
+ * Returns NAMG_OK or NAMG_NOT_CONVERGED (x holds the last iterate), or an error. */
+int namg_solve(namg_hier *h, const double *b_dev, double *x_dev, const namg_solve_params *p, void *stream,
+               namg_solve_stats *st);
+
+/* One preconditioner application x = M^{-1} b: one V-cycle with zero initial guess (Section 5).
+ * b_dev, x_dev: n float64 device vectors (x written). */
+int namg_vcycle(namg_hier *h, const double *b_dev, double *x_dev, const namg_solve_params *p, void *stream);
+
+/* One hot-path operator of level l on float64 device vectors of that level's sizes, for component
+ * checks and profiling. In FP32_PRECOND mode the operator runs in FP32 on converted copies.
+ *   NAMG_OP_SPMV          out = A_l in1                                   (n_l -> n_l)
+ *   NAMG_OP_RESIDUAL      out = in2 - A_l in1                             (in1 = x, in2 = b)
+ *   NAMG_OP_SMOOTH_PRE    out = in1 + M_pre^{-1}(in2 - A_l in1)           (one pre-smoothing sweep)
+ *   NAMG_OP_SMOOTH_POST   out = in1 + M_post^{-1}(in2 - A_l in1)          (one post-smoothing sweep)
+ *   NAMG_OP_RESTRICT      out = R_l in1                                   (n_l -> n_{l+1})
+ *   NAMG_OP_PROLONG       out = in2 + P_l in1                             (in1: n_{l+1}, in2/out: n_l)
+ *   NAMG_OP_COARSE        out = A_L^{-1} in1 on the coarsest level L
+ *   NAMG_OP_SPMV64        out = A_0 in1 with the FP64 operator the GMRES uses (level must be 0)
+ * The smoother kind, triangular mode and t come from p. */
+enum {
+  NAMG_OP_SPMV = 0, NAMG_OP_RESIDUAL = 1, NAMG_OP_SMOOTH_PRE = 2, NAMG_OP_SMOOTH_POST = 3,
+  NAMG_OP_RESTRICT = 4, NAMG_OP_PROLONG = 5, NAMG_OP_COARSE = 6, NAMG_OP_SPMV64 = 7
+};
+int namg_apply(namg_hier *h, int level, int op, const namg_solve_params *p, const double *in1_dev,
+               const double *in2_dev, double *out_dev, void *stream);
+
+/* Hierarchy shape: levels, n_l, nnz(A_l), operator and grid complexity, device bytes. */
+int namg_hier_info(const namg_hier *h, namg_hierarchy_info *out);
+
+/* Sizes of level l: n_l, nnz(A_l), nnz(P_l) (0 on the coarsest level) and n_{l+1}. */
+int namg_level_sizes(const namg_hier *h, int level, int32_t *n, int64_t *nnzA, int64_t *nnzP,
+                     int32_t *ncoarse);
+
+/* Host copies of level l for inspection: C/F markers (1 = C, 0 = F; n_l entries, not on the coarsest
+ * level), A_l in CSR, P_l in CSR (n_l x n_{l+1}). Any pointer may be NULL; sizes from namg_level_sizes. */
+int namg_export_level(const namg_hier *h, int level, int8_t *cf, int32_t *A_rowptr, int32_t *A_colind,
+                      double *A_vals, int32_t *P_rowptr, int32_t *P_colind, double *P_vals);
+
+/* Release the hierarchy and all its device memory. NULL is ignored. */
+void namg_destroy(namg_hier *h);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *namg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NAMG_H */

@@ -1,0 +1,209 @@
+"""namg: Neumann-series GMRES + classical AMG on AMD Instinct MI355X (gfx950).
+
+Thin ctypes binding of libnamg.so (include/namg.h). It only marshals arguments: every step of the solve
+runs in the library's HIP kernels. Device vectors are torch tensors (float64, contiguous, on the
+hierarchy's device); the stream is torch's current stream. There is no CPU fallback: if the compiled
+library is missing, importing the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnamg.so")
+
+OK, NOT_CONVERGED, PENDING = 0, 1, 2
+E_INVALID, E_ZERO_PIVOT, E_NONFINITE, E_NOMEM, E_HIP, E_BUDGET, E_NODEVICE = -1, -2, -3, -4, -5, -6, -7
+FP64, FP32_PRECOND = 0, 1
+SMOOTH_PGS, SMOOTH_ILU0 = 0, 1
+TRI_NEUMANN, TRI_DIRECT = 0, 1
+T_NEUMANN, T_DIRECT = 0, 1
+OP_SPMV, OP_RESIDUAL, OP_SMOOTH_PRE, OP_SMOOTH_POST, OP_RESTRICT, OP_PROLONG, OP_COARSE, OP_SPMV64 = range(8)
+MAX_LEVELS = 32
+
+EXPORTED = (
+    "namg_default_setup_params", "namg_default_solve_params", "namg_setup", "namg_solve", "namg_vcycle",
+    "namg_apply", "namg_hier_info", "namg_level_sizes", "namg_export_level", "namg_destroy",
+    "namg_last_error",
+)
+
+
+class SetupParams(C.Structure):
+    _fields_ = [("theta", C.c_double), ("max_levels", C.c_int), ("max_coarse", C.c_int), ("precision", C.c_int),
+                ("ilu_levels", C.c_int), ("device", C.c_int)]
+
+
+class SolveParams(C.Structure):
+    _fields_ = [("tol", C.c_double), ("restart", C.c_int), ("max_iters", C.c_int), ("smoother", C.c_int),
+                ("tri_mode", C.c_int), ("inner_terms", C.c_int), ("gmres_T", C.c_int), ("pre_sweeps", C.c_int),
+                ("post_sweeps", C.c_int)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("status", C.c_int), ("iters", C.c_int), ("cycles", C.c_int), ("precond_apps", C.c_int),
+                ("relres_true", C.c_double), ("relres_est", C.c_double), ("nrbe", C.c_double),
+                ("ms_total", C.c_double), ("alg_bytes", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class HierInfo(C.Structure):
+    _fields_ = [("levels", C.c_int), ("n", C.c_int32 * MAX_LEVELS), ("nnz", C.c_int64 * MAX_LEVELS),
+                ("op_complexity", C.c_double), ("grid_complexity", C.c_double), ("device_bytes", C.c_int64)]
+
+
+class NamgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"namg error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`"
+                          " (the HIP library is required; there is no CPU fallback)")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32p, f64p, i8p, i64p = C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_int8), \
+        C.POINTER(C.c_int64)
+    lib.namg_setup.argtypes = [C.c_int32, i32p, i32p, f64p, C.POINTER(SetupParams), C.POINTER(vp)]
+    lib.namg_solve.argtypes = [vp, vp, vp, C.POINTER(SolveParams), vp, C.POINTER(SolveStats)]
+    lib.namg_vcycle.argtypes = [vp, vp, vp, C.POINTER(SolveParams), vp]
+    lib.namg_apply.argtypes = [vp, C.c_int, C.c_int, C.POINTER(SolveParams), vp, vp, vp, vp]
+    lib.namg_hier_info.argtypes = [vp, C.POINTER(HierInfo)]
+    lib.namg_level_sizes.argtypes = [vp, C.c_int, i32p, i64p, i64p, i32p]
+    lib.namg_export_level.argtypes = [vp, C.c_int, i8p, i32p, i32p, f64p, i32p, i32p, f64p]
+    lib.namg_destroy.argtypes = [vp]
+    lib.namg_destroy.restype = None
+    lib.namg_last_error.restype = C.c_char_p
+    lib.namg_default_setup_params.argtypes = [C.POINTER(SetupParams)]
+    lib.namg_default_solve_params.argtypes = [C.POINTER(SolveParams)]
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(code):
+    if code < 0:
+        raise NamgError(code, _lib.namg_last_error().decode())
+    return code
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype)) if a is not None else None
+
+
+def setup_params(**kw) -> SetupParams:
+    p = SetupParams()
+    _lib.namg_default_setup_params(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def solve_params(**kw) -> SolveParams:
+    p = SolveParams()
+    _lib.namg_default_solve_params(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _dev_ptr(t, n=None):
+    """Device pointer of a contiguous float64 torch tensor (checked)."""
+    if t is None:
+        return None
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 device tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} entries, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(stream)
+    import torch
+
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Hierarchy:
+    """An AMG hierarchy set up from a host CSR matrix (namg_setup); owns its device memory."""
+
+    def __init__(self, A, **params):
+        rp = np.ascontiguousarray(A.rowptr, dtype=np.int32)
+        ci = np.ascontiguousarray(A.colind, dtype=np.int32)
+        v = np.ascontiguousarray(A.vals, dtype=np.float64)
+        self.n = int(A.n)
+        self.params = setup_params(**params)
+        h = C.c_void_p()
+        _check(_lib.namg_setup(self.n, _ptr(rp, C.c_int32), _ptr(ci, C.c_int32), _ptr(v, C.c_double),
+                               C.byref(self.params), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            _lib.namg_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        inf = HierInfo()
+        _check(_lib.namg_hier_info(self.h, C.byref(inf)))
+        L = inf.levels
+        return {"levels": L, "n": list(inf.n[:L]), "nnz": list(inf.nnz[:L]), "op_complexity": inf.op_complexity,
+                "grid_complexity": inf.grid_complexity, "device_bytes": inf.device_bytes}
+
+    def level_sizes(self, level):
+        n, na, npp, nc = C.c_int32(), C.c_int64(), C.c_int64(), C.c_int32()
+        _check(_lib.namg_level_sizes(self.h, level, C.byref(n), C.byref(na), C.byref(npp), C.byref(nc)))
+        return n.value, na.value, npp.value, nc.value
+
+    def export_level(self, level):
+        """Host copies (cf, A as CSR triple, P as CSR triple or None)."""
+        n, na, npp, nc = self.level_sizes(level)
+        last = npp == 0 and nc == 0
+        cf = None if last else np.zeros(n, np.int8)
+        Arp, Aci, Av = np.zeros(n + 1, np.int32), np.zeros(na, np.int32), np.zeros(na)
+        Prp = Pci = Pv = None
+        if not last:
+            Prp, Pci, Pv = np.zeros(n + 1, np.int32), np.zeros(npp, np.int32), np.zeros(npp)
+        _check(_lib.namg_export_level(self.h, level, _ptr(cf, C.c_int8), _ptr(Arp, C.c_int32), _ptr(Aci, C.c_int32),
+                                      _ptr(Av, C.c_double), _ptr(Prp, C.c_int32), _ptr(Pci, C.c_int32),
+                                      _ptr(Pv, C.c_double)))
+        return {"cf": cf, "A": (Arp, Aci, Av), "P": None if last else (Prp, Pci, Pv, nc)}
+
+    def solve(self, b, x, stream=None, **params) -> dict:
+        """namg_solve on device tensors b (read) and x (initial guess in, solution out)."""
+        p = solve_params(**params)
+        st = SolveStats()
+        code = _check(_lib.namg_solve(self.h, _dev_ptr(b, self.n), _dev_ptr(x, self.n), C.byref(p), _stream(stream),
+                                      C.byref(st)))
+        out = st.as_dict()
+        out["status"] = code
+        return out
+
+    def vcycle(self, b, x, stream=None, **params):
+        p = solve_params(**params)
+        _check(_lib.namg_vcycle(self.h, _dev_ptr(b, self.n), _dev_ptr(x, self.n), C.byref(p), _stream(stream)))
+
+    def apply(self, level, op, in1, in2, out, stream=None, **params):
+        p = solve_params(**params)
+        _check(_lib.namg_apply(self.h, level, op, C.byref(p), _dev_ptr(in1), _dev_ptr(in2), _dev_ptr(out),
+                               _stream(stream)))

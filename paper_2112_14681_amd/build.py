@@ -1,0 +1,44 @@
+"""Build libnamg.so in-tree for gfx950.
+
+Host setup (setup_host.cpp) is compiled with g++ -ffp-contract=off so that coarse operators are summed in
+their documented order; the HIP translation unit is compiled with hipcc for gfx950 with packed-FP32
+instructions disabled.
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(os.path.dirname(HERE), "_build")
+LIB = os.path.join(HERE, "libnamg.so")
+ARCH = os.environ.get("NAMG_OFFLOAD_ARCH", "gfx950")
+
+
+def _run(cmd):
+    print("+", " ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+
+
+def build(verbose: bool = True) -> str:
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    os.makedirs(BUILD, exist_ok=True)
+    host_o = os.path.join(BUILD, "setup_host.o")
+    dev_o = os.path.join(BUILD, "solver.o")
+    _run(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fPIC", "-Wall", "-c",
+          os.path.join(CSRC, "setup_host.cpp"), "-o", host_o])
+    _run([hipcc, f"--offload-arch={ARCH}", "-std=c++17", "-O3", "-fPIC", "-Wall",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-c", os.path.join(CSRC, "solver.hip"), "-o", dev_o])
+    tmp = LIB + ".tmp"
+    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", host_o, dev_o, "-o", tmp])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build()
+    sys.exit(0)

@@ -1,0 +1,185 @@
+// Device-side containers of the namg library: owned device buffers, the SELL-64 sparse layout used by
+// every streaming kernel, CSR views for the level-scheduled direct comparators and the Krylov state.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/namg.h"
+#include "setup_host.hpp"
+
+namespace namg {
+
+struct HipError {
+  int code;
+  std::string msg;
+};
+
+inline void hip_check(hipError_t e, const char *what) {
+  if (e == hipSuccess) return;
+  if (e == hipErrorOutOfMemory) throw HipError{NAMG_E_NOMEM, std::string(what) + ": out of device memory"};
+  throw HipError{NAMG_E_HIP, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+// Counts the bytes every DevBuf of one hierarchy holds.
+struct MemCounter {
+  int64_t bytes = 0;
+};
+
+// One device allocation, freed by the destructor (so a failed setup leaks nothing).
+template <class T>
+class DevBuf {
+ public:
+  DevBuf() = default;
+  DevBuf(size_t n, MemCounter *mc) { alloc(n, mc); }
+  ~DevBuf() { release(); }
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  DevBuf(DevBuf &&o) noexcept { *this = std::move(o); }
+  DevBuf &operator=(DevBuf &&o) noexcept {
+    if (this != &o) {
+      release();
+      p_ = o.p_;
+      n_ = o.n_;
+      mc_ = o.mc_;
+      o.p_ = nullptr;
+      o.n_ = 0;
+      o.mc_ = nullptr;
+    }
+    return *this;
+  }
+  void alloc(size_t n, MemCounter *mc) {
+    release();
+    if (n == 0) n = 1;
+    hip_check(hipMalloc(&p_, n * sizeof(T)), "hipMalloc");
+    n_ = n;
+    mc_ = mc;
+    if (mc_) mc_->bytes += (int64_t)(n * sizeof(T));
+  }
+  void upload(const T *h, size_t n) {
+    if (n) hip_check(hipMemcpy(p_, h, n * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy H2D");
+  }
+  void release() {
+    if (p_) {
+      (void)hipFree(p_);
+      if (mc_) mc_->bytes -= (int64_t)(n_ * sizeof(T));
+    }
+    p_ = nullptr;
+    n_ = 0;
+  }
+  T *get() const { return p_; }
+  size_t size() const { return n_; }
+
+ private:
+  T *p_ = nullptr;
+  size_t n_ = 0;
+  MemCounter *mc_ = nullptr;
+};
+
+// SELL-C sparse layout with C = 64 (one wavefront): rows are cut into slices of 64 consecutive rows;
+// slice s stores its rows' entries column-major, entry k of every row of the slice at
+// val[sp[s] + 64*k + lane], padded with (column 0, value 0) up to the slice's longest row. Row order and
+// the order of entries within each row are those of the CSR input.
+constexpr int SELL_C = 64;
+
+template <class T>
+struct SellView {
+  const int32_t *sp = nullptr;
+  const int32_t *col = nullptr;
+  const T *val = nullptr;
+  int32_t nrows = 0;
+};
+
+template <class T>
+struct DSell {
+  int32_t nrows = 0, ncols = 0, nslices = 0;
+  int64_t nnz = 0, stored = 0;
+  DevBuf<int32_t> sp, col;
+  DevBuf<T> val;
+  SellView<T> view() const { return SellView<T>{sp.get(), col.get(), val.get(), nrows}; }
+
+  void build(const HostCsr &A, MemCounter *mc) {
+    nrows = A.nr;
+    ncols = A.nc;
+    nnz = A.nnz();
+    nslices = (nrows + SELL_C - 1) / SELL_C;
+    std::vector<int32_t> hsp(nslices + 1, 0);
+    for (int32_t s = 0; s < nslices; ++s) {
+      int32_t w = 0;
+      for (int32_t r = s * SELL_C; r < std::min(nrows, (s + 1) * SELL_C); ++r)
+        w = std::max(w, A.rp[r + 1] - A.rp[r]);
+      hsp[s + 1] = hsp[s] + w * SELL_C;
+    }
+    stored = hsp[nslices];
+    std::vector<int32_t> hcol(stored, 0);
+    std::vector<T> hval(stored, T(0));
+    for (int32_t s = 0; s < nslices; ++s)
+      for (int32_t lane = 0; lane < SELL_C; ++lane) {
+        const int32_t r = s * SELL_C + lane;
+        if (r >= nrows) break;
+        for (int32_t k = 0; k < A.rp[r + 1] - A.rp[r]; ++k) {
+          const int64_t d = hsp[s] + (int64_t)k * SELL_C + lane;
+          hcol[d] = A.ci[A.rp[r] + k];
+          hval[d] = (T)A.v[A.rp[r] + k];
+        }
+      }
+    sp.alloc(hsp.size(), mc);
+    sp.upload(hsp.data(), hsp.size());
+    col.alloc(hcol.size(), mc);
+    col.upload(hcol.data(), hcol.size());
+    val.alloc(hval.size(), mc);
+    val.upload(hval.data(), hval.size());
+  }
+};
+
+// CSR rows grouped by dependency level, for the level-scheduled direct triangular solves.
+template <class T>
+struct DTri {
+  int32_t n = 0;
+  DevBuf<int32_t> rp, ci, order;
+  DevBuf<T> val;
+  std::vector<int32_t> lev_ptr;  // host copy: rows order[lev_ptr[k] .. lev_ptr[k+1]) form level k
+  int64_t nnz = 0;
+
+  void build(const HostCsr &S, const LevelSchedule &sch, MemCounter *mc) {
+    n = S.nr;
+    nnz = S.nnz();
+    rp.alloc(S.rp.size(), mc);
+    rp.upload(S.rp.data(), S.rp.size());
+    ci.alloc(S.ci.size(), mc);
+    ci.upload(S.ci.data(), S.ci.size());
+    std::vector<T> hv(S.v.begin(), S.v.end());
+    val.alloc(hv.size(), mc);
+    val.upload(hv.data(), hv.size());
+    order.alloc(sch.order.size(), mc);
+    order.upload(sch.order.data(), sch.order.size());
+    lev_ptr = sch.ptr;
+  }
+};
+
+// Low-synchronization GMRES state kept on the device (FP64), written by the single-workgroup step
+// kernel and read by the projection and update kernels.
+constexpr int KS_MAXR = NAMG_MAX_RESTART;
+constexpr int KS_LD = KS_MAXR + 2;
+
+struct KState {
+  double beta;     // ||b||
+  double est;      // |g_{i+1}| / ||b|| after the latest column
+  double rho_inv;  // 1 / r_{i+1,i+1} of the current step
+  int32_t flag;    // 0 continue, 1 stop (converged / last column / breakdown), -1 non-finite
+  int32_t pad;
+  double s[KS_LD];      // projection coefficients of the current step
+  double rprev[KS_LD];  // projection coefficients of the previous step (top of the pending H column)
+  double g[KS_LD];      // rotated right-hand side
+  double cs[KS_LD], sn[KS_LD];
+  double zs[KS_LD];     // lagged normalisation factors of z_j, folded into y
+  double y[KS_LD];      // y_j * zs_j after the back-substitution
+  double H[KS_LD * KS_LD];  // rotated Hessenberg, column j at H[j * KS_LD + row]
+  double L[KS_LD * KS_LD];  // strictly lower L, row r at L[r * KS_LD + col]
+};
+
+}  // namespace namg

@@ -1,0 +1,495 @@
+// Host-side AMG setup (Section 5 and 5.1 of arXiv 2112.14681, plus ILU(0) of Section 5.3).
+//
+// Canonical arithmetic (so that two independent setups produce bit-identical coarse operators and
+// therefore identical C/F splittings on every level):
+//   * strength: thr_i = theta * max_{k != i} |a_ik| (one multiply); j is strong iff |a_ij| >= thr_i;
+//   * interpolation weights: den_k summed over the strong C set in ascending column order; the
+//     numerator starts at a_ij and adds (a_ik * a_kj) / den_k for strong F neighbours k in ascending
+//     order; the denominator starts at a_ii and adds the weak entries in ascending column order;
+//   * Galerkin product: AP row i accumulates a_ij * p_jJ for j ascending; A_c row I accumulates
+//     p_iI * ap_iJ for fine rows i ascending; every touched position is kept (no zero dropping).
+#include "setup_host.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "../../include/namg.h"
+
+namespace namg {
+
+namespace {
+
+[[noreturn]] void fail(int code, const std::string &msg) { throw SetupError{code, msg}; }
+
+double diagonal(const HostCsr &A, int32_t i) {
+  const int32_t *b = A.ci.data() + A.rp[i], *e = A.ci.data() + A.rp[i + 1];
+  const int32_t *p = std::lower_bound(b, e, i);
+  if (p == e || *p != i) fail(NAMG_E_ZERO_PIVOT, "missing diagonal in row " + std::to_string(i));
+  return A.v[A.rp[i] + (p - b)];
+}
+
+// ---- strength of connection: S in CSR form -------------------------------------------------------
+struct Graph {
+  std::vector<int32_t> rp, ci;
+};
+
+Graph strength_graph(const HostCsr &A, double theta) {
+  Graph S;
+  S.rp.assign(A.nr + 1, 0);
+  S.ci.reserve(A.ci.size());
+  for (int32_t i = 0; i < A.nr; ++i) {
+    double mx = 0.0;
+    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+      if (A.ci[k] != i) {
+        double a = std::fabs(A.v[k]);
+        if (a > mx) mx = a;
+      }
+    if (mx > 0.0) {
+      const double thr = theta * mx;
+      for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+        if (A.ci[k] != i && std::fabs(A.v[k]) >= thr) S.ci.push_back(A.ci[k]);
+    }
+    S.rp[i + 1] = (int32_t)S.ci.size();
+  }
+  return S;
+}
+
+Graph transpose_graph(const Graph &S, int32_t n) {
+  Graph T;
+  T.rp.assign(n + 1, 0);
+  for (int32_t j : S.ci) T.rp[j + 1]++;
+  for (int32_t i = 0; i < n; ++i) T.rp[i + 1] += T.rp[i];
+  T.ci.resize(S.ci.size());
+  std::vector<int32_t> fill(T.rp.begin(), T.rp.end() - 1);
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t k = S.rp[i]; k < S.rp[i + 1]; ++k) T.ci[fill[S.ci[k]]++] = i;
+  return T;
+}
+
+// ---- Ruge-Stueben first pass ------------------------------------------------------------------------
+// Max-measure selection with a segment tree over the point index: each leaf holds the measure of an
+// undecided point (-1 once decided); an inner node keeps the larger measure, the smaller index on ties,
+// so the root is always the point to colour next.
+class MeasureTree {
+ public:
+  explicit MeasureTree(int32_t n) : n_(n) {
+    size_ = 1;
+    while (size_ < std::max<int32_t>(n, 1)) size_ <<= 1;
+    val_.assign(2 * size_, -1);
+    idx_.assign(2 * size_, INT32_MAX);
+    for (int32_t i = 0; i < size_; ++i) idx_[size_ + i] = i;
+    for (int32_t p = size_ - 1; p >= 1; --p) pull(p);
+  }
+  void set(int32_t i, int32_t v) {
+    int32_t p = size_ + i;
+    val_[p] = v;
+    for (p >>= 1; p >= 1; p >>= 1) pull(p);
+  }
+  void add(int32_t i, int32_t d) { set(i, val_[size_ + i] + d); }
+  int32_t top_value() const { return val_[1]; }
+  int32_t top_index() const { return idx_[1]; }
+
+ private:
+  void pull(int32_t p) {
+    const int32_t l = 2 * p, r = 2 * p + 1;
+    if (val_[r] > val_[l]) {
+      val_[p] = val_[r];
+      idx_[p] = idx_[r];
+    } else {
+      val_[p] = val_[l];
+      idx_[p] = idx_[l];
+    }
+  }
+  int32_t n_, size_;
+  std::vector<int32_t> val_, idx_;
+};
+
+// C/F splitting (1 = C, 0 = F). Measure lambda_i = |S^T_i & U| + 2 |S^T_i & F|, maintained incrementally:
+// a point turning F adds 1 to every undecided point it depends on, a point turning C subtracts 1.
+std::vector<int8_t> rs_coarsen(const Graph &S, int32_t n) {
+  const Graph ST = transpose_graph(S, n);
+  enum : int8_t { UNDECIDED = -1, FPT = 0, CPT = 1 };
+  std::vector<int8_t> st(n, UNDECIDED);
+  MeasureTree tree(n);
+  for (int32_t i = 0; i < n; ++i) {
+    if (S.rp[i + 1] == S.rp[i] && ST.rp[i + 1] == ST.rp[i])
+      st[i] = FPT;
+    else
+      tree.set(i, ST.rp[i + 1] - ST.rp[i]);
+  }
+  std::vector<int32_t> fresh;
+  while (tree.top_value() >= 0) {
+    const int32_t i = tree.top_index();
+    st[i] = CPT;
+    tree.set(i, -1);
+    fresh.clear();
+    for (int32_t k = ST.rp[i]; k < ST.rp[i + 1]; ++k) {
+      const int32_t j = ST.ci[k];
+      if (st[j] == UNDECIDED) {
+        st[j] = FPT;
+        tree.set(j, -1);
+        fresh.push_back(j);
+      }
+    }
+    for (int32_t j : fresh)
+      for (int32_t k = S.rp[j]; k < S.rp[j + 1]; ++k)
+        if (st[S.ci[k]] == UNDECIDED) tree.add(S.ci[k], 1);
+    for (int32_t k = S.rp[i]; k < S.rp[i + 1]; ++k)
+      if (st[S.ci[k]] == UNDECIDED) tree.add(S.ci[k], -1);
+  }
+  return st;
+}
+
+// ---- classical interpolation -------------------------------------------------------------------------
+HostCsr classical_interpolation(const HostCsr &A, const Graph &S, const std::vector<int8_t> &cf) {
+  const int32_t n = A.nr;
+  std::vector<int32_t> cnum(n, -1);
+  int32_t nc = 0;
+  for (int32_t i = 0; i < n; ++i)
+    if (cf[i] == 1) cnum[i] = nc++;
+  HostCsr P;
+  P.nr = n;
+  P.nc = nc;
+  P.rp.assign(n + 1, 0);
+  // role[j] for the current row: 0 none, 1 strong C, 2 strong F, 3 strong F treated as weak
+  std::vector<int8_t> role(n, 0);
+  std::vector<double> num(n, 0.0), dens;
+  std::vector<int32_t> strongF;
+  for (int32_t i = 0; i < n; ++i) {
+    if (cf[i] == 1) {
+      P.ci.push_back(cnum[i]);
+      P.v.push_back(1.0);
+      P.rp[i + 1] = (int32_t)P.ci.size();
+      continue;
+    }
+    bool anyC = false;
+    strongF.clear();
+    for (int32_t k = S.rp[i]; k < S.rp[i + 1]; ++k) {
+      const int32_t j = S.ci[k];
+      if (cf[j] == 1) {
+        role[j] = 1;
+        anyC = true;
+      } else {
+        role[j] = 2;
+        strongF.push_back(j);
+      }
+    }
+    if (anyC) {
+      dens.assign(strongF.size(), 0.0);
+      for (size_t q = 0; q < strongF.size(); ++q) {
+        const int32_t k = strongF[q];
+        double s = 0.0;
+        for (int32_t p = A.rp[k]; p < A.rp[k + 1]; ++p)
+          if (role[A.ci[p]] == 1) s += A.v[p];
+        dens[q] = s;
+        if (s == 0.0) role[k] = 3;
+      }
+      double dd = 0.0;
+      for (int32_t p = A.rp[i]; p < A.rp[i + 1]; ++p) {
+        const int32_t j = A.ci[p];
+        if (j == i) dd = A.v[p];
+      }
+      for (int32_t p = A.rp[i]; p < A.rp[i + 1]; ++p) {
+        const int32_t j = A.ci[p];
+        if (j != i && (role[j] == 0 || role[j] == 3)) dd += A.v[p];
+      }
+      for (int32_t p = A.rp[i]; p < A.rp[i + 1]; ++p)
+        if (role[A.ci[p]] == 1) num[A.ci[p]] = A.v[p];
+      // strong F neighbours in ascending order; their rows distribute into the strong C set
+      std::vector<double> aik(strongF.size());
+      for (int32_t p = A.rp[i]; p < A.rp[i + 1]; ++p)
+        for (size_t q = 0; q < strongF.size(); ++q)
+          if (strongF[q] == A.ci[p]) aik[q] = A.v[p];
+      for (size_t q = 0; q < strongF.size(); ++q) {
+        if (dens[q] == 0.0) continue;
+        const int32_t k = strongF[q];
+        for (int32_t p = A.rp[k]; p < A.rp[k + 1]; ++p) {
+          const int32_t j = A.ci[p];
+          if (role[j] == 1) num[j] += (aik[q] * A.v[p]) / dens[q];
+        }
+      }
+      for (int32_t k = S.rp[i]; k < S.rp[i + 1]; ++k) {
+        const int32_t j = S.ci[k];
+        if (cf[j] == 1) {
+          P.ci.push_back(cnum[j]);
+          P.v.push_back(-num[j] / dd);
+        }
+      }
+    }
+    for (int32_t k = S.rp[i]; k < S.rp[i + 1]; ++k) role[S.ci[k]] = 0;
+    P.rp[i + 1] = (int32_t)P.ci.size();
+  }
+  return P;
+}
+
+HostCsr transpose_csr(const HostCsr &P) {
+  HostCsr R;
+  R.nr = P.nc;
+  R.nc = P.nr;
+  R.rp.assign(R.nr + 1, 0);
+  for (int32_t j : P.ci) R.rp[j + 1]++;
+  for (int32_t i = 0; i < R.nr; ++i) R.rp[i + 1] += R.rp[i];
+  R.ci.resize(P.ci.size());
+  R.v.resize(P.v.size());
+  std::vector<int32_t> fill(R.rp.begin(), R.rp.end() - 1);
+  for (int32_t i = 0; i < P.nr; ++i)
+    for (int32_t k = P.rp[i]; k < P.rp[i + 1]; ++k) {
+      const int32_t d = fill[P.ci[k]]++;
+      R.ci[d] = i;
+      R.v[d] = P.v[k];
+    }
+  return R;
+}
+
+// C = X * Y with a dense sparse accumulator; row i of C accumulates x_ij * y_jJ over the entries of row
+// i of X in stored order and, inside, over row j of Y in stored order. Columns of each row sorted.
+HostCsr spgemm(const HostCsr &X, const HostCsr &Y) {
+  HostCsr C;
+  C.nr = X.nr;
+  C.nc = Y.nc;
+  C.rp.assign(X.nr + 1, 0);
+  std::vector<int32_t> mark(Y.nc, -1), cols;
+  std::vector<double> acc(Y.nc, 0.0);
+  for (int32_t i = 0; i < X.nr; ++i) {
+    cols.clear();
+    for (int32_t k = X.rp[i]; k < X.rp[i + 1]; ++k) {
+      const int32_t j = X.ci[k];
+      const double x = X.v[k];
+      for (int32_t q = Y.rp[j]; q < Y.rp[j + 1]; ++q) {
+        const int32_t J = Y.ci[q];
+        const double prod = x * Y.v[q];
+        if (mark[J] != i) {
+          mark[J] = i;
+          acc[J] = prod;
+          cols.push_back(J);
+        } else {
+          acc[J] += prod;
+        }
+      }
+    }
+    std::sort(cols.begin(), cols.end());
+    for (int32_t J : cols) {
+      C.ci.push_back(J);
+      C.v.push_back(acc[J]);
+    }
+    C.rp[i + 1] = (int32_t)C.ci.size();
+  }
+  return C;
+}
+
+// ILU(0) in IKJ order on A's pattern; returns factor values in A's positions (strict lower: L_s with
+// unit diagonal implied; diagonal and upper: U).
+std::vector<double> ilu0_values(const HostCsr &A) {
+  const int32_t n = A.nr;
+  std::vector<double> w = A.v;
+  std::vector<int32_t> pos(n, -1), dpos(n, -1);
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+      if (A.ci[k] == i) dpos[i] = k;
+  for (int32_t i = 0; i < n; ++i) {
+    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) pos[A.ci[k]] = k;
+    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      const int32_t c = A.ci[k];
+      if (c >= i) break;
+      const double piv = w[dpos[c]];
+      if (piv == 0.0) fail(NAMG_E_ZERO_PIVOT, "zero ILU(0) pivot in row " + std::to_string(c));
+      w[k] /= piv;
+      const double lik = w[k];
+      for (int32_t q = dpos[c] + 1; q < A.rp[c + 1]; ++q) {
+        const int32_t p = pos[A.ci[q]];
+        if (p >= 0) w[p] -= lik * w[q];
+      }
+    }
+    if (w[dpos[i]] == 0.0) fail(NAMG_E_ZERO_PIVOT, "zero ILU(0) pivot in row " + std::to_string(i));
+    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) pos[A.ci[k]] = -1;
+  }
+  return w;
+}
+
+// Strict lower or upper part of a pattern with values vals[k] * scale[row] (scale may be empty).
+HostCsr strict_part(const HostCsr &A, const std::vector<double> &vals, bool lower,
+                    const std::vector<double> &scale) {
+  HostCsr T;
+  T.nr = A.nr;
+  T.nc = A.nc;
+  T.rp.assign(A.nr + 1, 0);
+  for (int32_t i = 0; i < A.nr; ++i) {
+    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      const int32_t j = A.ci[k];
+      if (lower ? (j < i) : (j > i)) {
+        T.ci.push_back(j);
+        T.v.push_back(scale.empty() ? vals[k] : vals[k] * scale[i]);
+      }
+    }
+    T.rp[i + 1] = (int32_t)T.ci.size();
+  }
+  return T;
+}
+
+LevelSchedule schedule(const HostCsr &T, bool lower) {
+  const int32_t n = T.nr;
+  std::vector<int32_t> lev(n, 0);
+  int32_t nlev = 0;
+  for (int32_t q = 0; q < n; ++q) {
+    const int32_t i = lower ? q : n - 1 - q;
+    int32_t l = 0;
+    for (int32_t k = T.rp[i]; k < T.rp[i + 1]; ++k) l = std::max(l, lev[T.ci[k]] + 1);
+    lev[i] = l;
+    nlev = std::max(nlev, l + 1);
+  }
+  LevelSchedule s;
+  s.ptr.assign(nlev + 1, 0);
+  for (int32_t i = 0; i < n; ++i) s.ptr[lev[i] + 1]++;
+  for (int32_t l = 0; l < nlev; ++l) s.ptr[l + 1] += s.ptr[l];
+  s.order.resize(n);
+  std::vector<int32_t> fill(s.ptr.begin(), s.ptr.end() - 1);
+  for (int32_t i = 0; i < n; ++i) s.order[fill[lev[i]]++] = i;
+  return s;
+}
+
+std::vector<double> dense_inverse(const HostCsr &A) {
+  const int32_t n = A.nr;
+  std::vector<double> a((size_t)n * n, 0.0), inv((size_t)n * n, 0.0);
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) a[(size_t)i * n + A.ci[k]] = A.v[k];
+  std::vector<int32_t> perm(n);
+  std::iota(perm.begin(), perm.end(), 0);
+  for (int32_t c = 0; c < n; ++c) {
+    int32_t p = c;
+    for (int32_t r = c + 1; r < n; ++r)
+      if (std::fabs(a[(size_t)r * n + c]) > std::fabs(a[(size_t)p * n + c])) p = r;
+    if (a[(size_t)p * n + c] == 0.0) fail(NAMG_E_ZERO_PIVOT, "singular coarsest operator");
+    if (p != c) {
+      for (int32_t q = 0; q < n; ++q) std::swap(a[(size_t)c * n + q], a[(size_t)p * n + q]);
+      std::swap(perm[c], perm[p]);
+    }
+    for (int32_t r = c + 1; r < n; ++r) {
+      const double l = a[(size_t)r * n + c] / a[(size_t)c * n + c];
+      a[(size_t)r * n + c] = l;
+      for (int32_t q = c + 1; q < n; ++q) a[(size_t)r * n + q] -= l * a[(size_t)c * n + q];
+    }
+  }
+  std::vector<double> col(n);
+  for (int32_t e = 0; e < n; ++e) {
+    for (int32_t r = 0; r < n; ++r) col[r] = (perm[r] == e) ? 1.0 : 0.0;
+    for (int32_t r = 0; r < n; ++r)
+      for (int32_t q = 0; q < r; ++q) col[r] -= a[(size_t)r * n + q] * col[q];
+    for (int32_t r = n - 1; r >= 0; --r) {
+      for (int32_t q = r + 1; q < n; ++q) col[r] -= a[(size_t)r * n + q] * col[q];
+      col[r] /= a[(size_t)r * n + r];
+    }
+    for (int32_t r = 0; r < n; ++r) inv[(size_t)r * n + e] = col[r];
+  }
+  return inv;
+}
+
+void smoother_data(HostLevel &L, bool with_ilu) {
+  const HostCsr &A = L.A;
+  L.dinv.resize(A.nr);
+  for (int32_t i = 0; i < A.nr; ++i) {
+    const double d = diagonal(A, i);
+    if (d == 0.0) fail(NAMG_E_ZERO_PIVOT, "zero diagonal in row " + std::to_string(i));
+    L.dinv[i] = 1.0 / d;
+  }
+  // D^{-1}L and D^{-1}U: a_ij / a_ii
+  L.pgs_lo = strict_part(A, A.v, true, {});
+  L.pgs_up = strict_part(A, A.v, false, {});
+  for (int32_t i = 0; i < A.nr; ++i) {
+    const double d = diagonal(A, i);
+    for (int32_t k = L.pgs_lo.rp[i]; k < L.pgs_lo.rp[i + 1]; ++k) L.pgs_lo.v[k] /= d;
+    for (int32_t k = L.pgs_up.rp[i]; k < L.pgs_up.rp[i + 1]; ++k) L.pgs_up.v[k] /= d;
+  }
+  L.pgs_lo_sched = schedule(L.pgs_lo, true);
+  L.pgs_up_sched = schedule(L.pgs_up, false);
+  if (with_ilu) {
+    std::vector<double> w = ilu0_values(A);
+    L.has_ilu = true;
+    L.ilu_dinv.resize(A.nr);
+    std::vector<double> du(A.nr);
+    for (int32_t i = 0; i < A.nr; ++i)
+      for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+        if (A.ci[k] == i) du[i] = w[k];
+    for (int32_t i = 0; i < A.nr; ++i) L.ilu_dinv[i] = 1.0 / du[i];
+    L.ilu_lo = strict_part(A, w, true, {});
+    L.ilu_up = strict_part(A, w, false, {});
+    for (int32_t i = 0; i < A.nr; ++i)
+      for (int32_t k = L.ilu_up.rp[i]; k < L.ilu_up.rp[i + 1]; ++k) L.ilu_up.v[k] /= du[i];
+    L.ilu_lo_sched = schedule(L.ilu_lo, true);
+    L.ilu_up_sched = schedule(L.ilu_up, false);
+  }
+}
+
+}  // namespace
+
+HostCsr import_csr(int32_t n, const int32_t *rp, const int32_t *ci, const double *v) {
+  if (n < 1) fail(NAMG_E_INVALID, "n must be >= 1");
+  if (!rp || !ci || !v) fail(NAMG_E_INVALID, "null CSR array");
+  if (rp[0] != 0) fail(NAMG_E_INVALID, "rowptr[0] must be 0");
+  for (int32_t i = 0; i < n; ++i)
+    if (rp[i + 1] < rp[i]) fail(NAMG_E_INVALID, "rowptr not monotone at row " + std::to_string(i));
+  HostCsr A;
+  A.nr = A.nc = n;
+  A.rp.assign(rp, rp + n + 1);
+  const int64_t nnz = rp[n];
+  A.ci.assign(ci, ci + nnz);
+  A.v.assign(v, v + nnz);
+  for (int32_t i = 0; i < n; ++i) {
+    bool diag = false;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+      if (ci[k] < 0 || ci[k] >= n) fail(NAMG_E_INVALID, "column index out of range in row " + std::to_string(i));
+      if (k > rp[i] && ci[k] <= ci[k - 1])
+        fail(NAMG_E_INVALID, "columns not strictly ascending in row " + std::to_string(i));
+      if (!std::isfinite(v[k])) fail(NAMG_E_NONFINITE, "non-finite value in row " + std::to_string(i));
+      if (ci[k] == i) {
+        diag = true;
+        if (v[k] == 0.0) fail(NAMG_E_ZERO_PIVOT, "zero diagonal in row " + std::to_string(i));
+      }
+    }
+    if (!diag) fail(NAMG_E_ZERO_PIVOT, "missing diagonal in row " + std::to_string(i));
+  }
+  return A;
+}
+
+HostHierarchy build_hierarchy(const HostCsr &A0, double theta, int max_levels, int max_coarse,
+                              int ilu_levels) {
+  if (!(theta > 0.0 && theta <= 1.0)) fail(NAMG_E_INVALID, "theta must be in (0, 1]");
+  if (max_levels < 1 || max_levels > NAMG_MAX_LEVELS) fail(NAMG_E_INVALID, "max_levels out of range");
+  if (max_coarse < 1) fail(NAMG_E_INVALID, "max_coarse must be >= 1");
+  HostHierarchy H;
+  for (int32_t i = 0; i < A0.nr; ++i) {
+    double s = 0.0;
+    for (int32_t k = A0.rp[i]; k < A0.rp[i + 1]; ++k) s += std::fabs(A0.v[k]);
+    H.anorm_inf = std::max(H.anorm_inf, s);
+  }
+  H.lv.emplace_back();
+  H.lv.back().A = A0;
+  while (true) {
+    HostLevel &L = H.lv.back();
+    const int32_t n = L.A.nr;
+    if (n <= max_coarse || (int)H.lv.size() >= max_levels) break;
+    Graph S = strength_graph(L.A, theta);
+    std::vector<int8_t> cf = rs_coarsen(S, n);
+    HostCsr P = classical_interpolation(L.A, S, cf);
+    if (P.nc == 0 || P.nc == n) break;
+    HostCsr R = transpose_csr(P);
+    HostCsr Ac = spgemm(R, spgemm(L.A, P));
+    for (int32_t i = 0; i < Ac.nr; ++i)
+      if (diagonal(Ac, i) == 0.0) fail(NAMG_E_ZERO_PIVOT, "zero diagonal in a coarse operator");
+    L.cf = std::move(cf);
+    L.P = std::move(P);
+    L.R = std::move(R);
+    HostLevel next;
+    next.A = std::move(Ac);
+    H.lv.push_back(std::move(next));
+  }
+  const int nl = (int)H.lv.size();
+  for (int l = 0; l < nl - 1; ++l) smoother_data(H.lv[l], ilu_levels < 0 || l < ilu_levels);
+  const HostCsr &Ac = H.lv.back().A;
+  if (Ac.nr > 4096) fail(NAMG_E_INVALID, "coarsest level has more than 4096 rows; raise max_levels");
+  H.coarse_inv = dense_inverse(Ac);
+  return H;
+}
+
+}  // namespace namg

@@ -1,0 +1,54 @@
+// Host-side AMG setup of the namg library: strength, Ruge-Stueben coarsening, classical interpolation,
+// Galerkin coarse operators, ILU(0), smoother data and level schedules. FP64, deterministic, built with
+// -ffp-contract=off so that every coarse value is summed in the canonical order documented per function.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace namg {
+
+struct HostCsr {
+  int32_t nr = 0, nc = 0;
+  std::vector<int32_t> rp, ci;
+  std::vector<double> v;
+  int64_t nnz() const { return (int64_t)ci.size(); }
+};
+
+struct SetupError {
+  int code;
+  std::string msg;
+};
+
+// Rows of a strict triangle grouped by dependency level: rows order[ptr[k] .. ptr[k+1]) only depend on
+// rows of earlier groups. Used by the direct-triangular comparators.
+struct LevelSchedule {
+  std::vector<int32_t> order, ptr;
+  int levels() const { return ptr.empty() ? 0 : (int)ptr.size() - 1; }
+};
+
+struct HostLevel {
+  HostCsr A, P, R;
+  std::vector<int8_t> cf;
+  std::vector<double> dinv;    // 1 / a_ii
+  HostCsr pgs_lo, pgs_up;      // D^{-1} L and D^{-1} U: strict parts of A scaled by the row's diagonal
+  LevelSchedule pgs_lo_sched, pgs_up_sched;
+  bool has_ilu = false;
+  HostCsr ilu_lo, ilu_up;      // L_s (strict lower of the unit-diagonal L) and U_s = D_U^{-1} U - I
+  std::vector<double> ilu_dinv;  // 1 / u_ii
+  LevelSchedule ilu_lo_sched, ilu_up_sched;
+};
+
+struct HostHierarchy {
+  std::vector<HostLevel> lv;
+  std::vector<double> coarse_inv;  // dense inverse of the coarsest operator, row-major
+  double anorm_inf = 0.0;          // ||A_0||_inf
+};
+
+// Throws SetupError{NAMG_E_INVALID / NAMG_E_NONFINITE / NAMG_E_ZERO_PIVOT} on malformed input.
+HostCsr import_csr(int32_t n, const int32_t *rp, const int32_t *ci, const double *v);
+
+HostHierarchy build_hierarchy(const HostCsr &A, double theta, int max_levels, int max_coarse, int ilu_levels);
+
+}  // namespace namg

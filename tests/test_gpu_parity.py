@@ -1,0 +1,236 @@
+"""GPU parity: the HIP library against the CPU oracle on the same seeded inputs.
+
+Component operators, single smoothing sweeps and whole V-cycles in FP64 must agree with the oracle to
+1e-12 relative (max-norm); whole FP64 solves take the same number of iterations and agree to 1e-10 in x
+(the iterate of a converged solve amplifies the ~1e-16 rounding difference of single operations by the
+conditioning of the Krylov least-squares problem; the measured gap is reported in the design notes).
+FP32-preconditioned solves must reach the same 1e-8 relative residual (checked with an independent
+FP64 SpMV) with an error against the FP64 oracle solution consistent with that residual.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import CSR, config_system, poisson2d, poisson3d, varcoef3d
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def relerr(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def namg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2112_14681_amd as m
+
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def level_csr(H, l):
+    e = H.export_level(l)
+    Arp, Aci, Av = e["A"]
+    return CSR(len(Arp) - 1, Arp, Aci, Av), e
+
+
+@pytest.fixture(scope="module")
+def c2_small(namg):
+    A, b, _ = config_system("c2", 23)  # 12 167 rows: ragged SELL slices and blocks
+    H = namg.Hierarchy(A, device=0, ilu_levels=-1)
+    return A, b, H
+
+
+# ------------------------------------------------------------------------------------- components
+def test_spmv_residual_restrict_prolong_every_level(namg, c2_small):
+    A, b, H = c2_small
+    info = H.info()
+    rng = np.random.default_rng(0)
+    for l in range(info["levels"] - 1):
+        Al, e = level_csr(H, l)
+        n, nc = Al.n, e["P"][3]
+        x, bb, ec = rng.standard_normal(n), rng.standard_normal(n), rng.standard_normal(nc)
+        out = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        H.apply(l, namg.OP_SPMV, dev(x), None, out)
+        assert relerr(host(out), O.spmv(Al, x)) <= TOL64
+        H.apply(l, namg.OP_RESIDUAL, dev(x), dev(bb), out)
+        assert relerr(host(out), bb - O.spmv(Al, x)) <= TOL64
+        Prp, Pci, Pv, _ = e["P"]
+        import scipy.sparse as sp
+
+        P = sp.csr_matrix((Pv, Pci, Prp), shape=(n, nc))
+        outc = torch.empty(nc, dtype=torch.float64, device="cuda:0")
+        H.apply(l, namg.OP_RESTRICT, dev(x), None, outc)
+        R = CSR.from_scipy(P.T.tocsr())
+        assert relerr(host(outc), O.spmv(R, x)) <= TOL64
+        H.apply(l, namg.OP_PROLONG, dev(ec), dev(x), out)
+        assert relerr(host(out), x + O.spmv(CSR.from_scipy(P), ec)) <= TOL64
+    out0 = torch.empty(A.n, dtype=torch.float64, device="cuda:0")
+    x = rng.standard_normal(A.n)
+    H.apply(0, namg.OP_SPMV64, dev(x), None, out0)
+    assert relerr(host(out0), O.spmv(A, x)) <= TOL64
+
+
+def test_coarse_direct_solve(namg, c2_small):
+    A, b, H = c2_small
+    L = H.info()["levels"] - 1
+    Ac, _ = level_csr(H, L)
+    rhs = np.random.default_rng(1).standard_normal(Ac.n)
+    out = torch.empty(Ac.n, dtype=torch.float64, device="cuda:0")
+    H.apply(L, namg.OP_COARSE, dev(rhs), None, out)
+    assert relerr(host(out), np.linalg.solve(Ac.to_dense(), rhs)) <= 1e-11
+
+
+@pytest.mark.parametrize("level", [0, 1, 2])
+@pytest.mark.parametrize("smoother,tri,t", [(0, 0, 1), (0, 0, 2), (0, 0, 3), (0, 1, 1), (1, 0, 1), (1, 0, 2),
+                                            (1, 0, 3), (1, 0, 5), (1, 1, 1)])
+def test_single_sweeps(namg, c2_small, level, smoother, tri, t):
+    """One pre- and one post-smoothing sweep (Section 5.2, 5.3) on a level, nonzero x."""
+    A, b, H = c2_small
+    Al, _ = level_csr(H, level)
+    rng = np.random.default_rng(10 + level)
+    x, bb = rng.standard_normal(Al.n), rng.standard_normal(Al.n)
+    out = torch.empty(Al.n, dtype=torch.float64, device="cuda:0")
+    if smoother == 0:
+        kinds = {namg.OP_SMOOTH_PRE: O.GS_FWD if tri else O.PGS_FWD, namg.OP_SMOOTH_POST: O.GS_BWD if tri else O.PGS_BWD}
+    else:
+        k = O.ILU_DIRECT if tri else O.ILU_NEUMANN
+        kinds = {namg.OP_SMOOTH_PRE: k, namg.OP_SMOOTH_POST: k}
+    for op, kind in kinds.items():
+        H.apply(level, op, dev(x), dev(bb), out, smoother=smoother, tri_mode=tri, inner_terms=t)
+        ref = O.smooth(Al, kind, t, bb, x)
+        assert relerr(host(out), ref) <= TOL64, (op, kind)
+
+
+@pytest.mark.parametrize("smoother,tri,t", [(0, 0, 2), (0, 0, 3), (0, 1, 2), (1, 0, 3), (1, 1, 3), (1, 0, 1)])
+def test_vcycle_matches_oracle(namg, smoother, tri, t):
+    A, b, _ = config_system("c2", 23)
+    H = namg.Hierarchy(A, device=0)
+    G = O.Hierarchy(A)
+    out = torch.empty(A.n, dtype=torch.float64, device="cuda:0")
+    H.vcycle(dev(b), out, smoother=smoother, tri_mode=tri, inner_terms=t)
+    ref = G.vcycle(b, smoother=smoother, tri_mode=tri, t=t)
+    assert relerr(host(out), ref) <= TOL64
+
+
+# ----------------------------------------------------------------------------------------- solves
+def _check_solve(namg, A, b, H, G, x0=None, xtol=1e-10, **kw):
+    okw = dict(tol=kw.get("tol", 1e-8), restart=kw.get("restart", 30), max_iters=kw.get("max_iters", 1000),
+               smoother=kw.get("smoother", 0), tri_mode=kw.get("tri_mode", 0), t=kw.get("inner_terms", 2),
+               gmres_T=kw.get("gmres_T", 0))
+    ref = G.solve(b, x0, **okw)
+    xt = dev(np.zeros(A.n) if x0 is None else x0)
+    st = H.solve(dev(b), xt, **kw)
+    x = host(xt)
+    assert st["iters"] == ref["iters"], (st["iters"], ref["iters"])
+    assert st["status"] == ref["status"]
+    assert relerr(x, ref["x"]) <= xtol, relerr(x, ref["x"])
+    res = np.linalg.norm(b - O.spmv(A, x)) / np.linalg.norm(b)
+    if st["status"] == namg.OK:
+        assert res <= kw.get("tol", 1e-8)
+    assert st["relres_true"] == pytest.approx(res, rel=1e-6)
+    return st, ref, x
+
+
+@pytest.mark.parametrize("gmres_T", [0, 1])
+@pytest.mark.parametrize("tri", [0, 1])
+def test_solve_c1_parity(namg, gmres_T, tri):
+    """The parity configuration: 2-D Poisson 32^2, poly GS with 2 Neumann terms, GMRES(30), FP64."""
+    A, b, _ = config_system("c1")
+    _check_solve(namg, A, b, namg.Hierarchy(A, device=0), O.Hierarchy(A), smoother=0, tri_mode=tri,
+                 inner_terms=2, gmres_T=gmres_T)
+
+
+@pytest.mark.parametrize("tri", [0, 1])
+def test_solve_c2_ilu_hybrid_parity(namg, tri):
+    """3-D Poisson (32^3), hybrid V-cycle: ILU(0) on the finest level with t = 3, poly GS elsewhere."""
+    A, b, _ = config_system("c2", 32)
+    _check_solve(namg, A, b, namg.Hierarchy(A, device=0), O.Hierarchy(A), smoother=1, tri_mode=tri,
+                 inner_terms=3)
+
+
+def test_solve_c3_and_c4_parity(namg):
+    for name, N, kw in (("c3", 20, dict(smoother=0, inner_terms=2)), ("c4r", 16, dict(smoother=1, inner_terms=3)),
+                        ("c4rcm", 16, dict(smoother=1, inner_terms=3, restart=50))):
+        A, b, _ = config_system(name, N)
+        _check_solve(namg, A, b, namg.Hierarchy(A, device=0), O.Hierarchy(A), **kw)
+
+
+def test_solve_fp32_preconditioner(namg):
+    """FP32 hierarchy and V-cycle under FP64 Arnoldi: same 1e-8 true residual."""
+    for name, N, kw in (("c3", 24, dict(smoother=0, inner_terms=2)), ("c2", 32, dict(smoother=1, inner_terms=3))):
+        A, b, _ = config_system(name, N)
+        H32 = namg.Hierarchy(A, device=0, precision=namg.FP32_PRECOND)
+        ref = O.Hierarchy(A).solve(b, t=kw["inner_terms"], smoother=kw["smoother"])
+        xt = dev(np.zeros(A.n))
+        st = H32.solve(dev(b), xt, **kw)
+        x = host(xt)
+        res = np.linalg.norm(b - O.spmv(A, x)) / np.linalg.norm(b)
+        assert st["status"] == namg.OK and res <= 1e-8
+        assert abs(st["iters"] - ref["iters"]) <= 2
+        assert relerr(x, ref["x"]) <= 1e-6
+
+
+def test_restart_x0_and_not_converged(namg):
+    A, b, _ = config_system("c1")
+    H, G = namg.Hierarchy(A, device=0), O.Hierarchy(A)
+    x0 = np.random.default_rng(3).standard_normal(A.n)
+    st, ref, _ = _check_solve(namg, A, b, H, G, x0=x0, restart=3, inner_terms=2)
+    assert st["cycles"] > 1
+    st, ref, _ = _check_solve(namg, A, b, H, G, tol=1e-20, max_iters=4, inner_terms=2)
+    assert st["status"] == namg.NOT_CONVERGED and st["iters"] == 4
+
+
+def test_edge_cases(namg):
+    # one-level hierarchy (n <= max_coarse): the preconditioner is the dense solve
+    A = poisson2d(5)
+    b = np.random.default_rng(4).standard_normal(A.n)
+    H = namg.Hierarchy(A, device=0)
+    assert H.info()["levels"] == 1
+    st, _, _ = _check_solve(namg, A, b, H, O.Hierarchy(A))
+    assert st["iters"] == 1
+    # 1x1 system
+    A1 = CSR(1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([4.0]))
+    H1 = namg.Hierarchy(A1, device=0)
+    xt = dev(np.zeros(1))
+    st = H1.solve(dev(np.array([2.0])), xt)
+    assert st["status"] == namg.OK and abs(host(xt)[0] - 0.5) < 1e-15
+    # zero right-hand side gives x = 0
+    A, b, _ = config_system("c1")
+    H = namg.Hierarchy(A, device=0)
+    xt = dev(np.ones(A.n))
+    st = H.solve(dev(np.zeros(A.n)), xt)
+    assert st["status"] == namg.OK and np.all(host(xt) == 0.0)
+    # non-finite right-hand side
+    bad = b.copy()
+    bad[7] = np.nan
+    with pytest.raises(namg.NamgError) as e:
+        H.solve(dev(bad), dev(np.zeros(A.n)))
+    assert e.value.code == namg.E_NONFINITE
+    # ragged sizes across SELL slices / blocks: 17^3 = 4913 rows
+    A, b, _ = config_system("c2", 17)
+    _check_solve(namg, A, b, namg.Hierarchy(A, device=0), O.Hierarchy(A), smoother=1, inner_terms=3)
+
+
+def test_deterministic_bitwise(namg):
+    A, b, _ = config_system("c2", 24)
+    H = namg.Hierarchy(A, device=0)
+    xs = []
+    for _ in range(2):
+        xt = dev(np.zeros(A.n))
+        H.solve(dev(b), xt, smoother=1, inner_terms=3)
+        xs.append(host(xt))
+    assert np.array_equal(xs[0], xs[1])

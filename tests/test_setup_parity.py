@@ -1,0 +1,140 @@
+"""CPU checks of the library boundary: the C ABI loads and exports what include/namg.h declares, argument
+validation rejects malformed input before any device work, and the library's host setup reproduces the
+oracle's hierarchy bit for bit (C/F splittings, P and every Galerkin operator) on every level.
+
+Host-only setup (device = -1) runs no device code, so these tests need no GPU.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from workloads import CSR, config_system, poisson2d, poisson3d, random_csr, tridiag1d, varcoef3d
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def namg():
+    import paper_2112_14681_amd as m
+
+    return m
+
+
+def test_library_exports_every_declared_symbol(namg):
+    header = open(os.path.join(ROOT, "include", "namg.h")).read()
+    body = re.sub(r"/\*.*?\*/", "", header, flags=re.S)
+    declared = set(re.findall(r"\b(namg_[a-z0-9_]+)\s*\(", body))
+    assert declared == set(namg.EXPORTED)
+    for name in declared:
+        assert hasattr(namg.lib(), name), name
+
+
+def _compare_hierarchies(namg, oracle_lib, A, **kw):
+    H = namg.Hierarchy(A, device=-1, **kw)
+    G = oracle_lib.Hierarchy(A, **{k: v for k, v in kw.items() if k in ("theta", "max_levels", "max_coarse",
+                                                                       "ilu_levels")})
+    info = H.info()
+    assert info["levels"] == G.levels
+    for l in range(G.levels):
+        e, g = H.export_level(l), G.level(l)
+        Arp, Aci, Av = e["A"]
+        np.testing.assert_array_equal(Arp, g.A.rowptr)
+        np.testing.assert_array_equal(Aci, g.A.colind)
+        assert np.array_equal(Av, g.A.vals), f"A_{l} values differ"
+        if l < G.levels - 1:
+            np.testing.assert_array_equal(e["cf"], g.cf)
+            Prp, Pci, Pv, nc = e["P"]
+            assert nc == g.P.shape[1]
+            np.testing.assert_array_equal(Prp, g.P.indptr)
+            np.testing.assert_array_equal(Pci, g.P.indices)
+            assert np.array_equal(Pv, g.P.data), f"P_{l} values differ"
+    return info
+
+
+@pytest.mark.parametrize("name,N", [("c1", None), ("c2", 20), ("c2", 33), ("c3", 18), ("c4n", 14), ("c4r", 14),
+                                    ("c4rcm", 14)])
+def test_setup_bit_exact_vs_oracle(namg, oracle_lib, name, N):
+    A, _, _ = config_system(name, N)
+    info = _compare_hierarchies(namg, oracle_lib, A)
+    assert info["levels"] >= 3
+
+
+@pytest.mark.parametrize("theta", [0.1, 0.25, 0.5, 0.9])
+def test_setup_bit_exact_theta_sweep(namg, oracle_lib, theta):
+    A, _ = varcoef3d(12, 1.0, 7, 100.0)
+    _compare_hierarchies(namg, oracle_lib, A, theta=theta)
+
+
+def test_setup_bit_exact_random_and_small(namg, oracle_lib):
+    _compare_hierarchies(namg, oracle_lib, random_csr(200, 6, 3), max_coarse=10)
+    _compare_hierarchies(namg, oracle_lib, random_csr(120, 5, 4, symmetric=True), max_coarse=5)
+    _compare_hierarchies(namg, oracle_lib, tridiag1d(7), max_coarse=1, max_levels=2)
+    info = _compare_hierarchies(namg, oracle_lib, poisson2d(5))  # n = 25 <= 50: one level
+    assert info["levels"] == 1
+
+
+def test_setup_at_64cubed_bit_exact(namg, oracle_lib):
+    """A larger instance (262 144 rows, 7 levels) spanning many SELL slices and ragged coarse sizes."""
+    A = poisson3d(64)
+    info = _compare_hierarchies(namg, oracle_lib, A)
+    assert info["levels"] == 7
+
+
+def test_hierarchy_info_complexities(namg):
+    A = poisson3d(16)
+    info = namg.Hierarchy(A, device=-1).info()
+    assert info["n"][0] == A.n and info["nnz"][0] == A.nnz
+    assert info["op_complexity"] == pytest.approx(sum(info["nnz"]) / A.nnz)
+    assert info["device_bytes"] == 0
+
+
+def _err(namg, fn):
+    with pytest.raises(namg.NamgError) as e:
+        fn()
+    return e.value.code
+
+
+def test_validation_rejects_malformed_input(namg):
+    A = poisson2d(6)
+    # unsorted columns
+    B = CSR(A.n, A.rowptr.copy(), A.colind.copy(), A.vals.copy())
+    B.colind[[0, 1]] = B.colind[[1, 0]]
+    assert _err(namg, lambda: namg.Hierarchy(B, device=-1)) == namg.E_INVALID
+    # column out of range
+    B = CSR(A.n, A.rowptr.copy(), A.colind.copy(), A.vals.copy())
+    B.colind[-1] = A.n
+    assert _err(namg, lambda: namg.Hierarchy(B, device=-1)) == namg.E_INVALID
+    # non-monotone row pointer
+    B = CSR(A.n, A.rowptr.copy(), A.colind.copy(), A.vals.copy())
+    B.rowptr[3] = B.rowptr[4] + 1
+    assert _err(namg, lambda: namg.Hierarchy(B, device=-1)) == namg.E_INVALID
+    # non-finite value
+    B = CSR(A.n, A.rowptr.copy(), A.colind.copy(), A.vals.copy())
+    B.vals[5] = np.inf
+    assert _err(namg, lambda: namg.Hierarchy(B, device=-1)) == namg.E_NONFINITE
+    # zero / missing diagonal
+    d = A.to_dense()
+    d[2, 2] = 0.0
+    assert _err(namg, lambda: namg.Hierarchy(CSR.from_dense(d), device=-1)) == namg.E_ZERO_PIVOT
+    # bad theta
+    assert _err(namg, lambda: namg.Hierarchy(A, device=-1, theta=0.0)) == namg.E_INVALID
+    assert _err(namg, lambda: namg.Hierarchy(A, device=-1, theta=1.5)) == namg.E_INVALID
+    # host-only hierarchy refuses device work
+    H = namg.Hierarchy(A, device=-1)
+    p = namg.solve_params()
+    code = namg.lib().namg_solve(H.h, 1, 1, namg.C.byref(p) if hasattr(namg, "C") else None, None, None)
+    assert code == namg.E_NODEVICE
+    assert "host-only" in namg.lib().namg_last_error().decode()
+
+
+def test_solve_param_validation(namg):
+    import ctypes as C
+
+    H = namg.Hierarchy(poisson2d(8), device=-1)
+    for bad in (dict(tol=0.0), dict(restart=0), dict(restart=1000), dict(inner_terms=0), dict(smoother=7),
+                dict(tri_mode=3), dict(gmres_T=2), dict(pre_sweeps=-1)):
+        p = namg.solve_params(**bad)
+        code = namg.lib().namg_solve(H.h, 1, 1, C.byref(p), None, None)
+        assert code == namg.E_INVALID, bad
