@@ -130,6 +130,31 @@ enum {
 int namg_apply(namg_hier *h, int level, int op, const namg_solve_params *p, const double *in1_dev,
                const double *in2_dev, double *out_dev, void *stream);
 
+/* Kernel families that namg_profile_kernel can time. */
+enum {
+  NAMG_KF_NONE = 0,
+  NAMG_KF_NEUMANN = 1,     /* one Neumann/Jacobi inner term on a strict triangle (Sections 5.2, 5.3.2) */
+  NAMG_KF_RESIDUAL = 2,    /* r = b - A_l x [, f = D^{-1} r] inside the V-cycle */
+  NAMG_KF_SPMV = 3,        /* restriction R_l r and the coarsest-level dense inverse */
+  NAMG_KF_PROLONG = 4,     /* x += P_l e */
+  NAMG_KF_GMRES_SPMV = 5,  /* w = A z, FP64 operator (Algorithm 1, the matrix-vector product) */
+  NAMG_KF_MULTIDOT = 6,    /* c = V^T v, d = V^T w (Algorithm 1, the single reduction) */
+  NAMG_KF_PROJECT = 7,     /* v_{i+2} = w / rho - V s (Algorithm 1, projection and lagged normalisation) */
+  NAMG_KF_TRI = 8          /* one dependency level of a direct triangular solve (comparator) */
+};
+
+typedef struct {
+  int64_t launches;
+  double total_ms;  /* sum of the timed launches' durations (hipEvents attached to each dispatch) */
+  double alg_bytes; /* sum of their algorithmic HBM bytes */
+} namg_kernel_profile;
+
+/* Time every later launch of one kernel family (on one level, or -1 for all levels) with start/stop
+ * events attached to the dispatch on its stream; results accumulate until namg_profile_read, which
+ * returns and clears them. family NAMG_KF_NONE switches timing off. */
+int namg_profile_kernel(namg_hier *h, int family, int level);
+int namg_profile_read(namg_hier *h, namg_kernel_profile *out);
+
 /* Hierarchy shape: levels, n_l, nnz(A_l), operator and grid complexity, device bytes. */
 int namg_hier_info(const namg_hier *h, namg_hierarchy_info *out);
 

@@ -24,10 +24,12 @@ T_NEUMANN, T_DIRECT = 0, 1
 OP_SPMV, OP_RESIDUAL, OP_SMOOTH_PRE, OP_SMOOTH_POST, OP_RESTRICT, OP_PROLONG, OP_COARSE, OP_SPMV64 = range(8)
 MAX_LEVELS = 32
 
+KF_NONE, KF_NEUMANN, KF_RESIDUAL, KF_SPMV, KF_PROLONG, KF_GMRES_SPMV, KF_MULTIDOT, KF_PROJECT, KF_TRI = range(9)
+
 EXPORTED = (
     "namg_default_setup_params", "namg_default_solve_params", "namg_setup", "namg_solve", "namg_vcycle",
-    "namg_apply", "namg_hier_info", "namg_level_sizes", "namg_export_level", "namg_destroy",
-    "namg_last_error",
+    "namg_apply", "namg_profile_kernel", "namg_profile_read", "namg_hier_info", "namg_level_sizes",
+    "namg_export_level", "namg_destroy", "namg_last_error",
 )
 
 
@@ -49,6 +51,10 @@ class SolveStats(C.Structure):
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class KernelProfile(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("alg_bytes", C.c_double)]
 
 
 class HierInfo(C.Structure):
@@ -73,6 +79,8 @@ def _load():
     lib.namg_solve.argtypes = [vp, vp, vp, C.POINTER(SolveParams), vp, C.POINTER(SolveStats)]
     lib.namg_vcycle.argtypes = [vp, vp, vp, C.POINTER(SolveParams), vp]
     lib.namg_apply.argtypes = [vp, C.c_int, C.c_int, C.POINTER(SolveParams), vp, vp, vp, vp]
+    lib.namg_profile_kernel.argtypes = [vp, C.c_int, C.c_int]
+    lib.namg_profile_read.argtypes = [vp, C.POINTER(KernelProfile)]
     lib.namg_hier_info.argtypes = [vp, C.POINTER(HierInfo)]
     lib.namg_level_sizes.argtypes = [vp, C.c_int, i32p, i64p, i64p, i32p]
     lib.namg_export_level.argtypes = [vp, C.c_int, i8p, i32p, i32p, f64p, i32p, i32p, f64p]
@@ -202,6 +210,15 @@ class Hierarchy:
     def vcycle(self, b, x, stream=None, **params):
         p = solve_params(**params)
         _check(_lib.namg_vcycle(self.h, _dev_ptr(b, self.n), _dev_ptr(x, self.n), C.byref(p), _stream(stream)))
+
+    def profile_kernel(self, family, level=-1):
+        """Time every later launch of a kernel family (hipEvents attached to each dispatch)."""
+        _check(_lib.namg_profile_kernel(self.h, family, level))
+
+    def profile_read(self) -> dict:
+        kp = KernelProfile()
+        _check(_lib.namg_profile_read(self.h, C.byref(kp)))
+        return {"launches": kp.launches, "total_ms": kp.total_ms, "alg_bytes": kp.alg_bytes}
 
     def apply(self, level, op, in1, in2, out, stream=None, **params):
         p = solve_params(**params)

@@ -1,5 +1,5 @@
-// Device-side containers of the namg library: owned device buffers, the SELL-64 sparse layout used by
-// every streaming kernel, CSR views for the level-scheduled direct comparators and the Krylov state.
+// Device-side containers of the namg library: owned device buffers, the two sparse layouts used by the
+// streaming kernels, CSR views for the level-scheduled direct comparators and the Krylov state.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -80,33 +80,76 @@ class DevBuf {
   MemCounter *mc_ = nullptr;
 };
 
-// SELL-C sparse layout with C = 64 (one wavefront): rows are cut into slices of 64 consecutive rows;
-// slice s stores its rows' entries column-major, entry k of every row of the slice at
-// val[sp[s] + 64*k + lane], padded with (column 0, value 0) up to the slice's longest row. Row order and
-// the order of entries within each row are those of the CSR input.
+// Sparse operators on the device come in one of two layouts, chosen per matrix at setup from its row
+// lengths so that every row kernel keeps enough independent loads in flight:
+//  * group == 1: SELL-64. Rows are cut into slices of 64 consecutive rows (one wavefront); slice s
+//    stores entry k of each of its rows at val[ptr[s] + 64*k + lane], padded with (column 0, value 0)
+//    up to the slice's longest row. One lane per row; the loads of a wavefront are contiguous.
+//  * group == G in {2, 4, ..., 64}: CSR, G lanes per row. Lane j of a row's group takes entries
+//    j, j+G, ...; the G partial sums are combined by a fixed xor-butterfly. Used for the long rows of
+//    the Galerkin operators on coarse levels, where one lane per row would walk 30-100 dependent
+//    entries.
+// Row order and the order of entries within a row are those of the CSR input.
 constexpr int SELL_C = 64;
 
+// Launch-shape flags carried by every matrix view (set per hierarchy):
+//   KF_XCD_REMAP: workgroups are dispatched round-robin over the 8 XCDs; remap the block index so that
+//                 each XCD streams one contiguous range of rows and its L2 sees the stencil neighbours;
+//   KF_NT_LOADS:  matrix values and column indices are streamed once: load them nontemporally so that
+//                 they do not evict the gathered vector from the caches.
+constexpr uint32_t KF_XCD_REMAP = 1u, KF_NT_LOADS = 2u;
+
 template <class T>
-struct SellView {
-  const int32_t *sp = nullptr;
+struct MatView {
+  const int32_t *ptr = nullptr;  // SELL slice pointers (group 1) or CSR row pointers (group > 1)
   const int32_t *col = nullptr;
   const T *val = nullptr;
   int32_t nrows = 0;
+  uint32_t flags = 0;
 };
 
-template <class T>
-struct DSell {
-  int32_t nrows = 0, ncols = 0, nslices = 0;
-  int64_t nnz = 0, stored = 0;
-  DevBuf<int32_t> sp, col;
-  DevBuf<T> val;
-  SellView<T> view() const { return SellView<T>{sp.get(), col.get(), val.get(), nrows}; }
+// Lanes per row for a matrix with the given shape: one lane when rows are short or the matrix is large
+// enough to fill the device with one lane per row; otherwise about four entries per lane.
+inline int choose_group(int64_t nrows, int64_t nnz) {
+  const double avg = nrows > 0 ? (double)nnz / (double)nrows : 0.0;
+  if (avg <= 10.0 || nrows >= (1 << 19)) return 1;
+  int g = 2;
+  while (g < 64 && g * 4 < avg) g <<= 1;
+  return g;
+}
 
-  void build(const HostCsr &A, MemCounter *mc) {
+template <class T>
+struct DMat {
+  int32_t nrows = 0, ncols = 0, group = 1;
+  int64_t nnz = 0, stored = 0;
+  uint32_t flags = 0;
+  DevBuf<int32_t> ptr, col;
+  DevBuf<T> val;
+  MatView<T> view() const { return MatView<T>{ptr.get(), col.get(), val.get(), nrows, flags}; }
+  // algorithmic bytes of one pass over the matrix (entries once, row/slice pointers once)
+  double bytes() const {
+    const double nptr = group > 1 ? (double)nrows + 1.0 : (double)((nrows + SELL_C - 1) / SELL_C) + 1.0;
+    return (double)nnz * (sizeof(T) + 4.0) + 4.0 * nptr;
+  }
+
+  void build(const HostCsr &A, MemCounter *mc, int force_group, uint32_t kflags) {
+    flags = kflags;
     nrows = A.nr;
     ncols = A.nc;
     nnz = A.nnz();
-    nslices = (nrows + SELL_C - 1) / SELL_C;
+    group = force_group > 0 ? force_group : choose_group(nrows, nnz);
+    if (group > 1) {
+      stored = nnz;
+      std::vector<T> hv(A.v.begin(), A.v.end());
+      ptr.alloc(A.rp.size(), mc);
+      ptr.upload(A.rp.data(), A.rp.size());
+      col.alloc(A.ci.size(), mc);
+      col.upload(A.ci.data(), A.ci.size());
+      val.alloc(hv.size(), mc);
+      val.upload(hv.data(), hv.size());
+      return;
+    }
+    const int32_t nslices = (nrows + SELL_C - 1) / SELL_C;
     std::vector<int32_t> hsp(nslices + 1, 0);
     for (int32_t s = 0; s < nslices; ++s) {
       int32_t w = 0;
@@ -127,8 +170,8 @@ struct DSell {
           hval[d] = (T)A.v[A.rp[r] + k];
         }
       }
-    sp.alloc(hsp.size(), mc);
-    sp.upload(hsp.data(), hsp.size());
+    ptr.alloc(hsp.size(), mc);
+    ptr.upload(hsp.data(), hsp.size());
     col.alloc(hcol.size(), mc);
     col.upload(hcol.data(), hcol.size());
     val.alloc(hval.size(), mc);
@@ -167,7 +210,6 @@ constexpr int KS_MAXR = NAMG_MAX_RESTART;
 constexpr int KS_LD = KS_MAXR + 2;
 
 struct KState {
-  double beta;     // ||b||
   double est;      // |g_{i+1}| / ||b|| after the latest column
   double rho_inv;  // 1 / r_{i+1,i+1} of the current step
   int32_t flag;    // 0 continue, 1 stop (converged / last column / breakdown), -1 non-finite

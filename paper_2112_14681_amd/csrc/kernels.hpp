@@ -25,31 +25,70 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Row `row` of a SELL-64 matrix times x, entries in stored (CSR) order.
-template <class Acc, class TM, class TX>
-__device__ __forceinline__ Acc sell_row(const SellView<TM> &A, const TX *__restrict__ x, int32_t row) {
-  const int32_t s = row >> 6;
-  const int32_t end = A.sp[s + 1];
+// Row `row` of a sparse matrix times x, reduced over the G lanes of the row's group (every lane of the
+// group returns the full sum). G == 1: SELL-64, one lane per row. G > 1: CSR, lane `sub` takes entries
+// sub, sub + G, ...; groups are aligned inside the wavefront, so the butterfly never leaves the group.
+template <int G, class Acc, class TM, class TX>
+__device__ __forceinline__ Acc row_dot(const MatView<TM> &A, const TX *__restrict__ x, int32_t row, int sub) {
   Acc acc = Acc(0);
-  for (int32_t k = A.sp[s] + (row & 63); k < end; k += SELL_C) acc += (Acc)A.val[k] * (Acc)x[A.col[k]];
+  const bool nt = (A.flags & KF_NT_LOADS) != 0;
+  if constexpr (G == 1) {
+    const int32_t s = row >> 6;
+    const int32_t end = A.ptr[s + 1];
+    if (nt) {
+#pragma unroll 4
+      for (int32_t k = A.ptr[s] + (row & 63); k < end; k += SELL_C)
+        acc += (Acc)__builtin_nontemporal_load(A.val + k) * (Acc)x[__builtin_nontemporal_load(A.col + k)];
+    } else {
+#pragma unroll 4
+      for (int32_t k = A.ptr[s] + (row & 63); k < end; k += SELL_C) acc += (Acc)A.val[k] * (Acc)x[A.col[k]];
+    }
+  } else {
+    const int32_t end = A.ptr[row + 1];
+    if (nt) {
+#pragma unroll 2
+      for (int32_t k = A.ptr[row] + sub; k < end; k += G)
+        acc += (Acc)__builtin_nontemporal_load(A.val + k) * (Acc)x[__builtin_nontemporal_load(A.col + k)];
+    } else {
+#pragma unroll 2
+      for (int32_t k = A.ptr[row] + sub; k < end; k += G) acc += (Acc)A.val[k] * (Acc)x[A.col[k]];
+    }
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  }
   return acc;
 }
 
-// y = A x  (restriction R r, the GMRES product w = A z with z promoted on load, plain SpMV)
-template <class Acc, class TM, class TX, class TY>
-__global__ __launch_bounds__(BLK) void k_spmv(SellView<TM> A, const TX *__restrict__ x, TY *__restrict__ y) {
-  const int32_t row = blockIdx.x * BLK + threadIdx.x;
-  if (row >= A.nrows) return;
-  y[row] = (TY)sell_row<Acc>(A, x, row);
+// Logical block index: with KF_XCD_REMAP, XCD x (which receives blocks x, x+8, x+16, ...) is given the
+// contiguous logical range [x*q + min(x, r), ...) of the nb = 8q + r blocks.
+__device__ __forceinline__ uint32_t logical_block(uint32_t flags) {
+  const uint32_t b = blockIdx.x;
+  if (!(flags & KF_XCD_REMAP)) return b;
+  const uint32_t nb = gridDim.x, q = nb >> 3, r = nb & 7u, x = b & 7u;
+  return x * q + min(x, r) + (b >> 3);
+}
+
+#define NAMG_ROW_PROLOGUE(G, M)                                                  \
+  const int64_t gtid_ = (int64_t)logical_block((M).flags) * BLK + threadIdx.x;   \
+  const int32_t row = (int32_t)(gtid_ / (G));                                     \
+  const int sub = (int)(gtid_ % (G));                                             \
+  if (row >= (M).nrows) return;
+
+// y = A x  (restriction R r, the GMRES product w = A z with z promoted on load, the coarse inverse)
+template <int G, class Acc, class TM, class TX, class TY>
+__global__ __launch_bounds__(BLK) void k_spmv(MatView<TM> A, const TX *__restrict__ x, TY *__restrict__ y) {
+  NAMG_ROW_PROLOGUE(G, A)
+  const Acc v = row_dot<G, Acc>(A, x, row, sub);
+  if (sub == 0) y[row] = (TY)v;
 }
 
 // r = b - A x (x == nullptr means x = 0), optionally f = d .* r. One pass: SpMV, subtract, scale.
-template <class T>
-__global__ __launch_bounds__(BLK) void k_residual(SellView<T> A, const T *__restrict__ b, const T *__restrict__ x,
+template <int G, class T>
+__global__ __launch_bounds__(BLK) void k_residual(MatView<T> A, const T *__restrict__ b, const T *__restrict__ x,
                                                   const T *__restrict__ d, T *__restrict__ r, T *__restrict__ f) {
-  const int32_t row = blockIdx.x * BLK + threadIdx.x;
-  if (row >= A.nrows) return;
-  const T acc = x ? sell_row<T>(A, x, row) : T(0);
+  NAMG_ROW_PROLOGUE(G, A)
+  const T acc = x ? row_dot<G, T>(A, x, row, sub) : T(0);
+  if (sub != 0) return;
   const T rr = b[row] - acc;
   if (r) r[row] = rr;
   if (f) f[row] = d[row] * rr;
@@ -59,15 +98,24 @@ __global__ __launch_bounds__(BLK) void k_residual(SellView<T> A, const T *__rest
 //   out = [acc +] [scale .*] (f - S in)
 // Polynomial GS: S = D^{-1}L (or D^{-1}U), f = D^{-1} r; ILU: S = L_s with f = r, or S = U_s with
 // f = D_U^{-1} y. `acc` may alias `out` (x += ...); `in` never aliases `out`.
-template <class T>
-__global__ __launch_bounds__(BLK) void k_neumann(SellView<T> S, const T *__restrict__ f, const T *__restrict__ in,
+template <int G, class T>
+__global__ __launch_bounds__(BLK) void k_neumann(MatView<T> S, const T *__restrict__ f, const T *__restrict__ in,
                                                  const T *__restrict__ scale, const T *acc, T *out) {
-  const int32_t row = blockIdx.x * BLK + threadIdx.x;
-  if (row >= S.nrows) return;
-  T v = f[row] - sell_row<T>(S, in, row);
+  NAMG_ROW_PROLOGUE(G, S)
+  const T sv = row_dot<G, T>(S, in, row, sub);
+  if (sub != 0) return;
+  T v = f[row] - sv;
   if (scale) v *= scale[row];
   if (acc) v += acc[row];
   out[row] = v;
+}
+
+// x += P e  (prolongation and correction in one pass)
+template <int G, class T>
+__global__ __launch_bounds__(BLK) void k_prolong(MatView<T> P, const T *__restrict__ e, T *x) {
+  NAMG_ROW_PROLOGUE(G, P)
+  const T v = row_dot<G, T>(P, e, row, sub);
+  if (sub == 0) x[row] += v;
 }
 
 // out = [acc +] [scale .*] f
@@ -80,25 +128,6 @@ __global__ __launch_bounds__(BLK) void k_axpy(const T *__restrict__ f, const T *
   if (scale) v *= scale[row];
   if (acc) v += acc[row];
   out[row] = v;
-}
-
-// x += P e  (prolongation and correction in one pass)
-template <class T>
-__global__ __launch_bounds__(BLK) void k_prolong(SellView<T> P, const T *__restrict__ e, T *x) {
-  const int32_t row = blockIdx.x * BLK + threadIdx.x;
-  if (row >= P.nrows) return;
-  x[row] += sell_row<T>(P, e, row);
-}
-
-// x = A_c^{-1} b with the inverse stored column-major (coalesced across rows).
-template <class T>
-__global__ __launch_bounds__(BLK) void k_dense_gemv(const T *__restrict__ invT, int32_t n, const T *__restrict__ b,
-                                                    T *__restrict__ x) {
-  const int32_t row = blockIdx.x * BLK + threadIdx.x;
-  if (row >= n) return;
-  T acc = T(0);
-  for (int32_t j = 0; j < n; ++j) acc += invT[(int64_t)j * n + row] * b[j];
-  x[row] = acc;
 }
 
 // One dependency level of a direct triangular solve g = (I + S)^{-1} f: rows of the level only read
@@ -144,14 +173,14 @@ __device__ __forceinline__ double block_sum(double v, double *lds) {
 
 // r = b - A x in FP64 (true residual), optional low-precision copy of r, per-block partial of |r|^2.
 template <class TL>
-__global__ __launch_bounds__(BLK) void k_residual64(SellView<double> A, const double *__restrict__ b,
+__global__ __launch_bounds__(BLK) void k_residual64(MatView<double> A, const double *__restrict__ b,
                                                     const double *__restrict__ x, double *__restrict__ r,
                                                     TL *__restrict__ rlow, double *__restrict__ partial) {
   __shared__ double lds[WAVES];
   const int32_t row = blockIdx.x * BLK + threadIdx.x;
   double rr = 0.0;
   if (row < A.nrows) {
-    rr = b[row] - sell_row<double>(A, x, row);
+    rr = b[row] - row_dot<1, double>(A, x, row, 0);
     r[row] = rr;
     if (rlow) rlow[row] = (TL)rr;
   }
@@ -168,13 +197,24 @@ __global__ __launch_bounds__(BLK) void k_sumsq(const double *__restrict__ x, int
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-// out[0] = sum of partial[0..n) in a fixed order (one block).
-__global__ __launch_bounds__(BLK) void k_reduce(const double *__restrict__ partial, int32_t n, double *__restrict__ out) {
+// out[0] = sum of partial[0..n) in a fixed order (one block); out may be host-mapped memory.
+__global__ __launch_bounds__(BLK) void k_reduce(const double *__restrict__ partial, int32_t n, double *out) {
   __shared__ double lds[WAVES];
   double t = 0.0;
   for (int32_t k = threadIdx.x; k < n; k += BLK) t += partial[k];
   t = block_sum(t, lds);
   if (threadIdx.x == 0) out[0] = t;
+}
+
+// Block v: out[v] = sum over b < nblk of partial[v * nblk + b], in a fixed order.
+__global__ __launch_bounds__(BLK) void k_colreduce(const double *__restrict__ partial, int32_t nblk,
+                                                   double *__restrict__ out) {
+  __shared__ double lds[WAVES];
+  const double *p = partial + (int64_t)blockIdx.x * nblk;
+  double t = 0.0;
+  for (int32_t k = threadIdx.x; k < nblk; k += BLK) t += p[k];
+  t = block_sum(t, lds);
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
 }
 
 // The single fused reduction of an Arnoldi step (Algorithm 1, the global synchronisation):
@@ -228,29 +268,22 @@ __global__ __launch_bounds__(BLK) void k_multidot(const double *__restrict__ V, 
   }
 }
 
-// Small dense part of Arnoldi step i (0-based: columns 0..i of V are V_{i+1}), one workgroup:
-// finish the reduction; rho = sqrt(c_i) (lagged norm of v_{i+1}); Hessenberg column i-1 = [previous s;
-// rho] with the Givens rotations applied and the residual estimate |g_i| / ||b||; then the new row of L
-// (c_j / rho), q (d_j / rho, the last one d_i / rho^2) and s = T q with T = I - L (Neumann) or
-// T = (I + L)^{-1} (forward substitution). Writes s, 1/rho and a stop flag into the state.
-__global__ __launch_bounds__(BLK) void k_arnoldi_step(KState *__restrict__ st, const double *__restrict__ partial,
-                                                      int32_t nblk, int32_t i, int32_t has_w, int32_t t_direct,
-                                                      int32_t last, double tol) {
+// Small dense part of Arnoldi step i (0-based: columns 0..i of V are V_{i+1}), one workgroup; beta = ||b||.
+// cd holds the reduced inner products: c_j = cd[j], d_j = cd[i + 1 + j], j <= i.
+// rho = sqrt(c_i) is the lagged norm of v_{i+1}; Hessenberg column i-1 = [previous s; rho] gets the
+// Givens rotations and yields the residual estimate |g_i| / ||b||; then the new row of L (c_j / rho),
+// q (d_j / rho, the last one d_i / rho^2) and s = T q with T = I - L (Neumann) or T = (I + L)^{-1}
+// (forward substitution). Writes s, 1/rho and the stop flag to the state, and (est, flag) to host_out,
+// host-mapped memory the host reads after the stream synchronises.
+__global__ __launch_bounds__(BLK) void k_arnoldi_step(KState *__restrict__ st, const double *__restrict__ cd, int32_t i,
+                                                      int32_t has_w, int32_t t_direct, int32_t last, double tol,
+                                                      double beta, double *host_out) {
   __shared__ double c[KS_LD], d[KS_LD], q[KS_LD], s[KS_LD];
   __shared__ double rho_sh;
   __shared__ int stop_sh;
-  const int K = (has_w ? 2 : 1) * (i + 1);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int v = wave; v < K; v += WAVES) {
-    double t = 0.0;
-    for (int32_t b = lane; b < nblk; b += 64) t += partial[(int64_t)v * nblk + b];
-    t = wave_sum(t);
-    if (lane == 0) {
-      if (v <= i)
-        c[v] = t;
-      else
-        d[v - (i + 1)] = t;
-    }
+  for (int j = threadIdx.x; j <= i; j += BLK) {
+    c[j] = cd[j];
+    d[j] = has_w ? cd[i + 1 + j] : 0.0;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -260,7 +293,7 @@ __global__ __launch_bounds__(BLK) void k_arnoldi_step(KState *__restrict__ st, c
     st->zs[i] = st->rho_inv;
     if (i == 0) {
       st->g[0] = rho;
-      st->est = rho / st->beta;
+      st->est = rho / beta;
     } else {
       double *h = st->H + (int64_t)(i - 1) * KS_LD;
       for (int j = 0; j < i; ++j) h[j] = st->rprev[j];
@@ -283,11 +316,13 @@ __global__ __launch_bounds__(BLK) void k_arnoldi_step(KState *__restrict__ st, c
       const double gi = st->g[i - 1];
       st->g[i] = -sj * gi;
       st->g[i - 1] = cj * gi;
-      st->est = fabs(st->g[i]) / st->beta;
+      st->est = fabs(st->g[i]) / beta;
       if (st->est <= tol || last || rho == 0.0) flag = 1;
     }
     if (!isfinite(rho) || !isfinite(st->est)) flag = -1;
     st->flag = flag;
+    host_out[0] = st->est;
+    host_out[1] = (double)flag;
     rho_sh = rho;
     stop_sh = flag;
   }

@@ -1,9 +1,10 @@
 // namg solve phase: device hierarchy, V-cycle driver, low-synchronization flexible GMRES and the C ABI.
 //
 // Host code issues every kernel on the caller's stream; the only host<->device crossings inside a solve
-// are one 8-byte readback per Arnoldi step (the convergence estimate) and one per restart cycle
-// (the true residual norm).
+// are one readback per Arnoldi step (the convergence estimate, written by the step kernel straight into
+// host-mapped memory) and one per restart cycle (the true residual norm).
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cmath>
@@ -24,14 +25,6 @@ namespace namg {
 
 namespace {
 thread_local std::string g_last_error;
-
-#define NAMG_LAUNCH(kernel, grid, stream, ...)                                                 \
-  do {                                                                                         \
-    if ((grid) > 0) {                                                                          \
-      hipLaunchKernelGGL(kernel, dim3(grid), dim3(BLK), 0, stream, __VA_ARGS__);               \
-      hip_check(hipGetLastError(), #kernel);                                                   \
-    }                                                                                          \
-  } while (0)
 
 // Restores the caller's current device on scope exit.
 struct DeviceGuard {
@@ -66,6 +59,39 @@ void validate_solve_params(const namg_solve_params &p) {
   if (p.gmres_T != NAMG_T_NEUMANN && p.gmres_T != NAMG_T_DIRECT) throw SetupError{NAMG_E_INVALID, "unknown gmres_T"};
   if (p.pre_sweeps < 0 || p.post_sweeps < 0) throw SetupError{NAMG_E_INVALID, "negative sweep count"};
 }
+
+// Launch-shape flags of a hierarchy: NAMG_KFLAGS overrides the default (for measurements).
+uint32_t kernel_flags() {
+  const char *e = std::getenv("NAMG_KFLAGS");
+  if (e && *e) return (uint32_t)std::strtoul(e, nullptr, 0);
+  return 0u;
+}
+
+// One function pointer per lanes-per-row group for every row kernel.
+#define NAMG_GROUP_SWITCH(NAME, ...)                      \
+  switch (g) {                                            \
+    case 1: return &NAME<1, __VA_ARGS__>;                 \
+    case 2: return &NAME<2, __VA_ARGS__>;                 \
+    case 4: return &NAME<4, __VA_ARGS__>;                 \
+    case 8: return &NAME<8, __VA_ARGS__>;                 \
+    case 16: return &NAME<16, __VA_ARGS__>;               \
+    case 32: return &NAME<32, __VA_ARGS__>;               \
+    default: return &NAME<64, __VA_ARGS__>;               \
+  }
+template <class Acc, class TM, class TX, class TY>
+auto sel_spmv(int g) { NAMG_GROUP_SWITCH(k_spmv, Acc, TM, TX, TY) }
+template <class T>
+auto sel_residual(int g) { NAMG_GROUP_SWITCH(k_residual, T) }
+template <class T>
+auto sel_neumann(int g) { NAMG_GROUP_SWITCH(k_neumann, T) }
+template <class T>
+auto sel_prolong(int g) { NAMG_GROUP_SWITCH(k_prolong, T) }
+#undef NAMG_GROUP_SWITCH
+
+template <class T>
+unsigned rows_grid(const DMat<T> &M) {
+  return blocks_for((int64_t)M.nrows * M.group);
+}
 }  // namespace
 
 class SolverBase {
@@ -76,12 +102,14 @@ class SolverBase {
   virtual void apply(int level, int op, const namg_solve_params &p, const double *in1, const double *in2, double *out,
                      hipStream_t s) = 0;
   virtual int64_t device_bytes() const = 0;
+  virtual void profile(int family, int level) = 0;
+  virtual namg_kernel_profile profile_read() = 0;
 };
 
 template <class T>
 struct DevLevel {
   int32_t n = 0;
-  DSell<T> A, P, R, pgs_lo, pgs_up, ilu_lo, ilu_up;
+  DMat<T> A, P, R, pgs_lo, pgs_up, ilu_lo, ilu_up;
   DevBuf<T> dinv, ilu_dinv;
   bool has_ilu = false;
   DTri<T> tri_pgs_lo, tri_pgs_up, tri_ilu_lo, tri_ilu_up;
@@ -90,9 +118,12 @@ struct DevLevel {
 
 template <class T>
 class Solver final : public SolverBase {
+  static constexpr double S = sizeof(T);
+
  public:
   Solver(const HostHierarchy &H, int device) : dev_(device) {
     DeviceGuard g(dev_);
+    const uint32_t kf = kernel_flags();
     const int nl = (int)H.lv.size();
     lv_.resize(nl);
     for (int l = 0; l < nl; ++l) {
@@ -102,18 +133,18 @@ class Solver final : public SolverBase {
       d.b.alloc(d.n, &mc_);
       d.x.alloc(d.n, &mc_);
       if (l == nl - 1) break;
-      d.A.build(h.A, &mc_);
-      d.P.build(h.P, &mc_);
-      d.R.build(h.R, &mc_);
-      d.pgs_lo.build(h.pgs_lo, &mc_);
-      d.pgs_up.build(h.pgs_up, &mc_);
+      d.A.build(h.A, &mc_, 0, kf);
+      d.P.build(h.P, &mc_, 0, kf);
+      d.R.build(h.R, &mc_, 0, kf);
+      d.pgs_lo.build(h.pgs_lo, &mc_, 0, kf);
+      d.pgs_up.build(h.pgs_up, &mc_, 0, kf);
       upload_vec(d.dinv, h.dinv);
       d.tri_pgs_lo.build(h.pgs_lo, h.pgs_lo_sched, &mc_);
       d.tri_pgs_up.build(h.pgs_up, h.pgs_up_sched, &mc_);
       d.has_ilu = h.has_ilu;
       if (h.has_ilu) {
-        d.ilu_lo.build(h.ilu_lo, &mc_);
-        d.ilu_up.build(h.ilu_up, &mc_);
+        d.ilu_lo.build(h.ilu_lo, &mc_, 0, kf);
+        d.ilu_up.build(h.ilu_up, &mc_, 0, kf);
         upload_vec(d.ilu_dinv, h.ilu_dinv);
         d.tri_ilu_lo.build(h.ilu_lo, h.ilu_lo_sched, &mc_);
         d.tri_ilu_up.build(h.ilu_up, h.ilu_up_sched, &mc_);
@@ -124,25 +155,52 @@ class Solver final : public SolverBase {
       d.g2.alloc(d.n, &mc_);
     }
     nc_ = H.lv.back().A.nr;
-    std::vector<double> invT((size_t)nc_ * nc_);
+    // the coarsest level's dense inverse as a full CSR matrix, one wavefront per row
+    HostCsr inv;
+    inv.nr = inv.nc = nc_;
+    inv.rp.resize(nc_ + 1);
+    for (int32_t i = 0; i <= nc_; ++i) inv.rp[i] = i * nc_;
+    inv.ci.resize((size_t)nc_ * nc_);
     for (int32_t i = 0; i < nc_; ++i)
-      for (int32_t j = 0; j < nc_; ++j) invT[(size_t)j * nc_ + i] = H.coarse_inv[(size_t)i * nc_ + j];
-    upload_vec(coarse_invT_, invT);
-    A64_.build(H.lv[0].A, &mc_);
+      for (int32_t j = 0; j < nc_; ++j) inv.ci[(size_t)i * nc_ + j] = j;
+    inv.v = H.coarse_inv;
+    coarse_inv_.build(inv, &mc_, nc_ > 1 ? 64 : 1, 0);
+    A64_.build(H.lv[0].A, &mc_, 1, kf);
     anorm_inf_ = H.anorm_inf;
     const int32_t n = lv_[0].n;
     nblk_red_ = (int32_t)blocks_for(n);
     red_.alloc(std::max<int32_t>(nblk_red_, 1) + 8, &mc_);
     kst_.alloc(1, &mc_);
-    hip_check(hipHostMalloc((void **)&pinned_, 64, hipHostMallocDefault), "hipHostMalloc");
+    hip_check(hipHostMalloc((void **)&pinned_, 64, hipHostMallocMapped), "hipHostMalloc");
+    hip_check(hipHostGetDevicePointer((void **)&pinned_dev_, pinned_, 0), "hipHostGetDevicePointer");
     hip_check(hipDeviceSynchronize(), "upload");
   }
 
   ~Solver() override {
+    for (auto &e : events_) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
     if (pinned_) (void)hipHostFree(pinned_);
   }
 
   int64_t device_bytes() const override { return mc_.bytes; }
+
+  void profile(int family, int level) override {
+    DeviceGuard g(dev_);
+    flush_profile();
+    prof_family_ = family;
+    prof_level_ = level;
+    prof_ = namg_kernel_profile{0, 0.0, 0.0};
+  }
+
+  namg_kernel_profile profile_read() override {
+    DeviceGuard g(dev_);
+    flush_profile();
+    namg_kernel_profile out = prof_;
+    prof_ = namg_kernel_profile{0, 0.0, 0.0};
+    return out;
+  }
 
   // ------------------------------------------------------------------------------------------ V-cycle
   void vcycle64(const double *b, double *x, const namg_solve_params &p, hipStream_t s) override {
@@ -152,9 +210,9 @@ class Solver final : public SolverBase {
     if constexpr (std::is_same<T, double>::value) {
       vcycle(0, b, x, o, s);
     } else {
-      NAMG_LAUNCH((k_cast<double, T>), blocks_for(n), s, b, lv_[0].b.get(), n);
+      cast(b, lv_[0].b.get(), n, s);
       vcycle(0, lv_[0].b.get(), lv_[0].x.get(), o, s);
-      NAMG_LAUNCH((k_cast<T, double>), blocks_for(n), s, lv_[0].x.get(), x, n);
+      cast(lv_[0].x.get(), x, n, s);
     }
   }
 
@@ -164,56 +222,60 @@ class Solver final : public SolverBase {
     const int nl = (int)lv_.size();
     if (level < 0 || level >= nl) throw SetupError{NAMG_E_INVALID, "level out of range"};
     CycleOpts o = cycle_opts(p);
+    if (!in1) throw SetupError{NAMG_E_INVALID, "missing operand"};
     if (op == NAMG_OP_SPMV64) {
       if (level != 0) throw SetupError{NAMG_E_INVALID, "SPMV64 is defined on level 0 only"};
-      NAMG_LAUNCH((k_spmv<double, double, double, double>), blocks_for(A64_.nrows), s, A64_.view(), in1, out);
+      launch(NAMG_KF_GMRES_SPMV, 0, A64_.bytes() + 16.0 * A64_.nrows, sel_spmv<double, double, double, double>(1),
+             rows_grid(A64_), s, A64_.view(), in1, out);
       return;
     }
     if (op == NAMG_OP_COARSE) {
       if (level != nl - 1) throw SetupError{NAMG_E_INVALID, "COARSE applies to the coarsest level"};
       DevLevel<T> &d = lv_[level];
-      cast_in(in1, d.b.get(), d.n, s);
-      NAMG_LAUNCH((k_dense_gemv<T>), blocks_for(nc_), s, coarse_invT_.get(), nc_, d.b.get(), d.x.get());
-      cast_out(d.x.get(), out, d.n, s);
+      cast(in1, d.b.get(), d.n, s);
+      coarse_solve(level, d.b.get(), d.x.get(), s);
+      cast(d.x.get(), out, d.n, s);
       return;
     }
     if (level == nl - 1) throw SetupError{NAMG_E_INVALID, "operator not defined on the coarsest level"};
     DevLevel<T> &d = lv_[level];
     DevLevel<T> &c = lv_[level + 1];
     const int32_t n = d.n;
-    // private scratch for the operands: the level's b and x vectors and the next level's b / x
+    const bool need2 = op == NAMG_OP_RESIDUAL || op == NAMG_OP_SMOOTH_PRE || op == NAMG_OP_SMOOTH_POST ||
+                       op == NAMG_OP_PROLONG;
+    if (need2 && !in2) throw SetupError{NAMG_E_INVALID, "missing operand"};
     switch (op) {
       case NAMG_OP_SPMV:
-        cast_in(in1, d.x.get(), n, s);
-        NAMG_LAUNCH((k_spmv<T, T, T, T>), blocks_for(n), s, d.A.view(), d.x.get(), d.b.get());
-        cast_out(d.b.get(), out, n, s);
+        cast(in1, d.x.get(), n, s);
+        launch(NAMG_KF_SPMV, level, d.A.bytes() + 2 * S * n, sel_spmv<T, T, T, T>(d.A.group), rows_grid(d.A), s,
+               d.A.view(), (const T *)d.x.get(), d.b.get());
+        cast(d.b.get(), out, n, s);
         break;
       case NAMG_OP_RESIDUAL:
-        cast_in(in1, d.x.get(), n, s);
-        cast_in(in2, d.b.get(), n, s);
-        NAMG_LAUNCH((k_residual<T>), blocks_for(n), s, d.A.view(), d.b.get(), d.x.get(), (const T *)nullptr,
-                    d.r.get(), (T *)nullptr);
-        cast_out(d.r.get(), out, n, s);
+        cast(in1, d.x.get(), n, s);
+        cast(in2, d.b.get(), n, s);
+        residual(level, d.b.get(), d.x.get(), nullptr, d.r.get(), nullptr, s);
+        cast(d.r.get(), out, n, s);
         break;
       case NAMG_OP_SMOOTH_PRE:
       case NAMG_OP_SMOOTH_POST: {
-        cast_in(in1, d.x.get(), n, s);
-        cast_in(in2, d.b.get(), n, s);
+        cast(in1, d.x.get(), n, s);
+        cast(in2, d.b.get(), n, s);
         const bool ilu = (o.smoother == NAMG_SMOOTH_ILU0) && d.has_ilu;
         smooth(level, d.b.get(), d.x.get(), false, op == NAMG_OP_SMOOTH_PRE, ilu, o, s);
-        cast_out(d.x.get(), out, n, s);
+        cast(d.x.get(), out, n, s);
         break;
       }
       case NAMG_OP_RESTRICT:
-        cast_in(in1, d.r.get(), n, s);
-        NAMG_LAUNCH((k_spmv<T, T, T, T>), blocks_for(c.n), s, d.R.view(), d.r.get(), c.b.get());
-        cast_out(c.b.get(), out, c.n, s);
+        cast(in1, d.r.get(), n, s);
+        restrict_(level, s);
+        cast(c.b.get(), out, c.n, s);
         break;
       case NAMG_OP_PROLONG:
-        cast_in(in1, c.x.get(), c.n, s);
-        cast_in(in2, d.x.get(), n, s);
-        NAMG_LAUNCH((k_prolong<T>), blocks_for(n), s, d.P.view(), c.x.get(), d.x.get());
-        cast_out(d.x.get(), out, n, s);
+        cast(in1, c.x.get(), c.n, s);
+        cast(in2, d.x.get(), n, s);
+        prolong(level, d.x.get(), s);
+        cast(d.x.get(), out, n, s);
         break;
       default:
         throw SetupError{NAMG_E_INVALID, "unknown operator"};
@@ -234,26 +296,24 @@ class Solver final : public SolverBase {
     const CycleOpts o = cycle_opts(p);
     const bool trace = std::getenv("NAMG_TRACE") != nullptr;
     KState *ks = kst_.get();
+    double *cd = cd_.get();
     double *V = V_.get();
     T *Z = Z_.get();
     double *w = w_.get();
     T *vin = std::is_same<T, double>::value ? nullptr : vin_.get();
 
-    // beta = ||b||, kept on the device for the residual estimates
     const double beta = std::sqrt(norm2sq(b, n, s));
-    pinned_[4] = beta;
-    hip_check(hipMemcpyAsync(&ks->beta, pinned_ + 4, sizeof(double), hipMemcpyHostToDevice, s), "hipMemcpyAsync");
     namg_solve_stats st{};
     int status = NAMG_OK;
     double rn = 0.0;
     if (!std::isfinite(beta)) throw SetupError{NAMG_E_NONFINITE, "non-finite right-hand side"};
     if (beta == 0.0) {
-      NAMG_LAUNCH((k_fill<double>), blocks_for(n), s, x, 0.0, n);
+      launch(-1, 0, 8.0 * n, &k_fill<double>, blocks_for(n), s, x, 0.0, n);
     } else {
       while (true) {
         // true residual r = b - A x into V(:,0) (FP64), plus the FP32 copy for the V-cycle
-        NAMG_LAUNCH((k_residual64<T>), blocks_for(n), s, A64_.view(), b, x, V, vin, red_.get());
-        alg_ += spmv_bytes(A64_, 8, 8) + 8.0 * n * 2;
+        launch(-1, 0, A64_.bytes() + 24.0 * n + (vin ? S * n : 0.0), &k_residual64<T>, blocks_for(n), s, A64_.view(),
+               b, (const double *)x, V, vin, red_.get());
         rn = std::sqrt(reduce_read(red_.get(), nblk_red_, s));
         if (!std::isfinite(rn)) throw SetupError{NAMG_E_NONFINITE, "non-finite residual"};
         if (trace) std::fprintf(stderr, "[namg] cycle %d true relres %.3e\n", st.cycles, rn / beta);
@@ -280,21 +340,20 @@ class Solver final : public SolverBase {
               b0 = vin;
             vcycle(0, b0, zi, o, s);
             st.precond_apps++;
-            NAMG_LAUNCH((k_spmv<double, double, T, double>), blocks_for(n), s, A64_.view(), zi, w);
-            alg_ += spmv_bytes(A64_, sizeof(T), 8);
+            launch(NAMG_KF_GMRES_SPMV, 0, A64_.bytes() + (S + 8.0) * n, sel_spmv<double, double, T, double>(1),
+                   rows_grid(A64_), s, A64_.view(), (const T *)zi, w);
           }
           const int32_t ncols = i + 1;
-          NAMG_LAUNCH((k_multidot<8>), nblk_dot_, s, V, ldv_, ncols, has_w ? w : (const double *)nullptr, n,
-                      rows_per_dot_, dot_.get(), nblk_dot_);
-          alg_ += 8.0 * n * (ncols + (has_w ? 1 : 0));
-          hipLaunchKernelGGL(k_arnoldi_step, dim3(1), dim3(BLK), 0, s, ks, dot_.get(), nblk_dot_, i, (int)has_w,
-                             (int)(p.gmres_T == NAMG_T_DIRECT), (int)(i == me), p.tol);
-          hip_check(hipGetLastError(), "k_arnoldi_step");
-          hip_check(hipMemcpyAsync(pinned_, ks, 32, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+          launch(NAMG_KF_MULTIDOT, 0, 8.0 * n * (ncols + (has_w ? 1 : 0)), &k_multidot<8>, nblk_dot_, s,
+                 (const double *)V, ldv_, ncols, has_w ? (const double *)w : (const double *)nullptr, n,
+                 rows_per_dot_, dot_.get(), nblk_dot_);
+          launch(-1, 0, 0.0, &k_colreduce, (unsigned)(ncols * (has_w ? 2 : 1)), s, (const double *)dot_.get(),
+                 nblk_dot_, cd);
+          launch_small(&k_arnoldi_step, s, ks, (const double *)cd, i, (int)has_w, (int)(p.gmres_T == NAMG_T_DIRECT),
+                       (int)(i == me), p.tol, beta, pinned_dev_);
           hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
-          const double est = pinned_[1];
-          int32_t flag;
-          std::memcpy(&flag, pinned_ + 3, sizeof(flag));
+          const double est = pinned_[0];
+          const int flag = (int)pinned_[1];
           if (flag < 0) throw SetupError{NAMG_E_NONFINITE, "non-finite value in the Arnoldi step"};
           if (i >= 1) {
             st.iters++;
@@ -305,13 +364,12 @@ class Solver final : public SolverBase {
             k = i;
             break;
           }
-          NAMG_LAUNCH((k_project<T>), blocks_for(n), s, V, ldv_, i, w, ks, n, vin);
-          alg_ += 8.0 * n * (i + 4) + (vin ? sizeof(T) * (double)n : 0.0);
+          launch(NAMG_KF_PROJECT, 0, 8.0 * n * (i + 4) + (vin ? S * n : 0.0), &k_project<T>, blocks_for(n), s, V,
+                 ldv_, i, (const double *)w, (const KState *)ks, n, vin);
         }
-        hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, s, ks, k);
-        hip_check(hipGetLastError(), "k_backsolve");
-        NAMG_LAUNCH((k_update_x<T>), blocks_for(n), s, Z, ldz_, k, ks, x, n);
-        alg_ += (double)n * (sizeof(T) * k + 16.0);
+        launch_small(&k_backsolve, s, ks, k);
+        launch(-1, 0, (double)n * (S * k + 16.0), &k_update_x<T>, blocks_for(n), s, (const T *)Z, ldz_, k,
+               (const KState *)ks, x, n);
       }
     }
     const double xn = std::sqrt(norm2sq(x, n, s));
@@ -331,24 +389,57 @@ class Solver final : public SolverBase {
   }
 
  private:
+  // Launch a kernel of BLK threads per block. family/level select the launches that the profiler
+  // times (start/stop events attached to the dispatch); bytes are the launch's algorithmic HBM bytes.
+  template <class Kernel, class... Args>
+  void launch(int family, int level, double bytes, Kernel kernel, unsigned grid, hipStream_t s, Args... args) {
+    if (grid == 0) return;
+    alg_ += bytes;
+    if (family >= 0 && family == prof_family_ && (prof_level_ < 0 || prof_level_ == level)) {
+      if (ev_used_ == events_.size()) {
+        hipEvent_t a, b;
+        hip_check(hipEventCreate(&a), "hipEventCreate");
+        hip_check(hipEventCreate(&b), "hipEventCreate");
+        events_.push_back({a, b});
+      }
+      auto &ev = events_[ev_used_++];
+      hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(BLK), 0, s, ev.first, ev.second, 0, args...);
+      prof_.launches++;
+      prof_.alg_bytes += bytes;
+    } else {
+      hipLaunchKernelGGL(kernel, dim3(grid), dim3(BLK), 0, s, args...);
+    }
+    hip_check(hipGetLastError(), "kernel launch");
+  }
+
+  template <class Kernel, class... Args>
+  void launch_small(Kernel kernel, hipStream_t s, Args... args) {
+    hipLaunchKernelGGL(kernel, dim3(1), dim3(BLK), 0, s, args...);
+    hip_check(hipGetLastError(), "kernel launch");
+  }
+
+  void flush_profile() {
+    if (ev_used_ == 0) return;
+    for (size_t q = 0; q < ev_used_; ++q) {
+      hip_check(hipEventSynchronize(events_[q].second), "hipEventSynchronize");
+      float ms = 0.f;
+      hip_check(hipEventElapsedTime(&ms, events_[q].first, events_[q].second), "hipEventElapsedTime");
+      prof_.total_ms += ms;
+    }
+    ev_used_ = 0;
+  }
+
   void upload_vec(DevBuf<T> &d, const std::vector<double> &h) {
     std::vector<T> t(h.begin(), h.end());
     d.alloc(t.size(), &mc_);
     d.upload(t.data(), t.size());
   }
 
-  void cast_in(const double *src, T *dst, int32_t n, hipStream_t s) {
+  template <class TI, class TO>
+  void cast(const TI *src, TO *dst, int32_t n, hipStream_t s) {
     if (!src) throw SetupError{NAMG_E_INVALID, "missing operand"};
-    NAMG_LAUNCH((k_cast<double, T>), blocks_for(n), s, src, dst, n);
+    launch(-1, 0, (sizeof(TI) + sizeof(TO)) * (double)n, &k_cast<TI, TO>, blocks_for(n), s, src, dst, n);
   }
-  void cast_out(const T *src, double *dst, int32_t n, hipStream_t s) {
-    NAMG_LAUNCH((k_cast<T, double>), blocks_for(n), s, src, dst, n);
-  }
-
-  static double spmv_bytes(const DSell<double> &A, double sx, double sy) {
-    return A.nnz * (8.0 + 4.0) + sx * A.ncols + sy * A.nrows;
-  }
-  static double sell_bytes(const DSell<T> &A) { return A.nnz * (sizeof(T) + 4.0); }
 
   void ensure_workspace(int m) {
     if (ws_m_ >= m) return;
@@ -362,109 +453,137 @@ class Solver final : public SolverBase {
     nblk_dot_ = (int32_t)std::min<int64_t>(1024, std::max<int64_t>(1, blocks_for(n)));
     rows_per_dot_ = (int32_t)(((int64_t)n + nblk_dot_ - 1) / nblk_dot_);
     dot_.alloc((size_t)nblk_dot_ * 2 * (m + 2), &mc_);
+    cd_.alloc((size_t)2 * (m + 2), &mc_);
     ws_m_ = m;
   }
 
   // |v|^2 (deterministic two-stage reduction on the device, read back to the host)
   double norm2sq(const double *v, int32_t n, hipStream_t s) {
-    NAMG_LAUNCH(k_sumsq, blocks_for(n), s, v, n, red_.get());
+    launch(-1, 0, 8.0 * n, &k_sumsq, blocks_for(n), s, v, n, red_.get());
     return reduce_read(red_.get(), nblk_red_, s);
   }
 
+  // Deterministic final reduction written straight into host-mapped memory, then read by the host.
   double reduce_read(const double *partial, int32_t nb, hipStream_t s) {
-    double *out = red_.get() + (red_.size() - 1);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(BLK), 0, s, partial, nb, out);
-    hip_check(hipGetLastError(), "k_reduce");
-    hip_check(hipMemcpyAsync(pinned_, out, sizeof(double), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    launch_small(&k_reduce, s, partial, nb, pinned_dev_ + 2);
     hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
-    return pinned_[0];
+    return pinned_[2];
+  }
+
+  // r = b - A_l x (x may be null: x = 0) with optional outputs r and f = d .* r.
+  void residual(int l, const T *b, const T *x, const T *d, T *r, T *f, hipStream_t s) {
+    const DevLevel<T> &L = lv_[l];
+    const int32_t n = L.n;
+    const double bytes = (x ? L.A.bytes() + S * n : 0.0) + S * n * (1 + (r ? 1 : 0) + (f ? 2 : 0));
+    launch(NAMG_KF_RESIDUAL, l, bytes, sel_residual<T>(x ? L.A.group : 1), x ? rows_grid(L.A) : blocks_for(n), s,
+           L.A.view(), b, x, d, r, f);
+  }
+
+  // out = [acc +] [scale .*] (f - M in): one Neumann term on the strict triangle M of level l.
+  void neumann(int l, const DMat<T> &M, const T *f, const T *in, const T *scale, const T *acc, T *out,
+               hipStream_t s) {
+    const int32_t n = M.nrows;
+    const double vecs = (f == in ? 1 : 2) + 1 + (scale ? 1 : 0) + (acc ? 1 : 0);
+    launch(NAMG_KF_NEUMANN, l, M.bytes() + S * n * vecs, sel_neumann<T>(M.group), rows_grid(M), s, M.view(), f, in,
+           scale, acc, out);
+  }
+
+  void axpy(const T *f, const T *scale, const T *acc, T *out, int32_t n, hipStream_t s) {
+    const double vecs = 2 + (scale ? 1 : 0) + (acc ? 1 : 0);
+    launch(-1, 0, S * n * vecs, &k_axpy<T>, blocks_for(n), s, f, scale, acc, out, n);
+  }
+
+  void restrict_(int l, hipStream_t s) {
+    DevLevel<T> &d = lv_[l];
+    DevLevel<T> &c = lv_[l + 1];
+    launch(NAMG_KF_SPMV, l, d.R.bytes() + S * ((double)d.n + c.n), sel_spmv<T, T, T, T>(d.R.group), rows_grid(d.R), s,
+           d.R.view(), (const T *)d.r.get(), c.b.get());
+  }
+
+  void prolong(int l, T *x, hipStream_t s) {
+    DevLevel<T> &d = lv_[l];
+    DevLevel<T> &c = lv_[l + 1];
+    launch(NAMG_KF_PROLONG, l, d.P.bytes() + S * ((double)c.n + 2.0 * d.n), sel_prolong<T>(d.P.group), rows_grid(d.P),
+           s, d.P.view(), (const T *)c.x.get(), x);
+  }
+
+  void coarse_solve(int l, const T *b, T *x, hipStream_t s) {
+    launch(NAMG_KF_SPMV, l, coarse_inv_.bytes() + 2 * S * nc_, sel_spmv<T, T, T, T>(coarse_inv_.group),
+           rows_grid(coarse_inv_), s, coarse_inv_.view(), b, x);
+  }
+
+  // g = (I + S)^{-1} f, one launch per dependency level.
+  void tri_solve(int l, const DTri<T> &tr, const T *f, T *g, hipStream_t s) {
+    const int nlev = (int)tr.lev_ptr.size() - 1;
+    for (int k = 0; k < nlev; ++k) {
+      const int32_t beg = tr.lev_ptr[k], cnt = tr.lev_ptr[k + 1] - beg;
+      const double bytes = (double)(tr.lev_ptr[k + 1] - beg) / std::max<int32_t>(tr.n, 1) *
+                           (tr.nnz * (S + 4.0) + S * 3.0 * tr.n + 12.0 * tr.n);
+      launch(NAMG_KF_TRI, l, bytes, &k_tri_level<T>, blocks_for(cnt), s, (const int32_t *)tr.rp.get(),
+             (const int32_t *)tr.ci.get(), (const T *)tr.val.get(), (const int32_t *)tr.order.get(), beg, cnt, f, g);
+    }
   }
 
   // Smoothing sweep on level l: x <- x + Mhat^{-1}(b - A x); first = true means x == 0 on entry.
   void smooth(int l, const T *b, T *x, bool first, bool pre, bool ilu, const CycleOpts &o, hipStream_t s) {
     DevLevel<T> &d = lv_[l];
     const int32_t n = d.n;
-    const unsigned gb = blocks_for(n);
     const T *nul = nullptr;
     const int t = o.t;
     T *pp[2] = {d.g1.get(), d.g2.get()};
     if (!ilu) {
       // polynomial Gauss-Seidel (Section 5.2): f = D^{-1}(b - A x), g <- f - (D^{-1}L) g, x += g
-      NAMG_LAUNCH((k_residual<T>), gb, s, d.A.view(), b, first ? nul : (const T *)x, (const T *)d.dinv.get(),
-                  (T *)nullptr, d.f.get());
-      alg_ += (first ? 0.0 : sell_bytes(d.A)) + sizeof(T) * (double)n * (first ? 3 : 4);
-      const DSell<T> &S = pre ? d.pgs_lo : d.pgs_up;
+      residual(l, b, first ? nul : (const T *)x, d.dinv.get(), nullptr, d.f.get(), s);
+      const DMat<T> &M = pre ? d.pgs_lo : d.pgs_up;
       if (o.tri_mode == NAMG_TRI_NEUMANN) {
         if (t == 1) {
-          NAMG_LAUNCH((k_axpy<T>), gb, s, (const T *)d.f.get(), nul, first ? nul : (const T *)x, x, n);
-          alg_ += sizeof(T) * (double)n * (first ? 2 : 3);
+          axpy(d.f.get(), nul, first ? nul : (const T *)x, x, n, s);
         } else {
           const T *in = d.f.get();
           for (int q = 1; q < t; ++q) {
             const bool last = q == t - 1;
             T *out = last ? x : pp[q & 1];
-            NAMG_LAUNCH((k_neumann<T>), gb, s, S.view(), (const T *)d.f.get(), in, nul,
-                        (last && !first) ? (const T *)x : nul, out);
-            alg_ += sell_bytes(S) + sizeof(T) * (double)n * ((last && !first) ? 4 : 3);
+            neumann(l, M, d.f.get(), in, nul, (last && !first) ? (const T *)x : nul, out, s);
             in = out;
           }
         }
       } else {
-        const DTri<T> &tr = pre ? d.tri_pgs_lo : d.tri_pgs_up;
-        tri_solve(tr, d.f.get(), d.g1.get(), s);
-        NAMG_LAUNCH((k_axpy<T>), gb, s, (const T *)d.g1.get(), nul, first ? nul : (const T *)x, x, n);
-        alg_ += sizeof(T) * (double)n * (first ? 2 : 3);
+        tri_solve(l, pre ? d.tri_pgs_lo : d.tri_pgs_up, d.f.get(), d.g1.get(), s);
+        axpy(d.g1.get(), nul, first ? nul : (const T *)x, x, n, s);
       }
       return;
     }
     // ILU(0) (Section 5.3): r = b - A x; y <- r - L_s y; v <- D_U^{-1}y - U_s v; x += v
     const T *r = b;
     if (!first) {
-      NAMG_LAUNCH((k_residual<T>), gb, s, d.A.view(), b, (const T *)x, nul, d.r.get(), (T *)nullptr);
-      alg_ += sell_bytes(d.A) + sizeof(T) * (double)n * 3;
+      residual(l, b, x, nullptr, d.r.get(), nullptr, s);
       r = d.r.get();
     }
     if (o.tri_mode == NAMG_TRI_NEUMANN) {
       if (t == 1) {
-        NAMG_LAUNCH((k_axpy<T>), gb, s, r, (const T *)d.ilu_dinv.get(), first ? nul : (const T *)x, x, n);
-        alg_ += sizeof(T) * (double)n * (first ? 3 : 4);
+        axpy(r, d.ilu_dinv.get(), first ? nul : (const T *)x, x, n, s);
         return;
       }
       const T *in = r;
       for (int q = 1; q < t; ++q) {
         const bool last = q == t - 1;
         T *out = last ? d.f.get() : pp[q & 1];
-        NAMG_LAUNCH((k_neumann<T>), gb, s, d.ilu_lo.view(), r, in, last ? (const T *)d.ilu_dinv.get() : nul, nul, out);
-        alg_ += sell_bytes(d.ilu_lo) + sizeof(T) * (double)n * (last ? 4 : 3);
+        neumann(l, d.ilu_lo, r, in, last ? (const T *)d.ilu_dinv.get() : nul, nul, out, s);
         in = out;
       }
       in = d.f.get();
       for (int q = 1; q < t; ++q) {
         const bool last = q == t - 1;
         T *out = last ? x : pp[q & 1];
-        NAMG_LAUNCH((k_neumann<T>), gb, s, d.ilu_up.view(), (const T *)d.f.get(), in, nul,
-                    (last && !first) ? (const T *)x : nul, out);
-        alg_ += sell_bytes(d.ilu_up) + sizeof(T) * (double)n * ((last && !first) ? 4 : 3);
+        neumann(l, d.ilu_up, d.f.get(), in, nul, (last && !first) ? (const T *)x : nul, out, s);
         in = out;
       }
     } else {
-      tri_solve(d.tri_ilu_lo, r, d.g1.get(), s);
-      NAMG_LAUNCH((k_axpy<T>), gb, s, (const T *)d.g1.get(), (const T *)d.ilu_dinv.get(), nul, d.f.get(), n);
-      tri_solve(d.tri_ilu_up, d.f.get(), d.g2.get(), s);
-      NAMG_LAUNCH((k_axpy<T>), gb, s, (const T *)d.g2.get(), nul, first ? nul : (const T *)x, x, n);
-      alg_ += sizeof(T) * (double)n * (first ? 5 : 6);
+      tri_solve(l, d.tri_ilu_lo, r, d.g1.get(), s);
+      axpy(d.g1.get(), d.ilu_dinv.get(), nul, d.f.get(), n, s);
+      tri_solve(l, d.tri_ilu_up, d.f.get(), d.g2.get(), s);
+      axpy(d.g2.get(), nul, first ? nul : (const T *)x, x, n, s);
     }
-  }
-
-  // g = (I + S)^{-1} f, one launch per dependency level.
-  void tri_solve(const DTri<T> &tr, const T *f, T *g, hipStream_t s) {
-    const int nlev = (int)tr.lev_ptr.size() - 1;
-    for (int k = 0; k < nlev; ++k) {
-      const int32_t beg = tr.lev_ptr[k], cnt = tr.lev_ptr[k + 1] - beg;
-      NAMG_LAUNCH((k_tri_level<T>), blocks_for(cnt), s, tr.rp.get(), tr.ci.get(), tr.val.get(), tr.order.get(), beg,
-                  cnt, f, g);
-    }
-    alg_ += tr.nnz * (sizeof(T) + 4.0) + sizeof(T) * (double)tr.n * 3 + 8.0 * tr.n;
   }
 
   // One V-cycle with zero initial guess (Section 5): pre-smooth, residual, restrict, recurse, prolong
@@ -472,42 +591,42 @@ class Solver final : public SolverBase {
   void vcycle(int l, const T *b, T *x, const CycleOpts &o, hipStream_t s) {
     const int nl = (int)lv_.size();
     if (l == nl - 1) {
-      NAMG_LAUNCH((k_dense_gemv<T>), blocks_for(nc_), s, coarse_invT_.get(), nc_, b, x);
-      alg_ += sizeof(T) * ((double)nc_ * nc_ + 2.0 * nc_);
+      coarse_solve(l, b, x, s);
       return;
     }
     DevLevel<T> &d = lv_[l];
     DevLevel<T> &c = lv_[l + 1];
     const int32_t n = d.n;
     const bool ilu = (o.smoother == NAMG_SMOOTH_ILU0) && d.has_ilu;
-    if (o.nu1 == 0) NAMG_LAUNCH((k_fill<T>), blocks_for(n), s, x, T(0), n);
+    if (o.nu1 == 0) launch(-1, l, S * n, &k_fill<T>, blocks_for(n), s, x, T(0), n);
     for (int k = 0; k < o.nu1; ++k) smooth(l, b, x, k == 0, true, ilu, o, s);
-    NAMG_LAUNCH((k_residual<T>), blocks_for(n), s, d.A.view(), b, (const T *)x, (const T *)nullptr, d.r.get(),
-                (T *)nullptr);
-    alg_ += sell_bytes(d.A) + sizeof(T) * (double)n * 3;
-    NAMG_LAUNCH((k_spmv<T, T, T, T>), blocks_for(c.n), s, d.R.view(), (const T *)d.r.get(), c.b.get());
-    alg_ += sell_bytes(d.R) + sizeof(T) * ((double)n + c.n);
+    residual(l, b, x, nullptr, d.r.get(), nullptr, s);
+    restrict_(l, s);
     vcycle(l + 1, c.b.get(), c.x.get(), o, s);
-    NAMG_LAUNCH((k_prolong<T>), blocks_for(n), s, d.P.view(), (const T *)c.x.get(), x);
-    alg_ += sell_bytes(d.P) + sizeof(T) * ((double)c.n + 2.0 * n);
+    prolong(l, x, s);
     for (int k = 0; k < o.nu2; ++k) smooth(l, b, x, false, false, ilu, o, s);
   }
 
   int dev_;
   MemCounter mc_;
   std::vector<DevLevel<T>> lv_;
-  DevBuf<T> coarse_invT_;
+  DMat<T> coarse_inv_;
   int32_t nc_ = 0;
-  DSell<double> A64_;
+  DMat<double> A64_;
   double anorm_inf_ = 0.0;
-  DevBuf<double> red_, V_, w_, dot_;
+  DevBuf<double> red_, V_, w_, dot_, cd_;
   DevBuf<T> Z_, vin_;
   DevBuf<KState> kst_;
   int ws_m_ = 0;
   int64_t ldv_ = 0, ldz_ = 0;
   int32_t nblk_red_ = 0, nblk_dot_ = 0, rows_per_dot_ = 0;
-  double *pinned_ = nullptr;
+  double *pinned_ = nullptr;      // host-mapped scalars: [0] estimate, [1] flag, [2] reductions
+  double *pinned_dev_ = nullptr;  // the same memory as seen from the device
   double alg_ = 0.0;
+  int prof_family_ = NAMG_KF_NONE, prof_level_ = -1;
+  namg_kernel_profile prof_{0, 0.0, 0.0};
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events_;
+  size_t ev_used_ = 0;
 };
 
 }  // namespace namg
@@ -624,6 +743,22 @@ int namg_apply(namg_hier *h, int level, int op, const namg_solve_params *p, cons
     if (!p || !out_dev) throw namg::SetupError{NAMG_E_INVALID, "null argument"};
     namg::validate_solve_params(*p);
     device_of(h)->apply(level, op, *p, in1_dev, in2_dev, out_dev, (hipStream_t)stream);
+    return NAMG_OK;
+  });
+}
+
+int namg_profile_kernel(namg_hier *h, int family, int level) {
+  return guarded([&]() -> int {
+    if (family < NAMG_KF_NONE || family > NAMG_KF_TRI) throw namg::SetupError{NAMG_E_INVALID, "unknown kernel family"};
+    device_of(h)->profile(family, level);
+    return NAMG_OK;
+  });
+}
+
+int namg_profile_read(namg_hier *h, namg_kernel_profile *out) {
+  return guarded([&]() -> int {
+    if (!out) throw namg::SetupError{NAMG_E_INVALID, "null argument"};
+    *out = device_of(h)->profile_read();
     return NAMG_OK;
   });
 }
