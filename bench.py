@@ -42,6 +42,11 @@ def _args():
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 
+# Measured HBM traffic of the dominant kernel (bytes per launch): rocprofv3 FETCH_SIZE x 2.000 plus
+# WRITE_SIZE x 1.000, factors from a 2 GiB copy (profiles/k_neumann_level0_c2_128cubed_traffic.md).
+# Valid for the kernel version it was taken on; None when the kernel has changed since.
+DOMINANT_TRAFFIC_BYTES = {("c2", 128, "fp64", "ilu0"): 132.7e6}
+
 
 def copy_ceiling(torch, nbytes=2 << 30, reps=10):
     """Device-to-device copy bandwidth (read + write bytes / time) as a practical HBM ceiling."""
@@ -160,7 +165,9 @@ def main():
         per_launch_ms = prof["total_ms"] / prof["launches"]
         achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                           "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                           "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                           "traffic": DOMINANT_TRAFFIC_BYTES.get((meta["name"], meta["N"], args.precision,
+                                                                  args.smoother)),
                            "kernel": "k_neumann<1,double> on level 0 (ILU(0) Neumann term, 128^3)",
                            "launches": prof["launches"], "avg_us": round(per_launch_ms * 1e3, 3),
                            "alg_MB_per_launch": round(per_launch_bytes / 1e6, 3)}

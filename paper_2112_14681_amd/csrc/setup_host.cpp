@@ -11,7 +11,10 @@
 #include "setup_host.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 
@@ -458,6 +461,10 @@ HostHierarchy build_hierarchy(const HostCsr &A0, double theta, int max_levels, i
   if (max_levels < 1 || max_levels > NAMG_MAX_LEVELS) fail(NAMG_E_INVALID, "max_levels out of range");
   if (max_coarse < 1) fail(NAMG_E_INVALID, "max_coarse must be >= 1");
   HostHierarchy H;
+  const bool trace = std::getenv("NAMG_SETUP_TRACE") != nullptr;
+  double t_str = 0, t_rs = 0, t_int = 0, t_rap = 0;
+  auto now = [] { return std::chrono::steady_clock::now(); };
+  auto secs = [](auto a, auto b) { return std::chrono::duration<double>(b - a).count(); };
   for (int32_t i = 0; i < A0.nr; ++i) {
     double s = 0.0;
     for (int32_t k = A0.rp[i]; k < A0.rp[i + 1]; ++k) s += std::fabs(A0.v[k]);
@@ -469,12 +476,21 @@ HostHierarchy build_hierarchy(const HostCsr &A0, double theta, int max_levels, i
     HostLevel &L = H.lv.back();
     const int32_t n = L.A.nr;
     if (n <= max_coarse || (int)H.lv.size() >= max_levels) break;
+    auto t0 = now();
     Graph S = strength_graph(L.A, theta);
+    auto t1 = now();
     std::vector<int8_t> cf = rs_coarsen(S, n);
+    auto t2 = now();
     HostCsr P = classical_interpolation(L.A, S, cf);
+    auto t3 = now();
     if (P.nc == 0 || P.nc == n) break;
     HostCsr R = transpose_csr(P);
     HostCsr Ac = spgemm(R, spgemm(L.A, P));
+    auto t4 = now();
+    t_str += secs(t0, t1);
+    t_rs += secs(t1, t2);
+    t_int += secs(t2, t3);
+    t_rap += secs(t3, t4);
     for (int32_t i = 0; i < Ac.nr; ++i)
       if (diagonal(Ac, i) == 0.0) fail(NAMG_E_ZERO_PIVOT, "zero diagonal in a coarse operator");
     L.cf = std::move(cf);
@@ -485,10 +501,14 @@ HostHierarchy build_hierarchy(const HostCsr &A0, double theta, int max_levels, i
     H.lv.push_back(std::move(next));
   }
   const int nl = (int)H.lv.size();
+  auto t5 = now();
   for (int l = 0; l < nl - 1; ++l) smoother_data(H.lv[l], ilu_levels < 0 || l < ilu_levels);
   const HostCsr &Ac = H.lv.back().A;
   if (Ac.nr > 4096) fail(NAMG_E_INVALID, "coarsest level has more than 4096 rows; raise max_levels");
   H.coarse_inv = dense_inverse(Ac);
+  if (trace)
+    std::fprintf(stderr, "[namg setup] strength %.3f rs %.3f interp %.3f rap %.3f smoother+coarse %.3f s\n", t_str,
+                 t_rs, t_int, t_rap, secs(t5, now()));
   return H;
 }
 
