@@ -72,41 +72,74 @@ Graph transpose_graph(const Graph &S, int32_t n) {
 }
 
 // ---- Ruge-Stueben first pass ------------------------------------------------------------------------
-// Max-measure selection with a segment tree over the point index: each leaf holds the measure of an
-// undecided point (-1 once decided); an inner node keeps the larger measure, the smaller index on ties,
-// so the root is always the point to colour next.
-class MeasureTree {
+// Undecided points are kept in one bucket per measure value. A bucket is a 64-ary tree of bitsets over the
+// point index, so its smallest member is found with one count-trailing-zeros per tree level, and a point
+// moves between buckets in O(1) word updates. The next point to colour is the smallest index in the
+// highest non-empty bucket: the largest measure, ties broken by the smallest index.
+class BitTree {
  public:
-  explicit MeasureTree(int32_t n) : n_(n) {
-    size_ = 1;
-    while (size_ < std::max<int32_t>(n, 1)) size_ <<= 1;
-    val_.assign(2 * size_, -1);
-    idx_.assign(2 * size_, INT32_MAX);
-    for (int32_t i = 0; i < size_; ++i) idx_[size_ + i] = i;
-    for (int32_t p = size_ - 1; p >= 1; --p) pull(p);
+  void init(int32_t n) {
+    size_t m = (size_t)std::max<int32_t>(n, 1);
+    do {
+      const size_t words = (m + 63) / 64;
+      lv_.emplace_back(words, 0ull);
+      m = words;
+    } while (m > 1);
   }
-  void set(int32_t i, int32_t v) {
-    int32_t p = size_ + i;
-    val_[p] = v;
-    for (p >>= 1; p >= 1; p >>= 1) pull(p);
-  }
-  void add(int32_t i, int32_t d) { set(i, val_[size_ + i] + d); }
-  int32_t top_value() const { return val_[1]; }
-  int32_t top_index() const { return idx_[1]; }
-
- private:
-  void pull(int32_t p) {
-    const int32_t l = 2 * p, r = 2 * p + 1;
-    if (val_[r] > val_[l]) {
-      val_[p] = val_[r];
-      idx_[p] = idx_[r];
-    } else {
-      val_[p] = val_[l];
-      idx_[p] = idx_[l];
+  bool ready() const { return !lv_.empty(); }
+  void set(int32_t i) {
+    size_t bit = (size_t)i;
+    for (auto &L : lv_) {
+      uint64_t &w = L[bit >> 6];
+      const bool was_empty = (w == 0);
+      w |= 1ull << (bit & 63);
+      if (!was_empty) break;
+      bit >>= 6;
     }
   }
-  int32_t n_, size_;
-  std::vector<int32_t> val_, idx_;
+  void clear(int32_t i) {
+    size_t bit = (size_t)i;
+    for (auto &L : lv_) {
+      uint64_t &w = L[bit >> 6];
+      w &= ~(1ull << (bit & 63));
+      if (w != 0) break;
+      bit >>= 6;
+    }
+  }
+  int32_t first() const {
+    size_t word = 0;
+    for (int k = (int)lv_.size() - 1; k >= 0; --k) word = word * 64 + (size_t)__builtin_ctzll(lv_[k][word]);
+    return (int32_t)word;
+  }
+
+ private:
+  std::vector<std::vector<uint64_t>> lv_;
+};
+
+class MeasureBuckets {
+ public:
+  MeasureBuckets(int32_t n, int32_t max_measure) : n_(n), tree_(max_measure + 1), count_(max_measure + 1, 0) {}
+  void insert(int32_t i, int32_t m) {
+    if (!tree_[m].ready()) tree_[m].init(n_);
+    tree_[m].set(i);
+    count_[m]++;
+    if (m > top_) top_ = m;
+  }
+  void erase(int32_t i, int32_t m) {
+    tree_[m].clear(i);
+    count_[m]--;
+  }
+  bool empty() {
+    while (top_ >= 0 && count_[top_] == 0) --top_;
+    return top_ < 0;
+  }
+  int32_t top() const { return top_; }
+  int32_t smallest_in_top() const { return tree_[top_].first(); }
+
+ private:
+  int32_t n_, top_ = -1;
+  std::vector<BitTree> tree_;
+  std::vector<int32_t> count_;
 };
 
 // C/F splitting (1 = C, 0 = F). Measure lambda_i = |S^T_i & U| + 2 |S^T_i & F|, maintained incrementally:
@@ -115,32 +148,47 @@ std::vector<int8_t> rs_coarsen(const Graph &S, int32_t n) {
   const Graph ST = transpose_graph(S, n);
   enum : int8_t { UNDECIDED = -1, FPT = 0, CPT = 1 };
   std::vector<int8_t> st(n, UNDECIDED);
-  MeasureTree tree(n);
+  std::vector<int32_t> lam(n, 0);
+  int32_t maxm = 0;
+  for (int32_t i = 0; i < n; ++i) maxm = std::max(maxm, 2 * (ST.rp[i + 1] - ST.rp[i]));
+  MeasureBuckets B(n, maxm);
   for (int32_t i = 0; i < n; ++i) {
-    if (S.rp[i + 1] == S.rp[i] && ST.rp[i + 1] == ST.rp[i])
+    if (S.rp[i + 1] == S.rp[i] && ST.rp[i + 1] == ST.rp[i]) {
       st[i] = FPT;
-    else
-      tree.set(i, ST.rp[i + 1] - ST.rp[i]);
+    } else {
+      lam[i] = ST.rp[i + 1] - ST.rp[i];
+      B.insert(i, lam[i]);
+    }
   }
   std::vector<int32_t> fresh;
-  while (tree.top_value() >= 0) {
-    const int32_t i = tree.top_index();
+  while (!B.empty()) {
+    const int32_t i = B.smallest_in_top();
+    B.erase(i, lam[i]);
     st[i] = CPT;
-    tree.set(i, -1);
     fresh.clear();
     for (int32_t k = ST.rp[i]; k < ST.rp[i + 1]; ++k) {
       const int32_t j = ST.ci[k];
       if (st[j] == UNDECIDED) {
         st[j] = FPT;
-        tree.set(j, -1);
+        B.erase(j, lam[j]);
         fresh.push_back(j);
       }
     }
     for (int32_t j : fresh)
-      for (int32_t k = S.rp[j]; k < S.rp[j + 1]; ++k)
-        if (st[S.ci[k]] == UNDECIDED) tree.add(S.ci[k], 1);
-    for (int32_t k = S.rp[i]; k < S.rp[i + 1]; ++k)
-      if (st[S.ci[k]] == UNDECIDED) tree.add(S.ci[k], -1);
+      for (int32_t k = S.rp[j]; k < S.rp[j + 1]; ++k) {
+        const int32_t q = S.ci[k];
+        if (st[q] == UNDECIDED) {
+          B.erase(q, lam[q]);
+          B.insert(q, ++lam[q]);
+        }
+      }
+    for (int32_t k = S.rp[i]; k < S.rp[i + 1]; ++k) {
+      const int32_t q = S.ci[k];
+      if (st[q] == UNDECIDED) {
+        B.erase(q, lam[q]);
+        B.insert(q, --lam[q]);
+      }
+    }
   }
   return st;
 }
@@ -158,7 +206,7 @@ HostCsr classical_interpolation(const HostCsr &A, const Graph &S, const std::vec
   P.rp.assign(n + 1, 0);
   // role[j] for the current row: 0 none, 1 strong C, 2 strong F, 3 strong F treated as weak
   std::vector<int8_t> role(n, 0);
-  std::vector<double> num(n, 0.0), dens;
+  std::vector<double> num(n, 0.0), aval(n, 0.0), dens;
   std::vector<int32_t> strongF;
   for (int32_t i = 0; i < n; ++i) {
     if (cf[i] == 1) {
@@ -201,16 +249,14 @@ HostCsr classical_interpolation(const HostCsr &A, const Graph &S, const std::vec
       for (int32_t p = A.rp[i]; p < A.rp[i + 1]; ++p)
         if (role[A.ci[p]] == 1) num[A.ci[p]] = A.v[p];
       // strong F neighbours in ascending order; their rows distribute into the strong C set
-      std::vector<double> aik(strongF.size());
-      for (int32_t p = A.rp[i]; p < A.rp[i + 1]; ++p)
-        for (size_t q = 0; q < strongF.size(); ++q)
-          if (strongF[q] == A.ci[p]) aik[q] = A.v[p];
+      for (int32_t p = A.rp[i]; p < A.rp[i + 1]; ++p) aval[A.ci[p]] = A.v[p];
       for (size_t q = 0; q < strongF.size(); ++q) {
         if (dens[q] == 0.0) continue;
         const int32_t k = strongF[q];
+        const double aik = aval[k];
         for (int32_t p = A.rp[k]; p < A.rp[k + 1]; ++p) {
           const int32_t j = A.ci[p];
-          if (role[j] == 1) num[j] += (aik[q] * A.v[p]) / dens[q];
+          if (role[j] == 1) num[j] += (aik * A.v[p]) / dens[q];
         }
       }
       for (int32_t k = S.rp[i]; k < S.rp[i + 1]; ++k) {
@@ -331,27 +377,6 @@ HostCsr strict_part(const HostCsr &A, const std::vector<double> &vals, bool lowe
   return T;
 }
 
-LevelSchedule schedule(const HostCsr &T, bool lower) {
-  const int32_t n = T.nr;
-  std::vector<int32_t> lev(n, 0);
-  int32_t nlev = 0;
-  for (int32_t q = 0; q < n; ++q) {
-    const int32_t i = lower ? q : n - 1 - q;
-    int32_t l = 0;
-    for (int32_t k = T.rp[i]; k < T.rp[i + 1]; ++k) l = std::max(l, lev[T.ci[k]] + 1);
-    lev[i] = l;
-    nlev = std::max(nlev, l + 1);
-  }
-  LevelSchedule s;
-  s.ptr.assign(nlev + 1, 0);
-  for (int32_t i = 0; i < n; ++i) s.ptr[lev[i] + 1]++;
-  for (int32_t l = 0; l < nlev; ++l) s.ptr[l + 1] += s.ptr[l];
-  s.order.resize(n);
-  std::vector<int32_t> fill(s.ptr.begin(), s.ptr.end() - 1);
-  for (int32_t i = 0; i < n; ++i) s.order[fill[lev[i]]++] = i;
-  return s;
-}
-
 std::vector<double> dense_inverse(const HostCsr &A) {
   const int32_t n = A.nr;
   std::vector<double> a((size_t)n * n, 0.0), inv((size_t)n * n, 0.0);
@@ -404,8 +429,6 @@ void smoother_data(HostLevel &L, bool with_ilu) {
     for (int32_t k = L.pgs_lo.rp[i]; k < L.pgs_lo.rp[i + 1]; ++k) L.pgs_lo.v[k] /= d;
     for (int32_t k = L.pgs_up.rp[i]; k < L.pgs_up.rp[i + 1]; ++k) L.pgs_up.v[k] /= d;
   }
-  L.pgs_lo_sched = schedule(L.pgs_lo, true);
-  L.pgs_up_sched = schedule(L.pgs_up, false);
   if (with_ilu) {
     std::vector<double> w = ilu0_values(A);
     L.has_ilu = true;
@@ -419,12 +442,31 @@ void smoother_data(HostLevel &L, bool with_ilu) {
     L.ilu_up = strict_part(A, w, false, {});
     for (int32_t i = 0; i < A.nr; ++i)
       for (int32_t k = L.ilu_up.rp[i]; k < L.ilu_up.rp[i + 1]; ++k) L.ilu_up.v[k] /= du[i];
-    L.ilu_lo_sched = schedule(L.ilu_lo, true);
-    L.ilu_up_sched = schedule(L.ilu_up, false);
   }
 }
 
 }  // namespace
+
+LevelSchedule level_schedule(const HostCsr &T, bool lower) {
+  const int32_t n = T.nr;
+  std::vector<int32_t> lev(n, 0);
+  int32_t nlev = 0;
+  for (int32_t q = 0; q < n; ++q) {
+    const int32_t i = lower ? q : n - 1 - q;
+    int32_t l = 0;
+    for (int32_t k = T.rp[i]; k < T.rp[i + 1]; ++k) l = std::max(l, lev[T.ci[k]] + 1);
+    lev[i] = l;
+    nlev = std::max(nlev, l + 1);
+  }
+  LevelSchedule s;
+  s.ptr.assign(nlev + 1, 0);
+  for (int32_t i = 0; i < n; ++i) s.ptr[lev[i] + 1]++;
+  for (int32_t l = 0; l < nlev; ++l) s.ptr[l + 1] += s.ptr[l];
+  s.order.resize(n);
+  std::vector<int32_t> fill(s.ptr.begin(), s.ptr.end() - 1);
+  for (int32_t i = 0; i < n; ++i) s.order[fill[lev[i]]++] = i;
+  return s;
+}
 
 HostCsr import_csr(int32_t n, const int32_t *rp, const int32_t *ci, const double *v) {
   if (n < 1) fail(NAMG_E_INVALID, "n must be >= 1");

@@ -33,11 +33,9 @@ struct HostLevel {
   std::vector<int8_t> cf;
   std::vector<double> dinv;    // 1 / a_ii
   HostCsr pgs_lo, pgs_up;      // D^{-1} L and D^{-1} U: strict parts of A scaled by the row's diagonal
-  LevelSchedule pgs_lo_sched, pgs_up_sched;
   bool has_ilu = false;
   HostCsr ilu_lo, ilu_up;      // L_s (strict lower of the unit-diagonal L) and U_s = D_U^{-1} U - I
   std::vector<double> ilu_dinv;  // 1 / u_ii
-  LevelSchedule ilu_lo_sched, ilu_up_sched;
 };
 
 struct HostHierarchy {
@@ -50,5 +48,8 @@ struct HostHierarchy {
 HostCsr import_csr(int32_t n, const int32_t *rp, const int32_t *ci, const double *v);
 
 HostHierarchy build_hierarchy(const HostCsr &A, double theta, int max_levels, int max_coarse, int ilu_levels);
+
+// Dependency levels of a strict lower (lower = true) or upper triangle, for the direct comparators.
+LevelSchedule level_schedule(const HostCsr &T, bool lower);
 
 }  // namespace namg

@@ -121,7 +121,7 @@ class Solver final : public SolverBase {
   static constexpr double S = sizeof(T);
 
  public:
-  Solver(const HostHierarchy &H, int device) : dev_(device) {
+  Solver(const HostHierarchy &H, int device) : dev_(device), host_(&H) {
     DeviceGuard g(dev_);
     const uint32_t kf = kernel_flags();
     const int nl = (int)H.lv.size();
@@ -139,15 +139,11 @@ class Solver final : public SolverBase {
       d.pgs_lo.build(h.pgs_lo, &mc_, 0, kf);
       d.pgs_up.build(h.pgs_up, &mc_, 0, kf);
       upload_vec(d.dinv, h.dinv);
-      d.tri_pgs_lo.build(h.pgs_lo, h.pgs_lo_sched, &mc_);
-      d.tri_pgs_up.build(h.pgs_up, h.pgs_up_sched, &mc_);
       d.has_ilu = h.has_ilu;
       if (h.has_ilu) {
         d.ilu_lo.build(h.ilu_lo, &mc_, 0, kf);
         d.ilu_up.build(h.ilu_up, &mc_, 0, kf);
         upload_vec(d.ilu_dinv, h.ilu_dinv);
-        d.tri_ilu_lo.build(h.ilu_lo, h.ilu_lo_sched, &mc_);
-        d.tri_ilu_up.build(h.ilu_up, h.ilu_up_sched, &mc_);
       }
       d.r.alloc(d.n, &mc_);
       d.f.alloc(d.n, &mc_);
@@ -207,6 +203,7 @@ class Solver final : public SolverBase {
     DeviceGuard g(dev_);
     const int32_t n = lv_[0].n;
     CycleOpts o = cycle_opts(p);
+    if (o.tri_mode == NAMG_TRI_DIRECT) ensure_direct();
     if constexpr (std::is_same<T, double>::value) {
       vcycle(0, b, x, o, s);
     } else {
@@ -222,6 +219,7 @@ class Solver final : public SolverBase {
     const int nl = (int)lv_.size();
     if (level < 0 || level >= nl) throw SetupError{NAMG_E_INVALID, "level out of range"};
     CycleOpts o = cycle_opts(p);
+    if (o.tri_mode == NAMG_TRI_DIRECT) ensure_direct();
     if (!in1) throw SetupError{NAMG_E_INVALID, "missing operand"};
     if (op == NAMG_OP_SPMV64) {
       if (level != 0) throw SetupError{NAMG_E_INVALID, "SPMV64 is defined on level 0 only"};
@@ -294,6 +292,7 @@ class Solver final : public SolverBase {
     hip_check(hipEventCreate(&e1), "hipEventCreate");
     hip_check(hipEventRecord(e0, s), "hipEventRecord");
     const CycleOpts o = cycle_opts(p);
+    if (o.tri_mode == NAMG_TRI_DIRECT) ensure_direct();
     const bool trace = std::getenv("NAMG_TRACE") != nullptr;
     KState *ks = kst_.get();
     double *cd = cd_.get();
@@ -607,7 +606,25 @@ class Solver final : public SolverBase {
     for (int k = 0; k < o.nu2; ++k) smooth(l, b, x, false, false, ilu, o, s);
   }
 
+  // Level schedules and CSR copies for the direct comparators, built on their first use.
+  void ensure_direct() {
+    if (direct_ready_) return;
+    for (size_t l = 0; l + 1 < lv_.size(); ++l) {
+      const HostLevel &h = host_->lv[l];
+      DevLevel<T> &d = lv_[l];
+      d.tri_pgs_lo.build(h.pgs_lo, level_schedule(h.pgs_lo, true), &mc_);
+      d.tri_pgs_up.build(h.pgs_up, level_schedule(h.pgs_up, false), &mc_);
+      if (h.has_ilu) {
+        d.tri_ilu_lo.build(h.ilu_lo, level_schedule(h.ilu_lo, true), &mc_);
+        d.tri_ilu_up.build(h.ilu_up, level_schedule(h.ilu_up, false), &mc_);
+      }
+    }
+    direct_ready_ = true;
+  }
+
   int dev_;
+  const HostHierarchy *host_;
+  bool direct_ready_ = false;
   MemCounter mc_;
   std::vector<DevLevel<T>> lv_;
   DMat<T> coarse_inv_;
