@@ -167,6 +167,60 @@ int namg_level_sizes(const namg_hier *h, int level, int32_t *n, int64_t *nnzA, i
 int namg_export_level(const namg_hier *h, int level, int8_t *cf, int32_t *A_rowptr, int32_t *A_colind,
                       double *A_vals, int32_t *P_rowptr, int32_t *P_colind, double *P_vals);
 
+/* ---- Serving (continuous batching of many solves on one GPU) ------------------------------------- */
+
+typedef struct namg_server namg_server; /* opaque; owns its threads, stream and in-flight solves */
+
+typedef struct {
+  int64_t hbm_budget;  /* device bytes the in-flight solves may hold; <= 0: device memory - 16 GiB */
+  int max_inflight;    /* solves advanced together per scheduler tick, 1..256 */
+  int setup_threads;   /* host threads running the AMG setup of queued requests */
+  int device;          /* HIP device ordinal */
+  int precision;       /* NAMG_FP64 or NAMG_FP32_PRECOND, for every request */
+  namg_solve_params solve; /* shared by every request; tri_mode must be NAMG_TRI_NEUMANN */
+} namg_server_params;
+
+typedef struct {
+  double submit, setup_start, setup_done, admitted, done; /* seconds on the server's clock */
+} namg_request_times;
+
+typedef struct {
+  int64_t submitted, completed, failed, inflight, waiting, ticks, launches;
+  int64_t device_bytes_in_use, peak_device_bytes, peak_inflight;
+} namg_server_counters;
+
+void namg_default_server_params(namg_server_params *p);
+
+/* Start a server: setup threads, one scheduler thread and its stream. Requests are set up on the host
+ * (as namg_setup), admitted in order of setup completion when a slot is free and their exact device
+ * footprint fits the budget, and then advanced together: every scheduler tick moves every in-flight
+ * solve by one Arnoldi step of Algorithm 1 (or one restart-cycle boundary), with each V-cycle row
+ * operation and each Krylov kernel issued as one batched launch for all of them. Solves leave at tick
+ * boundaries and free their memory; waiting requests are admitted while the others keep running.
+ * Errors: NAMG_E_INVALID (bad parameters), NAMG_E_HIP. */
+int namg_server_create(const namg_server_params *p, namg_server **out);
+
+/* Queue one system A x = b (host CSR and b, copied; x0 = 0) with its setup parameters (precision and
+ * device come from the server). Returns at once with a ticket. */
+int namg_server_submit(namg_server *s, int32_t n, const int32_t *rowptr, const int32_t *colind, const double *vals,
+                       const double *b, const namg_setup_params *sp, uint64_t *ticket);
+
+/* NAMG_PENDING while the request is queued or in flight. Once it has finished: copies x (n doubles,
+ * host, may be NULL), its statistics and times, forgets the ticket and returns its status (NAMG_OK,
+ * NAMG_NOT_CONVERGED or the error of its setup or solve, e.g. NAMG_E_BUDGET). */
+int namg_server_poll(namg_server *s, uint64_t ticket, double *x, namg_solve_stats *st, namg_request_times *tm);
+
+/* As namg_server_poll, but blocks until the request has finished. */
+int namg_server_wait(namg_server *s, uint64_t ticket, double *x, namg_solve_stats *st, namg_request_times *tm);
+
+int namg_server_stats(namg_server *s, namg_server_counters *out);
+
+/* Seconds since the server started (the clock of namg_request_times). */
+double namg_server_clock(const namg_server *s);
+
+/* Stop the threads and release everything; requests still queued or in flight are dropped. */
+void namg_server_destroy(namg_server *s);
+
 /* Release the hierarchy and all its device memory. NULL is ignored. */
 void namg_destroy(namg_hier *h);
 

@@ -29,7 +29,9 @@ KF_NONE, KF_NEUMANN, KF_RESIDUAL, KF_SPMV, KF_PROLONG, KF_GMRES_SPMV, KF_MULTIDO
 EXPORTED = (
     "namg_default_setup_params", "namg_default_solve_params", "namg_setup", "namg_solve", "namg_vcycle",
     "namg_apply", "namg_profile_kernel", "namg_profile_read", "namg_hier_info", "namg_level_sizes",
-    "namg_export_level", "namg_destroy", "namg_last_error",
+    "namg_export_level", "namg_destroy", "namg_last_error", "namg_default_server_params", "namg_server_create",
+    "namg_server_submit", "namg_server_poll", "namg_server_wait", "namg_server_stats", "namg_server_clock",
+    "namg_server_destroy",
 )
 
 
@@ -62,6 +64,28 @@ class HierInfo(C.Structure):
                 ("op_complexity", C.c_double), ("grid_complexity", C.c_double), ("device_bytes", C.c_int64)]
 
 
+class ServerParams(C.Structure):
+    _fields_ = [("hbm_budget", C.c_int64), ("max_inflight", C.c_int), ("setup_threads", C.c_int), ("device", C.c_int),
+                ("precision", C.c_int), ("solve", SolveParams)]
+
+
+class RequestTimes(C.Structure):
+    _fields_ = [("submit", C.c_double), ("setup_start", C.c_double), ("setup_done", C.c_double),
+                ("admitted", C.c_double), ("done", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ServerCounters(C.Structure):
+    _fields_ = [(name, C.c_int64) for name in ("submitted", "completed", "failed", "inflight", "waiting", "ticks",
+                                               "launches", "device_bytes_in_use", "peak_device_bytes",
+                                               "peak_inflight")]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class NamgError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"namg error {code}: {msg}")
@@ -89,6 +113,17 @@ def _load():
     lib.namg_last_error.restype = C.c_char_p
     lib.namg_default_setup_params.argtypes = [C.POINTER(SetupParams)]
     lib.namg_default_solve_params.argtypes = [C.POINTER(SolveParams)]
+    lib.namg_default_server_params.argtypes = [C.POINTER(ServerParams)]
+    lib.namg_server_create.argtypes = [C.POINTER(ServerParams), C.POINTER(vp)]
+    lib.namg_server_submit.argtypes = [vp, C.c_int32, i32p, i32p, f64p, f64p, C.POINTER(SetupParams),
+                                       C.POINTER(C.c_uint64)]
+    lib.namg_server_poll.argtypes = [vp, C.c_uint64, f64p, C.POINTER(SolveStats), C.POINTER(RequestTimes)]
+    lib.namg_server_wait.argtypes = [vp, C.c_uint64, f64p, C.POINTER(SolveStats), C.POINTER(RequestTimes)]
+    lib.namg_server_stats.argtypes = [vp, C.POINTER(ServerCounters)]
+    lib.namg_server_clock.argtypes = [vp]
+    lib.namg_server_clock.restype = C.c_double
+    lib.namg_server_destroy.argtypes = [vp]
+    lib.namg_server_destroy.restype = None
     return lib
 
 
@@ -224,3 +259,76 @@ class Hierarchy:
         p = solve_params(**params)
         _check(_lib.namg_apply(self.h, level, op, C.byref(p), _dev_ptr(in1), _dev_ptr(in2), _dev_ptr(out),
                                _stream(stream)))
+
+
+def server_params(solve=None, **kw) -> ServerParams:
+    p = ServerParams()
+    _lib.namg_default_server_params(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    for k, v in (solve or {}).items():
+        setattr(p.solve, k, v)
+    return p
+
+
+class Server:
+    """Continuous-batching request server (namg_server_*): submit host systems, poll or wait for x."""
+
+    def __init__(self, solve=None, **params):
+        self.params = server_params(solve, **params)
+        h = C.c_void_p()
+        _check(_lib.namg_server_create(C.byref(self.params), C.byref(h)))
+        self.h = h
+        self._sizes = {}
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            _lib.namg_server_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def clock(self) -> float:
+        return _lib.namg_server_clock(self.h)
+
+    def submit(self, A, b, **setup) -> int:
+        rp = np.ascontiguousarray(A.rowptr, dtype=np.int32)
+        ci = np.ascontiguousarray(A.colind, dtype=np.int32)
+        v = np.ascontiguousarray(A.vals, dtype=np.float64)
+        bb = np.ascontiguousarray(b, dtype=np.float64)
+        sp = setup_params(**setup)
+        t = C.c_uint64()
+        _check(_lib.namg_server_submit(self.h, int(A.n), _ptr(rp, C.c_int32), _ptr(ci, C.c_int32), _ptr(v, C.c_double),
+                                       _ptr(bb, C.c_double), C.byref(sp), C.byref(t)))
+        self._sizes[t.value] = int(A.n)
+        return t.value
+
+    def _result(self, fn, ticket):
+        n = self._sizes[ticket]
+        x = np.zeros(n)
+        st, tm = SolveStats(), RequestTimes()
+        code = fn(self.h, ticket, _ptr(x, C.c_double), C.byref(st), C.byref(tm))
+        if code == PENDING:
+            return None
+        del self._sizes[ticket]
+        if code < 0:
+            raise NamgError(code, _lib.namg_last_error().decode())
+        out = st.as_dict()
+        out.update(status=code, x=x, times=tm.as_dict())
+        return out
+
+    def poll(self, ticket):
+        """None while pending, else the result dict (x, statistics, times)."""
+        return self._result(_lib.namg_server_poll, ticket)
+
+    def wait(self, ticket):
+        return self._result(_lib.namg_server_wait, ticket)
+
+    def stats(self) -> dict:
+        c = ServerCounters()
+        _check(_lib.namg_server_stats(self.h, C.byref(c)))
+        return c.as_dict()

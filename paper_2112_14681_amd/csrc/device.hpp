@@ -92,20 +92,12 @@ class DevBuf {
 // Row order and the order of entries within a row are those of the CSR input.
 constexpr int SELL_C = 64;
 
-// Launch-shape flags carried by every matrix view (set per hierarchy):
-//   KF_XCD_REMAP: workgroups are dispatched round-robin over the 8 XCDs; remap the block index so that
-//                 each XCD streams one contiguous range of rows and its L2 sees the stencil neighbours;
-//   KF_NT_LOADS:  matrix values and column indices are streamed once: load them nontemporally so that
-//                 they do not evict the gathered vector from the caches.
-constexpr uint32_t KF_XCD_REMAP = 1u, KF_NT_LOADS = 2u;
-
 template <class T>
 struct MatView {
   const int32_t *ptr = nullptr;  // SELL slice pointers (group 1) or CSR row pointers (group > 1)
   const int32_t *col = nullptr;
   const T *val = nullptr;
   int32_t nrows = 0;
-  uint32_t flags = 0;
 };
 
 // Lanes per row for a matrix with the given shape: one lane when rows are short or the matrix is large
@@ -122,18 +114,16 @@ template <class T>
 struct DMat {
   int32_t nrows = 0, ncols = 0, group = 1;
   int64_t nnz = 0, stored = 0;
-  uint32_t flags = 0;
   DevBuf<int32_t> ptr, col;
   DevBuf<T> val;
-  MatView<T> view() const { return MatView<T>{ptr.get(), col.get(), val.get(), nrows, flags}; }
+  MatView<T> view() const { return MatView<T>{ptr.get(), col.get(), val.get(), nrows}; }
   // algorithmic bytes of one pass over the matrix (entries once, row/slice pointers once)
   double bytes() const {
     const double nptr = group > 1 ? (double)nrows + 1.0 : (double)((nrows + SELL_C - 1) / SELL_C) + 1.0;
     return (double)nnz * (sizeof(T) + 4.0) + 4.0 * nptr;
   }
 
-  void build(const HostCsr &A, MemCounter *mc, int force_group, uint32_t kflags) {
-    flags = kflags;
+  void build(const HostCsr &A, MemCounter *mc, int force_group = 0) {
     nrows = A.nr;
     ncols = A.nc;
     nnz = A.nnz();

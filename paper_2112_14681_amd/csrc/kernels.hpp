@@ -2,10 +2,15 @@
 //
 // Every hot kernel is a streaming sparse or vector operation (arithmetic intensity <= 0.25 flop/byte),
 // so the HBM roofline bounds them; none is a dense contraction, and MFMA is not used. Sparse operators
-// use the SELL-64 layout (one wavefront per slice of 64 rows, one row per lane): the value and column
-// loads of a wavefront are 512 B / 256 B contiguous, and the x-gathers of a 3-D stencil hit the same or
-// neighbouring cache lines. Reductions are deterministic: a fixed xor-butterfly inside the wavefront,
-// a fixed order across wavefronts and blocks, no floating-point atomics.
+// use SELL-64 (one lane per row, contiguous wavefront loads) or CSR with a lane group per row (long
+// coarse-level rows). Reductions are deterministic: a fixed xor-butterfly inside the wavefront, a fixed
+// order across wavefronts and blocks, no floating-point atomics.
+//
+// Each kernel is a __device__ body taking its block index within one problem. Two kinds of launch use
+// the same bodies: the single-problem kernels (k_*), and the batched kernels (kb_*). A batched kernel
+// serves every in-flight solve of the serving scheduler in one launch: a task table lists one problem
+// per entry, and a prefix table of block offsets maps each block to its task. Because the per-row
+// arithmetic and the reduction partitions are the same, a solve gives bit-identical results either way.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -16,6 +21,7 @@ namespace namg {
 
 constexpr int BLK = 256;
 constexpr int WAVES = BLK / 64;
+constexpr int MAX_BATCH = 256;  // tasks per batched launch
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + BLK - 1) / BLK); }
 
@@ -25,68 +31,62 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Block sum of one double; the result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double *lds) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < WAVES; ++q) t += lds[q];
+  __syncthreads();
+  return t;
+}
+
 // Row `row` of a sparse matrix times x, reduced over the G lanes of the row's group (every lane of the
 // group returns the full sum). G == 1: SELL-64, one lane per row. G > 1: CSR, lane `sub` takes entries
 // sub, sub + G, ...; groups are aligned inside the wavefront, so the butterfly never leaves the group.
 template <int G, class Acc, class TM, class TX>
 __device__ __forceinline__ Acc row_dot(const MatView<TM> &A, const TX *__restrict__ x, int32_t row, int sub) {
   Acc acc = Acc(0);
-  const bool nt = (A.flags & KF_NT_LOADS) != 0;
   if constexpr (G == 1) {
     const int32_t s = row >> 6;
     const int32_t end = A.ptr[s + 1];
-    if (nt) {
 #pragma unroll 4
-      for (int32_t k = A.ptr[s] + (row & 63); k < end; k += SELL_C)
-        acc += (Acc)__builtin_nontemporal_load(A.val + k) * (Acc)x[__builtin_nontemporal_load(A.col + k)];
-    } else {
-#pragma unroll 4
-      for (int32_t k = A.ptr[s] + (row & 63); k < end; k += SELL_C) acc += (Acc)A.val[k] * (Acc)x[A.col[k]];
-    }
+    for (int32_t k = A.ptr[s] + (row & 63); k < end; k += SELL_C) acc += (Acc)A.val[k] * (Acc)x[A.col[k]];
   } else {
     const int32_t end = A.ptr[row + 1];
-    if (nt) {
 #pragma unroll 2
-      for (int32_t k = A.ptr[row] + sub; k < end; k += G)
-        acc += (Acc)__builtin_nontemporal_load(A.val + k) * (Acc)x[__builtin_nontemporal_load(A.col + k)];
-    } else {
-#pragma unroll 2
-      for (int32_t k = A.ptr[row] + sub; k < end; k += G) acc += (Acc)A.val[k] * (Acc)x[A.col[k]];
-    }
+    for (int32_t k = A.ptr[row] + sub; k < end; k += G) acc += (Acc)A.val[k] * (Acc)x[A.col[k]];
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
   }
   return acc;
 }
 
-// Logical block index: with KF_XCD_REMAP, XCD x (which receives blocks x, x+8, x+16, ...) is given the
-// contiguous logical range [x*q + min(x, r), ...) of the nb = 8q + r blocks.
-__device__ __forceinline__ uint32_t logical_block(uint32_t flags) {
-  const uint32_t b = blockIdx.x;
-  if (!(flags & KF_XCD_REMAP)) return b;
-  const uint32_t nb = gridDim.x, q = nb >> 3, r = nb & 7u, x = b & 7u;
-  return x * q + min(x, r) + (b >> 3);
-}
+#define NAMG_ROWS(G, NROWS, LB)                                   \
+  const int64_t gtid_ = (int64_t)(LB) * BLK + threadIdx.x;        \
+  const int32_t row = (int32_t)(gtid_ / (G));                      \
+  const int sub = (int)(gtid_ % (G));                              \
+  if (row >= (NROWS)) return;
 
-#define NAMG_ROW_PROLOGUE(G, M)                                                  \
-  const int64_t gtid_ = (int64_t)logical_block((M).flags) * BLK + threadIdx.x;   \
-  const int32_t row = (int32_t)(gtid_ / (G));                                     \
-  const int sub = (int)(gtid_ % (G));                                             \
-  if (row >= (M).nrows) return;
+// ---------------------------------------------------------------------------------------- row bodies
 
 // y = A x  (restriction R r, the GMRES product w = A z with z promoted on load, the coarse inverse)
 template <int G, class Acc, class TM, class TX, class TY>
-__global__ __launch_bounds__(BLK) void k_spmv(MatView<TM> A, const TX *__restrict__ x, TY *__restrict__ y) {
-  NAMG_ROW_PROLOGUE(G, A)
+__device__ __forceinline__ void spmv_body(uint32_t lb, const MatView<TM> &A, const TX *__restrict__ x,
+                                          TY *__restrict__ y) {
+  NAMG_ROWS(G, A.nrows, lb)
   const Acc v = row_dot<G, Acc>(A, x, row, sub);
   if (sub == 0) y[row] = (TY)v;
 }
 
 // r = b - A x (x == nullptr means x = 0), optionally f = d .* r. One pass: SpMV, subtract, scale.
 template <int G, class T>
-__global__ __launch_bounds__(BLK) void k_residual(MatView<T> A, const T *__restrict__ b, const T *__restrict__ x,
-                                                  const T *__restrict__ d, T *__restrict__ r, T *__restrict__ f) {
-  NAMG_ROW_PROLOGUE(G, A)
+__device__ __forceinline__ void residual_body(uint32_t lb, const MatView<T> &A, const T *__restrict__ b,
+                                              const T *__restrict__ x, const T *__restrict__ d, T *__restrict__ r,
+                                              T *__restrict__ f) {
+  NAMG_ROWS(G, A.nrows, lb)
   const T acc = x ? row_dot<G, T>(A, x, row, sub) : T(0);
   if (sub != 0) return;
   const T rr = b[row] - acc;
@@ -99,9 +99,10 @@ __global__ __launch_bounds__(BLK) void k_residual(MatView<T> A, const T *__restr
 // Polynomial GS: S = D^{-1}L (or D^{-1}U), f = D^{-1} r; ILU: S = L_s with f = r, or S = U_s with
 // f = D_U^{-1} y. `acc` may alias `out` (x += ...); `in` never aliases `out`.
 template <int G, class T>
-__global__ __launch_bounds__(BLK) void k_neumann(MatView<T> S, const T *__restrict__ f, const T *__restrict__ in,
-                                                 const T *__restrict__ scale, const T *acc, T *out) {
-  NAMG_ROW_PROLOGUE(G, S)
+__device__ __forceinline__ void neumann_body(uint32_t lb, const MatView<T> &S, const T *__restrict__ f,
+                                             const T *__restrict__ in, const T *__restrict__ scale, const T *acc,
+                                             T *out) {
+  NAMG_ROWS(G, S.nrows, lb)
   const T sv = row_dot<G, T>(S, in, row, sub);
   if (sub != 0) return;
   T v = f[row] - sv;
@@ -112,22 +113,52 @@ __global__ __launch_bounds__(BLK) void k_neumann(MatView<T> S, const T *__restri
 
 // x += P e  (prolongation and correction in one pass)
 template <int G, class T>
-__global__ __launch_bounds__(BLK) void k_prolong(MatView<T> P, const T *__restrict__ e, T *x) {
-  NAMG_ROW_PROLOGUE(G, P)
+__device__ __forceinline__ void prolong_body(uint32_t lb, const MatView<T> &P, const T *__restrict__ e, T *x) {
+  NAMG_ROWS(G, P.nrows, lb)
   const T v = row_dot<G, T>(P, e, row, sub);
   if (sub == 0) x[row] += v;
 }
 
 // out = [acc +] [scale .*] f
 template <class T>
-__global__ __launch_bounds__(BLK) void k_axpy(const T *__restrict__ f, const T *__restrict__ scale, const T *acc, T *out,
-                                              int32_t n) {
-  const int32_t row = blockIdx.x * BLK + threadIdx.x;
+__device__ __forceinline__ void axpy_body(uint32_t lb, const T *__restrict__ f, const T *__restrict__ scale,
+                                          const T *acc, T *out, int32_t n) {
+  const int32_t row = (int32_t)lb * BLK + threadIdx.x;
   if (row >= n) return;
   T v = f[row];
   if (scale) v *= scale[row];
   if (acc) v += acc[row];
   out[row] = v;
+}
+
+// --------------------------------------------------------------------------- single-problem kernels
+
+template <int G, class Acc, class TM, class TX, class TY>
+__global__ __launch_bounds__(BLK) void k_spmv(MatView<TM> A, const TX *__restrict__ x, TY *__restrict__ y) {
+  spmv_body<G, Acc>(blockIdx.x, A, x, y);
+}
+
+template <int G, class T>
+__global__ __launch_bounds__(BLK) void k_residual(MatView<T> A, const T *__restrict__ b, const T *__restrict__ x,
+                                                  const T *__restrict__ d, T *__restrict__ r, T *__restrict__ f) {
+  residual_body<G>(blockIdx.x, A, b, x, d, r, f);
+}
+
+template <int G, class T>
+__global__ __launch_bounds__(BLK) void k_neumann(MatView<T> S, const T *__restrict__ f, const T *__restrict__ in,
+                                                 const T *__restrict__ scale, const T *acc, T *out) {
+  neumann_body<G>(blockIdx.x, S, f, in, scale, acc, out);
+}
+
+template <int G, class T>
+__global__ __launch_bounds__(BLK) void k_prolong(MatView<T> P, const T *__restrict__ e, T *x) {
+  prolong_body<G>(blockIdx.x, P, e, x);
+}
+
+template <class T>
+__global__ __launch_bounds__(BLK) void k_axpy(const T *__restrict__ f, const T *__restrict__ scale, const T *acc, T *out,
+                                              int32_t n) {
+  axpy_body(blockIdx.x, f, scale, acc, out, n);
 }
 
 // One dependency level of a direct triangular solve g = (I + S)^{-1} f: rows of the level only read
@@ -156,28 +187,15 @@ __global__ __launch_bounds__(BLK) void k_fill(T *__restrict__ out, T v, int32_t 
   if (row < n) out[row] = v;
 }
 
-// ------------------------------------------------------------------------------------------------
-// FP64 Krylov kernels.
-
-// Block sum of one double; the result is valid in thread 0.
-__device__ __forceinline__ double block_sum(double v, double *lds) {
-  v = wave_sum(v);
-  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0)
-    for (int q = 0; q < WAVES; ++q) t += lds[q];
-  __syncthreads();
-  return t;
-}
+// ------------------------------------------------------------------------------ FP64 Krylov bodies
 
 // r = b - A x in FP64 (true residual), optional low-precision copy of r, per-block partial of |r|^2.
 template <class TL>
-__global__ __launch_bounds__(BLK) void k_residual64(MatView<double> A, const double *__restrict__ b,
-                                                    const double *__restrict__ x, double *__restrict__ r,
-                                                    TL *__restrict__ rlow, double *__restrict__ partial) {
+__device__ __forceinline__ void residual64_body(uint32_t lb, const MatView<double> &A, const double *__restrict__ b,
+                                                const double *__restrict__ x, double *__restrict__ r,
+                                                TL *__restrict__ rlow, double *__restrict__ partial) {
   __shared__ double lds[WAVES];
-  const int32_t row = blockIdx.x * BLK + threadIdx.x;
+  const int32_t row = (int32_t)lb * BLK + threadIdx.x;
   double rr = 0.0;
   if (row < A.nrows) {
     rr = b[row] - row_dot<1, double>(A, x, row, 0);
@@ -185,20 +203,21 @@ __global__ __launch_bounds__(BLK) void k_residual64(MatView<double> A, const dou
     if (rlow) rlow[row] = (TL)rr;
   }
   const double t = block_sum(rr * rr, lds);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  if (threadIdx.x == 0) partial[lb] = t;
 }
 
-// partial[b] = sum over block b's rows of x^2
-__global__ __launch_bounds__(BLK) void k_sumsq(const double *__restrict__ x, int32_t n, double *__restrict__ partial) {
+// partial[lb] = sum over block lb's rows of x^2
+__device__ __forceinline__ void sumsq_body(uint32_t lb, const double *__restrict__ x, int32_t n,
+                                           double *__restrict__ partial) {
   __shared__ double lds[WAVES];
-  const int32_t row = blockIdx.x * BLK + threadIdx.x;
+  const int32_t row = (int32_t)lb * BLK + threadIdx.x;
   const double v = row < n ? x[row] : 0.0;
   const double t = block_sum(v * v, lds);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  if (threadIdx.x == 0) partial[lb] = t;
 }
 
 // out[0] = sum of partial[0..n) in a fixed order (one block); out may be host-mapped memory.
-__global__ __launch_bounds__(BLK) void k_reduce(const double *__restrict__ partial, int32_t n, double *out) {
+__device__ __forceinline__ void reduce_body(const double *__restrict__ partial, int32_t n, double *out) {
   __shared__ double lds[WAVES];
   double t = 0.0;
   for (int32_t k = threadIdx.x; k < n; k += BLK) t += partial[k];
@@ -206,26 +225,26 @@ __global__ __launch_bounds__(BLK) void k_reduce(const double *__restrict__ parti
   if (threadIdx.x == 0) out[0] = t;
 }
 
-// Block v: out[v] = sum over b < nblk of partial[v * nblk + b], in a fixed order.
-__global__ __launch_bounds__(BLK) void k_colreduce(const double *__restrict__ partial, int32_t nblk,
-                                                   double *__restrict__ out) {
+// Block lb: out[lb] = sum over b < nblk of partial[lb * nblk + b], in a fixed order.
+__device__ __forceinline__ void colreduce_body(uint32_t lb, const double *__restrict__ partial, int32_t nblk,
+                                               double *__restrict__ out) {
   __shared__ double lds[WAVES];
-  const double *p = partial + (int64_t)blockIdx.x * nblk;
+  const double *p = partial + (int64_t)lb * nblk;
   double t = 0.0;
   for (int32_t k = threadIdx.x; k < nblk; k += BLK) t += p[k];
   t = block_sum(t, lds);
-  if (threadIdx.x == 0) out[blockIdx.x] = t;
+  if (threadIdx.x == 0) out[lb] = t;
 }
 
 // The single fused reduction of an Arnoldi step (Algorithm 1, the global synchronisation):
-// c = V_{i+1}^T v_{i+1} and d = V_{i+1}^T w in one pass over V. Block b owns a contiguous row range and
-// writes its partial sums value-major: partial[v * nblk + b], v < ncols for c, ncols + v for d.
+// c = V_{i+1}^T v_{i+1} and d = V_{i+1}^T w in one pass over V. Block lb owns a contiguous row range and
+// writes its partial sums value-major: partial[v * nblk + lb], v < ncols for c, ncols + v for d.
 template <int CH>
-__global__ __launch_bounds__(BLK) void k_multidot(const double *__restrict__ V, int64_t ldv, int32_t ncols,
-                                                  const double *__restrict__ w, int32_t n, int32_t rows_per_blk,
-                                                  double *__restrict__ partial, int32_t nblk) {
+__device__ __forceinline__ void multidot_body(uint32_t lb, const double *__restrict__ V, int64_t ldv, int32_t ncols,
+                                              const double *__restrict__ w, int32_t n, int32_t rows_per_blk,
+                                              double *__restrict__ partial, int32_t nblk) {
   __shared__ double lds[2 * CH][WAVES];
-  const int32_t r0 = blockIdx.x * rows_per_blk;
+  const int32_t r0 = (int32_t)lb * rows_per_blk;
   const int32_t r1 = min(n, r0 + rows_per_blk);
   const double *v = V + (int64_t)(ncols - 1) * ldv;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -261,7 +280,7 @@ __global__ __launch_bounds__(BLK) void k_multidot(const double *__restrict__ V, 
       if (col < ncols && (!isd || w)) {
         double t = 0.0;
         for (int q = 0; q < WAVES; ++q) t += lds[threadIdx.x][q];
-        partial[(int64_t)((isd ? ncols : 0) + col) * nblk + blockIdx.x] = t;
+        partial[(int64_t)((isd ? ncols : 0) + col) * nblk + lb] = t;
       }
     }
     __syncthreads();
@@ -275,9 +294,9 @@ __global__ __launch_bounds__(BLK) void k_multidot(const double *__restrict__ V, 
 // q (d_j / rho, the last one d_i / rho^2) and s = T q with T = I - L (Neumann) or T = (I + L)^{-1}
 // (forward substitution). Writes s, 1/rho and the stop flag to the state, and (est, flag) to host_out,
 // host-mapped memory the host reads after the stream synchronises.
-__global__ __launch_bounds__(BLK) void k_arnoldi_step(KState *__restrict__ st, const double *__restrict__ cd, int32_t i,
-                                                      int32_t has_w, int32_t t_direct, int32_t last, double tol,
-                                                      double beta, double *host_out) {
+__device__ __forceinline__ void arnoldi_step_body(KState *__restrict__ st, const double *__restrict__ cd, int32_t i,
+                                                  int32_t has_w, int32_t t_direct, int32_t last, double tol,
+                                                  double beta, double *host_out) {
   __shared__ double c[KS_LD], d[KS_LD], q[KS_LD], s[KS_LD];
   __shared__ double rho_sh;
   __shared__ int stop_sh;
@@ -370,16 +389,22 @@ __global__ __launch_bounds__(BLK) void k_arnoldi_step(KState *__restrict__ st, c
 
 // Lagged normalisation and projection (Algorithm 1): v_{i+1} <- v_{i+1} / rho and
 // v_{i+2} = w / rho - V_{i+1} s, with an optional low-precision copy of v_{i+2} for the next V-cycle.
+// Does nothing once the step kernel has raised the stop flag.
 template <class TL>
-__global__ __launch_bounds__(BLK) void k_project(double *__restrict__ V, int64_t ldv, int32_t i,
-                                                 const double *__restrict__ w, const KState *__restrict__ st,
-                                                 int32_t n, TL *__restrict__ vlow) {
+__device__ __forceinline__ void project_body(uint32_t lb, double *__restrict__ V, int64_t ldv, int32_t i,
+                                             const double *__restrict__ w, const KState *__restrict__ st, int32_t n,
+                                             TL *__restrict__ vlow) {
   __shared__ double s[KS_LD];
   __shared__ double ri;
+  __shared__ int32_t flag;
   for (int j = threadIdx.x; j <= i; j += BLK) s[j] = st->s[j];
-  if (threadIdx.x == 0) ri = st->rho_inv;
+  if (threadIdx.x == 0) {
+    ri = st->rho_inv;
+    flag = st->flag;
+  }
   __syncthreads();
-  const int32_t row = blockIdx.x * BLK + threadIdx.x;
+  if (flag != 0) return;
+  const int32_t row = (int32_t)lb * BLK + threadIdx.x;
   if (row >= n) return;
   const double vi = V[(int64_t)i * ldv + row] * ri;
   V[(int64_t)i * ldv + row] = vi;
@@ -391,8 +416,8 @@ __global__ __launch_bounds__(BLK) void k_project(double *__restrict__ V, int64_t
 }
 
 // y from the rotated k x k triangle (Algorithm 1, least squares), then y_j *= zs_j.
-__global__ void k_backsolve(KState *__restrict__ st, int32_t k) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ __forceinline__ void backsolve_body(KState *__restrict__ st, int32_t k) {
+  if (threadIdx.x != 0) return;
   double *y = st->y;
   for (int j = k - 1; j >= 0; --j) {
     double acc = st->g[j];
@@ -404,16 +429,158 @@ __global__ void k_backsolve(KState *__restrict__ st, int32_t k) {
 
 // x += Z_k y  (Algorithm 1, solution update; flexible GMRES uses the stored Z)
 template <class TZ>
-__global__ __launch_bounds__(BLK) void k_update_x(const TZ *__restrict__ Z, int64_t ldz, int32_t k,
-                                                  const KState *__restrict__ st, double *__restrict__ x, int32_t n) {
+__device__ __forceinline__ void update_x_body(uint32_t lb, const TZ *__restrict__ Z, int64_t ldz, int32_t k,
+                                              const KState *__restrict__ st, double *__restrict__ x, int32_t n) {
   __shared__ double y[KS_LD];
   for (int j = threadIdx.x; j < k; j += BLK) y[j] = st->y[j];
   __syncthreads();
-  const int32_t row = blockIdx.x * BLK + threadIdx.x;
+  const int32_t row = (int32_t)lb * BLK + threadIdx.x;
   if (row >= n) return;
   double acc = 0.0;
   for (int j = 0; j < k; ++j) acc += (double)Z[(int64_t)j * ldz + row] * y[j];
   x[row] += acc;
+}
+
+// ------------------------------------------------------------------ single-problem Krylov kernels
+
+template <class TL>
+__global__ __launch_bounds__(BLK) void k_residual64(MatView<double> A, const double *__restrict__ b,
+                                                    const double *__restrict__ x, double *__restrict__ r,
+                                                    TL *__restrict__ rlow, double *__restrict__ partial) {
+  residual64_body(blockIdx.x, A, b, x, r, rlow, partial);
+}
+
+__global__ __launch_bounds__(BLK) void k_sumsq(const double *__restrict__ x, int32_t n, double *__restrict__ partial) {
+  sumsq_body(blockIdx.x, x, n, partial);
+}
+
+__global__ __launch_bounds__(BLK) void k_reduce(const double *__restrict__ partial, int32_t n, double *out) {
+  reduce_body(partial, n, out);
+}
+
+__global__ __launch_bounds__(BLK) void k_colreduce(const double *__restrict__ partial, int32_t nblk,
+                                                   double *__restrict__ out) {
+  colreduce_body(blockIdx.x, partial, nblk, out);
+}
+
+template <int CH>
+__global__ __launch_bounds__(BLK) void k_multidot(const double *__restrict__ V, int64_t ldv, int32_t ncols,
+                                                  const double *__restrict__ w, int32_t n, int32_t rows_per_blk,
+                                                  double *__restrict__ partial, int32_t nblk) {
+  multidot_body<CH>(blockIdx.x, V, ldv, ncols, w, n, rows_per_blk, partial, nblk);
+}
+
+__global__ __launch_bounds__(BLK) void k_arnoldi_step(KState *__restrict__ st, const double *__restrict__ cd, int32_t i,
+                                                      int32_t has_w, int32_t t_direct, int32_t last, double tol,
+                                                      double beta, double *host_out) {
+  arnoldi_step_body(st, cd, i, has_w, t_direct, last, tol, beta, host_out);
+}
+
+template <class TL>
+__global__ __launch_bounds__(BLK) void k_project(double *__restrict__ V, int64_t ldv, int32_t i,
+                                                 const double *__restrict__ w, const KState *__restrict__ st,
+                                                 int32_t n, TL *__restrict__ vlow) {
+  project_body(blockIdx.x, V, ldv, i, w, st, n, vlow);
+}
+
+__global__ __launch_bounds__(BLK) void k_backsolve(KState *__restrict__ st, int32_t k) { backsolve_body(st, k); }
+
+template <class TZ>
+__global__ __launch_bounds__(BLK) void k_update_x(const TZ *__restrict__ Z, int64_t ldz, int32_t k,
+                                                  const KState *__restrict__ st, double *__restrict__ x, int32_t n) {
+  update_x_body(blockIdx.x, Z, ldz, k, st, x, n);
+}
+
+// ------------------------------------------------------------------------------ batched kernels
+
+// The task of this block: the largest k with off[k] <= blockIdx.x (off has ntasks + 1 entries). The
+// offsets are staged in LDS once per block and searched there.
+__device__ __forceinline__ int find_task(const uint32_t *__restrict__ off, int ntasks, uint32_t &local_block) {
+  __shared__ uint32_t s_off[MAX_BATCH + 1];
+  for (int k = threadIdx.x; k <= ntasks; k += BLK) s_off[k] = off[k];
+  __syncthreads();
+  int lo = 0, hi = ntasks - 1;
+  const uint32_t b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (s_off[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  local_block = b - s_off[lo];
+  return lo;
+}
+
+// One row operation on one level of one solve. Operand meaning per operation:
+//   ROP_RESIDUAL: a = b, b = x (may be null), c = D^{-1} (null unless o1 is set), o0 = r, o1 = f
+//   ROP_NEUMANN:  a = f, b = in, c = scale, d = acc, o0 = out
+//   ROP_SPMV:     b = x, o0 = y
+//   ROP_PROLONG:  b = e, o0 = x
+//   ROP_AXPY:     a = f, c = scale, d = acc, o0 = out, n rows
+//   ROP_FILL:     o0 = 0, n rows
+enum { ROP_RESIDUAL = 0, ROP_NEUMANN = 1, ROP_SPMV = 2, ROP_PROLONG = 3, ROP_AXPY = 4, ROP_FILL = 5 };
+
+template <class T>
+struct RowTask {
+  MatView<T> M;
+  const T *a, *b, *c, *d;
+  T *o0, *o1;
+  int32_t n, pad;
+};
+
+template <int OP, int G, class T>
+__global__ __launch_bounds__(BLK) void kb_rows(const RowTask<T> *__restrict__ tasks, const uint32_t *__restrict__ off,
+                                               int ntasks) {
+  uint32_t lb;
+  const RowTask<T> &t = tasks[find_task(off, ntasks, lb)];
+  if constexpr (OP == ROP_RESIDUAL) residual_body<G>(lb, t.M, t.a, t.b, t.c, t.o0, t.o1);
+  if constexpr (OP == ROP_NEUMANN) neumann_body<G>(lb, t.M, t.a, t.b, t.c, t.d, t.o0);
+  if constexpr (OP == ROP_SPMV) spmv_body<G, T>(lb, t.M, t.b, t.o0);
+  if constexpr (OP == ROP_PROLONG) prolong_body<G>(lb, t.M, t.b, t.o0);
+  if constexpr (OP == ROP_AXPY) axpy_body(lb, t.a, t.c, t.d, t.o0, t.n);
+  if constexpr (OP == ROP_FILL) {
+    const int32_t row = (int32_t)lb * BLK + threadIdx.x;
+    if (row < t.n) t.o0[row] = T(0);
+  }
+}
+
+// One Krylov operation of one solve (fields used per operation are listed at the launch site).
+enum {
+  KOP_RESIDUAL64 = 0, KOP_SPMV64 = 1, KOP_MULTIDOT = 2, KOP_COLREDUCE = 3, KOP_STEP = 4, KOP_PROJECT = 5,
+  KOP_BACKSOLVE = 6, KOP_UPDATE = 7, KOP_REDUCE = 8, KOP_SUMSQ = 9
+};
+
+template <class T>
+struct KTask {
+  MatView<double> A;
+  const double *b;
+  double *x, *V, *w, *partial, *cd, *host_out;
+  T *Z, *vlow;
+  const T *zin;
+  KState *ks;
+  int64_t ldv, ldz;
+  int32_t n, i, ncols, has_w, last, k, nblk, rows_per_blk;
+  double beta;
+};
+
+template <int OP, class T>
+__global__ __launch_bounds__(BLK) void kb_krylov(const KTask<T> *__restrict__ tasks, const uint32_t *__restrict__ off,
+                                                 int ntasks, int32_t t_direct, double tol) {
+  uint32_t lb;
+  const KTask<T> &t = tasks[find_task(off, ntasks, lb)];
+  if constexpr (OP == KOP_RESIDUAL64) residual64_body(lb, t.A, t.b, t.x, t.V, t.vlow, t.partial);
+  if constexpr (OP == KOP_SPMV64) spmv_body<1, double>(lb, t.A, t.zin, t.w);
+  if constexpr (OP == KOP_MULTIDOT)
+    multidot_body<8>(lb, t.V, t.ldv, t.ncols, t.has_w ? t.w : (const double *)nullptr, t.n, t.rows_per_blk, t.partial,
+                     t.nblk);
+  if constexpr (OP == KOP_COLREDUCE) colreduce_body(lb, t.partial, t.nblk, t.cd);
+  if constexpr (OP == KOP_STEP) arnoldi_step_body(t.ks, t.cd, t.i, t.has_w, t_direct, t.last, tol, t.beta, t.host_out);
+  if constexpr (OP == KOP_PROJECT) project_body(lb, t.V, t.ldv, t.i, t.w, t.ks, t.n, t.vlow);
+  if constexpr (OP == KOP_BACKSOLVE) backsolve_body(t.ks, t.k);
+  if constexpr (OP == KOP_UPDATE) update_x_body(lb, (const T *)t.Z, t.ldz, t.k, t.ks, t.x, t.n);
+  if constexpr (OP == KOP_REDUCE) reduce_body(t.partial, t.nblk, t.host_out);
+  if constexpr (OP == KOP_SUMSQ) sumsq_body(lb, t.x, t.n, t.partial);
 }
 
 }  // namespace namg

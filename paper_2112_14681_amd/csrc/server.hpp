@@ -1,0 +1,789 @@
+// Serving: a request scheduler that keeps many solves in flight on one GPU and advances them together.
+//
+// Requests (host CSR + right-hand side) are set up by a pool of host threads, admitted in arrival order
+// when a slot is free and their exact device footprint fits the HBM budget, uploaded, and then join the
+// scheduler. Each scheduler tick advances every in-flight solve by one Arnoldi step (or one restart-cycle
+// boundary) with *batched* launches: every row operation of the V-cycle and every Krylov kernel is
+// issued once per tick for all solves that need it, from one task table uploaded per tick. A finished
+// solve leaves at the tick boundary, its memory is released and the next request is admitted while the
+// others keep running (continuous batching). The per-solve arithmetic is the single-solve path's, so
+// a result is bit-identical alone and in the mix.
+#pragma once
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+namespace namg {
+
+// Device bytes one DMat<T>::build of A allocates (mirrors its layout choice and DevBuf rounding).
+template <class T>
+int64_t mat_alloc_bytes(const HostCsr &A, int force_group = 0) {
+  auto r1 = [](int64_t n) { return n == 0 ? (int64_t)1 : n; };
+  const int group = force_group > 0 ? force_group : choose_group(A.nr, A.nnz());
+  if (group > 1)
+    return 4 * r1((int64_t)A.rp.size()) + 4 * r1(A.nnz()) + (int64_t)sizeof(T) * r1(A.nnz());
+  const int64_t nslices = (A.nr + SELL_C - 1) / SELL_C;
+  int64_t stored = 0;
+  for (int64_t s = 0; s < nslices; ++s) {
+    int32_t w = 0;
+    for (int64_t r = s * SELL_C; r < std::min<int64_t>(A.nr, (s + 1) * SELL_C); ++r)
+      w = std::max(w, A.rp[r + 1] - A.rp[r]);
+    stored += (int64_t)w * SELL_C;
+  }
+  return 4 * (nslices + 1) + (4 + (int64_t)sizeof(T)) * r1(stored);
+}
+
+// Device bytes of Solver<T>(H) with its Krylov workspace for restart m (the direct comparators' level
+// schedules, which serving never builds, excluded).
+template <class T>
+int64_t solver_footprint(const HostHierarchy &H, int m) {
+  const int64_t S = sizeof(T);
+  const int nl = (int)H.lv.size();
+  int64_t total = 0;
+  for (int l = 0; l < nl; ++l) {
+    const HostLevel &h = H.lv[l];
+    const int64_t n = h.A.nr;
+    total += 2 * S * n;
+    if (l == nl - 1) break;
+    total += mat_alloc_bytes<T>(h.A) + mat_alloc_bytes<T>(h.P) + mat_alloc_bytes<T>(h.R) + mat_alloc_bytes<T>(h.pgs_lo) +
+             mat_alloc_bytes<T>(h.pgs_up) + S * n + 4 * S * n;
+    if (h.has_ilu) total += mat_alloc_bytes<T>(h.ilu_lo) + mat_alloc_bytes<T>(h.ilu_up) + S * n;
+  }
+  const int64_t nc = H.lv.back().A.nr;
+  total += nc > 1 ? 4 * (nc + 1) + (4 + S) * nc * nc : 4 * 2 + (4 + S);
+  total += mat_alloc_bytes<double>(H.lv[0].A, 1);
+  const int64_t n0 = H.lv[0].A.nr;
+  const int64_t nred = blocks_for(n0);
+  total += 8 * (std::max<int64_t>(nred, 1) + 8) + (int64_t)sizeof(KState);
+  const int64_t ld = (n0 + 63) / 64 * 64;
+  const int64_t nblk = std::min<int64_t>(1024, std::max<int64_t>(1, nred));
+  total += 8 * ld * (m + 2) + S * ld * m + 8 * n0 + (S == 4 ? 4 * n0 : 0) + 8 * nblk * 2 * (m + 2) + 16 * (m + 2);
+  return total;
+}
+
+template <class T>
+class BatchEngine {
+ public:
+  enum Phase { INIT = 0, STEP = 1, END = 2, DONE = 3 };
+  struct Slot {
+    Solver<T> *sv = nullptr;
+    const double *b = nullptr;
+    double *x = nullptr;
+    int32_t n = 0;
+    int phase = INIT, i = 0, me = 0, k = 0;
+    double beta = 0.0, rn = 0.0, est = 0.0, alg = 0.0;
+    int iters = 0, cycles = 0, apps = 0;
+    int status = NAMG_PENDING;
+    std::string err;
+  };
+
+  BatchEngine(int device, const namg_solve_params &p) : dev_(device), p_(p), o_(cycle_opts(p)) {
+    DeviceGuard g(dev_);
+    hip_check(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+  }
+  ~BatchEngine() {
+    if (pinned_) (void)hipHostFree(pinned_);
+    if (dbuf_) (void)hipFree(dbuf_);
+    if (s_) (void)hipStreamDestroy(s_);
+  }
+  hipStream_t stream() const { return s_; }
+  int64_t launches() const { return launches_; }
+
+  // Advance every slot that is not DONE by one step. Throws HipError on a runtime failure.
+  void tick(std::vector<Slot *> &slots) {
+    DeviceGuard g(dev_);
+    groups_.clear();
+    stage_.clear();
+    std::vector<Slot *> step, vc, init, end, resid;
+    for (Slot *sl : slots) {
+      if (sl->phase == STEP) {
+        step.push_back(sl);
+        if (sl->i < sl->me) vc.push_back(sl);
+      } else if (sl->phase == INIT) {
+        init.push_back(sl);
+        resid.push_back(sl);
+      } else if (sl->phase == END) {
+        end.push_back(sl);
+        resid.push_back(sl);
+      }
+    }
+    // 1. V-cycles z = M^{-1} v_{i+1} of every stepping solve, level by level, then w = A z
+    if (!vc.empty()) {
+      batch_vcycles(vc);
+      std::vector<KTask<T>> t;
+      std::vector<unsigned> nb;
+      for (Slot *sl : vc) {
+        KTask<T> k = base(sl);
+        k.zin = sl->sv->Z_.get() + (int64_t)sl->i * sl->sv->ldz_;
+        t.push_back(k);
+        nb.push_back(blocks_for(sl->n));
+        sl->alg += sl->sv->A64_.bytes() + (sizeof(T) + 8.0) * sl->n;
+      }
+      add_krylov(KOP_SPMV64, t, nb);
+    }
+    // 2. the fused reduction, the small dense step and the projection
+    if (!step.empty()) {
+      std::vector<KTask<T>> t;
+      std::vector<unsigned> nb, nc, ones, np;
+      std::vector<KTask<T>> tp;
+      for (Slot *sl : step) {
+        KTask<T> k = base(sl);
+        k.partial = sl->sv->dot_.get();
+        k.nblk = sl->sv->nblk_dot_;
+        k.host_out = sl->sv->pinned_dev_;
+        t.push_back(k);
+        nb.push_back((unsigned)sl->sv->nblk_dot_);
+        nc.push_back((unsigned)(k.ncols * (k.has_w ? 2 : 1)));
+        ones.push_back(1u);
+        if (k.has_w) {
+          tp.push_back(k);
+          np.push_back(blocks_for(sl->n));
+        }
+        sl->alg += 8.0 * sl->n * (k.ncols + (k.has_w ? 1 : 0)) + (k.has_w ? 8.0 * sl->n * (sl->i + 4) : 0.0);
+      }
+      add_krylov(KOP_MULTIDOT, t, nb);
+      add_krylov(KOP_COLREDUCE, t, nc);
+      add_krylov(KOP_STEP, t, ones);
+      if (!tp.empty()) add_krylov(KOP_PROJECT, tp, np);
+    }
+    // 3. cycle ends: y from the rotated Hessenberg, x += Z y
+    if (!end.empty()) {
+      std::vector<KTask<T>> t;
+      std::vector<unsigned> ones, nb;
+      for (Slot *sl : end) {
+        t.push_back(base(sl));
+        ones.push_back(1u);
+        nb.push_back(blocks_for(sl->n));
+        sl->alg += (double)sl->n * (sizeof(T) * sl->k + 16.0);
+      }
+      add_krylov(KOP_BACKSOLVE, t, ones);
+      add_krylov(KOP_UPDATE, t, nb);
+    }
+    // 4. ||b|| of new solves, then the true residual of new solves and finished cycles
+    if (!init.empty()) {
+      std::vector<KTask<T>> t, tr;
+      std::vector<unsigned> nb, ones;
+      for (Slot *sl : init) {
+        KTask<T> k = base(sl);
+        k.x = const_cast<double *>(sl->b);
+        k.partial = sl->sv->red_.get();
+        k.nblk = sl->sv->nblk_red_;
+        k.host_out = sl->sv->pinned_dev_ + 3;
+        t.push_back(k);
+        nb.push_back(blocks_for(sl->n));
+        ones.push_back(1u);
+      }
+      add_krylov(KOP_SUMSQ, t, nb);
+      add_krylov(KOP_REDUCE, t, ones);
+    }
+    if (!resid.empty()) {
+      std::vector<KTask<T>> t;
+      std::vector<unsigned> nb, ones;
+      for (Slot *sl : resid) {
+        KTask<T> k = base(sl);
+        k.partial = sl->sv->red_.get();
+        k.nblk = sl->sv->nblk_red_;
+        k.host_out = sl->sv->pinned_dev_ + 2;
+        t.push_back(k);
+        nb.push_back(blocks_for(sl->n));
+        ones.push_back(1u);
+        sl->alg += sl->sv->A64_.bytes() + 24.0 * sl->n;
+      }
+      add_krylov(KOP_RESIDUAL64, t, nb);
+      add_krylov(KOP_REDUCE, t, ones);
+    }
+    submit_and_wait();
+    // host side of the step: read back (estimate, flag) and the reductions, move every solve on
+    for (Slot *sl : step) {
+      const double *pin = sl->sv->pinned_;
+      const int flag = (int)pin[1];
+      if (flag < 0) {
+        fail(sl, NAMG_E_NONFINITE, "non-finite value in the Arnoldi step");
+        continue;
+      }
+      if (sl->i < sl->me) sl->apps++;
+      if (sl->i >= 1) {
+        sl->iters++;
+        sl->est = pin[0];
+      }
+      if (sl->i >= 1 && flag == 1) {
+        sl->k = sl->i;
+        sl->phase = END;
+      } else {
+        sl->i++;
+      }
+    }
+    for (Slot *sl : init) {
+      const double b2 = sl->sv->pinned_[3];
+      sl->beta = std::sqrt(b2);
+      if (!std::isfinite(sl->beta)) {
+        fail(sl, NAMG_E_NONFINITE, "non-finite right-hand side");
+        continue;
+      }
+      if (sl->beta == 0.0) {
+        hipLaunchKernelGGL(k_fill<double>, dim3(blocks_for(sl->n)), dim3(BLK), 0, s_, sl->x, 0.0, sl->n);
+        hip_check(hipGetLastError(), "k_fill");
+        hip_check(hipStreamSynchronize(s_), "hipStreamSynchronize");
+        sl->rn = 0.0;
+        sl->status = NAMG_OK;
+        sl->phase = DONE;
+        continue;
+      }
+      decide(sl);
+    }
+    for (Slot *sl : end) decide(sl);
+  }
+
+ private:
+  struct Group {
+    bool krylov;
+    int op, g;
+    size_t task_off, off_off;
+    int ntasks;
+    unsigned grid;
+  };
+
+  KTask<T> base(Slot *sl) const {
+    Solver<T> &v = *sl->sv;
+    KTask<T> k{};
+    k.A = v.A64_.view();
+    k.b = sl->b;
+    k.x = sl->x;
+    k.V = v.V_.get();
+    k.w = v.w_.get();
+    k.cd = v.cd_.get();
+    k.host_out = v.pinned_dev_;
+    k.Z = v.Z_.get();
+    k.vlow = std::is_same<T, double>::value ? nullptr : v.vin_.get();
+    k.ks = v.kst_.get();
+    k.ldv = v.ldv_;
+    k.ldz = v.ldz_;
+    k.n = sl->n;
+    k.i = sl->i;
+    k.ncols = sl->i + 1;
+    k.has_w = sl->i < sl->me;
+    k.last = sl->i == sl->me;
+    k.k = sl->k;
+    k.nblk = v.nblk_dot_;
+    k.rows_per_blk = v.rows_per_dot_;
+    k.beta = sl->beta;
+    return k;
+  }
+
+  void fail(Slot *sl, int code, const char *msg) {
+    sl->status = code;
+    sl->err = msg;
+    sl->phase = DONE;
+  }
+
+  // Cycle boundary: converged, out of iterations, or start the next cycle at step 0.
+  void decide(Slot *sl) {
+    sl->rn = std::sqrt(sl->sv->pinned_[2]);
+    if (!std::isfinite(sl->rn)) {
+      fail(sl, NAMG_E_NONFINITE, "non-finite residual");
+      return;
+    }
+    if (sl->rn / sl->beta <= p_.tol) {
+      sl->status = NAMG_OK;
+      sl->phase = DONE;
+    } else if (sl->iters >= p_.max_iters) {
+      sl->status = NAMG_NOT_CONVERGED;
+      sl->phase = DONE;
+    } else {
+      sl->cycles++;
+      sl->phase = STEP;
+      sl->i = 0;
+      sl->k = 0;
+      sl->me = std::min(p_.restart, p_.max_iters - sl->iters);
+    }
+  }
+
+  template <class Task>
+  void add(bool krylov, int op, int g, const std::vector<Task> &tasks, const std::vector<unsigned> &blocks) {
+    for (size_t c0 = 0; c0 < tasks.size(); c0 += MAX_BATCH) {
+      const size_t nt = std::min<size_t>(MAX_BATCH, tasks.size() - c0);
+      align();
+      const size_t toff = stage_.size();
+      stage_.resize(toff + nt * sizeof(Task));
+      std::memcpy(stage_.data() + toff, tasks.data() + c0, nt * sizeof(Task));
+      align();
+      const size_t ooff = stage_.size();
+      stage_.resize(ooff + (nt + 1) * sizeof(uint32_t));
+      uint32_t *off = reinterpret_cast<uint32_t *>(stage_.data() + ooff);
+      off[0] = 0;
+      for (size_t q = 0; q < nt; ++q) off[q + 1] = off[q] + blocks[c0 + q];
+      if (off[nt] == 0) continue;
+      groups_.push_back(Group{krylov, op, g, toff, ooff, (int)nt, off[nt]});
+    }
+  }
+  void add_krylov(int op, const std::vector<KTask<T>> &t, const std::vector<unsigned> &nb) { add(true, op, 0, t, nb); }
+  void align() { stage_.resize((stage_.size() + 15) / 16 * 16); }
+
+  // Record every stepping solve's V-cycle as row operations, then issue the k-th operation of every solve
+  // on a level together (grouped by operation and lanes-per-row), level by level down and back up.
+  void batch_vcycles(const std::vector<Slot *> &vc) {
+    using Op = typename Solver<T>::RowOp;
+    struct Rec {
+      std::vector<std::vector<Op>> down, up;
+      std::vector<Op> coarse;
+      int L = 0;
+    };
+    std::vector<Rec> rec(vc.size());
+    int Lmax = 0;
+    for (size_t q = 0; q < vc.size(); ++q) {
+      Slot *sl = vc[q];
+      Solver<T> &v = *sl->sv;
+      Rec &r = rec[q];
+      r.L = (int)v.lv_.size();
+      Lmax = std::max(Lmax, r.L);
+      r.down.resize(r.L);
+      r.up.resize(r.L);
+      const T *b0;
+      if constexpr (std::is_same<T, double>::value)
+        b0 = v.V_.get() + (int64_t)sl->i * v.ldv_;
+      else
+        b0 = v.vin_.get();
+      T *x0 = v.Z_.get() + (int64_t)sl->i * v.ldz_;
+      auto bl = [&](int l) -> const T * { return l == 0 ? b0 : v.lv_[l].b.get(); };
+      auto xl = [&](int l) -> T * { return l == 0 ? x0 : v.lv_[l].x.get(); };
+      for (int l = 0; l + 1 < r.L; ++l) {
+        v.record_ = &r.down[l];
+        v.level_down(l, bl(l), xl(l), o_, s_);
+        v.record_ = &r.up[l];
+        v.level_up(l, bl(l), xl(l), o_, s_);
+      }
+      v.record_ = &r.coarse;
+      v.coarse_solve(r.L - 1, bl(r.L - 1), xl(r.L - 1), s_);
+      v.record_ = nullptr;
+      for (auto &ops : r.down)
+        for (auto &op : ops) sl->alg += op.bytes;
+      for (auto &ops : r.up)
+        for (auto &op : ops) sl->alg += op.bytes;
+      for (auto &op : r.coarse) sl->alg += op.bytes;
+    }
+    auto zip = [&](auto pick) {
+      size_t maxlen = 0;
+      for (size_t q = 0; q < vc.size(); ++q)
+        if (const std::vector<Op> *ops = pick(q)) maxlen = std::max(maxlen, ops->size());
+      for (size_t k = 0; k < maxlen; ++k) {
+        // bucket the k-th operations by (kind, group), keeping solve order
+        std::vector<std::pair<int, int>> keys;
+        std::vector<std::vector<RowTask<T>>> tasks;
+        std::vector<std::vector<unsigned>> blocks;
+        for (size_t q = 0; q < vc.size(); ++q) {
+          const std::vector<Op> *ops = pick(q);
+          if (!ops || k >= ops->size()) continue;
+          const Op &op = (*ops)[k];
+          const std::pair<int, int> key{op.kind, op.group};
+          size_t j = 0;
+          while (j < keys.size() && keys[j] != key) ++j;
+          if (j == keys.size()) {
+            keys.push_back(key);
+            tasks.emplace_back();
+            blocks.emplace_back();
+          }
+          tasks[j].push_back(op.t);
+          blocks[j].push_back(op.grid);
+        }
+        for (size_t j = 0; j < keys.size(); ++j) add(false, keys[j].first, keys[j].second, tasks[j], blocks[j]);
+      }
+    };
+    for (int l = 0; l < Lmax; ++l) {
+      zip([&](size_t q) -> const std::vector<Op> * { return l + 1 < rec[q].L ? &rec[q].down[l] : nullptr; });
+      zip([&](size_t q) -> const std::vector<Op> * { return l == rec[q].L - 1 ? &rec[q].coarse : nullptr; });
+    }
+    for (int l = Lmax - 2; l >= 0; --l)
+      zip([&](size_t q) -> const std::vector<Op> * { return l + 1 < rec[q].L ? &rec[q].up[l] : nullptr; });
+  }
+
+  using RowKernel = void (*)(const RowTask<T> *, const uint32_t *, int);
+  using KKernel = void (*)(const KTask<T> *, const uint32_t *, int, int32_t, double);
+
+  template <int OP>
+  static RowKernel row_kernel(int g) {
+    switch (g) {
+      case 1: return &kb_rows<OP, 1, T>;
+      case 2: return &kb_rows<OP, 2, T>;
+      case 4: return &kb_rows<OP, 4, T>;
+      case 8: return &kb_rows<OP, 8, T>;
+      case 16: return &kb_rows<OP, 16, T>;
+      case 32: return &kb_rows<OP, 32, T>;
+      default: return &kb_rows<OP, 64, T>;
+    }
+  }
+  static RowKernel row_kernel(int op, int g) {
+    switch (op) {
+      case ROP_RESIDUAL: return row_kernel<ROP_RESIDUAL>(g);
+      case ROP_NEUMANN: return row_kernel<ROP_NEUMANN>(g);
+      case ROP_SPMV: return row_kernel<ROP_SPMV>(g);
+      case ROP_PROLONG: return row_kernel<ROP_PROLONG>(g);
+      case ROP_AXPY: return &kb_rows<ROP_AXPY, 1, T>;
+      default: return &kb_rows<ROP_FILL, 1, T>;
+    }
+  }
+  static KKernel krylov_kernel(int op) {
+    switch (op) {
+      case KOP_RESIDUAL64: return &kb_krylov<KOP_RESIDUAL64, T>;
+      case KOP_SPMV64: return &kb_krylov<KOP_SPMV64, T>;
+      case KOP_MULTIDOT: return &kb_krylov<KOP_MULTIDOT, T>;
+      case KOP_COLREDUCE: return &kb_krylov<KOP_COLREDUCE, T>;
+      case KOP_STEP: return &kb_krylov<KOP_STEP, T>;
+      case KOP_PROJECT: return &kb_krylov<KOP_PROJECT, T>;
+      case KOP_BACKSOLVE: return &kb_krylov<KOP_BACKSOLVE, T>;
+      case KOP_UPDATE: return &kb_krylov<KOP_UPDATE, T>;
+      case KOP_REDUCE: return &kb_krylov<KOP_REDUCE, T>;
+      default: return &kb_krylov<KOP_SUMSQ, T>;
+    }
+  }
+
+  // One host-to-device copy of the whole task table, every launch in order, one synchronisation.
+  void submit_and_wait() {
+    if (groups_.empty()) return;
+    const size_t bytes = stage_.size();
+    if (bytes > pinned_cap_) {
+      if (pinned_) hip_check(hipHostFree(pinned_), "hipHostFree");
+      pinned_cap_ = bytes * 2;
+      hip_check(hipHostMalloc((void **)&pinned_, pinned_cap_, hipHostMallocDefault), "hipHostMalloc");
+    }
+    if (bytes > dcap_) {
+      if (dbuf_) hip_check(hipFree(dbuf_), "hipFree");
+      dcap_ = bytes * 2;
+      hip_check(hipMalloc((void **)&dbuf_, dcap_), "hipMalloc");
+    }
+    std::memcpy(pinned_, stage_.data(), bytes);
+    hip_check(hipMemcpyAsync(dbuf_, pinned_, bytes, hipMemcpyHostToDevice, s_), "hipMemcpyAsync");
+    const int t_direct = p_.gmres_T == NAMG_T_DIRECT ? 1 : 0;
+    for (const Group &gr : groups_) {
+      const uint32_t *off = reinterpret_cast<const uint32_t *>(dbuf_ + gr.off_off);
+      if (gr.krylov) {
+        const KTask<T> *tasks = reinterpret_cast<const KTask<T> *>(dbuf_ + gr.task_off);
+        hipLaunchKernelGGL(krylov_kernel(gr.op), dim3(gr.grid), dim3(BLK), 0, s_, tasks, off, gr.ntasks, t_direct,
+                           p_.tol);
+      } else {
+        const RowTask<T> *tasks = reinterpret_cast<const RowTask<T> *>(dbuf_ + gr.task_off);
+        hipLaunchKernelGGL(row_kernel(gr.op, gr.g), dim3(gr.grid), dim3(BLK), 0, s_, tasks, off, gr.ntasks);
+      }
+      hip_check(hipGetLastError(), "batched launch");
+      launches_++;
+    }
+    hip_check(hipStreamSynchronize(s_), "hipStreamSynchronize");
+  }
+
+  int dev_;
+  namg_solve_params p_;
+  CycleOpts o_;
+  hipStream_t s_ = nullptr;
+  std::vector<char> stage_;
+  std::vector<Group> groups_;
+  char *pinned_ = nullptr, *dbuf_ = nullptr;
+  size_t pinned_cap_ = 0, dcap_ = 0;
+  int64_t launches_ = 0;
+};
+
+class ServerBase {
+ public:
+  virtual ~ServerBase() = default;
+  virtual uint64_t submit(const HostCsr &A, const double *b, const namg_setup_params &sp) = 0;
+  virtual int poll(uint64_t ticket, bool wait, double *x, namg_solve_stats *st, namg_request_times *tm) = 0;
+  virtual namg_server_counters stats() = 0;
+  virtual double clock() const = 0;
+};
+
+template <class T>
+class Server final : public ServerBase {
+  using Engine = BatchEngine<T>;
+  struct Req {
+    uint64_t ticket = 0;
+    HostCsr A;
+    std::vector<double> b;
+    namg_setup_params sp{};
+    std::unique_ptr<HostHierarchy> H;
+    std::unique_ptr<Solver<T>> sv;
+    DevBuf<double> bd, xd;
+    int64_t footprint = 0;
+    typename Engine::Slot slot;
+    std::vector<double> x;
+    namg_solve_stats st{};
+    namg_request_times tm{};
+    int status = NAMG_PENDING;
+    std::string err;
+    bool done = false, counted = false;
+  };
+
+ public:
+  explicit Server(const namg_server_params &p) : p_(p), t0_(std::chrono::steady_clock::now()), eng_(p.device, p.solve) {
+    for (int q = 0; q < p_.setup_threads; ++q) setup_.emplace_back([this] { setup_loop(); });
+    sched_ = std::thread([this] { sched_loop(); });
+  }
+
+  ~Server() override {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_setup_.notify_all();
+    cv_admit_.notify_all();
+    cv_sched_.notify_all();
+    cv_done_.notify_all();
+    for (auto &t : setup_) t.join();
+    sched_.join();
+    DeviceGuard g(p_.device);
+    reqs_.clear();
+  }
+
+  double clock() const override {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0_).count();
+  }
+
+  uint64_t submit(const HostCsr &A, const double *b, const namg_setup_params &sp) override {
+    auto r = std::make_unique<Req>();
+    r->A = A;
+    r->b.assign(b, b + A.nr);
+    r->sp = sp;
+    r->tm.submit = clock();
+    std::lock_guard<std::mutex> lk(mu_);
+    r->ticket = next_++;
+    const uint64_t t = r->ticket;
+    setup_q_.push_back(r.get());
+    reqs_[t] = std::move(r);
+    submitted_++;
+    cv_setup_.notify_one();
+    return t;
+  }
+
+  int poll(uint64_t ticket, bool wait, double *x, namg_solve_stats *st, namg_request_times *tm) override {
+    std::unique_lock<std::mutex> lk(mu_);
+    auto it = reqs_.find(ticket);
+    if (it == reqs_.end()) throw SetupError{NAMG_E_INVALID, "unknown ticket"};
+    Req *r = it->second.get();
+    if (wait) cv_done_.wait(lk, [&] { return r->done || stop_; });
+    if (!r->done) return NAMG_PENDING;
+    const int status = r->status;
+    const std::string err = r->err;
+    if (x && !r->x.empty()) std::copy(r->x.begin(), r->x.end(), x);
+    if (st) *st = r->st;
+    if (tm) *tm = r->tm;
+    reqs_.erase(it);
+    if (status < 0) throw SetupError{status, err};
+    return status;
+  }
+
+  namg_server_counters stats() override {
+    std::lock_guard<std::mutex> lk(mu_);
+    namg_server_counters s{};
+    s.submitted = submitted_;
+    s.completed = completed_;
+    s.failed = failed_;
+    s.inflight = inflight_;
+    s.waiting = (int64_t)(setup_q_.size() + admit_q_.size());
+    s.ticks = ticks_;
+    s.launches = eng_.launches();
+    s.device_bytes_in_use = used_;
+    s.peak_device_bytes = peak_;
+    s.peak_inflight = peak_inflight_;
+    return s;
+  }
+
+ private:
+  void finish_locked(Req *r) {
+    r->done = true;
+    if (r->status >= 0)
+      completed_++;
+    else
+      failed_++;
+    r->tm.done = clock();
+    cv_done_.notify_all();
+  }
+
+  void setup_loop() {
+    (void)hipSetDevice(p_.device);
+    while (true) {
+      Req *r = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_setup_.wait(lk, [&] { return stop_ || !setup_q_.empty(); });
+        if (stop_) return;
+        r = setup_q_.front();
+        setup_q_.pop_front();
+      }
+      r->tm.setup_start = clock();
+      try {
+        r->H = std::make_unique<HostHierarchy>(
+            build_hierarchy(r->A, r->sp.theta, r->sp.max_levels, r->sp.max_coarse, r->sp.ilu_levels));
+        r->footprint = solver_footprint<T>(*r->H, p_.solve.restart) + 16 * (int64_t)r->A.nr;
+        r->A = HostCsr{};
+      } catch (const SetupError &e) {
+        std::lock_guard<std::mutex> lk(mu_);
+        r->status = e.code;
+        r->err = e.msg;
+        finish_locked(r);
+        continue;
+      } catch (...) {
+        std::lock_guard<std::mutex> lk(mu_);
+        r->status = NAMG_E_NOMEM;
+        r->err = "host allocation failed during setup";
+        finish_locked(r);
+        continue;
+      }
+      r->tm.setup_done = clock();
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        if (r->footprint > p_.hbm_budget) {
+          r->status = NAMG_E_BUDGET;
+          r->err = "request needs more device memory than the whole budget";
+          finish_locked(r);
+          continue;
+        }
+        admit_q_.push_back(r);
+        cv_admit_.wait(lk, [&] {
+          return stop_ || (admit_q_.front() == r && inflight_ < p_.max_inflight && used_ + r->footprint <= p_.hbm_budget);
+        });
+        if (stop_) return;
+        admit_q_.pop_front();
+        used_ += r->footprint;
+        peak_ = std::max(peak_, used_);
+        inflight_++;
+        peak_inflight_ = std::max<int64_t>(peak_inflight_, inflight_);
+        cv_admit_.notify_all();
+      }
+      try {
+        const int32_t n = r->H->lv[0].A.nr;
+        r->sv = std::make_unique<Solver<T>>(*r->H, p_.device);
+        r->sv->reserve_workspace(p_.solve.restart);
+        r->bd.alloc(n, nullptr);
+        r->bd.upload(r->b.data(), n);
+        std::vector<double> zero(n, 0.0);
+        r->xd.alloc(n, nullptr);
+        r->xd.upload(zero.data(), n);
+        r->slot.sv = r->sv.get();
+        r->slot.b = r->bd.get();
+        r->slot.x = r->xd.get();
+        r->slot.n = n;
+      } catch (...) {
+        int code = NAMG_E_NOMEM;
+        std::string msg = "device upload failed";
+        try {
+          throw;
+        } catch (const HipError &e) {
+          code = e.code;
+          msg = e.msg;
+        } catch (...) {
+        }
+        r->sv.reset();
+        r->bd.release();
+        r->xd.release();
+        std::lock_guard<std::mutex> lk(mu_);
+        used_ -= r->footprint;
+        inflight_--;
+        r->status = code;
+        r->err = msg;
+        finish_locked(r);
+        cv_admit_.notify_all();
+        continue;
+      }
+      r->tm.admitted = clock();
+      {
+        std::lock_guard<std::mutex> lk(mu_);
+        join_q_.push_back(r);
+      }
+      cv_sched_.notify_one();
+    }
+  }
+
+  void complete(Req *r) {
+    const int32_t n = r->slot.n;
+    auto &sl = r->slot;
+    r->x.assign(n, 0.0);
+    if (sl.status >= 0)
+      hip_check(hipMemcpy(r->x.data(), r->xd.get(), sizeof(double) * n, hipMemcpyDeviceToHost), "hipMemcpy D2H");
+    double xn = 0.0;
+    for (double v : r->x) xn += v * v;
+    xn = std::sqrt(xn);
+    r->st.status = sl.status;
+    r->st.iters = sl.iters;
+    r->st.cycles = sl.cycles;
+    r->st.precond_apps = sl.apps;
+    r->st.relres_true = sl.beta > 0.0 ? sl.rn / sl.beta : 0.0;
+    r->st.relres_est = sl.est;
+    r->st.nrbe = sl.beta > 0.0 ? sl.rn / (sl.beta + r->H->anorm_inf * xn) : 0.0;
+    r->st.ms_total = (clock() - r->tm.admitted) * 1e3;
+    r->st.alg_bytes = sl.alg;
+    r->status = sl.status;
+    r->err = sl.err;
+    r->sv.reset();
+    r->bd.release();
+    r->xd.release();
+    r->H.reset();
+    r->b.clear();
+    r->b.shrink_to_fit();
+  }
+
+  void sched_loop() {
+    (void)hipSetDevice(p_.device);
+    std::vector<Req *> active;
+    while (true) {
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        if (active.empty()) cv_sched_.wait(lk, [&] { return stop_ || !join_q_.empty(); });
+        if (stop_) return;
+        for (Req *r : join_q_) active.push_back(r);
+        join_q_.clear();
+      }
+      std::vector<typename Engine::Slot *> slots;
+      for (Req *r : active) slots.push_back(&r->slot);
+      try {
+        eng_.tick(slots);
+      } catch (const HipError &e) {
+        for (auto *sl : slots) {
+          sl->status = e.code;
+          sl->err = e.msg;
+          sl->phase = Engine::DONE;
+        }
+      }
+      {
+        std::lock_guard<std::mutex> lk(mu_);
+        ticks_++;
+      }
+      std::vector<Req *> still;
+      for (Req *r : active) {
+        if (r->slot.phase != Engine::DONE) {
+          still.push_back(r);
+          continue;
+        }
+        try {
+          complete(r);
+        } catch (const HipError &e) {
+          r->status = e.code;
+          r->err = e.msg;
+        }
+        std::lock_guard<std::mutex> lk(mu_);
+        used_ -= r->footprint;
+        inflight_--;
+        finish_locked(r);
+        cv_admit_.notify_all();
+      }
+      active.swap(still);
+    }
+  }
+
+  namg_server_params p_;
+  std::chrono::steady_clock::time_point t0_;
+  Engine eng_;
+  std::mutex mu_;
+  std::condition_variable cv_setup_, cv_admit_, cv_sched_, cv_done_;
+  std::deque<Req *> setup_q_, admit_q_;
+  std::vector<Req *> join_q_;
+  std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs_;
+  std::vector<std::thread> setup_;
+  std::thread sched_;
+  bool stop_ = false;
+  uint64_t next_ = 1;
+  int64_t used_ = 0, peak_ = 0, inflight_ = 0, peak_inflight_ = 0, submitted_ = 0, completed_ = 0, failed_ = 0;
+  int64_t ticks_ = 0;
+};
+
+}  // namespace namg

@@ -60,13 +60,6 @@ void validate_solve_params(const namg_solve_params &p) {
   if (p.pre_sweeps < 0 || p.post_sweeps < 0) throw SetupError{NAMG_E_INVALID, "negative sweep count"};
 }
 
-// Launch-shape flags of a hierarchy: NAMG_KFLAGS overrides the default (for measurements).
-uint32_t kernel_flags() {
-  const char *e = std::getenv("NAMG_KFLAGS");
-  if (e && *e) return (uint32_t)std::strtoul(e, nullptr, 0);
-  return 0u;
-}
-
 // One function pointer per lanes-per-row group for every row kernel.
 #define NAMG_GROUP_SWITCH(NAME, ...)                      \
   switch (g) {                                            \
@@ -107,6 +100,9 @@ class SolverBase {
 };
 
 template <class T>
+class BatchEngine;
+
+template <class T>
 struct DevLevel {
   int32_t n = 0;
   DMat<T> A, P, R, pgs_lo, pgs_up, ilu_lo, ilu_up;
@@ -119,11 +115,11 @@ struct DevLevel {
 template <class T>
 class Solver final : public SolverBase {
   static constexpr double S = sizeof(T);
+  friend class BatchEngine<T>;
 
  public:
   Solver(const HostHierarchy &H, int device) : dev_(device), host_(&H) {
     DeviceGuard g(dev_);
-    const uint32_t kf = kernel_flags();
     const int nl = (int)H.lv.size();
     lv_.resize(nl);
     for (int l = 0; l < nl; ++l) {
@@ -133,16 +129,16 @@ class Solver final : public SolverBase {
       d.b.alloc(d.n, &mc_);
       d.x.alloc(d.n, &mc_);
       if (l == nl - 1) break;
-      d.A.build(h.A, &mc_, 0, kf);
-      d.P.build(h.P, &mc_, 0, kf);
-      d.R.build(h.R, &mc_, 0, kf);
-      d.pgs_lo.build(h.pgs_lo, &mc_, 0, kf);
-      d.pgs_up.build(h.pgs_up, &mc_, 0, kf);
+      d.A.build(h.A, &mc_);
+      d.P.build(h.P, &mc_);
+      d.R.build(h.R, &mc_);
+      d.pgs_lo.build(h.pgs_lo, &mc_);
+      d.pgs_up.build(h.pgs_up, &mc_);
       upload_vec(d.dinv, h.dinv);
       d.has_ilu = h.has_ilu;
       if (h.has_ilu) {
-        d.ilu_lo.build(h.ilu_lo, &mc_, 0, kf);
-        d.ilu_up.build(h.ilu_up, &mc_, 0, kf);
+        d.ilu_lo.build(h.ilu_lo, &mc_);
+        d.ilu_up.build(h.ilu_up, &mc_);
         upload_vec(d.ilu_dinv, h.ilu_dinv);
       }
       d.r.alloc(d.n, &mc_);
@@ -160,8 +156,8 @@ class Solver final : public SolverBase {
     for (int32_t i = 0; i < nc_; ++i)
       for (int32_t j = 0; j < nc_; ++j) inv.ci[(size_t)i * nc_ + j] = j;
     inv.v = H.coarse_inv;
-    coarse_inv_.build(inv, &mc_, nc_ > 1 ? 64 : 1, 0);
-    A64_.build(H.lv[0].A, &mc_, 1, kf);
+    coarse_inv_.build(inv, &mc_, nc_ > 1 ? 64 : 1);
+    A64_.build(H.lv[0].A, &mc_, 1);
     anorm_inf_ = H.anorm_inf;
     const int32_t n = lv_[0].n;
     nblk_red_ = (int32_t)blocks_for(n);
@@ -169,7 +165,6 @@ class Solver final : public SolverBase {
     kst_.alloc(1, &mc_);
     hip_check(hipHostMalloc((void **)&pinned_, 64, hipHostMallocMapped), "hipHostMalloc");
     hip_check(hipHostGetDevicePointer((void **)&pinned_dev_, pinned_, 0), "hipHostGetDevicePointer");
-    hip_check(hipDeviceSynchronize(), "upload");
   }
 
   ~Solver() override {
@@ -181,6 +176,12 @@ class Solver final : public SolverBase {
   }
 
   int64_t device_bytes() const override { return mc_.bytes; }
+
+  // Allocate the Krylov workspace for restart m ahead of the first solve (used by serving).
+  void reserve_workspace(int m) {
+    DeviceGuard g(dev_);
+    ensure_workspace(m);
+  }
 
   void profile(int family, int level) override {
     DeviceGuard g(dev_);
@@ -469,13 +470,77 @@ class Solver final : public SolverBase {
     return pinned_[2];
   }
 
+  // ------------------------------------------------------------------ V-cycle row operations
+  // Every row operation of the V-cycle is described by a RowOp. emit() launches it at once, or appends
+  // it to record_ while the batching engine collects the operations of several solves.
+ public:
+  struct RowOp {
+    int kind, group, family, level;
+    unsigned grid;
+    double bytes;
+    RowTask<T> t;
+  };
+
+ private:
+  std::vector<RowOp> *record_ = nullptr;
+
+  static RowOp row_op(int kind, int family, int level, const MatView<T> &M, int group, unsigned grid, double bytes,
+                      const T *a, const T *b, const T *c, const T *d, T *o0, T *o1, int32_t n) {
+    RowOp op;
+    op.kind = kind;
+    op.group = group;
+    op.family = family;
+    op.level = level;
+    op.grid = grid;
+    op.bytes = bytes;
+    op.t.M = M;
+    op.t.a = a;
+    op.t.b = b;
+    op.t.c = c;
+    op.t.d = d;
+    op.t.o0 = o0;
+    op.t.o1 = o1;
+    op.t.n = n;
+    op.t.pad = 0;
+    return op;
+  }
+
+  void emit(const RowOp &op, hipStream_t s) {
+    if (record_) {
+      record_->push_back(op);
+      return;
+    }
+    const RowTask<T> &t = op.t;
+    switch (op.kind) {
+      case ROP_RESIDUAL:
+        launch(op.family, op.level, op.bytes, sel_residual<T>(op.group), op.grid, s, t.M, t.a, t.b, t.c, t.o0, t.o1);
+        break;
+      case ROP_NEUMANN:
+        launch(op.family, op.level, op.bytes, sel_neumann<T>(op.group), op.grid, s, t.M, t.a, t.b, t.c, t.d, t.o0);
+        break;
+      case ROP_SPMV:
+        launch(op.family, op.level, op.bytes, sel_spmv<T, T, T, T>(op.group), op.grid, s, t.M, t.b, t.o0);
+        break;
+      case ROP_PROLONG:
+        launch(op.family, op.level, op.bytes, sel_prolong<T>(op.group), op.grid, s, t.M, t.b, t.o0);
+        break;
+      case ROP_AXPY:
+        launch(op.family, op.level, op.bytes, &k_axpy<T>, op.grid, s, t.a, t.c, t.d, t.o0, t.n);
+        break;
+      default:
+        launch(op.family, op.level, op.bytes, &k_fill<T>, op.grid, s, t.o0, T(0), t.n);
+        break;
+    }
+  }
+
   // r = b - A_l x (x may be null: x = 0) with optional outputs r and f = d .* r.
   void residual(int l, const T *b, const T *x, const T *d, T *r, T *f, hipStream_t s) {
     const DevLevel<T> &L = lv_[l];
     const int32_t n = L.n;
     const double bytes = (x ? L.A.bytes() + S * n : 0.0) + S * n * (1 + (r ? 1 : 0) + (f ? 2 : 0));
-    launch(NAMG_KF_RESIDUAL, l, bytes, sel_residual<T>(x ? L.A.group : 1), x ? rows_grid(L.A) : blocks_for(n), s,
-           L.A.view(), b, x, d, r, f);
+    emit(row_op(ROP_RESIDUAL, NAMG_KF_RESIDUAL, l, L.A.view(), x ? L.A.group : 1, x ? rows_grid(L.A) : blocks_for(n),
+                bytes, b, x, d, nullptr, r, f, n),
+         s);
   }
 
   // out = [acc +] [scale .*] (f - M in): one Neumann term on the strict triangle M of level l.
@@ -483,32 +548,44 @@ class Solver final : public SolverBase {
                hipStream_t s) {
     const int32_t n = M.nrows;
     const double vecs = (f == in ? 1 : 2) + 1 + (scale ? 1 : 0) + (acc ? 1 : 0);
-    launch(NAMG_KF_NEUMANN, l, M.bytes() + S * n * vecs, sel_neumann<T>(M.group), rows_grid(M), s, M.view(), f, in,
-           scale, acc, out);
+    emit(row_op(ROP_NEUMANN, NAMG_KF_NEUMANN, l, M.view(), M.group, rows_grid(M), M.bytes() + S * n * vecs, f, in,
+                scale, acc, out, nullptr, n),
+         s);
   }
 
-  void axpy(const T *f, const T *scale, const T *acc, T *out, int32_t n, hipStream_t s) {
+  void axpy(int l, const T *f, const T *scale, const T *acc, T *out, int32_t n, hipStream_t s) {
     const double vecs = 2 + (scale ? 1 : 0) + (acc ? 1 : 0);
-    launch(-1, 0, S * n * vecs, &k_axpy<T>, blocks_for(n), s, f, scale, acc, out, n);
+    emit(row_op(ROP_AXPY, -1, l, MatView<T>{nullptr, nullptr, nullptr, n}, 1, blocks_for(n), S * n * vecs, f, nullptr,
+                scale, acc, out, nullptr, n),
+         s);
+  }
+
+  void fill_zero(int l, T *out, int32_t n, hipStream_t s) {
+    emit(row_op(ROP_FILL, -1, l, MatView<T>{nullptr, nullptr, nullptr, n}, 1, blocks_for(n), S * n, nullptr, nullptr,
+                nullptr, nullptr, out, nullptr, n),
+         s);
   }
 
   void restrict_(int l, hipStream_t s) {
     DevLevel<T> &d = lv_[l];
     DevLevel<T> &c = lv_[l + 1];
-    launch(NAMG_KF_SPMV, l, d.R.bytes() + S * ((double)d.n + c.n), sel_spmv<T, T, T, T>(d.R.group), rows_grid(d.R), s,
-           d.R.view(), (const T *)d.r.get(), c.b.get());
+    emit(row_op(ROP_SPMV, NAMG_KF_SPMV, l, d.R.view(), d.R.group, rows_grid(d.R), d.R.bytes() + S * ((double)d.n + c.n),
+                nullptr, d.r.get(), nullptr, nullptr, c.b.get(), nullptr, c.n),
+         s);
   }
 
   void prolong(int l, T *x, hipStream_t s) {
     DevLevel<T> &d = lv_[l];
     DevLevel<T> &c = lv_[l + 1];
-    launch(NAMG_KF_PROLONG, l, d.P.bytes() + S * ((double)c.n + 2.0 * d.n), sel_prolong<T>(d.P.group), rows_grid(d.P),
-           s, d.P.view(), (const T *)c.x.get(), x);
+    emit(row_op(ROP_PROLONG, NAMG_KF_PROLONG, l, d.P.view(), d.P.group, rows_grid(d.P),
+                d.P.bytes() + S * ((double)c.n + 2.0 * d.n), nullptr, c.x.get(), nullptr, nullptr, x, nullptr, d.n),
+         s);
   }
 
   void coarse_solve(int l, const T *b, T *x, hipStream_t s) {
-    launch(NAMG_KF_SPMV, l, coarse_inv_.bytes() + 2 * S * nc_, sel_spmv<T, T, T, T>(coarse_inv_.group),
-           rows_grid(coarse_inv_), s, coarse_inv_.view(), b, x);
+    emit(row_op(ROP_SPMV, NAMG_KF_SPMV, l, coarse_inv_.view(), coarse_inv_.group, rows_grid(coarse_inv_),
+                coarse_inv_.bytes() + 2 * S * nc_, nullptr, b, nullptr, nullptr, x, nullptr, nc_),
+         s);
   }
 
   // g = (I + S)^{-1} f, one launch per dependency level.
@@ -536,7 +613,7 @@ class Solver final : public SolverBase {
       const DMat<T> &M = pre ? d.pgs_lo : d.pgs_up;
       if (o.tri_mode == NAMG_TRI_NEUMANN) {
         if (t == 1) {
-          axpy(d.f.get(), nul, first ? nul : (const T *)x, x, n, s);
+          axpy(l, d.f.get(), nul, first ? nul : (const T *)x, x, n, s);
         } else {
           const T *in = d.f.get();
           for (int q = 1; q < t; ++q) {
@@ -548,7 +625,7 @@ class Solver final : public SolverBase {
         }
       } else {
         tri_solve(l, pre ? d.tri_pgs_lo : d.tri_pgs_up, d.f.get(), d.g1.get(), s);
-        axpy(d.g1.get(), nul, first ? nul : (const T *)x, x, n, s);
+        axpy(l, d.g1.get(), nul, first ? nul : (const T *)x, x, n, s);
       }
       return;
     }
@@ -560,7 +637,7 @@ class Solver final : public SolverBase {
     }
     if (o.tri_mode == NAMG_TRI_NEUMANN) {
       if (t == 1) {
-        axpy(r, d.ilu_dinv.get(), first ? nul : (const T *)x, x, n, s);
+        axpy(l, r, d.ilu_dinv.get(), first ? nul : (const T *)x, x, n, s);
         return;
       }
       const T *in = r;
@@ -579,31 +656,41 @@ class Solver final : public SolverBase {
       }
     } else {
       tri_solve(l, d.tri_ilu_lo, r, d.g1.get(), s);
-      axpy(d.g1.get(), d.ilu_dinv.get(), nul, d.f.get(), n, s);
+      axpy(l, d.g1.get(), d.ilu_dinv.get(), nul, d.f.get(), n, s);
       tri_solve(l, d.tri_ilu_up, d.f.get(), d.g2.get(), s);
-      axpy(d.g2.get(), nul, first ? nul : (const T *)x, x, n, s);
+      axpy(l, d.g2.get(), nul, first ? nul : (const T *)x, x, n, s);
     }
   }
 
-  // One V-cycle with zero initial guess (Section 5): pre-smooth, residual, restrict, recurse, prolong
-  // and correct, post-smooth; dense solve on the coarsest level.
+  // The two halves of one level of the V-cycle (Section 5). Down: zero initial guess, pre-smoothing,
+  // residual, restriction. Up: prolongation and correction, post-smoothing.
+  void level_down(int l, const T *b, T *x, const CycleOpts &o, hipStream_t s) {
+    DevLevel<T> &d = lv_[l];
+    const bool ilu = (o.smoother == NAMG_SMOOTH_ILU0) && d.has_ilu;
+    if (o.nu1 == 0) fill_zero(l, x, d.n, s);
+    for (int k = 0; k < o.nu1; ++k) smooth(l, b, x, k == 0, true, ilu, o, s);
+    residual(l, b, x, nullptr, d.r.get(), nullptr, s);
+    restrict_(l, s);
+  }
+
+  void level_up(int l, const T *b, T *x, const CycleOpts &o, hipStream_t s) {
+    DevLevel<T> &d = lv_[l];
+    const bool ilu = (o.smoother == NAMG_SMOOTH_ILU0) && d.has_ilu;
+    prolong(l, x, s);
+    for (int k = 0; k < o.nu2; ++k) smooth(l, b, x, false, false, ilu, o, s);
+  }
+
+  // One V-cycle with zero initial guess; dense solve on the coarsest level.
   void vcycle(int l, const T *b, T *x, const CycleOpts &o, hipStream_t s) {
     const int nl = (int)lv_.size();
     if (l == nl - 1) {
       coarse_solve(l, b, x, s);
       return;
     }
-    DevLevel<T> &d = lv_[l];
     DevLevel<T> &c = lv_[l + 1];
-    const int32_t n = d.n;
-    const bool ilu = (o.smoother == NAMG_SMOOTH_ILU0) && d.has_ilu;
-    if (o.nu1 == 0) launch(-1, l, S * n, &k_fill<T>, blocks_for(n), s, x, T(0), n);
-    for (int k = 0; k < o.nu1; ++k) smooth(l, b, x, k == 0, true, ilu, o, s);
-    residual(l, b, x, nullptr, d.r.get(), nullptr, s);
-    restrict_(l, s);
+    level_down(l, b, x, o, s);
     vcycle(l + 1, c.b.get(), c.x.get(), o, s);
-    prolong(l, x, s);
-    for (int k = 0; k < o.nu2; ++k) smooth(l, b, x, false, false, ilu, o, s);
+    level_up(l, b, x, o, s);
   }
 
   // Level schedules and CSR copies for the direct comparators, built on their first use.
@@ -647,6 +734,8 @@ class Solver final : public SolverBase {
 };
 
 }  // namespace namg
+
+#include "server.hpp"
 
 struct namg_hier {
   namg::HostHierarchy host;
@@ -844,5 +933,95 @@ void namg_destroy(namg_hier *h) {
 }
 
 const char *namg_last_error(void) { return namg::g_last_error.c_str(); }
+
+struct namg_server {
+  std::unique_ptr<namg::ServerBase> impl;
+};
+
+void namg_default_server_params(namg_server_params *p) {
+  if (!p) return;
+  p->hbm_budget = 0;
+  p->max_inflight = 64;
+  p->setup_threads = 8;
+  p->device = 0;
+  p->precision = NAMG_FP32_PRECOND;
+  namg_default_solve_params(&p->solve);
+}
+
+int namg_server_create(const namg_server_params *p, namg_server **out) {
+  return guarded([&]() -> int {
+    if (!p || !out) throw namg::SetupError{NAMG_E_INVALID, "null argument"};
+    *out = nullptr;
+    namg::validate_solve_params(p->solve);
+    if (p->solve.tri_mode != NAMG_TRI_NEUMANN)
+      throw namg::SetupError{NAMG_E_INVALID, "serving batches the Neumann smoothers only (tri_mode must be NEUMANN)"};
+    if (p->max_inflight < 1 || p->max_inflight > namg::MAX_BATCH)
+      throw namg::SetupError{NAMG_E_INVALID, "max_inflight out of range"};
+    if (p->setup_threads < 1) throw namg::SetupError{NAMG_E_INVALID, "setup_threads must be >= 1"};
+    if (p->precision != NAMG_FP64 && p->precision != NAMG_FP32_PRECOND)
+      throw namg::SetupError{NAMG_E_INVALID, "unknown precision"};
+    int count = 0;
+    namg::hip_check(hipGetDeviceCount(&count), "hipGetDeviceCount");
+    if (p->device < 0 || p->device >= count) throw namg::SetupError{NAMG_E_INVALID, "device ordinal out of range"};
+    namg_server_params q = *p;
+    if (q.hbm_budget <= 0) {
+      namg::DeviceGuard g(q.device);
+      size_t free_b = 0, total_b = 0;
+      namg::hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+      q.hbm_budget = (int64_t)total_b - ((int64_t)16 << 30);
+      if (q.hbm_budget <= 0) q.hbm_budget = (int64_t)total_b / 2;
+    }
+    auto s = std::make_unique<namg_server>();
+    if (q.precision == NAMG_FP64)
+      s->impl = std::make_unique<namg::Server<double>>(q);
+    else
+      s->impl = std::make_unique<namg::Server<float>>(q);
+    *out = s.release();
+    return NAMG_OK;
+  });
+}
+
+int namg_server_submit(namg_server *s, int32_t n, const int32_t *rowptr, const int32_t *colind, const double *vals,
+                       const double *b, const namg_setup_params *sp, uint64_t *ticket) {
+  return guarded([&]() -> int {
+    if (!s || !b || !sp || !ticket) throw namg::SetupError{NAMG_E_INVALID, "null argument"};
+    namg::HostCsr A = namg::import_csr(n, rowptr, colind, vals);
+    *ticket = s->impl->submit(A, b, *sp);
+    return NAMG_OK;
+  });
+}
+
+int namg_server_poll(namg_server *s, uint64_t ticket, double *x, namg_solve_stats *st, namg_request_times *tm) {
+  return guarded([&]() -> int {
+    if (!s) throw namg::SetupError{NAMG_E_INVALID, "null server"};
+    return s->impl->poll(ticket, false, x, st, tm);
+  });
+}
+
+int namg_server_wait(namg_server *s, uint64_t ticket, double *x, namg_solve_stats *st, namg_request_times *tm) {
+  return guarded([&]() -> int {
+    if (!s) throw namg::SetupError{NAMG_E_INVALID, "null server"};
+    return s->impl->poll(ticket, true, x, st, tm);
+  });
+}
+
+int namg_server_stats(namg_server *s, namg_server_counters *out) {
+  return guarded([&]() -> int {
+    if (!s || !out) throw namg::SetupError{NAMG_E_INVALID, "null argument"};
+    *out = s->impl->stats();
+    return NAMG_OK;
+  });
+}
+
+double namg_server_clock(const namg_server *s) { return s ? s->impl->clock() : 0.0; }
+
+void namg_server_destroy(namg_server *s) {
+  if (!s) return;
+  try {
+    s->impl.reset();
+  } catch (...) {
+  }
+  delete s;
+}
 
 }  // extern "C"

@@ -1,0 +1,123 @@
+"""GPU tests of the serving scheduler (namg_server_*): continuous batching of many solves.
+
+* Each result is the same alone and in the mix: a request solved with max_inflight = 1 and the same
+  request solved among others (batched launches, different neighbours in every tick) give bit-identical
+  x and the same iteration count; both also equal the single-solve path (namg_solve) bit for bit.
+* Every result reaches the 1e-8 true relative residual, checked with the oracle's FP64 SpMV.
+* Admission keeps the device bytes of in-flight solves within the HBM budget; a request larger than the
+  whole budget fails with NAMG_E_BUDGET; malformed input is rejected at submission.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import CSR, varcoef3d
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def namg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2112_14681_amd as m
+
+    return m
+
+
+def stream_systems(k, nmin=10, nmax=22, seed=7):
+    """A mixed-size stream of variable-coefficient systems (the serving workload's generator, small n)."""
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(nmin, nmax + 1, k)
+    return [varcoef3d(int(N), 0.5, 1000 + j) for j, N in enumerate(sizes)]
+
+
+SOLVE = dict(smoother=0, inner_terms=2, restart=30, tol=1e-8)
+
+
+def relres(A, b, x):
+    return np.linalg.norm(b - O.spmv(A, x)) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_alone_vs_mix_bitwise(namg, precision):
+    systems = stream_systems(10)
+    alone = []
+    s1 = namg.Server(solve=SOLVE, max_inflight=1, setup_threads=2, precision=precision)
+    for A, b in systems:
+        alone.append(s1.wait(s1.submit(A, b)))
+    c1 = s1.stats()
+    s1.close()
+    assert c1["peak_inflight"] == 1 and c1["completed"] == len(systems)
+
+    s8 = namg.Server(solve=SOLVE, max_inflight=8, setup_threads=4, precision=precision)
+    tickets = [s8.submit(A, b) for A, b in systems]
+    mix = [s8.wait(t) for t in tickets]
+    c8 = s8.stats()
+    s8.close()
+    assert c8["completed"] == len(systems) and c8["peak_inflight"] > 1
+    assert c8["ticks"] < c1["ticks"]  # the solves really shared ticks
+    for (A, b), a, m in zip(systems, alone, mix):
+        assert a["status"] == namg.OK and m["status"] == namg.OK
+        assert a["iters"] == m["iters"]
+        assert np.array_equal(a["x"], m["x"])
+        assert relres(A, b, m["x"]) <= 1e-8
+        assert m["relres_true"] == pytest.approx(relres(A, b, m["x"]), rel=1e-6)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_server_matches_single_solve_path(namg, precision):
+    systems = stream_systems(3, 14, 20, seed=11)
+    srv = namg.Server(solve=SOLVE, max_inflight=4, setup_threads=3, precision=precision)
+    res = [srv.wait(t) for t in [srv.submit(A, b) for A, b in systems]]
+    srv.close()
+    for (A, b), r in zip(systems, res):
+        H = namg.Hierarchy(A, device=0, precision=precision)
+        bt = torch.from_numpy(b).to("cuda:0")
+        xt = torch.zeros_like(bt)
+        st = H.solve(bt, xt, **SOLVE)
+        torch.cuda.synchronize()
+        assert st["iters"] == r["iters"]
+        assert np.array_equal(xt.cpu().numpy(), r["x"])
+
+
+def test_budget_admission_and_rejection(namg):
+    systems = stream_systems(6, 16, 20, seed=3)
+    # one request at a time: the peak is the largest single footprint
+    probe = namg.Server(solve=SOLVE, max_inflight=1, setup_threads=2, precision=1)
+    ref = [probe.wait(t) for t in [probe.submit(A, b) for A, b in systems]]
+    one = probe.stats()["peak_device_bytes"]
+    probe.close()
+    assert one > 0
+    # a budget that holds at most one of these requests at a time
+    budget = int(1.5 * one)
+    srv = namg.Server(solve=SOLVE, max_inflight=8, setup_threads=3, precision=1, hbm_budget=budget)
+    out = [srv.wait(t) for t in [srv.submit(A, b) for A, b in systems]]
+    c = srv.stats()
+    assert c["peak_device_bytes"] <= budget
+    for r, q in zip(out, ref):
+        assert r["status"] == namg.OK and np.array_equal(r["x"], q["x"])
+    # a request larger than the whole budget
+    A, b = varcoef3d(40, 0.5, 5)
+    t = srv.submit(A, b)
+    with pytest.raises(namg.NamgError) as e:
+        srv.wait(t)
+    assert e.value.code == namg.E_BUDGET
+    srv.close()
+
+
+def test_bad_input_and_not_converged(namg):
+    srv = namg.Server(solve=dict(SOLVE, max_iters=2, tol=1e-14), max_inflight=4, setup_threads=1, precision=0)
+    A, b = varcoef3d(12, 0.5, 9)
+    bad = CSR(A.n, A.rowptr.copy(), A.colind.copy(), A.vals.copy())
+    bad.colind[[0, 1]] = bad.colind[[1, 0]]
+    with pytest.raises(namg.NamgError) as e:
+        srv.submit(bad, b)
+    assert e.value.code == namg.E_INVALID
+    r = srv.wait(srv.submit(A, b))
+    assert r["status"] == namg.NOT_CONVERGED and r["iters"] == 2
+    # b = 0 gives x = 0 at once
+    z = srv.wait(srv.submit(A, np.zeros(A.n)))
+    assert z["status"] == namg.OK and not np.any(z["x"])
+    srv.close()

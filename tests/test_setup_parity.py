@@ -138,3 +138,13 @@ def test_solve_param_validation(namg):
         p = namg.solve_params(**bad)
         code = namg.lib().namg_solve(H.h, 1, 1, C.byref(p), None, None)
         assert code == namg.E_INVALID, bad
+
+
+def test_server_parameter_validation(namg):
+    """Serving parameters are checked before any device work."""
+    for bad in (dict(solve=dict(tri_mode=1)), dict(max_inflight=0), dict(max_inflight=1000), dict(setup_threads=0),
+                dict(precision=5), dict(solve=dict(restart=0))):
+        solve = bad.pop("solve", None)
+        with pytest.raises(namg.NamgError) as e:
+            namg.Server(solve=solve, **bad)
+        assert e.value.code == namg.E_INVALID
