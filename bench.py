@@ -37,6 +37,11 @@ def _args():
     ap.add_argument("--gmres-T", default="neumann", choices=["neumann", "direct"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare", action="store_true", help="also time the direct-triangular and FP32 variants")
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="requests of the served stream to replay (0: skip; 2000: the whole stream)")
+    ap.add_argument("--serve-inflight", type=int, default=64)
+    ap.add_argument("--serve-setup-threads", type=int, default=12)
+    ap.add_argument("--serve-only", action="store_true")
     return ap.parse_args()
 
 
@@ -78,6 +83,66 @@ def _time_solves(torch, H, bt, xt, kw, steps, warmup):
     return (time.perf_counter() - t0) * 1e3 / steps, stats
 
 
+def _gen_request(args):
+    from workloads import varcoef3d
+
+    N, seed = args
+    return varcoef3d(N, 0.5, seed)
+
+
+def served_stream(namg, count, inflight, setup_threads):
+    """Replay the first `count` requests of the served stream (Poisson arrivals at 50/s, n log-uniform in
+    [32, 160], variable-k pressure systems) against the continuous-batching server: FP32 AMG + FP64 GMRES(30),
+    polynomial GS with 2 Neumann terms, tol 1e-8. Latency runs from each request's scheduled arrival to its
+    completion on the server's clock."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor, ThreadPoolExecutor
+
+    from workloads import serve_stream
+
+    reqs = serve_stream(2000, seed=5)[:count]
+    # fresh interpreters (spawn): the generator processes never inherit this process's GPU runtime
+    with ProcessPoolExecutor(max_workers=16, mp_context=mp.get_context("spawn")) as ex:
+        systems = list(ex.map(_gen_request, [(r["N"], r["seed"]) for r in reqs], chunksize=2))
+    srv = namg.Server(solve=dict(smoother=namg.SMOOTH_PGS, inner_terms=2, restart=30, tol=1e-8),
+                      max_inflight=inflight, setup_threads=setup_threads, precision=namg.FP32_PRECOND)
+    t0_srv = srv.clock()
+    t0 = time.perf_counter()
+
+    def submit(j):
+        delay = reqs[j]["arrival_s"] - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        A, b = systems[j]
+        return srv.submit(A, b)
+
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        tickets = list(ex.map(submit, range(count)))
+    results = [srv.wait(t) for t in tickets]
+    counters = srv.stats()
+    srv.close()
+    lat = np.array([r["times"]["done"] - (t0_srv + q["arrival_s"]) for r, q in zip(results, reqs)])
+    done = np.array([r["times"]["done"] - t0_srv for r in results])
+    solve_s = np.array([r["times"]["done"] - r["times"]["admitted"] for r in results])
+    setup_s = np.array([r["times"]["setup_done"] - r["times"]["setup_start"] for r in results])
+    queue_s = np.array([r["times"]["setup_start"] - r["times"]["submit"] for r in results])
+    ok = all(r["status"] == namg.OK and r["relres_true"] <= 1e-8 for r in results)
+    span = done.max() - reqs[0]["arrival_s"]
+    return {
+        "requests": count, "all_converged": bool(ok),
+        "p50_s": round(float(np.percentile(lat, 50)), 4), "p99_s": round(float(np.percentile(lat, 99)), 4),
+        "max_s": round(float(lat.max()), 4), "solves_per_s": round(count / span, 2),
+        "arrival_span_s": round(reqs[-1]["arrival_s"] - reqs[0]["arrival_s"], 3),
+        "median_queue_s": round(float(np.median(queue_s)), 4), "median_setup_s": round(float(np.median(setup_s)), 4),
+        "median_inflight_s": round(float(np.median(solve_s)), 4),
+        "mean_iters": round(float(np.mean([r["iters"] for r in results])), 2),
+        "alg_GBps_while_serving": round(sum(r["alg_bytes"] for r in results) / span / 1e9, 1),
+        "peak_inflight": counters["peak_inflight"], "ticks": counters["ticks"], "batched_launches": counters["launches"],
+        "peak_device_GB": round(counters["peak_device_bytes"] / 1e9, 2),
+        "setup_threads": setup_threads, "max_inflight": inflight,
+    }
+
+
 def cpu_baseline(A, b, kw, gpu_iters):
     """The oracle (single-threaded FP64 C++) on the same system: setup excluded, full solve timed."""
     import oracle
@@ -104,6 +169,12 @@ def main():
 
     import paper_2112_14681_amd as namg
     from workloads import config_system
+
+    if args.serve_only:
+        print(json.dumps({"metric": "served latency of the pressure-system request stream",
+                          "served": served_stream(namg, args.serve_requests, args.serve_inflight,
+                                                  args.serve_setup_threads)}), flush=True)
+        return
 
     A, b, meta = config_system(args.config, args.N)
     prec = namg.FP64 if args.precision == "fp64" else namg.FP32_PRECOND
@@ -183,6 +254,9 @@ def main():
             cmp[name] = {"ms": round(ms2, 3), "iters": st2[-1]["iters"], "relres": st2[-1]["relres_true"]}
         out["compare"] = cmp
 
+    if args.serve_requests > 0:
+        H.close()
+        out["served"] = served_stream(namg, args.serve_requests, args.serve_inflight, args.serve_setup_threads)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, b, kw, st["iters"])
     print(json.dumps(out), flush=True)
