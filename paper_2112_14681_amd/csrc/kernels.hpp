@@ -46,18 +46,41 @@ __device__ __forceinline__ double block_sum(double v, double *lds) {
 // Row `row` of a sparse matrix times x, reduced over the G lanes of the row's group (every lane of the
 // group returns the full sum). G == 1: SELL-64, one lane per row. G > 1: CSR, lane `sub` takes entries
 // sub, sub + G, ...; groups are aligned inside the wavefront, so the butterfly never leaves the group.
+// Entries go in chunks of U: the chunk's index and value loads are all issued, then all its gathers,
+// then the multiply-adds in entry order. A short row thus waits on two dependent memory latencies per
+// chunk rather than two per entry. Slots past the row's end reload the chunk's first entry (in bounds)
+// and are not added, so the sum is the plain in-order one.
 template <int G, class Acc, class TM, class TX>
 __device__ __forceinline__ Acc row_dot(const MatView<TM> &A, const TX *__restrict__ x, int32_t row, int sub) {
-  Acc acc = Acc(0);
+  constexpr int U = 4;
+  constexpr int32_t STEP = G == 1 ? SELL_C : G;
+  int32_t k, end;
   if constexpr (G == 1) {
     const int32_t s = row >> 6;
-    const int32_t end = A.ptr[s + 1];
-#pragma unroll 4
-    for (int32_t k = A.ptr[s] + (row & 63); k < end; k += SELL_C) acc += (Acc)A.val[k] * (Acc)x[A.col[k]];
+    k = A.ptr[s] + (row & 63);
+    end = A.ptr[s + 1];
   } else {
-    const int32_t end = A.ptr[row + 1];
-#pragma unroll 2
-    for (int32_t k = A.ptr[row] + sub; k < end; k += G) acc += (Acc)A.val[k] * (Acc)x[A.col[k]];
+    k = A.ptr[row] + sub;
+    end = A.ptr[row + 1];
+  }
+  Acc acc = Acc(0);
+  for (; k < end; k += U * STEP) {
+    int32_t c[U];
+    TM v[U];
+    TX xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t kk = k + u * STEP < end ? k + u * STEP : k;
+      c[u] = A.col[kk];
+      v[u] = A.val[kk];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k + u * STEP < end) acc += (Acc)v[u] * (Acc)xv[u];
+  }
+  if constexpr (G > 1) {
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
   }
@@ -87,11 +110,13 @@ __device__ __forceinline__ void residual_body(uint32_t lb, const MatView<T> &A, 
                                               const T *__restrict__ x, const T *__restrict__ d, T *__restrict__ r,
                                               T *__restrict__ f) {
   NAMG_ROWS(G, A.nrows, lb)
+  const T bv = b[row];
+  const T dv = f ? d[row] : T(0);
   const T acc = x ? row_dot<G, T>(A, x, row, sub) : T(0);
   if (sub != 0) return;
-  const T rr = b[row] - acc;
+  const T rr = bv - acc;
   if (r) r[row] = rr;
-  if (f) f[row] = d[row] * rr;
+  if (f) f[row] = dv * rr;
 }
 
 // One Neumann / Jacobi inner term on a pre-scaled strict triangle S:
@@ -103,11 +128,14 @@ __device__ __forceinline__ void neumann_body(uint32_t lb, const MatView<T> &S, c
                                              const T *__restrict__ in, const T *__restrict__ scale, const T *acc,
                                              T *out) {
   NAMG_ROWS(G, S.nrows, lb)
+  const T fv = f[row];
+  const T sc = scale ? scale[row] : T(1);
+  const T av = acc ? acc[row] : T(0);
   const T sv = row_dot<G, T>(S, in, row, sub);
   if (sub != 0) return;
-  T v = f[row] - sv;
-  if (scale) v *= scale[row];
-  if (acc) v += acc[row];
+  T v = fv - sv;
+  if (scale) v *= sc;
+  if (acc) v += av;
   out[row] = v;
 }
 
@@ -115,8 +143,9 @@ __device__ __forceinline__ void neumann_body(uint32_t lb, const MatView<T> &S, c
 template <int G, class T>
 __device__ __forceinline__ void prolong_body(uint32_t lb, const MatView<T> &P, const T *__restrict__ e, T *x) {
   NAMG_ROWS(G, P.nrows, lb)
+  const T xv = x[row];
   const T v = row_dot<G, T>(P, e, row, sub);
-  if (sub == 0) x[row] += v;
+  if (sub == 0) x[row] = xv + v;
 }
 
 // out = [acc +] [scale .*] f
