@@ -149,10 +149,11 @@ typedef struct {
   double alg_bytes; /* sum of their algorithmic HBM bytes */
 } namg_kernel_profile;
 
-/* Time every later launch of one kernel family (on one level, or -1 for all levels) with start/stop
- * events attached to the dispatch on its stream; results accumulate until namg_profile_read, which
- * returns and clears them. family NAMG_KF_NONE switches timing off. */
-int namg_profile_kernel(namg_hier *h, int family, int level);
+/* Time later launches of one kernel family (on one level, or -1 for all levels) with start/stop events
+ * attached to the dispatch on its stream: the first matching launch and then every `every`-th one
+ * (every >= 1; sampling keeps the events' own cost out of the timed work). Results accumulate until
+ * namg_profile_read, which returns and clears them. family NAMG_KF_NONE switches timing off. */
+int namg_profile_kernel(namg_hier *h, int family, int level, int every);
 int namg_profile_read(namg_hier *h, namg_kernel_profile *out);
 
 /* Hierarchy shape: levels, n_l, nnz(A_l), operator and grid complexity, device bytes. */

@@ -103,7 +103,7 @@ def _load():
     lib.namg_solve.argtypes = [vp, vp, vp, C.POINTER(SolveParams), vp, C.POINTER(SolveStats)]
     lib.namg_vcycle.argtypes = [vp, vp, vp, C.POINTER(SolveParams), vp]
     lib.namg_apply.argtypes = [vp, C.c_int, C.c_int, C.POINTER(SolveParams), vp, vp, vp, vp]
-    lib.namg_profile_kernel.argtypes = [vp, C.c_int, C.c_int]
+    lib.namg_profile_kernel.argtypes = [vp, C.c_int, C.c_int, C.c_int]
     lib.namg_profile_read.argtypes = [vp, C.POINTER(KernelProfile)]
     lib.namg_hier_info.argtypes = [vp, C.POINTER(HierInfo)]
     lib.namg_level_sizes.argtypes = [vp, C.c_int, i32p, i64p, i64p, i32p]
@@ -246,9 +246,10 @@ class Hierarchy:
         p = solve_params(**params)
         _check(_lib.namg_vcycle(self.h, _dev_ptr(b, self.n), _dev_ptr(x, self.n), C.byref(p), _stream(stream)))
 
-    def profile_kernel(self, family, level=-1):
-        """Time every later launch of a kernel family (hipEvents attached to each dispatch)."""
-        _check(_lib.namg_profile_kernel(self.h, family, level))
+    def profile_kernel(self, family, level=-1, every=1):
+        """Time later launches of a kernel family (hipEvents attached to the first and then every
+        `every`-th matching dispatch)."""
+        _check(_lib.namg_profile_kernel(self.h, family, level, every))
 
     def profile_read(self) -> dict:
         kp = KernelProfile()

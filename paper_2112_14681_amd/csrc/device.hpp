@@ -83,20 +83,48 @@ class DevBuf {
 // Sparse operators on the device come in one of two layouts, chosen per matrix at setup from its row
 // lengths so that every row kernel keeps enough independent loads in flight:
 //  * group == 1: SELL-64. Rows are cut into slices of 64 consecutive rows (one wavefront); slice s
-//    stores entry k of each of its rows at val[ptr[s] + 64*k + lane], padded with (column 0, value 0)
-//    up to the slice's longest row. One lane per row; the loads of a wavefront are contiguous.
+//    stores entry k of each of its rows at val[ptr[s] + 64*k + lane], padded with value 0 up to the
+//    slice's longest row. One lane per row; the loads of a wavefront are contiguous.
 //  * group == G in {2, 4, ..., 64}: CSR, G lanes per row. Lane j of a row's group takes entries
 //    j, j+G, ...; the G partial sums are combined by a fixed xor-butterfly. Used for the long rows of
 //    the Galerkin operators on coarse levels, where one lane per row would walk 30-100 dependent
 //    entries.
+// Column indices are stored in one of two widths, also chosen per matrix: as 16-bit offsets from the
+// row's scaled diagonal, base(r) = (r * mul) >> 20 with mul = (ncols << 20) / nrows, when every column
+// of the matrix lies within [-32768, 32767] of its row's base (stencil operators and their Galerkin
+// coarsenings up to about 180^2 unknowns per plane), else as plain 32-bit columns. The narrow form cuts
+// a pass over an FP64 matrix from 12 to 10 bytes per entry, and from 8 to 6 in FP32. Padding entries
+// carry offset 0 (column base(r)) or column 0.
 // Row order and the order of entries within a row are those of the CSR input.
 constexpr int SELL_C = 64;
+constexpr int COL_SHIFT = 20;
+
+__host__ __device__ inline int32_t diag_base(int32_t row, int64_t mul) {
+  return (int32_t)(((int64_t)row * mul) >> COL_SHIFT);
+}
+
+inline int64_t diag_mul(int64_t nrows, int64_t ncols) { return nrows > 0 ? (ncols << COL_SHIFT) / nrows : 0; }
+
+// True when every column of A fits the 16-bit offset form.
+inline bool fits_col16(const HostCsr &A) {
+  const int64_t mul = diag_mul(A.nr, A.nc);
+  for (int32_t r = 0; r < A.nr; ++r) {
+    const int32_t base = diag_base(r, mul);
+    for (int32_t k = A.rp[r]; k < A.rp[r + 1]; ++k) {
+      const int64_t d = (int64_t)A.ci[k] - base;
+      if (d < -32768 || d > 32767) return false;
+    }
+  }
+  return true;
+}
 
 template <class T>
 struct MatView {
-  const int32_t *ptr = nullptr;  // SELL slice pointers (group 1) or CSR row pointers (group > 1)
-  const int32_t *col = nullptr;
+  const int32_t *ptr = nullptr;    // SELL slice pointers (group 1) or CSR row pointers (group > 1)
+  const int32_t *col = nullptr;    // 32-bit columns, or null when col16 is used
+  const int16_t *col16 = nullptr;  // 16-bit offsets from diag_base(row, mul), or null
   const T *val = nullptr;
+  int64_t mul = 0;
   int32_t nrows = 0;
 };
 
@@ -113,57 +141,87 @@ inline int choose_group(int64_t nrows, int64_t nnz) {
 template <class T>
 struct DMat {
   int32_t nrows = 0, ncols = 0, group = 1;
-  int64_t nnz = 0, stored = 0;
+  int64_t nnz = 0, stored = 0, mul = 0;
+  bool narrow = false;
   DevBuf<int32_t> ptr, col;
+  DevBuf<int16_t> col16;
   DevBuf<T> val;
-  MatView<T> view() const { return MatView<T>{ptr.get(), col.get(), val.get(), nrows}; }
+  MatView<T> view() const {
+    MatView<T> v;
+    v.ptr = ptr.get();
+    v.col = narrow ? nullptr : col.get();
+    v.col16 = narrow ? col16.get() : nullptr;
+    v.val = val.get();
+    v.mul = mul;
+    v.nrows = nrows;
+    return v;
+  }
   // algorithmic bytes of one pass over the matrix (entries once, row/slice pointers once)
   double bytes() const {
     const double nptr = group > 1 ? (double)nrows + 1.0 : (double)((nrows + SELL_C - 1) / SELL_C) + 1.0;
-    return (double)nnz * (sizeof(T) + 4.0) + 4.0 * nptr;
+    return (double)nnz * (sizeof(T) + (narrow ? 2.0 : 4.0)) + 4.0 * nptr;
   }
 
   void build(const HostCsr &A, MemCounter *mc, int force_group = 0) {
     nrows = A.nr;
     ncols = A.nc;
     nnz = A.nnz();
+    mul = diag_mul(nrows, ncols);
+    narrow = fits_col16(A);
     group = force_group > 0 ? force_group : choose_group(nrows, nnz);
+    std::vector<int32_t> hptr;
+    std::vector<int32_t> hcol;  // column of each stored entry (padding: -1)
+    std::vector<T> hval;
     if (group > 1) {
       stored = nnz;
-      std::vector<T> hv(A.v.begin(), A.v.end());
-      ptr.alloc(A.rp.size(), mc);
-      ptr.upload(A.rp.data(), A.rp.size());
-      col.alloc(A.ci.size(), mc);
-      col.upload(A.ci.data(), A.ci.size());
-      val.alloc(hv.size(), mc);
-      val.upload(hv.data(), hv.size());
-      return;
-    }
-    const int32_t nslices = (nrows + SELL_C - 1) / SELL_C;
-    std::vector<int32_t> hsp(nslices + 1, 0);
-    for (int32_t s = 0; s < nslices; ++s) {
-      int32_t w = 0;
-      for (int32_t r = s * SELL_C; r < std::min(nrows, (s + 1) * SELL_C); ++r)
-        w = std::max(w, A.rp[r + 1] - A.rp[r]);
-      hsp[s + 1] = hsp[s] + w * SELL_C;
-    }
-    stored = hsp[nslices];
-    std::vector<int32_t> hcol(stored, 0);
-    std::vector<T> hval(stored, T(0));
-    for (int32_t s = 0; s < nslices; ++s)
-      for (int32_t lane = 0; lane < SELL_C; ++lane) {
-        const int32_t r = s * SELL_C + lane;
-        if (r >= nrows) break;
-        for (int32_t k = 0; k < A.rp[r + 1] - A.rp[r]; ++k) {
-          const int64_t d = hsp[s] + (int64_t)k * SELL_C + lane;
-          hcol[d] = A.ci[A.rp[r] + k];
-          hval[d] = (T)A.v[A.rp[r] + k];
-        }
+      hptr = A.rp;
+      hcol = A.ci;
+      hval.assign(A.v.begin(), A.v.end());
+    } else {
+      const int32_t nslices = (nrows + SELL_C - 1) / SELL_C;
+      hptr.assign(nslices + 1, 0);
+      for (int32_t s = 0; s < nslices; ++s) {
+        int32_t w = 0;
+        for (int32_t r = s * SELL_C; r < std::min(nrows, (s + 1) * SELL_C); ++r)
+          w = std::max(w, A.rp[r + 1] - A.rp[r]);
+        hptr[s + 1] = hptr[s] + w * SELL_C;
       }
-    ptr.alloc(hsp.size(), mc);
-    ptr.upload(hsp.data(), hsp.size());
-    col.alloc(hcol.size(), mc);
-    col.upload(hcol.data(), hcol.size());
+      stored = hptr[nslices];
+      hcol.assign(stored, -1);
+      hval.assign(stored, T(0));
+      for (int32_t s = 0; s < nslices; ++s)
+        for (int32_t lane = 0; lane < SELL_C; ++lane) {
+          const int32_t r = s * SELL_C + lane;
+          if (r >= nrows) break;
+          for (int32_t k = 0; k < A.rp[r + 1] - A.rp[r]; ++k) {
+            const int64_t d = hptr[s] + (int64_t)k * SELL_C + lane;
+            hcol[d] = A.ci[A.rp[r] + k];
+            hval[d] = (T)A.v[A.rp[r] + k];
+          }
+        }
+    }
+    ptr.alloc(hptr.size(), mc);
+    ptr.upload(hptr.data(), hptr.size());
+    if (narrow) {
+      // offsets from the owning row's base; SELL entry d belongs to row 64 * slice + (d - ptr[slice]) % 64
+      std::vector<int16_t> h16(hcol.size(), 0);
+      if (group > 1) {
+        for (int32_t r = 0; r < nrows; ++r)
+          for (int32_t k = hptr[r]; k < hptr[r + 1]; ++k) h16[k] = (int16_t)(hcol[k] - diag_base(r, mul));
+      } else {
+        for (size_t s = 0; s + 1 < hptr.size(); ++s)
+          for (int32_t d = hptr[s]; d < hptr[s + 1]; ++d) {
+            const int32_t r = (int32_t)s * SELL_C + (d - hptr[s]) % SELL_C;
+            h16[d] = hcol[d] < 0 ? (int16_t)0 : (int16_t)(hcol[d] - diag_base(r, mul));
+          }
+      }
+      col16.alloc(h16.size(), mc);
+      col16.upload(h16.data(), h16.size());
+    } else {
+      for (auto &c : hcol) c = std::max(c, 0);
+      col.alloc(hcol.size(), mc);
+      col.upload(hcol.data(), hcol.size());
+    }
     val.alloc(hval.size(), mc);
     val.upload(hval.data(), hval.size());
   }
@@ -201,11 +259,11 @@ constexpr int KS_LD = KS_MAXR + 2;
 
 struct KState {
   double est;      // |g_{i+1}| / ||b|| after the latest column
-  double rho_inv;  // 1 / r_{i+1,i+1} of the current step
+  double rho;      // ||v_{i+1}||, the lagged norm of the current step
+  double rho_inv;  // 1 / rho (0 on breakdown)
   int32_t flag;    // 0 continue, 1 stop (converged / last column / breakdown), -1 non-finite
   int32_t pad;
-  double s[KS_LD];      // projection coefficients of the current step
-  double rprev[KS_LD];  // projection coefficients of the previous step (top of the pending H column)
+  double s[KS_LD];      // projection coefficients of the latest step (top of the pending H column)
   double g[KS_LD];      // rotated right-hand side
   double cs[KS_LD], sn[KS_LD];
   double zs[KS_LD];     // lagged normalisation factors of z_j, folded into y

@@ -49,9 +49,10 @@ __device__ __forceinline__ double block_sum(double v, double *lds) {
 // Entries go in chunks of U: the chunk's index and value loads are all issued, then all its gathers,
 // then the multiply-adds in entry order. A short row thus waits on two dependent memory latencies per
 // chunk rather than two per entry. Slots past the row's end reload the chunk's first entry (in bounds)
-// and are not added, so the sum is the plain in-order one.
-template <int G, class Acc, class TM, class TX>
-__device__ __forceinline__ Acc row_dot(const MatView<TM> &A, const TX *__restrict__ x, int32_t row, int sub) {
+// and are not added, so the sum is the plain in-order one. NARROW: columns are 16-bit offsets from the
+// row's scaled diagonal (the matrix-wide choice is a uniform branch in row_dot).
+template <int G, bool NARROW, class Acc, class TM, class TX>
+__device__ __forceinline__ Acc row_dot_impl(const MatView<TM> &A, const TX *__restrict__ x, int32_t row, int sub) {
   constexpr int U = 4;
   constexpr int32_t STEP = G == 1 ? SELL_C : G;
   int32_t k, end;
@@ -63,6 +64,7 @@ __device__ __forceinline__ Acc row_dot(const MatView<TM> &A, const TX *__restric
     k = A.ptr[row] + sub;
     end = A.ptr[row + 1];
   }
+  const int32_t base = NARROW ? diag_base(row, A.mul) : 0;
   Acc acc = Acc(0);
   for (; k < end; k += U * STEP) {
     int32_t c[U];
@@ -71,7 +73,10 @@ __device__ __forceinline__ Acc row_dot(const MatView<TM> &A, const TX *__restric
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int32_t kk = k + u * STEP < end ? k + u * STEP : k;
-      c[u] = A.col[kk];
+      if constexpr (NARROW)
+        c[u] = base + (int32_t)A.col16[kk];
+      else
+        c[u] = A.col[kk];
       v[u] = A.val[kk];
     }
 #pragma unroll
@@ -85,6 +90,12 @@ __device__ __forceinline__ Acc row_dot(const MatView<TM> &A, const TX *__restric
     for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
   }
   return acc;
+}
+
+template <int G, class Acc, class TM, class TX>
+__device__ __forceinline__ Acc row_dot(const MatView<TM> &A, const TX *__restrict__ x, int32_t row, int sub) {
+  if (A.col16) return row_dot_impl<G, true, Acc>(A, x, row, sub);
+  return row_dot_impl<G, false, Acc>(A, x, row, sub);
 }
 
 #define NAMG_ROWS(G, NROWS, LB)                                   \
@@ -316,78 +327,81 @@ __device__ __forceinline__ void multidot_body(uint32_t lb, const double *__restr
   }
 }
 
-// Small dense part of Arnoldi step i (0-based: columns 0..i of V are V_{i+1}), one workgroup; beta = ||b||.
-// cd holds the reduced inner products: c_j = cd[j], d_j = cd[i + 1 + j], j <= i.
-// rho = sqrt(c_i) is the lagged norm of v_{i+1}; Hessenberg column i-1 = [previous s; rho] gets the
-// Givens rotations and yields the residual estimate |g_i| / ||b||; then the new row of L (c_j / rho),
-// q (d_j / rho, the last one d_i / rho^2) and s = T q with T = I - L (Neumann) or T = (I + L)^{-1}
-// (forward substitution). Writes s, 1/rho and the stop flag to the state, and (est, flag) to host_out,
-// host-mapped memory the host reads after the stream synchronises.
-__device__ __forceinline__ void arnoldi_step_body(KState *__restrict__ st, const double *__restrict__ cd, int32_t i,
-                                                  int32_t has_w, int32_t t_direct, int32_t last, double tol,
-                                                  double beta, double *host_out) {
-  __shared__ double c[KS_LD], d[KS_LD], q[KS_LD], s[KS_LD];
-  __shared__ double rho_sh;
-  __shared__ int stop_sh;
-  for (int j = threadIdx.x; j <= i; j += BLK) {
-    c[j] = cd[j];
-    d[j] = has_w ? cd[i + 1 + j] : 0.0;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const double rho = sqrt(c[i]);
-    int flag = 0;
-    st->rho_inv = rho > 0.0 ? 1.0 / rho : 0.0;
-    st->zs[i] = st->rho_inv;
-    if (i == 0) {
-      st->g[0] = rho;
-      st->est = rho / beta;
-    } else {
-      double *h = st->H + (int64_t)(i - 1) * KS_LD;
-      for (int j = 0; j < i; ++j) h[j] = st->rprev[j];
-      h[i] = rho;
-      for (int j = 0; j < i - 1; ++j) {
-        const double a = h[j], b = h[j + 1];
-        h[j] = st->cs[j] * a + st->sn[j] * b;
-        h[j + 1] = -st->sn[j] * a + st->cs[j] * b;
-      }
-      double cj = 1.0, sj = 0.0;
-      if (h[i] != 0.0) {
-        const double den = hypot(h[i - 1], h[i]);
-        cj = h[i - 1] / den;
-        sj = h[i] / den;
-      }
-      st->cs[i - 1] = cj;
-      st->sn[i - 1] = sj;
-      h[i - 1] = cj * h[i - 1] + sj * h[i];
-      h[i] = 0.0;
-      const double gi = st->g[i - 1];
-      st->g[i] = -sj * gi;
-      st->g[i - 1] = cj * gi;
-      st->est = fabs(st->g[i]) / beta;
-      if (st->est <= tol || last || rho == 0.0) flag = 1;
+// Column completion (Algorithm 1, lagged normalisation), one workgroup. c = the sum of partial[0..nblk)
+// is ||v_{i+1}||^2, reduced in the pass that wrote v_{i+1} (the true residual for i = 0, the projection
+// otherwise), so the column is finished without waiting for the next step's fused reduction.
+// rho = sqrt(c); i == 0: g_0 = rho. i >= 1: Hessenberg column i-1 = [s of step i-1; rho] gets the
+// previous Givens rotations and a new one, giving the residual estimate |g_i| / ||b|| (beta = ||b||).
+// The stop flag is raised on estimate <= tol, on the last column of the cycle, or on breakdown (rho == 0),
+// and set to -1 on a non-finite value; (est, flag) also go to host_out, host-mapped memory the host reads
+// after the stream synchronises.
+__device__ __forceinline__ void finish_body(KState *__restrict__ st, const double *__restrict__ partial, int32_t nblk,
+                                            int32_t i, int32_t last, double tol, double beta, double *host_out) {
+  __shared__ double lds[WAVES];
+  double t = 0.0;
+  for (int32_t k = threadIdx.x; k < nblk; k += BLK) t += partial[k];
+  t = block_sum(t, lds);
+  if (threadIdx.x != 0) return;
+  const double rho = sqrt(t);
+  int flag = 0;
+  st->rho = rho;
+  st->rho_inv = rho > 0.0 ? 1.0 / rho : 0.0;
+  st->zs[i] = st->rho_inv;
+  if (i == 0) {
+    st->g[0] = rho;
+    st->est = rho / beta;
+  } else {
+    double *h = st->H + (int64_t)(i - 1) * KS_LD;
+    for (int j = 0; j < i; ++j) h[j] = st->s[j];
+    h[i] = rho;
+    for (int j = 0; j < i - 1; ++j) {
+      const double a = h[j], b = h[j + 1];
+      h[j] = st->cs[j] * a + st->sn[j] * b;
+      h[j + 1] = -st->sn[j] * a + st->cs[j] * b;
     }
-    if (!isfinite(rho) || !isfinite(st->est)) flag = -1;
-    st->flag = flag;
-    host_out[0] = st->est;
-    host_out[1] = (double)flag;
-    rho_sh = rho;
-    stop_sh = flag;
+    double cj = 1.0, sj = 0.0;
+    if (h[i] != 0.0) {
+      const double den = hypot(h[i - 1], h[i]);
+      cj = h[i - 1] / den;
+      sj = h[i] / den;
+    }
+    st->cs[i - 1] = cj;
+    st->sn[i - 1] = sj;
+    h[i - 1] = cj * h[i - 1] + sj * h[i];
+    h[i] = 0.0;
+    const double gi = st->g[i - 1];
+    st->g[i] = -sj * gi;
+    st->g[i - 1] = cj * gi;
+    st->est = fabs(st->g[i]) / beta;
+    if (st->est <= tol || last || rho == 0.0) flag = 1;
   }
-  __syncthreads();
-  if (!has_w || stop_sh != 0) return;
-  const double ri = 1.0 / rho_sh;
+  if (!isfinite(rho) || !isfinite(st->est)) flag = -1;
+  st->flag = flag;
+  host_out[0] = st->est;
+  host_out[1] = (double)flag;
+}
+
+// Small dense part of Arnoldi step i (0-based: columns 0..i of V are V_{i+1}), one workgroup, after the
+// column completion has set rho = ||v_{i+1}||. cd holds the fused reduction's inner products
+// c_j = cd[j] (j < i) and d_j = cd[i + 1 + j] (j <= i). New row of L: c_j / rho; q: d_j / rho, the last
+// one d_i / rho^2; s = T q with T = I - L (Neumann) or T = (I + L)^{-1} (forward substitution).
+__device__ __forceinline__ void step_body(KState *__restrict__ st, const double *__restrict__ cd, int32_t i,
+                                          int32_t t_direct) {
+  __shared__ double c[KS_LD], q[KS_LD], s[KS_LD];
+  const double ri = 1.0 / st->rho;
   for (int j = threadIdx.x; j <= i; j += BLK) {
+    const double dj = cd[i + 1 + j];
     if (j < i) {
+      c[j] = cd[j];
       st->L[(int64_t)i * KS_LD + j] = c[j] * ri;
-      q[j] = d[j] * ri;
+      q[j] = dj * ri;
     } else {
-      q[j] = d[j] * ri * ri;
+      q[j] = dj * ri * ri;
     }
   }
   __syncthreads();
   if (!t_direct) {
-    // s = (I - L) q: one matrix-vector product
+    // s = (I - L) q: one matrix-vector product (row i of L read from c, it is being written)
     for (int j = threadIdx.x; j <= i; j += BLK) {
       double a = q[j];
       for (int l = 0; l < j; ++l) {
@@ -410,38 +424,35 @@ __device__ __forceinline__ void arnoldi_step_body(KState *__restrict__ st, const
     }
   }
   __syncthreads();
-  for (int j = threadIdx.x; j <= i; j += BLK) {
-    st->s[j] = s[j];
-    st->rprev[j] = s[j];
-  }
+  for (int j = threadIdx.x; j <= i; j += BLK) st->s[j] = s[j];
 }
 
 // Lagged normalisation and projection (Algorithm 1): v_{i+1} <- v_{i+1} / rho and
-// v_{i+2} = w / rho - V_{i+1} s, with an optional low-precision copy of v_{i+2} for the next V-cycle.
-// Does nothing once the step kernel has raised the stop flag.
+// v_{i+2} = w / rho - V_{i+1} s, with an optional low-precision copy of v_{i+2} for the next V-cycle,
+// and the block's partial sum of |v_{i+2}|^2 for the next column completion.
 template <class TL>
 __device__ __forceinline__ void project_body(uint32_t lb, double *__restrict__ V, int64_t ldv, int32_t i,
                                              const double *__restrict__ w, const KState *__restrict__ st, int32_t n,
-                                             TL *__restrict__ vlow) {
+                                             TL *__restrict__ vlow, double *__restrict__ partial) {
   __shared__ double s[KS_LD];
   __shared__ double ri;
-  __shared__ int32_t flag;
+  __shared__ double lds[WAVES];
   for (int j = threadIdx.x; j <= i; j += BLK) s[j] = st->s[j];
-  if (threadIdx.x == 0) {
-    ri = st->rho_inv;
-    flag = st->flag;
-  }
+  if (threadIdx.x == 0) ri = st->rho_inv;
   __syncthreads();
-  if (flag != 0) return;
   const int32_t row = (int32_t)lb * BLK + threadIdx.x;
-  if (row >= n) return;
-  const double vi = V[(int64_t)i * ldv + row] * ri;
-  V[(int64_t)i * ldv + row] = vi;
-  double acc = w[row] * ri;
-  for (int j = 0; j < i; ++j) acc -= s[j] * V[(int64_t)j * ldv + row];
-  acc -= s[i] * vi;
-  V[(int64_t)(i + 1) * ldv + row] = acc;
-  if (vlow) vlow[row] = (TL)acc;
+  double acc = 0.0;
+  if (row < n) {
+    const double vi = V[(int64_t)i * ldv + row] * ri;
+    V[(int64_t)i * ldv + row] = vi;
+    acc = w[row] * ri;
+    for (int j = 0; j < i; ++j) acc -= s[j] * V[(int64_t)j * ldv + row];
+    acc -= s[i] * vi;
+    V[(int64_t)(i + 1) * ldv + row] = acc;
+    if (vlow) vlow[row] = (TL)acc;
+  }
+  const double t = block_sum(acc * acc, lds);
+  if (threadIdx.x == 0) partial[lb] = t;
 }
 
 // y from the rotated k x k triangle (Algorithm 1, least squares), then y_j *= zs_j.
@@ -499,17 +510,21 @@ __global__ __launch_bounds__(BLK) void k_multidot(const double *__restrict__ V, 
   multidot_body<CH>(blockIdx.x, V, ldv, ncols, w, n, rows_per_blk, partial, nblk);
 }
 
-__global__ __launch_bounds__(BLK) void k_arnoldi_step(KState *__restrict__ st, const double *__restrict__ cd, int32_t i,
-                                                      int32_t has_w, int32_t t_direct, int32_t last, double tol,
-                                                      double beta, double *host_out) {
-  arnoldi_step_body(st, cd, i, has_w, t_direct, last, tol, beta, host_out);
+__global__ __launch_bounds__(BLK) void k_finish(KState *__restrict__ st, const double *__restrict__ partial, int32_t nblk,
+                                                int32_t i, int32_t last, double tol, double beta, double *host_out) {
+  finish_body(st, partial, nblk, i, last, tol, beta, host_out);
+}
+
+__global__ __launch_bounds__(BLK) void k_step(KState *__restrict__ st, const double *__restrict__ cd, int32_t i,
+                                              int32_t t_direct) {
+  step_body(st, cd, i, t_direct);
 }
 
 template <class TL>
 __global__ __launch_bounds__(BLK) void k_project(double *__restrict__ V, int64_t ldv, int32_t i,
                                                  const double *__restrict__ w, const KState *__restrict__ st,
-                                                 int32_t n, TL *__restrict__ vlow) {
-  project_body(blockIdx.x, V, ldv, i, w, st, n, vlow);
+                                                 int32_t n, TL *__restrict__ vlow, double *__restrict__ partial) {
+  project_body(blockIdx.x, V, ldv, i, w, st, n, vlow, partial);
 }
 
 __global__ __launch_bounds__(BLK) void k_backsolve(KState *__restrict__ st, int32_t k) { backsolve_body(st, k); }
@@ -577,7 +592,7 @@ __global__ __launch_bounds__(BLK) void kb_rows(const RowTask<T> *__restrict__ ta
 // One Krylov operation of one solve (fields used per operation are listed at the launch site).
 enum {
   KOP_RESIDUAL64 = 0, KOP_SPMV64 = 1, KOP_MULTIDOT = 2, KOP_COLREDUCE = 3, KOP_STEP = 4, KOP_PROJECT = 5,
-  KOP_BACKSOLVE = 6, KOP_UPDATE = 7, KOP_REDUCE = 8, KOP_SUMSQ = 9
+  KOP_BACKSOLVE = 6, KOP_UPDATE = 7, KOP_REDUCE = 8, KOP_SUMSQ = 9, KOP_FINISH = 10
 };
 
 template <class T>
@@ -604,8 +619,9 @@ __global__ __launch_bounds__(BLK) void kb_krylov(const KTask<T> *__restrict__ ta
     multidot_body<8>(lb, t.V, t.ldv, t.ncols, t.has_w ? t.w : (const double *)nullptr, t.n, t.rows_per_blk, t.partial,
                      t.nblk);
   if constexpr (OP == KOP_COLREDUCE) colreduce_body(lb, t.partial, t.nblk, t.cd);
-  if constexpr (OP == KOP_STEP) arnoldi_step_body(t.ks, t.cd, t.i, t.has_w, t_direct, t.last, tol, t.beta, t.host_out);
-  if constexpr (OP == KOP_PROJECT) project_body(lb, t.V, t.ldv, t.i, t.w, t.ks, t.n, t.vlow);
+  if constexpr (OP == KOP_STEP) step_body(t.ks, t.cd, t.i, t_direct);
+  if constexpr (OP == KOP_PROJECT) project_body(lb, t.V, t.ldv, t.i, t.w, t.ks, t.n, t.vlow, t.partial);
+  if constexpr (OP == KOP_FINISH) finish_body(t.ks, t.partial, t.nblk, t.i, t.last, tol, t.beta, t.host_out);
   if constexpr (OP == KOP_BACKSOLVE) backsolve_body(t.ks, t.k);
   if constexpr (OP == KOP_UPDATE) update_x_body(lb, (const T *)t.Z, t.ldz, t.k, t.ks, t.x, t.n);
   if constexpr (OP == KOP_REDUCE) reduce_body(t.partial, t.nblk, t.host_out);

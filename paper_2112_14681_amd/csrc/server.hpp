@@ -19,13 +19,13 @@
 
 namespace namg {
 
-// Device bytes one DMat<T>::build of A allocates (mirrors its layout choice and DevBuf rounding).
+// Device bytes one DMat<T>::build of A allocates (mirrors its layout choices and DevBuf rounding).
 template <class T>
 int64_t mat_alloc_bytes(const HostCsr &A, int force_group = 0) {
   auto r1 = [](int64_t n) { return n == 0 ? (int64_t)1 : n; };
   const int group = force_group > 0 ? force_group : choose_group(A.nr, A.nnz());
-  if (group > 1)
-    return 4 * r1((int64_t)A.rp.size()) + 4 * r1(A.nnz()) + (int64_t)sizeof(T) * r1(A.nnz());
+  const int64_t ib = fits_col16(A) ? 2 : 4;
+  if (group > 1) return 4 * r1((int64_t)A.rp.size()) + (ib + (int64_t)sizeof(T)) * r1(A.nnz());
   const int64_t nslices = (A.nr + SELL_C - 1) / SELL_C;
   int64_t stored = 0;
   for (int64_t s = 0; s < nslices; ++s) {
@@ -34,7 +34,7 @@ int64_t mat_alloc_bytes(const HostCsr &A, int force_group = 0) {
       w = std::max(w, A.rp[r + 1] - A.rp[r]);
     stored += (int64_t)w * SELL_C;
   }
-  return 4 * (nslices + 1) + (4 + (int64_t)sizeof(T)) * r1(stored);
+  return 4 * (nslices + 1) + (ib + (int64_t)sizeof(T)) * r1(stored);
 }
 
 // Device bytes of Solver<T>(H) with its Krylov workspace for restart m (the direct comparators' level
@@ -54,7 +54,8 @@ int64_t solver_footprint(const HostHierarchy &H, int m) {
     if (h.has_ilu) total += mat_alloc_bytes<T>(h.ilu_lo) + mat_alloc_bytes<T>(h.ilu_up) + S * n;
   }
   const int64_t nc = H.lv.back().A.nr;
-  total += nc > 1 ? 4 * (nc + 1) + (4 + S) * nc * nc : 4 * 2 + (4 + S);
+  // dense inverse: CSR with 64 lanes per row (one SELL slice when nc == 1); columns always fit 16 bits
+  total += nc > 1 ? 4 * (nc + 1) + (2 + S) * nc * nc : 4 * 2 + (2 + S) * SELL_C;
   total += mat_alloc_bytes<double>(H.lv[0].A, 1);
   const int64_t n0 = H.lv[0].A.nr;
   const int64_t nred = blocks_for(n0);
@@ -98,11 +99,10 @@ class BatchEngine {
     DeviceGuard g(dev_);
     groups_.clear();
     stage_.clear();
-    std::vector<Slot *> step, vc, init, end, resid;
+    std::vector<Slot *> step, init, end, resid;
     for (Slot *sl : slots) {
       if (sl->phase == STEP) {
         step.push_back(sl);
-        if (sl->i < sl->me) vc.push_back(sl);
       } else if (sl->phase == INIT) {
         init.push_back(sl);
         resid.push_back(sl);
@@ -112,11 +112,11 @@ class BatchEngine {
       }
     }
     // 1. V-cycles z = M^{-1} v_{i+1} of every stepping solve, level by level, then w = A z
-    if (!vc.empty()) {
-      batch_vcycles(vc);
+    if (!step.empty()) {
+      batch_vcycles(step);
       std::vector<KTask<T>> t;
       std::vector<unsigned> nb;
-      for (Slot *sl : vc) {
+      for (Slot *sl : step) {
         KTask<T> k = base(sl);
         k.zin = sl->sv->Z_.get() + (int64_t)sl->i * sl->sv->ldz_;
         t.push_back(k);
@@ -125,30 +125,40 @@ class BatchEngine {
       }
       add_krylov(KOP_SPMV64, t, nb);
     }
-    // 2. the fused reduction, the small dense step and the projection
+    // 2. column completion of step 0 (rho_0 from the residual pass), the fused reduction, the small dense
+    //    step, the projection, and the completion of column i from the projection's partial sums
     if (!step.empty()) {
-      std::vector<KTask<T>> t;
-      std::vector<unsigned> nb, nc, ones, np;
-      std::vector<KTask<T>> tp;
+      std::vector<KTask<T>> t, t0, tp, tf;
+      std::vector<unsigned> nb, nc, ones, ones0, np;
       for (Slot *sl : step) {
         KTask<T> k = base(sl);
         k.partial = sl->sv->dot_.get();
         k.nblk = sl->sv->nblk_dot_;
-        k.host_out = sl->sv->pinned_dev_;
         t.push_back(k);
         nb.push_back((unsigned)sl->sv->nblk_dot_);
-        nc.push_back((unsigned)(k.ncols * (k.has_w ? 2 : 1)));
+        nc.push_back((unsigned)(2 * k.ncols));
         ones.push_back(1u);
-        if (k.has_w) {
-          tp.push_back(k);
-          np.push_back(blocks_for(sl->n));
+        np.push_back(blocks_for(sl->n));
+        KTask<T> f = base(sl);
+        f.partial = sl->sv->red_.get();
+        f.nblk = sl->sv->nblk_red_;
+        tp.push_back(f);
+        if (sl->i == 0) {
+          f.last = 0;
+          t0.push_back(f);
+          ones0.push_back(1u);
         }
-        sl->alg += 8.0 * sl->n * (k.ncols + (k.has_w ? 1 : 0)) + (k.has_w ? 8.0 * sl->n * (sl->i + 4) : 0.0);
+        f.i = sl->i + 1;
+        f.last = sl->i + 1 == sl->me;
+        tf.push_back(f);
+        sl->alg += 8.0 * sl->n * (k.ncols + 1) + 8.0 * sl->n * (sl->i + 4);
       }
+      if (!t0.empty()) add_krylov(KOP_FINISH, t0, ones0);
       add_krylov(KOP_MULTIDOT, t, nb);
       add_krylov(KOP_COLREDUCE, t, nc);
       add_krylov(KOP_STEP, t, ones);
-      if (!tp.empty()) add_krylov(KOP_PROJECT, tp, np);
+      add_krylov(KOP_PROJECT, tp, np);
+      add_krylov(KOP_FINISH, tf, ones);
     }
     // 3. cycle ends: y from the rotated Hessenberg, x += Z y
     if (!end.empty()) {
@@ -205,13 +215,11 @@ class BatchEngine {
         fail(sl, NAMG_E_NONFINITE, "non-finite value in the Arnoldi step");
         continue;
       }
-      if (sl->i < sl->me) sl->apps++;
-      if (sl->i >= 1) {
-        sl->iters++;
-        sl->est = pin[0];
-      }
-      if (sl->i >= 1 && flag == 1) {
-        sl->k = sl->i;
+      sl->apps++;
+      sl->iters++;
+      sl->est = pin[0];
+      if (flag == 1) {
+        sl->k = sl->i + 1;
         sl->phase = END;
       } else {
         sl->i++;
@@ -265,8 +273,8 @@ class BatchEngine {
     k.n = sl->n;
     k.i = sl->i;
     k.ncols = sl->i + 1;
-    k.has_w = sl->i < sl->me;
-    k.last = sl->i == sl->me;
+    k.has_w = 1;
+    k.last = 0;
     k.k = sl->k;
     k.nblk = v.nblk_dot_;
     k.rows_per_blk = v.rows_per_dot_;
@@ -433,6 +441,7 @@ class BatchEngine {
       case KOP_COLREDUCE: return &kb_krylov<KOP_COLREDUCE, T>;
       case KOP_STEP: return &kb_krylov<KOP_STEP, T>;
       case KOP_PROJECT: return &kb_krylov<KOP_PROJECT, T>;
+      case KOP_FINISH: return &kb_krylov<KOP_FINISH, T>;
       case KOP_BACKSOLVE: return &kb_krylov<KOP_BACKSOLVE, T>;
       case KOP_UPDATE: return &kb_krylov<KOP_UPDATE, T>;
       case KOP_REDUCE: return &kb_krylov<KOP_REDUCE, T>;

@@ -95,7 +95,7 @@ class SolverBase {
   virtual void apply(int level, int op, const namg_solve_params &p, const double *in1, const double *in2, double *out,
                      hipStream_t s) = 0;
   virtual int64_t device_bytes() const = 0;
-  virtual void profile(int family, int level) = 0;
+  virtual void profile(int family, int level, int every) = 0;
   virtual namg_kernel_profile profile_read() = 0;
 };
 
@@ -183,11 +183,13 @@ class Solver final : public SolverBase {
     ensure_workspace(m);
   }
 
-  void profile(int family, int level) override {
+  void profile(int family, int level, int every) override {
     DeviceGuard g(dev_);
     flush_profile();
     prof_family_ = family;
     prof_level_ = level;
+    prof_every_ = every;
+    prof_seen_ = 0;
     prof_ = namg_kernel_profile{0, 0.0, 0.0};
   }
 
@@ -327,45 +329,42 @@ class Solver final : public SolverBase {
         }
         st.cycles++;
         const int me = std::min(m, p.max_iters - st.iters);
+        // column completion of step 0: rho_0 = ||r|| from the residual pass's partial sums
+        launch_small(&k_finish, s, ks, (const double *)red_.get(), nblk_red_, 0, 0, p.tol, beta, pinned_dev_);
         int k = 0;
-        for (int i = 0; i <= me; ++i) {
-          const bool has_w = i < me;
+        for (int i = 0; i < me; ++i) {
           double *vi = V + (int64_t)i * ldv_;
-          if (has_w) {
-            T *zi = Z + (int64_t)i * ldz_;
-            const T *b0;
-            if constexpr (std::is_same<T, double>::value)
-              b0 = vi;
-            else
-              b0 = vin;
-            vcycle(0, b0, zi, o, s);
-            st.precond_apps++;
-            launch(NAMG_KF_GMRES_SPMV, 0, A64_.bytes() + (S + 8.0) * n, sel_spmv<double, double, T, double>(1),
-                   rows_grid(A64_), s, A64_.view(), (const T *)zi, w);
-          }
+          T *zi = Z + (int64_t)i * ldz_;
+          const T *b0;
+          if constexpr (std::is_same<T, double>::value)
+            b0 = vi;
+          else
+            b0 = vin;
+          vcycle(0, b0, zi, o, s);
+          st.precond_apps++;
+          launch(NAMG_KF_GMRES_SPMV, 0, A64_.bytes() + (S + 8.0) * n, sel_spmv<double, double, T, double>(1),
+                 rows_grid(A64_), s, A64_.view(), (const T *)zi, w);
           const int32_t ncols = i + 1;
-          launch(NAMG_KF_MULTIDOT, 0, 8.0 * n * (ncols + (has_w ? 1 : 0)), &k_multidot<8>, nblk_dot_, s,
-                 (const double *)V, ldv_, ncols, has_w ? (const double *)w : (const double *)nullptr, n,
-                 rows_per_dot_, dot_.get(), nblk_dot_);
-          launch(-1, 0, 0.0, &k_colreduce, (unsigned)(ncols * (has_w ? 2 : 1)), s, (const double *)dot_.get(),
-                 nblk_dot_, cd);
-          launch_small(&k_arnoldi_step, s, ks, (const double *)cd, i, (int)has_w, (int)(p.gmres_T == NAMG_T_DIRECT),
-                       (int)(i == me), p.tol, beta, pinned_dev_);
+          launch(NAMG_KF_MULTIDOT, 0, 8.0 * n * (ncols + 1), &k_multidot<8>, nblk_dot_, s, (const double *)V, ldv_,
+                 ncols, (const double *)w, n, rows_per_dot_, dot_.get(), nblk_dot_);
+          launch(-1, 0, 0.0, &k_colreduce, (unsigned)(2 * ncols), s, (const double *)dot_.get(), nblk_dot_, cd);
+          launch_small(&k_step, s, ks, (const double *)cd, i, (int)(p.gmres_T == NAMG_T_DIRECT));
+          launch(NAMG_KF_PROJECT, 0, 8.0 * n * (i + 4) + (vin ? S * n : 0.0), &k_project<T>, blocks_for(n), s, V,
+                 ldv_, i, (const double *)w, (const KState *)ks, n, vin, red_.get());
+          // column i is complete once ||v_{i+2}|| is known: estimate and stop test before the next V-cycle
+          launch_small(&k_finish, s, ks, (const double *)red_.get(), nblk_red_, i + 1, (int)(i + 1 == me), p.tol, beta,
+                       pinned_dev_);
           hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
           const double est = pinned_[0];
           const int flag = (int)pinned_[1];
           if (flag < 0) throw SetupError{NAMG_E_NONFINITE, "non-finite value in the Arnoldi step"};
-          if (i >= 1) {
-            st.iters++;
-            st.relres_est = est;
-            if (trace) std::fprintf(stderr, "[namg]   iter %d est %.3e\n", st.iters, est);
-          }
-          if (i >= 1 && flag == 1) {
-            k = i;
+          st.iters++;
+          st.relres_est = est;
+          if (trace) std::fprintf(stderr, "[namg]   iter %d est %.3e\n", st.iters, est);
+          if (flag == 1) {
+            k = i + 1;
             break;
           }
-          launch(NAMG_KF_PROJECT, 0, 8.0 * n * (i + 4) + (vin ? S * n : 0.0), &k_project<T>, blocks_for(n), s, V,
-                 ldv_, i, (const double *)w, (const KState *)ks, n, vin);
         }
         launch_small(&k_backsolve, s, ks, k);
         launch(-1, 0, (double)n * (S * k + 16.0), &k_update_x<T>, blocks_for(n), s, (const T *)Z, ldz_, k,
@@ -395,7 +394,8 @@ class Solver final : public SolverBase {
   void launch(int family, int level, double bytes, Kernel kernel, unsigned grid, hipStream_t s, Args... args) {
     if (grid == 0) return;
     alg_ += bytes;
-    if (family >= 0 && family == prof_family_ && (prof_level_ < 0 || prof_level_ == level)) {
+    if (family >= 0 && family == prof_family_ && (prof_level_ < 0 || prof_level_ == level) &&
+        prof_seen_++ % prof_every_ == 0) {
       if (ev_used_ == events_.size()) {
         hipEvent_t a, b;
         hip_check(hipEventCreate(&a), "hipEventCreate");
@@ -484,6 +484,13 @@ class Solver final : public SolverBase {
  private:
   std::vector<RowOp> *record_ = nullptr;
 
+  // A matrix-free view that only carries the row count (vector operations).
+  static MatView<T> axpy_view(int32_t n) {
+    MatView<T> v;
+    v.nrows = n;
+    return v;
+  }
+
   static RowOp row_op(int kind, int family, int level, const MatView<T> &M, int group, unsigned grid, double bytes,
                       const T *a, const T *b, const T *c, const T *d, T *o0, T *o1, int32_t n) {
     RowOp op;
@@ -555,13 +562,13 @@ class Solver final : public SolverBase {
 
   void axpy(int l, const T *f, const T *scale, const T *acc, T *out, int32_t n, hipStream_t s) {
     const double vecs = 2 + (scale ? 1 : 0) + (acc ? 1 : 0);
-    emit(row_op(ROP_AXPY, -1, l, MatView<T>{nullptr, nullptr, nullptr, n}, 1, blocks_for(n), S * n * vecs, f, nullptr,
+    emit(row_op(ROP_AXPY, -1, l, axpy_view(n), 1, blocks_for(n), S * n * vecs, f, nullptr,
                 scale, acc, out, nullptr, n),
          s);
   }
 
   void fill_zero(int l, T *out, int32_t n, hipStream_t s) {
-    emit(row_op(ROP_FILL, -1, l, MatView<T>{nullptr, nullptr, nullptr, n}, 1, blocks_for(n), S * n, nullptr, nullptr,
+    emit(row_op(ROP_FILL, -1, l, axpy_view(n), 1, blocks_for(n), S * n, nullptr, nullptr,
                 nullptr, nullptr, out, nullptr, n),
          s);
   }
@@ -727,7 +734,8 @@ class Solver final : public SolverBase {
   double *pinned_ = nullptr;      // host-mapped scalars: [0] estimate, [1] flag, [2] reductions
   double *pinned_dev_ = nullptr;  // the same memory as seen from the device
   double alg_ = 0.0;
-  int prof_family_ = NAMG_KF_NONE, prof_level_ = -1;
+  int prof_family_ = NAMG_KF_NONE, prof_level_ = -1, prof_every_ = 1;
+  int64_t prof_seen_ = 0;
   namg_kernel_profile prof_{0, 0.0, 0.0};
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events_;
   size_t ev_used_ = 0;
@@ -853,10 +861,11 @@ int namg_apply(namg_hier *h, int level, int op, const namg_solve_params *p, cons
   });
 }
 
-int namg_profile_kernel(namg_hier *h, int family, int level) {
+int namg_profile_kernel(namg_hier *h, int family, int level, int every) {
   return guarded([&]() -> int {
     if (family < NAMG_KF_NONE || family > NAMG_KF_TRI) throw namg::SetupError{NAMG_E_INVALID, "unknown kernel family"};
-    device_of(h)->profile(family, level);
+    if (every < 1) throw namg::SetupError{NAMG_E_INVALID, "every must be >= 1"};
+    device_of(h)->profile(family, level, every);
     return NAMG_OK;
   });
 }

@@ -169,6 +169,20 @@ def test_solve_c3_and_c4_parity(namg):
         _check_solve(namg, A, b, namg.Hierarchy(A, device=0), O.Hierarchy(A), **kw)
 
 
+def test_wide_column_indices(namg):
+    """A randomly permuted 34^3 system: level 0 has columns more than 2^15 from the diagonal, so it is
+    stored with 32-bit columns while the coarse levels use 16-bit offsets; both forms in one solve."""
+    A, b, _ = config_system("c4r", 34)
+    assert np.abs(np.repeat(np.arange(A.n), np.diff(A.rowptr)) - A.colind).max() > 32767
+    H = namg.Hierarchy(A, device=0)
+    Al, e = level_csr(H, 0)
+    x = np.random.default_rng(5).standard_normal(A.n)
+    out = torch.empty(A.n, dtype=torch.float64, device="cuda:0")
+    H.apply(0, namg.OP_SPMV, dev(x), None, out)
+    assert relerr(host(out), O.spmv(Al, x)) <= TOL64
+    _check_solve(namg, A, b, H, O.Hierarchy(A), smoother=1, inner_terms=3)
+
+
 def test_solve_fp32_preconditioner(namg):
     """FP32 hierarchy and V-cycle under FP64 Arnoldi: same 1e-8 true residual."""
     for name, N, kw in (("c3", 24, dict(smoother=0, inner_terms=2)), ("c2", 32, dict(smoother=1, inner_terms=3))):
