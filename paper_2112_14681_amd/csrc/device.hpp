@@ -4,7 +4,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
+#include <cstdlib>
 #include <string>
 #include <utility>
 #include <vector>
@@ -128,13 +130,34 @@ struct MatView {
   int32_t nrows = 0;
 };
 
+// Layout tuning, read once from the environment (defaults in parentheses):
+//   NAMG_LANE_ENTRIES (8): CSR lane groups are sized so that a lane takes about this many entries;
+//   NAMG_SELL_MIN_ROWS (524288): a matrix with at least this many rows uses SELL-64 whatever its row
+//   length (one lane per row already fills the device).
+struct LayoutTuning {
+  int lane_entries = 8;
+  int64_t sell_min_rows = int64_t(1) << 19;
+};
+
+inline const LayoutTuning &layout_tuning() {
+  static const LayoutTuning t = [] {
+    LayoutTuning v;
+    if (const char *e = std::getenv("NAMG_LANE_ENTRIES")) v.lane_entries = std::max(1, std::atoi(e));
+    if (const char *e = std::getenv("NAMG_SELL_MIN_ROWS")) v.sell_min_rows = std::max<int64_t>(1, std::atoll(e));
+    return v;
+  }();
+  return t;
+}
+
 // Lanes per row for a matrix with the given shape: one lane when rows are short or the matrix is large
-// enough to fill the device with one lane per row; otherwise about four entries per lane.
+// enough to fill the device with one lane per row; otherwise a power of two up to 64 that gives each
+// lane about NAMG_LANE_ENTRIES entries.
 inline int choose_group(int64_t nrows, int64_t nnz) {
+  const LayoutTuning &t = layout_tuning();
   const double avg = nrows > 0 ? (double)nnz / (double)nrows : 0.0;
-  if (avg <= 10.0 || nrows >= (1 << 19)) return 1;
+  if (avg <= 10.0 || nrows >= t.sell_min_rows) return 1;
   int g = 2;
-  while (g < 64 && g * 4 < avg) g <<= 1;
+  while (g < 64 && g * t.lane_entries < avg) g <<= 1;
   return g;
 }
 

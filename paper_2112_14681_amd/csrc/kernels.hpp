@@ -43,6 +43,22 @@ __device__ __forceinline__ double block_sum(double v, double *lds) {
   return t;
 }
 
+// This thread's share of sum(p[0..n)): p[tid] + p[tid + BLK] + ..., added in that order. Loads go in
+// groups of eight so that a long sum waits on one memory latency per group, not per element.
+__device__ __forceinline__ double strided_sum(const double *__restrict__ p, int32_t n) {
+  double t = 0.0;
+  int32_t k = threadIdx.x;
+  for (; k + 7 * BLK < n; k += 8 * BLK) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = p[k + u * BLK];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t += v[u];
+  }
+  for (; k < n; k += BLK) t += p[k];
+  return t;
+}
+
 // Row `row` of a sparse matrix times x, reduced over the G lanes of the row's group (every lane of the
 // group returns the full sum). G == 1: SELL-64, one lane per row. G > 1: CSR, lane `sub` takes entries
 // sub, sub + G, ...; groups are aligned inside the wavefront, so the butterfly never leaves the group.
@@ -98,21 +114,141 @@ __device__ __forceinline__ Acc row_dot(const MatView<TM> &A, const TX *__restric
   return row_dot_impl<G, false, Acc>(A, x, row, sub);
 }
 
-#define NAMG_ROWS(G, NROWS, LB)                                   \
-  const int64_t gtid_ = (int64_t)(LB) * BLK + threadIdx.x;        \
-  const int32_t row = (int32_t)(gtid_ / (G));                      \
-  const int sub = (int)(gtid_ % (G));                              \
-  if (row >= (NROWS)) return;
+// SELL-64 rows r0 and r0 + 64 (the same lane of two adjacent slices) of one thread, interleaved so that
+// both rows' loads are in flight together. Each row's sum is row_dot's in-order sum. has1: row r0 + 64
+// exists. There is no branch between the loads (a branch would make the compiler wait for every load
+// issued before it): a slot past its row's end loads an in-bounds entry of the chunk, gathers from a
+// valid column (an existing row's base, or column 0) and is not added.
+template <bool NARROW, class Acc, class TM, class TX>
+__device__ __forceinline__ void sell_dot2_impl(const MatView<TM> &A, const TX *__restrict__ x, int32_t r0, bool has1,
+                                               Acc &a0, Acc &a1) {
+  constexpr int U = 4;
+  const int32_t s0 = r0 >> 6, lane = r0 & 63;
+  int32_t k0 = A.ptr[s0] + lane;
+  const int32_t e0 = A.ptr[s0 + 1];
+  int32_t k1 = 0, e1 = 0;
+  if (has1) {
+    k1 = e0 + lane;
+    e1 = A.ptr[s0 + 2];
+  }
+  // the column an inactive slot gathers from: its row's base, which is < ncols for an existing row; a lane
+  // without a second row uses the first row's base (the second row's would lie past the end of x)
+  const int32_t b0 = NARROW ? diag_base(r0, A.mul) : 0;
+  const int32_t b1 = NARROW ? diag_base(has1 ? r0 + SELL_C : r0, A.mul) : 0;
+  a0 = Acc(0);
+  a1 = Acc(0);
+  while (k0 < e0 || k1 < e1) {
+    const int32_t kb0 = k0 < e0 ? k0 : k1;  // an entry of this chunk that exists
+    const int32_t kb1 = k1 < e1 ? k1 : k0;
+    bool ok0[U], ok1[U];
+    int32_t c0[U], c1[U];
+    TM v0[U], v1[U];
+    TX x0[U], x1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ok0[u] = k0 + u * SELL_C < e0;
+      ok1[u] = k1 + u * SELL_C < e1;
+      const int32_t kk0 = ok0[u] ? k0 + u * SELL_C : kb0;
+      const int32_t kk1 = ok1[u] ? k1 + u * SELL_C : kb1;
+      int32_t q0, q1;
+      if constexpr (NARROW) {
+        q0 = b0 + (int32_t)A.col16[kk0];
+        q1 = b1 + (int32_t)A.col16[kk1];
+      } else {
+        q0 = A.col[kk0];
+        q1 = A.col[kk1];
+      }
+      c0[u] = ok0[u] ? q0 : b0;
+      c1[u] = ok1[u] ? q1 : b1;
+      v0[u] = A.val[kk0];
+      v1[u] = A.val[kk1];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      x0[u] = x[c0[u]];
+      x1[u] = x[c1[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (ok0[u]) a0 += (Acc)v0[u] * (Acc)x0[u];
+      if (ok1[u]) a1 += (Acc)v1[u] * (Acc)x1[u];
+    }
+    k0 += U * SELL_C;
+    k1 += U * SELL_C;
+  }
+}
+
+// The rows one thread of a row kernel computes. SELL-64 (G == 1) with 4-byte values: two rows, r and
+// r + 64, the same lane of a pair of adjacent slices (block lb covers rows [512 lb, 512 lb + 512);
+// wavefront w takes slices 2w and 2w + 1 of the block), so that each lane keeps two independent load
+// chains in flight. SELL-64 with 8-byte values: one row per lane (its loads are wide enough; measured
+// faster). CSR lane groups (G > 1): lane `sub` of the group of one row.
+template <int G, class TM>
+struct ThreadRows {
+  static constexpr int R = (G == 1 && sizeof(TM) == 4) ? 2 : 1;
+  int32_t row[R];
+  bool ok[R];
+  int sub;
+  __device__ __forceinline__ ThreadRows(uint32_t lb, int32_t nrows) {
+    if constexpr (R == 2) {
+      row[0] = (int32_t)lb * (2 * BLK) + (int32_t)(threadIdx.x >> 6) * (2 * SELL_C) + (int32_t)(threadIdx.x & 63);
+      row[1] = row[0] + SELL_C;
+      ok[0] = row[0] < nrows;
+      ok[1] = row[1] < nrows;
+      sub = 0;
+    } else {
+      const int64_t g = (int64_t)lb * BLK + threadIdx.x;
+      row[0] = (int32_t)(g / G);
+      sub = (int)(g % G);
+      ok[0] = row[0] < nrows;
+    }
+  }
+};
+
+// Blocks of a row kernel over nrows rows with `group` lanes per row and val_bytes-byte matrix values.
+inline unsigned row_blocks(int64_t nrows, int group, int val_bytes) {
+  if (group == 1 && val_bytes == 4) return (unsigned)((nrows + 2 * BLK - 1) / (2 * BLK));
+  return blocks_for(nrows * group);
+}
+
+// The row sums of this thread's rows (every lane of a CSR group gets its row's full sum).
+template <int G, class Acc, class TM, class TX>
+__device__ __forceinline__ void row_dots(const MatView<TM> &A, const TX *__restrict__ x, const ThreadRows<G, TM> &t,
+                                         Acc (&out)[ThreadRows<G, TM>::R]) {
+  if constexpr (ThreadRows<G, TM>::R == 2) {
+    if (A.col16)
+      sell_dot2_impl<true, Acc>(A, x, t.row[0], t.ok[1], out[0], out[1]);
+    else
+      sell_dot2_impl<false, Acc>(A, x, t.row[0], t.ok[1], out[0], out[1]);
+  } else {
+    out[0] = row_dot<G, Acc>(A, x, t.row[0], t.sub);
+  }
+}
 
 // ---------------------------------------------------------------------------------------- row bodies
 
-// y = A x  (restriction R r, the GMRES product w = A z with z promoted on load, the coarse inverse)
+// y = A x  (restriction R r, the GMRES product w = A z with z promoted on load, the coarse inverse),
+// optionally f = d .* y as well: the restriction also produces the first term f = D^{-1} b of the
+// coarse level's polynomial Gauss-Seidel sweep (same product as the residual pass with x = 0).
 template <int G, class Acc, class TM, class TX, class TY>
 __device__ __forceinline__ void spmv_body(uint32_t lb, const MatView<TM> &A, const TX *__restrict__ x,
-                                          TY *__restrict__ y) {
-  NAMG_ROWS(G, A.nrows, lb)
-  const Acc v = row_dot<G, Acc>(A, x, row, sub);
-  if (sub == 0) y[row] = (TY)v;
+                                          TY *__restrict__ y, const TY *__restrict__ d, TY *__restrict__ f) {
+  constexpr int R = ThreadRows<G, TM>::R;
+  const ThreadRows<G, TM> t(lb, A.nrows);
+  if (!t.ok[0]) return;
+  TY dv[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) dv[q] = (f && t.ok[q]) ? d[t.row[q]] : TY(0);
+  Acc v[R];
+  row_dots<G, Acc>(A, x, t, v);
+  if (t.sub != 0) return;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    if (!t.ok[q]) continue;
+    const TY yv = (TY)v[q];
+    y[t.row[q]] = yv;
+    if (f) f[t.row[q]] = dv[q] * yv;
+  }
 }
 
 // r = b - A x (x == nullptr means x = 0), optionally f = d .* r. One pass: SpMV, subtract, scale.
@@ -120,14 +256,25 @@ template <int G, class T>
 __device__ __forceinline__ void residual_body(uint32_t lb, const MatView<T> &A, const T *__restrict__ b,
                                               const T *__restrict__ x, const T *__restrict__ d, T *__restrict__ r,
                                               T *__restrict__ f) {
-  NAMG_ROWS(G, A.nrows, lb)
-  const T bv = b[row];
-  const T dv = f ? d[row] : T(0);
-  const T acc = x ? row_dot<G, T>(A, x, row, sub) : T(0);
-  if (sub != 0) return;
-  const T rr = bv - acc;
-  if (r) r[row] = rr;
-  if (f) f[row] = dv * rr;
+  constexpr int R = ThreadRows<G, T>::R;
+  const ThreadRows<G, T> t(lb, A.nrows);
+  if (!t.ok[0]) return;
+  T bv[R], dv[R], acc[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    bv[q] = t.ok[q] ? b[t.row[q]] : T(0);
+    dv[q] = (f && t.ok[q]) ? d[t.row[q]] : T(0);
+    acc[q] = T(0);
+  }
+  if (x) row_dots<G, T>(A, x, t, acc);
+  if (t.sub != 0) return;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    if (!t.ok[q]) continue;
+    const T rr = bv[q] - acc[q];
+    if (r) r[t.row[q]] = rr;
+    if (f) f[t.row[q]] = dv[q] * rr;
+  }
 }
 
 // One Neumann / Jacobi inner term on a pre-scaled strict triangle S:
@@ -138,25 +285,43 @@ template <int G, class T>
 __device__ __forceinline__ void neumann_body(uint32_t lb, const MatView<T> &S, const T *__restrict__ f,
                                              const T *__restrict__ in, const T *__restrict__ scale, const T *acc,
                                              T *out) {
-  NAMG_ROWS(G, S.nrows, lb)
-  const T fv = f[row];
-  const T sc = scale ? scale[row] : T(1);
-  const T av = acc ? acc[row] : T(0);
-  const T sv = row_dot<G, T>(S, in, row, sub);
-  if (sub != 0) return;
-  T v = fv - sv;
-  if (scale) v *= sc;
-  if (acc) v += av;
-  out[row] = v;
+  constexpr int R = ThreadRows<G, T>::R;
+  const ThreadRows<G, T> t(lb, S.nrows);
+  if (!t.ok[0]) return;
+  T fv[R], sc[R], av[R], sv[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int32_t row = t.ok[q] ? t.row[q] : t.row[0];
+    fv[q] = f[row];
+    sc[q] = scale ? scale[row] : T(1);
+    av[q] = acc ? acc[row] : T(0);
+  }
+  row_dots<G, T>(S, in, t, sv);
+  if (t.sub != 0) return;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    if (!t.ok[q]) continue;
+    T v = fv[q] - sv[q];
+    if (scale) v *= sc[q];
+    if (acc) v += av[q];
+    out[t.row[q]] = v;
+  }
 }
 
 // x += P e  (prolongation and correction in one pass)
 template <int G, class T>
 __device__ __forceinline__ void prolong_body(uint32_t lb, const MatView<T> &P, const T *__restrict__ e, T *x) {
-  NAMG_ROWS(G, P.nrows, lb)
-  const T xv = x[row];
-  const T v = row_dot<G, T>(P, e, row, sub);
-  if (sub == 0) x[row] = xv + v;
+  constexpr int R = ThreadRows<G, T>::R;
+  const ThreadRows<G, T> t(lb, P.nrows);
+  if (!t.ok[0]) return;
+  T xv[R], v[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) xv[q] = x[t.ok[q] ? t.row[q] : t.row[0]];
+  row_dots<G, T>(P, e, t, v);
+  if (t.sub != 0) return;
+#pragma unroll
+  for (int q = 0; q < R; ++q)
+    if (t.ok[q]) x[t.row[q]] = xv[q] + v[q];
 }
 
 // out = [acc +] [scale .*] f
@@ -174,8 +339,9 @@ __device__ __forceinline__ void axpy_body(uint32_t lb, const T *__restrict__ f, 
 // --------------------------------------------------------------------------- single-problem kernels
 
 template <int G, class Acc, class TM, class TX, class TY>
-__global__ __launch_bounds__(BLK) void k_spmv(MatView<TM> A, const TX *__restrict__ x, TY *__restrict__ y) {
-  spmv_body<G, Acc>(blockIdx.x, A, x, y);
+__global__ __launch_bounds__(BLK) void k_spmv(MatView<TM> A, const TX *__restrict__ x, TY *__restrict__ y,
+                                              const TY *__restrict__ d, TY *__restrict__ f) {
+  spmv_body<G, Acc>(blockIdx.x, A, x, y, d, f);
 }
 
 template <int G, class T>
@@ -259,9 +425,7 @@ __device__ __forceinline__ void sumsq_body(uint32_t lb, const double *__restrict
 // out[0] = sum of partial[0..n) in a fixed order (one block); out may be host-mapped memory.
 __device__ __forceinline__ void reduce_body(const double *__restrict__ partial, int32_t n, double *out) {
   __shared__ double lds[WAVES];
-  double t = 0.0;
-  for (int32_t k = threadIdx.x; k < n; k += BLK) t += partial[k];
-  t = block_sum(t, lds);
+  const double t = block_sum(strided_sum(partial, n), lds);
   if (threadIdx.x == 0) out[0] = t;
 }
 
@@ -269,16 +433,15 @@ __device__ __forceinline__ void reduce_body(const double *__restrict__ partial, 
 __device__ __forceinline__ void colreduce_body(uint32_t lb, const double *__restrict__ partial, int32_t nblk,
                                                double *__restrict__ out) {
   __shared__ double lds[WAVES];
-  const double *p = partial + (int64_t)lb * nblk;
-  double t = 0.0;
-  for (int32_t k = threadIdx.x; k < nblk; k += BLK) t += p[k];
-  t = block_sum(t, lds);
+  const double t = block_sum(strided_sum(partial + (int64_t)lb * nblk, nblk), lds);
   if (threadIdx.x == 0) out[lb] = t;
 }
 
 // The single fused reduction of an Arnoldi step (Algorithm 1, the global synchronisation):
-// c = V_{i+1}^T v_{i+1} and d = V_{i+1}^T w in one pass over V. Block lb owns a contiguous row range and
-// writes its partial sums value-major: partial[v * nblk + lb], v < ncols for c, ncols + v for d.
+// c = V_{i+1}^T v_{i+1} and d = V_{i+1}^T w in one pass over V. Block lb owns the contiguous row range
+// [lb * rows_per_blk, (lb + 1) * rows_per_blk) (rows_per_blk even); each thread takes row pairs with
+// 16-byte loads, so every wavefront load moves 1 KiB. Partial sums are written value-major:
+// partial[v * nblk + lb], v < ncols for c, ncols + v for d.
 template <int CH>
 __device__ __forceinline__ void multidot_body(uint32_t lb, const double *__restrict__ V, int64_t ldv, int32_t ncols,
                                               const double *__restrict__ w, int32_t n, int32_t rows_per_blk,
@@ -292,16 +455,31 @@ __device__ __forceinline__ void multidot_body(uint32_t lb, const double *__restr
     double ac[CH], ad[CH];
 #pragma unroll
     for (int c = 0; c < CH; ++c) ac[c] = ad[c] = 0.0;
-    for (int32_t r = r0 + threadIdx.x; r < r1; r += BLK) {
-      const double vr = v[r];
-      const double wr = w ? w[r] : 0.0;
+#pragma unroll 2
+    for (int32_t r = r0 + 2 * (int32_t)threadIdx.x; r < r1; r += 2 * BLK) {
+      if (r + 1 < r1) {
+        const double2 vr = *reinterpret_cast<const double2 *>(v + r);
+        const double2 wr = w ? *reinterpret_cast<const double2 *>(w + r) : make_double2(0.0, 0.0);
 #pragma unroll
-      for (int c = 0; c < CH; ++c)
-        if (j0 + c < ncols) {
-          const double vj = V[(int64_t)(j0 + c) * ldv + r];
-          ac[c] += vj * vr;
-          ad[c] += vj * wr;
-        }
+        for (int c = 0; c < CH; ++c)
+          if (j0 + c < ncols) {
+            const double2 vj = *reinterpret_cast<const double2 *>(V + (int64_t)(j0 + c) * ldv + r);
+            ac[c] += vj.x * vr.x;
+            ac[c] += vj.y * vr.y;
+            ad[c] += vj.x * wr.x;
+            ad[c] += vj.y * wr.y;
+          }
+      } else {
+        const double vr = v[r];
+        const double wr = w ? w[r] : 0.0;
+#pragma unroll
+        for (int c = 0; c < CH; ++c)
+          if (j0 + c < ncols) {
+            const double vj = V[(int64_t)(j0 + c) * ldv + r];
+            ac[c] += vj * vr;
+            ad[c] += vj * wr;
+          }
+      }
     }
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
@@ -327,6 +505,17 @@ __device__ __forceinline__ void multidot_body(uint32_t lb, const double *__restr
   }
 }
 
+// Partition of the fused reduction over n rows: at most 2048 blocks of an even number of rows (at least
+// 512), so that a thread takes one or a few row pairs.
+inline int32_t dot_rows_per_block(int64_t n) {
+  const int64_t nb = std::min<int64_t>(2048, std::max<int64_t>(1, (n + 511) / 512));
+  const int64_t rows = (n + nb - 1) / nb;
+  return (int32_t)std::max<int64_t>(2, (rows + 1) / 2 * 2);
+}
+inline int32_t dot_blocks(int64_t n) {
+  return (int32_t)std::max<int64_t>(1, (n + dot_rows_per_block(n) - 1) / dot_rows_per_block(n));
+}
+
 // Column completion (Algorithm 1, lagged normalisation), one workgroup. c = the sum of partial[0..nblk)
 // is ||v_{i+1}||^2, reduced in the pass that wrote v_{i+1} (the true residual for i = 0, the projection
 // otherwise), so the column is finished without waiting for the next step's fused reduction.
@@ -338,9 +527,7 @@ __device__ __forceinline__ void multidot_body(uint32_t lb, const double *__restr
 __device__ __forceinline__ void finish_body(KState *__restrict__ st, const double *__restrict__ partial, int32_t nblk,
                                             int32_t i, int32_t last, double tol, double beta, double *host_out) {
   __shared__ double lds[WAVES];
-  double t = 0.0;
-  for (int32_t k = threadIdx.x; k < nblk; k += BLK) t += partial[k];
-  t = block_sum(t, lds);
+  const double t = block_sum(strided_sum(partial, nblk), lds);
   if (threadIdx.x != 0) return;
   const double rho = sqrt(t);
   int flag = 0;
@@ -559,7 +746,7 @@ __device__ __forceinline__ int find_task(const uint32_t *__restrict__ off, int n
 // One row operation on one level of one solve. Operand meaning per operation:
 //   ROP_RESIDUAL: a = b, b = x (may be null), c = D^{-1} (null unless o1 is set), o0 = r, o1 = f
 //   ROP_NEUMANN:  a = f, b = in, c = scale, d = acc, o0 = out
-//   ROP_SPMV:     b = x, o0 = y
+//   ROP_SPMV:     b = x, o0 = y, optionally c = d and o1 = f = d .* y
 //   ROP_PROLONG:  b = e, o0 = x
 //   ROP_AXPY:     a = f, c = scale, d = acc, o0 = out, n rows
 //   ROP_FILL:     o0 = 0, n rows
@@ -580,7 +767,7 @@ __global__ __launch_bounds__(BLK) void kb_rows(const RowTask<T> *__restrict__ ta
   const RowTask<T> &t = tasks[find_task(off, ntasks, lb)];
   if constexpr (OP == ROP_RESIDUAL) residual_body<G>(lb, t.M, t.a, t.b, t.c, t.o0, t.o1);
   if constexpr (OP == ROP_NEUMANN) neumann_body<G>(lb, t.M, t.a, t.b, t.c, t.d, t.o0);
-  if constexpr (OP == ROP_SPMV) spmv_body<G, T>(lb, t.M, t.b, t.o0);
+  if constexpr (OP == ROP_SPMV) spmv_body<G, T>(lb, t.M, t.b, t.o0, t.c, t.o1);
   if constexpr (OP == ROP_PROLONG) prolong_body<G>(lb, t.M, t.b, t.o0);
   if constexpr (OP == ROP_AXPY) axpy_body(lb, t.a, t.c, t.d, t.o0, t.n);
   if constexpr (OP == ROP_FILL) {
@@ -614,7 +801,8 @@ __global__ __launch_bounds__(BLK) void kb_krylov(const KTask<T> *__restrict__ ta
   uint32_t lb;
   const KTask<T> &t = tasks[find_task(off, ntasks, lb)];
   if constexpr (OP == KOP_RESIDUAL64) residual64_body(lb, t.A, t.b, t.x, t.V, t.vlow, t.partial);
-  if constexpr (OP == KOP_SPMV64) spmv_body<1, double>(lb, t.A, t.zin, t.w);
+  if constexpr (OP == KOP_SPMV64)
+    spmv_body<1, double>(lb, t.A, t.zin, t.w, (const double *)nullptr, (double *)nullptr);
   if constexpr (OP == KOP_MULTIDOT)
     multidot_body<8>(lb, t.V, t.ldv, t.ncols, t.has_w ? t.w : (const double *)nullptr, t.n, t.rows_per_blk, t.partial,
                      t.nblk);

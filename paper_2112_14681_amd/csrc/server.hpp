@@ -61,7 +61,7 @@ int64_t solver_footprint(const HostHierarchy &H, int m) {
   const int64_t nred = blocks_for(n0);
   total += 8 * (std::max<int64_t>(nred, 1) + 8) + (int64_t)sizeof(KState);
   const int64_t ld = (n0 + 63) / 64 * 64;
-  const int64_t nblk = std::min<int64_t>(1024, std::max<int64_t>(1, nred));
+  const int64_t nblk = dot_blocks(n0);
   total += 8 * ld * (m + 2) + S * ld * m + 8 * n0 + (S == 4 ? 4 * n0 : 0) + 8 * nblk * 2 * (m + 2) + 16 * (m + 2);
   return total;
 }
@@ -120,7 +120,7 @@ class BatchEngine {
         KTask<T> k = base(sl);
         k.zin = sl->sv->Z_.get() + (int64_t)sl->i * sl->sv->ldz_;
         t.push_back(k);
-        nb.push_back(blocks_for(sl->n));
+        nb.push_back(row_blocks(sl->n, 1, 8));
         sl->alg += sl->sv->A64_.bytes() + (sizeof(T) + 8.0) * sl->n;
       }
       add_krylov(KOP_SPMV64, t, nb);

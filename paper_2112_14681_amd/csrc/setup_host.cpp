@@ -292,16 +292,31 @@ HostCsr transpose_csr(const HostCsr &P) {
   return R;
 }
 
-// C = X * Y with a dense sparse accumulator; row i of C accumulates x_ij * y_jJ over the entries of row
-// i of X in stored order and, inside, over row j of Y in stored order. Columns of each row sorted.
+// C = X * Y, row by row (Gustavson). Row i of C accumulates x_ij * y_jJ over the entries of row i of X in
+// stored order and, inside, over row j of Y in stored order; every c_iJ is that running sum, so the
+// result does not depend on how the accumulator is stored. The accumulator is a small open-addressing
+// table sized for the row (it stays in the L1 cache), not an array over all columns. Columns of each row
+// come out sorted.
 HostCsr spgemm(const HostCsr &X, const HostCsr &Y) {
   HostCsr C;
   C.nr = X.nr;
   C.nc = Y.nc;
   C.rp.assign(X.nr + 1, 0);
-  std::vector<int32_t> mark(Y.nc, -1), cols;
-  std::vector<double> acc(Y.nc, 0.0);
+  std::vector<int32_t> key, cols;
+  std::vector<double> acc;
+  std::vector<std::pair<int32_t, double>> row;
+  C.ci.reserve(X.ci.size() * 4);
+  C.v.reserve(X.ci.size() * 4);
   for (int32_t i = 0; i < X.nr; ++i) {
+    int64_t bound = 0;
+    for (int32_t k = X.rp[i]; k < X.rp[i + 1]; ++k) bound += Y.rp[X.ci[k] + 1] - Y.rp[X.ci[k]];
+    size_t cap = 16;
+    while ((int64_t)cap < 2 * bound) cap <<= 1;
+    if (key.size() < cap) {
+      key.assign(cap, -1);
+      acc.resize(cap);
+    }
+    const size_t mask = cap - 1;
     cols.clear();
     for (int32_t k = X.rp[i]; k < X.rp[i + 1]; ++k) {
       const int32_t j = X.ci[k];
@@ -309,19 +324,26 @@ HostCsr spgemm(const HostCsr &X, const HostCsr &Y) {
       for (int32_t q = Y.rp[j]; q < Y.rp[j + 1]; ++q) {
         const int32_t J = Y.ci[q];
         const double prod = x * Y.v[q];
-        if (mark[J] != i) {
-          mark[J] = i;
-          acc[J] = prod;
-          cols.push_back(J);
+        size_t h = ((uint32_t)J * 2654435761u) & mask;
+        while (key[h] != J && key[h] != -1) h = (h + 1) & mask;
+        if (key[h] == -1) {
+          key[h] = J;
+          acc[h] = prod;
+          cols.push_back((int32_t)h);
         } else {
-          acc[J] += prod;
+          acc[h] += prod;
         }
       }
     }
-    std::sort(cols.begin(), cols.end());
-    for (int32_t J : cols) {
-      C.ci.push_back(J);
-      C.v.push_back(acc[J]);
+    row.clear();
+    for (int32_t h : cols) {
+      row.emplace_back(key[h], acc[h]);
+      key[h] = -1;
+    }
+    std::sort(row.begin(), row.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+    for (const auto &e : row) {
+      C.ci.push_back(e.first);
+      C.v.push_back(e.second);
     }
     C.rp[i + 1] = (int32_t)C.ci.size();
   }
@@ -533,6 +555,9 @@ HostHierarchy build_hierarchy(const HostCsr &A0, double theta, int max_levels, i
     t_rs += secs(t1, t2);
     t_int += secs(t2, t3);
     t_rap += secs(t3, t4);
+    if (trace)
+      std::fprintf(stderr, "[namg setup]   level %d n %d nnz %zu: strength %.3f rs %.3f interp %.3f rap %.3f s\n",
+                   (int)H.lv.size() - 1, n, L.A.ci.size(), secs(t0, t1), secs(t1, t2), secs(t2, t3), secs(t3, t4));
     for (int32_t i = 0; i < Ac.nr; ++i)
       if (diagonal(Ac, i) == 0.0) fail(NAMG_E_ZERO_PIVOT, "zero diagonal in a coarse operator");
     L.cf = std::move(cf);

@@ -83,7 +83,7 @@ auto sel_prolong(int g) { NAMG_GROUP_SWITCH(k_prolong, T) }
 
 template <class T>
 unsigned rows_grid(const DMat<T> &M) {
-  return blocks_for((int64_t)M.nrows * M.group);
+  return row_blocks(M.nrows, M.group, (int)sizeof(T));
 }
 }  // namespace
 
@@ -227,7 +227,7 @@ class Solver final : public SolverBase {
     if (op == NAMG_OP_SPMV64) {
       if (level != 0) throw SetupError{NAMG_E_INVALID, "SPMV64 is defined on level 0 only"};
       launch(NAMG_KF_GMRES_SPMV, 0, A64_.bytes() + 16.0 * A64_.nrows, sel_spmv<double, double, double, double>(1),
-             rows_grid(A64_), s, A64_.view(), in1, out);
+             rows_grid(A64_), s, A64_.view(), in1, out, (const double *)nullptr, (double *)nullptr);
       return;
     }
     if (op == NAMG_OP_COARSE) {
@@ -249,7 +249,7 @@ class Solver final : public SolverBase {
       case NAMG_OP_SPMV:
         cast(in1, d.x.get(), n, s);
         launch(NAMG_KF_SPMV, level, d.A.bytes() + 2 * S * n, sel_spmv<T, T, T, T>(d.A.group), rows_grid(d.A), s,
-               d.A.view(), (const T *)d.x.get(), d.b.get());
+               d.A.view(), (const T *)d.x.get(), d.b.get(), (const T *)nullptr, (T *)nullptr);
         cast(d.b.get(), out, n, s);
         break;
       case NAMG_OP_RESIDUAL:
@@ -269,7 +269,7 @@ class Solver final : public SolverBase {
       }
       case NAMG_OP_RESTRICT:
         cast(in1, d.r.get(), n, s);
-        restrict_(level, s);
+        restrict_(level, o, s);
         cast(c.b.get(), out, c.n, s);
         break;
       case NAMG_OP_PROLONG:
@@ -343,7 +343,7 @@ class Solver final : public SolverBase {
           vcycle(0, b0, zi, o, s);
           st.precond_apps++;
           launch(NAMG_KF_GMRES_SPMV, 0, A64_.bytes() + (S + 8.0) * n, sel_spmv<double, double, T, double>(1),
-                 rows_grid(A64_), s, A64_.view(), (const T *)zi, w);
+                 rows_grid(A64_), s, A64_.view(), (const T *)zi, w, (const double *)nullptr, (double *)nullptr);
           const int32_t ncols = i + 1;
           launch(NAMG_KF_MULTIDOT, 0, 8.0 * n * (ncols + 1), &k_multidot<8>, nblk_dot_, s, (const double *)V, ldv_,
                  ncols, (const double *)w, n, rows_per_dot_, dot_.get(), nblk_dot_);
@@ -450,8 +450,8 @@ class Solver final : public SolverBase {
     Z_.alloc((size_t)ldz_ * m, &mc_);
     w_.alloc(n, &mc_);
     if (!std::is_same<T, double>::value) vin_.alloc(n, &mc_);
-    nblk_dot_ = (int32_t)std::min<int64_t>(1024, std::max<int64_t>(1, blocks_for(n)));
-    rows_per_dot_ = (int32_t)(((int64_t)n + nblk_dot_ - 1) / nblk_dot_);
+    nblk_dot_ = dot_blocks(n);
+    rows_per_dot_ = dot_rows_per_block(n);
     dot_.alloc((size_t)nblk_dot_ * 2 * (m + 2), &mc_);
     cd_.alloc((size_t)2 * (m + 2), &mc_);
     ws_m_ = m;
@@ -526,7 +526,7 @@ class Solver final : public SolverBase {
         launch(op.family, op.level, op.bytes, sel_neumann<T>(op.group), op.grid, s, t.M, t.a, t.b, t.c, t.d, t.o0);
         break;
       case ROP_SPMV:
-        launch(op.family, op.level, op.bytes, sel_spmv<T, T, T, T>(op.group), op.grid, s, t.M, t.b, t.o0);
+        launch(op.family, op.level, op.bytes, sel_spmv<T, T, T, T>(op.group), op.grid, s, t.M, t.b, t.o0, t.c, t.o1);
         break;
       case ROP_PROLONG:
         launch(op.family, op.level, op.bytes, sel_prolong<T>(op.group), op.grid, s, t.M, t.b, t.o0);
@@ -545,8 +545,9 @@ class Solver final : public SolverBase {
     const DevLevel<T> &L = lv_[l];
     const int32_t n = L.n;
     const double bytes = (x ? L.A.bytes() + S * n : 0.0) + S * n * (1 + (r ? 1 : 0) + (f ? 2 : 0));
-    emit(row_op(ROP_RESIDUAL, NAMG_KF_RESIDUAL, l, L.A.view(), x ? L.A.group : 1, x ? rows_grid(L.A) : blocks_for(n),
-                bytes, b, x, d, nullptr, r, f, n),
+    const unsigned grid = x ? rows_grid(L.A) : row_blocks(n, 1, (int)sizeof(T));
+    emit(row_op(ROP_RESIDUAL, NAMG_KF_RESIDUAL, l, L.A.view(), x ? L.A.group : 1, grid, bytes, b, x, d, nullptr, r, f,
+                n),
          s);
   }
 
@@ -573,11 +574,22 @@ class Solver final : public SolverBase {
          s);
   }
 
-  void restrict_(int l, hipStream_t s) {
+  // True when level l's first pre-smoothing term f = D^{-1} b (polynomial GS, zero initial guess) is
+  // produced by the restriction from level l - 1 instead of a pass of its own.
+  bool fused_f(int l, const CycleOpts &o) const {
+    const int nl = (int)lv_.size();
+    if (l < 1 || l + 1 >= nl || o.nu1 < 1) return false;
+    return !((o.smoother == NAMG_SMOOTH_ILU0) && lv_[l].has_ilu);
+  }
+
+  // b_{l+1} = R_l r_l [and f_{l+1} = D_{l+1}^{-1} b_{l+1} when the coarse level's sweep starts with it]
+  void restrict_(int l, const CycleOpts &o, hipStream_t s) {
     DevLevel<T> &d = lv_[l];
     DevLevel<T> &c = lv_[l + 1];
-    emit(row_op(ROP_SPMV, NAMG_KF_SPMV, l, d.R.view(), d.R.group, rows_grid(d.R), d.R.bytes() + S * ((double)d.n + c.n),
-                nullptr, d.r.get(), nullptr, nullptr, c.b.get(), nullptr, c.n),
+    const bool ff = fused_f(l + 1, o);
+    emit(row_op(ROP_SPMV, NAMG_KF_SPMV, l, d.R.view(), d.R.group, rows_grid(d.R),
+                d.R.bytes() + S * ((double)d.n + c.n) + (ff ? 2.0 * S * c.n : 0.0), nullptr, d.r.get(),
+                ff ? (const T *)c.dinv.get() : nullptr, nullptr, c.b.get(), ff ? c.f.get() : nullptr, c.n),
          s);
   }
 
@@ -608,7 +620,9 @@ class Solver final : public SolverBase {
   }
 
   // Smoothing sweep on level l: x <- x + Mhat^{-1}(b - A x); first = true means x == 0 on entry.
-  void smooth(int l, const T *b, T *x, bool first, bool pre, bool ilu, const CycleOpts &o, hipStream_t s) {
+  // f_ready: f = D^{-1} b is already in place (first sweep of a level fed by a fused restriction).
+  void smooth(int l, const T *b, T *x, bool first, bool pre, bool ilu, const CycleOpts &o, hipStream_t s,
+              bool f_ready = false) {
     DevLevel<T> &d = lv_[l];
     const int32_t n = d.n;
     const T *nul = nullptr;
@@ -616,7 +630,7 @@ class Solver final : public SolverBase {
     T *pp[2] = {d.g1.get(), d.g2.get()};
     if (!ilu) {
       // polynomial Gauss-Seidel (Section 5.2): f = D^{-1}(b - A x), g <- f - (D^{-1}L) g, x += g
-      residual(l, b, first ? nul : (const T *)x, d.dinv.get(), nullptr, d.f.get(), s);
+      if (!f_ready) residual(l, b, first ? nul : (const T *)x, d.dinv.get(), nullptr, d.f.get(), s);
       const DMat<T> &M = pre ? d.pgs_lo : d.pgs_up;
       if (o.tri_mode == NAMG_TRI_NEUMANN) {
         if (t == 1) {
@@ -675,9 +689,9 @@ class Solver final : public SolverBase {
     DevLevel<T> &d = lv_[l];
     const bool ilu = (o.smoother == NAMG_SMOOTH_ILU0) && d.has_ilu;
     if (o.nu1 == 0) fill_zero(l, x, d.n, s);
-    for (int k = 0; k < o.nu1; ++k) smooth(l, b, x, k == 0, true, ilu, o, s);
+    for (int k = 0; k < o.nu1; ++k) smooth(l, b, x, k == 0, true, ilu, o, s, k == 0 && fused_f(l, o));
     residual(l, b, x, nullptr, d.r.get(), nullptr, s);
-    restrict_(l, s);
+    restrict_(l, o, s);
   }
 
   void level_up(int l, const T *b, T *x, const CycleOpts &o, hipStream_t s) {
