@@ -71,6 +71,21 @@ def copy_ceiling(torch, nbytes=2 << 30, reps=10):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
+def read_ceiling(torch, nbytes=2 << 30, reps=10):
+    """Read-only streaming bandwidth (a full reduction of a 2 GiB array) as the ceiling for read-bound kernels."""
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    a.sum()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        a.sum()
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a
+    return nbytes / (ms * 1e-3) / 1e9
+
+
 def _time_solves(torch, H, bt, xt, kw, steps, warmup):
     for _ in range(warmup):
         xt.zero_()
@@ -116,7 +131,7 @@ def served_stream(namg, count, inflight, setup_threads):
         if delay > 0:
             time.sleep(delay)
         A, b = systems[j]
-        return srv.submit(A, b)
+        return srv.submit(A, b, ilu_levels=0)  # polynomial GS throughout: no ILU(0) factors to build
 
     with ThreadPoolExecutor(max_workers=4) as ex:
         tickets = list(ex.map(submit, range(count)))
@@ -156,7 +171,14 @@ def cpu_baseline(A, b, kw, gpu_iters):
     r = G.solve(b, tol=kw["tol"], restart=kw["restart"], smoother=kw["smoother"], tri_mode=kw["tri_mode"],
                 t=kw["inner_terms"], gmres_T=kw["gmres_T"])
     solve_s = time.perf_counter() - t0
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next(line.split(":", 1)[1].strip() for line in f if line.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": solve_s * 1e3, "unit": "ms", "cores": 1, "kind": "oracle",
+            "host": f"{model}; {os.cpu_count()} logical CPUs visible, the oracle uses 1",
             "sample": f"one full oracle solve of the same system ({r['iters']} iterations, relres "
                       f"{r['relres_true']:.1e}; GPU {gpu_iters}); oracle setup {setup_s:.1f} s excluded"}
 
@@ -248,6 +270,7 @@ def main():
                            "avg_us": round(per_launch_ms * 1e3, 3),
                            "alg_MB_per_launch": round(per_launch_bytes / 1e6, 3)}
     out["copy_ceiling_GBps"] = round(copy_ceiling(torch), 1)
+    out["read_ceiling_GBps"] = round(read_ceiling(torch), 1)
 
     if args.compare:
         cmp = {}
