@@ -455,34 +455,41 @@ __device__ __forceinline__ void multidot_body(uint32_t lb, const double *__restr
     double ac[CH], ad[CH];
 #pragma unroll
     for (int c = 0; c < CH; ++c) ac[c] = ad[c] = 0.0;
-#pragma unroll 2
+    // every slot loads a valid column (slots past ncols repeat the last one and are discarded below), so
+    // there is no branch between the loads and all CH + 2 of them are in flight together
+    const double *cols[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) cols[c] = V + (int64_t)min(j0 + c, ncols - 1) * ldv;
     for (int32_t r = r0 + 2 * (int32_t)threadIdx.x; r < r1; r += 2 * BLK) {
       if (r + 1 < r1) {
         const double2 vr = *reinterpret_cast<const double2 *>(v + r);
         const double2 wr = w ? *reinterpret_cast<const double2 *>(w + r) : make_double2(0.0, 0.0);
+        double2 vj[CH];
 #pragma unroll
-        for (int c = 0; c < CH; ++c)
-          if (j0 + c < ncols) {
-            const double2 vj = *reinterpret_cast<const double2 *>(V + (int64_t)(j0 + c) * ldv + r);
-            ac[c] += vj.x * vr.x;
-            ac[c] += vj.y * vr.y;
-            ad[c] += vj.x * wr.x;
-            ad[c] += vj.y * wr.y;
-          }
+        for (int c = 0; c < CH; ++c) vj[c] = *reinterpret_cast<const double2 *>(cols[c] + r);
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          ac[c] += vj[c].x * vr.x;
+          ac[c] += vj[c].y * vr.y;
+          ad[c] += vj[c].x * wr.x;
+          ad[c] += vj[c].y * wr.y;
+        }
       } else {
         const double vr = v[r];
         const double wr = w ? w[r] : 0.0;
+        double vj[CH];
 #pragma unroll
-        for (int c = 0; c < CH; ++c)
-          if (j0 + c < ncols) {
-            const double vj = V[(int64_t)(j0 + c) * ldv + r];
-            ac[c] += vj * vr;
-            ad[c] += vj * wr;
-          }
+        for (int c = 0; c < CH; ++c) vj[c] = cols[c][r];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          ac[c] += vj[c] * vr;
+          ad[c] += vj[c] * wr;
+        }
       }
     }
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
+      if (j0 + c >= ncols) break;  // uniform: the discarded slots are not reduced
       ac[c] = wave_sum(ac[c]);
       ad[c] = wave_sum(ad[c]);
       if (lane == 0) {
