@@ -207,7 +207,8 @@ HostCsr classical_interpolation(const HostCsr &A, const Graph &S, const std::vec
   // role[j] for the current row: 0 none, 1 strong C, 2 strong F, 3 strong F treated as weak
   std::vector<int8_t> role(n, 0);
   std::vector<double> num(n, 0.0), aval(n, 0.0), dens;
-  std::vector<int32_t> strongF;
+  std::vector<int32_t> strongF, cpos;
+  std::vector<std::pair<int32_t, double>> centries;
   for (int32_t i = 0; i < n; ++i) {
     if (cf[i] == 1) {
       P.ci.push_back(cnum[i]);
@@ -228,13 +229,21 @@ HostCsr classical_interpolation(const HostCsr &A, const Graph &S, const std::vec
       }
     }
     if (anyC) {
+      // one scan of each strong F neighbour's row: its entries in the strong C set (in row order) are
+      // kept for the distribution below, and their sum is the denominator
       dens.assign(strongF.size(), 0.0);
+      cpos.assign(strongF.size() + 1, 0);
+      centries.clear();
       for (size_t q = 0; q < strongF.size(); ++q) {
         const int32_t k = strongF[q];
         double s = 0.0;
         for (int32_t p = A.rp[k]; p < A.rp[k + 1]; ++p)
-          if (role[A.ci[p]] == 1) s += A.v[p];
+          if (role[A.ci[p]] == 1) {
+            s += A.v[p];
+            centries.emplace_back(A.ci[p], A.v[p]);
+          }
         dens[q] = s;
+        cpos[q + 1] = (int32_t)centries.size();
         if (s == 0.0) role[k] = 3;
       }
       double dd = 0.0;
@@ -252,12 +261,8 @@ HostCsr classical_interpolation(const HostCsr &A, const Graph &S, const std::vec
       for (int32_t p = A.rp[i]; p < A.rp[i + 1]; ++p) aval[A.ci[p]] = A.v[p];
       for (size_t q = 0; q < strongF.size(); ++q) {
         if (dens[q] == 0.0) continue;
-        const int32_t k = strongF[q];
-        const double aik = aval[k];
-        for (int32_t p = A.rp[k]; p < A.rp[k + 1]; ++p) {
-          const int32_t j = A.ci[p];
-          if (role[j] == 1) num[j] += (aik * A.v[p]) / dens[q];
-        }
+        const double aik = aval[strongF[q]];
+        for (int32_t e = cpos[q]; e < cpos[q + 1]; ++e) num[centries[e].first] += (aik * centries[e].second) / dens[q];
       }
       for (int32_t k = S.rp[i]; k < S.rp[i + 1]; ++k) {
         const int32_t j = S.ci[k];
@@ -386,6 +391,8 @@ HostCsr strict_part(const HostCsr &A, const std::vector<double> &vals, bool lowe
   T.nr = A.nr;
   T.nc = A.nc;
   T.rp.assign(A.nr + 1, 0);
+  T.ci.reserve(A.ci.size() / 2 + 1);
+  T.v.reserve(A.ci.size() / 2 + 1);
   for (int32_t i = 0; i < A.nr; ++i) {
     for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
       const int32_t j = A.ci[k];

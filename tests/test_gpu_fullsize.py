@@ -2,7 +2,7 @@
 V-cycle with 3 Neumann terms, low-sync GMRES(30) with T = I - L, FP64, in the launch configuration the
 benchmark times.
 
-The expected values were written by tests/golden/make_c2_golden.py, which calls only the CPU oracle:
+The expected values were written by tests/golden/make_golden.py, which calls only the CPU oracle:
 every level's size and C/F splitting (SHA-256), the iteration count, the residual estimate after every
 iteration, and 4096 entries of the solution at seeded positions. The true residual of the GPU solution
 is recomputed here with an FP64 SpMV on the host.
@@ -103,3 +103,58 @@ def test_fp32_preconditioner_full_size(namg, golden, system):
     assert abs(st["iters"] - golden["iters"]) <= 2
     idx = np.asarray(golden["sample_index"])
     assert np.abs(x[idx] - np.asarray(golden["sample_x"])).max() / golden["x_max_abs"] <= 1e-6
+
+
+# ------------------------------------------------------------------------------------ C3 at 192^3
+GOLDEN_C3 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_192_fp64_pgs_t2.json")
+SOLVE_C3 = dict(smoother=0, tri_mode=0, inner_terms=2, restart=30, gmres_T=0, tol=1e-8)
+
+
+@pytest.fixture(scope="module")
+def golden_c3():
+    with open(GOLDEN_C3) as f:
+        return json.load(f)
+
+
+@pytest.fixture(scope="module")
+def system_c3(namg):
+    A, b, meta = config_system("c3")
+    assert meta["N"] == 192
+    return A, b
+
+
+def test_c3_fp64_matches_oracle(namg, golden_c3, system_c3):
+    """-div(k grad p) at 192^3 (7 077 888 rows, lognormal k, z stretched 1:100), polynomial GS t = 2."""
+    A, b = system_c3
+    H = namg.Hierarchy(A, device=0, ilu_levels=0)
+    info = H.info()
+    assert info["levels"] == len(golden_c3["levels"])
+    for l, g in enumerate(golden_c3["levels"]):
+        assert (info["n"][l], info["nnz"][l]) == (g["n"], g["nnz"]), l
+    cf0 = np.ascontiguousarray(H.export_level(0)["cf"], dtype=np.int8)
+    assert hashlib.sha256(cf0.tobytes()).hexdigest() == golden_c3["levels"][0]["cf_sha256"]
+    st, x = _solve(namg, H, b, **SOLVE_C3)
+    H.close()
+    assert st["status"] == namg.OK and st["iters"] == golden_c3["iters"]
+    assert st["relres_est"] == pytest.approx(golden_c3["hist"][-1], rel=1e-8)
+    idx = np.asarray(golden_c3["sample_index"])
+    gap = np.abs(x[idx] - np.asarray(golden_c3["sample_x"])).max() / golden_c3["x_max_abs"]
+    assert gap <= 1e-10, gap
+    res = np.linalg.norm(b - O.spmv(A, x)) / np.linalg.norm(b)
+    assert res <= 1e-8 and st["relres_true"] == pytest.approx(res, rel=1e-6)
+
+
+def test_c3_fp32_preconditioner(namg, golden_c3, system_c3):
+    """The C3 configuration's FP32 hierarchy and V-cycle under FP64 GMRES: the same 1e-8 true residual
+    (independent FP64 SpMV) in at most two more iterations than the FP64 oracle."""
+    A, b = system_c3
+    H = namg.Hierarchy(A, device=0, precision=namg.FP32_PRECOND, ilu_levels=0)
+    st, x = _solve(namg, H, b, **SOLVE_C3)
+    H.close()
+    res = np.linalg.norm(b - O.spmv(A, x)) / np.linalg.norm(b)
+    assert st["status"] == namg.OK and res <= 1e-8
+    assert abs(st["iters"] - golden_c3["iters"]) <= 2
+    idx = np.asarray(golden_c3["sample_index"])
+    gap = np.abs(x[idx] - np.asarray(golden_c3["sample_x"])).max() / golden_c3["x_max_abs"]
+    print(f"C3 FP32: iters {st['iters']}, relres {res:.2e}, sampled |x - x_oracle| / max|x| = {gap:.2e}")
+    assert gap <= 1e-3, gap

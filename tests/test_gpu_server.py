@@ -121,3 +121,32 @@ def test_bad_input_and_not_converged(namg):
     z = srv.wait(srv.submit(A, np.zeros(A.n)))
     assert z["status"] == namg.OK and not np.any(z["x"])
     srv.close()
+
+
+def test_served_stream_subset_alone_vs_mix(namg):
+    """50 requests of the served stream (variable-k systems, Poisson arrivals, n log-uniform in [32, 160];
+    the 50 earliest with n <= 64 keep generation and setup short): every result is bit-identical alone
+    (max_inflight = 1) and in the mix (all submitted at once), and reaches the 1e-8 true residual."""
+    from workloads import serve_stream
+
+    reqs = [r for r in serve_stream(2000, seed=5) if r["N"] <= 64][:50]
+    assert len(reqs) == 50 and len({r["N"] for r in reqs}) > 10
+    systems = [varcoef3d(r["N"], 0.5, r["seed"]) for r in reqs]
+    solve = dict(smoother=0, inner_terms=2, restart=30, tol=1e-8)
+
+    def run(inflight):
+        srv = namg.Server(solve=solve, max_inflight=inflight, setup_threads=8, precision=1)
+        tickets = [srv.submit(A, b, ilu_levels=0) for A, b in systems]
+        out = [srv.wait(t) for t in tickets]
+        counters = srv.stats()
+        srv.close()
+        return out, counters
+
+    alone, c1 = run(1)
+    mix, c64 = run(64)
+    assert c1["peak_inflight"] == 1 and c64["peak_inflight"] > 1
+    for (A, b), a, m in zip(systems, alone, mix):
+        assert a["status"] == namg.OK and m["status"] == namg.OK
+        assert a["iters"] == m["iters"]
+        assert np.array_equal(a["x"], m["x"])
+        assert relres(A, b, m["x"]) <= 1e-8
