@@ -157,4 +157,6 @@ def test_c3_fp32_preconditioner(namg, golden_c3, system_c3):
     idx = np.asarray(golden_c3["sample_index"])
     gap = np.abs(x[idx] - np.asarray(golden_c3["sample_x"])).max() / golden_c3["x_max_abs"]
     print(f"C3 FP32: iters {st['iters']}, relres {res:.2e}, sampled |x - x_oracle| / max|x| = {gap:.2e}")
-    assert gap <= 1e-3, gap
+    # measured 1.4e-13: the residual left at 1e-8 lies in the stiff (large-eigenvalue) components, which
+    # carry little of x; the bound keeps five orders of margin
+    assert gap <= 1e-8, gap
