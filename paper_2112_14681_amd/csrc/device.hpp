@@ -250,23 +250,37 @@ struct DMat {
   }
 };
 
-// CSR rows grouped by dependency level, for the level-scheduled direct triangular solves.
+// CSR rows grouped by dependency level, for the level-scheduled direct triangular solves. The rows are
+// stored in schedule order (position q holds row order[q] with its entries in their CSR order), so a
+// thread finds its row's entries from its position alone and the row index and the entry range load
+// in parallel.
 template <class T>
 struct DTri {
   int32_t n = 0;
-  DevBuf<int32_t> rp, ci, order;
+  DevBuf<int32_t> rp, ci, order;  // rp, ci, val: rows in schedule order
   DevBuf<T> val;
-  std::vector<int32_t> lev_ptr;  // host copy: rows order[lev_ptr[k] .. lev_ptr[k+1]) form level k
+  std::vector<int32_t> lev_ptr;  // host copy: positions lev_ptr[k] .. lev_ptr[k+1] form level k
   int64_t nnz = 0;
 
   void build(const HostCsr &S, const LevelSchedule &sch, MemCounter *mc) {
     n = S.nr;
     nnz = S.nnz();
-    rp.alloc(S.rp.size(), mc);
-    rp.upload(S.rp.data(), S.rp.size());
-    ci.alloc(S.ci.size(), mc);
-    ci.upload(S.ci.data(), S.ci.size());
-    std::vector<T> hv(S.v.begin(), S.v.end());
+    std::vector<int32_t> hrp(n + 1, 0), hci;
+    std::vector<T> hv;
+    hci.reserve(S.ci.size());
+    hv.reserve(S.v.size());
+    for (int32_t q = 0; q < n; ++q) {
+      const int32_t i = sch.order[q];
+      for (int32_t k = S.rp[i]; k < S.rp[i + 1]; ++k) {
+        hci.push_back(S.ci[k]);
+        hv.push_back((T)S.v[k]);
+      }
+      hrp[q + 1] = (int32_t)hci.size();
+    }
+    rp.alloc(hrp.size(), mc);
+    rp.upload(hrp.data(), hrp.size());
+    ci.alloc(hci.size(), mc);
+    ci.upload(hci.data(), hci.size());
     val.alloc(hv.size(), mc);
     val.upload(hv.data(), hv.size());
     order.alloc(sch.order.size(), mc);

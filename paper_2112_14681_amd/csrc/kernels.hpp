@@ -367,17 +367,37 @@ __global__ __launch_bounds__(BLK) void k_axpy(const T *__restrict__ f, const T *
   axpy_body(blockIdx.x, f, scale, acc, out, n);
 }
 
-// One dependency level of a direct triangular solve g = (I + S)^{-1} f: rows of the level only read
-// g of earlier levels.
+// One dependency level of a direct triangular solve g = (I + S)^{-1} f: rows of the level only read g of
+// earlier levels. Position q = beg + thread holds row order[q]; rp / ci / val store the rows in schedule
+// order, so the row index and the entry range load together, and a row's entries are loaded in chunks
+// of four before their gathers. The subtraction order is the row's entry order.
 template <class T>
 __global__ __launch_bounds__(BLK) void k_tri_level(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                                    const T *__restrict__ val, const int32_t *__restrict__ order,
                                                    int32_t beg, int32_t cnt, const T *__restrict__ f, T *g) {
-  const int32_t q = blockIdx.x * BLK + threadIdx.x;
-  if (q >= cnt) return;
-  const int32_t i = order[beg + q];
+  constexpr int U = 4;
+  const int32_t t = blockIdx.x * BLK + threadIdx.x;
+  if (t >= cnt) return;
+  const int32_t q = beg + t;
+  const int32_t i = order[q];
+  int32_t k = rp[q];
+  const int32_t end = rp[q + 1];
   T acc = f[i];
-  for (int32_t k = rp[i]; k < rp[i + 1]; ++k) acc -= val[k] * g[ci[k]];
+  for (; k < end; k += U) {
+    int32_t c[U];
+    T v[U], x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t kk = k + u < end ? k + u : k;
+      c[u] = ci[kk];
+      v[u] = val[kk];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) x[u] = g[c[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k + u < end) acc -= v[u] * x[u];
+  }
   g[i] = acc;
 }
 

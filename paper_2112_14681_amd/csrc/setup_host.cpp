@@ -556,15 +556,20 @@ HostHierarchy build_hierarchy(const HostCsr &A0, double theta, int max_levels, i
     auto t3 = now();
     if (P.nc == 0 || P.nc == n) break;
     HostCsr R = transpose_csr(P);
-    HostCsr Ac = spgemm(R, spgemm(L.A, P));
+    HostCsr AP = spgemm(L.A, P);
+    auto t3b = now();
+    HostCsr Ac = spgemm(R, AP);
     auto t4 = now();
     t_str += secs(t0, t1);
     t_rs += secs(t1, t2);
     t_int += secs(t2, t3);
     t_rap += secs(t3, t4);
     if (trace)
-      std::fprintf(stderr, "[namg setup]   level %d n %d nnz %zu: strength %.3f rs %.3f interp %.3f rap %.3f s\n",
-                   (int)H.lv.size() - 1, n, L.A.ci.size(), secs(t0, t1), secs(t1, t2), secs(t2, t3), secs(t3, t4));
+      std::fprintf(stderr,
+                   "[namg setup]   level %d n %d nnz %zu: strength %.3f rs %.3f interp %.3f ap %.3f r(ap) %.3f s "
+                   "(nnz P %zu AP %zu Ac %zu)\n",
+                   (int)H.lv.size() - 1, n, L.A.ci.size(), secs(t0, t1), secs(t1, t2), secs(t2, t3), secs(t3, t3b),
+                   secs(t3b, t4), P.ci.size(), AP.ci.size(), Ac.ci.size());
     for (int32_t i = 0; i < Ac.nr; ++i)
       if (diagonal(Ac, i) == 0.0) fail(NAMG_E_ZERO_PIVOT, "zero diagonal in a coarse operator");
     L.cf = std::move(cf);

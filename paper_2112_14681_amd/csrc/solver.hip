@@ -11,8 +11,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <string>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 
@@ -168,6 +170,8 @@ class Solver final : public SolverBase {
   }
 
   ~Solver() override {
+    for (auto &kv : tri_graphs_) (void)hipGraphExecDestroy(kv.second);
+    if (capture_) (void)hipStreamDestroy(capture_);
     for (auto &e : events_) {
       (void)hipEventDestroy(e.first);
       (void)hipEventDestroy(e.second);
@@ -607,16 +611,38 @@ class Solver final : public SolverBase {
          s);
   }
 
-  // g = (I + S)^{-1} f, one launch per dependency level.
+  // g = (I + S)^{-1} f, one launch per dependency level: hundreds of small dependent launches per
+  // triangle. The chain is captured once per (triangle, f, g) into a HIP graph and replayed, so the host
+  // issues one graph launch per triangular solve. (Timing events are not attached inside graphs.)
   void tri_solve(int l, const DTri<T> &tr, const T *f, T *g, hipStream_t s) {
+    (void)l;
     const int nlev = (int)tr.lev_ptr.size() - 1;
-    for (int k = 0; k < nlev; ++k) {
-      const int32_t beg = tr.lev_ptr[k], cnt = tr.lev_ptr[k + 1] - beg;
-      const double bytes = (double)(tr.lev_ptr[k + 1] - beg) / std::max<int32_t>(tr.n, 1) *
-                           (tr.nnz * (S + 4.0) + S * 3.0 * tr.n + 12.0 * tr.n);
-      launch(NAMG_KF_TRI, l, bytes, &k_tri_level<T>, blocks_for(cnt), s, (const int32_t *)tr.rp.get(),
-             (const int32_t *)tr.ci.get(), (const T *)tr.val.get(), (const int32_t *)tr.order.get(), beg, cnt, f, g);
+    if (nlev <= 0) return;
+    alg_ += tr.nnz * (S + 4.0) + S * 3.0 * tr.n + 12.0 * tr.n;
+    const auto key = std::make_tuple((const void *)&tr, (const void *)f, (const void *)g);
+    auto it = tri_graphs_.find(key);
+    if (it == tri_graphs_.end()) {
+      if (!capture_) hip_check(hipStreamCreateWithFlags(&capture_, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+      hip_check(hipStreamBeginCapture(capture_, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+      hipError_t launch_err = hipSuccess;
+      for (int k = 0; k < nlev; ++k) {
+        const int32_t beg = tr.lev_ptr[k], cnt = tr.lev_ptr[k + 1] - beg;
+        hipLaunchKernelGGL(k_tri_level<T>, dim3(blocks_for(cnt)), dim3(BLK), 0, capture_, (const int32_t *)tr.rp.get(),
+                           (const int32_t *)tr.ci.get(), (const T *)tr.val.get(), (const int32_t *)tr.order.get(), beg,
+                           cnt, f, g);
+        if (launch_err == hipSuccess) launch_err = hipGetLastError();
+      }
+      hipGraph_t graph = nullptr;
+      const hipError_t end_err = hipStreamEndCapture(capture_, &graph);
+      hip_check(launch_err, "kernel launch during graph capture");
+      hip_check(end_err, "hipStreamEndCapture");
+      hipGraphExec_t exec = nullptr;
+      const hipError_t inst_err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      hip_check(inst_err, "hipGraphInstantiate");
+      it = tri_graphs_.emplace(key, exec).first;
     }
+    hip_check(hipGraphLaunch(it->second, s), "hipGraphLaunch");
   }
 
   // Smoothing sweep on level l: x <- x + Mhat^{-1}(b - A x); first = true means x == 0 on entry.
@@ -676,6 +702,10 @@ class Solver final : public SolverBase {
         in = out;
       }
     } else {
+      if (first) {
+        axpy(l, b, nul, nul, d.r.get(), n, s);  // the captured solve reads a fixed buffer
+        r = d.r.get();
+      }
       tri_solve(l, d.tri_ilu_lo, r, d.g1.get(), s);
       axpy(l, d.g1.get(), d.ilu_dinv.get(), nul, d.f.get(), n, s);
       tri_solve(l, d.tri_ilu_up, d.f.get(), d.g2.get(), s);
@@ -733,6 +763,8 @@ class Solver final : public SolverBase {
   int dev_;
   const HostHierarchy *host_;
   bool direct_ready_ = false;
+  std::map<std::tuple<const void *, const void *, const void *>, hipGraphExec_t> tri_graphs_;
+  hipStream_t capture_ = nullptr;
   MemCounter mc_;
   std::vector<DevLevel<T>> lv_;
   DMat<T> coarse_inv_;

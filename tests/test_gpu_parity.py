@@ -115,6 +115,35 @@ def test_single_sweeps(namg, c2_small, level, smoother, tri, t):
         assert relerr(host(out), ref) <= TOL64, (op, kind)
 
 
+def test_direct_sweep_graph_replays(namg):
+    """The direct comparators replay captured HIP graphs (one per triangle and operand pair): repeated
+    sweeps, with eager work and synchronisations in between, each match the oracle and the first
+    replay bit for bit."""
+    A, b, _ = config_system("c2", 23)
+    H = namg.Hierarchy(A, device=0, ilu_levels=-1)
+    rng = np.random.default_rng(77)
+    for level in (0, 1):
+        Al, _ = level_csr(H, level)
+        for smoother, op, kind in ((0, namg.OP_SMOOTH_PRE, O.GS_FWD), (0, namg.OP_SMOOTH_POST, O.GS_BWD),
+                                   (1, namg.OP_SMOOTH_PRE, O.ILU_DIRECT), (1, namg.OP_SMOOTH_POST, O.ILU_DIRECT)):
+            first = None
+            for rep in range(4):
+                x, bb = rng.standard_normal(Al.n), rng.standard_normal(Al.n)
+                if first is not None:
+                    x, bb = x0, b0
+                out = torch.empty(Al.n, dtype=torch.float64, device="cuda:0")
+                H.apply(level, op, dev(x), dev(bb), out, smoother=smoother, tri_mode=1, inner_terms=1)
+                got = host(out)
+                assert relerr(got, O.smooth(Al, kind, 1, bb, x)) <= TOL64, (level, smoother, op, rep)
+                if first is None:
+                    first, x0, b0 = got, x, bb
+                else:
+                    assert np.array_equal(got, first), (level, smoother, op, rep)
+                # eager work between replays
+                H.apply(level, namg.OP_SPMV, dev(x), None, out)
+                torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("smoother,tri,t", [(0, 0, 2), (0, 0, 3), (0, 1, 2), (1, 0, 3), (1, 1, 3), (1, 0, 1)])
 def test_vcycle_matches_oracle(namg, smoother, tri, t):
     A, b, _ = config_system("c2", 23)
