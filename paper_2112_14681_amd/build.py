@@ -30,8 +30,11 @@ def build(verbose: bool = True) -> str:
     dev_o = os.path.join(BUILD, "solver.o")
     _run(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fPIC", "-Wall", "-c",
           os.path.join(CSRC, "setup_host.cpp"), "-o", host_o])
+    # kernarg preloading: the leading kernel arguments arrive in scalar registers (the compiler keeps a
+    # loading prologue for firmware that does not preload)
     _run([hipcc, f"--offload-arch={ARCH}", "-std=c++17", "-O3", "-fPIC", "-Wall",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-mllvm", "-amdgpu-kernarg-preload-count=16",
           "-c", os.path.join(CSRC, "solver.hip"), "-o", dev_o])
     tmp = LIB + ".tmp"
     _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", host_o, dev_o, "-o", tmp])

@@ -337,28 +337,52 @@ __device__ __forceinline__ void axpy_body(uint32_t lb, const T *__restrict__ f, 
 }
 
 // --------------------------------------------------------------------------- single-problem kernels
+//
+// The single-problem kernels take a sparse operator as plain fields: row/slice pointers, one index array
+// (int32 columns or 16-bit offsets, `narrow` says which), values, row count; then the operands the body
+// loads first; then the rest. The build preloads the first 56 bytes of kernel arguments into scalar
+// registers (kernarg preloading on gfx950), so the first loads of a launch do not wait for a
+// kernel-argument load. The bodies get the MatView rebuilt in registers.
+#define NAMG_MAT_HEAD(T) \
+  const int32_t *__restrict__ m_ptr, const void *__restrict__ m_idx, const T *__restrict__ m_val, int32_t m_nrows, \
+      int32_t m_narrow
+
+template <class T>
+__device__ __forceinline__ MatView<T> make_view(const int32_t *ptr, const void *idx, const T *val, int32_t nrows,
+                                                int32_t narrow, int64_t mul) {
+  MatView<T> v;
+  v.ptr = ptr;
+  v.col = narrow ? nullptr : static_cast<const int32_t *>(idx);
+  v.col16 = narrow ? static_cast<const int16_t *>(idx) : nullptr;
+  v.val = val;
+  v.mul = mul;
+  v.nrows = nrows;
+  return v;
+}
+#define NAMG_MAT_VIEW(T) make_view<T>(m_ptr, m_idx, m_val, m_nrows, m_narrow, m_mul)
 
 template <int G, class Acc, class TM, class TX, class TY>
-__global__ __launch_bounds__(BLK) void k_spmv(MatView<TM> A, const TX *__restrict__ x, TY *__restrict__ y,
-                                              const TY *__restrict__ d, TY *__restrict__ f) {
-  spmv_body<G, Acc>(blockIdx.x, A, x, y, d, f);
+__global__ __launch_bounds__(BLK) void k_spmv(NAMG_MAT_HEAD(TM), const TX *__restrict__ x, const TY *__restrict__ d,
+                                              TY *__restrict__ y, TY *__restrict__ f, int64_t m_mul) {
+  spmv_body<G, Acc>(blockIdx.x, NAMG_MAT_VIEW(TM), x, y, d, f);
 }
 
 template <int G, class T>
-__global__ __launch_bounds__(BLK) void k_residual(MatView<T> A, const T *__restrict__ b, const T *__restrict__ x,
-                                                  const T *__restrict__ d, T *__restrict__ r, T *__restrict__ f) {
-  residual_body<G>(blockIdx.x, A, b, x, d, r, f);
+__global__ __launch_bounds__(BLK) void k_residual(NAMG_MAT_HEAD(T), const T *__restrict__ b, const T *__restrict__ d,
+                                                  const T *__restrict__ x, T *__restrict__ r, T *__restrict__ f,
+                                                  int64_t m_mul) {
+  residual_body<G>(blockIdx.x, NAMG_MAT_VIEW(T), b, x, d, r, f);
 }
 
 template <int G, class T>
-__global__ __launch_bounds__(BLK) void k_neumann(MatView<T> S, const T *__restrict__ f, const T *__restrict__ in,
-                                                 const T *__restrict__ scale, const T *acc, T *out) {
-  neumann_body<G>(blockIdx.x, S, f, in, scale, acc, out);
+__global__ __launch_bounds__(BLK) void k_neumann(NAMG_MAT_HEAD(T), const T *__restrict__ f, const T *__restrict__ scale,
+                                                 const T *acc, const T *__restrict__ in, T *out, int64_t m_mul) {
+  neumann_body<G>(blockIdx.x, NAMG_MAT_VIEW(T), f, in, scale, acc, out);
 }
 
 template <int G, class T>
-__global__ __launch_bounds__(BLK) void k_prolong(MatView<T> P, const T *__restrict__ e, T *x) {
-  prolong_body<G>(blockIdx.x, P, e, x);
+__global__ __launch_bounds__(BLK) void k_prolong(NAMG_MAT_HEAD(T), T *x, const T *__restrict__ e, int64_t m_mul) {
+  prolong_body<G>(blockIdx.x, NAMG_MAT_VIEW(T), e, x);
 }
 
 template <class T>
@@ -698,10 +722,10 @@ __device__ __forceinline__ void update_x_body(uint32_t lb, const TZ *__restrict_
 // ------------------------------------------------------------------ single-problem Krylov kernels
 
 template <class TL>
-__global__ __launch_bounds__(BLK) void k_residual64(MatView<double> A, const double *__restrict__ b,
+__global__ __launch_bounds__(BLK) void k_residual64(NAMG_MAT_HEAD(double), const double *__restrict__ b,
                                                     const double *__restrict__ x, double *__restrict__ r,
-                                                    TL *__restrict__ rlow, double *__restrict__ partial) {
-  residual64_body(blockIdx.x, A, b, x, r, rlow, partial);
+                                                    TL *__restrict__ rlow, double *__restrict__ partial, int64_t m_mul) {
+  residual64_body(blockIdx.x, NAMG_MAT_VIEW(double), b, x, r, rlow, partial);
 }
 
 __global__ __launch_bounds__(BLK) void k_sumsq(const double *__restrict__ x, int32_t n, double *__restrict__ partial) {

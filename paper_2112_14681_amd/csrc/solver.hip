@@ -83,6 +83,13 @@ template <class T>
 auto sel_prolong(int g) { NAMG_GROUP_SWITCH(k_prolong, T) }
 #undef NAMG_GROUP_SWITCH
 
+// The leading kernel arguments of a sparse operator (see NAMG_MAT_HEAD in kernels.hpp).
+template <class T>
+const void *mat_idx(const MatView<T> &M) {
+  return M.col16 ? static_cast<const void *>(M.col16) : static_cast<const void *>(M.col);
+}
+#define NAMG_HEAD_ARGS(M) (M).ptr, mat_idx(M), (M).val, (M).nrows, (int32_t)((M).col16 != nullptr)
+
 template <class T>
 unsigned rows_grid(const DMat<T> &M) {
   return row_blocks(M.nrows, M.group, (int)sizeof(T));
@@ -230,8 +237,9 @@ class Solver final : public SolverBase {
     if (!in1) throw SetupError{NAMG_E_INVALID, "missing operand"};
     if (op == NAMG_OP_SPMV64) {
       if (level != 0) throw SetupError{NAMG_E_INVALID, "SPMV64 is defined on level 0 only"};
+      const MatView<double> M = A64_.view();
       launch(NAMG_KF_GMRES_SPMV, 0, A64_.bytes() + 16.0 * A64_.nrows, sel_spmv<double, double, double, double>(1),
-             rows_grid(A64_), s, A64_.view(), in1, out, (const double *)nullptr, (double *)nullptr);
+             rows_grid(A64_), s, NAMG_HEAD_ARGS(M), in1, (const double *)nullptr, out, (double *)nullptr, M.mul);
       return;
     }
     if (op == NAMG_OP_COARSE) {
@@ -252,8 +260,11 @@ class Solver final : public SolverBase {
     switch (op) {
       case NAMG_OP_SPMV:
         cast(in1, d.x.get(), n, s);
+      {
+        const MatView<T> M = d.A.view();
         launch(NAMG_KF_SPMV, level, d.A.bytes() + 2 * S * n, sel_spmv<T, T, T, T>(d.A.group), rows_grid(d.A), s,
-               d.A.view(), (const T *)d.x.get(), d.b.get(), (const T *)nullptr, (T *)nullptr);
+               NAMG_HEAD_ARGS(M), (const T *)d.x.get(), (const T *)nullptr, d.b.get(), (T *)nullptr, M.mul);
+      }
         cast(d.b.get(), out, n, s);
         break;
       case NAMG_OP_RESIDUAL:
@@ -307,6 +318,7 @@ class Solver final : public SolverBase {
     T *Z = Z_.get();
     double *w = w_.get();
     T *vin = std::is_same<T, double>::value ? nullptr : vin_.get();
+    const MatView<double> M64 = A64_.view();
 
     const double beta = std::sqrt(norm2sq(b, n, s));
     namg_solve_stats st{};
@@ -318,8 +330,8 @@ class Solver final : public SolverBase {
     } else {
       while (true) {
         // true residual r = b - A x into V(:,0) (FP64), plus the FP32 copy for the V-cycle
-        launch(-1, 0, A64_.bytes() + 24.0 * n + (vin ? S * n : 0.0), &k_residual64<T>, blocks_for(n), s, A64_.view(),
-               b, (const double *)x, V, vin, red_.get());
+        launch(-1, 0, A64_.bytes() + 24.0 * n + (vin ? S * n : 0.0), &k_residual64<T>, blocks_for(n), s,
+               NAMG_HEAD_ARGS(M64), b, (const double *)x, V, vin, red_.get(), M64.mul);
         rn = std::sqrt(reduce_read(red_.get(), nblk_red_, s));
         if (!std::isfinite(rn)) throw SetupError{NAMG_E_NONFINITE, "non-finite residual"};
         if (trace) std::fprintf(stderr, "[namg] cycle %d true relres %.3e\n", st.cycles, rn / beta);
@@ -347,7 +359,8 @@ class Solver final : public SolverBase {
           vcycle(0, b0, zi, o, s);
           st.precond_apps++;
           launch(NAMG_KF_GMRES_SPMV, 0, A64_.bytes() + (S + 8.0) * n, sel_spmv<double, double, T, double>(1),
-                 rows_grid(A64_), s, A64_.view(), (const T *)zi, w, (const double *)nullptr, (double *)nullptr);
+                 rows_grid(A64_), s, NAMG_HEAD_ARGS(M64), (const T *)zi, (const double *)nullptr, w, (double *)nullptr,
+                 M64.mul);
           const int32_t ncols = i + 1;
           launch(NAMG_KF_MULTIDOT, 0, 8.0 * n * (ncols + 1), &k_multidot<8>, nblk_dot_, s, (const double *)V, ldv_,
                  ncols, (const double *)w, n, rows_per_dot_, dot_.get(), nblk_dot_);
@@ -524,16 +537,20 @@ class Solver final : public SolverBase {
     const RowTask<T> &t = op.t;
     switch (op.kind) {
       case ROP_RESIDUAL:
-        launch(op.family, op.level, op.bytes, sel_residual<T>(op.group), op.grid, s, t.M, t.a, t.b, t.c, t.o0, t.o1);
+        launch(op.family, op.level, op.bytes, sel_residual<T>(op.group), op.grid, s, NAMG_HEAD_ARGS(t.M), t.a, t.c, t.b,
+               t.o0, t.o1, t.M.mul);
         break;
       case ROP_NEUMANN:
-        launch(op.family, op.level, op.bytes, sel_neumann<T>(op.group), op.grid, s, t.M, t.a, t.b, t.c, t.d, t.o0);
+        launch(op.family, op.level, op.bytes, sel_neumann<T>(op.group), op.grid, s, NAMG_HEAD_ARGS(t.M), t.a, t.c, t.d,
+               t.b, t.o0, t.M.mul);
         break;
       case ROP_SPMV:
-        launch(op.family, op.level, op.bytes, sel_spmv<T, T, T, T>(op.group), op.grid, s, t.M, t.b, t.o0, t.c, t.o1);
+        launch(op.family, op.level, op.bytes, sel_spmv<T, T, T, T>(op.group), op.grid, s, NAMG_HEAD_ARGS(t.M), t.b, t.c,
+               t.o0, t.o1, t.M.mul);
         break;
       case ROP_PROLONG:
-        launch(op.family, op.level, op.bytes, sel_prolong<T>(op.group), op.grid, s, t.M, t.b, t.o0);
+        launch(op.family, op.level, op.bytes, sel_prolong<T>(op.group), op.grid, s, NAMG_HEAD_ARGS(t.M), t.o0, t.b,
+               t.M.mul);
         break;
       case ROP_AXPY:
         launch(op.family, op.level, op.bytes, &k_axpy<T>, op.grid, s, t.a, t.c, t.d, t.o0, t.n);
