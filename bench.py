@@ -46,8 +46,8 @@ def _args():
 
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
-PROFILE_EVERY = 9  # dominant-kernel dispatches carrying timing events: the first, then every 9th (coprime
-# with the 8 launches per V-cycle, so the sample visits every position of the launch pattern)
+PROFILE_EVERY = 3  # time every 3rd run of consecutive dominant-kernel dispatches (one event pair per run;
+# odd, so pre- and post-smoothing runs alternate in the sample)
 
 # Measured HBM traffic of the dominant kernel (bytes per launch): rocprofv3 FETCH_SIZE x 2.000 plus
 # WRITE_SIZE x 1.000, factors from a 2 GiB copy (profiles/k_neumann_level0_c2_128cubed_traffic.md).
@@ -212,9 +212,10 @@ def main():
     dev = torch.device("cuda:0")
     bt = torch.from_numpy(b).to(dev)
     xt = torch.zeros_like(bt)
-    # the dominant kernel: the Neumann inner term on the finest level (ILU(0) triangles), timed live with
-    # start/stop events attached to a sample of its dispatches (the first, then every PROFILE_EVERY-th)
-    # during the timed solves; the sampling keeps the events' own cost out of the timed work
+    # the dominant kernel: the Neumann inner term on the finest level (ILU(0) triangles), timed live during
+    # the timed solves: a run of its consecutive dispatches (the four terms of one smoothing sweep) gets
+    # one start event on its first dispatch and one stop event after its last, so the events' own cost is
+    # spread over the run; every PROFILE_EVERY-th run is timed
     dom_family, dom_level = namg.KF_NEUMANN, 0
     for _ in range(args.warmup):
         xt.zero_()
@@ -266,7 +267,8 @@ def main():
                                                                   args.smoother)),
                            "kernel": f"k_neumann<1,{'double' if prec == namg.FP64 else 'float'}> on level 0 "
                                      f"({'ILU(0)' if args.smoother == 'ilu0' else 'poly-GS'} Neumann term)",
-                           "launches_timed": prof["launches"], "sampled_every": PROFILE_EVERY,
+                           "launches_timed": prof["launches"],
+                           "timing": f"hipEvents around every {PROFILE_EVERY}th run of consecutive dispatches",
                            "avg_us": round(per_launch_ms * 1e3, 3),
                            "alg_MB_per_launch": round(per_launch_bytes / 1e6, 3)}
     out["copy_ceiling_GBps"] = round(copy_ceiling(torch), 1)

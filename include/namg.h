@@ -149,10 +149,12 @@ typedef struct {
   double alg_bytes; /* sum of their algorithmic HBM bytes */
 } namg_kernel_profile;
 
-/* Time later launches of one kernel family (on one level, or -1 for all levels) with start/stop events
- * attached to the dispatch on its stream: the first matching launch and then every `every`-th one
- * (every >= 1; sampling keeps the events' own cost out of the timed work). Results accumulate until
- * namg_profile_read, which returns and clears them. family NAMG_KF_NONE switches timing off. */
+/* Time later launches of one kernel family (on one level, or -1 for all levels). Timing works on runs:
+ * a maximal sequence of consecutive launches of the family on one stream gets a start event on its first
+ * dispatch and a stop event after its last; the first run and then every `every`-th run are timed
+ * (every >= 1). namg_profile_read returns the timed launches, their summed run times (so total_ms /
+ * launches is the average launch duration, the events' own cost spread over each run) and their
+ * algorithmic bytes, and clears them. family NAMG_KF_NONE switches timing off. */
 int namg_profile_kernel(namg_hier *h, int family, int level, int every);
 int namg_profile_read(namg_hier *h, namg_kernel_profile *out);
 

@@ -405,37 +405,67 @@ class Solver final : public SolverBase {
   }
 
  private:
-  // Launch a kernel of BLK threads per block. family/level select the launches that the profiler
-  // times (start/stop events attached to the dispatch); bytes are the launch's algorithmic HBM bytes.
+  // Launch a kernel of BLK threads per block; bytes are the launch's algorithmic HBM bytes. family/level
+  // select the launches the profiler times. It times runs: a maximal sequence of consecutive launches of
+  // the selected family (for instance the four Neumann terms of one smoothing sweep) carries one start
+  // event, attached to its first dispatch, and one stop event, recorded on the stream when the next other
+  // kernel is issued; every prof_every_-th run is timed. The run's time over its launch count is the
+  // average launch duration, with the events' own cost spread over the run.
   template <class Kernel, class... Args>
   void launch(int family, int level, double bytes, Kernel kernel, unsigned grid, hipStream_t s, Args... args) {
     if (grid == 0) return;
     alg_ += bytes;
-    if (family >= 0 && family == prof_family_ && (prof_level_ < 0 || prof_level_ == level) &&
-        prof_seen_++ % prof_every_ == 0) {
-      if (ev_used_ == events_.size()) {
-        hipEvent_t a, b;
-        hip_check(hipEventCreate(&a), "hipEventCreate");
-        hip_check(hipEventCreate(&b), "hipEventCreate");
-        events_.push_back({a, b});
+    const bool selected = family >= 0 && family == prof_family_ && (prof_level_ < 0 || prof_level_ == level);
+    if (!selected) {
+      end_run();
+    } else if (!in_run_) {
+      in_run_ = true;
+      run_timed_ = prof_seen_++ % prof_every_ == 0;
+      if (run_timed_) {
+        auto &ev = next_events();
+        run_stream_ = s;
+        prof_.launches++;
+        prof_.alg_bytes += bytes;
+        hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(BLK), 0, s, ev.first, (hipEvent_t) nullptr, 0, args...);
+        hip_check(hipGetLastError(), "kernel launch");
+        return;
       }
-      auto &ev = events_[ev_used_++];
-      hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(BLK), 0, s, ev.first, ev.second, 0, args...);
+    } else if (run_timed_) {
       prof_.launches++;
       prof_.alg_bytes += bytes;
-    } else {
-      hipLaunchKernelGGL(kernel, dim3(grid), dim3(BLK), 0, s, args...);
     }
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(BLK), 0, s, args...);
     hip_check(hipGetLastError(), "kernel launch");
+  }
+
+  // Close the open profiler run: its stop event follows the run's last launch on its stream.
+  void end_run() {
+    if (!in_run_) return;
+    if (run_timed_) hip_check(hipEventRecord(events_[ev_used_ - 1].second, run_stream_), "hipEventRecord");
+    in_run_ = false;
+    run_timed_ = false;
+  }
+
+  // The next free start/stop event pair of the kernel profiler.
+  std::pair<hipEvent_t, hipEvent_t> &next_events() {
+    if (ev_used_ == events_.size()) {
+      hipEvent_t a, b;
+      hip_check(hipEventCreate(&a), "hipEventCreate");
+      hip_check(hipEventCreate(&b), "hipEventCreate");
+      events_.push_back({a, b});
+    }
+    return events_[ev_used_++];
   }
 
   template <class Kernel, class... Args>
   void launch_small(Kernel kernel, hipStream_t s, Args... args) {
+    end_run();
     hipLaunchKernelGGL(kernel, dim3(1), dim3(BLK), 0, s, args...);
     hip_check(hipGetLastError(), "kernel launch");
   }
 
   void flush_profile() {
+    end_run();
     if (ev_used_ == 0) return;
     for (size_t q = 0; q < ev_used_; ++q) {
       hip_check(hipEventSynchronize(events_[q].second), "hipEventSynchronize");
@@ -659,6 +689,7 @@ class Solver final : public SolverBase {
       hip_check(inst_err, "hipGraphInstantiate");
       it = tri_graphs_.emplace(key, exec).first;
     }
+    end_run();
     hip_check(hipGraphLaunch(it->second, s), "hipGraphLaunch");
   }
 
@@ -799,6 +830,8 @@ class Solver final : public SolverBase {
   double alg_ = 0.0;
   int prof_family_ = NAMG_KF_NONE, prof_level_ = -1, prof_every_ = 1;
   int64_t prof_seen_ = 0;
+  bool in_run_ = false, run_timed_ = false;
+  hipStream_t run_stream_ = nullptr;
   namg_kernel_profile prof_{0, 0.0, 0.0};
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events_;
   size_t ev_used_ = 0;

@@ -268,6 +268,24 @@ def test_edge_cases(namg):
     _check_solve(namg, A, b, namg.Hierarchy(A, device=0), O.Hierarchy(A), smoother=1, inner_terms=3)
 
 
+def test_kernel_profiler_runs(namg):
+    """namg_profile_kernel times runs of consecutive launches of one family: with the ILU(0) sweep
+    (t = 3) every V-cycle issues the four Neumann terms of the finest level twice in a row (pre and post),
+    so timing every run counts 8 launches per preconditioner application, every second run 4."""
+    A, b, _ = config_system("c2", 24)
+    H = namg.Hierarchy(A, device=0)
+    for every, per_app in ((1, 8), (2, 4)):
+        H.profile_kernel(namg.KF_NEUMANN, 0, every)
+        st = H.solve(dev(b), dev(np.zeros(A.n)), smoother=1, inner_terms=3)
+        p = H.profile_read()
+        H.profile_kernel(namg.KF_NONE)
+        assert st["status"] == namg.OK
+        assert p["launches"] == per_app * st["precond_apps"], (every, p, st["precond_apps"])
+        assert p["total_ms"] > 0.0 and p["alg_bytes"] > 0.0
+    with pytest.raises(namg.NamgError):
+        H.profile_kernel(namg.KF_NEUMANN, 0, 0)
+
+
 def test_deterministic_bitwise(namg):
     A, b, _ = config_system("c2", 24)
     H = namg.Hierarchy(A, device=0)
