@@ -37,7 +37,7 @@ def build(force: bool = False) -> str:
 class Params(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int), ("max_iters", C.c_int), ("precond", C.c_int),
                 ("smoother", C.c_int), ("tri_mode", C.c_int), ("inner_terms", C.c_int), ("gmres_T", C.c_int),
-                ("pre_sweeps", C.c_int), ("post_sweeps", C.c_int)]
+                ("pre_sweeps", C.c_int), ("post_sweeps", C.c_int), ("t_degree", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -185,9 +185,9 @@ class Hierarchy:
 
     def solve(self, b, x0=None, tol=1e-8, restart=30, max_iters=1000, precond=PRECOND_AMG,
               smoother=SMOOTH_PGS, tri_mode=TRI_NEUMANN, t=2, gmres_T=T_NEUMANN, nu1=1, nu2=1,
-              capture=False):
+              capture=False, t_degree=1):
         x = np.zeros(self.n) if x0 is None else _f64(x0).copy()
-        p = Params(tol, restart, max_iters, precond, smoother, tri_mode, t, gmres_T, nu1, nu2)
+        p = Params(tol, restart, max_iters, precond, smoother, tri_mode, t, gmres_T, nu1, nu2, t_degree)
         st = Stats()
         cap = 4096
         hist = np.zeros(cap)

@@ -670,14 +670,22 @@ int fgmres(Hierarchy *Hh, const Csr &A, const std::vector<double> &b, std::vecto
           Lm[i] = Lrow;
           for (int j = 0; j < i; ++j) qv[j] = d[j] / rho;
           qv[i] = (d[i] / rho) / rho;
-          for (int j = 0; j <= i; ++j) {
-            double acc = qv[j];
-            if (p.gmres_T == ORC_T_DIRECT) {  // (I + L) s = q
+          if (p.gmres_T == ORC_T_DIRECT) {  // (I + L) s = q by forward substitution
+            for (int j = 0; j <= i; ++j) {
+              double acc = qv[j];
               for (int l = 0; l < j; ++l) acc -= Lm[j][l] * s[l];
-            } else {  // s = (I - L) q
-              for (int l = 0; l < j; ++l) acc -= Lm[j][l] * qv[l];
+              s[j] = acc;
             }
-            s[j] = acc;
+          } else {  // s = sum_{j=0..p} (-L)^j q, by Horner: s <- q, then p times s <- q - L s
+            std::vector<double> prev = qv;
+            for (int deg = 0; deg < p.t_degree; ++deg) {
+              for (int j = 0; j <= i; ++j) {
+                double acc = qv[j];
+                for (int l = 0; l < j; ++l) acc -= Lm[j][l] * prev[l];
+                s[j] = acc;
+              }
+              prev = s;
+            }
           }
           std::vector<double> vn(n);
           for (int q = 0; q < n; ++q) {
@@ -881,7 +889,8 @@ int orc_solve(void *h, const double *b, double *x, const orc_params *p, orc_stat
               double *cap_Z, double *cap_H, int *cap_k) {
   return guarded([&]() -> int {
     auto *H = static_cast<Hierarchy *>(h);
-    if (!(p->tol > 0.0) || p->restart < 1 || p->max_iters < 0 || p->inner_terms < 1) return (int)ORC_E_INVALID;
+    if (!(p->tol > 0.0) || p->restart < 1 || p->max_iters < 0 || p->inner_terms < 1 || p->t_degree < 1)
+      return (int)ORC_E_INVALID;
     const Csr &A = H->lv[0].A;
     const int n = A.nr;
     std::vector<double> bv(b, b + n), xv(x, x + n), hv, cv;

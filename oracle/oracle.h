@@ -39,6 +39,7 @@ typedef struct {
   int inner_terms;/* t >= 1: number of Neumann terms */
   int gmres_T;    /* ORC_T_* */
   int pre_sweeps, post_sweeps;
+  int t_degree;   /* p >= 1: T = sum_{j=0..p} (-L)^j when gmres_T == ORC_T_NEUMANN (p = 1: I - L) */
 } orc_params;
 
 typedef struct {

@@ -399,6 +399,48 @@ def test_T_neumann_matches_T_direct(oracle_lib):
     assert a["relres_true"] <= 1e-8
 
 
+def _ill_conditioned_dense(n=60, seed=7):
+    """A dense nonsymmetric matrix with singular values logspace(0, 8): unpreconditioned GMRES loses
+    orthogonality quickly on it, so the lower triangle L of the low-sync step is far from negligible."""
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    W, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = (U * np.logspace(0, 8, n)) @ W.T
+    return CSR.from_dense(A), rng.standard_normal(n)
+
+
+def test_t_degree_one_is_I_minus_L(oracle_lib):
+    """Degree p = 1 of T = sum_{j<=p} (-L)^j is the default T = I - L, bit for bit."""
+    O = oracle_lib
+    A, b, _ = __import__("workloads").config_system("c1")
+    H = O.Hierarchy(A)
+    a = H.solve(b, t=2)
+    c = H.solve(b, t=2, t_degree=1)
+    assert a["iters"] == c["iters"] and np.array_equal(a["x"], c["x"])
+
+
+def test_t_degree_truncation_error(oracle_lib):
+    """Section 1: T = sum_{j<=p} (-L)^j truncates the Neumann series of (I + L)^{-1}, with an error of
+    order ||L||^(p+1). Where L is far from negligible (loss of orthogonality near 1 after 60 steps),
+    p = 1 differs visibly from the exact (I + L)^{-1}, p = 2 already agrees to rounding, and p >= the
+    step count is exact because L is nilpotent."""
+    O = oracle_lib
+    A, b = _ill_conditioned_dense()
+    H = O.Hierarchy(A, max_coarse=A.n + 1)
+    kw = dict(precond=O.PRECOND_NONE, restart=60, max_iters=60, tol=1e-14, capture=True)
+    d = H.solve(b, gmres_T=O.T_DIRECT, **kw)
+    assert O.loss_orth(d["V"]) > 0.5
+    err = {}
+    for p in (1, 2, 3, 60):
+        r = H.solve(b, gmres_T=O.T_NEUMANN, t_degree=p, **kw)
+        assert r["iters"] == d["iters"]
+        err[p] = np.linalg.norm(r["x"] - d["x"]) / np.linalg.norm(d["x"])
+    assert err[1] > 1e-12
+    assert err[2] <= 1e-14 and err[3] <= 1e-14 and err[60] <= 1e-14
+    with pytest.raises(O.OracleFailure):
+        H.solve(b, t_degree=0)
+
+
 def test_lucky_breakdown_on_eigenvector(oracle_lib):
     O = oracle_lib
     N = 7
