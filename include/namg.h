@@ -70,6 +70,8 @@ typedef struct {
                       strict triangle); default 2 */
   int gmres_T;     /* NAMG_T_NEUMANN: T = I - L (Section 4); NAMG_T_DIRECT: T = (I + L)^{-1} */
   int pre_sweeps, post_sweeps; /* smoothing sweeps nu1, nu2 per level; default 1, 1 */
+  int t_degree;    /* with NAMG_T_NEUMANN: T = sum_{j=0..p} (-L)^j, the Neumann series of (I + L)^{-1}
+                      truncated at degree p (Section 1); 1 <= p <= NAMG_MAX_RESTART, default 1 (I - L) */
 } namg_solve_params;
 
 typedef struct {

@@ -43,7 +43,7 @@ class SetupParams(C.Structure):
 class SolveParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int), ("max_iters", C.c_int), ("smoother", C.c_int),
                 ("tri_mode", C.c_int), ("inner_terms", C.c_int), ("gmres_T", C.c_int), ("pre_sweeps", C.c_int),
-                ("post_sweeps", C.c_int)]
+                ("post_sweeps", C.c_int), ("t_degree", C.c_int)]
 
 
 class SolveStats(C.Structure):

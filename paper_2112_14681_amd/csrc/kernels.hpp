@@ -622,10 +622,12 @@ __device__ __forceinline__ void finish_body(KState *__restrict__ st, const doubl
 // Small dense part of Arnoldi step i (0-based: columns 0..i of V are V_{i+1}), one workgroup, after the
 // column completion has set rho = ||v_{i+1}||. cd holds the fused reduction's inner products
 // c_j = cd[j] (j < i) and d_j = cd[i + 1 + j] (j <= i). New row of L: c_j / rho; q: d_j / rho, the last
-// one d_i / rho^2; s = T q with T = I - L (Neumann) or T = (I + L)^{-1} (forward substitution).
+// one d_i / rho^2; s = T q. t_mode 0: T = (I + L)^{-1} by forward substitution; t_mode p >= 1:
+// T = sum_{j=0..p} (-L)^j, the Neumann series truncated at degree p (Section 1), by Horner (s <- q, then
+// p times s <- q - L s); p = 1 is T = I - L.
 __device__ __forceinline__ void step_body(KState *__restrict__ st, const double *__restrict__ cd, int32_t i,
-                                          int32_t t_direct) {
-  __shared__ double c[KS_LD], q[KS_LD], s[KS_LD];
+                                          int32_t t_mode) {
+  __shared__ double c[KS_LD], q[KS_LD], s[KS_LD], u[KS_LD];
   const double ri = 1.0 / st->rho;
   for (int j = threadIdx.x; j <= i; j += BLK) {
     const double dj = cd[i + 1 + j];
@@ -638,15 +640,23 @@ __device__ __forceinline__ void step_body(KState *__restrict__ st, const double 
     }
   }
   __syncthreads();
-  if (!t_direct) {
-    // s = (I - L) q: one matrix-vector product (row i of L read from c, it is being written)
-    for (int j = threadIdx.x; j <= i; j += BLK) {
-      double a = q[j];
-      for (int l = 0; l < j; ++l) {
-        const double Ljl = (j == i) ? c[l] * ri : st->L[(int64_t)j * KS_LD + l];
-        a -= Ljl * q[l];
+  if (t_mode > 0) {
+    // Horner steps s <- q - L s from s = q (row i of L is read from c: it is being written)
+    for (int deg = 0; deg < t_mode; ++deg) {
+      const double *prev = deg == 0 ? q : u;
+      for (int j = threadIdx.x; j <= i; j += BLK) {
+        double a = q[j];
+        for (int l = 0; l < j; ++l) {
+          const double Ljl = (j == i) ? c[l] * ri : st->L[(int64_t)j * KS_LD + l];
+          a -= Ljl * prev[l];
+        }
+        s[j] = a;
       }
-      s[j] = a;
+      __syncthreads();
+      if (deg + 1 < t_mode) {
+        for (int j = threadIdx.x; j <= i; j += BLK) u[j] = s[j];
+        __syncthreads();
+      }
     }
   } else {
     // (I + L) s = q by column-oriented forward substitution
@@ -754,8 +764,8 @@ __global__ __launch_bounds__(BLK) void k_finish(KState *__restrict__ st, const d
 }
 
 __global__ __launch_bounds__(BLK) void k_step(KState *__restrict__ st, const double *__restrict__ cd, int32_t i,
-                                              int32_t t_direct) {
-  step_body(st, cd, i, t_direct);
+                                              int32_t t_mode) {
+  step_body(st, cd, i, t_mode);
 }
 
 template <class TL>
@@ -848,7 +858,7 @@ struct KTask {
 
 template <int OP, class T>
 __global__ __launch_bounds__(BLK) void kb_krylov(const KTask<T> *__restrict__ tasks, const uint32_t *__restrict__ off,
-                                                 int ntasks, int32_t t_direct, double tol) {
+                                                 int ntasks, int32_t t_mode, double tol) {
   uint32_t lb;
   const KTask<T> &t = tasks[find_task(off, ntasks, lb)];
   if constexpr (OP == KOP_RESIDUAL64) residual64_body(lb, t.A, t.b, t.x, t.V, t.vlow, t.partial);
@@ -858,7 +868,7 @@ __global__ __launch_bounds__(BLK) void kb_krylov(const KTask<T> *__restrict__ ta
     multidot_body<8>(lb, t.V, t.ldv, t.ncols, t.has_w ? t.w : (const double *)nullptr, t.n, t.rows_per_blk, t.partial,
                      t.nblk);
   if constexpr (OP == KOP_COLREDUCE) colreduce_body(lb, t.partial, t.nblk, t.cd);
-  if constexpr (OP == KOP_STEP) step_body(t.ks, t.cd, t.i, t_direct);
+  if constexpr (OP == KOP_STEP) step_body(t.ks, t.cd, t.i, t_mode);
   if constexpr (OP == KOP_PROJECT) project_body(lb, t.V, t.ldv, t.i, t.w, t.ks, t.n, t.vlow, t.partial);
   if constexpr (OP == KOP_FINISH) finish_body(t.ks, t.partial, t.nblk, t.i, t.last, tol, t.beta, t.host_out);
   if constexpr (OP == KOP_BACKSOLVE) backsolve_body(t.ks, t.k);

@@ -465,13 +465,12 @@ class BatchEngine {
     }
     std::memcpy(pinned_, stage_.data(), bytes);
     hip_check(hipMemcpyAsync(dbuf_, pinned_, bytes, hipMemcpyHostToDevice, s_), "hipMemcpyAsync");
-    const int t_direct = p_.gmres_T == NAMG_T_DIRECT ? 1 : 0;
+    const int32_t tm = t_mode(p_);
     for (const Group &gr : groups_) {
       const uint32_t *off = reinterpret_cast<const uint32_t *>(dbuf_ + gr.off_off);
       if (gr.krylov) {
         const KTask<T> *tasks = reinterpret_cast<const KTask<T> *>(dbuf_ + gr.task_off);
-        hipLaunchKernelGGL(krylov_kernel(gr.op), dim3(gr.grid), dim3(BLK), 0, s_, tasks, off, gr.ntasks, t_direct,
-                           p_.tol);
+        hipLaunchKernelGGL(krylov_kernel(gr.op), dim3(gr.grid), dim3(BLK), 0, s_, tasks, off, gr.ntasks, tm, p_.tol);
       } else {
         const RowTask<T> *tasks = reinterpret_cast<const RowTask<T> *>(dbuf_ + gr.task_off);
         hipLaunchKernelGGL(row_kernel(gr.op, gr.g), dim3(gr.grid), dim3(BLK), 0, s_, tasks, off, gr.ntasks);

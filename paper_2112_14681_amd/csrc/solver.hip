@@ -49,6 +49,10 @@ CycleOpts cycle_opts(const namg_solve_params &p) {
   return CycleOpts{p.smoother, p.tri_mode, p.inner_terms, p.pre_sweeps, p.post_sweeps};
 }
 
+// The correction T of the small dense step as the step kernels take it: 0 = (I + L)^{-1} by forward
+// substitution, p >= 1 = the Neumann series truncated at degree p.
+inline int32_t t_mode(const namg_solve_params &p) { return p.gmres_T == NAMG_T_DIRECT ? 0 : p.t_degree; }
+
 void validate_solve_params(const namg_solve_params &p) {
   if (!(p.tol > 0.0) || !std::isfinite(p.tol)) throw SetupError{NAMG_E_INVALID, "tol must be > 0"};
   if (p.restart < 1 || p.restart > NAMG_MAX_RESTART) throw SetupError{NAMG_E_INVALID, "restart out of range"};
@@ -60,6 +64,7 @@ void validate_solve_params(const namg_solve_params &p) {
     throw SetupError{NAMG_E_INVALID, "unknown tri_mode"};
   if (p.gmres_T != NAMG_T_NEUMANN && p.gmres_T != NAMG_T_DIRECT) throw SetupError{NAMG_E_INVALID, "unknown gmres_T"};
   if (p.pre_sweeps < 0 || p.post_sweeps < 0) throw SetupError{NAMG_E_INVALID, "negative sweep count"};
+  if (p.t_degree < 1 || p.t_degree > NAMG_MAX_RESTART) throw SetupError{NAMG_E_INVALID, "t_degree out of range"};
 }
 
 // One function pointer per lanes-per-row group for every row kernel.
@@ -365,7 +370,7 @@ class Solver final : public SolverBase {
           launch(NAMG_KF_MULTIDOT, 0, 8.0 * n * (ncols + 1), &k_multidot<8>, nblk_dot_, s, (const double *)V, ldv_,
                  ncols, (const double *)w, n, rows_per_dot_, dot_.get(), nblk_dot_);
           launch(-1, 0, 0.0, &k_colreduce, (unsigned)(2 * ncols), s, (const double *)dot_.get(), nblk_dot_, cd);
-          launch_small(&k_step, s, ks, (const double *)cd, i, (int)(p.gmres_T == NAMG_T_DIRECT));
+          launch_small(&k_step, s, ks, (const double *)cd, i, t_mode(p));
           launch(NAMG_KF_PROJECT, 0, 8.0 * n * (i + 4) + (vin ? S * n : 0.0), &k_project<T>, blocks_for(n), s, V,
                  ldv_, i, (const double *)w, (const KState *)ks, n, vin, red_.get());
           // column i is complete once ||v_{i+2}|| is known: estimate and stop test before the next V-cycle
@@ -901,6 +906,7 @@ void namg_default_solve_params(namg_solve_params *p) {
   p->gmres_T = NAMG_T_NEUMANN;
   p->pre_sweeps = 1;
   p->post_sweeps = 1;
+  p->t_degree = 1;
 }
 
 int namg_setup(int32_t n, const int32_t *rowptr, const int32_t *colind, const double *vals,

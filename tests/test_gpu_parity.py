@@ -159,7 +159,7 @@ def test_vcycle_matches_oracle(namg, smoother, tri, t):
 def _check_solve(namg, A, b, H, G, x0=None, xtol=1e-10, **kw):
     okw = dict(tol=kw.get("tol", 1e-8), restart=kw.get("restart", 30), max_iters=kw.get("max_iters", 1000),
                smoother=kw.get("smoother", 0), tri_mode=kw.get("tri_mode", 0), t=kw.get("inner_terms", 2),
-               gmres_T=kw.get("gmres_T", 0))
+               gmres_T=kw.get("gmres_T", 0), t_degree=kw.get("t_degree", 1))
     ref = G.solve(b, x0, **okw)
     xt = dev(np.zeros(A.n) if x0 is None else x0)
     st = H.solve(dev(b), xt, **kw)
@@ -181,6 +181,23 @@ def test_solve_c1_parity(namg, gmres_T, tri):
     A, b, _ = config_system("c1")
     _check_solve(namg, A, b, namg.Hierarchy(A, device=0), O.Hierarchy(A), smoother=0, tri_mode=tri,
                  inner_terms=2, gmres_T=gmres_T)
+
+
+@pytest.mark.parametrize("t_degree", [2, 3, 31])
+def test_solve_t_degree_parity(namg, t_degree):
+    """Degree-p T = sum_{j<=p} (-L)^j (Section 1) in the low-sync step: same iterations and iterate as the
+    oracle, on C1 and on C2 (20^3, ILU(0) hybrid), and through the serving engine (C1)."""
+    for name, N, kw in (("c1", None, dict(smoother=0, inner_terms=2)), ("c2", 20, dict(smoother=1, inner_terms=3))):
+        A, b, _ = config_system(name, N)
+        H, G = namg.Hierarchy(A, device=0), O.Hierarchy(A)
+        _check_solve(namg, A, b, H, G, gmres_T=0, t_degree=t_degree, **kw)
+    A, b, _ = config_system("c1")
+    srv = namg.Server(solve=dict(smoother=0, inner_terms=2, t_degree=t_degree), max_inflight=2, setup_threads=1,
+                      precision=0)
+    r = srv.wait(srv.submit(A, b))
+    srv.close()
+    ref = O.Hierarchy(A).solve(b, t=2, t_degree=t_degree)
+    assert r["iters"] == ref["iters"] and relerr(r["x"], ref["x"]) <= 1e-10
 
 
 @pytest.mark.parametrize("tri", [0, 1])
