@@ -17,11 +17,11 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "oracle.cpp")
 
 OK, NOT_CONVERGED, E_INVALID, E_ZERO_PIVOT, E_NONFINITE = 0, 1, -1, -2, -3
-SMOOTH_PGS, SMOOTH_ILU0 = 0, 1
+SMOOTH_PGS, SMOOTH_ILU0, SMOOTH_L1JAC = 0, 1, 2
 TRI_NEUMANN, TRI_DIRECT = 0, 1
 T_NEUMANN, T_DIRECT = 0, 1
 PRECOND_NONE, PRECOND_AMG = 0, 1
-PGS_FWD, PGS_BWD, GS_FWD, GS_BWD, ILU_NEUMANN, ILU_DIRECT = range(6)
+PGS_FWD, PGS_BWD, GS_FWD, GS_BWD, ILU_NEUMANN, ILU_DIRECT, L1_JACOBI = range(7)
 
 
 def build(force: bool = False) -> str:

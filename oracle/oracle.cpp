@@ -344,6 +344,21 @@ std::vector<double> ilu0(const Csr &A) {
 // ---------------------------------------------------------------------------------------------
 // Smoothers, one sweep each: x <- x + Mhat^{-1} (b - A x).
 
+// l1-Jacobi (the comparator of Section 6, Table 6): x <- x + D_l1^{-1} (b - A x), every row updated from
+// the previous x, with (D_l1)_ii = sum_j |a_ij|, the l1 norm of row i. (The l1 smoother adds to a_ii the
+// absolute couplings a row has outside its own block; on one device each row is taken as its own block,
+// which makes D_l1 - A positive semidefinite for symmetric A with positive diagonal.)
+void l1_jacobi(const Csr &A, const std::vector<double> &b, std::vector<double> &x) {
+  const int n = A.nr;
+  std::vector<double> r;
+  residual(A, b, x, r);
+  for (int i = 0; i < n; ++i) {
+    double d = 0.0;
+    for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) d += std::fabs(A.v[k]);
+    x[i] += r[i] / d;
+  }
+}
+
 // Polynomial Gauss-Seidel (Section 5.2): g^(0) = D^{-1} r, then t-1 Jacobi inner iterations
 // g^(j+1) = D^{-1}(r - L g^(j)) (forward) or with U (backward); every inner step uses the previous
 // iterate in full, so the sweep equals the truncated Neumann series sum_{j<t} (-D^{-1}L)^j D^{-1} r.
@@ -530,7 +545,8 @@ struct CycleOpts {
 // One V-cycle (Section 5; the cycle itself is the standard one the paper cites): zero initial guess,
 // nu1 pre-smoothing sweeps, residual, restriction by R, coarse correction, prolongation by P,
 // nu2 post-smoothing sweeps; the coarsest level is solved directly. ILU smoothing is used on the levels
-// that carry ILU factors (the hybrid V-cycle of Section 6.2) and polynomial GS elsewhere.
+// that carry ILU factors (the hybrid V-cycle of Section 6.2) and polynomial GS elsewhere; the l1-Jacobi
+// comparator smooths every level with l1-Jacobi.
 void vcycle(const Hierarchy &H, int l, const CycleOpts &o, const std::vector<double> &b,
             std::vector<double> &x) {
   const Level &L = H.lv[l];
@@ -542,7 +558,9 @@ void vcycle(const Hierarchy &H, int l, const CycleOpts &o, const std::vector<dou
   const bool direct = (o.tri_mode == ORC_TRI_DIRECT);
   x.assign(L.A.nr, 0.0);
   for (int s = 0; s < o.nu1; ++s) {
-    if (use_ilu)
+    if (o.smoother == ORC_SMOOTH_L1JAC)
+      l1_jacobi(L.A, b, x);
+    else if (use_ilu)
       direct ? ilu_direct(L.A, L.ilu, b, x) : ilu_neumann(L.A, L.ilu, b, x, o.t);
     else
       direct ? gs_direct(L.A, b, x, true) : pgs_neumann(L.A, b, x, o.t, true);
@@ -554,7 +572,9 @@ void vcycle(const Hierarchy &H, int l, const CycleOpts &o, const std::vector<dou
   spmv(L.P, ec, corr);
   for (int i = 0; i < L.A.nr; ++i) x[i] += corr[i];
   for (int s = 0; s < o.nu2; ++s) {
-    if (use_ilu)
+    if (o.smoother == ORC_SMOOTH_L1JAC)
+      l1_jacobi(L.A, b, x);
+    else if (use_ilu)
       direct ? ilu_direct(L.A, L.ilu, b, x) : ilu_neumann(L.A, L.ilu, b, x, o.t);
     else
       direct ? gs_direct(L.A, b, x, false) : pgs_neumann(L.A, b, x, o.t, false);
@@ -820,6 +840,7 @@ int orc_smooth(int n, const int *rp, const int *ci, const double *v, int kind, i
       case ORC_GS_BWD: gs_direct(A, bv, xv, false); break;
       case ORC_ILU_NEUMANN: ilu_neumann(A, ilu0(A), bv, xv, t); break;
       case ORC_ILU_DIRECT: ilu_direct(A, ilu0(A), bv, xv); break;
+      case ORC_L1_JACOBI: l1_jacobi(A, bv, xv); break;
       default: return (int)ORC_E_INVALID;
     }
     std::copy(xv.begin(), xv.end(), x);

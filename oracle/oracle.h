@@ -15,7 +15,7 @@ extern "C" {
 #endif
 
 enum { ORC_OK = 0, ORC_NOT_CONVERGED = 1, ORC_E_INVALID = -1, ORC_E_ZERO_PIVOT = -2, ORC_E_NONFINITE = -3 };
-enum { ORC_SMOOTH_PGS = 0, ORC_SMOOTH_ILU0 = 1 };
+enum { ORC_SMOOTH_PGS = 0, ORC_SMOOTH_ILU0 = 1, ORC_SMOOTH_L1JAC = 2 };
 enum { ORC_TRI_NEUMANN = 0, ORC_TRI_DIRECT = 1 };
 enum { ORC_T_NEUMANN = 0, ORC_T_DIRECT = 1 };
 enum { ORC_PRECOND_NONE = 0, ORC_PRECOND_AMG = 1 };
@@ -26,7 +26,8 @@ enum {
   ORC_GS_FWD = 2,      /* GS, forward substitution                           */
   ORC_GS_BWD = 3,      /* GS, backward substitution                          */
   ORC_ILU_NEUMANN = 4, /* ILU(0) with t-term Jacobi/Neumann triangular solves */
-  ORC_ILU_DIRECT = 5   /* ILU(0) with substitution                            */
+  ORC_ILU_DIRECT = 5,  /* ILU(0) with substitution                            */
+  ORC_L1_JACOBI = 6    /* l1-Jacobi: x += D_l1^{-1} (b - A x)                */
 };
 
 typedef struct {

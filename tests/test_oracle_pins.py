@@ -269,14 +269,50 @@ def test_one_level_hierarchy_is_direct_solve(oracle_lib):
     np.testing.assert_allclose(H.vcycle(b), np.linalg.solve(A.to_dense(), b), rtol=1e-13)
 
 
+def test_l1_jacobi_closed_forms(oracle_lib):
+    """l1-Jacobi, x <- x + D_l1^{-1}(b - A x) with (D_l1)_ii = sum_j |a_ij| (the Table 6 comparator):
+    one sweep from x = 0 on the 5-point Poisson matrix is x_i = b_i / (4 + number of neighbours of i);
+    on a positive diagonal matrix one sweep is the exact solve; repeated sweeps converge to A^{-1} b
+    (D_l1 - A is positive semidefinite for symmetric A with positive diagonal, so the iteration
+    contracts in the A-norm)."""
+    O = oracle_lib
+    N = 6
+    A = poisson2d(N)
+    b = np.random.default_rng(2).standard_normal(A.n)
+    x1 = O.smooth(A, O.L1_JACOBI, 1, b, np.zeros(A.n))
+    gx, gy = np.meshgrid(np.arange(N), np.arange(N), indexing="xy")
+    nb = (gx > 0).astype(int) + (gx < N - 1) + (gy > 0) + (gy < N - 1)
+    np.testing.assert_allclose(x1, b / (4.0 + nb.ravel()), rtol=1e-15)
+    dvals = np.linspace(1.0, 5.0, 9)
+    D = CSR.from_dense(np.diag(dvals))
+    np.testing.assert_allclose(O.smooth(D, O.L1_JACOBI, 1, dvals * 2.0, np.ones(9)), 2.0 * np.ones(9), rtol=1e-15)
+    xs = np.linalg.solve(A.to_dense(), b)
+    x = np.zeros(A.n)
+    errs = []
+    for _ in range(400):
+        x = O.smooth(A, O.L1_JACOBI, 1, b, x)
+        e = x - xs
+        errs.append(np.sqrt(e @ (A.to_dense() @ e)))
+    assert all(e2 <= e1 * (1 + 1e-12) for e1, e2 in zip(errs, errs[1:]))
+    np.testing.assert_allclose(x, xs, rtol=1e-8, atol=1e-10)
+
+
+def test_l1_jacobi_preconditioned_solve(oracle_lib):
+    O = oracle_lib
+    A, b, _ = __import__("workloads").config_system("c1")
+    r = O.Hierarchy(A).solve(b, smoother=O.SMOOTH_L1JAC)
+    assert r["status"] == 0 and r["relres_true"] <= 1e-8
+
+
 def _dense_op(f, n):
     return np.stack([f(e) for e in np.eye(n)], axis=1)
 
 
-@pytest.mark.parametrize("smoother,tri", [(0, 0), (0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("smoother,tri", [(0, 0), (0, 1), (1, 0), (1, 1), (2, 0)])
 def test_vcycle_linear_and_symmetric(oracle_lib, smoother, tri):
-    """The V-cycle is a linear operator; with forward pre- and backward post-smoothing (PGS) or the
-    ILU sweep (symmetric A gives U = D L^T) it is symmetric for symmetric A."""
+    """The V-cycle is a linear operator; with forward pre- and backward post-smoothing (PGS), the ILU
+    sweep (symmetric A gives U = D L^T) or l1-Jacobi (a symmetric smoother) it is symmetric for
+    symmetric A."""
     O = oracle_lib
     A = poisson2d(10)
     H = O.Hierarchy(A, ilu_levels=1)
