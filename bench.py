@@ -36,7 +36,8 @@ def _args():
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--gmres-T", default="neumann", choices=["neumann", "direct"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--compare", action="store_true", help="also time the direct-triangular and FP32 variants")
+    ap.add_argument("--compare", action="store_true",
+                    help="also time the direct-triangular, l1-Jacobi and FP32-preconditioner variants")
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests of the served stream to replay (0: skip; 2000: the whole stream)")
     ap.add_argument("--serve-inflight", type=int, default=64)
@@ -277,6 +278,7 @@ def main():
     if args.compare:
         cmp = {}
         for name, extra, prec2 in (("direct_tri", dict(tri_mode=namg.TRI_DIRECT), prec),
+                                   ("l1_jacobi", dict(smoother=namg.SMOOTH_L1JAC), prec),
                                    ("fp32_precond", {}, namg.FP32_PRECOND), ("fp64", {}, namg.FP64)):
             H2 = H if prec2 == prec else namg.Hierarchy(A, device=0, precision=prec2, ilu_levels=1)
             kw2 = dict(kw, **extra)

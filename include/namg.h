@@ -38,7 +38,7 @@ extern "C" {
 #define NAMG_E_NODEVICE (-7)   /* the hierarchy was set up host-only (device = -1) */
 
 enum { NAMG_FP64 = 0, NAMG_FP32_PRECOND = 1 };        /* namg_setup_params.precision */
-enum { NAMG_SMOOTH_PGS = 0, NAMG_SMOOTH_ILU0 = 1 };   /* namg_solve_params.smoother  */
+enum { NAMG_SMOOTH_PGS = 0, NAMG_SMOOTH_ILU0 = 1, NAMG_SMOOTH_L1JAC = 2 }; /* namg_solve_params.smoother */
 enum { NAMG_TRI_NEUMANN = 0, NAMG_TRI_DIRECT = 1 };   /* namg_solve_params.tri_mode  */
 enum { NAMG_T_NEUMANN = 0, NAMG_T_DIRECT = 1 };       /* namg_solve_params.gmres_T   */
 
@@ -62,8 +62,10 @@ typedef struct {
   double tol;      /* stop when ||b - A x||_2 / ||b||_2 <= tol (Section 4, eq. relres); default 1e-8 */
   int restart;     /* m, 1..NAMG_MAX_RESTART; default 30 */
   int max_iters;   /* total Arnoldi iterations over all cycles; default 1000 */
-  int smoother;    /* NAMG_SMOOTH_PGS (all levels) or NAMG_SMOOTH_ILU0 (ILU on the levels that carry
-                      factors, polynomial GS elsewhere) */
+  int smoother;    /* NAMG_SMOOTH_PGS (all levels), NAMG_SMOOTH_ILU0 (ILU on the levels that carry
+                      factors, polynomial GS elsewhere) or NAMG_SMOOTH_L1JAC (the l1-Jacobi comparator of
+                      Section 6, Table 6, on all levels: x += D_l1^{-1}(b - A x), (D_l1)_ii = sum_j |a_ij|;
+                      tri_mode and inner_terms do not apply) */
   int tri_mode;    /* NAMG_TRI_NEUMANN (Jacobi/Neumann inner iterations) or NAMG_TRI_DIRECT (the
                       direct-triangular comparators: GS and ILU by substitution) */
   int inner_terms; /* t >= 1: Neumann terms per triangular solve (t = 1: Jacobi; t - 1 products with the

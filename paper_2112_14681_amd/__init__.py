@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libnamg.so")
 OK, NOT_CONVERGED, PENDING = 0, 1, 2
 E_INVALID, E_ZERO_PIVOT, E_NONFINITE, E_NOMEM, E_HIP, E_BUDGET, E_NODEVICE = -1, -2, -3, -4, -5, -6, -7
 FP64, FP32_PRECOND = 0, 1
-SMOOTH_PGS, SMOOTH_ILU0 = 0, 1
+SMOOTH_PGS, SMOOTH_ILU0, SMOOTH_L1JAC = 0, 1, 2
 TRI_NEUMANN, TRI_DIRECT = 0, 1
 T_NEUMANN, T_DIRECT = 0, 1
 OP_SPMV, OP_RESIDUAL, OP_SMOOTH_PRE, OP_SMOOTH_POST, OP_RESTRICT, OP_PROLONG, OP_COARSE, OP_SPMV64 = range(8)

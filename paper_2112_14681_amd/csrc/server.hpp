@@ -50,7 +50,7 @@ int64_t solver_footprint(const HostHierarchy &H, int m) {
     total += 2 * S * n;
     if (l == nl - 1) break;
     total += mat_alloc_bytes<T>(h.A) + mat_alloc_bytes<T>(h.P) + mat_alloc_bytes<T>(h.R) + mat_alloc_bytes<T>(h.pgs_lo) +
-             mat_alloc_bytes<T>(h.pgs_up) + S * n + 4 * S * n;
+             mat_alloc_bytes<T>(h.pgs_up) + 2 * S * n + 4 * S * n;
     if (h.has_ilu) total += mat_alloc_bytes<T>(h.ilu_lo) + mat_alloc_bytes<T>(h.ilu_up) + S * n;
   }
   const int64_t nc = H.lv.back().A.nr;

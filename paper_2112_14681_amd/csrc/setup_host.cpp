@@ -450,6 +450,12 @@ void smoother_data(HostLevel &L, bool with_ilu) {
     if (d == 0.0) fail(NAMG_E_ZERO_PIVOT, "zero diagonal in row " + std::to_string(i));
     L.dinv[i] = 1.0 / d;
   }
+  L.dl1inv.resize(A.nr);
+  for (int32_t i = 0; i < A.nr; ++i) {
+    double d = 0.0;
+    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) d += std::fabs(A.v[k]);
+    L.dl1inv[i] = 1.0 / d;
+  }
   // D^{-1}L and D^{-1}U: a_ij / a_ii
   L.pgs_lo = strict_part(A, A.v, true, {});
   L.pgs_up = strict_part(A, A.v, false, {});

@@ -32,6 +32,7 @@ struct HostLevel {
   HostCsr A, P, R;
   std::vector<int8_t> cf;
   std::vector<double> dinv;    // 1 / a_ii
+  std::vector<double> dl1inv;  // 1 / sum_j |a_ij| (l1-Jacobi)
   HostCsr pgs_lo, pgs_up;      // D^{-1} L and D^{-1} U: strict parts of A scaled by the row's diagonal
   bool has_ilu = false;
   HostCsr ilu_lo, ilu_up;      // L_s (strict lower of the unit-diagonal L) and U_s = D_U^{-1} U - I

@@ -58,7 +58,7 @@ void validate_solve_params(const namg_solve_params &p) {
   if (p.restart < 1 || p.restart > NAMG_MAX_RESTART) throw SetupError{NAMG_E_INVALID, "restart out of range"};
   if (p.max_iters < 0) throw SetupError{NAMG_E_INVALID, "max_iters must be >= 0"};
   if (p.inner_terms < 1) throw SetupError{NAMG_E_INVALID, "inner_terms must be >= 1"};
-  if (p.smoother != NAMG_SMOOTH_PGS && p.smoother != NAMG_SMOOTH_ILU0)
+  if (p.smoother != NAMG_SMOOTH_PGS && p.smoother != NAMG_SMOOTH_ILU0 && p.smoother != NAMG_SMOOTH_L1JAC)
     throw SetupError{NAMG_E_INVALID, "unknown smoother"};
   if (p.tri_mode != NAMG_TRI_NEUMANN && p.tri_mode != NAMG_TRI_DIRECT)
     throw SetupError{NAMG_E_INVALID, "unknown tri_mode"};
@@ -120,7 +120,7 @@ template <class T>
 struct DevLevel {
   int32_t n = 0;
   DMat<T> A, P, R, pgs_lo, pgs_up, ilu_lo, ilu_up;
-  DevBuf<T> dinv, ilu_dinv;
+  DevBuf<T> dinv, dl1inv, ilu_dinv;
   bool has_ilu = false;
   DTri<T> tri_pgs_lo, tri_pgs_up, tri_ilu_lo, tri_ilu_up;
   DevBuf<T> b, x, r, f, g1, g2;
@@ -149,6 +149,7 @@ class Solver final : public SolverBase {
       d.pgs_lo.build(h.pgs_lo, &mc_);
       d.pgs_up.build(h.pgs_up, &mc_);
       upload_vec(d.dinv, h.dinv);
+      upload_vec(d.dl1inv, h.dl1inv);
       d.has_ilu = h.has_ilu;
       if (h.has_ilu) {
         d.ilu_lo.build(h.ilu_lo, &mc_);
@@ -635,6 +636,7 @@ class Solver final : public SolverBase {
   bool fused_f(int l, const CycleOpts &o) const {
     const int nl = (int)lv_.size();
     if (l < 1 || l + 1 >= nl || o.nu1 < 1) return false;
+    if (o.smoother == NAMG_SMOOTH_L1JAC) return false;
     return !((o.smoother == NAMG_SMOOTH_ILU0) && lv_[l].has_ilu);
   }
 
@@ -707,6 +709,16 @@ class Solver final : public SolverBase {
     const T *nul = nullptr;
     const int t = o.t;
     T *pp[2] = {d.g1.get(), d.g2.get()};
+    if (o.smoother == NAMG_SMOOTH_L1JAC) {
+      // l1-Jacobi (the Table 6 comparator): x <- x + D_l1^{-1}(b - A x); from x = 0 one pass x = D_l1^{-1} b
+      if (first) {
+        residual(l, b, nul, d.dl1inv.get(), nullptr, x, s);
+      } else {
+        residual(l, b, x, d.dl1inv.get(), nullptr, d.f.get(), s);
+        axpy(l, d.f.get(), nul, x, x, n, s);
+      }
+      return;
+    }
     if (!ilu) {
       // polynomial Gauss-Seidel (Section 5.2): f = D^{-1}(b - A x), g <- f - (D^{-1}L) g, x += g
       if (!f_ready) residual(l, b, first ? nul : (const T *)x, d.dinv.get(), nullptr, d.f.get(), s);

@@ -115,6 +115,27 @@ def test_single_sweeps(namg, c2_small, level, smoother, tri, t):
         assert relerr(host(out), ref) <= TOL64, (op, kind)
 
 
+def test_l1_jacobi_smoother(namg, c2_small):
+    """The l1-Jacobi comparator (Section 6, Table 6): single sweeps on three levels, whole V-cycles and
+    whole solves against the oracle."""
+    A, b, H = c2_small
+    rng = np.random.default_rng(21)
+    for level in (0, 1, 2):
+        Al, _ = level_csr(H, level)
+        x, bb = rng.standard_normal(Al.n), rng.standard_normal(Al.n)
+        out = torch.empty(Al.n, dtype=torch.float64, device="cuda:0")
+        for op in (namg.OP_SMOOTH_PRE, namg.OP_SMOOTH_POST):
+            H.apply(level, op, dev(x), dev(bb), out, smoother=namg.SMOOTH_L1JAC)
+            assert relerr(host(out), O.smooth(Al, O.L1_JACOBI, 1, bb, x)) <= TOL64, (level, op)
+    G = O.Hierarchy(A, ilu_levels=-1)
+    out = torch.empty(A.n, dtype=torch.float64, device="cuda:0")
+    H.vcycle(dev(b), out, smoother=namg.SMOOTH_L1JAC)
+    assert relerr(host(out), G.vcycle(b, smoother=O.SMOOTH_L1JAC)) <= TOL64
+    for name, N in (("c1", None), ("c2", 20)):
+        A2, b2, _ = config_system(name, N)
+        _check_solve(namg, A2, b2, namg.Hierarchy(A2, device=0), O.Hierarchy(A2), smoother=namg.SMOOTH_L1JAC)
+
+
 def test_direct_sweep_graph_replays(namg):
     """The direct comparators replay captured HIP graphs (one per triangle and operand pair): repeated
     sweeps, with eager work and synchronisations in between, each match the oracle and the first
