@@ -21,6 +21,7 @@ SMOOTH_PGS, SMOOTH_ILU0, SMOOTH_L1JAC = 0, 1, 2
 TRI_NEUMANN, TRI_DIRECT = 0, 1
 T_NEUMANN, T_DIRECT = 0, 1
 PRECOND_NONE, PRECOND_AMG = 0, 1
+STOP_RELRES, STOP_NRBE = 0, 1
 PGS_FWD, PGS_BWD, GS_FWD, GS_BWD, ILU_NEUMANN, ILU_DIRECT, L1_JACOBI = range(7)
 
 
@@ -37,7 +38,7 @@ def build(force: bool = False) -> str:
 class Params(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int), ("max_iters", C.c_int), ("precond", C.c_int),
                 ("smoother", C.c_int), ("tri_mode", C.c_int), ("inner_terms", C.c_int), ("gmres_T", C.c_int),
-                ("pre_sweeps", C.c_int), ("post_sweeps", C.c_int), ("t_degree", C.c_int)]
+                ("pre_sweeps", C.c_int), ("post_sweeps", C.c_int), ("t_degree", C.c_int), ("stop_rule", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -185,9 +186,9 @@ class Hierarchy:
 
     def solve(self, b, x0=None, tol=1e-8, restart=30, max_iters=1000, precond=PRECOND_AMG,
               smoother=SMOOTH_PGS, tri_mode=TRI_NEUMANN, t=2, gmres_T=T_NEUMANN, nu1=1, nu2=1,
-              capture=False, t_degree=1):
+              capture=False, t_degree=1, stop_rule=STOP_RELRES):
         x = np.zeros(self.n) if x0 is None else _f64(x0).copy()
-        p = Params(tol, restart, max_iters, precond, smoother, tri_mode, t, gmres_T, nu1, nu2, t_degree)
+        p = Params(tol, restart, max_iters, precond, smoother, tri_mode, t, gmres_T, nu1, nu2, t_degree, stop_rule)
         st = Stats()
         cap = 4096
         hist = np.zeros(cap)

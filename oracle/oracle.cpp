@@ -633,7 +633,10 @@ int fgmres(Hierarchy *Hh, const Csr &A, const std::vector<double> &b, std::vecto
     const double rn = norm2(r);
     if (!std::isfinite(rn)) throw OracleError{ORC_E_NONFINITE};
     cyc.push_back(rn / beta);
-    if (rn / beta <= p.tol) return finish(ORC_OK, rn);
+    // the stopping test's denominator: ||b|| (relative residual), or ||b|| + ||A||_inf ||x|| with the
+    // cycle's starting iterate (normwise relative backward error, Section 3)
+    const double denom = p.stop_rule == ORC_STOP_NRBE ? beta + anorm * norm2(x) : beta;
+    if (rn / denom <= p.tol) return finish(ORC_OK, rn);
     if (st.iters >= p.max_iters) return finish(ORC_NOT_CONVERGED, rn);
     st.cycles++;
     const int me = std::min(m, p.max_iters - st.iters);
@@ -742,7 +745,7 @@ int fgmres(Hierarchy *Hh, const Csr &A, const std::vector<double> &b, std::vecto
       hist.push_back(est);
       st.relres_est = est;
       k = i;
-      if (est <= p.tol || i == me || rho == 0.0) stop = true;
+      if (std::fabs(g[i]) / denom <= p.tol || i == me || rho == 0.0) stop = true;
     }
     // y from the rotated k x k triangle, then x += Z_k y (Algorithm 1, steps 14-15)
     std::vector<double> y(k, 0.0);
@@ -910,7 +913,8 @@ int orc_solve(void *h, const double *b, double *x, const orc_params *p, orc_stat
               double *cap_Z, double *cap_H, int *cap_k) {
   return guarded([&]() -> int {
     auto *H = static_cast<Hierarchy *>(h);
-    if (!(p->tol > 0.0) || p->restart < 1 || p->max_iters < 0 || p->inner_terms < 1 || p->t_degree < 1)
+    if (!(p->tol > 0.0) || p->restart < 1 || p->max_iters < 0 || p->inner_terms < 1 || p->t_degree < 1 ||
+        (p->stop_rule != ORC_STOP_RELRES && p->stop_rule != ORC_STOP_NRBE))
       return (int)ORC_E_INVALID;
     const Csr &A = H->lv[0].A;
     const int n = A.nr;

@@ -19,6 +19,7 @@ enum { ORC_SMOOTH_PGS = 0, ORC_SMOOTH_ILU0 = 1, ORC_SMOOTH_L1JAC = 2 };
 enum { ORC_TRI_NEUMANN = 0, ORC_TRI_DIRECT = 1 };
 enum { ORC_T_NEUMANN = 0, ORC_T_DIRECT = 1 };
 enum { ORC_PRECOND_NONE = 0, ORC_PRECOND_AMG = 1 };
+enum { ORC_STOP_RELRES = 0, ORC_STOP_NRBE = 1 };
 /* single-level smoother kinds for orc_smooth */
 enum {
   ORC_PGS_FWD = 0,     /* polynomial GS, forward (D+L), t Neumann terms      */
@@ -41,6 +42,7 @@ typedef struct {
   int gmres_T;    /* ORC_T_* */
   int pre_sweeps, post_sweeps;
   int t_degree;   /* p >= 1: T = sum_{j=0..p} (-L)^j when gmres_T == ORC_T_NEUMANN (p = 1: I - L) */
+  int stop_rule;  /* ORC_STOP_RELRES: ||r|| / ||b|| <= tol; ORC_STOP_NRBE: ||r|| / (||b|| + ||A||_inf ||x||) <= tol */
 } orc_params;
 
 typedef struct {

@@ -477,6 +477,36 @@ def test_t_degree_truncation_error(oracle_lib):
         H.solve(b, t_degree=0)
 
 
+def test_nrbe_stopping_rule(oracle_lib):
+    """Section 3: stopping on the normwise relative backward error ||r|| / (||b|| + ||A||_inf ||x||).
+    The solve ends with NRBE <= tol; since NRBE <= ||r|| / ||b|| at any x, the rule never takes more
+    iterations than the relative-residual rule. Inside a cycle the denominator uses the cycle's
+    starting iterate, so the first cycle (x0 = 0) stops where the relative-residual rule does; with
+    short restarts later cycles see ||A||_inf ||x|| >> ||b|| and stop strictly earlier. The rule
+    only changes when the iteration stops: its iterate equals the relative-residual run cut off at
+    the same iteration count."""
+    O = oracle_lib
+    A, b, _ = __import__("workloads").config_system("c1")
+    H = O.Hierarchy(A)
+    rel = H.solve(b, tol=1e-8, t=2)
+    nrbe = H.solve(b, tol=1e-8, t=2, stop_rule=O.STOP_NRBE)
+    assert nrbe["status"] == 0 and nrbe["nrbe"] <= 1e-8
+    Ad = A.to_dense()
+    r = b - Ad @ nrbe["x"]
+    direct = np.linalg.norm(r) / (np.linalg.norm(b) + np.abs(Ad).sum(axis=1).max() * np.linalg.norm(nrbe["x"]))
+    assert nrbe["nrbe"] == pytest.approx(direct, rel=1e-6)
+    assert nrbe["iters"] <= rel["iters"]
+    for rhs in (b, np.ones(A.n)):
+        short_rel = H.solve(rhs, tol=1e-8, t=2, restart=3)
+        short = H.solve(rhs, tol=1e-8, t=2, restart=3, stop_rule=O.STOP_NRBE)
+        assert short["status"] == 0 and short["iters"] < short_rel["iters"]
+        cut = H.solve(rhs, tol=1e-8, t=2, restart=3, max_iters=short["iters"])
+        assert cut["iters"] == short["iters"]
+        np.testing.assert_array_equal(cut["x"], short["x"])
+    with pytest.raises(O.OracleFailure):
+        H.solve(b, stop_rule=2)
+
+
 def test_lucky_breakdown_on_eigenvector(oracle_lib):
     O = oracle_lib
     N = 7
