@@ -41,6 +41,7 @@ enum { NAMG_FP64 = 0, NAMG_FP32_PRECOND = 1 };        /* namg_setup_params.preci
 enum { NAMG_SMOOTH_PGS = 0, NAMG_SMOOTH_ILU0 = 1, NAMG_SMOOTH_L1JAC = 2 }; /* namg_solve_params.smoother */
 enum { NAMG_TRI_NEUMANN = 0, NAMG_TRI_DIRECT = 1 };   /* namg_solve_params.tri_mode  */
 enum { NAMG_T_NEUMANN = 0, NAMG_T_DIRECT = 1 };       /* namg_solve_params.gmres_T   */
+enum { NAMG_STOP_RELRES = 0, NAMG_STOP_NRBE = 1 };    /* namg_solve_params.stop_rule */
 
 #define NAMG_MAX_LEVELS 32
 #define NAMG_MAX_RESTART 128
@@ -59,7 +60,7 @@ typedef struct {
 } namg_setup_params;
 
 typedef struct {
-  double tol;      /* stop when ||b - A x||_2 / ||b||_2 <= tol (Section 4, eq. relres); default 1e-8 */
+  double tol;      /* stop when the quantity stop_rule names is <= tol; default 1e-8 */
   int restart;     /* m, 1..NAMG_MAX_RESTART; default 30 */
   int max_iters;   /* total Arnoldi iterations over all cycles; default 1000 */
   int smoother;    /* NAMG_SMOOTH_PGS (all levels), NAMG_SMOOTH_ILU0 (ILU on the levels that carry
@@ -74,6 +75,11 @@ typedef struct {
   int pre_sweeps, post_sweeps; /* smoothing sweeps nu1, nu2 per level; default 1, 1 */
   int t_degree;    /* with NAMG_T_NEUMANN: T = sum_{j=0..p} (-L)^j, the Neumann series of (I + L)^{-1}
                       truncated at degree p (Section 1); 1 <= p <= NAMG_MAX_RESTART, default 1 (I - L) */
+  int stop_rule;   /* NAMG_STOP_RELRES (default): ||b - A x||_2 / ||b||_2 (Section 4); NAMG_STOP_NRBE: the
+                      normwise relative backward error ||b - A x||_2 / (||b||_2 + ||A||_inf ||x||_2) of
+                      Section 3. Inside a restart cycle the residual norm is the Arnoldi estimate and ||x||
+                      is that of the cycle's starting iterate (x is formed at the cycle's end); every cycle
+                      starts with the true residual. The rule changes only when the iteration stops. */
 } namg_solve_params;
 
 typedef struct {

@@ -21,6 +21,7 @@ FP64, FP32_PRECOND = 0, 1
 SMOOTH_PGS, SMOOTH_ILU0, SMOOTH_L1JAC = 0, 1, 2
 TRI_NEUMANN, TRI_DIRECT = 0, 1
 T_NEUMANN, T_DIRECT = 0, 1
+STOP_RELRES, STOP_NRBE = 0, 1
 OP_SPMV, OP_RESIDUAL, OP_SMOOTH_PRE, OP_SMOOTH_POST, OP_RESTRICT, OP_PROLONG, OP_COARSE, OP_SPMV64 = range(8)
 MAX_LEVELS = 32
 
@@ -43,7 +44,7 @@ class SetupParams(C.Structure):
 class SolveParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int), ("max_iters", C.c_int), ("smoother", C.c_int),
                 ("tri_mode", C.c_int), ("inner_terms", C.c_int), ("gmres_T", C.c_int), ("pre_sweeps", C.c_int),
-                ("post_sweeps", C.c_int), ("t_degree", C.c_int)]
+                ("post_sweeps", C.c_int), ("t_degree", C.c_int), ("stop_rule", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -147,17 +148,24 @@ def _ptr(a, ctype):
 def setup_params(**kw) -> SetupParams:
     p = SetupParams()
     _lib.namg_default_setup_params(C.byref(p))
-    for k, v in kw.items():
-        setattr(p, k, v)
+    _set_fields(p, kw)
     return p
 
 
 def solve_params(**kw) -> SolveParams:
     p = SolveParams()
     _lib.namg_default_solve_params(C.byref(p))
-    for k, v in kw.items():
-        setattr(p, k, v)
+    _set_fields(p, kw)
     return p
+
+
+def _set_fields(p, kw):
+    """Set named fields of a parameter struct; an unknown name is an error, not a silent attribute."""
+    names = {f[0] for f in type(p)._fields_}
+    for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"{type(p).__name__} has no field {k!r}")
+        setattr(p, k, v)
 
 
 def _dev_ptr(t, n=None):
@@ -265,10 +273,8 @@ class Hierarchy:
 def server_params(solve=None, **kw) -> ServerParams:
     p = ServerParams()
     _lib.namg_default_server_params(C.byref(p))
-    for k, v in kw.items():
-        setattr(p, k, v)
-    for k, v in (solve or {}).items():
-        setattr(p.solve, k, v)
+    _set_fields(p, kw)
+    _set_fields(p.solve, solve or {})
     return p
 
 

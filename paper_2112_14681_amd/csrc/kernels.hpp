@@ -572,11 +572,13 @@ inline int32_t dot_blocks(int64_t n) {
 // otherwise), so the column is finished without waiting for the next step's fused reduction.
 // rho = sqrt(c); i == 0: g_0 = rho. i >= 1: Hessenberg column i-1 = [s of step i-1; rho] gets the
 // previous Givens rotations and a new one, giving the residual estimate |g_i| / ||b|| (beta = ||b||).
-// The stop flag is raised on estimate <= tol, on the last column of the cycle, or on breakdown (rho == 0),
+// The stop flag is raised on |g_i| / denom <= tol (denom = ||b||, or ||b|| + ||A||_inf ||x_0|| for the
+// backward-error rule of Section 3), on the last column of the cycle, or on breakdown (rho == 0),
 // and set to -1 on a non-finite value; (est, flag) also go to host_out, host-mapped memory the host reads
 // after the stream synchronises.
 __device__ __forceinline__ void finish_body(KState *__restrict__ st, const double *__restrict__ partial, int32_t nblk,
-                                            int32_t i, int32_t last, double tol, double beta, double *host_out) {
+                                            int32_t i, int32_t last, double tol, double beta, double denom,
+                                            double *host_out) {
   __shared__ double lds[WAVES];
   const double t = block_sum(strided_sum(partial, nblk), lds);
   if (threadIdx.x != 0) return;
@@ -611,7 +613,7 @@ __device__ __forceinline__ void finish_body(KState *__restrict__ st, const doubl
     st->g[i] = -sj * gi;
     st->g[i - 1] = cj * gi;
     st->est = fabs(st->g[i]) / beta;
-    if (st->est <= tol || last || rho == 0.0) flag = 1;
+    if (fabs(st->g[i]) / denom <= tol || last || rho == 0.0) flag = 1;
   }
   if (!isfinite(rho) || !isfinite(st->est)) flag = -1;
   st->flag = flag;
@@ -759,8 +761,9 @@ __global__ __launch_bounds__(BLK) void k_multidot(const double *__restrict__ V, 
 }
 
 __global__ __launch_bounds__(BLK) void k_finish(KState *__restrict__ st, const double *__restrict__ partial, int32_t nblk,
-                                                int32_t i, int32_t last, double tol, double beta, double *host_out) {
-  finish_body(st, partial, nblk, i, last, tol, beta, host_out);
+                                                int32_t i, int32_t last, double tol, double beta, double denom,
+                                                double *host_out) {
+  finish_body(st, partial, nblk, i, last, tol, beta, denom, host_out);
 }
 
 __global__ __launch_bounds__(BLK) void k_step(KState *__restrict__ st, const double *__restrict__ cd, int32_t i,
@@ -853,7 +856,7 @@ struct KTask {
   KState *ks;
   int64_t ldv, ldz;
   int32_t n, i, ncols, has_w, last, k, nblk, rows_per_blk;
-  double beta;
+  double beta, denom;
 };
 
 template <int OP, class T>
@@ -870,7 +873,7 @@ __global__ __launch_bounds__(BLK) void kb_krylov(const KTask<T> *__restrict__ ta
   if constexpr (OP == KOP_COLREDUCE) colreduce_body(lb, t.partial, t.nblk, t.cd);
   if constexpr (OP == KOP_STEP) step_body(t.ks, t.cd, t.i, t_mode);
   if constexpr (OP == KOP_PROJECT) project_body(lb, t.V, t.ldv, t.i, t.w, t.ks, t.n, t.vlow, t.partial);
-  if constexpr (OP == KOP_FINISH) finish_body(t.ks, t.partial, t.nblk, t.i, t.last, tol, t.beta, t.host_out);
+  if constexpr (OP == KOP_FINISH) finish_body(t.ks, t.partial, t.nblk, t.i, t.last, tol, t.beta, t.denom, t.host_out);
   if constexpr (OP == KOP_BACKSOLVE) backsolve_body(t.ks, t.k);
   if constexpr (OP == KOP_UPDATE) update_x_body(lb, (const T *)t.Z, t.ldz, t.k, t.ks, t.x, t.n);
   if constexpr (OP == KOP_REDUCE) reduce_body(t.partial, t.nblk, t.host_out);

@@ -76,7 +76,7 @@ class BatchEngine {
     double *x = nullptr;
     int32_t n = 0;
     int phase = INIT, i = 0, me = 0, k = 0;
-    double beta = 0.0, rn = 0.0, est = 0.0, alg = 0.0;
+    double beta = 0.0, denom = 0.0, rn = 0.0, est = 0.0, alg = 0.0;
     int iters = 0, cycles = 0, apps = 0;
     int status = NAMG_PENDING;
     std::string err;
@@ -190,6 +190,24 @@ class BatchEngine {
       add_krylov(KOP_SUMSQ, t, nb);
       add_krylov(KOP_REDUCE, t, ones);
     }
+    if (!resid.empty() && p_.stop_rule == NAMG_STOP_NRBE) {
+      // ||x||^2 at the cycle's start for the backward-error denominator, before the residual pass
+      // reuses the same partial-sum buffer
+      std::vector<KTask<T>> t;
+      std::vector<unsigned> nb, ones;
+      for (Slot *sl : resid) {
+        KTask<T> k = base(sl);
+        k.partial = sl->sv->red_.get();
+        k.nblk = sl->sv->nblk_red_;
+        k.host_out = sl->sv->pinned_dev_ + 4;
+        t.push_back(k);
+        nb.push_back(blocks_for(sl->n));
+        ones.push_back(1u);
+        sl->alg += 8.0 * sl->n;
+      }
+      add_krylov(KOP_SUMSQ, t, nb);
+      add_krylov(KOP_REDUCE, t, ones);
+    }
     if (!resid.empty()) {
       std::vector<KTask<T>> t;
       std::vector<unsigned> nb, ones;
@@ -279,6 +297,7 @@ class BatchEngine {
     k.nblk = v.nblk_dot_;
     k.rows_per_blk = v.rows_per_dot_;
     k.beta = sl->beta;
+    k.denom = sl->denom;
     return k;
   }
 
@@ -295,7 +314,9 @@ class BatchEngine {
       fail(sl, NAMG_E_NONFINITE, "non-finite residual");
       return;
     }
-    if (sl->rn / sl->beta <= p_.tol) {
+    sl->denom = sl->beta;
+    if (p_.stop_rule == NAMG_STOP_NRBE) sl->denom += sl->sv->anorm_inf_ * std::sqrt(sl->sv->pinned_[4]);
+    if (sl->rn / sl->denom <= p_.tol) {
       sl->status = NAMG_OK;
       sl->phase = DONE;
     } else if (sl->iters >= p_.max_iters) {

@@ -65,6 +65,8 @@ void validate_solve_params(const namg_solve_params &p) {
   if (p.gmres_T != NAMG_T_NEUMANN && p.gmres_T != NAMG_T_DIRECT) throw SetupError{NAMG_E_INVALID, "unknown gmres_T"};
   if (p.pre_sweeps < 0 || p.post_sweeps < 0) throw SetupError{NAMG_E_INVALID, "negative sweep count"};
   if (p.t_degree < 1 || p.t_degree > NAMG_MAX_RESTART) throw SetupError{NAMG_E_INVALID, "t_degree out of range"};
+  if (p.stop_rule != NAMG_STOP_RELRES && p.stop_rule != NAMG_STOP_NRBE)
+    throw SetupError{NAMG_E_INVALID, "unknown stop_rule"};
 }
 
 // One function pointer per lanes-per-row group for every row kernel.
@@ -335,13 +337,16 @@ class Solver final : public SolverBase {
       launch(-1, 0, 8.0 * n, &k_fill<double>, blocks_for(n), s, x, 0.0, n);
     } else {
       while (true) {
+        // the stopping test's denominator: ||b||, or ||b|| + ||A||_inf ||x|| at the cycle's start
+        const double denom =
+            p.stop_rule == NAMG_STOP_NRBE ? beta + anorm_inf_ * std::sqrt(norm2sq(x, n, s)) : beta;
         // true residual r = b - A x into V(:,0) (FP64), plus the FP32 copy for the V-cycle
         launch(-1, 0, A64_.bytes() + 24.0 * n + (vin ? S * n : 0.0), &k_residual64<T>, blocks_for(n), s,
                NAMG_HEAD_ARGS(M64), b, (const double *)x, V, vin, red_.get(), M64.mul);
         rn = std::sqrt(reduce_read(red_.get(), nblk_red_, s));
         if (!std::isfinite(rn)) throw SetupError{NAMG_E_NONFINITE, "non-finite residual"};
         if (trace) std::fprintf(stderr, "[namg] cycle %d true relres %.3e\n", st.cycles, rn / beta);
-        if (rn / beta <= p.tol) {
+        if (rn / denom <= p.tol) {
           status = NAMG_OK;
           break;
         }
@@ -352,7 +357,8 @@ class Solver final : public SolverBase {
         st.cycles++;
         const int me = std::min(m, p.max_iters - st.iters);
         // column completion of step 0: rho_0 = ||r|| from the residual pass's partial sums
-        launch_small(&k_finish, s, ks, (const double *)red_.get(), nblk_red_, 0, 0, p.tol, beta, pinned_dev_);
+        launch_small(&k_finish, s, ks, (const double *)red_.get(), nblk_red_, 0, 0, p.tol, beta, denom,
+                     pinned_dev_);
         int k = 0;
         for (int i = 0; i < me; ++i) {
           double *vi = V + (int64_t)i * ldv_;
@@ -376,7 +382,7 @@ class Solver final : public SolverBase {
                  ldv_, i, (const double *)w, (const KState *)ks, n, vin, red_.get());
           // column i is complete once ||v_{i+2}|| is known: estimate and stop test before the next V-cycle
           launch_small(&k_finish, s, ks, (const double *)red_.get(), nblk_red_, i + 1, (int)(i + 1 == me), p.tol, beta,
-                       pinned_dev_);
+                       denom, pinned_dev_);
           hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
           const double est = pinned_[0];
           const int flag = (int)pinned_[1];
@@ -919,6 +925,7 @@ void namg_default_solve_params(namg_solve_params *p) {
   p->pre_sweeps = 1;
   p->post_sweeps = 1;
   p->t_degree = 1;
+  p->stop_rule = NAMG_STOP_RELRES;
 }
 
 int namg_setup(int32_t n, const int32_t *rowptr, const int32_t *colind, const double *vals,

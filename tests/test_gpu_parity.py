@@ -180,7 +180,8 @@ def test_vcycle_matches_oracle(namg, smoother, tri, t):
 def _check_solve(namg, A, b, H, G, x0=None, xtol=1e-10, **kw):
     okw = dict(tol=kw.get("tol", 1e-8), restart=kw.get("restart", 30), max_iters=kw.get("max_iters", 1000),
                smoother=kw.get("smoother", 0), tri_mode=kw.get("tri_mode", 0), t=kw.get("inner_terms", 2),
-               gmres_T=kw.get("gmres_T", 0), t_degree=kw.get("t_degree", 1))
+               gmres_T=kw.get("gmres_T", 0), t_degree=kw.get("t_degree", 1),
+               stop_rule=kw.get("stop_rule", O.STOP_RELRES))
     ref = G.solve(b, x0, **okw)
     xt = dev(np.zeros(A.n) if x0 is None else x0)
     st = H.solve(dev(b), xt, **kw)
@@ -189,8 +190,10 @@ def _check_solve(namg, A, b, H, G, x0=None, xtol=1e-10, **kw):
     assert st["status"] == ref["status"]
     assert relerr(x, ref["x"]) <= xtol, relerr(x, ref["x"])
     res = np.linalg.norm(b - O.spmv(A, x)) / np.linalg.norm(b)
-    if st["status"] == namg.OK:
+    if st["status"] == namg.OK and kw.get("stop_rule", namg.STOP_RELRES) == namg.STOP_RELRES:
         assert res <= kw.get("tol", 1e-8)
+    if st["status"] == namg.OK:
+        assert st["nrbe"] <= kw.get("tol", 1e-8)
     assert st["relres_true"] == pytest.approx(res, rel=1e-6)
     return st, ref, x
 
@@ -218,6 +221,29 @@ def test_solve_t_degree_parity(namg, t_degree):
     r = srv.wait(srv.submit(A, b))
     srv.close()
     ref = O.Hierarchy(A).solve(b, t=2, t_degree=t_degree)
+    assert r["iters"] == ref["iters"] and relerr(r["x"], ref["x"]) <= 1e-10
+
+
+def test_nrbe_stopping_rule_parity(namg):
+    """Stopping on the normwise relative backward error of Section 3: with short restarts the later
+    cycles start from x != 0, the denominator ||b|| + ||A||_inf ||x_0|| exceeds ||b||, and the solve
+    stops earlier than under the relative-residual rule, at the oracle's iteration with its iterate.
+    Covers C1 (restart 3), C2 at 20^3 (ILU(0) hybrid, restart 5), a nonzero starting guess, and the
+    serving engine."""
+    A, b, _ = config_system("c1")
+    H, G = namg.Hierarchy(A, device=0), O.Hierarchy(A)
+    kw = dict(smoother=0, inner_terms=2, restart=3)
+    st, ref, _ = _check_solve(namg, A, b, H, G, stop_rule=namg.STOP_NRBE, **kw)
+    rel, _, _ = _check_solve(namg, A, b, H, G, **kw)
+    assert st["iters"] < rel["iters"]
+    x0 = np.random.default_rng(5).standard_normal(A.n)
+    _check_solve(namg, A, b, H, G, x0=x0, stop_rule=namg.STOP_NRBE, **kw)
+    A2, b2, _ = config_system("c2", 20)
+    _check_solve(namg, A2, b2, namg.Hierarchy(A2, device=0), O.Hierarchy(A2), stop_rule=namg.STOP_NRBE,
+                 smoother=1, inner_terms=3, restart=5)
+    srv = namg.Server(solve=dict(kw, stop_rule=namg.STOP_NRBE), max_inflight=2, setup_threads=1, precision=0)
+    r = srv.wait(srv.submit(A, b))
+    srv.close()
     assert r["iters"] == ref["iters"] and relerr(r["x"], ref["x"]) <= 1e-10
 
 

@@ -134,10 +134,16 @@ def test_solve_param_validation(namg):
 
     H = namg.Hierarchy(poisson2d(8), device=-1)
     for bad in (dict(tol=0.0), dict(restart=0), dict(restart=1000), dict(inner_terms=0), dict(smoother=7),
-                dict(tri_mode=3), dict(gmres_T=2), dict(pre_sweeps=-1), dict(t_degree=0), dict(t_degree=1000)):
+                dict(tri_mode=3), dict(gmres_T=2), dict(pre_sweeps=-1), dict(t_degree=0), dict(t_degree=1000), dict(stop_rule=2),
+                dict(stop_rule=-1)):
         p = namg.solve_params(**bad)
         code = namg.lib().namg_solve(H.h, 1, 1, C.byref(p), None, None)
         assert code == namg.E_INVALID, bad
+    with pytest.raises(TypeError):
+        namg.solve_params(stop_rules=1)
+    with pytest.raises(TypeError):
+        namg.server_params(solve=dict(tdegree=2))
+    assert namg.solve_params().stop_rule == namg.STOP_RELRES
 
 
 def test_server_parameter_validation(namg):
