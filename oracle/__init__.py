@@ -22,6 +22,7 @@ TRI_NEUMANN, TRI_DIRECT = 0, 1
 T_NEUMANN, T_DIRECT = 0, 1
 PRECOND_NONE, PRECOND_AMG = 0, 1
 STOP_RELRES, STOP_NRBE = 0, 1
+ILU_KIND_ILU0, ILU_KIND_ILUT = 0, 1
 PGS_FWD, PGS_BWD, GS_FWD, GS_BWD, ILU_NEUMANN, ILU_DIRECT, L1_JACOBI = range(7)
 
 
@@ -115,6 +116,28 @@ def ilu0(A):
     return out
 
 
+def ilut(A, droptol, lfil):
+    """ILUT(droptol, lfil) factors as a CSR holding L \\ U (strict lower = L_s, the rest = U)."""
+    from workloads import CSR  # input container only
+
+    n = A.n
+    cap = n * min(n, 2 * lfil + 1)
+    rp, ci, v = np.zeros(n + 1, np.int32), np.zeros(cap, np.int32), np.zeros(cap)
+    nnz = C.c_longlong()
+    _check(lib().orc_ilut(n, _p(_i32(A.rowptr), C.c_int), _p(_i32(A.colind), C.c_int), _p(_f64(A.vals), C.c_double),
+                          C.c_double(droptol), lfil, C.c_longlong(cap), _p(rp, C.c_int), _p(ci, C.c_int), _p(v, C.c_double),
+                          C.byref(nnz)))
+    return CSR(n, rp, ci[: nnz.value].copy(), v[: nnz.value].copy())
+
+
+def smooth_ilut(A, droptol, lfil, t, b, x, direct=False):
+    xo = _f64(x).copy()
+    _check(lib().orc_smooth_ilut(A.n, _p(_i32(A.rowptr), C.c_int), _p(_i32(A.colind), C.c_int),
+                                 _p(_f64(A.vals), C.c_double), C.c_double(droptol), lfil, int(direct), t,
+                                 _p(_f64(b), C.c_double), _p(xo, C.c_double)))
+    return xo
+
+
 def smooth(A, kind, t, b, x):
     xo = _f64(x).copy()
     _check(lib().orc_smooth(A.n, _p(_i32(A.rowptr), C.c_int), _p(_i32(A.colind), C.c_int),
@@ -133,7 +156,8 @@ class LevelExport:
 class Hierarchy:
     """Oracle AMG hierarchy (strength, RS first pass, classical P, Galerkin RAP, ILU(0), dense LU)."""
 
-    def __init__(self, A, theta=0.25, max_levels=25, max_coarse=50, ilu_levels=1):
+    def __init__(self, A, theta=0.25, max_levels=25, max_coarse=50, ilu_levels=1, ilu_kind=ILU_KIND_ILU0,
+                 ilut_droptol=1e-2, ilut_lfil=5):
         from workloads import CSR  # input container only
 
         self._CSR = CSR
@@ -141,7 +165,8 @@ class Hierarchy:
         self._rp, self._ci, self._v = _i32(A.rowptr), _i32(A.colind), _f64(A.vals)
         st = C.c_int(0)
         h = lib().orc_setup(A.n, _p(self._rp, C.c_int), _p(self._ci, C.c_int), _p(self._v, C.c_double),
-                            C.c_double(theta), max_levels, max_coarse, ilu_levels, C.byref(st))
+                            C.c_double(theta), max_levels, max_coarse, ilu_levels, ilu_kind,
+                            C.c_double(ilut_droptol), ilut_lfil, C.byref(st))
         if st.value != 0 or not h:
             raise OracleFailure(st.value)
         self.h = C.c_void_p(h)

@@ -341,6 +341,84 @@ std::vector<double> ilu0(const Csr &A) {
   return w;
 }
 
+// ILU(0) as a factor matrix: A's pattern with the ILU(0) values (strict lower = L_s, the rest = U).
+Csr ilu0_factor(const Csr &A) {
+  Csr F = A;
+  F.v = ilu0(A);
+  return F;
+}
+
+// ILUT(droptol, lfil), the threshold incomplete LU that Algorithm 2 factors with (Section 5.3.4; the
+// paper fixes the two parameters, the dropping rule is Saad's dual-threshold ILUT). Row i is
+// eliminated in a sparse work row w = a_i with tau_i = droptol * ||a_i||_2: for each k < i with
+// w_k != 0, in increasing k, the multiplier w_k / u_kk is dropped when its magnitude is below tau_i and
+// otherwise kept and used, w_j -= w_k u_kj for the stored entries of U's row k (j > k), which creates
+// fill. Afterwards every off-diagonal w_j that is zero or below tau_i is dropped, and of the rest at most
+// lfil of largest magnitude stay in the strict lower part and lfil in the strict upper part (equal
+// magnitudes: the smaller column first). Returns L \ U as one CSR with sorted columns: strict lower =
+// L_s (unit diagonal implied), diagonal and strict upper = U.
+Csr ilut(const Csr &A, double droptol, int lfil) {
+  if (!(droptol >= 0.0) || lfil < 0) throw OracleError{ORC_E_INVALID};
+  const int n = A.nr;
+  Csr F;
+  F.nr = F.nc = n;
+  F.rp.assign(1, 0);
+  std::vector<int> udiag(n, -1);  // position of u_kk in F
+  for (int i = 0; i < n; ++i) {
+    std::map<int, double> w;
+    double nrm2 = 0.0;
+    for (int q = A.rp[i]; q < A.rp[i + 1]; ++q) {
+      w[A.ci[q]] = A.v[q];
+      nrm2 += A.v[q] * A.v[q];
+    }
+    const double tau = droptol * std::sqrt(nrm2);
+    for (auto it = w.begin(); it != w.end() && it->first < i; ++it) {
+      const int k = it->first;
+      if (it->second == 0.0) continue;
+      const double lik = it->second / F.v[udiag[k]];
+      if (std::fabs(lik) < tau) {
+        it->second = 0.0;
+        continue;
+      }
+      it->second = lik;
+      for (int q = udiag[k] + 1; q < F.rp[k + 1]; ++q) w[F.ci[q]] -= lik * F.v[q];
+    }
+    std::vector<std::pair<int, double>> lo, up;
+    double diag = 0.0;
+    for (const auto &e : w) {
+      if (e.first == i) {
+        diag = e.second;
+      } else if (e.second != 0.0 && std::fabs(e.second) >= tau) {
+        (e.first < i ? lo : up).push_back(e);
+      }
+    }
+    if (diag == 0.0) throw OracleError{ORC_E_ZERO_PIVOT};
+    auto keep_largest = [lfil](std::vector<std::pair<int, double>> &v) {
+      std::sort(v.begin(), v.end(), [](const std::pair<int, double> &a, const std::pair<int, double> &b) {
+        const double ma = std::fabs(a.second), mb = std::fabs(b.second);
+        return ma > mb || (ma == mb && a.first < b.first);
+      });
+      if ((int)v.size() > lfil) v.resize(lfil);
+      std::sort(v.begin(), v.end());
+    };
+    keep_largest(lo);
+    keep_largest(up);
+    for (const auto &e : lo) {
+      F.ci.push_back(e.first);
+      F.v.push_back(e.second);
+    }
+    udiag[i] = (int)F.ci.size();
+    F.ci.push_back(i);
+    F.v.push_back(diag);
+    for (const auto &e : up) {
+      F.ci.push_back(e.first);
+      F.v.push_back(e.second);
+    }
+    F.rp.push_back((int)F.ci.size());
+  }
+  return F;
+}
+
 // ---------------------------------------------------------------------------------------------
 // Smoothers, one sweep each: x <- x + Mhat^{-1} (b - A x).
 
@@ -400,21 +478,21 @@ void gs_direct(const Csr &A, const std::vector<double> &b, std::vector<double> &
 
 // ILU smoother with Jacobi triangular solves (Section 5.3.2 and Algorithm 2 without Ruiz scaling,
 // row scaling D_U = diag(U) per its footnote): y = r then t-1 steps y <- r - L_s y; v = D_U^{-1} y then
-// t-1 steps v <- D_U^{-1}(y - U_s v), with U_s the strict upper part of U.
-void ilu_neumann(const Csr &A, const std::vector<double> &LU, const std::vector<double> &b,
-                 std::vector<double> &x, int t) {
+// t-1 steps v <- D_U^{-1}(y - U_s v), with U_s the strict upper part of U. F holds L \ U (ILU(0) in A's
+// pattern, or ILUT with its own fill).
+void ilu_neumann(const Csr &A, const Csr &F, const std::vector<double> &b, std::vector<double> &x, int t) {
   const int n = A.nr;
   std::vector<double> r, y, yn(n), v(n), vn(n), du(n);
   residual(A, b, x, r);
   for (int i = 0; i < n; ++i)
-    for (int k = A.rp[i]; k < A.rp[i + 1]; ++k)
-      if (A.ci[k] == i) du[i] = LU[k];
+    for (int k = F.rp[i]; k < F.rp[i + 1]; ++k)
+      if (F.ci[k] == i) du[i] = F.v[k];
   y = r;
   for (int rep = 1; rep < t; ++rep) {
     for (int i = 0; i < n; ++i) {
       double s = 0.0;
-      for (int k = A.rp[i]; k < A.rp[i + 1]; ++k)
-        if (A.ci[k] < i) s += LU[k] * y[A.ci[k]];
+      for (int k = F.rp[i]; k < F.rp[i + 1]; ++k)
+        if (F.ci[k] < i) s += F.v[k] * y[F.ci[k]];
       yn[i] = r[i] - s;
     }
     y.swap(yn);
@@ -423,8 +501,8 @@ void ilu_neumann(const Csr &A, const std::vector<double> &LU, const std::vector<
   for (int rep = 1; rep < t; ++rep) {
     for (int i = 0; i < n; ++i) {
       double s = 0.0;
-      for (int k = A.rp[i]; k < A.rp[i + 1]; ++k)
-        if (A.ci[k] > i) s += LU[k] * v[A.ci[k]];
+      for (int k = F.rp[i]; k < F.rp[i + 1]; ++k)
+        if (F.ci[k] > i) s += F.v[k] * v[F.ci[k]];
       vn[i] = (y[i] - s) / du[i];
     }
     v.swap(vn);
@@ -433,22 +511,21 @@ void ilu_neumann(const Csr &A, const std::vector<double> &LU, const std::vector<
 }
 
 // ILU smoother with direct forward/backward substitution (the comparator of Section 6.2, Table 7).
-void ilu_direct(const Csr &A, const std::vector<double> &LU, const std::vector<double> &b,
-                std::vector<double> &x) {
+void ilu_direct(const Csr &A, const Csr &F, const std::vector<double> &b, std::vector<double> &x) {
   const int n = A.nr;
   std::vector<double> r, y(n), v(n);
   residual(A, b, x, r);
   for (int i = 0; i < n; ++i) {
     double s = 0.0;
-    for (int k = A.rp[i]; k < A.rp[i + 1]; ++k)
-      if (A.ci[k] < i) s += LU[k] * y[A.ci[k]];
+    for (int k = F.rp[i]; k < F.rp[i + 1]; ++k)
+      if (F.ci[k] < i) s += F.v[k] * y[F.ci[k]];
     y[i] = r[i] - s;
   }
   for (int i = n - 1; i >= 0; --i) {
     double s = 0.0, d = 0.0;
-    for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
-      if (A.ci[k] > i) s += LU[k] * v[A.ci[k]];
-      if (A.ci[k] == i) d = LU[k];
+    for (int k = F.rp[i]; k < F.rp[i + 1]; ++k) {
+      if (F.ci[k] > i) s += F.v[k] * v[F.ci[k]];
+      if (F.ci[k] == i) d = F.v[k];
     }
     v[i] = (y[i] - s) / d;
   }
@@ -497,7 +574,7 @@ struct DenseLU {
 struct Level {
   Csr A, P, R;
   std::vector<signed char> cf;
-  std::vector<double> ilu;  // ILU(0) factors in A's pattern (empty when not requested)
+  Csr ilu;  // L \ U of ILU(0) or ILUT (no rows when not requested)
 };
 
 struct Hierarchy {
@@ -507,9 +584,14 @@ struct Hierarchy {
 
 // Setup: strength, RS first pass, classical interpolation, R = P^T, A_{l+1} = P^T A_l P (Section 5).
 // Coarsen while n_l > max_coarse and l + 1 < max_levels; stop if the next level would be empty or
-// as large as this one. ILU(0) factors on the first ilu_levels levels (-1: all but the coarsest).
-Hierarchy *build(const Csr &A0, double theta, int max_levels, int max_coarse, int ilu_levels) {
+// as large as this one. ILU factors on the first ilu_levels levels (-1: all but the coarsest): ILU(0),
+// or ILUT(droptol, lfil) when ilu_kind is ORC_ILU_KIND_ILUT.
+Hierarchy *build(const Csr &A0, double theta, int max_levels, int max_coarse, int ilu_levels, int ilu_kind,
+                 double droptol, int lfil) {
   if (!(theta > 0.0 && theta <= 1.0) || max_levels < 1 || max_coarse < 1) throw OracleError{ORC_E_INVALID};
+  if (ilu_kind != ORC_ILU_KIND_ILU0 && ilu_kind != ORC_ILU_KIND_ILUT) throw OracleError{ORC_E_INVALID};
+  if (ilu_kind == ORC_ILU_KIND_ILUT && (!(droptol >= 0.0) || !std::isfinite(droptol) || lfil < 0))
+    throw OracleError{ORC_E_INVALID};
   for (int i = 0; i < A0.nr; ++i)
     if (diag_of(A0, i) == 0.0) throw OracleError{ORC_E_ZERO_PIVOT};
   auto *H = new Hierarchy;
@@ -533,7 +615,8 @@ Hierarchy *build(const Csr &A0, double theta, int max_levels, int max_coarse, in
   }
   const int nl = (int)H->lv.size();
   for (int l = 0; l < nl - 1; ++l)
-    if (ilu_levels < 0 || l < ilu_levels) H->lv[l].ilu = ilu0(H->lv[l].A);
+    if (ilu_levels < 0 || l < ilu_levels)
+      H->lv[l].ilu = ilu_kind == ORC_ILU_KIND_ILUT ? ilut(H->lv[l].A, droptol, lfil) : ilu0_factor(H->lv[l].A);
   H->coarse.factor(H->lv.back().A);
   return H;
 }
@@ -554,7 +637,7 @@ void vcycle(const Hierarchy &H, int l, const CycleOpts &o, const std::vector<dou
     H.coarse.solve(b, x);
     return;
   }
-  const bool use_ilu = (o.smoother == ORC_SMOOTH_ILU0) && !L.ilu.empty();
+  const bool use_ilu = (o.smoother == ORC_SMOOTH_ILU0) && L.ilu.nr > 0;
   const bool direct = (o.tri_mode == ORC_TRI_DIRECT);
   x.assign(L.A.nr, 0.0);
   for (int s = 0; s < o.nu1; ++s) {
@@ -841,8 +924,8 @@ int orc_smooth(int n, const int *rp, const int *ci, const double *v, int kind, i
       case ORC_PGS_BWD: pgs_neumann(A, bv, xv, t, false); break;
       case ORC_GS_FWD: gs_direct(A, bv, xv, true); break;
       case ORC_GS_BWD: gs_direct(A, bv, xv, false); break;
-      case ORC_ILU_NEUMANN: ilu_neumann(A, ilu0(A), bv, xv, t); break;
-      case ORC_ILU_DIRECT: ilu_direct(A, ilu0(A), bv, xv); break;
+      case ORC_ILU_NEUMANN: ilu_neumann(A, ilu0_factor(A), bv, xv, t); break;
+      case ORC_ILU_DIRECT: ilu_direct(A, ilu0_factor(A), bv, xv); break;
       case ORC_L1_JACOBI: l1_jacobi(A, bv, xv); break;
       default: return (int)ORC_E_INVALID;
     }
@@ -851,13 +934,40 @@ int orc_smooth(int n, const int *rp, const int *ci, const double *v, int kind, i
   });
 }
 
+int orc_ilut(int n, const int *rp, const int *ci, const double *v, double droptol, int lfil, long long cap,
+             int *frp, int *fci, double *fv, long long *nnz) {
+  return guarded([&]() -> int {
+    Csr A = make_csr(n, n, rp, ci, v);
+    Csr F = ilut(A, droptol, lfil);
+    *nnz = (long long)F.ci.size();
+    if (*nnz > cap) return (int)ORC_E_INVALID;
+    std::copy(F.rp.begin(), F.rp.end(), frp);
+    std::copy(F.ci.begin(), F.ci.end(), fci);
+    std::copy(F.v.begin(), F.v.end(), fv);
+    return ORC_OK;
+  });
+}
+
+int orc_smooth_ilut(int n, const int *rp, const int *ci, const double *v, double droptol, int lfil, int direct,
+                    int t, const double *b, double *x) {
+  return guarded([&]() -> int {
+    Csr A = make_csr(n, n, rp, ci, v);
+    if (t < 1) return (int)ORC_E_INVALID;
+    Csr F = ilut(A, droptol, lfil);
+    std::vector<double> bv(b, b + n), xv(x, x + n);
+    direct ? ilu_direct(A, F, bv, xv) : ilu_neumann(A, F, bv, xv, t);
+    std::copy(xv.begin(), xv.end(), x);
+    return ORC_OK;
+  });
+}
+
 void *orc_setup(int n, const int *rp, const int *ci, const double *v, double theta, int max_levels,
-                int max_coarse, int ilu_levels, int *status) {
+                int max_coarse, int ilu_levels, int ilu_kind, double droptol, int lfil, int *status) {
   Hierarchy *H = nullptr;
   int s = guarded([&]() -> int {
     Csr A = make_csr(n, n, rp, ci, v);
     if (n < 1) return (int)ORC_E_INVALID;
-    H = build(A, theta, max_levels, max_coarse, ilu_levels);
+    H = build(A, theta, max_levels, max_coarse, ilu_levels, ilu_kind, droptol, lfil);
     return ORC_OK;
   });
   if (status) *status = s;

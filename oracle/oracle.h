@@ -20,6 +20,7 @@ enum { ORC_TRI_NEUMANN = 0, ORC_TRI_DIRECT = 1 };
 enum { ORC_T_NEUMANN = 0, ORC_T_DIRECT = 1 };
 enum { ORC_PRECOND_NONE = 0, ORC_PRECOND_AMG = 1 };
 enum { ORC_STOP_RELRES = 0, ORC_STOP_NRBE = 1 };
+enum { ORC_ILU_KIND_ILU0 = 0, ORC_ILU_KIND_ILUT = 1 };
 /* single-level smoother kinds for orc_smooth */
 enum {
   ORC_PGS_FWD = 0,     /* polynomial GS, forward (D+L), t Neumann terms      */
@@ -59,12 +60,19 @@ int orc_coarsen(int n, const int *rp, const int *ci, const double *v, double the
 /* ILU(0) on A's pattern: out holds L's strict-lower entries (unit diagonal implied) and U's
  * upper entries (diagonal included) in A's positions. */
 int orc_ilu0(int n, const int *rp, const int *ci, const double *v, double *out);
+/* ILUT(droptol, lfil) factors L \ U as CSR (frp: n + 1 entries; fci, fv: up to cap entries); *nnz gets the
+   factor's entry count, ORC_E_INVALID when it exceeds cap */
+int orc_ilut(int n, const int *rp, const int *ci, const double *v, double droptol, int lfil, long long cap,
+             int *frp, int *fci, double *fv, long long *nnz);
+/* one ILUT smoothing sweep: Jacobi triangular solves with t terms (direct = 0) or substitution (1) */
+int orc_smooth_ilut(int n, const int *rp, const int *ci, const double *v, double droptol, int lfil, int direct,
+                    int t, const double *b, double *x);
 /* one smoothing sweep x <- x + M^{-1}(b - A x) of the given kind */
 int orc_smooth(int n, const int *rp, const int *ci, const double *v, int kind, int t, const double *b, double *x);
 
 /* ---- hierarchy ---- */
 void *orc_setup(int n, const int *rp, const int *ci, const double *v, double theta, int max_levels,
-                int max_coarse, int ilu_levels, int *status);
+                int max_coarse, int ilu_levels, int ilu_kind, double droptol, int lfil, int *status);
 void orc_free(void *h);
 int orc_num_levels(const void *h);
 /* n, nnz(A_l), nnz(P_l) (0 on the coarsest level), n_{l+1} */

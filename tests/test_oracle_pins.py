@@ -172,6 +172,124 @@ def test_ilu0_tridiagonal_is_exact_lu(oracle_lib):
     np.testing.assert_allclose(x, np.linalg.solve(A.to_dense(), b), rtol=1e-12)
 
 
+# -------------------------------------------------------------------------------------------- ILUT
+def _split_factor(F):
+    """Dense (L, U) from a CSR holding L \\ U (unit diagonal of L implied)."""
+    d = F.to_dense()
+    return np.tril(d, -1) + np.eye(F.n), np.triu(d)
+
+
+@pytest.mark.parametrize("maker", [lambda: poisson2d(6), lambda: convdiff3d(3, 3)[0], lambda: random_csr(30, 5, 3)])
+def test_ilut_without_dropping_is_exact_lu(oracle_lib, maker):
+    """ILUT with droptol = 0 and no fill limit drops nothing, so it is Gaussian elimination without
+    pivoting: the LU factors scipy computes (whose partial pivoting picks the diagonal on these
+    diagonally dominant matrices), and one direct sweep from x = 0 solves A x = b."""
+    O = oracle_lib
+    A = maker()
+    F = O.ilut(A, 0.0, A.n)
+    L, U = _split_factor(F)
+    P, Ls, Us = sla.lu(A.to_dense())
+    assert np.array_equal(P, np.eye(A.n))
+    np.testing.assert_allclose(L, Ls, atol=1e-13)
+    np.testing.assert_allclose(U, Us, atol=1e-12)
+    b = np.random.default_rng(1).standard_normal(A.n)
+    x = O.smooth_ilut(A, 0.0, A.n, 1, b, np.zeros(A.n), direct=True)
+    np.testing.assert_allclose(x, np.linalg.solve(A.to_dense(), b), rtol=1e-11, atol=1e-12)
+
+
+@pytest.mark.parametrize("droptol", [1e-3, 1e-2, 1e-1])
+@pytest.mark.parametrize("maker", [lambda: poisson2d(10), lambda: convdiff3d(4, 3)[0], lambda: random_csr(40, 6, 2)])
+def test_ilut_reproduces_A_on_its_pattern(oracle_lib, maker, droptol):
+    """Without the fill limit every multiplier ILUT keeps is used and stored, and every stored U entry is
+    the one later rows eliminate with, so (LU)_ij = a_ij at each stored position; a position of A that
+    is not stored was dropped at the end of its row, so there LU differs from A by less than the
+    row's threshold droptol ||a_i||_2 (times u_jj for a lower entry)."""
+    O = oracle_lib
+    A = maker()
+    F = O.ilut(A, droptol, A.n)
+    L, U = _split_factor(F)
+    Ad, LU = A.to_dense(), L @ U
+    mask = F.to_dense() != 0
+    np.testing.assert_allclose(LU[mask], Ad[mask], atol=1e-12 * np.abs(Ad).max())
+    tau = droptol * np.linalg.norm(Ad, axis=1)
+    ii, jj = np.nonzero((Ad != 0) & ~mask)
+    bound = np.where(jj < ii, tau[ii] * np.abs(np.diag(U))[jj], tau[ii])
+    assert np.all(np.abs(LU[ii, jj] - Ad[ii, jj]) <= bound * (1 + 1e-12))
+
+
+def test_ilut_degenerate_limits(oracle_lib):
+    """A drop tolerance above every entry, or lfil = 0, leaves only the diagonal: with no stored U rows
+    nothing updates u_ii, so U = diag(A) and the Neumann ILUT sweep is a Jacobi step x + D^{-1}(b - A x)."""
+    O = oracle_lib
+    A = poisson2d(7)
+    Ad = A.to_dense()
+    for F in (O.ilut(A, 1e3, 5), O.ilut(A, 1e-2, 0)):
+        np.testing.assert_array_equal(F.to_dense(), np.diag(np.diag(Ad)))
+    rng = np.random.default_rng(2)
+    b, x = rng.standard_normal(A.n), rng.standard_normal(A.n)
+    jac = x + (b - Ad @ x) / np.diag(Ad)
+    np.testing.assert_allclose(O.smooth_ilut(A, 1e-2, 0, 3, b, x), jac, rtol=1e-14, atol=1e-14)
+
+
+def test_ilut_keeps_the_lfil_largest(oracle_lib):
+    """Row 0 has nothing to eliminate, so U's row 0 is A's row 0 after the two rules: entries below
+    droptol * ||a_0||_2 go, then the lfil largest in magnitude stay (equal magnitudes: smaller column)."""
+    O = oracle_lib
+    d = np.eye(8) * 10.0
+    d[0, 1:] = [-1.0, 1.0, -1.0, 0.5, 3.0, 0.01, -1.0]
+    d[1:, 0] = 0.1
+    A = CSR.from_dense(d)
+    F = O.ilut(A, 0.05 / np.linalg.norm(d[0]), 3)  # tau = 0.05: drops the 0.01 entry
+    row0 = F.to_dense()[0]
+    assert list(np.nonzero(row0[1:])[0] + 1) == [1, 2, 5]  # 3.0, then the first two of the four |1|
+    assert row0[5] == 3.0 and row0[1] == -1.0 and row0[2] == 1.0
+    F = O.ilut(A, 0.0, 7)
+    np.testing.assert_array_equal(F.to_dense()[0], d[0])
+    F = O.ilut(A, 0.05 / np.linalg.norm(d[0]), 7)
+    assert F.to_dense()[0, 6] == 0.0 and np.count_nonzero(F.to_dense()[0]) == 7
+    # tau = 0.9 in the row's 2-norm drops 0.5 and 0.01 but none of the |1| (the 1-norm would drop them)
+    F = O.ilut(A, 0.9 / np.linalg.norm(d[0]), 7)
+    assert list(np.nonzero(F.to_dense()[0])[0]) == [0, 1, 2, 3, 5, 7]
+
+
+def test_ilut_fill_limits_and_tridiagonal(oracle_lib):
+    """At most lfil entries per row in each strict triangle; on a tridiagonal matrix there is no fill,
+    so ILUT(0, 1) is ILU(0), the exact LU."""
+    O = oracle_lib
+    A = poisson2d(16)
+    for droptol, lfil in ((1e-2, 5), (1e-3, 2), (0.0, 1)):
+        F = O.ilut(A, droptol, lfil)
+        for i in range(A.n):
+            cols = F.colind[F.rowptr[i]:F.rowptr[i + 1]]
+            assert (cols < i).sum() <= lfil and (cols > i).sum() <= lfil and i in cols
+            assert np.all(np.diff(cols) > 0)
+    T = tridiag1d(20)
+    F = O.ilut(T, 0.0, 1)
+    np.testing.assert_array_equal(F.rowptr, T.rowptr)
+    np.testing.assert_array_equal(F.colind, T.colind)
+    np.testing.assert_allclose(F.vals, O.ilu0(T), rtol=1e-15)
+
+
+def test_ilut_hierarchy_solves(oracle_lib):
+    """The hybrid V-cycle with ILUT(1e-2, 5) on the finest level (Algorithm 2 with row scaling) as
+    preconditioner: converges to the true relative residual with Jacobi and with direct triangular
+    solves, and the direct ILUT smoother needs no more iterations than the direct ILU(0) one."""
+    O = oracle_lib
+    A, b, _ = __import__("workloads").config_system("c2", 12)
+    H = O.Hierarchy(A, ilu_kind=O.ILU_KIND_ILUT, ilut_droptol=1e-2, ilut_lfil=5)
+    H0 = O.Hierarchy(A)
+    Ad = A.to_dense()
+    for tri in (O.TRI_NEUMANN, O.TRI_DIRECT):
+        r = H.solve(b, smoother=O.SMOOTH_ILU0, tri_mode=tri, t=3)
+        assert r["status"] == 0 and np.linalg.norm(b - Ad @ r["x"]) <= 1e-8 * np.linalg.norm(b)
+    assert (H.solve(b, smoother=O.SMOOTH_ILU0, tri_mode=O.TRI_DIRECT)["iters"]
+            <= H0.solve(b, smoother=O.SMOOTH_ILU0, tri_mode=O.TRI_DIRECT)["iters"])
+    with pytest.raises(O.OracleFailure):
+        O.Hierarchy(A, ilu_kind=O.ILU_KIND_ILUT, ilut_lfil=-1)
+    with pytest.raises(O.OracleFailure):
+        O.Hierarchy(A, ilu_kind=2)
+
+
 # ---------------------------------------------------------------------------------------- smoothers
 def _depth(A, lower=True):
     """Number of levels of the dependency DAG of the strict triangle (brute force)."""
