@@ -276,14 +276,33 @@ def main():
     out["read_ceiling_GBps"] = round(read_ceiling(torch), 1)
 
     if args.compare:
+        # the Table 7 family on this workload: ILUT(1e-2, 5) on the finest level with Jacobi (Neumann) or
+        # direct triangular solves next to ILU(0), plus the Table 6 comparator and the other precision
         cmp = {}
-        for name, extra, prec2 in (("direct_tri", dict(tri_mode=namg.TRI_DIRECT), prec),
-                                   ("l1_jacobi", dict(smoother=namg.SMOOTH_L1JAC), prec),
-                                   ("fp32_precond", {}, namg.FP32_PRECOND), ("fp64", {}, namg.FP64)):
-            H2 = H if prec2 == prec else namg.Hierarchy(A, device=0, precision=prec2, ilu_levels=1)
+        ilut = dict(ilu_kind=namg.ILUT, ilut_droptol=1e-2, ilut_lfil=5)
+        H_ilut = None
+        for name, extra, prec2, setup2 in (("direct_tri", dict(tri_mode=namg.TRI_DIRECT), prec, None),
+                                           ("l1_jacobi", dict(smoother=namg.SMOOTH_L1JAC), prec, None),
+                                           ("ilut_jacobi", dict(smoother=namg.SMOOTH_ILU0), prec, ilut),
+                                           ("ilut_direct", dict(smoother=namg.SMOOTH_ILU0, tri_mode=namg.TRI_DIRECT),
+                                            prec, ilut),
+                                           ("fp32_precond", {}, namg.FP32_PRECOND, None), ("fp64", {}, namg.FP64, None)):
+            if setup2 is not None:
+                if H_ilut is None:
+                    t0 = time.perf_counter()
+                    H_ilut = namg.Hierarchy(A, device=0, precision=prec, ilu_levels=1, **setup2)
+                    ilut_setup_ms = (time.perf_counter() - t0) * 1e3
+                H2 = H_ilut
+            else:
+                H2 = H if prec2 == prec else namg.Hierarchy(A, device=0, precision=prec2, ilu_levels=1)
             kw2 = dict(kw, **extra)
             ms2, st2 = _time_solves(torch, H2, bt, xt, kw2, max(1, args.steps // 2), 1)
             cmp[name] = {"ms": round(ms2, 3), "iters": st2[-1]["iters"], "relres": st2[-1]["relres_true"]}
+            if setup2 is not None:
+                cmp[name].update(setup=dict(droptol=setup2["ilut_droptol"], lfil=setup2["ilut_lfil"]),
+                                 setup_ms=round(ilut_setup_ms, 1))
+        if H_ilut is not None:
+            H_ilut.close()
         out["compare"] = cmp
 
     if args.serve_requests > 0:

@@ -42,6 +42,7 @@ enum { NAMG_SMOOTH_PGS = 0, NAMG_SMOOTH_ILU0 = 1, NAMG_SMOOTH_L1JAC = 2 }; /* na
 enum { NAMG_TRI_NEUMANN = 0, NAMG_TRI_DIRECT = 1 };   /* namg_solve_params.tri_mode  */
 enum { NAMG_T_NEUMANN = 0, NAMG_T_DIRECT = 1 };       /* namg_solve_params.gmres_T   */
 enum { NAMG_STOP_RELRES = 0, NAMG_STOP_NRBE = 1 };    /* namg_solve_params.stop_rule */
+enum { NAMG_ILU0 = 0, NAMG_ILUT = 1 };                /* namg_setup_params.ilu_kind  */
 
 #define NAMG_MAX_LEVELS 32
 #define NAMG_MAX_RESTART 128
@@ -54,9 +55,17 @@ typedef struct {
   int max_coarse; /* stop coarsening at <= max_coarse rows (dense direct solve); default 50 */
   int precision;  /* NAMG_FP64, or NAMG_FP32_PRECOND: hierarchy values and the V-cycle in FP32,
                      Arnoldi / Hessenberg / true residual in FP64 */
-  int ilu_levels; /* ILU(0) factors on levels l < ilu_levels (1 = finest only, the hybrid V-cycle of
+  int ilu_levels; /* ILU factors on levels l < ilu_levels (1 = finest only, the hybrid V-cycle of
                      Section 6.2; -1 = every level but the coarsest; 0 = none); default 1 */
   int device;     /* HIP device ordinal; -1 = host-only setup (for inspection; solves are refused) */
+  int ilu_kind;   /* NAMG_ILU0 (default): ILU(0) on A's pattern; NAMG_ILUT: ILUT(ilut_droptol, ilut_lfil),
+                     the threshold factorization of Algorithm 2 (Section 5.3.4) with Saad's dual rule:
+                     with tau_i = ilut_droptol * ||a_i||_2, multipliers below tau_i are dropped during the
+                     elimination of row i, then off-diagonal entries below tau_i, and at most ilut_lfil
+                     entries of largest magnitude stay in each strict triangle of the row (ties: smaller
+                     column). The smoother applies either factor the same way (row scaling D_U = diag(U)) */
+  int ilut_lfil;  /* >= 0; default 5 */
+  double ilut_droptol; /* >= 0; default 1e-2 */
 } namg_setup_params;
 
 typedef struct {
@@ -179,6 +188,14 @@ int namg_level_sizes(const namg_hier *h, int level, int32_t *n, int64_t *nnzA, i
  * level), A_l in CSR, P_l in CSR (n_l x n_{l+1}). Any pointer may be NULL; sizes from namg_level_sizes. */
 int namg_export_level(const namg_hier *h, int level, int8_t *cf, int32_t *A_rowptr, int32_t *A_colind,
                       double *A_vals, int32_t *P_rowptr, int32_t *P_colind, double *P_vals);
+
+/* Host copies of the ILU smoother factors of level l (Section 5.3.2: L = I + L_s, U = D_U (I + U_s)):
+ * L_s (strict lower, as factored), U_s = D_U^{-1} times the strict upper part of U, and d_inv[i] = 1/u_ii,
+ * each CSR with n_l + 1 row pointers. Call with NULL arrays first to get *nnz_lower and *nnz_upper.
+ * NAMG_E_INVALID if the level carries no ILU factors. */
+int namg_export_ilu(const namg_hier *h, int level, int64_t *nnz_lower, int64_t *nnz_upper, int32_t *L_rowptr,
+                    int32_t *L_colind, double *L_vals, int32_t *U_rowptr, int32_t *U_colind, double *U_vals,
+                    double *d_inv);
 
 /* ---- Serving (continuous batching of many solves on one GPU) ------------------------------------- */
 

@@ -22,6 +22,7 @@ SMOOTH_PGS, SMOOTH_ILU0, SMOOTH_L1JAC = 0, 1, 2
 TRI_NEUMANN, TRI_DIRECT = 0, 1
 T_NEUMANN, T_DIRECT = 0, 1
 STOP_RELRES, STOP_NRBE = 0, 1
+ILU0, ILUT = 0, 1
 OP_SPMV, OP_RESIDUAL, OP_SMOOTH_PRE, OP_SMOOTH_POST, OP_RESTRICT, OP_PROLONG, OP_COARSE, OP_SPMV64 = range(8)
 MAX_LEVELS = 32
 
@@ -30,7 +31,8 @@ KF_NONE, KF_NEUMANN, KF_RESIDUAL, KF_SPMV, KF_PROLONG, KF_GMRES_SPMV, KF_MULTIDO
 EXPORTED = (
     "namg_default_setup_params", "namg_default_solve_params", "namg_setup", "namg_solve", "namg_vcycle",
     "namg_apply", "namg_profile_kernel", "namg_profile_read", "namg_hier_info", "namg_level_sizes",
-    "namg_export_level", "namg_destroy", "namg_last_error", "namg_default_server_params", "namg_server_create",
+    "namg_export_level", "namg_export_ilu", "namg_destroy", "namg_last_error", "namg_default_server_params",
+    "namg_server_create",
     "namg_server_submit", "namg_server_poll", "namg_server_wait", "namg_server_stats", "namg_server_clock",
     "namg_server_destroy",
 )
@@ -38,7 +40,8 @@ EXPORTED = (
 
 class SetupParams(C.Structure):
     _fields_ = [("theta", C.c_double), ("max_levels", C.c_int), ("max_coarse", C.c_int), ("precision", C.c_int),
-                ("ilu_levels", C.c_int), ("device", C.c_int)]
+                ("ilu_levels", C.c_int), ("device", C.c_int), ("ilu_kind", C.c_int), ("ilut_lfil", C.c_int),
+                ("ilut_droptol", C.c_double)]
 
 
 class SolveParams(C.Structure):
@@ -239,6 +242,19 @@ class Hierarchy:
                                       _ptr(Av, C.c_double), _ptr(Prp, C.c_int32), _ptr(Pci, C.c_int32),
                                       _ptr(Pv, C.c_double)))
         return {"cf": cf, "A": (Arp, Aci, Av), "P": None if last else (Prp, Pci, Pv, nc)}
+
+    def export_ilu(self, level):
+        """Host copies of the ILU smoother factors: L_s and U_s = D_U^{-1} strict(U) as CSR triples, 1/u_ii."""
+        nl, nu = C.c_int64(), C.c_int64()
+        _check(_lib.namg_export_ilu(self.h, level, C.byref(nl), C.byref(nu), None, None, None, None, None, None, None))
+        n = self.level_sizes(level)[0]
+        L = (np.zeros(n + 1, np.int32), np.zeros(nl.value, np.int32), np.zeros(nl.value))
+        U = (np.zeros(n + 1, np.int32), np.zeros(nu.value, np.int32), np.zeros(nu.value))
+        dinv = np.zeros(n)
+        _check(_lib.namg_export_ilu(self.h, level, C.byref(nl), C.byref(nu), _ptr(L[0], C.c_int32),
+                                    _ptr(L[1], C.c_int32), _ptr(L[2], C.c_double), _ptr(U[0], C.c_int32),
+                                    _ptr(U[1], C.c_int32), _ptr(U[2], C.c_double), _ptr(dinv, C.c_double)))
+        return {"L": L, "U": U, "dinv": dinv}
 
     def solve(self, b, x, stream=None, **params) -> dict:
         """namg_solve on device tensors b (read) and x (initial guess in, solution out)."""

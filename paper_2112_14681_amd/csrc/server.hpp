@@ -642,7 +642,7 @@ class Server final : public ServerBase {
       r->tm.setup_start = clock();
       try {
         r->H = std::make_unique<HostHierarchy>(
-            build_hierarchy(r->A, r->sp.theta, r->sp.max_levels, r->sp.max_coarse, r->sp.ilu_levels));
+            build_hierarchy(r->A, r->sp));
         r->footprint = solver_footprint<T>(*r->H, p_.solve.restart) + 16 * (int64_t)r->A.nr;
         r->A = HostCsr{};
       } catch (const SetupError &e) {

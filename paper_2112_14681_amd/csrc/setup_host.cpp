@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <numeric>
+#include <queue>
 
 #include "../../include/namg.h"
 
@@ -384,6 +385,98 @@ std::vector<double> ilu0_values(const HostCsr &A) {
   return w;
 }
 
+// ILUT(droptol, lfil) with Saad's dual threshold (Algorithm 2 factors with it, Section 5.3.4). Row i is
+// eliminated in a dense work row w (scattered from a_i, reset through its list of touched columns), with
+// tau_i = droptol * ||a_i||_2. The lower positions of w are taken in increasing column order from a
+// min-heap, which also receives fill created below the diagonal: the multiplier w_k / u_kk is dropped
+// when below tau_i, else kept and used (w_j -= l_ik u_kj over U's finished row k). Each w_j thus takes its
+// updates in increasing k, the same sequence of roundings as any other increasing-k elimination.
+// Afterwards off-diagonal entries that are zero or below tau_i go, and at most lfil of the largest
+// magnitude (ties: smaller column) stay in each strict triangle. Returns L \ U with sorted columns.
+HostCsr ilut_factor(const HostCsr &A, double droptol, int32_t lfil) {
+  const int32_t n = A.nr;
+  HostCsr F;
+  F.nr = F.nc = n;
+  F.rp.assign(n + 1, 0);
+  F.ci.reserve((size_t)n * (2 * (size_t)std::min<int32_t>(lfil, 8) + 1));
+  F.v.reserve(F.ci.capacity());
+  std::vector<int32_t> udiag(n, -1), touched;
+  std::vector<double> w(n, 0.0);
+  std::vector<uint8_t> in(n, 0);
+  std::priority_queue<int32_t, std::vector<int32_t>, std::greater<int32_t>> lower;
+  std::vector<std::pair<int32_t, double>> lo, up;
+  auto by_magnitude = [](const std::pair<int32_t, double> &a, const std::pair<int32_t, double> &b) {
+    const double ma = std::fabs(a.second), mb = std::fabs(b.second);
+    return ma > mb || (ma == mb && a.first < b.first);
+  };
+  auto keep_largest = [&](std::vector<std::pair<int32_t, double>> &v) {
+    if ((int64_t)v.size() > lfil) {
+      std::nth_element(v.begin(), v.begin() + lfil, v.end(), by_magnitude);
+      v.resize(lfil);
+    }
+    std::sort(v.begin(), v.end());
+  };
+  for (int32_t i = 0; i < n; ++i) {
+    double nrm2 = 0.0;
+    for (int32_t q = A.rp[i]; q < A.rp[i + 1]; ++q) {
+      const int32_t j = A.ci[q];
+      w[j] = A.v[q];
+      in[j] = 1;
+      touched.push_back(j);
+      if (j < i) lower.push(j);
+      nrm2 += A.v[q] * A.v[q];
+    }
+    const double tau = droptol * std::sqrt(nrm2);
+    while (!lower.empty()) {
+      const int32_t k = lower.top();
+      lower.pop();
+      if (w[k] == 0.0) continue;
+      const double lik = w[k] / F.v[udiag[k]];
+      if (std::fabs(lik) < tau) {
+        w[k] = 0.0;
+        continue;
+      }
+      w[k] = lik;
+      for (int32_t q = udiag[k] + 1; q < F.rp[k + 1]; ++q) {
+        const int32_t j = F.ci[q];
+        if (!in[j]) {
+          in[j] = 1;
+          w[j] = 0.0;
+          touched.push_back(j);
+          if (j < i) lower.push(j);
+        }
+        w[j] -= lik * F.v[q];
+      }
+    }
+    const double diag = in[i] ? w[i] : 0.0;
+    if (diag == 0.0) fail(NAMG_E_ZERO_PIVOT, "zero ILUT pivot in row " + std::to_string(i));
+    lo.clear();
+    up.clear();
+    for (int32_t j : touched) {
+      if (j != i && w[j] != 0.0 && std::fabs(w[j]) >= tau) (j < i ? lo : up).emplace_back(j, w[j]);
+      w[j] = 0.0;
+      in[j] = 0;
+    }
+    touched.clear();
+    keep_largest(lo);
+    keep_largest(up);
+    for (const auto &e : lo) {
+      F.ci.push_back(e.first);
+      F.v.push_back(e.second);
+    }
+    udiag[i] = (int32_t)F.ci.size();
+    F.ci.push_back(i);
+    F.v.push_back(diag);
+    for (const auto &e : up) {
+      F.ci.push_back(e.first);
+      F.v.push_back(e.second);
+    }
+    if (F.ci.size() > (size_t)INT32_MAX) fail(NAMG_E_INVALID, "ILUT factor exceeds 2^31 entries");
+    F.rp[i + 1] = (int32_t)F.ci.size();
+  }
+  return F;
+}
+
 // Strict lower or upper part of a pattern with values vals[k] * scale[row] (scale may be empty).
 HostCsr strict_part(const HostCsr &A, const std::vector<double> &vals, bool lower,
                     const std::vector<double> &scale) {
@@ -442,7 +535,7 @@ std::vector<double> dense_inverse(const HostCsr &A) {
   return inv;
 }
 
-void smoother_data(HostLevel &L, bool with_ilu) {
+void smoother_data(HostLevel &L, bool with_ilu, const namg_setup_params &p) {
   const HostCsr &A = L.A;
   L.dinv.resize(A.nr);
   for (int32_t i = 0; i < A.nr; ++i) {
@@ -465,16 +558,26 @@ void smoother_data(HostLevel &L, bool with_ilu) {
     for (int32_t k = L.pgs_up.rp[i]; k < L.pgs_up.rp[i + 1]; ++k) L.pgs_up.v[k] /= d;
   }
   if (with_ilu) {
-    std::vector<double> w = ilu0_values(A);
+    // L \ U as one CSR: ILU(0) values in A's pattern, or the ILUT factor with its own fill
+    HostCsr F;
+    if (p.ilu_kind == NAMG_ILUT) {
+      F = ilut_factor(A, p.ilut_droptol, p.ilut_lfil);
+    } else {
+      F.nr = A.nr;
+      F.nc = A.nc;
+      F.rp = A.rp;
+      F.ci = A.ci;
+      F.v = ilu0_values(A);
+    }
     L.has_ilu = true;
     L.ilu_dinv.resize(A.nr);
     std::vector<double> du(A.nr);
     for (int32_t i = 0; i < A.nr; ++i)
-      for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
-        if (A.ci[k] == i) du[i] = w[k];
+      for (int32_t k = F.rp[i]; k < F.rp[i + 1]; ++k)
+        if (F.ci[k] == i) du[i] = F.v[k];
     for (int32_t i = 0; i < A.nr; ++i) L.ilu_dinv[i] = 1.0 / du[i];
-    L.ilu_lo = strict_part(A, w, true, {});
-    L.ilu_up = strict_part(A, w, false, {});
+    L.ilu_lo = strict_part(F, F.v, true, {});
+    L.ilu_up = strict_part(F, F.v, false, {});
     for (int32_t i = 0; i < A.nr; ++i)
       for (int32_t k = L.ilu_up.rp[i]; k < L.ilu_up.rp[i + 1]; ++k) L.ilu_up.v[k] /= du[i];
   }
@@ -532,9 +635,13 @@ HostCsr import_csr(int32_t n, const int32_t *rp, const int32_t *ci, const double
   return A;
 }
 
-HostHierarchy build_hierarchy(const HostCsr &A0, double theta, int max_levels, int max_coarse,
-                              int ilu_levels) {
+HostHierarchy build_hierarchy(const HostCsr &A0, const namg_setup_params &p) {
+  const double theta = p.theta;
+  const int max_levels = p.max_levels, max_coarse = p.max_coarse, ilu_levels = p.ilu_levels;
   if (!(theta > 0.0 && theta <= 1.0)) fail(NAMG_E_INVALID, "theta must be in (0, 1]");
+  if (p.ilu_kind != NAMG_ILU0 && p.ilu_kind != NAMG_ILUT) fail(NAMG_E_INVALID, "unknown ilu_kind");
+  if (p.ilu_kind == NAMG_ILUT && (!(p.ilut_droptol >= 0.0) || !std::isfinite(p.ilut_droptol) || p.ilut_lfil < 0))
+    fail(NAMG_E_INVALID, "ILUT needs ilut_droptol >= 0 and ilut_lfil >= 0");
   if (max_levels < 1 || max_levels > NAMG_MAX_LEVELS) fail(NAMG_E_INVALID, "max_levels out of range");
   if (max_coarse < 1) fail(NAMG_E_INVALID, "max_coarse must be >= 1");
   HostHierarchy H;
@@ -587,7 +694,7 @@ HostHierarchy build_hierarchy(const HostCsr &A0, double theta, int max_levels, i
   }
   const int nl = (int)H.lv.size();
   auto t5 = now();
-  for (int l = 0; l < nl - 1; ++l) smoother_data(H.lv[l], ilu_levels < 0 || l < ilu_levels);
+  for (int l = 0; l < nl - 1; ++l) smoother_data(H.lv[l], ilu_levels < 0 || l < ilu_levels, p);
   const HostCsr &Ac = H.lv.back().A;
   if (Ac.nr > 4096) fail(NAMG_E_INVALID, "coarsest level has more than 4096 rows; raise max_levels");
   H.coarse_inv = dense_inverse(Ac);

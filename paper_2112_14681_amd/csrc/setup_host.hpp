@@ -7,6 +7,8 @@
 #include <string>
 #include <vector>
 
+#include "../../include/namg.h"
+
 namespace namg {
 
 struct HostCsr {
@@ -48,7 +50,9 @@ struct HostHierarchy {
 // Throws SetupError{NAMG_E_INVALID / NAMG_E_NONFINITE / NAMG_E_ZERO_PIVOT} on malformed input.
 HostCsr import_csr(int32_t n, const int32_t *rp, const int32_t *ci, const double *v);
 
-HostHierarchy build_hierarchy(const HostCsr &A, double theta, int max_levels, int max_coarse, int ilu_levels);
+// The hierarchy of namg_setup_params p (theta, max_levels, max_coarse and the ILU fields; precision and
+// device are the caller's). Throws SetupError on invalid parameters or a zero pivot.
+HostHierarchy build_hierarchy(const HostCsr &A, const namg_setup_params &p);
 
 // Dependency levels of a strict lower (lower = true) or upper triangle, for the direct comparators.
 LevelSchedule level_schedule(const HostCsr &T, bool lower);

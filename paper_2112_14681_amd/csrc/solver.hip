@@ -911,6 +911,9 @@ void namg_default_setup_params(namg_setup_params *p) {
   p->precision = NAMG_FP64;
   p->ilu_levels = 1;
   p->device = 0;
+  p->ilu_kind = NAMG_ILU0;
+  p->ilut_lfil = 5;
+  p->ilut_droptol = 1e-2;
 }
 
 void namg_default_solve_params(namg_solve_params *p) {
@@ -937,7 +940,7 @@ int namg_setup(int32_t n, const int32_t *rowptr, const int32_t *colind, const do
       throw namg::SetupError{NAMG_E_INVALID, "unknown precision"};
     namg::HostCsr A = namg::import_csr(n, rowptr, colind, vals);
     auto h = std::make_unique<namg_hier>();
-    h->host = namg::build_hierarchy(A, p->theta, p->max_levels, p->max_coarse, p->ilu_levels);
+    h->host = namg::build_hierarchy(A, *p);
     h->precision = p->precision;
     h->device = p->device;
     if (p->device >= 0) {
@@ -1046,6 +1049,28 @@ int namg_export_level(const namg_hier *h, int level, int8_t *cf, int32_t *A_rowp
       if (P_colind) std::copy(L.P.ci.begin(), L.P.ci.end(), P_colind);
       if (P_vals) std::copy(L.P.v.begin(), L.P.v.end(), P_vals);
     }
+    return NAMG_OK;
+  });
+}
+
+int namg_export_ilu(const namg_hier *h, int level, int64_t *nnz_lower, int64_t *nnz_upper, int32_t *L_rowptr,
+                    int32_t *L_colind, double *L_vals, int32_t *U_rowptr, int32_t *U_colind, double *U_vals,
+                    double *d_inv) {
+  return guarded([&]() -> int {
+    if (!h) throw namg::SetupError{NAMG_E_INVALID, "null hierarchy"};
+    if (level < 0 || level >= (int)h->host.lv.size()) throw namg::SetupError{NAMG_E_INVALID, "level out of range"};
+    const auto &L = h->host.lv[level];
+    if (!L.has_ilu) throw namg::SetupError{NAMG_E_INVALID, "level carries no ILU factors"};
+    if (nnz_lower) *nnz_lower = (int64_t)L.ilu_lo.ci.size();
+    if (nnz_upper) *nnz_upper = (int64_t)L.ilu_up.ci.size();
+    auto put = [](const namg::HostCsr &T, int32_t *rp, int32_t *ci, double *v) {
+      if (rp) std::copy(T.rp.begin(), T.rp.end(), rp);
+      if (ci) std::copy(T.ci.begin(), T.ci.end(), ci);
+      if (v) std::copy(T.v.begin(), T.v.end(), v);
+    };
+    put(L.ilu_lo, L_rowptr, L_colind, L_vals);
+    put(L.ilu_up, U_rowptr, U_colind, U_vals);
+    if (d_inv) std::copy(L.ilu_dinv.begin(), L.ilu_dinv.end(), d_inv);
     return NAMG_OK;
   });
 }

@@ -255,6 +255,53 @@ def test_solve_c2_ilu_hybrid_parity(namg, tri):
                  inner_terms=3)
 
 
+@pytest.mark.parametrize("droptol,lfil", [(1e-2, 5), (1e-3, 10), (1e-2, 0)])
+def test_ilut_sweeps_vcycle_and_solves(namg, droptol, lfil):
+    """ILUT(droptol, lfil) factors (Algorithm 2 with row scaling) in place of ILU(0): single sweeps on the
+    two finest levels (Neumann t = 1, 2, 3, 5 and direct substitution) match the oracle's ILUT sweep on
+    the same level operator to 1e-12; the hybrid solve (ILUT on the finest level, polynomial GS below;
+    Neumann t = 3 and direct) takes the oracle's iterations with x within 1e-10. lfil = 0 leaves both
+    strict triangles empty (the sweep is a Jacobi step)."""
+    A, b, _ = config_system("c2", 23)
+    setup = dict(ilu_kind=namg.ILUT, ilut_droptol=droptol, ilut_lfil=lfil)
+    H = namg.Hierarchy(A, device=0, ilu_levels=-1, **setup)
+    rng = np.random.default_rng(31)
+    for level in (0, 1):
+        Al, _ = level_csr(H, level)
+        x, bb = rng.standard_normal(Al.n), rng.standard_normal(Al.n)
+        out = torch.empty(Al.n, dtype=torch.float64, device="cuda:0")
+        for tri, t in ((0, 1), (0, 2), (0, 3), (0, 5), (1, 1)):
+            H.apply(level, namg.OP_SMOOTH_PRE, dev(x), dev(bb), out, smoother=1, tri_mode=tri, inner_terms=t)
+            ref = O.smooth_ilut(Al, droptol, lfil, t, bb, x, direct=bool(tri))
+            assert relerr(host(out), ref) <= TOL64, (level, tri, t)
+    G = O.Hierarchy(A, ilu_kind=O.ILU_KIND_ILUT, ilut_droptol=droptol, ilut_lfil=lfil)
+    H1 = namg.Hierarchy(A, device=0, **setup)
+    gv = G.vcycle(b, smoother=1, tri_mode=0, t=3)
+    out = torch.empty(A.n, dtype=torch.float64, device="cuda:0")
+    H1.vcycle(dev(b), out, smoother=1, tri_mode=0, inner_terms=3)
+    assert relerr(host(out), gv) <= TOL64
+    for tri in (0, 1):
+        _check_solve(namg, A, b, H1, G, smoother=1, tri_mode=tri, inner_terms=3)
+
+
+def test_ilut_fp32_and_server(namg):
+    """ILUT with the FP32 preconditioner reaches the FP64 oracle's residual, and a served request with
+    ILUT setup parameters gives the oracle's iterations and iterate."""
+    A, b, _ = config_system("c2", 20)
+    setup = dict(ilu_kind=namg.ILUT, ilut_droptol=1e-2, ilut_lfil=5)
+    ref = O.Hierarchy(A, ilu_kind=O.ILU_KIND_ILUT, ilut_droptol=1e-2, ilut_lfil=5).solve(b, t=3, smoother=1)
+    H32 = namg.Hierarchy(A, device=0, precision=namg.FP32_PRECOND, **setup)
+    xt = dev(np.zeros(A.n))
+    st = H32.solve(dev(b), xt, smoother=1, inner_terms=3)
+    x = host(xt)
+    assert st["status"] == namg.OK and np.linalg.norm(b - O.spmv(A, x)) <= 1e-8 * np.linalg.norm(b)
+    assert abs(st["iters"] - ref["iters"]) <= 2 and relerr(x, ref["x"]) <= 1e-6
+    srv = namg.Server(solve=dict(smoother=1, inner_terms=3), max_inflight=2, setup_threads=1, precision=0)
+    r = srv.wait(srv.submit(A, b, **setup))
+    srv.close()
+    assert r["status"] == namg.OK and r["iters"] == ref["iters"] and relerr(r["x"], ref["x"]) <= 1e-10
+
+
 def test_solve_c3_and_c4_parity(namg):
     for name, N, kw in (("c3", 20, dict(smoother=0, inner_terms=2)), ("c4r", 16, dict(smoother=1, inner_terms=3)),
                         ("c4rcm", 16, dict(smoother=1, inner_terms=3, restart=50))):

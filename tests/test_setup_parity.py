@@ -82,6 +82,63 @@ def test_setup_at_64cubed_bit_exact(namg, oracle_lib):
     assert info["levels"] == 7
 
 
+def _check_ilu_factors(namg, oracle_lib, A, ilu_levels=1, **ilu):
+    """The library's smoother factors on every ILU level equal the oracle's factorization of the same
+    (bit-exact) level operator: L_s, U_s = D_U^{-1} strict(U) and 1/u_ii, pattern and value."""
+    O = oracle_lib
+    H = namg.Hierarchy(A, device=-1, ilu_levels=ilu_levels, **ilu)
+    G = O.Hierarchy(A, ilu_levels=0)
+    nl = H.info()["levels"]
+    top = nl - 1 if ilu_levels < 0 else min(ilu_levels, nl - 1)
+    for l in range(top):
+        Al = G.level(l).A
+        if ilu.get("ilu_kind", namg.ILU0) == namg.ILUT:
+            F = O.ilut(Al, ilu["ilut_droptol"], ilu["ilut_lfil"])
+        else:
+            F = CSR(Al.n, Al.rowptr, Al.colind, O.ilu0(Al))
+        e = H.export_ilu(l)
+        rows = np.repeat(np.arange(F.n), np.diff(F.rowptr))
+        lo, up, dg = F.colind < rows, F.colind > rows, F.colind == rows
+        Lrp, Lci, Lv = e["L"]
+        Urp, Uci, Uv = e["U"]
+        np.testing.assert_array_equal(Lrp, np.concatenate([[0], np.cumsum(np.bincount(rows[lo], minlength=F.n))]))
+        np.testing.assert_array_equal(Lci, F.colind[lo])
+        assert np.array_equal(Lv, F.vals[lo]), l
+        np.testing.assert_array_equal(Urp, np.concatenate([[0], np.cumsum(np.bincount(rows[up], minlength=F.n))]))
+        np.testing.assert_array_equal(Uci, F.colind[up])
+        du = F.vals[dg]
+        assert np.array_equal(Uv, F.vals[up] / du[rows[up]]), l
+        assert np.array_equal(e["dinv"], 1.0 / du), l
+    with pytest.raises(namg.NamgError):
+        H.export_ilu(top)  # the first level without factors (or the coarsest)
+
+
+@pytest.mark.parametrize("name,N", [("c1", None), ("c2", 20), ("c3", 18), ("c4r", 14), ("c4n", 12)])
+@pytest.mark.parametrize("ilu", [dict(), dict(ilu_kind=1, ilut_droptol=1e-2, ilut_lfil=5),
+                                 dict(ilu_kind=1, ilut_droptol=1e-3, ilut_lfil=10),
+                                 dict(ilu_kind=1, ilut_droptol=0.0, ilut_lfil=2)])
+def test_ilu_factors_bit_exact_vs_oracle(namg, oracle_lib, name, N, ilu):
+    A, _, _ = config_system(name, N)
+    _check_ilu_factors(namg, oracle_lib, A, **ilu)
+
+
+def test_ilut_every_level_and_nonsymmetric(namg, oracle_lib):
+    """ILUT on every level but the coarsest, on a nonsymmetric random matrix and on ragged coarse levels."""
+    _check_ilu_factors(namg, oracle_lib, config_system("c2", 17)[0], ilu_levels=-1, ilu_kind=namg.ILUT,
+                       ilut_droptol=1e-2, ilut_lfil=5)
+    _check_ilu_factors(namg, oracle_lib, random_csr(300, 7, 9), ilu_levels=-1, ilu_kind=namg.ILUT,
+                       ilut_droptol=5e-3, ilut_lfil=4)
+
+
+def test_ilut_parameter_validation(namg):
+    A = poisson2d(12)
+    for bad in (dict(ilu_kind=2), dict(ilu_kind=1, ilut_lfil=-1), dict(ilu_kind=1, ilut_droptol=-1e-3),
+                dict(ilu_kind=1, ilut_droptol=float("nan")), dict(ilu_kind=1, ilut_droptol=float("inf"))):
+        assert _err(namg, lambda: namg.Hierarchy(A, device=-1, **bad)) == namg.E_INVALID, bad
+    p = namg.setup_params()
+    assert (p.ilu_kind, p.ilut_lfil, p.ilut_droptol) == (namg.ILU0, 5, 1e-2)
+
+
 def test_hierarchy_info_complexities(namg):
     A = poisson3d(16)
     info = namg.Hierarchy(A, device=-1).info()
