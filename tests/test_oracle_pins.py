@@ -671,3 +671,117 @@ def test_not_converged_status_and_error_paths(oracle_lib):
     with pytest.raises(O.OracleFailure) as e:
         O.Hierarchy(Z)
     assert e.value.code == O.E_INVALID
+
+
+# ------------------------------------------------------------------- non-normality (Section 5.3.4)
+def test_henrici_departure_closed_forms():
+    """dep(T)^2 = ||T||_F^2 - sum |lambda|^2: zero for normal matrices, |a| for [[1, a], [0, 2]], and
+    ||strict(T)||_F for any triangular T (its eigenvalues are its diagonal)."""
+    from oracle.nonnormal import henrici_dep
+
+    assert henrici_dep(np.array([[1.0, -3.5], [0.0, 2.0]])) == pytest.approx(3.5, rel=1e-14)
+    rng = np.random.default_rng(3)
+    S = rng.standard_normal((30, 30))
+    S = S + S.T
+    Q, _ = np.linalg.qr(rng.standard_normal((30, 30)))
+    for N in (S, Q):
+        assert henrici_dep(N) <= 1e-6 * np.linalg.norm(N, "fro")
+    T = np.triu(rng.standard_normal((40, 40)))
+    assert henrici_dep(T) == pytest.approx(np.linalg.norm(np.triu(T, 1), "fro"), rel=1e-10)
+
+
+def test_ruiz_equilibrates_rows_and_columns():
+    """Ruiz scaling converges to a matrix whose every row and column has largest magnitude 1 (to tol);
+    a symmetric matrix gets equal row and column scalings; a diagonal matrix becomes I in one step."""
+    from oracle.nonnormal import ruiz
+
+    A = random_csr(60, 6, 5).to_dense()
+    U = np.triu(A) * np.exp(np.random.default_rng(1).uniform(-6, 6, 60))[:, None]  # badly row-scaled
+    dr, dc, it = ruiz(U, 1e-10, 100)
+    S = np.abs(dr[:, None] * U * dc[None, :])
+    assert 1 <= it < 100
+    np.testing.assert_allclose(S.max(axis=1), 1.0, atol=1e-10)
+    np.testing.assert_allclose(S.max(axis=0), 1.0, atol=1e-10)
+    As = A + A.T
+    dr, dc, _ = ruiz(As, 1e-12, 100)
+    np.testing.assert_array_equal(dr, dc)
+    D = np.diag(np.arange(1.0, 9.0) ** 3)
+    dr, dc, it = ruiz(D, 1e-14, 10)
+    assert it == 1
+    np.testing.assert_allclose(dr[:, None] * D * dc[None, :], np.eye(8), atol=1e-15)
+
+
+@pytest.mark.parametrize("droptol,lfil", [(1e-2, 5), (1e-3, 10), (1e-1, 2)])
+def test_theorems_1_to_4_hold_on_ilut_factors(oracle_lib, droptol, lfil):
+    """Section 5.3.4 on ILUT factors of a nonsymmetric 3-D operator and of 2-D Poisson, row-scaled
+    U = D_U (I + U_s): ||U_s||_2 <= ||U_s||_F <= sqrt(n (p - 1)) when the entries of U_s are at most 1
+    (Theorem 1); 1/sqrt(rank) <= ||U_s||_2 when ||U_s||_2 < 1 < ||U_s||_F (Theorem 2); dep(I + U_s),
+    which equals ||U_s||_F, is within the bounds of Theorems 3 and 4; Ruiz scaling lowers dep(U) of
+    these badly row-scaled factors."""
+    from oracle.nonnormal import factor_diagnostics, henrici_dep, split_factor
+
+    O = oracle_lib
+    for A in (convdiff3d(5, 3)[0], poisson2d(14)):
+        F = O.ilut(A, droptol, lfil)
+        d = factor_diagnostics(F)
+        _, U = split_factor(F)
+        Us = np.triu(U / np.diag(U)[:, None], 1)
+        assert d["norm2_Us"] <= d["nu"] * (1 + 1e-12)
+        if np.abs(Us).max() <= 1.0:
+            assert d["nu"] <= d["th1_bound"]
+        if d["norm2_Us"] < 1.0 < d["nu"]:
+            assert 1.0 / np.sqrt(np.linalg.matrix_rank(Us)) <= d["norm2_Us"]
+        dep1 = henrici_dep(np.eye(F.n) + Us)
+        assert dep1 == pytest.approx(d["nu"], rel=1e-10)
+        assert dep1 <= d["th3_bound"] and dep1 <= d["th4_bound"] * (1 + 1e-12)
+        assert d["max_row_upper"] <= lfil + 1
+    # a factor with rows of very different scale: Ruiz brings dep(U) down by orders of magnitude
+    A = convdiff3d(5, 3)[0]
+    w = np.exp(np.random.default_rng(0).uniform(-5, 5, A.n))
+    As = CSR.from_dense(A.to_dense() * w[:, None])
+    d = factor_diagnostics(O.ilut(As, 1e-2, 5))
+    assert d["dep_U_ruiz"] < 1e-2 * d["dep_U"]
+
+
+def test_ruiz_jacobi_equals_row_scaled_jacobi(oracle_lib):
+    """Algorithm 2 with Ruiz scaling U~ = D_r U D_c, the transforms y~ = D_r y and v = D_c v~ (the ones that
+    make U~ v~ = y~ equivalent to U v = y) and D = diag(U~)^{-1}: since diagonal scalings commute,
+    D_c D D_r = D_U^{-1}, so every Jacobi iterate equals the row-scaled one (the smoother's form). With the
+    transforms as printed (D_r^{-1} y, D_c^{-1} v~) the iteration does not solve U v = y."""
+    from oracle.nonnormal import ruiz, split_factor
+
+    O = oracle_lib
+    A = convdiff3d(4, 3)[0]
+    _, U = split_factor(O.ilut(A, 1e-2, 5))
+    n = A.n
+    dr, dc, _ = ruiz(U, 1e-12, 50)
+    Ut = dr[:, None] * U * dc[None, :]
+    D = 1.0 / np.diag(Ut)
+    y = np.random.default_rng(8).standard_normal(n)
+    v, vt, vp = np.zeros(n), np.zeros(n), np.zeros(n)
+    yt, yp = dr * y, y / dr
+    for _ in range(60):
+        v = v + (y - U @ v) / np.diag(U)
+        vt = vt + D * (yt - Ut @ vt)
+        vp = vp + D * (yp - Ut @ vp)
+        np.testing.assert_allclose(dc * vt, v, rtol=1e-11, atol=1e-13 * np.abs(v).max())
+    assert np.linalg.norm(y - U @ v) <= 1e-12 * np.linalg.norm(y)
+    assert np.linalg.norm(y - U @ (vp / dc)) > 1e-3 * np.linalg.norm(y)
+
+
+def test_jacobi_triangular_residuals(oracle_lib):
+    """Table 2's residuals: one iteration gives y = b and v = D_U^{-1} y, so the residuals are
+    ||L_s b|| / ||b|| and ||strict(U) v|| / ||y||; at the dependency depth both solves are exact."""
+    from oracle.nonnormal import jacobi_tri_residuals, split_factor
+
+    O = oracle_lib
+    A = poisson2d(9)
+    F = O.ilut(A, 1e-3, 4)
+    L, U = split_factor(F)
+    b = np.random.default_rng(2).standard_normal(A.n)
+    rl, ru = jacobi_tri_residuals(F, b, 1)
+    assert rl == pytest.approx(np.linalg.norm((L - np.eye(A.n)) @ b) / np.linalg.norm(b), rel=1e-13)
+    v = b / np.diag(U)
+    assert ru == pytest.approx(np.linalg.norm(np.triu(U, 1) @ v) / np.linalg.norm(b), rel=1e-13)
+    rl, ru = jacobi_tri_residuals(F, b, A.n)
+    assert rl <= 1e-14 and ru <= 1e-13
