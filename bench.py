@@ -43,6 +43,11 @@ def _args():
     ap.add_argument("--serve-inflight", type=int, default=64)
     ap.add_argument("--serve-setup-threads", type=int, default=14)
     ap.add_argument("--serve-only", action="store_true")
+    ap.add_argument("--nonnormality", action="store_true",
+                    help="the factor study of Section 5.3.4 instead of the benchmark: orderings of C4 (Table 2) "
+                         "and an ILUT fill sweep (Tables 3-5), with GMRES iterations when a GPU is present")
+    ap.add_argument("--nn-N", type=int, default=128, help="grid size of the ordering study")
+    ap.add_argument("--nn-fill-N", type=int, default=64, help="grid size of the fill sweep")
     return ap.parse_args()
 
 
@@ -184,16 +189,76 @@ def cpu_baseline(A, b, kw, gpu_iters):
                       f"{r['relres_true']:.1e}; GPU {gpu_iters}); oracle setup {setup_s:.1f} s excluded"}
 
 
+def nonnormality_study(namg, torch, N, fill_N):
+    """Section 5.3.4 on our workloads, one JSON object. (1) Orderings (Table 2 and its dep table): C4,
+    upwind convection-diffusion, in natural, random and RCM-of-random order, ILU(0) on the finest level:
+    dep(L), dep(U), ||U_s||_F, ||U_s||_2, the residuals of 5 Jacobi iterations for L y = b and U v = y,
+    and the hybrid GMRES(30) solve (ILU(0) Neumann t = 3) when a GPU is present. (2) Fill sweep (Tables
+    3 to 5): ILUT(1e-3, lfil) on the finest level of C4 natural at fill_N^3 for lfil = 5, 10, 20, 50:
+    ||U_s||_2, ||U_s||_F and Theorem 1's bound, dep(U) before and after Ruiz scaling with Theorem 3's
+    bound, and GMRES iterations."""
+    from workloads import config_system
+
+    gpu = torch is not None and torch.cuda.is_available()
+    dev = 0 if gpu else -1
+    solve_kw = dict(tol=1e-8, restart=30, smoother=namg.SMOOTH_ILU0, tri_mode=namg.TRI_NEUMANN, inner_terms=3)
+
+    def solve(H, b):
+        if not gpu:
+            return {}
+        bt = torch.from_numpy(b).to("cuda:0")
+        xt = torch.zeros_like(bt)
+        ms, st = _time_solves(torch, H, bt, xt, solve_kw, 2, 1)
+        return {"gmres_iters": st[-1]["iters"], "solve_ms": round(ms, 3), "relres": st[-1]["relres_true"]}
+
+    def diag(H, b):
+        d = H.ilu_diagnostics(0, power_iters=100)
+        rl, ru = H.tri_jacobi_residuals(0, b, 5)
+        keep = ("nnz_lower", "nnz_upper", "max_row_upper", "dep_L", "dep_U", "nu", "norm2_Us", "th1_bound",
+                "dep_U_ruiz", "ruiz_iters", "th3_bound", "delta", "th4_bound")
+        out = {k: (round(d[k], 6) if isinstance(d[k], float) else d[k]) for k in keep}
+        out.update(jacobi5_res_L=rl, jacobi5_res_U=ru)
+        return out
+
+    orderings = {}
+    for name in ("c4n", "c4r", "c4rcm"):
+        A, b, _ = config_system(name, N)
+        t0 = time.perf_counter()
+        H = namg.Hierarchy(A, device=dev, ilu_levels=1)
+        row = {"setup_ms": round((time.perf_counter() - t0) * 1e3, 1)}
+        row.update(diag(H, b))
+        row.update(solve(H, b))
+        H.close()
+        orderings[name] = row
+        print(f"[nonnormality] ordering {name} done", file=sys.stderr, flush=True)
+    fill = {}
+    A, b, _ = config_system("c4n", fill_N)
+    for lfil in (5, 10, 20, 50):
+        H = namg.Hierarchy(A, device=dev, ilu_levels=1, ilu_kind=namg.ILUT, ilut_droptol=1e-3, ilut_lfil=lfil)
+        row = diag(H, b)
+        row.update(solve(H, b))
+        H.close()
+        fill[str(lfil)] = row
+        print(f"[nonnormality] lfil {lfil} done", file=sys.stderr, flush=True)
+    return {"metric": "non-normality of the ILU factors (Section 5.3.4)", "gpu": gpu,
+            "orderings": {"workload": f"c4 convection-diffusion {N}^3, ILU(0) finest level", **orderings},
+            "fill_sweep": {"workload": f"c4n {fill_N}^3, ILUT(droptol 1e-3, lfil)", **fill}}
+
+
 def main():
     args = _args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the solve phase is not sharded in this build "
-              "(see the multi-GPU design notes); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the solve phase is not sharded across GPUs "
+              "(the row-sharded design is described, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
 
     import paper_2112_14681_amd as namg
     from workloads import config_system
+
+    if args.nonnormality:
+        print(json.dumps(nonnormality_study(namg, torch, args.nn_N, args.nn_fill_N)), flush=True)
+        return
 
     if args.serve_only:
         print(json.dumps({"metric": "served latency of the pressure-system request stream",

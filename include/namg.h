@@ -113,7 +113,7 @@ void namg_default_solve_params(namg_solve_params *p);
 
 /* AMG setup (Section 5 and 5.1): per level the strength graph S (|a_ij| >= theta max_{k!=i}|a_ik|), the
  * Ruge-Stueben first-pass C/F splitting, classical interpolation P, R = P^T and the Galerkin operator
- * A_{l+1} = P^T A_l P; ILU(0) of the first ilu_levels levels (Section 5.3); the coarsest level's dense
+ * A_{l+1} = P^T A_l P; ILU(0) or ILUT of the first ilu_levels levels (Section 5.3); the coarsest level's dense
  * inverse. Runs on the host in FP64, then uploads (FP64 or FP32 copies) to p->device.
  * rowptr/colind/vals: host CSR of A (n rows). *out receives a new handle (release with namg_destroy).
  * Errors: NAMG_E_INVALID, NAMG_E_NONFINITE, NAMG_E_ZERO_PIVOT, NAMG_E_NOMEM, NAMG_E_HIP. */
@@ -196,6 +196,36 @@ int namg_export_level(const namg_hier *h, int level, int8_t *cf, int32_t *A_rowp
 int namg_export_ilu(const namg_hier *h, int level, int64_t *nnz_lower, int64_t *nnz_upper, int32_t *L_rowptr,
                     int32_t *L_colind, double *L_vals, int32_t *U_rowptr, int32_t *U_colind, double *U_vals,
                     double *d_inv);
+
+/* Non-normality of the ILU factors of level l (Section 5.3.4), computed on the host from the factors the
+ * smoother applies (L = I + L_s; U = D_U (I + U_s), D_U = diag(U)). Departure from normality (Henrici):
+ * dep(T)^2 = ||T||_F^2 - sum |lambda_i(T)|^2, which for a triangular T is ||strict(T)||_F^2. */
+typedef struct {
+  int64_t n, nnz_lower, nnz_upper; /* rows; stored strict entries of L_s and U_s */
+  int max_row_upper;   /* p: most stored entries in a row of U, diagonal included */
+  int ruiz_iters;      /* Ruiz iterations taken (<= ruiz_max_iters) */
+  double dep_L;        /* dep(L) = ||L_s||_F */
+  double dep_U;        /* dep(U) = ||strict(U)||_F, unscaled */
+  double nu;           /* ||U_s||_F = dep(I + U_s) */
+  double norm2_Us;     /* ||U_s||_2 = sigma_1(U_s): power iteration on U_s^T U_s, a lower estimate */
+  double th1_bound;    /* Theorem 1: sqrt(n (p - 1)) */
+  double th3_bound;    /* Theorem 3: sqrt((2 sqrt(n) + nu) nu) */
+  double delta;        /* max_i max(0, sum_j |(U_s)_ij| - 1): near diagonal dominance of I + U_s */
+  double th4_bound;    /* Theorem 4: sqrt(n) (1 + delta) */
+  double dep_U_ruiz;   /* dep(D_r U D_c) after Ruiz scaling: rows and columns scaled together by
+                          1/sqrt(largest magnitude) until each is within ruiz_tol of 1 */
+} namg_ilu_diag;
+
+/* Fill *out for level l. power_iters >= 1 (iterations for norm2_Us; the start vector is fixed), ruiz_max_iters
+ * >= 0, ruiz_tol >= 0. NAMG_E_INVALID if the level carries no ILU factors or an argument is out of range. */
+int namg_ilu_diagnostics(const namg_hier *h, int level, int power_iters, int ruiz_max_iters, double ruiz_tol,
+                         namg_ilu_diag *out);
+
+/* Table 2's measure on level l: `iters` Jacobi iterations from zero for L y = b (y <- y + (b - L y)), then
+ * for U v = y with row scaling (v <- v + D_U^{-1}(y - U v)); *res_L = ||b - L y|| / ||b||,
+ * *res_U = ||y - U v|| / ||y||. b: host array of n_l doubles; iters >= 0. */
+int namg_tri_jacobi_residuals(const namg_hier *h, int level, const double *b, int iters, double *res_L,
+                              double *res_U);
 
 /* ---- Serving (continuous batching of many solves on one GPU) ------------------------------------- */
 

@@ -31,9 +31,8 @@ KF_NONE, KF_NEUMANN, KF_RESIDUAL, KF_SPMV, KF_PROLONG, KF_GMRES_SPMV, KF_MULTIDO
 EXPORTED = (
     "namg_default_setup_params", "namg_default_solve_params", "namg_setup", "namg_solve", "namg_vcycle",
     "namg_apply", "namg_profile_kernel", "namg_profile_read", "namg_hier_info", "namg_level_sizes",
-    "namg_export_level", "namg_export_ilu", "namg_destroy", "namg_last_error", "namg_default_server_params",
-    "namg_server_create",
-    "namg_server_submit", "namg_server_poll", "namg_server_wait", "namg_server_stats", "namg_server_clock",
+    "namg_export_level", "namg_export_ilu", "namg_ilu_diagnostics", "namg_tri_jacobi_residuals", "namg_destroy",
+    "namg_last_error", "namg_default_server_params", "namg_server_create", "namg_server_submit", "namg_server_poll", "namg_server_wait", "namg_server_stats", "namg_server_clock",
     "namg_server_destroy",
 )
 
@@ -48,6 +47,16 @@ class SolveParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int), ("max_iters", C.c_int), ("smoother", C.c_int),
                 ("tri_mode", C.c_int), ("inner_terms", C.c_int), ("gmres_T", C.c_int), ("pre_sweeps", C.c_int),
                 ("post_sweeps", C.c_int), ("t_degree", C.c_int), ("stop_rule", C.c_int)]
+
+
+class IluDiag(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz_lower", C.c_int64), ("nnz_upper", C.c_int64), ("max_row_upper", C.c_int),
+                ("ruiz_iters", C.c_int), ("dep_L", C.c_double), ("dep_U", C.c_double), ("nu", C.c_double),
+                ("norm2_Us", C.c_double), ("th1_bound", C.c_double), ("th3_bound", C.c_double),
+                ("delta", C.c_double), ("th4_bound", C.c_double), ("dep_U_ruiz", C.c_double)]
+
+    def as_dict(self):
+        return {f[0]: getattr(self, f[0]) for f in self._fields_}
 
 
 class SolveStats(C.Structure):
@@ -255,6 +264,22 @@ class Hierarchy:
                                     _ptr(L[1], C.c_int32), _ptr(L[2], C.c_double), _ptr(U[0], C.c_int32),
                                     _ptr(U[1], C.c_int32), _ptr(U[2], C.c_double), _ptr(dinv, C.c_double)))
         return {"L": L, "U": U, "dinv": dinv}
+
+    def ilu_diagnostics(self, level, power_iters=100, ruiz_max_iters=20, ruiz_tol=1e-8) -> dict:
+        """Non-normality of the level's ILU factors (namg_ilu_diagnostics)."""
+        d = IluDiag()
+        _check(_lib.namg_ilu_diagnostics(self.h, level, power_iters, ruiz_max_iters, C.c_double(ruiz_tol),
+                                         C.byref(d)))
+        return d.as_dict()
+
+    def tri_jacobi_residuals(self, level, b, iters) -> tuple:
+        """(||b - L y|| / ||b||, ||y - U v|| / ||y||) after `iters` Jacobi iterations (host b)."""
+        bb = np.ascontiguousarray(b, dtype=np.float64)
+        if bb.shape != (self.level_sizes(level)[0],):
+            raise ValueError("b must have n_l entries")
+        rl, ru = C.c_double(), C.c_double()
+        _check(_lib.namg_tri_jacobi_residuals(self.h, level, _ptr(bb, C.c_double), iters, C.byref(rl), C.byref(ru)))
+        return rl.value, ru.value
 
     def solve(self, b, x, stream=None, **params) -> dict:
         """namg_solve on device tensors b (read) and x (initial guess in, solution out)."""

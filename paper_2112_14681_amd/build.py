@@ -1,8 +1,8 @@
 """Build libnamg.so in-tree for gfx950.
 
-Host setup (setup_host.cpp) is compiled with g++ -ffp-contract=off so that coarse operators are summed in
-their documented order; the HIP translation unit is compiled with hipcc for gfx950 with packed-FP32
-instructions disabled.
+Host setup (setup_host.cpp) and the factor diagnostics (diagnostics.cpp) are compiled with g++
+-ffp-contract=off so that coarse operators are summed in their documented order; the HIP translation unit
+is compiled with hipcc for gfx950 with packed-FP32 instructions disabled.
 """
 from __future__ import annotations
 
@@ -27,9 +27,12 @@ def build(verbose: bool = True) -> str:
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     os.makedirs(BUILD, exist_ok=True)
     host_o = os.path.join(BUILD, "setup_host.o")
+    diag_o = os.path.join(BUILD, "diagnostics.o")
     dev_o = os.path.join(BUILD, "solver.o")
     _run(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fPIC", "-Wall", "-c",
           os.path.join(CSRC, "setup_host.cpp"), "-o", host_o])
+    _run(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fPIC", "-Wall", "-c",
+          os.path.join(CSRC, "diagnostics.cpp"), "-o", diag_o])
     # kernarg preloading: the leading kernel arguments arrive in scalar registers (the compiler keeps a
     # loading prologue for firmware that does not preload)
     _run([hipcc, f"--offload-arch={ARCH}", "-std=c++17", "-O3", "-fPIC", "-Wall",
@@ -37,7 +40,7 @@ def build(verbose: bool = True) -> str:
           "-mllvm", "-amdgpu-kernarg-preload-count=16",
           "-c", os.path.join(CSRC, "solver.hip"), "-o", dev_o])
     tmp = LIB + ".tmp"
-    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", host_o, dev_o, "-o", tmp])
+    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", host_o, diag_o, dev_o, "-o", tmp])
     os.replace(tmp, LIB)
     return LIB
 

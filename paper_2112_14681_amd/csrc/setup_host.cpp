@@ -576,6 +576,7 @@ void smoother_data(HostLevel &L, bool with_ilu, const namg_setup_params &p) {
       for (int32_t k = F.rp[i]; k < F.rp[i + 1]; ++k)
         if (F.ci[k] == i) du[i] = F.v[k];
     for (int32_t i = 0; i < A.nr; ++i) L.ilu_dinv[i] = 1.0 / du[i];
+    L.ilu_diag = du;
     L.ilu_lo = strict_part(F, F.v, true, {});
     L.ilu_up = strict_part(F, F.v, false, {});
     for (int32_t i = 0; i < A.nr; ++i)

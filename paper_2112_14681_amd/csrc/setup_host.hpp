@@ -39,6 +39,7 @@ struct HostLevel {
   bool has_ilu = false;
   HostCsr ilu_lo, ilu_up;      // L_s (strict lower of the unit-diagonal L) and U_s = D_U^{-1} U - I
   std::vector<double> ilu_dinv;  // 1 / u_ii
+  std::vector<double> ilu_diag;  // u_ii
 };
 
 struct HostHierarchy {
@@ -56,5 +57,10 @@ HostHierarchy build_hierarchy(const HostCsr &A, const namg_setup_params &p);
 
 // Dependency levels of a strict lower (lower = true) or upper triangle, for the direct comparators.
 LevelSchedule level_schedule(const HostCsr &T, bool lower);
+
+// Non-normality diagnostics of a level's ILU factors and the Jacobi triangular-solve residuals
+// (diagnostics.cpp). Throw SetupError on invalid arguments.
+void ilu_diagnostics(const HostLevel &L, int power_iters, int ruiz_max_iters, double ruiz_tol, namg_ilu_diag *out);
+void tri_jacobi_residuals(const HostLevel &L, const double *b, int iters, double *res_L, double *res_U);
 
 }  // namespace namg

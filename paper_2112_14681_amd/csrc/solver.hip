@@ -1075,6 +1075,26 @@ int namg_export_ilu(const namg_hier *h, int level, int64_t *nnz_lower, int64_t *
   });
 }
 
+int namg_ilu_diagnostics(const namg_hier *h, int level, int power_iters, int ruiz_max_iters, double ruiz_tol,
+                         namg_ilu_diag *out) {
+  return guarded([&]() -> int {
+    if (!h || !out) throw namg::SetupError{NAMG_E_INVALID, "null argument"};
+    if (level < 0 || level >= (int)h->host.lv.size()) throw namg::SetupError{NAMG_E_INVALID, "level out of range"};
+    namg::ilu_diagnostics(h->host.lv[level], power_iters, ruiz_max_iters, ruiz_tol, out);
+    return NAMG_OK;
+  });
+}
+
+int namg_tri_jacobi_residuals(const namg_hier *h, int level, const double *b, int iters, double *res_L,
+                              double *res_U) {
+  return guarded([&]() -> int {
+    if (!h || !res_L || !res_U) throw namg::SetupError{NAMG_E_INVALID, "null argument"};
+    if (level < 0 || level >= (int)h->host.lv.size()) throw namg::SetupError{NAMG_E_INVALID, "level out of range"};
+    namg::tri_jacobi_residuals(h->host.lv[level], b, iters, res_L, res_U);
+    return NAMG_OK;
+  });
+}
+
 void namg_destroy(namg_hier *h) {
   if (!h) return;
   try {

@@ -211,3 +211,64 @@ def test_server_parameter_validation(namg):
         with pytest.raises(namg.NamgError) as e:
             namg.Server(solve=solve, **bad)
         assert e.value.code == namg.E_INVALID
+
+
+# ------------------------------------------------------------ non-normality diagnostics (host code)
+@pytest.mark.parametrize("name,N,ilu", [("c1", 20, dict()), ("c4n", 9, dict(ilu_kind=1, ilut_droptol=1e-2, ilut_lfil=5)),
+                                        ("c4r", 9, dict()), ("c3", 10, dict(ilu_kind=1, ilut_droptol=1e-3, ilut_lfil=8))])
+def test_ilu_diagnostics_match_oracle_definitions(namg, oracle_lib, name, N, ilu):
+    """namg_ilu_diagnostics against the dense definitions (Henrici's dep via eigenvalues, ||U_s||_2 via
+    the dense 2-norm, Ruiz's iteration) on the same factors: exact quantities to 1e-10, the power
+    iteration's ||U_s||_2 from below to 1e-3, and the Table 2 residuals to 1e-10."""
+    from oracle.nonnormal import factor_diagnostics, jacobi_tri_residuals
+
+    O = oracle_lib
+    A, _, _ = config_system(name, N)
+    H = namg.Hierarchy(A, device=-1, **ilu)
+    F = O.ilut(A, ilu["ilut_droptol"], ilu["ilut_lfil"]) if ilu else CSR(A.n, A.rowptr, A.colind, O.ilu0(A))
+    ref = factor_diagnostics(F)
+    got = H.ilu_diagnostics(0, power_iters=2000)
+    assert got["n"] == A.n and got["max_row_upper"] == ref["max_row_upper"]
+    assert got["ruiz_iters"] == ref["ruiz_iters"]
+    for k in ("dep_L", "dep_U", "nu", "th1_bound", "th3_bound", "delta", "th4_bound", "dep_U_ruiz"):
+        assert got[k] == pytest.approx(ref[k], rel=1e-10, abs=1e-12), k
+    assert ref["norm2_Us"] * (1 - 1e-3) <= got["norm2_Us"] <= ref["norm2_Us"] * (1 + 1e-12)
+    b = np.random.default_rng(4).standard_normal(A.n)
+    for it in (0, 1, 5):
+        rl, ru = H.tri_jacobi_residuals(0, b, it)
+        if it == 0:
+            assert rl == 1.0  # y = 0
+            continue
+        erl, eru = jacobi_tri_residuals(F, b, it)
+        assert rl == pytest.approx(erl, rel=1e-10) and ru == pytest.approx(eru, rel=1e-10)
+
+
+def test_ilu_diagnostics_validation(namg):
+    A = poisson2d(12)
+    H = namg.Hierarchy(A, device=-1, max_coarse=200)
+    for kw in (dict(power_iters=0), dict(ruiz_max_iters=-1), dict(ruiz_tol=-1.0)):
+        assert _err(namg, lambda: H.ilu_diagnostics(0, **kw)) == namg.E_INVALID
+    assert _err(namg, lambda: H.ilu_diagnostics(5)) == namg.E_INVALID
+    H0 = namg.Hierarchy(A, device=-1, ilu_levels=0)
+    assert _err(namg, lambda: H0.ilu_diagnostics(0)) == namg.E_INVALID
+    assert _err(namg, lambda: H.tri_jacobi_residuals(0, np.ones(A.n), -1)) == namg.E_INVALID
+    with pytest.raises(ValueError):
+        H.tri_jacobi_residuals(0, np.ones(A.n + 1), 3)
+
+
+def test_nonnormality_study_host_only(namg):
+    """bench.py's factor study runs without a GPU (host setup and diagnostics only) and reports the
+    Section 5.3.4 quantities per ordering and fill level, each within its theorem's bound."""
+    import importlib.util
+
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    out = bench.nonnormality_study(namg, None, 12, 10)
+    assert out["gpu"] is False
+    for name in ("c4n", "c4r", "c4rcm"):
+        r = out["orderings"][name]
+        assert r["norm2_Us"] <= r["nu"] * (1 + 1e-12) and r["nu"] <= r["th3_bound"]
+        assert 0.0 < r["jacobi5_res_L"] < 1.0 and "gmres_iters" not in r
+    fills = [out["fill_sweep"][k]["nnz_upper"] for k in ("5", "10", "20", "50")]
+    assert fills == sorted(fills)
