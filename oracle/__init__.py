@@ -157,7 +157,7 @@ class Hierarchy:
     """Oracle AMG hierarchy (strength, RS first pass, classical P, Galerkin RAP, ILU(0), dense LU)."""
 
     def __init__(self, A, theta=0.25, max_levels=25, max_coarse=50, ilu_levels=1, ilu_kind=ILU_KIND_ILU0,
-                 ilut_droptol=1e-2, ilut_lfil=5):
+                 ilut_droptol=1e-2, ilut_lfil=5, agg_levels=0):
         from workloads import CSR  # input container only
 
         self._CSR = CSR
@@ -166,7 +166,7 @@ class Hierarchy:
         st = C.c_int(0)
         h = lib().orc_setup(A.n, _p(self._rp, C.c_int), _p(self._ci, C.c_int), _p(self._v, C.c_double),
                             C.c_double(theta), max_levels, max_coarse, ilu_levels, ilu_kind,
-                            C.c_double(ilut_droptol), ilut_lfil, C.byref(st))
+                            C.c_double(ilut_droptol), ilut_lfil, agg_levels, C.byref(st))
         if st.value != 0 or not h:
             raise OracleFailure(st.value)
         self.h = C.c_void_p(h)

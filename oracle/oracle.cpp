@@ -260,6 +260,58 @@ Csr transpose(const Csr &P) {
   return R;
 }
 
+// Sparse product X Y by rows: row i of the result accumulates x_ij y_jJ over j in row i of X (stored,
+// ascending order) and J in row j of Y; the first product of an entry starts its sum.
+Csr spgemm(const Csr &X, const Csr &Y) {
+  Csr C;
+  C.nr = X.nr;
+  C.nc = Y.nc;
+  C.rp.assign(1, 0);
+  for (int i = 0; i < X.nr; ++i) {
+    std::map<int, double> row;
+    for (int k = X.rp[i]; k < X.rp[i + 1]; ++k) {
+      const int j = X.ci[k];
+      for (int q = Y.rp[j]; q < Y.rp[j + 1]; ++q) {
+        auto it = row.find(Y.ci[q]);
+        if (it == row.end())
+          row.emplace(Y.ci[q], X.v[k] * Y.v[q]);
+        else
+          it->second += X.v[k] * Y.v[q];
+      }
+    }
+    for (const auto &e : row) {
+      C.ci.push_back(e.first);
+      C.v.push_back(e.second);
+    }
+    C.rp.push_back((int)C.ci.size());
+  }
+  return C;
+}
+
+// Strength among the C points for the second pass of aggressive (A-1) coarsening (Section 5.1): C point
+// i is connected to C point j != i when a path of at most two strong connections leads from i to j,
+// j in S_i or j in S_k for some k in S_i (the CC block of S + S^2). Returned in C numbering, ascending.
+std::vector<std::vector<int>> cc_distance2(const std::vector<std::vector<int>> &S,
+                                           const std::vector<signed char> &cf) {
+  const int n = (int)S.size();
+  std::vector<int> cidx(n, -1);
+  int nc = 0;
+  for (int i = 0; i < n; ++i)
+    if (cf[i] == 1) cidx[i] = nc++;
+  std::vector<std::vector<int>> G(nc);
+  for (int i = 0; i < n; ++i) {
+    if (cf[i] != 1) continue;
+    std::set<int> reach;
+    for (int k : S[i]) {
+      if (cf[k] == 1 && k != i) reach.insert(cidx[k]);
+      for (int j : S[k])
+        if (cf[j] == 1 && j != i) reach.insert(cidx[j]);
+    }
+    G[cidx[i]].assign(reach.begin(), reach.end());
+  }
+  return G;
+}
+
 // Galerkin coarse operator A_c = P^T A P (Section 5, A_k = R_k A_{k-1} P_k with R_k = P_k^T).
 // AP first: row i of AP accumulates a_ij p_jJ over j ascending in row i of A and J in row j of P.
 // Then A_c[I][J] accumulates p_iI ap_iJ over fine rows i ascending. The pattern is the structural
@@ -586,10 +638,17 @@ struct Hierarchy {
 // Coarsen while n_l > max_coarse and l + 1 < max_levels; stop if the next level would be empty or
 // as large as this one. ILU factors on the first ilu_levels levels (-1: all but the coarsest): ILU(0),
 // or ILUT(droptol, lfil) when ilu_kind is ORC_ILU_KIND_ILUT.
+// On the first agg_levels levels the coarsening is aggressive (A-1, Section 5.1): the first pass gives
+// C_1 with classical interpolation P_1 and A_1 = P_1^T A P_1; a second first pass on the distance-two
+// strength among the C_1 points keeps C_2 within C_1; P_2 is the classical interpolation of A_1 (its own
+// strength) onto C_2, the level's interpolation is P = P_1 P_2 and its coarse operator
+// A_c = P_2^T A_1 P_2 (= P^T A P). A second pass that keeps every C_1 point, or none, leaves the level
+// standard.
 Hierarchy *build(const Csr &A0, double theta, int max_levels, int max_coarse, int ilu_levels, int ilu_kind,
-                 double droptol, int lfil) {
+                 double droptol, int lfil, int agg_levels) {
   if (!(theta > 0.0 && theta <= 1.0) || max_levels < 1 || max_coarse < 1) throw OracleError{ORC_E_INVALID};
   if (ilu_kind != ORC_ILU_KIND_ILU0 && ilu_kind != ORC_ILU_KIND_ILUT) throw OracleError{ORC_E_INVALID};
+  if (agg_levels < 0) throw OracleError{ORC_E_INVALID};
   if (ilu_kind == ORC_ILU_KIND_ILUT && (!(droptol >= 0.0) || !std::isfinite(droptol) || lfil < 0))
     throw OracleError{ORC_E_INVALID};
   for (int i = 0; i < A0.nr; ++i)
@@ -606,6 +665,22 @@ Hierarchy *build(const Csr &A0, double theta, int max_levels, int max_coarse, in
     Csr P = classical_interp(L.A, S, cf, nc);
     if (nc == 0 || nc == n) break;
     Csr Ac = galerkin(L.A, P);
+    if ((int)H->lv.size() <= agg_levels) {
+      auto cf2 = rs_first_pass(cc_distance2(S, cf));
+      int nc2 = 0;
+      for (signed char c : cf2) nc2 += c;
+      if (nc2 > 0 && nc2 < nc) {
+        for (int i = 0; i < Ac.nr; ++i)
+          if (diag_of(Ac, i) == 0.0) throw OracleError{ORC_E_ZERO_PIVOT};
+        int nc2b = 0;
+        Csr P2 = classical_interp(Ac, strength(Ac, theta), cf2, nc2b);
+        P = spgemm(P, P2);
+        Ac = galerkin(Ac, P2);
+        int q = 0;  // the level's C points are C_2, marked on the fine grid
+        for (int i = 0; i < n; ++i)
+          if (cf[i] == 1) cf[i] = cf2[q++];
+      }
+    }
     for (int i = 0; i < Ac.nr; ++i)
       if (diag_of(Ac, i) == 0.0) throw OracleError{ORC_E_ZERO_PIVOT};
     L.cf = cf;
@@ -962,12 +1037,13 @@ int orc_smooth_ilut(int n, const int *rp, const int *ci, const double *v, double
 }
 
 void *orc_setup(int n, const int *rp, const int *ci, const double *v, double theta, int max_levels,
-                int max_coarse, int ilu_levels, int ilu_kind, double droptol, int lfil, int *status) {
+                int max_coarse, int ilu_levels, int ilu_kind, double droptol, int lfil, int agg_levels,
+                int *status) {
   Hierarchy *H = nullptr;
   int s = guarded([&]() -> int {
     Csr A = make_csr(n, n, rp, ci, v);
     if (n < 1) return (int)ORC_E_INVALID;
-    H = build(A, theta, max_levels, max_coarse, ilu_levels, ilu_kind, droptol, lfil);
+    H = build(A, theta, max_levels, max_coarse, ilu_levels, ilu_kind, droptol, lfil, agg_levels);
     return ORC_OK;
   });
   if (status) *status = s;

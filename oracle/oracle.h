@@ -72,7 +72,8 @@ int orc_smooth(int n, const int *rp, const int *ci, const double *v, int kind, i
 
 /* ---- hierarchy ---- */
 void *orc_setup(int n, const int *rp, const int *ci, const double *v, double theta, int max_levels,
-                int max_coarse, int ilu_levels, int ilu_kind, double droptol, int lfil, int *status);
+                int max_coarse, int ilu_levels, int ilu_kind, double droptol, int lfil, int agg_levels,
+                int *status);
 void orc_free(void *h);
 int orc_num_levels(const void *h);
 /* n, nnz(A_l), nnz(P_l) (0 on the coarsest level), n_{l+1} */

@@ -785,3 +785,69 @@ def test_jacobi_triangular_residuals(oracle_lib):
     assert ru == pytest.approx(np.linalg.norm(np.triu(U, 1) @ v) / np.linalg.norm(b), rel=1e-13)
     rl, ru = jacobi_tri_residuals(F, b, A.n)
     assert rl <= 1e-14 and ru <= 1e-13
+
+
+# ------------------------------------------------------------- aggressive (A-1) coarsening, Section 5.1
+def _dist2_cc_graph(srp, sci, cf):
+    """Brute force: for each first-pass C point, the C points reachable by one or two strong connections."""
+    S = [set(sci[srp[i]:srp[i + 1]]) for i in range(len(srp) - 1)]
+    C = np.nonzero(cf == 1)[0]
+    pos = {c: q for q, c in enumerate(C)}
+    G = []
+    for i in C:
+        reach = set(S[i])
+        for k in S[i]:
+            reach |= S[k]
+        G.append({pos[j] for j in reach if j in pos and j != i})
+    return C, G
+
+
+@pytest.mark.parametrize("maker", [lambda: poisson2d(24), lambda: poisson3d(12), lambda: convdiff3d(12, 3)[0],
+                                   lambda: varcoef3d(12, 1.0, 2, 100.0)[0]])
+def test_aggressive_coarsening_structure(oracle_lib, maker):
+    """A-1 aggressive coarsening on the finest level: the final C points are a subset of the first
+    pass's C points, chosen by an RS first pass on the distance-two strength among them (every C point
+    that is dropped has a kept point among its one- or two-step strong connections); P = P_1 P_2 keeps
+    the identity rows of the kept points; the coarse operator is the Galerkin product P^T A P (dense
+    check); and the hierarchy has fewer coarse unknowns and a lower operator complexity than standard
+    coarsening."""
+    O = oracle_lib
+    A = maker()
+    theta = 0.25
+    cf1 = O.coarsen(A, theta)
+    srp, sci = O.strength(A, theta)
+    C1, G = _dist2_cc_graph(srp, sci, cf1)
+    H = O.Hierarchy(A, theta=theta, agg_levels=1)
+    H0 = O.Hierarchy(A, theta=theta)
+    lv0, lv1 = H.level(0), H.level(1)
+    cf = lv0.cf
+    assert np.all(cf[cf1 == 0] == 0)  # C_2 within C_1
+    keep = cf[C1] == 1
+    assert 0 < keep.sum() < len(C1)
+    for q in np.nonzero(~keep)[0]:
+        if G[q] or any(q in G[r] for r in range(len(G))):
+            assert any(keep[r] for r in G[q]), q
+    P = lv0.P.toarray()
+    cidx = np.cumsum(cf) - 1
+    for i in np.nonzero(cf == 1)[0]:
+        row = np.zeros(P.shape[1])
+        row[cidx[i]] = 1.0
+        np.testing.assert_array_equal(P[i], row)
+    Ad = A.to_dense()
+    Ac = lv1.A.to_dense()
+    np.testing.assert_allclose(Ac, P.T @ Ad @ P, atol=1e-12 * np.abs(Ac).max())
+    nnz = [H.level(l).A.nnz for l in range(H.levels)]
+    nnz0 = [H0.level(l).A.nnz for l in range(H0.levels)]
+    assert lv1.A.n < H0.level(1).A.n and sum(nnz) < sum(nnz0)
+
+
+def test_aggressive_coarsening_solves(oracle_lib):
+    """With aggressive coarsening on the first two levels (as in Section 6.1) the preconditioned solve
+    still reaches the true relative residual; agg_levels < 0 is rejected."""
+    O = oracle_lib
+    for name, N, sm, t in (("c1", None, 0, 2), ("c2", 16, 1, 3), ("c3", 16, 0, 2)):
+        A, b, _ = __import__("workloads").config_system(name, N)
+        r = O.Hierarchy(A, agg_levels=2).solve(b, smoother=sm, t=t)
+        assert r["status"] == 0 and np.linalg.norm(b - A.to_dense() @ r["x"]) <= 1e-8 * np.linalg.norm(b)
+    with pytest.raises(O.OracleFailure):
+        O.Hierarchy(poisson2d(10), agg_levels=-1)
