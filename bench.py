@@ -342,7 +342,8 @@ def main():
 
     if args.compare:
         # the Table 7 family on this workload: ILUT(1e-2, 5) on the finest level with Jacobi (Neumann) or
-        # direct triangular solves next to ILU(0), plus the Table 6 comparator and the other precision
+        # direct triangular solves next to ILU(0), plus the Table 6 comparator, aggressive coarsening on
+        # the first two levels and the other precision
         cmp = {}
         ilut = dict(ilu_kind=namg.ILUT, ilut_droptol=1e-2, ilut_lfil=5)
         H_ilut = None
@@ -351,21 +352,31 @@ def main():
                                            ("ilut_jacobi", dict(smoother=namg.SMOOTH_ILU0), prec, ilut),
                                            ("ilut_direct", dict(smoother=namg.SMOOTH_ILU0, tri_mode=namg.TRI_DIRECT),
                                             prec, ilut),
+                                           ("aggressive2", {}, prec, dict(agg_levels=2)),
                                            ("fp32_precond", {}, namg.FP32_PRECOND, None), ("fp64", {}, namg.FP64, None)):
-            if setup2 is not None:
+            if setup2 is ilut:
                 if H_ilut is None:
                     t0 = time.perf_counter()
                     H_ilut = namg.Hierarchy(A, device=0, precision=prec, ilu_levels=1, **setup2)
                     ilut_setup_ms = (time.perf_counter() - t0) * 1e3
                 H2 = H_ilut
+            elif setup2 is not None:
+                t0 = time.perf_counter()
+                H2 = namg.Hierarchy(A, device=0, precision=prec, ilu_levels=1, **setup2)
+                other_setup_ms = (time.perf_counter() - t0) * 1e3
             else:
                 H2 = H if prec2 == prec else namg.Hierarchy(A, device=0, precision=prec2, ilu_levels=1)
             kw2 = dict(kw, **extra)
             ms2, st2 = _time_solves(torch, H2, bt, xt, kw2, max(1, args.steps // 2), 1)
             cmp[name] = {"ms": round(ms2, 3), "iters": st2[-1]["iters"], "relres": st2[-1]["relres_true"]}
-            if setup2 is not None:
+            if setup2 is ilut:
                 cmp[name].update(setup=dict(droptol=setup2["ilut_droptol"], lfil=setup2["ilut_lfil"]),
                                  setup_ms=round(ilut_setup_ms, 1))
+            elif setup2 is not None:
+                info2 = H2.info()
+                cmp[name].update(setup=setup2, setup_ms=round(other_setup_ms, 1), levels=info2["levels"],
+                                 op_complexity=round(info2["op_complexity"], 3))
+                H2.close()
         if H_ilut is not None:
             H_ilut.close()
         out["compare"] = cmp

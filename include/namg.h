@@ -66,6 +66,10 @@ typedef struct {
                      column). The smoother applies either factor the same way (row scaling D_U = diag(U)) */
   int ilut_lfil;  /* >= 0; default 5 */
   double ilut_droptol; /* >= 0; default 1e-2 */
+  int agg_levels; /* aggressive (A-1) coarsening on levels l < agg_levels (Section 5.1; the paper's runs use
+                     2), default 0: a second first pass over the C points with the distance-two strength
+                     (paths of at most two strong connections) keeps C_2; P = P_1 P_2 with P_2 the classical
+                     interpolation of A_1 = P_1^T A P_1 onto C_2, and A_c = P_2^T A_1 P_2 */
 } namg_setup_params;
 
 typedef struct {

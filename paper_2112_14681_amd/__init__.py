@@ -40,7 +40,7 @@ EXPORTED = (
 class SetupParams(C.Structure):
     _fields_ = [("theta", C.c_double), ("max_levels", C.c_int), ("max_coarse", C.c_int), ("precision", C.c_int),
                 ("ilu_levels", C.c_int), ("device", C.c_int), ("ilu_kind", C.c_int), ("ilut_lfil", C.c_int),
-                ("ilut_droptol", C.c_double)]
+                ("ilut_droptol", C.c_double), ("agg_levels", C.c_int)]
 
 
 class SolveParams(C.Structure):

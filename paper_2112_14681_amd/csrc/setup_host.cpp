@@ -195,6 +195,39 @@ std::vector<int8_t> rs_coarsen(const Graph &S, int32_t n) {
 }
 
 // ---- classical interpolation -------------------------------------------------------------------------
+// Second-pass strength of aggressive (A-1) coarsening: among the C points (numbered in fine order), C
+// point i is connected to C point j != i when j is in S_i or in S_k for some k in S_i (the CC block of
+// S + S^2). A marker per C point collects each row once; rows come out sorted.
+Graph cc_distance2(const Graph &S, const std::vector<int8_t> &cf) {
+  const int32_t n = (int32_t)cf.size();
+  std::vector<int32_t> cnum(n, -1);
+  int32_t nc = 0;
+  for (int32_t i = 0; i < n; ++i)
+    if (cf[i] == 1) cnum[i] = nc++;
+  Graph G;
+  G.rp.assign(nc + 1, 0);
+  std::vector<int32_t> mark(nc, -1);
+  for (int32_t i = 0; i < n; ++i) {
+    if (cf[i] != 1) continue;
+    const int32_t I = cnum[i];
+    const size_t start = G.ci.size();
+    auto add = [&](int32_t j) {
+      if (j != i && cf[j] == 1 && mark[cnum[j]] != I) {
+        mark[cnum[j]] = I;
+        G.ci.push_back(cnum[j]);
+      }
+    };
+    for (int32_t q = S.rp[i]; q < S.rp[i + 1]; ++q) {
+      const int32_t k = S.ci[q];
+      add(k);
+      for (int32_t r = S.rp[k]; r < S.rp[k + 1]; ++r) add(S.ci[r]);
+    }
+    std::sort(G.ci.begin() + start, G.ci.end());
+    G.rp[I + 1] = (int32_t)G.ci.size();
+  }
+  return G;
+}
+
 HostCsr classical_interpolation(const HostCsr &A, const Graph &S, const std::vector<int8_t> &cf) {
   const int32_t n = A.nr;
   std::vector<int32_t> cnum(n, -1);
@@ -641,6 +674,7 @@ HostHierarchy build_hierarchy(const HostCsr &A0, const namg_setup_params &p) {
   const int max_levels = p.max_levels, max_coarse = p.max_coarse, ilu_levels = p.ilu_levels;
   if (!(theta > 0.0 && theta <= 1.0)) fail(NAMG_E_INVALID, "theta must be in (0, 1]");
   if (p.ilu_kind != NAMG_ILU0 && p.ilu_kind != NAMG_ILUT) fail(NAMG_E_INVALID, "unknown ilu_kind");
+  if (p.agg_levels < 0) fail(NAMG_E_INVALID, "agg_levels must be >= 0");
   if (p.ilu_kind == NAMG_ILUT && (!(p.ilut_droptol >= 0.0) || !std::isfinite(p.ilut_droptol) || p.ilut_lfil < 0))
     fail(NAMG_E_INVALID, "ILUT needs ilut_droptol >= 0 and ilut_lfil >= 0");
   if (max_levels < 1 || max_levels > NAMG_MAX_LEVELS) fail(NAMG_E_INVALID, "max_levels out of range");
@@ -673,6 +707,27 @@ HostHierarchy build_hierarchy(const HostCsr &A0, const namg_setup_params &p) {
     HostCsr AP = spgemm(L.A, P);
     auto t3b = now();
     HostCsr Ac = spgemm(R, AP);
+    if ((int)H.lv.size() <= p.agg_levels) {
+      // aggressive (A-1): a second first pass on the distance-two strength among the C points keeps C_2;
+      // P_2 interpolates A_1 = P_1^T A P_1 onto C_2 with A_1's own strength; P = P_1 P_2 and
+      // A_c = P_2^T A_1 P_2
+      std::vector<int8_t> cf2 = rs_coarsen(cc_distance2(S, cf), P.nc);
+      int32_t nc2 = 0;
+      for (int8_t c : cf2) nc2 += c;
+      if (nc2 > 0 && nc2 < P.nc) {
+        for (int32_t i = 0; i < Ac.nr; ++i)
+          if (diagonal(Ac, i) == 0.0) fail(NAMG_E_ZERO_PIVOT, "zero diagonal in a coarse operator");
+        HostCsr P2 = classical_interpolation(Ac, strength_graph(Ac, theta), cf2);
+        HostCsr R2 = transpose_csr(P2);
+        HostCsr AP2 = spgemm(Ac, P2);
+        Ac = spgemm(R2, AP2);
+        P = spgemm(P, P2);
+        R = transpose_csr(P);
+        int32_t q = 0;
+        for (int32_t i = 0; i < n; ++i)
+          if (cf[i] == 1) cf[i] = cf2[q++];
+      }
+    }
     auto t4 = now();
     t_str += secs(t0, t1);
     t_rs += secs(t1, t2);

@@ -914,6 +914,7 @@ void namg_default_setup_params(namg_setup_params *p) {
   p->ilu_kind = NAMG_ILU0;
   p->ilut_lfil = 5;
   p->ilut_droptol = 1e-2;
+  p->agg_levels = 0;
 }
 
 void namg_default_solve_params(namg_solve_params *p) {

@@ -302,6 +302,25 @@ def test_ilut_fp32_and_server(namg):
     assert r["status"] == namg.OK and r["iters"] == ref["iters"] and relerr(r["x"], ref["x"]) <= 1e-10
 
 
+def test_aggressive_coarsening_parity(namg):
+    """Aggressive (A-1) coarsening on the first two levels (P = P_1 P_2, denser rows in P and R): V-cycle to
+    1e-12 and solves with the oracle's iterations and x within 1e-10, on C2 at 24^3 (ILU(0) hybrid) and
+    C3 at 20^3 (polynomial GS); the FP32 preconditioner reaches the same residual."""
+    for name, N, kw in (("c2", 24, dict(smoother=1, inner_terms=3)), ("c3", 20, dict(smoother=0, inner_terms=2))):
+        A, b, _ = config_system(name, N)
+        H, G = namg.Hierarchy(A, device=0, agg_levels=2), O.Hierarchy(A, agg_levels=2)
+        assert H.info()["levels"] == G.levels
+        out = torch.empty(A.n, dtype=torch.float64, device="cuda:0")
+        H.vcycle(dev(b), out, **kw)
+        assert relerr(host(out), G.vcycle(b, smoother=kw["smoother"], t=kw["inner_terms"])) <= TOL64
+        _, ref, _ = _check_solve(namg, A, b, H, G, **kw)
+        H32 = namg.Hierarchy(A, device=0, agg_levels=2, precision=namg.FP32_PRECOND)
+        xt = dev(np.zeros(A.n))
+        st = H32.solve(dev(b), xt, **kw)
+        assert st["status"] == namg.OK and abs(st["iters"] - ref["iters"]) <= 2
+        assert np.linalg.norm(b - O.spmv(A, host(xt))) <= 1e-8 * np.linalg.norm(b)
+
+
 def test_solve_c3_and_c4_parity(namg):
     for name, N, kw in (("c3", 20, dict(smoother=0, inner_terms=2)), ("c4r", 16, dict(smoother=1, inner_terms=3)),
                         ("c4rcm", 16, dict(smoother=1, inner_terms=3, restart=50))):

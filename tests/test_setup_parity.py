@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol(namg):
 def _compare_hierarchies(namg, oracle_lib, A, **kw):
     H = namg.Hierarchy(A, device=-1, **kw)
     G = oracle_lib.Hierarchy(A, **{k: v for k, v in kw.items() if k in ("theta", "max_levels", "max_coarse",
-                                                                       "ilu_levels")})
+                                                                       "ilu_levels", "agg_levels")})
     info = H.info()
     assert info["levels"] == G.levels
     for l in range(G.levels):
@@ -73,6 +73,17 @@ def test_setup_bit_exact_random_and_small(namg, oracle_lib):
     _compare_hierarchies(namg, oracle_lib, tridiag1d(7), max_coarse=1, max_levels=2)
     info = _compare_hierarchies(namg, oracle_lib, poisson2d(5))  # n = 25 <= 50: one level
     assert info["levels"] == 1
+
+
+@pytest.mark.parametrize("name,N,agg", [("c1", None, 1), ("c1", None, 2), ("c2", 24, 2), ("c3", 20, 2), ("c4r", 14, 2),
+                                        ("c2", 20, 30)])
+def test_aggressive_setup_bit_exact_vs_oracle(namg, oracle_lib, name, N, agg):
+    """Aggressive (A-1) coarsening on the first agg levels: C/F, P = P_1 P_2 and every Galerkin operator
+    equal the oracle's bit for bit (agg = 30: every level)."""
+    A, _, _ = config_system(name, N)
+    info = _compare_hierarchies(namg, oracle_lib, A, agg_levels=agg)
+    std = namg.Hierarchy(A, device=-1).info()
+    assert info["op_complexity"] < std["op_complexity"]
 
 
 def test_setup_at_64cubed_bit_exact(namg, oracle_lib):
@@ -132,7 +143,7 @@ def test_ilut_every_level_and_nonsymmetric(namg, oracle_lib):
 
 def test_ilut_parameter_validation(namg):
     A = poisson2d(12)
-    for bad in (dict(ilu_kind=2), dict(ilu_kind=1, ilut_lfil=-1), dict(ilu_kind=1, ilut_droptol=-1e-3),
+    for bad in (dict(ilu_kind=2), dict(agg_levels=-1), dict(ilu_kind=1, ilut_lfil=-1), dict(ilu_kind=1, ilut_droptol=-1e-3),
                 dict(ilu_kind=1, ilut_droptol=float("nan")), dict(ilu_kind=1, ilut_droptol=float("inf"))):
         assert _err(namg, lambda: namg.Hierarchy(A, device=-1, **bad)) == namg.E_INVALID, bad
     p = namg.setup_params()
