@@ -23,6 +23,7 @@ T_NEUMANN, T_DIRECT = 0, 1
 PRECOND_NONE, PRECOND_AMG = 0, 1
 STOP_RELRES, STOP_NRBE = 0, 1
 ILU_KIND_ILU0, ILU_KIND_ILUT = 0, 1
+COARSEN_RS, COARSEN_PMIS = 0, 1
 PGS_FWD, PGS_BWD, GS_FWD, GS_BWD, ILU_NEUMANN, ILU_DIRECT, L1_JACOBI = range(7)
 
 
@@ -56,6 +57,8 @@ def lib():
         _lib = C.CDLL(build())
         _lib.orc_setup.restype = C.c_void_p
         _lib.orc_loss_orth.restype = C.c_double
+        _lib.orc_splitmix64.restype = C.c_ulonglong
+        _lib.orc_uniform01.restype = C.c_double
         for name in ("orc_free", "orc_num_levels", "orc_level_info", "orc_level_export", "orc_vcycle",
                      "orc_solve"):
             getattr(_lib, name).argtypes = None
@@ -116,6 +119,14 @@ def ilu0(A):
     return out
 
 
+def splitmix64(seed, k):
+    return int(lib().orc_splitmix64(C.c_ulonglong(seed), C.c_ulonglong(k)))
+
+
+def uniform01(seed, i):
+    return float(lib().orc_uniform01(C.c_ulonglong(seed), C.c_longlong(i)))
+
+
 def ilut(A, droptol, lfil):
     """ILUT(droptol, lfil) factors as a CSR holding L \\ U (strict lower = L_s, the rest = U)."""
     from workloads import CSR  # input container only
@@ -157,7 +168,7 @@ class Hierarchy:
     """Oracle AMG hierarchy (strength, RS first pass, classical P, Galerkin RAP, ILU(0), dense LU)."""
 
     def __init__(self, A, theta=0.25, max_levels=25, max_coarse=50, ilu_levels=1, ilu_kind=ILU_KIND_ILU0,
-                 ilut_droptol=1e-2, ilut_lfil=5, agg_levels=0):
+                 ilut_droptol=1e-2, ilut_lfil=5, agg_levels=0, coarsen=COARSEN_RS, seed=0):
         from workloads import CSR  # input container only
 
         self._CSR = CSR
@@ -166,7 +177,8 @@ class Hierarchy:
         st = C.c_int(0)
         h = lib().orc_setup(A.n, _p(self._rp, C.c_int), _p(self._ci, C.c_int), _p(self._v, C.c_double),
                             C.c_double(theta), max_levels, max_coarse, ilu_levels, ilu_kind,
-                            C.c_double(ilut_droptol), ilut_lfil, agg_levels, C.byref(st))
+                            C.c_double(ilut_droptol), ilut_lfil, agg_levels, coarsen, C.c_ulonglong(seed),
+                            C.byref(st))
         if st.value != 0 or not h:
             raise OracleFailure(st.value)
         self.h = C.c_void_p(h)

@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <set>
@@ -172,6 +173,111 @@ std::vector<signed char> rs_first_pass(const std::vector<std::vector<int>> &S) {
   std::vector<signed char> cf(n);
   for (int i = 0; i < n; ++i) cf[i] = (state[i] == C) ? 1 : 0;
   return cf;
+}
+
+// SplitMix64 (Steele, Lea and Flood 2014): the k-th output (k >= 1) of the stream seeded with s is
+// mix(s + k * 0x9E3779B97F4A7C15). Used as a counter-based generator: point i of level l draws the
+// (i + 1)-th output of the stream seeded with seed + l, as a double in [0, 1) from its top 53 bits.
+uint64_t splitmix64_output(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + k * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+double uniform01(uint64_t seed, int64_t i) {
+  return (double)(splitmix64_output(seed, (uint64_t)i + 1) >> 11) * 0x1.0p-53;
+}
+
+// PMIS coarsening (Section 5.1: Luby's maximal independent set with random numbers, as modified by De
+// Sterck, Yang and Heys). Weights w_i = |S^T_i| + u_i with u_i in [0, 1) drawn as above. Points that
+// influence no other point (w_i < 1) are F from the start. Then, in rounds until no point is undecided,
+// every undecided point whose weight beats that of each undecided point it is strongly connected to
+// (either direction; equal weights: the smaller index wins) becomes C, all at once, and every undecided
+// point that strongly depends on one of these new C points becomes F.
+std::vector<signed char> pmis(const std::vector<std::vector<int>> &S, uint64_t seed) {
+  const int n = (int)S.size();
+  const auto ST = transpose_graph(S);
+  enum { U = 0, C = 1, F = 2 };
+  std::vector<int> state(n, U);
+  std::vector<double> w(n);
+  for (int i = 0; i < n; ++i) {
+    w[i] = (double)ST[i].size() + uniform01(seed, i);
+    if (ST[i].empty()) state[i] = F;
+  }
+  auto beats = [&](int i, int j) { return w[i] > w[j] || (w[i] == w[j] && i < j); };
+  while (true) {
+    std::vector<int> newC;
+    for (int i = 0; i < n; ++i) {
+      if (state[i] != U) continue;
+      bool best = true;
+      for (int j : S[i])
+        if (state[j] == U && !beats(i, j)) best = false;
+      for (int j : ST[i])
+        if (state[j] == U && !beats(i, j)) best = false;
+      if (best) newC.push_back(i);
+    }
+    if (newC.empty()) break;
+    for (int i : newC) state[i] = C;
+    for (int i : newC)
+      for (int j : ST[i])
+        if (state[j] == U) state[j] = F;
+  }
+  std::vector<signed char> cf(n);
+  for (int i = 0; i < n; ++i) cf[i] = (state[i] == C) ? 1 : 0;
+  return cf;
+}
+
+// BAMG direct interpolation (Section 5.1, the closed form of the local least-squares problem with target
+// f = 1): for an F point i with strong C neighbours C_i (n_i of them), strong F neighbours and weak
+// neighbours N^w_i, w_ij = -(a_ij + beta_i / n_i) / (a_ii + sum_{k in N^w_i} a_ik) for j in C_i with
+// beta_i = the sum of a_ik over the strong F neighbours (both sums in ascending column order, the
+// denominator starting from a_ii). An F point without strong C neighbours gets an empty row.
+Csr bamg_direct_interp(const Csr &A, const std::vector<std::vector<int>> &S, const std::vector<signed char> &cf,
+                       int &nc_out) {
+  const int n = A.nr;
+  std::vector<int> cidx(n, -1);
+  int nc = 0;
+  for (int i = 0; i < n; ++i)
+    if (cf[i] == 1) cidx[i] = nc++;
+  nc_out = nc;
+  Csr P;
+  P.nr = n;
+  P.nc = nc;
+  P.rp.assign(1, 0);
+  for (int i = 0; i < n; ++i) {
+    if (cf[i] == 1) {
+      P.ci.push_back(cidx[i]);
+      P.v.push_back(1.0);
+      P.rp.push_back((int)P.ci.size());
+      continue;
+    }
+    const std::vector<int> &Si = S[i];
+    auto is_strong = [&](int j) { return std::binary_search(Si.begin(), Si.end(), j); };
+    int ni = 0;
+    double beta = 0.0, dd = diag_of(A, i);
+    for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      const int j = A.ci[k];
+      if (j == i) continue;
+      if (!is_strong(j))
+        dd += A.v[k];
+      else if (cf[j] == 1)
+        ++ni;
+      else
+        beta += A.v[k];
+    }
+    if (ni > 0) {
+      for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+        const int j = A.ci[k];
+        if (j != i && cf[j] == 1 && is_strong(j)) {
+          P.ci.push_back(cidx[j]);
+          P.v.push_back(-(A.v[k] + beta / ni) / dd);
+        }
+      }
+    }
+    P.rp.push_back((int)P.ci.size());
+  }
+  return P;
 }
 
 // Classical (Ruge-Stueben standard) interpolation, P = [W; I] in the ordering of the fine grid.
@@ -644,11 +750,16 @@ struct Hierarchy {
 // strength) onto C_2, the level's interpolation is P = P_1 P_2 and its coarse operator
 // A_c = P_2^T A_1 P_2 (= P^T A P). A second pass that keeps every C_1 point, or none, leaves the level
 // standard.
+// coarsen = ORC_COARSEN_PMIS replaces the RS first pass and classical interpolation on every level by
+// PMIS (level l seeded with seed + l) and BAMG direct interpolation; it does not combine with
+// aggressive coarsening.
 Hierarchy *build(const Csr &A0, double theta, int max_levels, int max_coarse, int ilu_levels, int ilu_kind,
-                 double droptol, int lfil, int agg_levels) {
+                 double droptol, int lfil, int agg_levels, int coarsen, uint64_t seed) {
   if (!(theta > 0.0 && theta <= 1.0) || max_levels < 1 || max_coarse < 1) throw OracleError{ORC_E_INVALID};
   if (ilu_kind != ORC_ILU_KIND_ILU0 && ilu_kind != ORC_ILU_KIND_ILUT) throw OracleError{ORC_E_INVALID};
   if (agg_levels < 0) throw OracleError{ORC_E_INVALID};
+  if (coarsen != ORC_COARSEN_RS && coarsen != ORC_COARSEN_PMIS) throw OracleError{ORC_E_INVALID};
+  if (coarsen == ORC_COARSEN_PMIS && agg_levels > 0) throw OracleError{ORC_E_INVALID};
   if (ilu_kind == ORC_ILU_KIND_ILUT && (!(droptol >= 0.0) || !std::isfinite(droptol) || lfil < 0))
     throw OracleError{ORC_E_INVALID};
   for (int i = 0; i < A0.nr; ++i)
@@ -660,9 +771,10 @@ Hierarchy *build(const Csr &A0, double theta, int max_levels, int max_coarse, in
     const int n = L.A.nr;
     if (n <= max_coarse || (int)H->lv.size() >= max_levels) break;
     auto S = strength(L.A, theta);
-    auto cf = rs_first_pass(S);
+    const bool use_pmis = coarsen == ORC_COARSEN_PMIS;
+    auto cf = use_pmis ? pmis(S, seed + (uint64_t)(H->lv.size() - 1)) : rs_first_pass(S);
     int nc = 0;
-    Csr P = classical_interp(L.A, S, cf, nc);
+    Csr P = use_pmis ? bamg_direct_interp(L.A, S, cf, nc) : classical_interp(L.A, S, cf, nc);
     if (nc == 0 || nc == n) break;
     Csr Ac = galerkin(L.A, P);
     if ((int)H->lv.size() <= agg_levels) {
@@ -980,6 +1092,12 @@ int orc_coarsen(int n, const int *rp, const int *ci, const double *v, double the
   });
 }
 
+unsigned long long orc_splitmix64(unsigned long long seed, unsigned long long k) {
+  return splitmix64_output(seed, k);
+}
+
+double orc_uniform01(unsigned long long seed, long long i) { return uniform01(seed, i); }
+
 int orc_ilu0(int n, const int *rp, const int *ci, const double *v, double *out) {
   return guarded([&]() -> int {
     Csr A = make_csr(n, n, rp, ci, v);
@@ -1038,12 +1156,13 @@ int orc_smooth_ilut(int n, const int *rp, const int *ci, const double *v, double
 
 void *orc_setup(int n, const int *rp, const int *ci, const double *v, double theta, int max_levels,
                 int max_coarse, int ilu_levels, int ilu_kind, double droptol, int lfil, int agg_levels,
-                int *status) {
+                int coarsen, unsigned long long seed, int *status) {
   Hierarchy *H = nullptr;
   int s = guarded([&]() -> int {
     Csr A = make_csr(n, n, rp, ci, v);
     if (n < 1) return (int)ORC_E_INVALID;
-    H = build(A, theta, max_levels, max_coarse, ilu_levels, ilu_kind, droptol, lfil, agg_levels);
+    H = build(A, theta, max_levels, max_coarse, ilu_levels, ilu_kind, droptol, lfil, agg_levels, coarsen,
+              (uint64_t)seed);
     return ORC_OK;
   });
   if (status) *status = s;

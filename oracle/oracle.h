@@ -21,6 +21,7 @@ enum { ORC_T_NEUMANN = 0, ORC_T_DIRECT = 1 };
 enum { ORC_PRECOND_NONE = 0, ORC_PRECOND_AMG = 1 };
 enum { ORC_STOP_RELRES = 0, ORC_STOP_NRBE = 1 };
 enum { ORC_ILU_KIND_ILU0 = 0, ORC_ILU_KIND_ILUT = 1 };
+enum { ORC_COARSEN_RS = 0, ORC_COARSEN_PMIS = 1 }; /* RS + classical, or PMIS + BAMG direct interpolation */
 /* single-level smoother kinds for orc_smooth */
 enum {
   ORC_PGS_FWD = 0,     /* polynomial GS, forward (D+L), t Neumann terms      */
@@ -73,7 +74,10 @@ int orc_smooth(int n, const int *rp, const int *ci, const double *v, int kind, i
 /* ---- hierarchy ---- */
 void *orc_setup(int n, const int *rp, const int *ci, const double *v, double theta, int max_levels,
                 int max_coarse, int ilu_levels, int ilu_kind, double droptol, int lfil, int agg_levels,
-                int *status);
+                int coarsen, unsigned long long seed, int *status);
+/* the k-th output (k >= 1) of SplitMix64 seeded with seed, and the [0, 1) draw of point i (output i + 1) */
+unsigned long long orc_splitmix64(unsigned long long seed, unsigned long long k);
+double orc_uniform01(unsigned long long seed, long long i);
 void orc_free(void *h);
 int orc_num_levels(const void *h);
 /* n, nnz(A_l), nnz(P_l) (0 on the coarsest level), n_{l+1} */

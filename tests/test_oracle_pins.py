@@ -851,3 +851,107 @@ def test_aggressive_coarsening_solves(oracle_lib):
         assert r["status"] == 0 and np.linalg.norm(b - A.to_dense() @ r["x"]) <= 1e-8 * np.linalg.norm(b)
     with pytest.raises(O.OracleFailure):
         O.Hierarchy(poisson2d(10), agg_levels=-1)
+
+
+# -------------------------------------------------- PMIS and BAMG direct interpolation (Section 5.1)
+def test_splitmix64_reference_outputs(oracle_lib):
+    """The generator behind PMIS's random weights is SplitMix64 as published: its first four outputs from
+    state 0 (tests/golden/splitmix64_state0.json); the draw of point i is output i + 1 scaled to [0, 1)."""
+    g = json.load(open(os.path.join(GOLD, "splitmix64_state0.json")))
+    O = oracle_lib
+    assert [O.splitmix64(g["state"], k) for k in range(1, 5)] == [int(h, 16) for h in g["outputs_hex"]]
+    for seed, i in ((0, 0), (0, 3), (5, 1000), (2 ** 63 + 11, 7)):
+        u = O.uniform01(seed, i)
+        assert 0.0 <= u < 1.0 and u == (O.splitmix64(seed, i + 1) >> 11) / 2.0 ** 53
+
+
+def _strong_lists(O, A, theta=0.25):
+    srp, sci = O.strength(A, theta)
+    S = [list(sci[srp[i]:srp[i + 1]]) for i in range(A.n)]
+    ST = [[] for _ in range(A.n)]
+    for i, row in enumerate(S):
+        for j in row:
+            ST[j].append(i)
+    return S, ST
+
+
+@pytest.mark.parametrize("maker", [lambda: poisson2d(20), lambda: poisson3d(9), lambda: convdiff3d(9, 3)[0],
+                                   lambda: varcoef3d(9, 1.0, 2, 100.0)[0], lambda: random_csr(200, 6, 4)])
+@pytest.mark.parametrize("seed", [0, 12345])
+def test_pmis_splitting_properties(oracle_lib, maker, seed):
+    """PMIS (Section 5.1) on the finest level, checked against its definition with the weights recomputed
+    from the pinned generator: a point that influences no other point is F; every other F point strongly
+    depends on a C point; and a C point that strongly depends on another C point has the larger weight
+    (it was chosen while the other was still undecided and adjacent)."""
+    O = oracle_lib
+    A = maker()
+    S, ST = _strong_lists(O, A)
+    H = O.Hierarchy(A, coarsen=O.COARSEN_PMIS, seed=seed, max_levels=2, max_coarse=1)
+    cf = H.level(0).cf
+    w = np.array([len(ST[i]) + O.uniform01(seed, i) for i in range(A.n)])
+    for i in range(A.n):
+        if not ST[i]:
+            assert cf[i] == 0, i
+        elif cf[i] == 0:
+            assert any(cf[j] == 1 for j in S[i]), i
+        else:
+            for j in S[i]:
+                if cf[j] == 1:
+                    assert w[i] > w[j] or (w[i] == w[j] and i < j), (i, j)
+    assert 0 < cf.sum() < A.n
+
+
+@pytest.mark.parametrize("maker", [lambda: poisson2d(16), lambda: convdiff3d(8, 3)[0], lambda: varcoef3d(8, 1.0, 2, 100.0)[0]])
+def test_bamg_direct_interpolation(oracle_lib, maker):
+    """BAMG direct interpolation (Section 5.1): C rows are identity rows; an F row interpolates from
+    exactly its strong C neighbours (none: empty row); on zero-row-sum rows the weights solve the local
+    problem min || a~_ii w + a_{i,C} || subject to w^T 1 = 1 (a~_ii: the diagonal with the weak
+    neighbours added), computed here from its KKT system, and therefore interpolate constants."""
+    O = oracle_lib
+    A = maker()
+    S, _ = _strong_lists(O, A)
+    H = O.Hierarchy(A, coarsen=O.COARSEN_PMIS, seed=3, max_levels=2, max_coarse=1)
+    lv = H.level(0)
+    cf, P = lv.cf, lv.P.tocsr()
+    cidx = np.cumsum(cf) - 1
+    Ad = A.to_dense()
+    checked = 0
+    for i in range(A.n):
+        row = P.getrow(i)
+        if cf[i] == 1:
+            assert list(row.indices) == [cidx[i]] and list(row.data) == [1.0]
+            continue
+        Ci = [j for j in S[i] if cf[j] == 1]
+        assert sorted(row.indices) == sorted(cidx[j] for j in Ci)
+        if not Ci or abs(Ad[i].sum()) > 1e-12 * np.abs(Ad[i]).max():
+            continue
+        weak = [k for k in np.nonzero(Ad[i])[0] if k != i and k not in S[i]]
+        at = Ad[i, i] + Ad[i, weak].sum()
+        m = len(Ci)
+        K = np.zeros((m + 1, m + 1))
+        K[:m, :m] = 2 * at * at * np.eye(m)
+        K[:m, m] = K[m, :m] = 1.0
+        rhs = np.concatenate([-2 * at * Ad[i, Ci], [1.0]])
+        wk = np.linalg.solve(K, rhs)[:m]
+        got = np.array([P[i, cidx[j]] for j in Ci])
+        np.testing.assert_allclose(got, wk, rtol=1e-12, atol=1e-14)
+        assert got.sum() == pytest.approx(1.0, rel=1e-13)
+        checked += 1
+    assert checked > 0
+
+
+def test_pmis_hierarchy_solves_and_seeds(oracle_lib):
+    """The PMIS + BAMG direct hierarchy is deterministic for a seed, changes with it, and as a
+    preconditioner reaches the true relative residual; it does not combine with aggressive coarsening."""
+    O = oracle_lib
+    A, b, _ = __import__("workloads").config_system("c2", 16)
+    H1, H2 = O.Hierarchy(A, coarsen=O.COARSEN_PMIS, seed=1), O.Hierarchy(A, coarsen=O.COARSEN_PMIS, seed=1)
+    H3 = O.Hierarchy(A, coarsen=O.COARSEN_PMIS, seed=2)
+    assert np.array_equal(H1.level(0).cf, H2.level(0).cf) and not np.array_equal(H1.level(0).cf, H3.level(0).cf)
+    for sm, t in ((0, 2), (1, 3)):
+        r = H1.solve(b, smoother=sm, t=t)
+        assert r["status"] == 0 and np.linalg.norm(b - A.to_dense() @ r["x"]) <= 1e-8 * np.linalg.norm(b)
+    with pytest.raises(O.OracleFailure):
+        O.Hierarchy(A, coarsen=O.COARSEN_PMIS, agg_levels=1)
+    with pytest.raises(O.OracleFailure):
+        O.Hierarchy(A, coarsen=2)
