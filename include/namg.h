@@ -43,6 +43,7 @@ enum { NAMG_TRI_NEUMANN = 0, NAMG_TRI_DIRECT = 1 };   /* namg_solve_params.tri_m
 enum { NAMG_T_NEUMANN = 0, NAMG_T_DIRECT = 1 };       /* namg_solve_params.gmres_T   */
 enum { NAMG_STOP_RELRES = 0, NAMG_STOP_NRBE = 1 };    /* namg_solve_params.stop_rule */
 enum { NAMG_ILU0 = 0, NAMG_ILUT = 1 };                /* namg_setup_params.ilu_kind  */
+enum { NAMG_COARSEN_RS = 0, NAMG_COARSEN_PMIS = 1 };  /* namg_setup_params.coarsen   */
 
 #define NAMG_MAX_LEVELS 32
 #define NAMG_MAX_RESTART 128
@@ -70,6 +71,13 @@ typedef struct {
                      2), default 0: a second first pass over the C points with the distance-two strength
                      (paths of at most two strong connections) keeps C_2; P = P_1 P_2 with P_2 the classical
                      interpolation of A_1 = P_1^T A P_1 onto C_2, and A_c = P_2^T A_1 P_2 */
+  int coarsen;    /* NAMG_COARSEN_RS (default): host setup, Ruge-Stueben first pass and classical
+                     interpolation. NAMG_COARSEN_PMIS: setup on `device`, PMIS coarsening (Section 5.1; weights
+                     |S^T_i| + u_i, u_i the (i+1)-th SplitMix64 output of the stream seeded with seed + l on
+                     level l, top 53 bits in [0, 1)) with BAMG direct interpolation
+                     w_ij = -(a_ij + beta_i / n_i) / (a_ii + sum of the weak a_ik), beta_i the sum over
+                     strong F neighbours; not with agg_levels > 0 */
+  uint64_t seed;  /* PMIS stream seed; default 0 */
 } namg_setup_params;
 
 typedef struct {

@@ -23,6 +23,7 @@ TRI_NEUMANN, TRI_DIRECT = 0, 1
 T_NEUMANN, T_DIRECT = 0, 1
 STOP_RELRES, STOP_NRBE = 0, 1
 ILU0, ILUT = 0, 1
+COARSEN_RS, COARSEN_PMIS = 0, 1
 OP_SPMV, OP_RESIDUAL, OP_SMOOTH_PRE, OP_SMOOTH_POST, OP_RESTRICT, OP_PROLONG, OP_COARSE, OP_SPMV64 = range(8)
 MAX_LEVELS = 32
 
@@ -40,7 +41,7 @@ EXPORTED = (
 class SetupParams(C.Structure):
     _fields_ = [("theta", C.c_double), ("max_levels", C.c_int), ("max_coarse", C.c_int), ("precision", C.c_int),
                 ("ilu_levels", C.c_int), ("device", C.c_int), ("ilu_kind", C.c_int), ("ilut_lfil", C.c_int),
-                ("ilut_droptol", C.c_double), ("agg_levels", C.c_int)]
+                ("ilut_droptol", C.c_double), ("agg_levels", C.c_int), ("coarsen", C.c_int), ("seed", C.c_uint64)]
 
 
 class SolveParams(C.Structure):

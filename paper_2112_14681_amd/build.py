@@ -29,6 +29,7 @@ def build(verbose: bool = True) -> str:
     host_o = os.path.join(BUILD, "setup_host.o")
     diag_o = os.path.join(BUILD, "diagnostics.o")
     dev_o = os.path.join(BUILD, "solver.o")
+    gset_o = os.path.join(BUILD, "gpu_setup.o")
     _run(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fPIC", "-Wall", "-c",
           os.path.join(CSRC, "setup_host.cpp"), "-o", host_o])
     _run(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fPIC", "-Wall", "-c",
@@ -39,8 +40,11 @@ def build(verbose: bool = True) -> str:
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-mllvm", "-amdgpu-kernarg-preload-count=16",
           "-c", os.path.join(CSRC, "solver.hip"), "-o", dev_o])
+    _run([hipcc, f"--offload-arch={ARCH}", "-std=c++17", "-O3", "-fPIC", "-Wall",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-c", os.path.join(CSRC, "gpu_setup.hip"), "-o", gset_o])
     tmp = LIB + ".tmp"
-    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", host_o, diag_o, dev_o, "-o", tmp])
+    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", host_o, diag_o, dev_o, gset_o, "-o", tmp])
     os.replace(tmp, LIB)
     return LIB
 

@@ -20,6 +20,7 @@
 #include <queue>
 
 #include "../../include/namg.h"
+#include "gpu_setup.hpp"
 
 namespace namg {
 
@@ -669,26 +670,46 @@ HostCsr import_csr(int32_t n, const int32_t *rp, const int32_t *ci, const double
   return A;
 }
 
-HostHierarchy build_hierarchy(const HostCsr &A0, const namg_setup_params &p) {
-  const double theta = p.theta;
-  const int max_levels = p.max_levels, max_coarse = p.max_coarse, ilu_levels = p.ilu_levels;
-  if (!(theta > 0.0 && theta <= 1.0)) fail(NAMG_E_INVALID, "theta must be in (0, 1]");
+void validate_hierarchy_params(const namg_setup_params &p) {
+  if (!(p.theta > 0.0 && p.theta <= 1.0)) fail(NAMG_E_INVALID, "theta must be in (0, 1]");
   if (p.ilu_kind != NAMG_ILU0 && p.ilu_kind != NAMG_ILUT) fail(NAMG_E_INVALID, "unknown ilu_kind");
   if (p.agg_levels < 0) fail(NAMG_E_INVALID, "agg_levels must be >= 0");
+  if (p.coarsen != NAMG_COARSEN_RS && p.coarsen != NAMG_COARSEN_PMIS) fail(NAMG_E_INVALID, "unknown coarsen");
   if (p.ilu_kind == NAMG_ILUT && (!(p.ilut_droptol >= 0.0) || !std::isfinite(p.ilut_droptol) || p.ilut_lfil < 0))
     fail(NAMG_E_INVALID, "ILUT needs ilut_droptol >= 0 and ilut_lfil >= 0");
-  if (max_levels < 1 || max_levels > NAMG_MAX_LEVELS) fail(NAMG_E_INVALID, "max_levels out of range");
-  if (max_coarse < 1) fail(NAMG_E_INVALID, "max_coarse must be >= 1");
+  if (p.max_levels < 1 || p.max_levels > NAMG_MAX_LEVELS) fail(NAMG_E_INVALID, "max_levels out of range");
+  if (p.max_coarse < 1) fail(NAMG_E_INVALID, "max_coarse must be >= 1");
+}
+
+double inf_norm(const HostCsr &A) {
+  double m = 0.0;
+  for (int32_t i = 0; i < A.nr; ++i) {
+    double s = 0.0;
+    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) s += std::fabs(A.v[k]);
+    m = std::max(m, s);
+  }
+  return m;
+}
+
+void finish_hierarchy(HostHierarchy &H, const namg_setup_params &p) {
+  const int nl = (int)H.lv.size();
+  for (int l = 0; l < nl - 1; ++l) smoother_data(H.lv[l], p.ilu_levels < 0 || l < p.ilu_levels, p);
+  const HostCsr &Ac = H.lv.back().A;
+  if (Ac.nr > 4096) fail(NAMG_E_INVALID, "coarsest level has more than 4096 rows; raise max_levels");
+  H.coarse_inv = dense_inverse(Ac);
+}
+
+HostHierarchy build_hierarchy(const HostCsr &A0, const namg_setup_params &p) {
+  validate_hierarchy_params(p);
+  if (p.coarsen == NAMG_COARSEN_PMIS) return build_hierarchy_pmis_device(A0, p);
+  const double theta = p.theta;
+  const int max_levels = p.max_levels, max_coarse = p.max_coarse;
   HostHierarchy H;
   const bool trace = std::getenv("NAMG_SETUP_TRACE") != nullptr;
   double t_str = 0, t_rs = 0, t_int = 0, t_rap = 0;
   auto now = [] { return std::chrono::steady_clock::now(); };
   auto secs = [](auto a, auto b) { return std::chrono::duration<double>(b - a).count(); };
-  for (int32_t i = 0; i < A0.nr; ++i) {
-    double s = 0.0;
-    for (int32_t k = A0.rp[i]; k < A0.rp[i + 1]; ++k) s += std::fabs(A0.v[k]);
-    H.anorm_inf = std::max(H.anorm_inf, s);
-  }
+  H.anorm_inf = inf_norm(A0);
   H.lv.emplace_back();
   H.lv.back().A = A0;
   while (true) {
@@ -748,12 +769,8 @@ HostHierarchy build_hierarchy(const HostCsr &A0, const namg_setup_params &p) {
     next.A = std::move(Ac);
     H.lv.push_back(std::move(next));
   }
-  const int nl = (int)H.lv.size();
   auto t5 = now();
-  for (int l = 0; l < nl - 1; ++l) smoother_data(H.lv[l], ilu_levels < 0 || l < ilu_levels, p);
-  const HostCsr &Ac = H.lv.back().A;
-  if (Ac.nr > 4096) fail(NAMG_E_INVALID, "coarsest level has more than 4096 rows; raise max_levels");
-  H.coarse_inv = dense_inverse(Ac);
+  finish_hierarchy(H, p);
   if (trace)
     std::fprintf(stderr, "[namg setup] strength %.3f rs %.3f interp %.3f rap %.3f smoother+coarse %.3f s\n", t_str,
                  t_rs, t_int, t_rap, secs(t5, now()));

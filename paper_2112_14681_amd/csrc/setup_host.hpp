@@ -55,6 +55,12 @@ HostCsr import_csr(int32_t n, const int32_t *rp, const int32_t *ci, const double
 // device are the caller's). Throws SetupError on invalid parameters or a zero pivot.
 HostHierarchy build_hierarchy(const HostCsr &A, const namg_setup_params &p);
 
+// Parameter checks shared by both setups, ||A||_inf, and the host part that completes a hierarchy whose
+// levels (A, P, R, C/F) are built: smoother data of every level but the coarsest, the coarse inverse.
+void validate_hierarchy_params(const namg_setup_params &p);
+double inf_norm(const HostCsr &A);
+void finish_hierarchy(HostHierarchy &H, const namg_setup_params &p);
+
 // Dependency levels of a strict lower (lower = true) or upper triangle, for the direct comparators.
 LevelSchedule level_schedule(const HostCsr &T, bool lower);
 

@@ -915,6 +915,8 @@ void namg_default_setup_params(namg_setup_params *p) {
   p->ilut_lfil = 5;
   p->ilut_droptol = 1e-2;
   p->agg_levels = 0;
+  p->coarsen = NAMG_COARSEN_RS;
+  p->seed = 0;
 }
 
 void namg_default_solve_params(namg_solve_params *p) {
@@ -940,14 +942,18 @@ int namg_setup(int32_t n, const int32_t *rowptr, const int32_t *colind, const do
     if (p->precision != NAMG_FP64 && p->precision != NAMG_FP32_PRECOND)
       throw namg::SetupError{NAMG_E_INVALID, "unknown precision"};
     namg::HostCsr A = namg::import_csr(n, rowptr, colind, vals);
+    if (p->coarsen == NAMG_COARSEN_PMIS && p->device < 0)
+      throw namg::SetupError{NAMG_E_INVALID, "PMIS setup runs on a device (device >= 0)"};
+    if (p->device >= 0) {
+      int count = 0;
+      namg::hip_check(hipGetDeviceCount(&count), "hipGetDeviceCount");
+      if (p->device >= count) throw namg::SetupError{NAMG_E_INVALID, "device ordinal out of range"};
+    }
     auto h = std::make_unique<namg_hier>();
     h->host = namg::build_hierarchy(A, *p);
     h->precision = p->precision;
     h->device = p->device;
     if (p->device >= 0) {
-      int count = 0;
-      namg::hip_check(hipGetDeviceCount(&count), "hipGetDeviceCount");
-      if (p->device >= count) throw namg::SetupError{NAMG_E_INVALID, "device ordinal out of range"};
       if (p->precision == NAMG_FP64)
         h->dev = std::make_unique<namg::Solver<double>>(h->host, p->device);
       else

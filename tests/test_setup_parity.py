@@ -141,6 +141,16 @@ def test_ilut_every_level_and_nonsymmetric(namg, oracle_lib):
                        ilut_droptol=5e-3, ilut_lfil=4)
 
 
+def test_pmis_setup_validation(namg):
+    """The device setup needs a device and does not combine with aggressive coarsening; an unknown
+    coarsening is rejected (all before any device work)."""
+    A = poisson2d(12)
+    assert _err(namg, lambda: namg.Hierarchy(A, device=-1, coarsen=namg.COARSEN_PMIS)) == namg.E_INVALID
+    assert _err(namg, lambda: namg.Hierarchy(A, device=-1, coarsen=2)) == namg.E_INVALID
+    p = namg.setup_params()
+    assert (p.coarsen, p.seed) == (namg.COARSEN_RS, 0)
+
+
 def test_ilut_parameter_validation(namg):
     A = poisson2d(12)
     for bad in (dict(ilu_kind=2), dict(agg_levels=-1), dict(ilu_kind=1, ilut_lfil=-1), dict(ilu_kind=1, ilut_droptol=-1e-3),
