@@ -43,6 +43,8 @@ def _args():
     ap.add_argument("--serve-inflight", type=int, default=64)
     ap.add_argument("--serve-setup-threads", type=int, default=14)
     ap.add_argument("--serve-only", action="store_true")
+    ap.add_argument("--serve-coarsen", default="pmis", choices=["rs", "pmis"],
+                    help="setup of the served requests: the device PMIS setup (default) or host RS")
     ap.add_argument("--nonnormality", action="store_true",
                     help="the factor study of Section 5.3.4 instead of the benchmark: orderings of C4 (Table 2) "
                          "and an ILUT fill sweep (Tables 3-5), with GMRES iterations when a GPU is present")
@@ -113,11 +115,12 @@ def _gen_request(args):
     return varcoef3d(N, 0.5, seed)
 
 
-def served_stream(namg, count, inflight, setup_threads):
+def served_stream(namg, count, inflight, setup_threads, coarsen="pmis"):
     """Replay the first `count` requests of the served stream (Poisson arrivals at 50/s, n log-uniform in
     [32, 160], variable-k pressure systems) against the continuous-batching server: FP32 AMG + FP64 GMRES(30),
     polynomial GS with 2 Neumann terms, tol 1e-8. Latency runs from each request's scheduled arrival to its
-    completion on the server's clock."""
+    completion on the server's clock. coarsen "rs": host setup (RS, classical interpolation); "pmis": the
+    device setup (PMIS, BAMG direct interpolation)."""
     import multiprocessing as mp
     from concurrent.futures import ProcessPoolExecutor, ThreadPoolExecutor
 
@@ -137,7 +140,10 @@ def served_stream(namg, count, inflight, setup_threads):
         if delay > 0:
             time.sleep(delay)
         A, b = systems[j]
-        return srv.submit(A, b, ilu_levels=0)  # polynomial GS throughout: no ILU(0) factors to build
+        # polynomial GS throughout: no ILU(0) factors to build
+        if coarsen == "pmis":
+            return srv.submit(A, b, ilu_levels=0, coarsen=namg.COARSEN_PMIS, seed=j)
+        return srv.submit(A, b, ilu_levels=0)
 
     with ThreadPoolExecutor(max_workers=4) as ex:
         tickets = list(ex.map(submit, range(count)))
@@ -162,7 +168,7 @@ def served_stream(namg, count, inflight, setup_threads):
         "alg_GBps_while_serving": round(sum(r["alg_bytes"] for r in results) / span / 1e9, 1),
         "peak_inflight": counters["peak_inflight"], "ticks": counters["ticks"], "batched_launches": counters["launches"],
         "peak_device_GB": round(counters["peak_device_bytes"] / 1e9, 2),
-        "setup_threads": setup_threads, "max_inflight": inflight,
+        "setup_threads": setup_threads, "max_inflight": inflight, "setup": coarsen,
     }
 
 
@@ -263,7 +269,7 @@ def main():
     if args.serve_only:
         print(json.dumps({"metric": "served latency of the pressure-system request stream",
                           "served": served_stream(namg, args.serve_requests, args.serve_inflight,
-                                                  args.serve_setup_threads)}), flush=True)
+                                                  args.serve_setup_threads, args.serve_coarsen)}), flush=True)
         return
 
     A, b, meta = config_system(args.config, args.N)
@@ -383,7 +389,8 @@ def main():
 
     if args.serve_requests > 0:
         H.close()
-        out["served"] = served_stream(namg, args.serve_requests, args.serve_inflight, args.serve_setup_threads)
+        out["served"] = served_stream(namg, args.serve_requests, args.serve_inflight, args.serve_setup_threads,
+                                      args.serve_coarsen)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, b, kw, st["iters"])
     print(json.dumps(out), flush=True)

@@ -110,6 +110,13 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`"
                           " (the HIP library is required; there is no CPU fallback)")
+    # One HIP runtime per process: torch ships its own, and a second one loaded first (the system's, which
+    # the library links) finds no device once torch has initialised its copy. Importing torch first makes
+    # the library resolve to torch's already-loaded runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     vp, i32p, f64p, i8p, i64p = C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_int8), \
         C.POINTER(C.c_int64)

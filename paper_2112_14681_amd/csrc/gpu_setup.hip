@@ -14,8 +14,13 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <condition_variable>
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -533,37 +538,79 @@ class Builder {
   DevBuf<uint8_t> temp_;
 };
 
-}  // namespace
+// At most MAX_DEVICE_SETUPS device phases run at once per process (each holds a few GB of scratch at
+// 10^6-10^7 rows, outside any serving budget); the host part that follows is not limited.
+constexpr int MAX_DEVICE_SETUPS = 4;
 
-HostHierarchy build_hierarchy_pmis_device(const HostCsr &A0, const namg_setup_params &p) {
-  validate_hierarchy_params(p);
-  if (p.device < 0) throw SetupError{NAMG_E_INVALID, "PMIS setup runs on a device (device >= 0)"};
-  if (p.agg_levels > 0) throw SetupError{NAMG_E_INVALID, "aggressive coarsening needs coarsen = NAMG_COARSEN_RS"};
+class SetupSlots {
+ public:
+  void acquire() {
+    std::unique_lock<std::mutex> lk(mu_);
+    cv_.wait(lk, [&] { return busy_ < MAX_DEVICE_SETUPS; });
+    ++busy_;
+  }
+  void release() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      --busy_;
+    }
+    cv_.notify_one();
+  }
+
+ private:
+  std::mutex mu_;
+  std::condition_variable cv_;
+  int busy_ = 0;
+};
+
+struct SlotHold {
+  SetupSlots &s;
+  explicit SlotHold(SetupSlots &slots) : s(slots) { s.acquire(); }
+  ~SlotHold() { s.release(); }
+};
+
+// The levels of H (whose level 0 holds A_0) built on the device, on a stream of their own.
+void device_levels(HostHierarchy &H, const namg_setup_params &p) {
+  static SetupSlots slots;
+  const bool trace = std::getenv("NAMG_SETUP_TRACE") != nullptr;
+  auto now = [] { return std::chrono::steady_clock::now(); };
+  auto ms = [](auto a, auto b) { return std::chrono::duration<double, std::milli>(b - a).count(); };
+  const auto t_wait = now();
+  SlotHold hold(slots);
+  const auto t_start = now();
   Guard g(p.device);
   Stream st;
   Builder B(st.s);
-  HostHierarchy H;
-  H.anorm_inf = inf_norm(A0);
-  H.lv.emplace_back();
-  H.lv.back().A = A0;
   DCsr A;
-  B.upload(A, A0);
+  B.upload(A, H.lv[0].A);
+  if (trace) std::fprintf(stderr, "[namg device setup] slot wait %.1f ms, upload %.1f ms\n", ms(t_wait, t_start),
+                          ms(t_start, now()));
   while (true) {
     HostLevel &L = H.lv.back();
     const int32_t n = L.A.nr;
     if (n <= p.max_coarse || (int)H.lv.size() >= p.max_levels) break;
     std::vector<int8_t> cf;
     DCsr P;
+    const auto t0 = now();
     if (!B.coarsen(A, p.theta, p.seed + (uint64_t)(H.lv.size() - 1), cf, P)) break;
+    const auto t1 = now();
     DCsr R, AP, Ac;
     B.transpose(P, R);
     B.spgemm(A, P, AP);
+    const auto t2 = now();
     B.spgemm(R, AP, Ac);
+    const auto t3 = now();
     L.cf = std::move(cf);
     B.download(L.P, P);
     B.download(L.R, R);
     HostLevel next;
     B.download(next.A, Ac);
+    if (trace)
+      std::fprintf(stderr,
+                   "[namg device setup]   level %d n %d nnz %lld: strength+pmis+interp %.2f, R and AP %.2f, R(AP) "
+                   "%.2f, download %.2f ms (nnz P %lld AP %lld Ac %lld)\n",
+                   (int)H.lv.size() - 1, n, (long long)A.nnz, ms(t0, t1), ms(t1, t2), ms(t2, t3), ms(t3, now()),
+                   (long long)P.nnz, (long long)AP.nnz, (long long)Ac.nnz);
     for (int32_t i = 0; i < next.A.nr; ++i) {
       double d = 0.0;
       for (int32_t k = next.A.rp[i]; k < next.A.rp[i + 1]; ++k)
@@ -573,6 +620,19 @@ HostHierarchy build_hierarchy_pmis_device(const HostCsr &A0, const namg_setup_pa
     H.lv.push_back(std::move(next));
     A = std::move(Ac);
   }
+}
+
+}  // namespace
+
+HostHierarchy build_hierarchy_pmis_device(const HostCsr &A0, const namg_setup_params &p) {
+  validate_hierarchy_params(p);
+  if (p.device < 0) throw SetupError{NAMG_E_INVALID, "PMIS setup runs on a device (device >= 0)"};
+  if (p.agg_levels > 0) throw SetupError{NAMG_E_INVALID, "aggressive coarsening needs coarsen = NAMG_COARSEN_RS"};
+  HostHierarchy H;
+  H.anorm_inf = inf_norm(A0);
+  H.lv.emplace_back();
+  H.lv.back().A = A0;
+  device_levels(H, p);
   finish_hierarchy(H, p);
   return H;
 }

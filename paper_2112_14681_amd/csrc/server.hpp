@@ -641,15 +641,8 @@ class Server final : public ServerBase {
       }
       r->tm.setup_start = clock();
       try {
-        if (r->sp.coarsen == NAMG_COARSEN_PMIS) {
-          // device setup on the server's GPU, one request at a time (its scratch memory is outside the
-          // HBM budget)
-          r->sp.device = p_.device;
-          std::lock_guard<std::mutex> glk(gpu_setup_mu_);
-          r->H = std::make_unique<HostHierarchy>(build_hierarchy(r->A, r->sp));
-        } else {
-          r->H = std::make_unique<HostHierarchy>(build_hierarchy(r->A, r->sp));
-        }
+        if (r->sp.coarsen == NAMG_COARSEN_PMIS) r->sp.device = p_.device;  // device setup on the server's GPU
+        r->H = std::make_unique<HostHierarchy>(build_hierarchy(r->A, r->sp));
         r->footprint = solver_footprint<T>(*r->H, p_.solve.restart) + 16 * (int64_t)r->A.nr;
         r->A = HostCsr{};
       } catch (const SetupError &e) {
@@ -815,7 +808,7 @@ class Server final : public ServerBase {
   namg_server_params p_;
   std::chrono::steady_clock::time_point t0_;
   Engine eng_;
-  std::mutex mu_, gpu_setup_mu_;
+  std::mutex mu_;
   std::condition_variable cv_setup_, cv_admit_, cv_sched_, cv_done_;
   std::deque<Req *> setup_q_, admit_q_;
   std::vector<Req *> join_q_;
