@@ -359,6 +359,7 @@ def main():
                                            ("ilut_direct", dict(smoother=namg.SMOOTH_ILU0, tri_mode=namg.TRI_DIRECT),
                                             prec, ilut),
                                            ("aggressive2", {}, prec, dict(agg_levels=2)),
+                                           ("pmis_device_setup", {}, prec, dict(coarsen=namg.COARSEN_PMIS)),
                                            ("fp32_precond", {}, namg.FP32_PRECOND, None), ("fp64", {}, namg.FP64, None)):
             if setup2 is ilut:
                 if H_ilut is None:
