@@ -35,6 +35,9 @@ def _args():
     ap.add_argument("--terms", type=int, default=3)
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--gmres-T", default="neumann", choices=["neumann", "direct"])
+    ap.add_argument("--max-coarse", type=int, default=None,
+                    help="coarsen to at most this many rows (dense direct solve on the coarsest level); default "
+                         "50 for c1, whose configuration fixes it, 1000 otherwise")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare", action="store_true",
                     help="also time the direct-triangular, l1-Jacobi and FP32-preconditioner variants")
@@ -172,12 +175,13 @@ def served_stream(namg, count, inflight, setup_threads, coarsen="pmis"):
     }
 
 
-def cpu_baseline(A, b, kw, gpu_iters):
-    """The oracle (single-threaded FP64 C++) on the same system: setup excluded, full solve timed."""
+def cpu_baseline(A, b, kw, gpu_iters, max_coarse):
+    """The oracle (single-threaded FP64 C++) on the same system and hierarchy configuration: setup
+    excluded, full solve timed."""
     import oracle
 
     t0 = time.perf_counter()
-    G = oracle.Hierarchy(A)
+    G = oracle.Hierarchy(A, max_coarse=max_coarse)
     setup_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     r = G.solve(b, tol=kw["tol"], restart=kw["restart"], smoother=kw["smoother"], tri_mode=kw["tri_mode"],
@@ -275,7 +279,9 @@ def main():
     A, b, meta = config_system(args.config, args.N)
     prec = namg.FP64 if args.precision == "fp64" else namg.FP32_PRECOND
     t0 = time.perf_counter()
-    H = namg.Hierarchy(A, device=0, precision=prec, ilu_levels=1)
+    if args.max_coarse is None:
+        args.max_coarse = 50 if args.config == "c1" else 1000
+    H = namg.Hierarchy(A, device=0, precision=prec, ilu_levels=1, max_coarse=args.max_coarse)
     setup_ms = (time.perf_counter() - t0) * 1e3
     info = H.info()
     kw = dict(tol=1e-8, restart=args.restart, smoother=namg.SMOOTH_ILU0 if args.smoother == "ilu0" else namg.SMOOTH_PGS,
@@ -322,7 +328,7 @@ def main():
                 "c4rcm": "3-D upwind conv-diff RCM order"}[meta["name"]] + f" N={meta['N']}",
             "n": A.n, "nnz": A.nnz, "smoother": args.smoother, "tri_mode": args.tri, "inner_terms": args.terms,
             "restart": args.restart, "gmres_T": args.gmres_T, "precision": args.precision, "tol": 1e-8,
-            "levels": info["levels"], "op_complexity": round(info["op_complexity"], 3),
+            "max_coarse": args.max_coarse, "levels": info["levels"], "op_complexity": round(info["op_complexity"], 3),
         },
         "iters": st["iters"],
         "relres": st["relres_true"],
@@ -364,15 +370,17 @@ def main():
             if setup2 is ilut:
                 if H_ilut is None:
                     t0 = time.perf_counter()
-                    H_ilut = namg.Hierarchy(A, device=0, precision=prec, ilu_levels=1, **setup2)
+                    H_ilut = namg.Hierarchy(A, device=0, precision=prec, ilu_levels=1, max_coarse=args.max_coarse,
+                                            **setup2)
                     ilut_setup_ms = (time.perf_counter() - t0) * 1e3
                 H2 = H_ilut
             elif setup2 is not None:
                 t0 = time.perf_counter()
-                H2 = namg.Hierarchy(A, device=0, precision=prec, ilu_levels=1, **setup2)
+                H2 = namg.Hierarchy(A, device=0, precision=prec, ilu_levels=1, max_coarse=args.max_coarse, **setup2)
                 other_setup_ms = (time.perf_counter() - t0) * 1e3
             else:
-                H2 = H if prec2 == prec else namg.Hierarchy(A, device=0, precision=prec2, ilu_levels=1)
+                H2 = H if prec2 == prec else namg.Hierarchy(A, device=0, precision=prec2, ilu_levels=1,
+                                                            max_coarse=args.max_coarse)
             kw2 = dict(kw, **extra)
             ms2, st2 = _time_solves(torch, H2, bt, xt, kw2, max(1, args.steps // 2), 1)
             cmp[name] = {"ms": round(ms2, 3), "iters": st2[-1]["iters"], "relres": st2[-1]["relres_true"]}
@@ -393,7 +401,7 @@ def main():
         out["served"] = served_stream(namg, args.serve_requests, args.serve_inflight, args.serve_setup_threads,
                                       args.serve_coarsen)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(A, b, kw, st["iters"])
+        out["cpu_baseline"] = cpu_baseline(A, b, kw, st["iters"], args.max_coarse)
     print(json.dumps(out), flush=True)
 
 

@@ -3,8 +3,9 @@
     python tests/golden/make_golden.py c2   ->  c2_128_fp64_ilu0_t3.json   (about a minute)
     python tests/golden/make_golden.py c3   ->  c3_192_fp64_pgs_t2.json    (a few minutes)
 
-c2: the benchmark's configuration. 7-point Poisson, N = 128 (2 097 152 rows), b ~ N(0, 1) seed 1,
-RS-AMG theta = 0.25 coarsened to <= 50 rows, hybrid V-cycle (ILU(0) on level 0, polynomial GS elsewhere)
+Both use the benchmark's launch configuration: RS-AMG theta = 0.25 coarsened to <= 1000 rows (a dense
+direct solve on the coarsest level).
+c2: the benchmark's workload. 7-point Poisson, N = 128 (2 097 152 rows), b ~ N(0, 1) seed 1, hybrid V-cycle (ILU(0) on level 0, polynomial GS elsewhere)
 with 3 Neumann terms, low-sync MGS-GMRES(30) with T = I - L, tol 1e-8, FP64.
 c3: -div(k grad p), cell-centred, N = 192 (7 077 888 rows), lognormal k (sigma 1, seed 2), z spacing
 stretched 1:100; polynomial GS with 2 Neumann terms on every level, GMRES(30), tol 1e-8, FP64 (the
@@ -29,6 +30,8 @@ import oracle  # noqa: E402
 from workloads import config_system  # noqa: E402
 
 
+MAX_COARSE = 1000
+
 CONFIGS = {
     "c2": dict(file="c2_128_fp64_ilu0_t3.json", smoother="ILU0", t=3, ilu_levels=1,
                desc={"workload": "3-D Poisson 7-point", "rhs_seed": 1, "smoother": "ILU0 hybrid", "inner_terms": 3}),
@@ -43,7 +46,7 @@ def main():
     cfg = CONFIGS[name]
     A, b, meta = config_system(name)
     t0 = time.time()
-    H = oracle.Hierarchy(A, theta=0.25, max_levels=25, max_coarse=50, ilu_levels=cfg["ilu_levels"])
+    H = oracle.Hierarchy(A, theta=0.25, max_levels=25, max_coarse=MAX_COARSE, ilu_levels=cfg["ilu_levels"])
     t1 = time.time()
     levels = []
     for l in range(H.levels):
@@ -61,7 +64,8 @@ def main():
     idx = np.sort(np.random.default_rng(2024).choice(A.n, 4096, replace=False))
     out = {
         "source": f"oracle/ (CPU FP64), written by tests/golden/make_golden.py {name}",
-        "config": dict(cfg["desc"], N=meta["N"], theta=0.25, max_coarse=50, restart=30, gmres_T="I-L", tol=1e-8),
+        "config": dict(cfg["desc"], N=meta["N"], theta=0.25, max_coarse=MAX_COARSE, restart=30, gmres_T="I-L",
+                       tol=1e-8),
         "levels": levels,
         "iters": r["iters"],
         "cycles": r["cycles"],

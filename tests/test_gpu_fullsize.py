@@ -1,6 +1,6 @@
 """GPU parity at the benchmark's full size: 3-D Poisson 128^3 (2 097 152 rows), hybrid ILU(0)/poly-GS
 V-cycle with 3 Neumann terms, low-sync GMRES(30) with T = I - L, FP64, in the launch configuration the
-benchmark times.
+benchmark times (coarsened to <= 1000 rows, dense solve on the coarsest level).
 
 The expected values were written by tests/golden/make_golden.py, which calls only the CPU oracle:
 every level's size and C/F splitting (SHA-256), the iteration count, the residual estimate after every
@@ -22,6 +22,7 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_128_fp64_ilu0_t3.json")
 SOLVE = dict(smoother=1, tri_mode=0, inner_terms=3, restart=30, gmres_T=0, tol=1e-8)
+MAX_COARSE = 1000  # the benchmark's coarsest-level bound for C2 and C3
 
 
 @pytest.fixture(scope="module")
@@ -43,7 +44,7 @@ def golden():
 def system(namg):
     A, b, meta = config_system("c2")
     assert meta["N"] == 128
-    H = namg.Hierarchy(A, device=0, ilu_levels=1)
+    H = namg.Hierarchy(A, device=0, ilu_levels=1, max_coarse=MAX_COARSE)
     return A, b, H
 
 
@@ -96,7 +97,7 @@ def test_residual_history_matches_oracle(namg, golden, system):
 
 def test_fp32_preconditioner_full_size(namg, golden, system):
     A, b, _ = system
-    H32 = namg.Hierarchy(A, device=0, precision=namg.FP32_PRECOND, ilu_levels=1)
+    H32 = namg.Hierarchy(A, device=0, precision=namg.FP32_PRECOND, ilu_levels=1, max_coarse=MAX_COARSE)
     st, x = _solve(namg, H32, b)
     res = np.linalg.norm(b - O.spmv(A, x)) / np.linalg.norm(b)
     assert st["status"] == namg.OK and res <= 1e-8
@@ -126,7 +127,7 @@ def system_c3(namg):
 def test_c3_fp64_matches_oracle(namg, golden_c3, system_c3):
     """-div(k grad p) at 192^3 (7 077 888 rows, lognormal k, z stretched 1:100), polynomial GS t = 2."""
     A, b = system_c3
-    H = namg.Hierarchy(A, device=0, ilu_levels=0)
+    H = namg.Hierarchy(A, device=0, ilu_levels=0, max_coarse=MAX_COARSE)
     info = H.info()
     assert info["levels"] == len(golden_c3["levels"])
     for l, g in enumerate(golden_c3["levels"]):
@@ -148,7 +149,7 @@ def test_c3_fp32_preconditioner(namg, golden_c3, system_c3):
     """The C3 configuration's FP32 hierarchy and V-cycle under FP64 GMRES: the same 1e-8 true residual
     (independent FP64 SpMV) in at most two more iterations than the FP64 oracle."""
     A, b = system_c3
-    H = namg.Hierarchy(A, device=0, precision=namg.FP32_PRECOND, ilu_levels=0)
+    H = namg.Hierarchy(A, device=0, precision=namg.FP32_PRECOND, ilu_levels=0, max_coarse=MAX_COARSE)
     st, x = _solve(namg, H, b, **SOLVE_C3)
     H.close()
     res = np.linalg.norm(b - O.spmv(A, x)) / np.linalg.norm(b)
