@@ -293,7 +293,10 @@ double namg_server_clock(const namg_server *s);
 /* Stop the threads and release everything; requests still queued or in flight are dropped. */
 void namg_server_destroy(namg_server *s);
 
-/* Release the hierarchy and all its device memory. NULL is ignored. */
+/* Release the hierarchy. Waits for the device to finish pending work (namg_vcycle / namg_apply on the
+ * caller's stream), then returns its device memory to the library's block cache: freed blocks are
+ * handed to later allocations of the same size class instead of being freed (a free can wait for every
+ * stream of the device), up to 32 GiB cached per device, held until the process ends. NULL is ignored. */
 void namg_destroy(namg_hier *h);
 
 /* Message of the last error on the calling thread ("" if none). */

@@ -7,6 +7,8 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstdlib>
+#include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -32,7 +34,50 @@ struct MemCounter {
   int64_t bytes = 0;
 };
 
-// One device allocation, freed by the destructor (so a failed setup leaks nothing).
+// Device memory blocks are recycled instead of freed: a released block is kept per (device, size class)
+// and handed to the next allocation of that class, so a process that keeps setting up and solving
+// systems (a server) reaches a steady state without hipMalloc or hipFree; a free can wait for work on
+// every stream of the device. Size classes are 1/8-octave steps above 4 KiB (at most 12.5 % rounding);
+// at most CACHE_CAP bytes stay cached per device, beyond that blocks are freed. Cached blocks live until
+// the process ends.
+class BlockCache {
+ public:
+  static constexpr size_t CACHE_CAP = size_t(32) << 30;
+  static BlockCache &instance() {
+    static BlockCache c;
+    return c;
+  }
+  static size_t size_class(size_t bytes) {
+    if (bytes <= 4096) return 4096;
+    int k = 63 - __builtin_clzll((unsigned long long)bytes);
+    const size_t step = size_t(1) << (k - 3);
+    return (bytes + step - 1) / step * step;
+  }
+  void *take(int dev, size_t cls) {
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = free_.find({dev, cls});
+    if (it == free_.end() || it->second.empty()) return nullptr;
+    void *p = it->second.back();
+    it->second.pop_back();
+    cached_[dev] -= cls;
+    return p;
+  }
+  // true when the block was kept; false: the caller frees it
+  bool put(int dev, size_t cls, void *p) {
+    std::lock_guard<std::mutex> lk(mu_);
+    if (cached_[dev] + cls > CACHE_CAP) return false;
+    free_[{dev, cls}].push_back(p);
+    cached_[dev] += cls;
+    return true;
+  }
+
+ private:
+  std::mutex mu_;
+  std::map<std::pair<int, size_t>, std::vector<void *>> free_;
+  std::map<int, size_t> cached_;
+};
+
+// One device allocation, returned to the block cache by the destructor (so a failed setup leaks nothing).
 template <class T>
 class DevBuf {
  public:
@@ -48,6 +93,8 @@ class DevBuf {
       p_ = o.p_;
       n_ = o.n_;
       mc_ = o.mc_;
+      dev_ = o.dev_;
+      cls_ = o.cls_;
       o.p_ = nullptr;
       o.n_ = 0;
       o.mc_ = nullptr;
@@ -57,7 +104,14 @@ class DevBuf {
   void alloc(size_t n, MemCounter *mc) {
     release();
     if (n == 0) n = 1;
-    hip_check(hipMalloc(&p_, n * sizeof(T)), "hipMalloc");
+    hip_check(hipGetDevice(&dev_), "hipGetDevice");
+    cls_ = BlockCache::size_class(n * sizeof(T));
+    p_ = static_cast<T *>(BlockCache::instance().take(dev_, cls_));
+    if (!p_) {
+      void *q = nullptr;
+      hip_check(hipMalloc(&q, cls_), "hipMalloc");
+      p_ = static_cast<T *>(q);
+    }
     n_ = n;
     mc_ = mc;
     if (mc_) mc_->bytes += (int64_t)(n * sizeof(T));
@@ -67,7 +121,13 @@ class DevBuf {
   }
   void release() {
     if (p_) {
-      (void)hipFree(p_);
+      if (!BlockCache::instance().put(dev_, cls_, p_)) {
+        int cur = -1;
+        (void)hipGetDevice(&cur);
+        if (cur != dev_) (void)hipSetDevice(dev_);
+        (void)hipFree(p_);
+        if (cur != dev_ && cur >= 0) (void)hipSetDevice(cur);
+      }
       if (mc_) mc_->bytes -= (int64_t)(n_ * sizeof(T));
     }
     p_ = nullptr;
@@ -80,6 +140,8 @@ class DevBuf {
   T *p_ = nullptr;
   size_t n_ = 0;
   MemCounter *mc_ = nullptr;
+  int dev_ = 0;
+  size_t cls_ = 0;
 };
 
 // Sparse operators on the device come in one of two layouts, chosen per matrix at setup from its row

@@ -259,8 +259,9 @@ __global__ __launch_bounds__(TB) void k_spgemm_size(int32_t nrows, const int32_t
   tsize[i] = ts;
 }
 
-// Row i of X Y accumulated into its own open-addressing table [toff[i], toff[i+1]); cnt[i] = distinct
-// columns, cnt[nrows] = 0.
+// Row i of X Y accumulated into its own open-addressing table [toff[i], toff[i+1]) (keys cleared to -1
+// beforehand); the slot of each new column is appended to order[toff[i] + c], so the row's entries can be
+// read back without scanning the table; cnt[i] = distinct columns, cnt[nrows] = 0.
 __global__ __launch_bounds__(TB) void k_spgemm_accumulate(int32_t nrows, const int32_t *__restrict__ xrp,
                                                           const int32_t *__restrict__ xci,
                                                           const double *__restrict__ xv,
@@ -268,7 +269,8 @@ __global__ __launch_bounds__(TB) void k_spgemm_accumulate(int32_t nrows, const i
                                                           const int32_t *__restrict__ yci,
                                                           const double *__restrict__ yv,
                                                           const int64_t *__restrict__ toff, int32_t *__restrict__ tkey,
-                                                          double *__restrict__ tval, int32_t *__restrict__ cnt) {
+                                                          double *__restrict__ tval, int32_t *__restrict__ order,
+                                                          int32_t *__restrict__ cnt) {
   const int32_t i = blockIdx.x * TB + threadIdx.x;
   if (i == nrows) cnt[nrows] = 0;
   if (i >= nrows) return;
@@ -280,7 +282,7 @@ __global__ __launch_bounds__(TB) void k_spgemm_accumulate(int32_t nrows, const i
   }
   int32_t *key = tkey + base;
   double *acc = tval + base;
-  for (int64_t h = 0; h < ts; ++h) key[h] = -1;
+  int32_t *ord = order + base;
   const uint32_t mask = (uint32_t)(ts - 1);
   int32_t c = 0;
   for (int32_t k = xrp[i]; k < xrp[i + 1]; ++k) {
@@ -294,6 +296,7 @@ __global__ __launch_bounds__(TB) void k_spgemm_accumulate(int32_t nrows, const i
       if (key[h] == -1) {
         key[h] = J;
         acc[h] = prod;
+        ord[c] = (int32_t)h;
         ++c;
       } else {
         acc[h] += prod;
@@ -303,22 +306,22 @@ __global__ __launch_bounds__(TB) void k_spgemm_accumulate(int32_t nrows, const i
   cnt[i] = c;
 }
 
-// Row i of the product: the table's entries, sorted by column.
+// Row i of the product: its entries in insertion order, then sorted by column.
 __global__ __launch_bounds__(TB) void k_spgemm_emit(int32_t nrows, const int64_t *__restrict__ toff,
                                                     const int32_t *__restrict__ tkey, const double *__restrict__ tval,
-                                                    const int32_t *__restrict__ crp, int32_t *__restrict__ cci,
-                                                    double *__restrict__ cv) {
+                                                    const int32_t *__restrict__ order, const int32_t *__restrict__ crp,
+                                                    int32_t *__restrict__ cci, double *__restrict__ cv) {
   const int32_t i = blockIdx.x * TB + threadIdx.x;
   if (i >= nrows) return;
-  const int64_t base = toff[i], ts = toff[i + 1] - base;
-  const int32_t a = crp[i];
+  const int64_t base = toff[i];
+  const int32_t a = crp[i], b = crp[i + 1];
   int32_t out = a;
-  for (int64_t h = 0; h < ts; ++h)
-    if (tkey[base + h] != -1) {
-      cci[out] = tkey[base + h];
-      cv[out] = tval[base + h];
-      ++out;
-    }
+  for (int32_t q = 0; q < b - a; ++q) {
+    const int64_t h = base + order[base + q];
+    cci[out] = tkey[h];
+    cv[out] = tval[h];
+    ++out;
+  }
   for (int32_t k = a + 1; k < out; ++k) {
     const int32_t c = cci[k];
     const double x = cv[k];
@@ -427,10 +430,13 @@ class Builder {
     const int64_t total = read_at(toff.get() + nr);
     DevBuf<int32_t> tkey((size_t)std::max<int64_t>(total, 1), nullptr);
     DevBuf<double> tval((size_t)std::max<int64_t>(total, 1), nullptr);
+    DevBuf<int32_t> order((size_t)std::max<int64_t>(total, 1), nullptr);
     DevBuf<int32_t> cnt((size_t)nr + 1, nullptr);
+    // every key to -1 (all bytes 0xFF) in one coalesced pass
+    hip_check(hipMemsetAsync(tkey.get(), 0xFF, (size_t)std::max<int64_t>(total, 1) * 4, s_), "memset");
     hipLaunchKernelGGL(k_spgemm_accumulate, dim3(grid_for((int64_t)nr + 1)), dim3(TB), 0, s_, nr, X.rp.get(),
                        X.ci.get(), X.v.get(), Y.rp.get(), Y.ci.get(), Y.v.get(), toff.get(), tkey.get(), tval.get(),
-                       cnt.get());
+                       order.get(), cnt.get());
     check("k_spgemm_accumulate");
     C.nr = nr;
     C.nc = Y.nc;
@@ -440,7 +446,7 @@ class Builder {
     C.ci.alloc((size_t)std::max<int64_t>(C.nnz, 1), nullptr);
     C.v.alloc((size_t)std::max<int64_t>(C.nnz, 1), nullptr);
     hipLaunchKernelGGL(k_spgemm_emit, dim3(grid_for(nr)), dim3(TB), 0, s_, nr, toff.get(), tkey.get(), tval.get(),
-                       C.rp.get(), C.ci.get(), C.v.get());
+                       order.get(), C.rp.get(), C.ci.get(), C.v.get());
     check("k_spgemm_emit");
     sync();
   }

@@ -93,6 +93,7 @@ class BatchEngine {
   }
   hipStream_t stream() const { return s_; }
   int64_t launches() const { return launches_; }
+  double sync_seconds() const { return sync_s_; }
 
   // Advance every slot that is not DONE by one step. Throws HipError on a runtime failure.
   void tick(std::vector<Slot *> &slots) {
@@ -499,13 +500,16 @@ class BatchEngine {
       hip_check(hipGetLastError(), "batched launch");
       launches_++;
     }
+    const auto w0 = std::chrono::steady_clock::now();
     hip_check(hipStreamSynchronize(s_), "hipStreamSynchronize");
+    sync_s_ += std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
   }
 
   int dev_;
   namg_solve_params p_;
   CycleOpts o_;
   hipStream_t s_ = nullptr;
+  double sync_s_ = 0.0;
   std::vector<char> stage_;
   std::vector<Group> groups_;
   char *pinned_ = nullptr, *dbuf_ = nullptr;
@@ -547,6 +551,7 @@ class Server final : public ServerBase {
   explicit Server(const namg_server_params &p) : p_(p), t0_(std::chrono::steady_clock::now()), eng_(p.device, p.solve) {
     for (int q = 0; q < p_.setup_threads; ++q) setup_.emplace_back([this] { setup_loop(); });
     sched_ = std::thread([this] { sched_loop(); });
+    finisher_ = std::thread([this] { finish_loop(); });
   }
 
   ~Server() override {
@@ -558,8 +563,10 @@ class Server final : public ServerBase {
     cv_admit_.notify_all();
     cv_sched_.notify_all();
     cv_done_.notify_all();
+    cv_finish_.notify_all();
     for (auto &t : setup_) t.join();
     sched_.join();
+    finisher_.join();
     DeviceGuard g(p_.device);
     reqs_.clear();
   }
@@ -760,7 +767,26 @@ class Server final : public ServerBase {
   void sched_loop() {
     (void)hipSetDevice(p_.device);
     std::vector<Req *> active;
+    // NAMG_SERVER_TRACE: where the scheduler thread's time goes (printed when the server stops)
+    const bool trace = std::getenv("NAMG_SERVER_TRACE") != nullptr;
+    double t_idle = 0.0, t_tick = 0.0, t_complete = 0.0;
+    auto sec = [] { return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count(); };
+    struct Report {
+      bool on;
+      const double &idle, &tick, &comp;
+      ~Report() {
+        if (on) std::fprintf(stderr, "[namg server] scheduler: idle %.3f s, ticks %.3f s, hand-off %.3f s\n", idle, tick, comp);
+      }
+    } report{trace, t_idle, t_tick, t_complete};
+    struct SyncReport {
+      bool on;
+      const Engine &e;
+      ~SyncReport() {
+        if (on) std::fprintf(stderr, "[namg server] ticks: %.3f s waiting for the device\n", e.sync_seconds());
+      }
+    } sync_report{trace, eng_};
     while (true) {
+      const double w0 = trace ? sec() : 0.0;
       {
         std::unique_lock<std::mutex> lk(mu_);
         if (active.empty()) cv_sched_.wait(lk, [&] { return stop_ || !join_q_.empty(); });
@@ -768,6 +794,8 @@ class Server final : public ServerBase {
         for (Req *r : join_q_) active.push_back(r);
         join_q_.clear();
       }
+      const double w1 = trace ? sec() : 0.0;
+      t_idle += w1 - w0;
       std::vector<typename Engine::Slot *> slots;
       for (Req *r : active) slots.push_back(&r->slot);
       try {
@@ -783,25 +811,51 @@ class Server final : public ServerBase {
         std::lock_guard<std::mutex> lk(mu_);
         ticks_++;
       }
+      const double w2 = trace ? sec() : 0.0;
+      t_tick += w2 - w1;
+      // finished solves go to the finisher thread: copying x back and freeing the solve's device memory
+      // (whose frees can wait for the whole device) must not hold up the next tick
       std::vector<Req *> still;
+      bool handed = false;
       for (Req *r : active) {
         if (r->slot.phase != Engine::DONE) {
           still.push_back(r);
           continue;
         }
-        try {
-          complete(r);
-        } catch (const HipError &e) {
-          r->status = e.code;
-          r->err = e.msg;
-        }
         std::lock_guard<std::mutex> lk(mu_);
-        used_ -= r->footprint;
-        inflight_--;
-        finish_locked(r);
-        cv_admit_.notify_all();
+        finish_q_.push_back(r);
+        handed = true;
       }
+      if (handed) cv_finish_.notify_one();
       active.swap(still);
+      if (trace) t_complete += sec() - w2;
+    }
+  }
+
+  // Completes finished solves: x to the host, statistics, device memory released, then the request's
+  // HBM share is returned to admission.
+  void finish_loop() {
+    (void)hipSetDevice(p_.device);
+    while (true) {
+      Req *r = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_finish_.wait(lk, [&] { return stop_ || !finish_q_.empty(); });
+        if (finish_q_.empty()) return;  // stopping, nothing left
+        r = finish_q_.front();
+        finish_q_.pop_front();
+      }
+      try {
+        complete(r);
+      } catch (const HipError &e) {
+        r->status = e.code;
+        r->err = e.msg;
+      }
+      std::lock_guard<std::mutex> lk(mu_);
+      used_ -= r->footprint;
+      inflight_--;
+      finish_locked(r);
+      cv_admit_.notify_all();
     }
   }
 
@@ -809,12 +863,12 @@ class Server final : public ServerBase {
   std::chrono::steady_clock::time_point t0_;
   Engine eng_;
   std::mutex mu_;
-  std::condition_variable cv_setup_, cv_admit_, cv_sched_, cv_done_;
-  std::deque<Req *> setup_q_, admit_q_;
+  std::condition_variable cv_setup_, cv_admit_, cv_sched_, cv_done_, cv_finish_;
+  std::deque<Req *> setup_q_, admit_q_, finish_q_;
   std::vector<Req *> join_q_;
   std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs_;
   std::vector<std::thread> setup_;
-  std::thread sched_;
+  std::thread sched_, finisher_;
   bool stop_ = false;
   uint64_t next_ = 1;
   int64_t used_ = 0, peak_ = 0, inflight_ = 0, peak_inflight_ = 0, submitted_ = 0, completed_ = 0, failed_ = 0;

@@ -1107,6 +1107,9 @@ void namg_destroy(namg_hier *h) {
   try {
     if (h->dev) {
       namg::DeviceGuard g(h->device);
+      // namg_vcycle and namg_apply may still run on the caller's stream; the hierarchy's device blocks go
+      // back to the block cache for reuse, so they must be idle first
+      (void)hipDeviceSynchronize();
       h->dev.reset();
     }
   } catch (...) {
