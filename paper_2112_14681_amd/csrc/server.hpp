@@ -545,6 +545,7 @@ class Server final : public ServerBase {
     int status = NAMG_PENDING;
     std::string err;
     bool done = false, counted = false;
+    double tm_granted = 0.0;  // admission granted (before the device upload)
   };
 
  public:
@@ -567,6 +568,9 @@ class Server final : public ServerBase {
     for (auto &t : setup_) t.join();
     sched_.join();
     finisher_.join();
+    if (std::getenv("NAMG_SERVER_TRACE"))
+      std::fprintf(stderr, "[namg server] setup threads, summed over requests: setup %.3f s, admission wait %.3f s, "
+                           "device upload %.3f s\n", t_setup_, t_wait_admit_, t_upload_);
     DeviceGuard g(p_.device);
     reqs_.clear();
   }
@@ -686,6 +690,7 @@ class Server final : public ServerBase {
         });
         if (stop_) return;
         admit_q_.pop_front();
+        r->tm_granted = clock();
         used_ += r->footprint;
         peak_ = std::max(peak_, used_);
         inflight_++;
@@ -731,6 +736,9 @@ class Server final : public ServerBase {
       {
         std::lock_guard<std::mutex> lk(mu_);
         join_q_.push_back(r);
+        t_setup_ += r->tm.setup_done - r->tm.setup_start;
+        t_wait_admit_ += r->tm_granted - r->tm.setup_done;
+        t_upload_ += r->tm.admitted - r->tm_granted;
       }
       cv_sched_.notify_one();
     }
@@ -873,6 +881,7 @@ class Server final : public ServerBase {
   uint64_t next_ = 1;
   int64_t used_ = 0, peak_ = 0, inflight_ = 0, peak_inflight_ = 0, submitted_ = 0, completed_ = 0, failed_ = 0;
   int64_t ticks_ = 0;
+  double t_setup_ = 0.0, t_wait_admit_ = 0.0, t_upload_ = 0.0;
 };
 
 }  // namespace namg
