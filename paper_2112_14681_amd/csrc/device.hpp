@@ -62,6 +62,24 @@ class BlockCache {
     cached_[dev] -= cls;
     return p;
   }
+  // Frees every cached block of device dev (current device must be dev); returns the bytes released.
+  size_t trim(int dev) {
+    std::lock_guard<std::mutex> lk(mu_);
+    size_t freed = 0;
+    for (auto it = free_.begin(); it != free_.end();) {
+      if (it->first.first != dev) {
+        ++it;
+        continue;
+      }
+      for (void *p : it->second) {
+        (void)hipFree(p);
+        freed += it->first.second;
+      }
+      it = free_.erase(it);
+    }
+    cached_[dev] = 0;
+    return freed;
+  }
   // true when the block was kept; false: the caller frees it
   bool put(int dev, size_t cls, void *p) {
     std::lock_guard<std::mutex> lk(mu_);
@@ -109,7 +127,12 @@ class DevBuf {
     p_ = static_cast<T *>(BlockCache::instance().take(dev_, cls_));
     if (!p_) {
       void *q = nullptr;
-      hip_check(hipMalloc(&q, cls_), "hipMalloc");
+      hipError_t e = hipMalloc(&q, cls_);
+      if (e == hipErrorOutOfMemory && BlockCache::instance().trim(dev_) > 0) {
+        (void)hipGetLastError();  // clear the failed allocation's error, then retry with the cache emptied
+        e = hipMalloc(&q, cls_);
+      }
+      hip_check(e, "hipMalloc");
       p_ = static_cast<T *>(q);
     }
     n_ = n;
