@@ -278,13 +278,22 @@ struct DMat {
     narrow = fits_col16(A);
     group = force_group > 0 ? force_group : choose_group(nrows, nnz);
     std::vector<int32_t> hptr;
-    std::vector<int32_t> hcol;  // column of each stored entry (padding: -1)
+    std::vector<int32_t> hcol;  // wide columns (padding: column 0)
+    std::vector<int16_t> h16;   // narrow offsets from the owning row's base (padding: offset 0)
     std::vector<T> hval;
     if (group > 1) {
       stored = nnz;
       hptr = A.rp;
-      hcol = A.ci;
       hval.assign(A.v.begin(), A.v.end());
+      if (narrow) {
+        h16.resize(nnz);
+        for (int32_t r = 0; r < nrows; ++r) {
+          const int32_t base = diag_base(r, mul);
+          for (int32_t k = A.rp[r]; k < A.rp[r + 1]; ++k) h16[k] = (int16_t)(A.ci[k] - base);
+        }
+      } else {
+        hcol = A.ci;
+      }
     } else {
       const int32_t nslices = (nrows + SELL_C - 1) / SELL_C;
       hptr.assign(nslices + 1, 0);
@@ -295,38 +304,37 @@ struct DMat {
         hptr[s + 1] = hptr[s] + w * SELL_C;
       }
       stored = hptr[nslices];
-      hcol.assign(stored, -1);
-      hval.assign(stored, T(0));
-      for (int32_t s = 0; s < nslices; ++s)
-        for (int32_t lane = 0; lane < SELL_C; ++lane) {
-          const int32_t r = s * SELL_C + lane;
-          if (r >= nrows) break;
-          for (int32_t k = 0; k < A.rp[r + 1] - A.rp[r]; ++k) {
-            const int64_t d = hptr[s] + (int64_t)k * SELL_C + lane;
-            hcol[d] = A.ci[A.rp[r] + k];
-            hval[d] = (T)A.v[A.rp[r] + k];
+      hval.resize(stored);
+      if (narrow)
+        h16.resize(stored);
+      else
+        hcol.resize(stored);
+      // one pass in storage order (entry k of every row of the slice, lane by lane), so the writes stream
+      // and the reads come from 64 row cursors
+      for (int32_t s = 0; s < nslices; ++s) {
+        const int32_t r0 = s * SELL_C;
+        const int32_t width = (hptr[s + 1] - hptr[s]) / SELL_C;
+        int64_t d = hptr[s];
+        for (int32_t k = 0; k < width; ++k) {
+          for (int32_t lane = 0; lane < SELL_C; ++lane, ++d) {
+            const int32_t r = r0 + lane;
+            const bool has = r < nrows && k < A.rp[r + 1] - A.rp[r];
+            const int32_t c = has ? A.ci[A.rp[r] + k] : -1;
+            hval[d] = has ? (T)A.v[A.rp[r] + k] : T(0);
+            if (narrow)
+              h16[d] = has ? (int16_t)(c - diag_base(r, mul)) : (int16_t)0;
+            else
+              hcol[d] = has ? c : 0;
           }
         }
+      }
     }
     ptr.alloc(hptr.size(), mc);
     ptr.upload(hptr.data(), hptr.size());
     if (narrow) {
-      // offsets from the owning row's base; SELL entry d belongs to row 64 * slice + (d - ptr[slice]) % 64
-      std::vector<int16_t> h16(hcol.size(), 0);
-      if (group > 1) {
-        for (int32_t r = 0; r < nrows; ++r)
-          for (int32_t k = hptr[r]; k < hptr[r + 1]; ++k) h16[k] = (int16_t)(hcol[k] - diag_base(r, mul));
-      } else {
-        for (size_t s = 0; s + 1 < hptr.size(); ++s)
-          for (int32_t d = hptr[s]; d < hptr[s + 1]; ++d) {
-            const int32_t r = (int32_t)s * SELL_C + (d - hptr[s]) % SELL_C;
-            h16[d] = hcol[d] < 0 ? (int16_t)0 : (int16_t)(hcol[d] - diag_base(r, mul));
-          }
-      }
       col16.alloc(h16.size(), mc);
       col16.upload(h16.data(), h16.size());
     } else {
-      for (auto &c : hcol) c = std::max(c, 0);
       col.alloc(hcol.size(), mc);
       col.upload(hcol.data(), hcol.size());
     }
