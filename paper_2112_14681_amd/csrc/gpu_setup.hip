@@ -630,16 +630,20 @@ void device_levels(HostHierarchy &H, const namg_setup_params &p) {
 
 }  // namespace
 
-HostHierarchy build_hierarchy_pmis_device(const HostCsr &A0, const namg_setup_params &p) {
+HostHierarchy build_hierarchy_pmis_device(HostCsr &&A0, const namg_setup_params &p) {
   validate_hierarchy_params(p);
   if (p.device < 0) throw SetupError{NAMG_E_INVALID, "PMIS setup runs on a device (device >= 0)"};
   if (p.agg_levels > 0) throw SetupError{NAMG_E_INVALID, "aggressive coarsening needs coarsen = NAMG_COARSEN_RS"};
   HostHierarchy H;
   H.anorm_inf = inf_norm(A0);
   H.lv.emplace_back();
-  H.lv.back().A = A0;
+  H.lv.back().A = std::move(A0);
+  const auto t0 = std::chrono::steady_clock::now();
   device_levels(H, p);
+  const auto t1 = std::chrono::steady_clock::now();
   finish_hierarchy(H, p);
+  H.t_levels = std::chrono::duration<double>(t1 - t0).count();
+  H.t_finish = std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
   return H;
 }
 

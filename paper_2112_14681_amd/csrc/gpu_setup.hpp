@@ -9,6 +9,6 @@ namespace namg {
 
 // The hierarchy of p with coarsen = NAMG_COARSEN_PMIS, built level by level on device p.device (seed of
 // level l: p.seed + l). Throws SetupError (invalid parameters, zero coarse diagonal) or HipError.
-HostHierarchy build_hierarchy_pmis_device(const HostCsr &A, const namg_setup_params &p);
+HostHierarchy build_hierarchy_pmis_device(HostCsr &&A, const namg_setup_params &p);
 
 }  // namespace namg

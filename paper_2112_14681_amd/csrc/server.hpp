@@ -569,8 +569,9 @@ class Server final : public ServerBase {
     sched_.join();
     finisher_.join();
     if (std::getenv("NAMG_SERVER_TRACE"))
-      std::fprintf(stderr, "[namg server] setup threads, summed over requests: setup %.3f s, admission wait %.3f s, "
-                           "device upload %.3f s\n", t_setup_, t_wait_admit_, t_upload_);
+      std::fprintf(stderr, "[namg server] setup threads, summed over requests: setup %.3f s (device levels %.3f s, "
+                           "host finish %.3f s), admission wait %.3f s, device upload %.3f s\n", t_setup_, t_levels_,
+                   t_finish_, t_wait_admit_, t_upload_);
     DeviceGuard g(p_.device);
     reqs_.clear();
   }
@@ -653,8 +654,8 @@ class Server final : public ServerBase {
       r->tm.setup_start = clock();
       try {
         if (r->sp.coarsen == NAMG_COARSEN_PMIS) r->sp.device = p_.device;  // device setup on the server's GPU
-        r->H = std::make_unique<HostHierarchy>(build_hierarchy(r->A, r->sp));
-        r->footprint = solver_footprint<T>(*r->H, p_.solve.restart) + 16 * (int64_t)r->A.nr;
+        r->H = std::make_unique<HostHierarchy>(build_hierarchy(std::move(r->A), r->sp));
+        r->footprint = solver_footprint<T>(*r->H, p_.solve.restart) + 16 * (int64_t)r->H->lv[0].A.nr;
         r->A = HostCsr{};
       } catch (const SetupError &e) {
         std::lock_guard<std::mutex> lk(mu_);
@@ -737,6 +738,8 @@ class Server final : public ServerBase {
         std::lock_guard<std::mutex> lk(mu_);
         join_q_.push_back(r);
         t_setup_ += r->tm.setup_done - r->tm.setup_start;
+        t_levels_ += r->H->t_levels;
+        t_finish_ += r->H->t_finish;
         t_wait_admit_ += r->tm_granted - r->tm.setup_done;
         t_upload_ += r->tm.admitted - r->tm_granted;
       }
@@ -881,7 +884,7 @@ class Server final : public ServerBase {
   uint64_t next_ = 1;
   int64_t used_ = 0, peak_ = 0, inflight_ = 0, peak_inflight_ = 0, submitted_ = 0, completed_ = 0, failed_ = 0;
   int64_t ticks_ = 0;
-  double t_setup_ = 0.0, t_wait_admit_ = 0.0, t_upload_ = 0.0;
+  double t_setup_ = 0.0, t_wait_admit_ = 0.0, t_upload_ = 0.0, t_levels_ = 0.0, t_finish_ = 0.0;
 };
 
 }  // namespace namg

@@ -570,26 +570,46 @@ std::vector<double> dense_inverse(const HostCsr &A) {
 }
 
 void smoother_data(HostLevel &L, bool with_ilu, const namg_setup_params &p) {
+  // One pass per row: 1 / a_ii, 1 / sum_j |a_ij| (l1-Jacobi), and D^{-1}L, D^{-1}U with entries a_ij / a_ii
   const HostCsr &A = L.A;
-  L.dinv.resize(A.nr);
-  for (int32_t i = 0; i < A.nr; ++i) {
+  const int32_t n = A.nr;
+  L.dinv.resize(n);
+  L.dl1inv.resize(n);
+  HostCsr &lo = L.pgs_lo, &up = L.pgs_up;
+  lo.nr = up.nr = n;
+  lo.nc = up.nc = A.nc;
+  lo.rp.assign(n + 1, 0);
+  up.rp.assign(n + 1, 0);
+  int64_t nlo = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const int32_t *b = A.ci.data() + A.rp[i], *e = A.ci.data() + A.rp[i + 1];
+    nlo += std::lower_bound(b, e, i) - b;
+  }
+  const int64_t nup = A.nnz() - nlo - n;
+  lo.ci.resize(nlo);
+  lo.v.resize(nlo);
+  up.ci.resize(std::max<int64_t>(nup, 0));
+  up.v.resize(std::max<int64_t>(nup, 0));
+  int64_t ql = 0, qu = 0;
+  for (int32_t i = 0; i < n; ++i) {
     const double d = diagonal(A, i);
     if (d == 0.0) fail(NAMG_E_ZERO_PIVOT, "zero diagonal in row " + std::to_string(i));
     L.dinv[i] = 1.0 / d;
-  }
-  L.dl1inv.resize(A.nr);
-  for (int32_t i = 0; i < A.nr; ++i) {
-    double d = 0.0;
-    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) d += std::fabs(A.v[k]);
-    L.dl1inv[i] = 1.0 / d;
-  }
-  // D^{-1}L and D^{-1}U: a_ij / a_ii
-  L.pgs_lo = strict_part(A, A.v, true, {});
-  L.pgs_up = strict_part(A, A.v, false, {});
-  for (int32_t i = 0; i < A.nr; ++i) {
-    const double d = diagonal(A, i);
-    for (int32_t k = L.pgs_lo.rp[i]; k < L.pgs_lo.rp[i + 1]; ++k) L.pgs_lo.v[k] /= d;
-    for (int32_t k = L.pgs_up.rp[i]; k < L.pgs_up.rp[i + 1]; ++k) L.pgs_up.v[k] /= d;
+    double l1 = 0.0;
+    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      const int32_t j = A.ci[k];
+      l1 += std::fabs(A.v[k]);
+      if (j < i) {
+        lo.ci[ql] = j;
+        lo.v[ql++] = A.v[k] / d;
+      } else if (j > i) {
+        up.ci[qu] = j;
+        up.v[qu++] = A.v[k] / d;
+      }
+    }
+    L.dl1inv[i] = 1.0 / l1;
+    lo.rp[i + 1] = (int32_t)ql;
+    up.rp[i + 1] = (int32_t)qu;
   }
   if (with_ilu) {
     // L \ U as one CSR: ILU(0) values in A's pattern, or the ILUT factor with its own fill
@@ -699,9 +719,15 @@ void finish_hierarchy(HostHierarchy &H, const namg_setup_params &p) {
   H.coarse_inv = dense_inverse(Ac);
 }
 
+HostHierarchy build_hierarchy(HostCsr &&A0, const namg_setup_params &p) {
+  validate_hierarchy_params(p);
+  if (p.coarsen == NAMG_COARSEN_PMIS) return build_hierarchy_pmis_device(std::move(A0), p);
+  return build_hierarchy(static_cast<const HostCsr &>(A0), p);
+}
+
 HostHierarchy build_hierarchy(const HostCsr &A0, const namg_setup_params &p) {
   validate_hierarchy_params(p);
-  if (p.coarsen == NAMG_COARSEN_PMIS) return build_hierarchy_pmis_device(A0, p);
+  if (p.coarsen == NAMG_COARSEN_PMIS) return build_hierarchy_pmis_device(HostCsr(A0), p);
   const double theta = p.theta;
   const int max_levels = p.max_levels, max_coarse = p.max_coarse;
   HostHierarchy H;

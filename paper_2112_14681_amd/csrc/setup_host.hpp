@@ -46,6 +46,7 @@ struct HostHierarchy {
   std::vector<HostLevel> lv;
   std::vector<double> coarse_inv;  // dense inverse of the coarsest operator, row-major
   double anorm_inf = 0.0;          // ||A_0||_inf
+  double t_levels = 0.0, t_finish = 0.0;  // seconds: building the levels (device phase incl. waits), finishing
 };
 
 // Throws SetupError{NAMG_E_INVALID / NAMG_E_NONFINITE / NAMG_E_ZERO_PIVOT} on malformed input.
@@ -54,6 +55,8 @@ HostCsr import_csr(int32_t n, const int32_t *rp, const int32_t *ci, const double
 // The hierarchy of namg_setup_params p (theta, max_levels, max_coarse and the ILU fields; precision and
 // device are the caller's). Throws SetupError on invalid parameters or a zero pivot.
 HostHierarchy build_hierarchy(const HostCsr &A, const namg_setup_params &p);
+// The same, taking ownership of A (the device setup keeps it as level 0 without a copy).
+HostHierarchy build_hierarchy(HostCsr &&A, const namg_setup_params &p);
 
 // Parameter checks shared by both setups, ||A||_inf, and the host part that completes a hierarchy whose
 // levels (A, P, R, C/F) are built: smoother data of every level but the coarsest, the coarse inverse.
