@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstdlib>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
@@ -33,6 +34,74 @@ inline void hip_check(hipError_t e, const char *what) {
 struct MemCounter {
   int64_t bytes = 0;
 };
+
+// Host<->device copies of pageable memory go through a pool of pinned staging buffers (64 MiB chunks):
+// the runtime's own pageable path shares one staging route among all threads, and many setup threads copy
+// at once. The pool holds as many buffers as copies ever ran at the same time, for the life of the
+// process.
+class PinnedPool {
+ public:
+  static constexpr size_t CHUNK = size_t(64) << 20;
+  static PinnedPool &instance() {
+    static PinnedPool p;
+    return p;
+  }
+  char *acquire() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      if (!free_.empty()) {
+        char *b = free_.back();
+        free_.pop_back();
+        return b;
+      }
+    }
+    void *b = nullptr;
+    hip_check(hipHostMalloc(&b, CHUNK, hipHostMallocDefault), "hipHostMalloc");
+    return static_cast<char *>(b);
+  }
+  void release(char *b) {
+    std::lock_guard<std::mutex> lk(mu_);
+    free_.push_back(b);
+  }
+
+ private:
+  std::mutex mu_;
+  std::vector<char *> free_;
+};
+
+// Synchronous copies through one pinned staging buffer, chunk by chunk.
+inline void copy_to_device(void *dst, const void *src, size_t bytes) {
+  if (bytes == 0) return;
+  PinnedPool &pool = PinnedPool::instance();
+  char *stage = pool.acquire();
+  struct Back {
+    PinnedPool &p;
+    char *b;
+    ~Back() { p.release(b); }
+  } back{pool, stage};
+  for (size_t off = 0; off < bytes; off += PinnedPool::CHUNK) {
+    const size_t c = std::min(PinnedPool::CHUNK, bytes - off);
+    std::memcpy(stage, static_cast<const char *>(src) + off, c);
+    hip_check(hipMemcpy(static_cast<char *>(dst) + off, stage, c, hipMemcpyHostToDevice), "hipMemcpy H2D");
+  }
+}
+
+inline void copy_to_host(void *dst, const void *src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return;
+  PinnedPool &pool = PinnedPool::instance();
+  char *stage = pool.acquire();
+  struct Back {
+    PinnedPool &p;
+    char *b;
+    ~Back() { p.release(b); }
+  } back{pool, stage};
+  for (size_t off = 0; off < bytes; off += PinnedPool::CHUNK) {
+    const size_t c = std::min(PinnedPool::CHUNK, bytes - off);
+    hip_check(hipMemcpyAsync(stage, static_cast<const char *>(src) + off, c, hipMemcpyDeviceToHost, s), "D2H");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    std::memcpy(static_cast<char *>(dst) + off, stage, c);
+  }
+}
 
 // Device memory blocks are recycled instead of freed: a released block is kept per (device, size class)
 // and handed to the next allocation of that class, so a process that keeps setting up and solving
@@ -139,9 +208,7 @@ class DevBuf {
     mc_ = mc;
     if (mc_) mc_->bytes += (int64_t)(n * sizeof(T));
   }
-  void upload(const T *h, size_t n) {
-    if (n) hip_check(hipMemcpy(p_, h, n * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy H2D");
-  }
+  void upload(const T *h, size_t n) { copy_to_device(p_, h, n * sizeof(T)); }
   void release() {
     if (p_) {
       if (!BlockCache::instance().put(dev_, cls_, p_)) {

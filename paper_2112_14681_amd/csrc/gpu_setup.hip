@@ -370,10 +370,11 @@ class Builder {
 
   void check(const char *what) { hip_check(hipGetLastError(), what); }
 
+  // copies through pinned staging; synchronises the stream
   template <class T>
   void to_host(std::vector<T> &h, const DevBuf<T> &d, size_t n) {
     h.resize(n);
-    if (n) hip_check(hipMemcpyAsync(h.data(), d.get(), n * sizeof(T), hipMemcpyDeviceToHost, s_), "D2H");
+    copy_to_host(h.data(), d.get(), n * sizeof(T), s_);
   }
   void sync() { hip_check(hipStreamSynchronize(s_), "hipStreamSynchronize"); }
 
@@ -402,12 +403,9 @@ class Builder {
     D.rp.alloc(A.rp.size(), nullptr);
     D.ci.alloc(A.ci.size(), nullptr);
     D.v.alloc(A.v.size(), nullptr);
-    hip_check(hipMemcpyAsync(D.rp.get(), A.rp.data(), A.rp.size() * 4, hipMemcpyHostToDevice, s_), "H2D");
-    if (D.nnz) {
-      hip_check(hipMemcpyAsync(D.ci.get(), A.ci.data(), A.ci.size() * 4, hipMemcpyHostToDevice, s_), "H2D");
-      hip_check(hipMemcpyAsync(D.v.get(), A.v.data(), A.v.size() * 8, hipMemcpyHostToDevice, s_), "H2D");
-    }
-    sync();
+    D.rp.upload(A.rp.data(), A.rp.size());
+    D.ci.upload(A.ci.data(), A.ci.size());
+    D.v.upload(A.v.data(), A.v.size());
   }
 
   void download(HostCsr &H, const DCsr &D) {
