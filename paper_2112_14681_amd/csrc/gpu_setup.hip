@@ -544,7 +544,7 @@ class Builder {
 
 // At most MAX_DEVICE_SETUPS device phases run at once per process (each holds a few GB of scratch at
 // 10^6-10^7 rows, outside any serving budget); the host part that follows is not limited.
-constexpr int MAX_DEVICE_SETUPS = 4;
+constexpr int MAX_DEVICE_SETUPS = 8;
 
 class SetupSlots {
  public:
