@@ -426,6 +426,9 @@ class Builder {
     check("k_spgemm_size");
     scan(tsize.get(), toff.get(), (int64_t)nr + 1);
     const int64_t total = read_at(toff.get() + nr);
+    // every table is at least twice its row's entry count, so total / 2 bounds the product's entries,
+    // whose row pointers are 32-bit
+    if (total / 2 >= (int64_t)INT32_MAX) throw SetupError{NAMG_E_INVALID, "sparse product exceeds 2^31 entries"};
     DevBuf<int32_t> tkey((size_t)std::max<int64_t>(total, 1), nullptr);
     DevBuf<double> tval((size_t)std::max<int64_t>(total, 1), nullptr);
     DevBuf<int32_t> order((size_t)std::max<int64_t>(total, 1), nullptr);
