@@ -150,3 +150,28 @@ def test_served_stream_subset_alone_vs_mix(namg):
         assert a["iters"] == m["iters"]
         assert np.array_equal(a["x"], m["x"])
         assert relres(A, b, m["x"]) <= 1e-8
+
+
+def test_device_setup_requests_in_the_mix(namg):
+    """Requests set up on the device (PMIS, one seed each) with 8 setup threads, so that device setups,
+    batched solves and completions overlap and recycled device blocks are handed from one request to the
+    next: every result equals namg_solve on the same device-built hierarchy bit for bit, and reaches the
+    1e-8 true relative residual. Mixed with host-setup (RS) requests and the backward-error stop rule."""
+    systems = stream_systems(24, nmin=12, nmax=40, seed=11)
+    solve = dict(SOLVE, stop_rule=namg.STOP_NRBE)
+    srv = namg.Server(solve=solve, max_inflight=8, setup_threads=8, precision=0)
+    setups = [dict(coarsen=namg.COARSEN_PMIS, seed=50 + j, ilu_levels=0) if j % 3 else dict(ilu_levels=0)
+              for j in range(len(systems))]
+    tickets = [srv.submit(A, b, **sp) for (A, b), sp in zip(systems, setups)]
+    results = [srv.wait(t) for t in tickets]
+    srv.close()
+    for (A, b), sp, r in zip(systems, setups, results):
+        H = namg.Hierarchy(A, device=0, **sp)
+        bt = torch.from_numpy(b).to("cuda:0")
+        xt = torch.zeros_like(bt)
+        st = H.solve(bt, xt, **solve)
+        H.close()
+        assert r["status"] == namg.OK and st["status"] == namg.OK
+        assert r["iters"] == st["iters"], (sp, r["iters"], st["iters"])
+        assert np.array_equal(r["x"], xt.cpu().numpy()), sp
+        assert r["nrbe"] <= 1e-8
