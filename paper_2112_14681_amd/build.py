@@ -30,6 +30,7 @@ def build(verbose: bool = True) -> str:
     diag_o = os.path.join(BUILD, "diagnostics.o")
     dev_o = os.path.join(BUILD, "solver.o")
     gset_o = os.path.join(BUILD, "gpu_setup.o")
+    pack_o = os.path.join(BUILD, "pack.o")
     _run(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fPIC", "-Wall", "-c",
           os.path.join(CSRC, "setup_host.cpp"), "-o", host_o])
     _run(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fPIC", "-Wall", "-c",
@@ -43,8 +44,11 @@ def build(verbose: bool = True) -> str:
     _run([hipcc, f"--offload-arch={ARCH}", "-std=c++17", "-O3", "-fPIC", "-Wall",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-c", os.path.join(CSRC, "gpu_setup.hip"), "-o", gset_o])
+    _run([hipcc, f"--offload-arch={ARCH}", "-std=c++17", "-O3", "-fPIC", "-Wall",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-c", os.path.join(CSRC, "pack.hip"), "-o", pack_o])
     tmp = LIB + ".tmp"
-    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", host_o, diag_o, dev_o, gset_o, "-o", tmp])
+    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", host_o, diag_o, dev_o, gset_o, pack_o, "-o", tmp])
     os.replace(tmp, LIB)
     return LIB
 

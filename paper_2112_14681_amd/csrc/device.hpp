@@ -234,6 +234,20 @@ class DevBuf {
   size_t cls_ = 0;
 };
 
+// A CSR matrix on the device with FP64 values.
+struct DCsr {
+  int32_t nr = 0, nc = 0;
+  int64_t nnz = 0;
+  DevBuf<int32_t> rp, ci;
+  DevBuf<double> v;
+};
+
+// The operators of a hierarchy built on the device, kept there for its solve-phase layouts: A for every
+// level, P and R for every level but the coarsest.
+struct DeviceLevels {
+  std::vector<DCsr> A, P, R;
+};
+
 // Sparse operators on the device come in one of two layouts, chosen per matrix at setup from its row
 // lengths so that every row kernel keeps enough independent loads in flight:
 //  * group == 1: SELL-64. Rows are cut into slices of 64 consecutive rows (one wavefront); slice s

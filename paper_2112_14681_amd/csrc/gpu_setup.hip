@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <condition_variable>
+#include <memory>
 #include <cstdint>
 #include <mutex>
 #include <string>
@@ -356,13 +357,6 @@ struct Stream {
   }
 };
 
-// A device CSR.
-struct DCsr {
-  int32_t nr = 0, nc = 0;
-  int64_t nnz = 0;
-  DevBuf<int32_t> rp, ci;
-  DevBuf<double> v;
-};
 
 class Builder {
  public:
@@ -588,6 +582,7 @@ void device_levels(HostHierarchy &H, const namg_setup_params &p) {
   Guard g(p.device);
   Stream st;
   Builder B(st.s);
+  auto keep = std::make_shared<DeviceLevels>();
   DCsr A;
   B.upload(A, H.lv[0].A);
   if (trace) std::fprintf(stderr, "[namg device setup] slot wait %.1f ms, upload %.1f ms\n", ms(t_wait, t_start),
@@ -625,8 +620,14 @@ void device_levels(HostHierarchy &H, const namg_setup_params &p) {
       if (d == 0.0) throw SetupError{NAMG_E_ZERO_PIVOT, "zero diagonal in a coarse operator"};
     }
     H.lv.push_back(std::move(next));
+    keep->A.push_back(std::move(A));
+    keep->P.push_back(std::move(P));
+    keep->R.push_back(std::move(R));
     A = std::move(Ac);
   }
+  keep->A.push_back(std::move(A));
+  // the levels stay on the device for the solve-phase layouts (packed there, see pack.hip)
+  H.device_levels = keep;
 }
 
 }  // namespace

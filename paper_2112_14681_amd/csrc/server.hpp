@@ -701,6 +701,7 @@ class Server final : public ServerBase {
       try {
         const int32_t n = r->H->lv[0].A.nr;
         r->sv = std::make_unique<Solver<T>>(*r->H, p_.device);
+        r->H->device_levels.reset();  // packed into the solver's layouts; the blocks go back to the cache
         r->sv->reserve_workspace(p_.solve.restart);
         r->bd.alloc(n, nullptr);
         r->bd.upload(r->b.data(), n);

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -47,6 +48,9 @@ struct HostHierarchy {
   std::vector<double> coarse_inv;  // dense inverse of the coarsest operator, row-major
   double anorm_inf = 0.0;          // ||A_0||_inf
   double t_levels = 0.0, t_finish = 0.0;  // seconds: building the levels (device phase incl. waits), finishing
+  // Levels built on the device (a DeviceLevels, opaque here): the solve-phase layouts are packed from them
+  // on the device; released once they are built.
+  std::shared_ptr<void> device_levels;
 };
 
 // Throws SetupError{NAMG_E_INVALID / NAMG_E_NONFINITE / NAMG_E_ZERO_PIVOT} on malformed input.

@@ -21,6 +21,7 @@
 #include "../../include/namg.h"
 #include "device.hpp"
 #include "kernels.hpp"
+#include "pack.hpp"
 #include "setup_host.hpp"
 
 namespace namg {
@@ -138,6 +139,10 @@ class Solver final : public SolverBase {
     DeviceGuard g(dev_);
     const int nl = (int)H.lv.size();
     lv_.resize(nl);
+    // levels built on the device are packed there (same bytes as the host packing below)
+    const DeviceLevels *dl = (H.device_levels && device_packing_enabled())
+                                 ? static_cast<const DeviceLevels *>(H.device_levels.get())
+                                 : nullptr;
     for (int l = 0; l < nl; ++l) {
       const HostLevel &h = H.lv[l];
       DevLevel<T> &d = lv_[l];
@@ -145,13 +150,23 @@ class Solver final : public SolverBase {
       d.b.alloc(d.n, &mc_);
       d.x.alloc(d.n, &mc_);
       if (l == nl - 1) break;
-      d.A.build(h.A, &mc_);
-      d.P.build(h.P, &mc_);
-      d.R.build(h.R, &mc_);
-      d.pgs_lo.build(h.pgs_lo, &mc_);
-      d.pgs_up.build(h.pgs_up, &mc_);
-      upload_vec(d.dinv, h.dinv);
-      upload_vec(d.dl1inv, h.dl1inv);
+      if (dl) {
+        pack_device(d.A, dl->A[l], &mc_);
+        pack_device(d.P, dl->P[l], &mc_);
+        pack_device(d.R, dl->R[l], &mc_);
+        DCsr lo, up;
+        smoother_data_device(dl->A[l], lo, up, d.dinv, d.dl1inv, &mc_);
+        pack_device(d.pgs_lo, lo, &mc_);
+        pack_device(d.pgs_up, up, &mc_);
+      } else {
+        d.A.build(h.A, &mc_);
+        d.P.build(h.P, &mc_);
+        d.R.build(h.R, &mc_);
+        d.pgs_lo.build(h.pgs_lo, &mc_);
+        d.pgs_up.build(h.pgs_up, &mc_);
+        upload_vec(d.dinv, h.dinv);
+        upload_vec(d.dl1inv, h.dl1inv);
+      }
       d.has_ilu = h.has_ilu;
       if (h.has_ilu) {
         d.ilu_lo.build(h.ilu_lo, &mc_);
@@ -174,7 +189,10 @@ class Solver final : public SolverBase {
       for (int32_t j = 0; j < nc_; ++j) inv.ci[(size_t)i * nc_ + j] = j;
     inv.v = H.coarse_inv;
     coarse_inv_.build(inv, &mc_, nc_ > 1 ? 64 : 1);
-    A64_.build(H.lv[0].A, &mc_, 1);
+    if (dl)
+      pack_device(A64_, dl->A[0], &mc_, 1);
+    else
+      A64_.build(H.lv[0].A, &mc_, 1);
     anorm_inf_ = H.anorm_inf;
     const int32_t n = lv_[0].n;
     nblk_red_ = (int32_t)blocks_for(n);
@@ -959,6 +977,7 @@ int namg_setup(int32_t n, const int32_t *rowptr, const int32_t *colind, const do
       else
         h->dev = std::make_unique<namg::Solver<float>>(h->host, p->device);
     }
+    h->host.device_levels.reset();  // device-built levels, now packed into the solver's layouts
     *out = h.release();
     return NAMG_OK;
   });

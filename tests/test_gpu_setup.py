@@ -114,3 +114,36 @@ def test_device_setup_time_and_server(namg):
     for r in res:
         assert r["status"] == namg.OK and r["iters"] == st["iters"]
         assert np.array_equal(r["x"], xt.cpu().numpy())
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_device_packing_matches_host_packing(namg, precision, monkeypatch):
+    """Levels built on the device are packed into the solve-phase layouts on the device; with
+    NAMG_HOST_PACK set the same hierarchy is packed on the host. Both give the same V-cycle and the same
+    solve bit for bit (FP64 and FP32 layouts, SELL-64 and lane-group levels, 16-bit and 32-bit columns:
+    the random relabelling keeps 32-bit columns on the finest level)."""
+    for name, N, kw, ilu in (("c2", 24, dict(smoother=1, inner_terms=3), 1),
+                             ("c3", 20, dict(smoother=0, inner_terms=2), 0),
+                             ("c4r", 18, dict(smoother=0, inner_terms=2), 0)):
+        A, b, _ = config_system(name, N)
+        setup = dict(device=0, coarsen=namg.COARSEN_PMIS, seed=3, precision=precision, ilu_levels=ilu)
+        bt = torch.from_numpy(b).to("cuda:0")
+        out = []
+        for host_pack in (False, True):
+            if host_pack:
+                monkeypatch.setenv("NAMG_HOST_PACK", "1")
+            else:
+                monkeypatch.delenv("NAMG_HOST_PACK", raising=False)
+            H = namg.Hierarchy(A, **setup)
+            zt = torch.empty_like(bt)
+            H.vcycle(bt, zt, **kw)
+            xt = torch.zeros_like(bt)
+            st = H.solve(bt, xt, **kw)
+            torch.cuda.synchronize()
+            out.append((zt.cpu().numpy(), xt.cpu().numpy(), st["iters"], H.info()["device_bytes"]))
+            H.close()
+        monkeypatch.delenv("NAMG_HOST_PACK", raising=False)
+        (z0, x0, i0, b0), (z1, x1, i1, b1) = out
+        assert np.array_equal(z0, z1), name
+        assert np.array_equal(x0, x1) and i0 == i1, name
+        assert b0 == b1, name
