@@ -256,9 +256,13 @@ typedef struct {
   double submit, setup_start, setup_done, admitted, done; /* seconds on the server's clock */
 } namg_request_times;
 
+/* device_bytes_in_use and peak_device_bytes count the footprints reserved at admission;
+ * footprint_mismatches counts admitted requests whose solver allocated other than its reserved footprint
+ * (0 when the admission estimate is exact). */
 typedef struct {
   int64_t submitted, completed, failed, inflight, waiting, ticks, launches;
   int64_t device_bytes_in_use, peak_device_bytes, peak_inflight;
+  int64_t footprint_mismatches;
 } namg_server_counters;
 
 void namg_default_server_params(namg_server_params *p);

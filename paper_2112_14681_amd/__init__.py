@@ -94,7 +94,7 @@ class RequestTimes(C.Structure):
 class ServerCounters(C.Structure):
     _fields_ = [(name, C.c_int64) for name in ("submitted", "completed", "failed", "inflight", "waiting", "ticks",
                                                "launches", "device_bytes_in_use", "peak_device_bytes",
-                                               "peak_inflight")]
+                                               "peak_inflight", "footprint_mismatches")]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -28,6 +28,7 @@
 #include "../../include/namg.h"
 #include "device.hpp"
 #include "gpu_setup.hpp"
+#include "pack.hpp"
 #include "setup_host.hpp"
 
 namespace namg {
@@ -643,7 +644,8 @@ HostHierarchy build_hierarchy_pmis_device(HostCsr &&A0, const namg_setup_params 
   const auto t0 = std::chrono::steady_clock::now();
   device_levels(H, p);
   const auto t1 = std::chrono::steady_clock::now();
-  finish_hierarchy(H, p);
+  // the solver packs the polynomial-GS data from the device levels: the host copy is not built
+  finish_hierarchy(H, p, !device_packing_enabled());
   H.t_levels = std::chrono::duration<double>(t1 - t0).count();
   H.t_finish = std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
   return H;

@@ -37,6 +37,41 @@ int64_t mat_alloc_bytes(const HostCsr &A, int force_group = 0) {
   return 4 * (nslices + 1) + (ib + (int64_t)sizeof(T)) * r1(stored);
 }
 
+// Device bytes one DMat<T> of the strict lower (or upper) part of A allocates: mat_alloc_bytes of that part,
+// computed from A's row structure without building it (rows of A sorted by column, as the setup keeps them).
+template <class T>
+int64_t strict_alloc_bytes(const HostCsr &A, bool lower) {
+  auto r1 = [](int64_t n) { return n == 0 ? (int64_t)1 : n; };
+  const int64_t mul = diag_mul(A.nr, A.nc);
+  std::vector<int32_t> len(A.nr);
+  int64_t nnz = 0;
+  bool narrow = true;
+  for (int32_t r = 0; r < A.nr; ++r) {
+    const int32_t *b = A.ci.data() + A.rp[r], *e = A.ci.data() + A.rp[r + 1];
+    const int32_t *lo_end = std::lower_bound(b, e, r);
+    const int32_t *up_begin = std::upper_bound(lo_end, e, r);
+    const int32_t *p0 = lower ? b : up_begin, *p1 = lower ? lo_end : e;
+    len[r] = (int32_t)(p1 - p0);
+    nnz += len[r];
+    const int32_t base = diag_base(r, mul);
+    for (const int32_t *q = p0; q < p1 && narrow; ++q) {
+      const int64_t d = (int64_t)*q - base;
+      if (d < -32768 || d > 32767) narrow = false;
+    }
+  }
+  const int group = choose_group(A.nr, nnz);
+  const int64_t ib = narrow ? 2 : 4;
+  if (group > 1) return 4 * r1((int64_t)A.nr + 1) + (ib + (int64_t)sizeof(T)) * r1(nnz);
+  const int64_t nslices = (A.nr + SELL_C - 1) / SELL_C;
+  int64_t stored = 0;
+  for (int64_t s = 0; s < nslices; ++s) {
+    int32_t w = 0;
+    for (int64_t r = s * SELL_C; r < std::min<int64_t>(A.nr, (s + 1) * SELL_C); ++r) w = std::max(w, len[r]);
+    stored += (int64_t)w * SELL_C;
+  }
+  return 4 * (nslices + 1) + (ib + (int64_t)sizeof(T)) * r1(stored);
+}
+
 // Device bytes of Solver<T>(H) with its Krylov workspace for restart m (the direct comparators' level
 // schedules, which serving never builds, excluded).
 template <class T>
@@ -49,8 +84,9 @@ int64_t solver_footprint(const HostHierarchy &H, int m) {
     const int64_t n = h.A.nr;
     total += 2 * S * n;
     if (l == nl - 1) break;
-    total += mat_alloc_bytes<T>(h.A) + mat_alloc_bytes<T>(h.P) + mat_alloc_bytes<T>(h.R) + mat_alloc_bytes<T>(h.pgs_lo) +
-             mat_alloc_bytes<T>(h.pgs_up) + 2 * S * n + 4 * S * n;
+    total += mat_alloc_bytes<T>(h.A) + mat_alloc_bytes<T>(h.P) + mat_alloc_bytes<T>(h.R) + 2 * S * n + 4 * S * n;
+    total += h.host_smoother ? mat_alloc_bytes<T>(h.pgs_lo) + mat_alloc_bytes<T>(h.pgs_up)
+                             : strict_alloc_bytes<T>(h.A, true) + strict_alloc_bytes<T>(h.A, false);
     if (h.has_ilu) total += mat_alloc_bytes<T>(h.ilu_lo) + mat_alloc_bytes<T>(h.ilu_up) + S * n;
   }
   const int64_t nc = H.lv.back().A.nr;
@@ -626,6 +662,7 @@ class Server final : public ServerBase {
     s.device_bytes_in_use = used_;
     s.peak_device_bytes = peak_;
     s.peak_inflight = peak_inflight_;
+    s.footprint_mismatches = footprint_mismatches_;
     return s;
   }
 
@@ -703,6 +740,10 @@ class Server final : public ServerBase {
         r->sv = std::make_unique<Solver<T>>(*r->H, p_.device);
         r->H->device_levels.reset();  // packed into the solver's layouts; the blocks go back to the cache
         r->sv->reserve_workspace(p_.solve.restart);
+        if (r->sv->device_bytes() + 16 * (int64_t)n != r->footprint) {
+          std::lock_guard<std::mutex> lk(mu_);
+          footprint_mismatches_++;
+        }
         r->bd.alloc(n, nullptr);
         r->bd.upload(r->b.data(), n);
         std::vector<double> zero(n, 0.0);
@@ -884,6 +925,7 @@ class Server final : public ServerBase {
   bool stop_ = false;
   uint64_t next_ = 1;
   int64_t used_ = 0, peak_ = 0, inflight_ = 0, peak_inflight_ = 0, submitted_ = 0, completed_ = 0, failed_ = 0;
+  int64_t footprint_mismatches_ = 0;
   int64_t ticks_ = 0;
   double t_setup_ = 0.0, t_wait_admit_ = 0.0, t_upload_ = 0.0, t_levels_ = 0.0, t_finish_ = 0.0;
 };

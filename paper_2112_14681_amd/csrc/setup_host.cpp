@@ -569,47 +569,14 @@ std::vector<double> dense_inverse(const HostCsr &A) {
   return inv;
 }
 
-void smoother_data(HostLevel &L, bool with_ilu, const namg_setup_params &p) {
-  // One pass per row: 1 / a_ii, 1 / sum_j |a_ij| (l1-Jacobi), and D^{-1}L, D^{-1}U with entries a_ij / a_ii
+void smoother_data(HostLevel &L, bool with_ilu, const namg_setup_params &p, bool host_smoother) {
   const HostCsr &A = L.A;
-  const int32_t n = A.nr;
-  L.dinv.resize(n);
-  L.dl1inv.resize(n);
-  HostCsr &lo = L.pgs_lo, &up = L.pgs_up;
-  lo.nr = up.nr = n;
-  lo.nc = up.nc = A.nc;
-  lo.rp.assign(n + 1, 0);
-  up.rp.assign(n + 1, 0);
-  int64_t nlo = 0;
-  for (int32_t i = 0; i < n; ++i) {
-    const int32_t *b = A.ci.data() + A.rp[i], *e = A.ci.data() + A.rp[i + 1];
-    nlo += std::lower_bound(b, e, i) - b;
-  }
-  const int64_t nup = A.nnz() - nlo - n;
-  lo.ci.resize(nlo);
-  lo.v.resize(nlo);
-  up.ci.resize(std::max<int64_t>(nup, 0));
-  up.v.resize(std::max<int64_t>(nup, 0));
-  int64_t ql = 0, qu = 0;
-  for (int32_t i = 0; i < n; ++i) {
-    const double d = diagonal(A, i);
-    if (d == 0.0) fail(NAMG_E_ZERO_PIVOT, "zero diagonal in row " + std::to_string(i));
-    L.dinv[i] = 1.0 / d;
-    double l1 = 0.0;
-    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
-      const int32_t j = A.ci[k];
-      l1 += std::fabs(A.v[k]);
-      if (j < i) {
-        lo.ci[ql] = j;
-        lo.v[ql++] = A.v[k] / d;
-      } else if (j > i) {
-        up.ci[qu] = j;
-        up.v[qu++] = A.v[k] / d;
-      }
-    }
-    L.dl1inv[i] = 1.0 / l1;
-    lo.rp[i + 1] = (int32_t)ql;
-    up.rp[i + 1] = (int32_t)qu;
+  L.host_smoother = host_smoother;
+  if (host_smoother) {
+    pgs_data(A, L.dinv, L.dl1inv, L.pgs_lo, L.pgs_up);
+  } else {
+    for (int32_t i = 0; i < A.nr; ++i)
+      if (diagonal(A, i) == 0.0) fail(NAMG_E_ZERO_PIVOT, "zero diagonal in row " + std::to_string(i));
   }
   if (with_ilu) {
     // L \ U as one CSR: ILU(0) values in A's pattern, or the ILUT factor with its own fill
@@ -711,9 +678,52 @@ double inf_norm(const HostCsr &A) {
   return m;
 }
 
-void finish_hierarchy(HostHierarchy &H, const namg_setup_params &p) {
+void pgs_data(const HostCsr &A, std::vector<double> &dinv, std::vector<double> &dl1inv, HostCsr &lo, HostCsr &up) {
+  // One pass per row: 1 / a_ii, 1 / sum_j |a_ij| (l1-Jacobi), and D^{-1}L, D^{-1}U with entries a_ij / a_ii
+  const int32_t n = A.nr;
+  dinv.resize(n);
+  dl1inv.resize(n);
+  lo.nr = up.nr = n;
+  lo.nc = up.nc = A.nc;
+  lo.rp.assign(n + 1, 0);
+  up.rp.assign(n + 1, 0);
+  int64_t nlo = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const int32_t *b = A.ci.data() + A.rp[i], *e = A.ci.data() + A.rp[i + 1];
+    nlo += std::lower_bound(b, e, i) - b;
+  }
+  const int64_t nup = A.nnz() - nlo - n;
+  lo.ci.resize(nlo);
+  lo.v.resize(nlo);
+  up.ci.resize(std::max<int64_t>(nup, 0));
+  up.v.resize(std::max<int64_t>(nup, 0));
+  int64_t ql = 0, qu = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const double d = diagonal(A, i);
+    if (d == 0.0) fail(NAMG_E_ZERO_PIVOT, "zero diagonal in row " + std::to_string(i));
+    dinv[i] = 1.0 / d;
+    double l1 = 0.0;
+    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      const int32_t j = A.ci[k];
+      l1 += std::fabs(A.v[k]);
+      if (j < i) {
+        lo.ci[ql] = j;
+        lo.v[ql++] = A.v[k] / d;
+      } else if (j > i) {
+        up.ci[qu] = j;
+        up.v[qu++] = A.v[k] / d;
+      }
+    }
+    dl1inv[i] = 1.0 / l1;
+    lo.rp[i + 1] = (int32_t)ql;
+    up.rp[i + 1] = (int32_t)qu;
+  }
+}
+
+void finish_hierarchy(HostHierarchy &H, const namg_setup_params &p, bool host_smoother) {
   const int nl = (int)H.lv.size();
-  for (int l = 0; l < nl - 1; ++l) smoother_data(H.lv[l], p.ilu_levels < 0 || l < p.ilu_levels, p);
+  for (int l = 0; l < nl - 1; ++l)
+    smoother_data(H.lv[l], p.ilu_levels < 0 || l < p.ilu_levels, p, host_smoother);
   const HostCsr &Ac = H.lv.back().A;
   if (Ac.nr > 4096) fail(NAMG_E_INVALID, "coarsest level has more than 4096 rows; raise max_levels");
   H.coarse_inv = dense_inverse(Ac);

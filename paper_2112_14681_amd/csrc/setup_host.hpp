@@ -37,6 +37,7 @@ struct HostLevel {
   std::vector<double> dinv;    // 1 / a_ii
   std::vector<double> dl1inv;  // 1 / sum_j |a_ij| (l1-Jacobi)
   HostCsr pgs_lo, pgs_up;      // D^{-1} L and D^{-1} U: strict parts of A scaled by the row's diagonal
+  bool host_smoother = true;   // false: dinv, dl1inv, pgs_lo, pgs_up left empty (built on the device)
   bool has_ilu = false;
   HostCsr ilu_lo, ilu_up;      // L_s (strict lower of the unit-diagonal L) and U_s = D_U^{-1} U - I
   std::vector<double> ilu_dinv;  // 1 / u_ii
@@ -64,9 +65,14 @@ HostHierarchy build_hierarchy(HostCsr &&A, const namg_setup_params &p);
 
 // Parameter checks shared by both setups, ||A||_inf, and the host part that completes a hierarchy whose
 // levels (A, P, R, C/F) are built: smoother data of every level but the coarsest, the coarse inverse.
+// host_smoother = false leaves the polynomial-GS data to a device packing (the ILU factors and the zero
+// diagonal check stay on the host).
 void validate_hierarchy_params(const namg_setup_params &p);
 double inf_norm(const HostCsr &A);
-void finish_hierarchy(HostHierarchy &H, const namg_setup_params &p);
+void finish_hierarchy(HostHierarchy &H, const namg_setup_params &p, bool host_smoother = true);
+// The polynomial-GS and l1-Jacobi data of a level matrix in one pass per row: 1 / a_ii, 1 / sum_j |a_ij|,
+// D^{-1}L and D^{-1}U. Throws SetupError{NAMG_E_ZERO_PIVOT} on a zero diagonal.
+void pgs_data(const HostCsr &A, std::vector<double> &dinv, std::vector<double> &dl1inv, HostCsr &lo, HostCsr &up);
 
 // Dependency levels of a strict lower (lower = true) or upper triangle, for the direct comparators.
 LevelSchedule level_schedule(const HostCsr &T, bool lower);

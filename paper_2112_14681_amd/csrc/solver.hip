@@ -162,10 +162,20 @@ class Solver final : public SolverBase {
         d.A.build(h.A, &mc_);
         d.P.build(h.P, &mc_);
         d.R.build(h.R, &mc_);
-        d.pgs_lo.build(h.pgs_lo, &mc_);
-        d.pgs_up.build(h.pgs_up, &mc_);
-        upload_vec(d.dinv, h.dinv);
-        upload_vec(d.dl1inv, h.dl1inv);
+        if (h.host_smoother) {
+          d.pgs_lo.build(h.pgs_lo, &mc_);
+          d.pgs_up.build(h.pgs_up, &mc_);
+          upload_vec(d.dinv, h.dinv);
+          upload_vec(d.dl1inv, h.dl1inv);
+        } else {
+          std::vector<double> dinv, dl1inv;
+          HostCsr lo, up;
+          pgs_data(h.A, dinv, dl1inv, lo, up);
+          d.pgs_lo.build(lo, &mc_);
+          d.pgs_up.build(up, &mc_);
+          upload_vec(d.dinv, dinv);
+          upload_vec(d.dl1inv, dl1inv);
+        }
       }
       d.has_ilu = h.has_ilu;
       if (h.has_ilu) {
@@ -839,8 +849,16 @@ class Solver final : public SolverBase {
     for (size_t l = 0; l + 1 < lv_.size(); ++l) {
       const HostLevel &h = host_->lv[l];
       DevLevel<T> &d = lv_[l];
-      d.tri_pgs_lo.build(h.pgs_lo, level_schedule(h.pgs_lo, true), &mc_);
-      d.tri_pgs_up.build(h.pgs_up, level_schedule(h.pgs_up, false), &mc_);
+      if (h.host_smoother) {
+        d.tri_pgs_lo.build(h.pgs_lo, level_schedule(h.pgs_lo, true), &mc_);
+        d.tri_pgs_up.build(h.pgs_up, level_schedule(h.pgs_up, false), &mc_);
+      } else {
+        std::vector<double> dinv, dl1inv;
+        HostCsr lo, up;
+        pgs_data(h.A, dinv, dl1inv, lo, up);
+        d.tri_pgs_lo.build(lo, level_schedule(lo, true), &mc_);
+        d.tri_pgs_up.build(up, level_schedule(up, false), &mc_);
+      }
       if (h.has_ilu) {
         d.tri_ilu_lo.build(h.ilu_lo, level_schedule(h.ilu_lo, true), &mc_);
         d.tri_ilu_up.build(h.ilu_up, level_schedule(h.ilu_up, false), &mc_);

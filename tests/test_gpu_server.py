@@ -50,6 +50,7 @@ def test_alone_vs_mix_bitwise(namg, precision):
     c1 = s1.stats()
     s1.close()
     assert c1["peak_inflight"] == 1 and c1["completed"] == len(systems)
+    assert c1["footprint_mismatches"] == 0  # admission reserved exactly what each solver allocated
 
     s8 = namg.Server(solve=SOLVE, max_inflight=8, setup_threads=4, precision=precision)
     tickets = [s8.submit(A, b) for A, b in systems]
@@ -95,7 +96,7 @@ def test_budget_admission_and_rejection(namg):
     srv = namg.Server(solve=SOLVE, max_inflight=8, setup_threads=3, precision=1, hbm_budget=budget)
     out = [srv.wait(t) for t in [srv.submit(A, b) for A, b in systems]]
     c = srv.stats()
-    assert c["peak_device_bytes"] <= budget
+    assert c["peak_device_bytes"] <= budget and c["footprint_mismatches"] == 0
     for r, q in zip(out, ref):
         assert r["status"] == namg.OK and np.array_equal(r["x"], q["x"])
     # a request larger than the whole budget
@@ -164,6 +165,8 @@ def test_device_setup_requests_in_the_mix(namg):
               for j in range(len(systems))]
     tickets = [srv.submit(A, b, **sp) for (A, b), sp in zip(systems, setups)]
     results = [srv.wait(t) for t in tickets]
+    # the footprint of a device-built hierarchy (no host copy of the polynomial-GS data) is exact too
+    assert srv.stats()["footprint_mismatches"] == 0
     srv.close()
     for (A, b), sp, r in zip(systems, setups, results):
         H = namg.Hierarchy(A, device=0, **sp)
