@@ -69,37 +69,66 @@ class PinnedPool {
   std::vector<char *> free_;
 };
 
-// Synchronous copies through one pinned staging buffer, chunk by chunk.
-inline void copy_to_device(void *dst, const void *src, size_t bytes) {
-  if (bytes == 0) return;
-  PinnedPool &pool = PinnedPool::instance();
-  char *stage = pool.acquire();
-  struct Back {
-    PinnedPool &p;
-    char *b;
-    ~Back() { p.release(b); }
-  } back{pool, stage};
-  for (size_t off = 0; off < bytes; off += PinnedPool::CHUNK) {
-    const size_t c = std::min(PinnedPool::CHUNK, bytes - off);
-    std::memcpy(stage, static_cast<const char *>(src) + off, c);
-    hip_check(hipMemcpy(static_cast<char *>(dst) + off, stage, c, hipMemcpyHostToDevice), "hipMemcpy H2D");
+// Synchronous copies through one pinned staging buffer, split into SLOTS slices that form a pipeline: the
+// DMA of one slice overlaps the host memcpy of another, and an event per slice says when it is reusable.
+constexpr int STAGE_SLOTS = 8;
+
+struct StageEvents {
+  hipEvent_t e[STAGE_SLOTS] = {};
+  StageEvents() {
+    for (auto &x : e) hip_check(hipEventCreateWithFlags(&x, hipEventDisableTiming), "hipEventCreateWithFlags");
   }
+  ~StageEvents() {
+    for (auto &x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+};
+
+struct StageBuffer {
+  PinnedPool &pool = PinnedPool::instance();
+  char *b = pool.acquire();
+  ~StageBuffer() { pool.release(b); }
+};
+
+// Copies of pageable memory on stream s (the null stream by default); return when the copy is complete.
+inline void copy_to_device(void *dst, const void *src, size_t bytes, hipStream_t s = nullptr) {
+  if (bytes == 0) return;
+  constexpr size_t SL = PinnedPool::CHUNK / STAGE_SLOTS;
+  StageBuffer stage;
+  StageEvents ev;
+  const size_t n = (bytes + SL - 1) / SL;
+  for (size_t k = 0; k < n; ++k) {
+    const int j = (int)(k % STAGE_SLOTS);
+    const size_t off = k * SL, c = std::min(SL, bytes - off);
+    if (k >= (size_t)STAGE_SLOTS) hip_check(hipEventSynchronize(ev.e[j]), "hipEventSynchronize");
+    std::memcpy(stage.b + j * SL, static_cast<const char *>(src) + off, c);
+    hip_check(hipMemcpyAsync(static_cast<char *>(dst) + off, stage.b + j * SL, c, hipMemcpyHostToDevice, s), "H2D");
+    hip_check(hipEventRecord(ev.e[j], s), "hipEventRecord");
+  }
+  for (size_t k = (n > (size_t)STAGE_SLOTS ? n - STAGE_SLOTS : 0); k < n; ++k)
+    hip_check(hipEventSynchronize(ev.e[k % STAGE_SLOTS]), "hipEventSynchronize");
 }
 
 inline void copy_to_host(void *dst, const void *src, size_t bytes, hipStream_t s) {
   if (bytes == 0) return;
-  PinnedPool &pool = PinnedPool::instance();
-  char *stage = pool.acquire();
-  struct Back {
-    PinnedPool &p;
-    char *b;
-    ~Back() { p.release(b); }
-  } back{pool, stage};
-  for (size_t off = 0; off < bytes; off += PinnedPool::CHUNK) {
-    const size_t c = std::min(PinnedPool::CHUNK, bytes - off);
-    hip_check(hipMemcpyAsync(stage, static_cast<const char *>(src) + off, c, hipMemcpyDeviceToHost, s), "D2H");
-    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
-    std::memcpy(static_cast<char *>(dst) + off, stage, c);
+  constexpr size_t SL = PinnedPool::CHUNK / STAGE_SLOTS;
+  StageBuffer stage;
+  StageEvents ev;
+  const size_t n = (bytes + SL - 1) / SL;
+  auto issue = [&](size_t k) {
+    const int j = (int)(k % STAGE_SLOTS);
+    const size_t off = k * SL, c = std::min(SL, bytes - off);
+    hip_check(hipMemcpyAsync(stage.b + j * SL, static_cast<const char *>(src) + off, c, hipMemcpyDeviceToHost, s),
+              "D2H");
+    hip_check(hipEventRecord(ev.e[j], s), "hipEventRecord");
+  };
+  for (size_t k = 0; k < std::min(n, (size_t)STAGE_SLOTS); ++k) issue(k);
+  for (size_t k = 0; k < n; ++k) {
+    const int j = (int)(k % STAGE_SLOTS);
+    const size_t off = k * SL, c = std::min(SL, bytes - off);
+    hip_check(hipEventSynchronize(ev.e[j]), "hipEventSynchronize");
+    std::memcpy(static_cast<char *>(dst) + off, stage.b + j * SL, c);
+    if (k + STAGE_SLOTS < n) issue(k + STAGE_SLOTS);  // slice j has been copied out
   }
 }
 

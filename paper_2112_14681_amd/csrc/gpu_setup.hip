@@ -605,7 +605,9 @@ void device_levels(HostHierarchy &H, const namg_setup_params &p) {
     const auto t3 = now();
     L.cf = std::move(cf);
     B.download(L.P, P);
-    B.download(L.R, R);
+    // the solver packs R from the device level; a host copy only serves the host packing
+    L.host_restriction = !device_packing_enabled();
+    if (L.host_restriction) B.download(L.R, R);
     HostLevel next;
     B.download(next.A, Ac);
     if (trace)

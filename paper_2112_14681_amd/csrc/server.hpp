@@ -72,6 +72,35 @@ int64_t strict_alloc_bytes(const HostCsr &A, bool lower) {
   return 4 * (nslices + 1) + (ib + (int64_t)sizeof(T)) * r1(stored);
 }
 
+// Device bytes one DMat<T> of R = P^T allocates: mat_alloc_bytes of R, computed from P without building R.
+template <class T>
+int64_t restriction_alloc_bytes(const HostCsr &P) {
+  auto r1 = [](int64_t n) { return n == 0 ? (int64_t)1 : n; };
+  const int32_t nr = P.nc;  // rows of R
+  const int64_t mul = diag_mul(nr, P.nr);
+  std::vector<int32_t> len(nr, 0);
+  bool narrow = true;
+  for (int32_t i = 0; i < P.nr; ++i)
+    for (int32_t k = P.rp[i]; k < P.rp[i + 1]; ++k) {
+      const int32_t c = P.ci[k];  // entry (c, i) of R
+      len[c]++;
+      const int64_t d = (int64_t)i - diag_base(c, mul);
+      if (d < -32768 || d > 32767) narrow = false;
+    }
+  const int64_t nnz = P.nnz();
+  const int group = choose_group(nr, nnz);
+  const int64_t ib = narrow ? 2 : 4;
+  if (group > 1) return 4 * r1((int64_t)nr + 1) + (ib + (int64_t)sizeof(T)) * r1(nnz);
+  const int64_t nslices = (nr + SELL_C - 1) / SELL_C;
+  int64_t stored = 0;
+  for (int64_t s = 0; s < nslices; ++s) {
+    int32_t w = 0;
+    for (int64_t r = s * SELL_C; r < std::min<int64_t>(nr, (s + 1) * SELL_C); ++r) w = std::max(w, len[r]);
+    stored += (int64_t)w * SELL_C;
+  }
+  return 4 * (nslices + 1) + (ib + (int64_t)sizeof(T)) * r1(stored);
+}
+
 // Device bytes of Solver<T>(H) with its Krylov workspace for restart m (the direct comparators' level
 // schedules, which serving never builds, excluded).
 template <class T>
@@ -84,7 +113,8 @@ int64_t solver_footprint(const HostHierarchy &H, int m) {
     const int64_t n = h.A.nr;
     total += 2 * S * n;
     if (l == nl - 1) break;
-    total += mat_alloc_bytes<T>(h.A) + mat_alloc_bytes<T>(h.P) + mat_alloc_bytes<T>(h.R) + 2 * S * n + 4 * S * n;
+    total += mat_alloc_bytes<T>(h.A) + mat_alloc_bytes<T>(h.P) + 2 * S * n + 4 * S * n;
+    total += h.host_restriction ? mat_alloc_bytes<T>(h.R) : restriction_alloc_bytes<T>(h.P);
     total += h.host_smoother ? mat_alloc_bytes<T>(h.pgs_lo) + mat_alloc_bytes<T>(h.pgs_up)
                              : strict_alloc_bytes<T>(h.A, true) + strict_alloc_bytes<T>(h.A, false);
     if (h.has_ilu) total += mat_alloc_bytes<T>(h.ilu_lo) + mat_alloc_bytes<T>(h.ilu_up) + S * n;

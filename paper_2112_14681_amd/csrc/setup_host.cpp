@@ -678,6 +678,8 @@ double inf_norm(const HostCsr &A) {
   return m;
 }
 
+HostCsr restriction_of(const HostCsr &P) { return transpose_csr(P); }
+
 void pgs_data(const HostCsr &A, std::vector<double> &dinv, std::vector<double> &dl1inv, HostCsr &lo, HostCsr &up) {
   // One pass per row: 1 / a_ii, 1 / sum_j |a_ij| (l1-Jacobi), and D^{-1}L, D^{-1}U with entries a_ij / a_ii
   const int32_t n = A.nr;

@@ -38,6 +38,7 @@ struct HostLevel {
   std::vector<double> dl1inv;  // 1 / sum_j |a_ij| (l1-Jacobi)
   HostCsr pgs_lo, pgs_up;      // D^{-1} L and D^{-1} U: strict parts of A scaled by the row's diagonal
   bool host_smoother = true;   // false: dinv, dl1inv, pgs_lo, pgs_up left empty (built on the device)
+  bool host_restriction = true;  // false: R is not copied to the host (restriction_of(P) derives it)
   bool has_ilu = false;
   HostCsr ilu_lo, ilu_up;      // L_s (strict lower of the unit-diagonal L) and U_s = D_U^{-1} U - I
   std::vector<double> ilu_dinv;  // 1 / u_ii
@@ -70,6 +71,8 @@ HostHierarchy build_hierarchy(HostCsr &&A, const namg_setup_params &p);
 void validate_hierarchy_params(const namg_setup_params &p);
 double inf_norm(const HostCsr &A);
 void finish_hierarchy(HostHierarchy &H, const namg_setup_params &p, bool host_smoother = true);
+// R = P^T, rows sorted by fine index (the host setup's restriction, bit for bit the device setup's).
+HostCsr restriction_of(const HostCsr &P);
 // The polynomial-GS and l1-Jacobi data of a level matrix in one pass per row: 1 / a_ii, 1 / sum_j |a_ij|,
 // D^{-1}L and D^{-1}U. Throws SetupError{NAMG_E_ZERO_PIVOT} on a zero diagonal.
 void pgs_data(const HostCsr &A, std::vector<double> &dinv, std::vector<double> &dl1inv, HostCsr &lo, HostCsr &up);

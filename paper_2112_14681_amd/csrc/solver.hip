@@ -161,7 +161,10 @@ class Solver final : public SolverBase {
       } else {
         d.A.build(h.A, &mc_);
         d.P.build(h.P, &mc_);
-        d.R.build(h.R, &mc_);
+        if (h.host_restriction)
+          d.R.build(h.R, &mc_);
+        else
+          d.R.build(restriction_of(h.P), &mc_);
         if (h.host_smoother) {
           d.pgs_lo.build(h.pgs_lo, &mc_);
           d.pgs_up.build(h.pgs_up, &mc_);
