@@ -308,32 +308,70 @@ __global__ __launch_bounds__(TB) void k_spgemm_accumulate(int32_t nrows, const i
   cnt[i] = c;
 }
 
-// Row i of the product: its entries in insertion order, then sorted by column.
-__global__ __launch_bounds__(TB) void k_spgemm_emit(int32_t nrows, const int64_t *__restrict__ toff,
-                                                    const int32_t *__restrict__ tkey, const double *__restrict__ tval,
-                                                    const int32_t *__restrict__ order, const int32_t *__restrict__ crp,
-                                                    int32_t *__restrict__ cci, double *__restrict__ cv) {
-  const int32_t i = blockIdx.x * TB + threadIdx.x;
+// Row i of the product sorted by column. Rows of at most EMIT_CAP entries are sorted in LDS: each thread
+// owns one column of the block's arrays (entry q of lane l at q * EMIT_TB + l, so a wavefront's accesses
+// fall in distinct banks); it gathers its row's (column, slot) pairs, sorts them by insertion, then writes
+// the columns and reads the values in sorted order. Longer rows are copied out in insertion order and
+// sorted in place in global memory. Columns within a row are distinct, so both give the same result.
+constexpr int EMIT_TB = 64;
+constexpr int EMIT_CAP = 64;
+
+__global__ __launch_bounds__(EMIT_TB) void k_spgemm_emit(int32_t nrows, const int64_t *__restrict__ toff,
+                                                         const int32_t *__restrict__ tkey,
+                                                         const double *__restrict__ tval,
+                                                         const int32_t *__restrict__ order,
+                                                         const int32_t *__restrict__ crp, int32_t *__restrict__ cci,
+                                                         double *__restrict__ cv) {
+  __shared__ int32_t skey[EMIT_CAP * EMIT_TB];
+  __shared__ int32_t sslot[EMIT_CAP * EMIT_TB];
+  const int32_t i = blockIdx.x * EMIT_TB + threadIdx.x;
   if (i >= nrows) return;
   const int64_t base = toff[i];
   const int32_t a = crp[i], b = crp[i + 1];
+  const int32_t c = b - a;
+  if (c <= EMIT_CAP) {
+    int32_t *K = skey + threadIdx.x, *S = sslot + threadIdx.x;
+#pragma unroll 4
+    for (int32_t q = 0; q < c; ++q) {
+      const int32_t slot = order[base + q];
+      S[q * EMIT_TB] = slot;
+      K[q * EMIT_TB] = tkey[base + slot];
+    }
+    for (int32_t q = 1; q < c; ++q) {
+      const int32_t key = K[q * EMIT_TB], slot = S[q * EMIT_TB];
+      int32_t j = q;
+      while (j > 0 && K[(j - 1) * EMIT_TB] > key) {
+        K[j * EMIT_TB] = K[(j - 1) * EMIT_TB];
+        S[j * EMIT_TB] = S[(j - 1) * EMIT_TB];
+        --j;
+      }
+      K[j * EMIT_TB] = key;
+      S[j * EMIT_TB] = slot;
+    }
+#pragma unroll 4
+    for (int32_t q = 0; q < c; ++q) {
+      cci[a + q] = K[q * EMIT_TB];
+      cv[a + q] = tval[base + S[q * EMIT_TB]];
+    }
+    return;
+  }
   int32_t out = a;
-  for (int32_t q = 0; q < b - a; ++q) {
+  for (int32_t q = 0; q < c; ++q) {
     const int64_t h = base + order[base + q];
     cci[out] = tkey[h];
     cv[out] = tval[h];
     ++out;
   }
   for (int32_t k = a + 1; k < out; ++k) {
-    const int32_t c = cci[k];
+    const int32_t col = cci[k];
     const double x = cv[k];
     int32_t q = k - 1;
-    while (q >= a && cci[q] > c) {
+    while (q >= a && cci[q] > col) {
       cci[q + 1] = cci[q];
       cv[q + 1] = cv[q];
       --q;
     }
-    cci[q + 1] = c;
+    cci[q + 1] = col;
     cv[q + 1] = x;
   }
 }
@@ -441,7 +479,8 @@ class Builder {
     C.nnz = read_at(C.rp.get() + nr);
     C.ci.alloc((size_t)std::max<int64_t>(C.nnz, 1), nullptr);
     C.v.alloc((size_t)std::max<int64_t>(C.nnz, 1), nullptr);
-    hipLaunchKernelGGL(k_spgemm_emit, dim3(grid_for(nr)), dim3(TB), 0, s_, nr, toff.get(), tkey.get(), tval.get(),
+    const unsigned emit_grid = (unsigned)std::max<int64_t>(((int64_t)nr + EMIT_TB - 1) / EMIT_TB, 1);
+    hipLaunchKernelGGL(k_spgemm_emit, dim3(emit_grid), dim3(EMIT_TB), 0, s_, nr, toff.get(), tkey.get(), tval.get(),
                        order.get(), C.rp.get(), C.ci.get(), C.v.get());
     check("k_spgemm_emit");
     sync();
