@@ -645,7 +645,7 @@ void device_levels(HostHierarchy &H, const namg_setup_params &p) {
     L.cf = std::move(cf);
     B.download(L.P, P);
     // the solver packs R from the device level; a host copy only serves the host packing
-    L.host_restriction = !device_packing_enabled();
+    L.host_restriction = !H.pack_on_device;
     if (L.host_restriction) B.download(L.R, R);
     HostLevel next;
     B.download(next.A, Ac);
@@ -682,11 +682,12 @@ HostHierarchy build_hierarchy_pmis_device(HostCsr &&A0, const namg_setup_params 
   H.anorm_inf = inf_norm(A0);
   H.lv.emplace_back();
   H.lv.back().A = std::move(A0);
+  H.pack_on_device = device_packing_enabled();
   const auto t0 = std::chrono::steady_clock::now();
   device_levels(H, p);
   const auto t1 = std::chrono::steady_clock::now();
   // the solver packs the polynomial-GS data from the device levels: the host copy is not built
-  finish_hierarchy(H, p, !device_packing_enabled());
+  finish_hierarchy(H, p, !H.pack_on_device);
   H.t_levels = std::chrono::duration<double>(t1 - t0).count();
   H.t_finish = std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
   return H;

@@ -53,6 +53,9 @@ struct HostHierarchy {
   // Levels built on the device (a DeviceLevels, opaque here): the solve-phase layouts are packed from them
   // on the device; released once they are built.
   std::shared_ptr<void> device_levels;
+  // Decided once at setup: the solver packs device_levels on the device, so R and the polynomial-GS data
+  // have no host copies (false: host packing, every host copy present).
+  bool pack_on_device = false;
 };
 
 // Throws SetupError{NAMG_E_INVALID / NAMG_E_NONFINITE / NAMG_E_ZERO_PIVOT} on malformed input.

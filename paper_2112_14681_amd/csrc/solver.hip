@@ -140,7 +140,7 @@ class Solver final : public SolverBase {
     const int nl = (int)H.lv.size();
     lv_.resize(nl);
     // levels built on the device are packed there (same bytes as the host packing below)
-    const DeviceLevels *dl = (H.device_levels && device_packing_enabled())
+    const DeviceLevels *dl = (H.device_levels && H.pack_on_device)
                                  ? static_cast<const DeviceLevels *>(H.device_levels.get())
                                  : nullptr;
     for (int l = 0; l < nl; ++l) {

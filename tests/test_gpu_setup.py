@@ -147,3 +147,33 @@ def test_device_packing_matches_host_packing(namg, precision, monkeypatch):
         assert np.array_equal(z0, z1), name
         assert np.array_equal(x0, x1) and i0 == i1, name
         assert b0 == b1, name
+
+
+@pytest.mark.parametrize("smoother", [0, 1])
+def test_direct_comparator_on_device_built_hierarchy(namg, smoother, monkeypatch):
+    """A hierarchy packed on the device keeps no host copy of the scaled triangles; the direct-triangular
+    comparator derives them on its first use. Its V-cycle and solve equal those of the same hierarchy
+    packed on the host (where the setup builds the copies), bit for bit, for polynomial GS and ILU(0)."""
+    A, b, _ = config_system("c2", 16)
+    setup = dict(device=0, coarsen=namg.COARSEN_PMIS, seed=5, ilu_levels=1)
+    kw = dict(smoother=smoother, tri_mode=namg.TRI_DIRECT, inner_terms=2)
+    bt = torch.from_numpy(b).to("cuda:0")
+    out = []
+    for host_pack in (False, True):
+        if host_pack:
+            monkeypatch.setenv("NAMG_HOST_PACK", "1")
+        else:
+            monkeypatch.delenv("NAMG_HOST_PACK", raising=False)
+        H = namg.Hierarchy(A, **setup)
+        monkeypatch.delenv("NAMG_HOST_PACK", raising=False)  # the hierarchy keeps the choice made at setup
+        zt = torch.empty_like(bt)
+        H.vcycle(bt, zt, **kw)
+        xt = torch.zeros_like(bt)
+        st = H.solve(bt, xt, **kw)
+        torch.cuda.synchronize()
+        out.append((zt.cpu().numpy(), xt.cpu().numpy(), st["iters"], st["status"]))
+        H.close()
+    (z0, x0, i0, s0), (z1, x1, i1, s1) = out
+    assert s0 == namg.OK and s1 == namg.OK
+    assert np.array_equal(z0, z1)
+    assert np.array_equal(x0, x1) and i0 == i1
