@@ -1,5 +1,6 @@
 """Non-normality diagnostics of incomplete triangular factors (Section 5.3.2 to 5.3.4: Henrici's departure
-from normality, Theorems 1 to 4, Ruiz scaling, and the Jacobi triangular-solve residuals of Table 2).
+from normality, Theorems 1 to 4, Ruiz scaling, the powers of U_s that the Neumann series sums, and the
+Jacobi triangular-solve residuals of Table 2).
 
 Plain dense numpy definitions for small matrices. Test infrastructure, like the rest of the oracle: only
 the tests and the benchmark's CPU leg import it.
@@ -88,3 +89,21 @@ def jacobi_tri_residuals(F, b, iters):
         v = v + d * (y - U @ v)
     return (float(np.linalg.norm(b - L @ y) / np.linalg.norm(b)),
             float(np.linalg.norm(y - U @ v) / np.linalg.norm(y)))
+
+
+def us_power_sequence(F, pmax):
+    """The sequence that Section 5.3.4 plots for a factor (its figure of max |(U_s^p)_ij|, ||U_s^p||_2 and
+    nnz(U_s^p) against p): for p = 1..pmax, the largest magnitude, the 2-norm and the number of nonzero
+    entries of the p-th power of U_s = D_U^{-1} U - I, the strictly upper triangular part of the row-scaled
+    U. U_s is nilpotent, so the powers vanish once p exceeds the longest chain of its graph; the Neumann
+    form of the U solve sums the terms (-U_s)^j, and these numbers say how fast they decay."""
+    _, U = split_factor(F)
+    Us = np.triu(U / np.diag(U)[:, None], 1)
+    P = np.eye(F.n)
+    max_abs, norm2, nnz = [], [], []
+    for _ in range(pmax):
+        P = P @ Us
+        max_abs.append(float(np.abs(P).max()) if P.size else 0.0)
+        norm2.append(float(np.linalg.norm(P, 2)) if P.size else 0.0)
+        nnz.append(int(np.count_nonzero(P)))
+    return {"max_abs": np.array(max_abs), "norm2": np.array(norm2), "nnz": np.array(nnz, dtype=np.int64)}

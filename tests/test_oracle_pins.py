@@ -787,6 +787,56 @@ def test_jacobi_triangular_residuals(oracle_lib):
     assert rl <= 1e-14 and ru <= 1e-13
 
 
+def test_us_power_sequence_closed_form():
+    """Section 5.3.4's power sequence on U = upper bidiagonal with (U_s)_{i,i+1} = a for every i: U_s = a J
+    with J the shift, so U_s^p = a^p J^p has n - p entries, all a^p, and 2-norm |a|^p; it vanishes at p = n.
+    The diagonal varies over powers of two, so the scaled superdiagonal is exactly a = -3/4."""
+    from oracle.nonnormal import us_power_sequence
+
+    n, a = 12, -0.75
+    d = np.array([2.0 ** (i % 3) for i in range(n)])
+    U = np.diag(d) + np.diag(a * d[:-1], 1)
+    seq = us_power_sequence(CSR.from_dense(U), n + 2)
+    for p in range(1, n + 3):
+        expect = abs(a) ** p if p < n else 0.0
+        assert seq["max_abs"][p - 1] == expect
+        assert seq["norm2"][p - 1] == pytest.approx(expect, rel=1e-14, abs=0.0)
+        assert seq["nnz"][p - 1] == max(n - p, 0)
+
+
+def test_us_power_sequence_nilpotency_and_bounds(oracle_lib):
+    """On ILUT factors of a 3-D Poisson matrix (an M-matrix, so every entry of U_s is <= 0 and the entries
+    of U_s^p share the sign (-1)^p: no cancellation), nnz(U_s^p) equals the number of index pairs joined by
+    a path of exactly p edges in U_s's graph (brute force on the pattern), the powers vanish exactly one
+    step past the longest chain, and max |(U_s^p)_ij| <= ||U_s^p||_2 <= ||U_s||_2^p."""
+    from oracle.nonnormal import split_factor, us_power_sequence
+
+    O = oracle_lib
+    A = poisson3d(4)
+    for droptol, lfil in ((1e-2, 5), (1e-3, 20)):
+        F = O.ilut(A, droptol, lfil)
+        _, U = split_factor(F)
+        Us = np.triu(U / np.diag(U)[:, None], 1)
+        assert (Us <= 0).all()
+        n = A.n
+        depth = np.zeros(n, dtype=int)  # edges of the longest chain starting at i
+        for i in range(n - 1, -1, -1):
+            js = np.nonzero(Us[i])[0]
+            depth[i] = 1 + depth[js].max() if len(js) else 0
+        chain = int(depth.max())
+        seq = us_power_sequence(F, chain + 2)
+        B = (Us != 0).astype(np.int64)
+        R = np.eye(n, dtype=np.int64)
+        for p in range(1, chain + 3):
+            R = np.minimum(R @ B, 1)  # pairs joined by a path of exactly p edges
+            assert seq["nnz"][p - 1] == int(R.sum()), (droptol, p)
+        assert (seq["nnz"][:chain] > 0).all() and seq["nnz"][chain] == 0 and seq["nnz"][chain + 1] == 0
+        s1 = seq["norm2"][0]
+        for p in range(1, chain + 1):
+            assert seq["max_abs"][p - 1] <= seq["norm2"][p - 1] * (1 + 1e-12)
+            assert seq["norm2"][p - 1] <= s1 ** p * (1 + 1e-12)
+
+
 # ------------------------------------------------------------- aggressive (A-1) coarsening, Section 5.1
 def _dist2_cc_graph(srp, sci, cf):
     """Brute force: for each first-pass C point, the C points reachable by one or two strong connections."""
