@@ -206,7 +206,9 @@ def nonnormality_study(namg, torch, N, fill_N):
     and the hybrid GMRES(30) solve (ILU(0) Neumann t = 3) when a GPU is present. (2) Fill sweep (Tables
     3 to 5): ILUT(1e-3, lfil) on the finest level of C4 natural at fill_N^3 for lfil = 5, 10, 20, 50:
     ||U_s||_2, ||U_s||_F and Theorem 1's bound, dep(U) before and after Ruiz scaling with Theorem 3's
-    bound, and GMRES iterations."""
+    bound, and GMRES iterations. (3) Powers of U_s (the figure of Section 5.3.4, a 331-row system there):
+    max |(U_s^p)_ij|, ||U_s^p||_2 and nnz(U_s^p) on C4 natural at 7^3 = 343 rows, ILU(0) and ILUT(1e-3, 20),
+    for every p up to the power at which U_s^p vanishes."""
     from workloads import config_system
 
     gpu = torch is not None and torch.cuda.is_available()
@@ -250,9 +252,23 @@ def nonnormality_study(namg, torch, N, fill_N):
         H.close()
         fill[str(lfil)] = row
         print(f"[nonnormality] lfil {lfil} done", file=sys.stderr, flush=True)
+    powers = {}
+    A, b, _ = config_system("c4n", 7)
+    for label, kw in (("ilu0", {}), ("ilut_1e-3_20", dict(ilu_kind=namg.ILUT, ilut_droptol=1e-3, ilut_lfil=20))):
+        H = namg.Hierarchy(A, device=-1, ilu_levels=1, **kw)
+        # U_s^p = 0 by p = n at the latest; powers after the first zero one cost nothing
+        seq = H.us_powers(0, A.n, power_iters=300)
+        H.close()
+        last = int(np.nonzero(seq["nnz"])[0].max()) + 1 if seq["nnz"].any() else 0
+        powers[label] = {"vanishes_at_p": last + 1,
+                         "max_abs": [float(f"{v:.4g}") for v in seq["max_abs"][:last]],
+                         "norm2": [float(f"{v:.4g}") for v in seq["norm2"][:last]],
+                         "nnz": [int(v) for v in seq["nnz"][:last]]}
+    print("[nonnormality] powers of U_s done", file=sys.stderr, flush=True)
     return {"metric": "non-normality of the ILU factors (Section 5.3.4)", "gpu": gpu,
             "orderings": {"workload": f"c4 convection-diffusion {N}^3, ILU(0) finest level", **orderings},
-            "fill_sweep": {"workload": f"c4n {fill_N}^3, ILUT(droptol 1e-3, lfil)", **fill}}
+            "fill_sweep": {"workload": f"c4n {fill_N}^3, ILUT(droptol 1e-3, lfil)", **fill},
+            "us_powers": {"workload": f"c4n 7^3 = {A.n} rows, finest-level factors", **powers}}
 
 
 def main():

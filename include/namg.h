@@ -239,6 +239,17 @@ int namg_ilu_diagnostics(const namg_hier *h, int level, int power_iters, int rui
 int namg_tri_jacobi_residuals(const namg_hier *h, int level, const double *b, int iters, double *res_L,
                               double *res_U);
 
+/* The powers of U_s that the Neumann form of the U solve sums (Section 5.3.4, the figure of max |(U_s^p)_ij|,
+ * ||U_s^p||_2 and nnz(U_s^p) against p): for p = 1..pmax, max_abs[p-1] = the largest magnitude,
+ * norm2[p-1] = sigma_1(U_s^p) by power_iters power iterations on (U_s^p)^T U_s^p from a fixed start (a lower
+ * estimate), nnz[p-1] = the entries of U_s^p that are not exactly zero. U_s = D_U^{-1} U - I of level l's
+ * ILU factors; U_s^p is formed by sparse products (row i sums over the entries of row i of U_s^{p-1} in
+ * order), so the cost grows with the fill of the powers; once a power is zero the later ones are reported
+ * as zero without work. Output arrays: host, pmax entries each, caller-owned. NAMG_E_INVALID if the level
+ * has no ILU factors, pmax < 1, power_iters < 1, an output is NULL or a power exceeds 2^31 entries. */
+int namg_us_powers(const namg_hier *h, int level, int pmax, int power_iters, double *max_abs, double *norm2,
+                   int64_t *nnz);
+
 /* ---- Serving (continuous batching of many solves on one GPU) ------------------------------------- */
 
 typedef struct namg_server namg_server; /* opaque; owns its threads, stream and in-flight solves */

@@ -32,8 +32,9 @@ KF_NONE, KF_NEUMANN, KF_RESIDUAL, KF_SPMV, KF_PROLONG, KF_GMRES_SPMV, KF_MULTIDO
 EXPORTED = (
     "namg_default_setup_params", "namg_default_solve_params", "namg_setup", "namg_solve", "namg_vcycle",
     "namg_apply", "namg_profile_kernel", "namg_profile_read", "namg_hier_info", "namg_level_sizes",
-    "namg_export_level", "namg_export_ilu", "namg_ilu_diagnostics", "namg_tri_jacobi_residuals", "namg_destroy",
-    "namg_last_error", "namg_default_server_params", "namg_server_create", "namg_server_submit", "namg_server_poll", "namg_server_wait", "namg_server_stats", "namg_server_clock",
+    "namg_export_level", "namg_export_ilu", "namg_ilu_diagnostics", "namg_tri_jacobi_residuals",
+    "namg_us_powers", "namg_destroy", "namg_last_error", "namg_default_server_params", "namg_server_create",
+    "namg_server_submit", "namg_server_poll", "namg_server_wait", "namg_server_stats", "namg_server_clock",
     "namg_server_destroy",
 )
 
@@ -288,6 +289,14 @@ class Hierarchy:
         rl, ru = C.c_double(), C.c_double()
         _check(_lib.namg_tri_jacobi_residuals(self.h, level, _ptr(bb, C.c_double), iters, C.byref(rl), C.byref(ru)))
         return rl.value, ru.value
+
+    def us_powers(self, level, pmax, power_iters=200) -> dict:
+        """max |(U_s^p)_ij|, ||U_s^p||_2 (power-iteration estimate) and nnz(U_s^p) for p = 1..pmax."""
+        ma, n2 = np.zeros(pmax), np.zeros(pmax)
+        nz = np.zeros(pmax, dtype=np.int64)
+        _check(_lib.namg_us_powers(self.h, level, pmax, power_iters, _ptr(ma, C.c_double), _ptr(n2, C.c_double),
+                                   _ptr(nz, C.c_int64)))
+        return {"max_abs": ma, "norm2": n2, "nnz": nz}
 
     def solve(self, b, x, stream=None, **params) -> dict:
         """namg_solve on device tensors b (read) and x (initial guess in, solution out)."""

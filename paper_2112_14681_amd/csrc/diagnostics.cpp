@@ -1,6 +1,6 @@
 // Non-normality diagnostics of the ILU smoother factors (Section 5.3.4 of arXiv 2112.14681: Henrici's
-// departure from normality, Theorems 1 to 4, Ruiz scaling) and the Jacobi triangular-solve residuals of
-// Table 2. Host code on the factors a level stores for its smoother: L_s, U_s = D_U^{-1} strict(U) and
+// departure from normality, Theorems 1 to 4, Ruiz scaling, the powers of U_s) and the Jacobi
+// triangular-solve residuals of Table 2. Host code on the factors a level stores for its smoother: L_s, U_s = D_U^{-1} strict(U) and
 // D_U = diag(U). For triangular T the eigenvalues are the diagonal, so dep(T) = ||strict(T)||_F.
 #include <algorithm>
 #include <cmath>
@@ -42,7 +42,112 @@ double norm2(const std::vector<double> &v) {
   return std::sqrt(s);
 }
 
+// sigma_1(T) by power iteration on T^T T from a fixed start; ||T x|| / ||x|| at the last iterate never
+// exceeds sigma_1. The iteration runs on T scaled by a power of two that brings its largest magnitude into
+// [0.5, 1), so that T^T T x neither underflows nor overflows (the scaling is exact).
+double sigma1_scaled(const HostCsr &T, int iters);
+
+double sigma1(const HostCsr &T, int iters) {
+  double m = 0.0;
+  for (double v : T.v) m = std::max(m, std::fabs(v));
+  if (m == 0.0) return 0.0;
+  int e = 0;
+  (void)std::frexp(m, &e);
+  HostCsr S = T;
+  for (double &v : S.v) v = std::ldexp(v, -e);
+  return std::ldexp(sigma1_scaled(S, iters), e);
+}
+
+double sigma1_scaled(const HostCsr &T, int iters) {
+  std::vector<double> x(T.nc), y, z;
+  for (int32_t i = 0; i < T.nc; ++i) x[i] = 1.0 + 0.5 * std::sin((double)i);
+  double est = 0.0;
+  for (int it = 0; it < iters; ++it) {
+    const double xn = norm2(x);
+    for (double &a : x) a /= xn;
+    csr_mv(T, x, y);
+    est = norm2(y);
+    csr_mtv(T, y, z);
+    if (norm2(z) == 0.0) break;  // T x = 0 (e.g. T = 0)
+    x.swap(z);
+  }
+  return est;
+}
+
+// C = X Y by rows with a dense accumulator (row i of C: the sum over the entries x_ik of x_ik times row k
+// of Y, in entry order); exact zeros are not stored.
+HostCsr csr_product(const HostCsr &X, const HostCsr &Y, int64_t max_nnz) {
+  HostCsr C;
+  C.nr = X.nr;
+  C.nc = Y.nc;
+  C.rp.assign(X.nr + 1, 0);
+  std::vector<double> acc(Y.nc, 0.0);
+  std::vector<int32_t> mark(Y.nc, -1), cols;
+  for (int32_t i = 0; i < X.nr; ++i) {
+    cols.clear();
+    for (int32_t k = X.rp[i]; k < X.rp[i + 1]; ++k) {
+      const int32_t r = X.ci[k];
+      for (int32_t q = Y.rp[r]; q < Y.rp[r + 1]; ++q) {
+        const int32_t j = Y.ci[q];
+        if (mark[j] != i) {
+          mark[j] = i;
+          acc[j] = 0.0;
+          cols.push_back(j);
+        }
+        acc[j] += X.v[k] * Y.v[q];
+      }
+    }
+    std::sort(cols.begin(), cols.end());
+    for (int32_t j : cols)
+      if (acc[j] != 0.0) {
+        C.ci.push_back(j);
+        C.v.push_back(acc[j]);
+      }
+    if ((int64_t)C.ci.size() > max_nnz) bad("a power of U_s exceeds 2^31 stored entries");
+    C.rp[i + 1] = (int32_t)C.ci.size();
+  }
+  return C;
+}
+
 }  // namespace
+
+void us_powers(const HostLevel &L, int pmax, int power_iters, double *max_abs, double *norm2_out, int64_t *nnz) {
+  if (!L.has_ilu) bad("level carries no ILU factors");
+  if (pmax < 1 || power_iters < 1) bad("diagnostic parameter out of range");
+  if (!max_abs || !norm2_out || !nnz) bad("null output array");
+  const HostCsr &Us = L.ilu_up;
+  HostCsr P = Us;
+  // exact zeros of U_s are not entries of its powers
+  {
+    HostCsr Q;
+    Q.nr = P.nr;
+    Q.nc = P.nc;
+    Q.rp.assign(P.nr + 1, 0);
+    for (int32_t i = 0; i < P.nr; ++i) {
+      for (int32_t k = P.rp[i]; k < P.rp[i + 1]; ++k)
+        if (P.v[k] != 0.0) {
+          Q.ci.push_back(P.ci[k]);
+          Q.v.push_back(P.v[k]);
+        }
+      Q.rp[i + 1] = (int32_t)Q.ci.size();
+    }
+    P = std::move(Q);
+  }
+  for (int p = 1; p <= pmax; ++p) {
+    if (P.nnz() == 0) {
+      max_abs[p - 1] = 0.0;
+      norm2_out[p - 1] = 0.0;
+      nnz[p - 1] = 0;
+      continue;
+    }
+    double m = 0.0;
+    for (double v : P.v) m = std::max(m, std::fabs(v));
+    max_abs[p - 1] = m;
+    norm2_out[p - 1] = sigma1(P, power_iters);
+    nnz[p - 1] = P.nnz();
+    if (p < pmax) P = csr_product(P, Us, (int64_t)INT32_MAX);
+  }
+}
 
 void ilu_diagnostics(const HostLevel &L, int power_iters, int ruiz_max_iters, double ruiz_tol, namg_ilu_diag *out) {
   if (!L.has_ilu) bad("level carries no ILU factors");
@@ -77,21 +182,7 @@ void ilu_diagnostics(const HostLevel &L, int power_iters, int ruiz_max_iters, do
   d.delta = delta;
   d.th4_bound = std::sqrt((double)n) * (1.0 + delta);
 
-  // sigma_1(U_s): power iteration on U_s^T U_s from a fixed start; the estimate ||U_s x|| / ||x|| at the
-  // last iterate never exceeds sigma_1
-  std::vector<double> x(n), y, z;
-  for (int32_t i = 0; i < n; ++i) x[i] = 1.0 + 0.5 * std::sin((double)i);
-  double est = 0.0;
-  for (int it = 0; it < power_iters; ++it) {
-    const double xn = norm2(x);
-    for (double &a : x) a /= xn;
-    csr_mv(Us, x, y);
-    est = norm2(y);
-    csr_mtv(Us, y, z);
-    if (norm2(z) == 0.0) break;  // U_s x = 0 (e.g. U_s = 0)
-    x.swap(z);
-  }
-  d.norm2_Us = est;
+  d.norm2_Us = sigma1(Us, power_iters);
 
   // Ruiz scaling of U (diagonal u_ii, strict part u_ii (U_s)_ij): r_i and c_j are the largest magnitudes in
   // row i and column j of diag(dr) U diag(dc); both scalings update together until all are within tol of 1

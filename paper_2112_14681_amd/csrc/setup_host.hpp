@@ -87,5 +87,6 @@ LevelSchedule level_schedule(const HostCsr &T, bool lower);
 // (diagnostics.cpp). Throw SetupError on invalid arguments.
 void ilu_diagnostics(const HostLevel &L, int power_iters, int ruiz_max_iters, double ruiz_tol, namg_ilu_diag *out);
 void tri_jacobi_residuals(const HostLevel &L, const double *b, int iters, double *res_L, double *res_U);
+void us_powers(const HostLevel &L, int pmax, int power_iters, double *max_abs, double *norm2, int64_t *nnz);
 
 }  // namespace namg

@@ -1142,6 +1142,16 @@ int namg_tri_jacobi_residuals(const namg_hier *h, int level, const double *b, in
   });
 }
 
+int namg_us_powers(const namg_hier *h, int level, int pmax, int power_iters, double *max_abs, double *norm2,
+                   int64_t *nnz) {
+  return guarded([&]() -> int {
+    if (!h) throw namg::SetupError{NAMG_E_INVALID, "null argument"};
+    if (level < 0 || level >= (int)h->host.lv.size()) throw namg::SetupError{NAMG_E_INVALID, "level out of range"};
+    namg::us_powers(h->host.lv[level], pmax, power_iters, max_abs, norm2, nnz);
+    return NAMG_OK;
+  });
+}
+
 void namg_destroy(namg_hier *h) {
   if (!h) return;
   try {

@@ -264,6 +264,49 @@ def test_ilu_diagnostics_match_oracle_definitions(namg, oracle_lib, name, N, ilu
         assert rl == pytest.approx(erl, rel=1e-10) and ru == pytest.approx(eru, rel=1e-10)
 
 
+@pytest.mark.parametrize("name,N,ilu", [("c1", 20, dict()), ("c4n", 7, dict(ilu_kind=1, ilut_droptol=1e-2, ilut_lfil=5)),
+                                        ("c3", 7, dict(ilu_kind=1, ilut_droptol=1e-3, ilut_lfil=8))])
+def test_us_powers_match_oracle(namg, oracle_lib, name, N, ilu):
+    """namg_us_powers against the dense powers of the same U_s (M-matrix factors, so no entry cancels and
+    the nonzero counts must agree exactly): nnz exactly, max |(U_s^p)_ij| to 1e-12, the power-iteration
+    ||U_s^p||_2 from below to 1e-3, through the power at which U_s^p vanishes and two beyond it."""
+    from oracle.nonnormal import split_factor, us_power_sequence
+
+    O = oracle_lib
+    A, _, _ = config_system(name, N)
+    H = namg.Hierarchy(A, device=-1, **ilu)
+    F = O.ilut(A, ilu["ilut_droptol"], ilu["ilut_lfil"]) if ilu else CSR(A.n, A.rowptr, A.colind, O.ilu0(A))
+    _, U = split_factor(F)
+    depth = np.zeros(A.n, dtype=int)  # edges of the longest chain of U_s's graph from each row
+    for i in range(A.n - 1, -1, -1):
+        js = i + 1 + np.nonzero(U[i, i + 1:])[0]
+        depth[i] = 1 + depth[js].max() if len(js) else 0
+    pmax = int(depth.max()) + 2
+    ref = us_power_sequence(F, pmax)
+    assert ref["nnz"][pmax - 3] > 0 and ref["nnz"][pmax - 2] == 0
+    got = H.us_powers(0, pmax, power_iters=2000)
+    assert np.array_equal(got["nnz"], ref["nnz"])
+    np.testing.assert_allclose(got["max_abs"], ref["max_abs"], rtol=1e-12, atol=0.0)
+    r2 = ref["norm2"]
+    assert (got["norm2"] <= r2 * (1 + 1e-12)).all() and (got["norm2"] >= r2 * (1 - 1e-3)).all()
+
+
+def test_us_powers_far_powers(namg):
+    """Powers far down the sequence (entries near 1e-139 on ILUT(1e-3, 20) factors of C4 at 7^3): the
+    2-norm estimate never falls below the largest entry (max |t_ij| <= ||T||_2), the last nonzero power
+    (a single entry here) has 2-norm equal to that entry, and every later power is reported as zero."""
+    A, _, _ = config_system("c4n", 7)
+    H = namg.Hierarchy(A, device=-1, ilu_levels=1, ilu_kind=namg.ILUT, ilut_droptol=1e-3, ilut_lfil=20)
+    seq = H.us_powers(0, A.n, power_iters=300)
+    live = seq["nnz"] > 0
+    last = int(np.nonzero(live)[0].max())
+    assert live[:last + 1].all() and not live[last + 1:].any()
+    assert seq["max_abs"][last] < 1e-100
+    assert (seq["norm2"][live] >= seq["max_abs"][live] * (1 - 1e-12)).all()
+    assert seq["nnz"][last] == 1 and seq["norm2"][last] == seq["max_abs"][last]
+    assert not seq["max_abs"][last + 1:].any() and not seq["norm2"][last + 1:].any()
+
+
 def test_ilu_diagnostics_validation(namg):
     A = poisson2d(12)
     H = namg.Hierarchy(A, device=-1, max_coarse=200)
@@ -273,6 +316,9 @@ def test_ilu_diagnostics_validation(namg):
     H0 = namg.Hierarchy(A, device=-1, ilu_levels=0)
     assert _err(namg, lambda: H0.ilu_diagnostics(0)) == namg.E_INVALID
     assert _err(namg, lambda: H.tri_jacobi_residuals(0, np.ones(A.n), -1)) == namg.E_INVALID
+    assert _err(namg, lambda: H.us_powers(0, 0)) == namg.E_INVALID
+    assert _err(namg, lambda: H.us_powers(0, 3, power_iters=0)) == namg.E_INVALID
+    assert _err(namg, lambda: H0.us_powers(0, 3)) == namg.E_INVALID
     with pytest.raises(ValueError):
         H.tri_jacobi_residuals(0, np.ones(A.n + 1), 3)
 
