@@ -19,29 +19,35 @@
 
 namespace namg {
 
-// Device bytes one DMat<T>::build of A allocates (mirrors its layout choices and DevBuf rounding).
-template <class T>
-int64_t mat_alloc_bytes(const HostCsr &A, int force_group = 0) {
+// Device bytes of a DMat<T> with nr rows whose row r holds len(r) entries, nnz in all, with 16-bit column
+// offsets when narrow (mirrors DMat::build's layout choice and DevBuf's rounding of empty buffers).
+template <class T, class Len>
+int64_t layout_bytes(int32_t nr, int64_t nnz, bool narrow, int force_group, Len len) {
   auto r1 = [](int64_t n) { return n == 0 ? (int64_t)1 : n; };
-  const int group = force_group > 0 ? force_group : choose_group(A.nr, A.nnz());
-  const int64_t ib = fits_col16(A) ? 2 : 4;
-  if (group > 1) return 4 * r1((int64_t)A.rp.size()) + (ib + (int64_t)sizeof(T)) * r1(A.nnz());
-  const int64_t nslices = (A.nr + SELL_C - 1) / SELL_C;
+  const int group = force_group > 0 ? force_group : choose_group(nr, nnz);
+  const int64_t ib = narrow ? 2 : 4;
+  if (group > 1) return 4 * r1((int64_t)nr + 1) + (ib + (int64_t)sizeof(T)) * r1(nnz);
+  const int64_t nslices = ((int64_t)nr + SELL_C - 1) / SELL_C;
   int64_t stored = 0;
   for (int64_t s = 0; s < nslices; ++s) {
     int32_t w = 0;
-    for (int64_t r = s * SELL_C; r < std::min<int64_t>(A.nr, (s + 1) * SELL_C); ++r)
-      w = std::max(w, A.rp[r + 1] - A.rp[r]);
+    for (int64_t r = s * SELL_C; r < std::min<int64_t>(nr, (s + 1) * SELL_C); ++r) w = std::max(w, len((int32_t)r));
     stored += (int64_t)w * SELL_C;
   }
   return 4 * (nslices + 1) + (ib + (int64_t)sizeof(T)) * r1(stored);
 }
 
-// Device bytes one DMat<T> of the strict lower (or upper) part of A allocates: mat_alloc_bytes of that part,
-// computed from A's row structure without building it (rows of A sorted by column, as the setup keeps them).
+// Device bytes one DMat<T>::build of A allocates.
+template <class T>
+int64_t mat_alloc_bytes(const HostCsr &A, int force_group = 0) {
+  return layout_bytes<T>(A.nr, A.nnz(), fits_col16(A), force_group,
+                         [&](int32_t r) { return A.rp[r + 1] - A.rp[r]; });
+}
+
+// Device bytes one DMat<T> of the strict lower (or upper) part of A allocates, computed from A's row
+// structure without building the part (rows of A sorted by column, as the setup keeps them).
 template <class T>
 int64_t strict_alloc_bytes(const HostCsr &A, bool lower) {
-  auto r1 = [](int64_t n) { return n == 0 ? (int64_t)1 : n; };
   const int64_t mul = diag_mul(A.nr, A.nc);
   std::vector<int32_t> len(A.nr);
   int64_t nnz = 0;
@@ -59,23 +65,12 @@ int64_t strict_alloc_bytes(const HostCsr &A, bool lower) {
       if (d < -32768 || d > 32767) narrow = false;
     }
   }
-  const int group = choose_group(A.nr, nnz);
-  const int64_t ib = narrow ? 2 : 4;
-  if (group > 1) return 4 * r1((int64_t)A.nr + 1) + (ib + (int64_t)sizeof(T)) * r1(nnz);
-  const int64_t nslices = (A.nr + SELL_C - 1) / SELL_C;
-  int64_t stored = 0;
-  for (int64_t s = 0; s < nslices; ++s) {
-    int32_t w = 0;
-    for (int64_t r = s * SELL_C; r < std::min<int64_t>(A.nr, (s + 1) * SELL_C); ++r) w = std::max(w, len[r]);
-    stored += (int64_t)w * SELL_C;
-  }
-  return 4 * (nslices + 1) + (ib + (int64_t)sizeof(T)) * r1(stored);
+  return layout_bytes<T>(A.nr, nnz, narrow, 0, [&](int32_t r) { return len[r]; });
 }
 
-// Device bytes one DMat<T> of R = P^T allocates: mat_alloc_bytes of R, computed from P without building R.
+// Device bytes one DMat<T> of R = P^T allocates, computed from P without building R.
 template <class T>
 int64_t restriction_alloc_bytes(const HostCsr &P) {
-  auto r1 = [](int64_t n) { return n == 0 ? (int64_t)1 : n; };
   const int32_t nr = P.nc;  // rows of R
   const int64_t mul = diag_mul(nr, P.nr);
   std::vector<int32_t> len(nr, 0);
@@ -87,18 +82,7 @@ int64_t restriction_alloc_bytes(const HostCsr &P) {
       const int64_t d = (int64_t)i - diag_base(c, mul);
       if (d < -32768 || d > 32767) narrow = false;
     }
-  const int64_t nnz = P.nnz();
-  const int group = choose_group(nr, nnz);
-  const int64_t ib = narrow ? 2 : 4;
-  if (group > 1) return 4 * r1((int64_t)nr + 1) + (ib + (int64_t)sizeof(T)) * r1(nnz);
-  const int64_t nslices = (nr + SELL_C - 1) / SELL_C;
-  int64_t stored = 0;
-  for (int64_t s = 0; s < nslices; ++s) {
-    int32_t w = 0;
-    for (int64_t r = s * SELL_C; r < std::min<int64_t>(nr, (s + 1) * SELL_C); ++r) w = std::max(w, len[r]);
-    stored += (int64_t)w * SELL_C;
-  }
-  return 4 * (nslices + 1) + (ib + (int64_t)sizeof(T)) * r1(stored);
+  return layout_bytes<T>(nr, P.nnz(), narrow, 0, [&](int32_t r) { return len[r]; });
 }
 
 // Device bytes of Solver<T>(H) with its Krylov workspace for restart m (the direct comparators' level
