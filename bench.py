@@ -49,7 +49,7 @@ def _args():
     ap.add_argument("--serve-coarsen", default="pmis", choices=["rs", "pmis"],
                     help="setup of the served requests: the device PMIS setup (default) or host RS")
     ap.add_argument("--nonnormality", action="store_true",
-                    help="the factor study of Section 5.3.4 instead of the benchmark: orderings of C4 (Table 2) "
+                    help="the factor study of Sections 5.3.2 to 5.3.4 instead of the benchmark: orderings of C4 (Table 2) "
                          "and an ILUT fill sweep (Tables 3-5), with GMRES iterations when a GPU is present")
     ap.add_argument("--nn-N", type=int, default=128, help="grid size of the ordering study")
     ap.add_argument("--nn-fill-N", type=int, default=64, help="grid size of the fill sweep")
@@ -200,13 +200,13 @@ def cpu_baseline(A, b, kw, gpu_iters, max_coarse):
 
 
 def nonnormality_study(namg, torch, N, fill_N):
-    """Section 5.3.4 on our workloads, one JSON object. (1) Orderings (Table 2 and its dep table): C4,
+    """Sections 5.3.2 to 5.3.4 on our workloads, one JSON object. (1) Orderings (Table 2 and its dep table): C4,
     upwind convection-diffusion, in natural, random and RCM-of-random order, ILU(0) on the finest level:
     dep(L), dep(U), ||U_s||_F, ||U_s||_2, the residuals of 5 Jacobi iterations for L y = b and U v = y,
     and the hybrid GMRES(30) solve (ILU(0) Neumann t = 3) when a GPU is present. (2) Fill sweep (Tables
     3 to 5): ILUT(1e-3, lfil) on the finest level of C4 natural at fill_N^3 for lfil = 5, 10, 20, 50:
     ||U_s||_2, ||U_s||_F and Theorem 1's bound, dep(U) before and after Ruiz scaling with Theorem 3's
-    bound, and GMRES iterations. (3) Powers of U_s (the figure of Section 5.3.4, a 331-row system there):
+    bound, and GMRES iterations. (3) Powers of U_s (the figure of Section 5.3.2, a 331-row system there):
     max |(U_s^p)_ij|, ||U_s^p||_2 and nnz(U_s^p) on C4 natural at 7^3 = 343 rows, ILU(0) and ILUT(1e-3, 20),
     for every p up to the power at which U_s^p vanishes."""
     from workloads import config_system
@@ -265,7 +265,7 @@ def nonnormality_study(namg, torch, N, fill_N):
                          "norm2": [float(f"{v:.4g}") for v in seq["norm2"][:last]],
                          "nnz": [int(v) for v in seq["nnz"][:last]]}
     print("[nonnormality] powers of U_s done", file=sys.stderr, flush=True)
-    return {"metric": "non-normality of the ILU factors (Section 5.3.4)", "gpu": gpu,
+    return {"metric": "non-normality of the ILU factors (Sections 5.3.2 to 5.3.4)", "gpu": gpu,
             "orderings": {"workload": f"c4 convection-diffusion {N}^3, ILU(0) finest level", **orderings},
             "fill_sweep": {"workload": f"c4n {fill_N}^3, ILUT(droptol 1e-3, lfil)", **fill},
             "us_powers": {"workload": f"c4n 7^3 = {A.n} rows, finest-level factors", **powers}}

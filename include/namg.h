@@ -239,7 +239,7 @@ int namg_ilu_diagnostics(const namg_hier *h, int level, int power_iters, int rui
 int namg_tri_jacobi_residuals(const namg_hier *h, int level, const double *b, int iters, double *res_L,
                               double *res_U);
 
-/* The powers of U_s that the Neumann form of the U solve sums (Section 5.3.4, the figure of max |(U_s^p)_ij|,
+/* The powers of U_s that the Neumann form of the U solve sums (Section 5.3.2, the figure of max |(U_s^p)_ij|,
  * ||U_s^p||_2 and nnz(U_s^p) against p): for p = 1..pmax, max_abs[p-1] = the largest magnitude,
  * norm2[p-1] = sigma_1(U_s^p) by power_iters power iterations on (U_s^p)^T U_s^p from a fixed start (a lower
  * estimate), nnz[p-1] = the entries of U_s^p that are not exactly zero. U_s = D_U^{-1} U - I of level l's

@@ -1,6 +1,6 @@
-"""Non-normality diagnostics of incomplete triangular factors (Section 5.3.2 to 5.3.4: Henrici's departure
-from normality, Theorems 1 to 4, Ruiz scaling, the powers of U_s that the Neumann series sums, and the
-Jacobi triangular-solve residuals of Table 2).
+"""Non-normality diagnostics of incomplete triangular factors (Sections 5.3.1 to 5.3.4: Henrici's departure
+from normality, 5.3.1; the powers of U_s that the Neumann series sums, 5.3.2; the Jacobi triangular-solve
+residuals of Table 2, 5.3.3; Theorems 1 to 4 and Ruiz scaling, 5.3.4).
 
 Plain dense numpy definitions for small matrices. Test infrastructure, like the rest of the oracle: only
 the tests and the benchmark's CPU leg import it.
@@ -92,7 +92,7 @@ def jacobi_tri_residuals(F, b, iters):
 
 
 def us_power_sequence(F, pmax):
-    """The sequence that Section 5.3.4 plots for a factor (its figure of max |(U_s^p)_ij|, ||U_s^p||_2 and
+    """The sequence that Section 5.3.2 plots for a factor (its figure of max |(U_s^p)_ij|, ||U_s^p||_2 and
     nnz(U_s^p) against p): for p = 1..pmax, the largest magnitude, the 2-norm and the number of nonzero
     entries of the p-th power of U_s = D_U^{-1} U - I, the strictly upper triangular part of the row-scaled
     U. U_s is nilpotent, so the powers vanish once p exceeds the longest chain of its graph; the Neumann

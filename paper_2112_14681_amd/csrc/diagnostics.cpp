@@ -1,6 +1,6 @@
-// Non-normality diagnostics of the ILU smoother factors (Section 5.3.4 of arXiv 2112.14681: Henrici's
-// departure from normality, Theorems 1 to 4, Ruiz scaling, the powers of U_s) and the Jacobi
-// triangular-solve residuals of Table 2. Host code on the factors a level stores for its smoother: L_s, U_s = D_U^{-1} strict(U) and
+// Non-normality diagnostics of the ILU smoother factors (Sections 5.3.1 to 5.3.4 of arXiv 2112.14681:
+// Henrici's departure from normality, 5.3.1; the powers of U_s, 5.3.2; Theorems 1 to 4 and Ruiz scaling,
+// 5.3.4) and the Jacobi triangular-solve residuals of Table 2 (5.3.3). Host code on the factors a level stores for its smoother: L_s, U_s = D_U^{-1} strict(U) and
 // D_U = diag(U). For triangular T the eigenvalues are the diagonal, so dep(T) = ||strict(T)||_F.
 #include <algorithm>
 #include <cmath>

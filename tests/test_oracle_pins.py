@@ -673,7 +673,7 @@ def test_not_converged_status_and_error_paths(oracle_lib):
     assert e.value.code == O.E_INVALID
 
 
-# ------------------------------------------------------------------- non-normality (Section 5.3.4)
+# ------------------------------------------------------------ non-normality (Sections 5.3.1 to 5.3.4)
 def test_henrici_departure_closed_forms():
     """dep(T)^2 = ||T||_F^2 - sum |lambda|^2: zero for normal matrices, |a| for [[1, a], [0, 2]], and
     ||strict(T)||_F for any triangular T (its eigenvalues are its diagonal)."""
@@ -788,7 +788,7 @@ def test_jacobi_triangular_residuals(oracle_lib):
 
 
 def test_us_power_sequence_closed_form():
-    """Section 5.3.4's power sequence on U = upper bidiagonal with (U_s)_{i,i+1} = a for every i: U_s = a J
+    """Section 5.3.2's power sequence on U = upper bidiagonal with (U_s)_{i,i+1} = a for every i: U_s = a J
     with J the shift, so U_s^p = a^p J^p has n - p entries, all a^p, and 2-norm |a|^p; it vanishes at p = n.
     The diagonal varies over powers of two, so the scaled superdiagonal is exactly a = -3/4."""
     from oracle.nonnormal import us_power_sequence
