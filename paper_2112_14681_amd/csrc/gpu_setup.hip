@@ -655,11 +655,12 @@ void device_levels(HostHierarchy &H, const namg_setup_params &p) {
                    "%.2f, download %.2f ms (nnz P %lld AP %lld Ac %lld)\n",
                    (int)H.lv.size() - 1, n, (long long)A.nnz, ms(t0, t1), ms(t1, t2), ms(t2, t3), ms(t3, now()),
                    (long long)P.nnz, (long long)AP.nnz, (long long)Ac.nnz);
+    // rows are sorted by column: the diagonal by binary search
     for (int32_t i = 0; i < next.A.nr; ++i) {
-      double d = 0.0;
-      for (int32_t k = next.A.rp[i]; k < next.A.rp[i + 1]; ++k)
-        if (next.A.ci[k] == i) d = next.A.v[k];
-      if (d == 0.0) throw SetupError{NAMG_E_ZERO_PIVOT, "zero diagonal in a coarse operator"};
+      const int32_t *b = next.A.ci.data() + next.A.rp[i], *e = next.A.ci.data() + next.A.rp[i + 1];
+      const int32_t *q = std::lower_bound(b, e, i);
+      if (q == e || *q != i || next.A.v[q - next.A.ci.data()] == 0.0)
+        throw SetupError{NAMG_E_ZERO_PIVOT, "zero diagonal in a coarse operator"};
     }
     H.lv.push_back(std::move(next));
     keep->A.push_back(std::move(A));

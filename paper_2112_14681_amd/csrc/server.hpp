@@ -16,73 +16,95 @@
 #include <mutex>
 #include <thread>
 #include <unordered_map>
+#include <utility>
 
 namespace namg {
 
-// Device bytes of a DMat<T> with nr rows whose row r holds len(r) entries, nnz in all, with 16-bit column
-// offsets when narrow (mirrors DMat::build's layout choice and DevBuf's rounding of empty buffers).
-template <class T, class Len>
-int64_t layout_bytes(int32_t nr, int64_t nnz, bool narrow, int force_group, Len len) {
-  auto r1 = [](int64_t n) { return n == 0 ? (int64_t)1 : n; };
-  const int group = force_group > 0 ? force_group : choose_group(nr, nnz);
-  const int64_t ib = narrow ? 2 : 4;
-  if (group > 1) return 4 * r1((int64_t)nr + 1) + (ib + (int64_t)sizeof(T)) * r1(nnz);
-  const int64_t nslices = ((int64_t)nr + SELL_C - 1) / SELL_C;
-  int64_t stored = 0;
-  for (int64_t s = 0; s < nslices; ++s) {
-    int32_t w = 0;
-    for (int64_t r = s * SELL_C; r < std::min<int64_t>(nr, (s + 1) * SELL_C); ++r) w = std::max(w, len((int32_t)r));
-    stored += (int64_t)w * SELL_C;
+// Sizes of one DMat layout, counted row by row in increasing row order: the entries, the SELL-64 storage
+// (each slice as wide as its longest row) and whether every column fits the 16-bit offset form.
+struct LayoutCount {
+  int64_t nnz = 0, sell_stored = 0;
+  int32_t slice_w = 0;
+  bool narrow = true;
+  void row(int32_t r, int32_t len) {
+    nnz += len;
+    slice_w = std::max(slice_w, len);
+    if ((r + 1) % SELL_C == 0) {
+      sell_stored += (int64_t)slice_w * SELL_C;
+      slice_w = 0;
+    }
   }
-  return 4 * (nslices + 1) + (ib + (int64_t)sizeof(T)) * r1(stored);
+  void col(int64_t offset) {
+    if (offset < -32768 || offset > 32767) narrow = false;
+  }
+  // device bytes of the DMat<T> of nr rows (DMat::build's layout choice, DevBuf's rounding of empty buffers)
+  template <class T>
+  int64_t bytes(int32_t nr, int force_group = 0) const {
+    auto r1 = [](int64_t n) { return n == 0 ? (int64_t)1 : n; };
+    const int group = force_group > 0 ? force_group : choose_group(nr, nnz);
+    const int64_t ib = narrow ? 2 : 4;
+    if (group > 1) return 4 * r1((int64_t)nr + 1) + (ib + (int64_t)sizeof(T)) * r1(nnz);
+    const int64_t nslices = ((int64_t)nr + SELL_C - 1) / SELL_C;
+    const int64_t stored = sell_stored + (int64_t)slice_w * SELL_C;  // the last, partial slice
+    return 4 * (nslices + 1) + (ib + (int64_t)sizeof(T)) * r1(stored);
+  }
+};
+
+// One pass over a level matrix: its own layout and those of its strict lower and upper parts (the scaled
+// triangles of polynomial GS, which have A's rows and columns and so A's column offsets).
+struct MatrixShape {
+  LayoutCount all, lo, up;
+};
+
+inline MatrixShape matrix_shape(const HostCsr &A) {
+  MatrixShape m;
+  const int64_t mul = diag_mul(A.nr, A.nc);
+  for (int32_t r = 0; r < A.nr; ++r) {
+    const int32_t base = diag_base(r, mul);
+    int32_t nlo = 0, nup = 0;
+    for (int32_t k = A.rp[r]; k < A.rp[r + 1]; ++k) {
+      const int32_t c = A.ci[k];
+      const int64_t d = (int64_t)c - base;
+      m.all.col(d);
+      if (c < r) {
+        ++nlo;
+        m.lo.col(d);
+      } else if (c > r) {
+        ++nup;
+        m.up.col(d);
+      }
+    }
+    m.all.row(r, A.rp[r + 1] - A.rp[r]);
+    m.lo.row(r, nlo);
+    m.up.row(r, nup);
+  }
+  return m;
 }
 
 // Device bytes one DMat<T>::build of A allocates.
 template <class T>
 int64_t mat_alloc_bytes(const HostCsr &A, int force_group = 0) {
-  return layout_bytes<T>(A.nr, A.nnz(), fits_col16(A), force_group,
-                         [&](int32_t r) { return A.rp[r + 1] - A.rp[r]; });
+  return matrix_shape(A).all.bytes<T>(A.nr, force_group);
 }
 
-// Device bytes one DMat<T> of the strict lower (or upper) part of A allocates, computed from A's row
-// structure without building the part (rows of A sorted by column, as the setup keeps them).
-template <class T>
-int64_t strict_alloc_bytes(const HostCsr &A, bool lower) {
-  const int64_t mul = diag_mul(A.nr, A.nc);
-  std::vector<int32_t> len(A.nr);
-  int64_t nnz = 0;
-  bool narrow = true;
-  for (int32_t r = 0; r < A.nr; ++r) {
-    const int32_t *b = A.ci.data() + A.rp[r], *e = A.ci.data() + A.rp[r + 1];
-    const int32_t *lo_end = std::lower_bound(b, e, r);
-    const int32_t *up_begin = std::upper_bound(lo_end, e, r);
-    const int32_t *p0 = lower ? b : up_begin, *p1 = lower ? lo_end : e;
-    len[r] = (int32_t)(p1 - p0);
-    nnz += len[r];
-    const int32_t base = diag_base(r, mul);
-    for (const int32_t *q = p0; q < p1 && narrow; ++q) {
-      const int64_t d = (int64_t)*q - base;
-      if (d < -32768 || d > 32767) narrow = false;
-    }
-  }
-  return layout_bytes<T>(A.nr, nnz, narrow, 0, [&](int32_t r) { return len[r]; });
-}
-
-// Device bytes one DMat<T> of R = P^T allocates, computed from P without building R.
-template <class T>
-int64_t restriction_alloc_bytes(const HostCsr &P) {
-  const int32_t nr = P.nc;  // rows of R
-  const int64_t mul = diag_mul(nr, P.nr);
-  std::vector<int32_t> len(nr, 0);
-  bool narrow = true;
-  for (int32_t i = 0; i < P.nr; ++i)
+// One pass over P for the layouts of P and of R = P^T (R's rows are P's columns; entry (c, i) of R takes its
+// column offset from R's own diagonal base).
+inline std::pair<LayoutCount, LayoutCount> transfer_shape(const HostCsr &P) {
+  LayoutCount lp, lr;
+  const int64_t mul_p = diag_mul(P.nr, P.nc), mul_r = diag_mul(P.nc, P.nr);
+  std::vector<int32_t> rlen(P.nc, 0);
+  for (int32_t i = 0; i < P.nr; ++i) {
+    const int32_t base = diag_base(i, mul_p);
     for (int32_t k = P.rp[i]; k < P.rp[i + 1]; ++k) {
-      const int32_t c = P.ci[k];  // entry (c, i) of R
-      len[c]++;
-      const int64_t d = (int64_t)i - diag_base(c, mul);
-      if (d < -32768 || d > 32767) narrow = false;
+      const int32_t c = P.ci[k];
+      lp.col((int64_t)c - base);
+      lr.col((int64_t)i - diag_base(c, mul_r));
+      rlen[c]++;
     }
-  return layout_bytes<T>(nr, P.nnz(), narrow, 0, [&](int32_t r) { return len[r]; });
+    lp.row(i, P.rp[i + 1] - P.rp[i]);
+  }
+  for (int32_t c = 0; c < P.nc; ++c) lr.row(c, rlen[c]);
+  return {lp, lr};
 }
 
 // Device bytes of Solver<T>(H) with its Krylov workspace for restart m (the direct comparators' level
@@ -97,16 +119,20 @@ int64_t solver_footprint(const HostHierarchy &H, int m) {
     const int64_t n = h.A.nr;
     total += 2 * S * n;
     if (l == nl - 1) break;
-    total += mat_alloc_bytes<T>(h.A) + mat_alloc_bytes<T>(h.P) + 2 * S * n + 4 * S * n;
-    total += h.host_restriction ? mat_alloc_bytes<T>(h.R) : restriction_alloc_bytes<T>(h.P);
+    // A, its strict parts and (level 0) its FP64 copy from one pass; P and R from one pass over P
+    const MatrixShape ms = matrix_shape(h.A);
+    const auto pr = transfer_shape(h.P);
+    if (l == 0) total += ms.all.bytes<double>(h.A.nr, 1);
+    total += ms.all.bytes<T>(h.A.nr) + pr.first.bytes<T>(h.P.nr) + 2 * S * n + 4 * S * n;
+    total += h.host_restriction ? mat_alloc_bytes<T>(h.R) : pr.second.bytes<T>(h.P.nc);
     total += h.host_smoother ? mat_alloc_bytes<T>(h.pgs_lo) + mat_alloc_bytes<T>(h.pgs_up)
-                             : strict_alloc_bytes<T>(h.A, true) + strict_alloc_bytes<T>(h.A, false);
+                             : ms.lo.bytes<T>(h.A.nr) + ms.up.bytes<T>(h.A.nr);
     if (h.has_ilu) total += mat_alloc_bytes<T>(h.ilu_lo) + mat_alloc_bytes<T>(h.ilu_up) + S * n;
   }
   const int64_t nc = H.lv.back().A.nr;
   // dense inverse: CSR with 64 lanes per row (one SELL slice when nc == 1); columns always fit 16 bits
   total += nc > 1 ? 4 * (nc + 1) + (2 + S) * nc * nc : 4 * 2 + (2 + S) * SELL_C;
-  total += mat_alloc_bytes<double>(H.lv[0].A, 1);
+  if (nl == 1) total += mat_alloc_bytes<double>(H.lv[0].A, 1);
   const int64_t n0 = H.lv[0].A.nr;
   const int64_t nred = blocks_for(n0);
   total += 8 * (std::max<int64_t>(nred, 1) + 8) + (int64_t)sizeof(KState);
