@@ -596,7 +596,7 @@ class BatchEngine {
 class ServerBase {
  public:
   virtual ~ServerBase() = default;
-  virtual uint64_t submit(const HostCsr &A, const double *b, const namg_setup_params &sp) = 0;
+  virtual uint64_t submit(HostCsr &&A, const double *b, const namg_setup_params &sp) = 0;
   virtual int poll(uint64_t ticket, bool wait, double *x, namg_solve_stats *st, namg_request_times *tm) = 0;
   virtual namg_server_counters stats() = 0;
   virtual double clock() const = 0;
@@ -656,10 +656,10 @@ class Server final : public ServerBase {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0_).count();
   }
 
-  uint64_t submit(const HostCsr &A, const double *b, const namg_setup_params &sp) override {
+  uint64_t submit(HostCsr &&A, const double *b, const namg_setup_params &sp) override {
     auto r = std::make_unique<Req>();
-    r->A = A;
     r->b.assign(b, b + A.nr);
+    r->A = std::move(A);
     r->sp = sp;
     r->tm.submit = clock();
     std::lock_guard<std::mutex> lk(mu_);

@@ -1220,8 +1220,7 @@ int namg_server_submit(namg_server *s, int32_t n, const int32_t *rowptr, const i
                        const double *b, const namg_setup_params *sp, uint64_t *ticket) {
   return guarded([&]() -> int {
     if (!s || !b || !sp || !ticket) throw namg::SetupError{NAMG_E_INVALID, "null argument"};
-    namg::HostCsr A = namg::import_csr(n, rowptr, colind, vals);
-    *ticket = s->impl->submit(A, b, *sp);
+    *ticket = s->impl->submit(namg::import_csr(n, rowptr, colind, vals), b, *sp);
     return NAMG_OK;
   });
 }
