@@ -31,6 +31,10 @@
 #include "pack.hpp"
 #include "setup_host.hpp"
 
+// Every product and sum of the setup is rounded on its own (no fused multiply-add), as in the oracle, so
+// that P and the Galerkin operators match it bit for bit.
+#pragma clang fp contract(off)
+
 namespace namg {
 namespace {
 
@@ -261,6 +265,109 @@ __global__ __launch_bounds__(TB) void k_spgemm_size(int32_t nrows, const int32_t
   tsize[i] = ts;
 }
 
+// Short rows of X Y, one wavefront per row: a row whose X row has at most WAVE entries and at most WAVE
+// products. Lane k < len(X row) holds X's entry k and the length of Y's row x_ci[k]; an inclusive scan of
+// the lengths places every product, so lane l computes product l of the canonical order (X's entries in
+// order, each Y row in order). A bitonic sort of the keys (column << 6 | l) across the wavefront brings each
+// column's products together in that order, and the first lane of each run sums the run left to right,
+// starting from its first product: the running sums of the canonical order, bit for bit. The distinct
+// columns, sorted, go to the row's table region with order[base + q] = q and cnt[i] = their number. All
+// lanes of a wavefront stay active through the shuffles; the early returns are uniform per wavefront.
+constexpr int WAVE = 64;
+constexpr int WROWS = 4;  // wavefronts (rows) per block
+
+__device__ __forceinline__ bool wave_product_row(int32_t i, const int32_t *__restrict__ xrp,
+                                                 const int32_t *__restrict__ xci, const int32_t *__restrict__ yrp) {
+  const int32_t a = xrp[i], lx = xrp[i + 1] - a;
+  if (lx > WAVE) return false;
+  int64_t bound = 0;
+  for (int32_t k = a; k < a + lx; ++k) bound += yrp[xci[k] + 1] - yrp[xci[k]];
+  return bound <= WAVE;
+}
+
+__global__ __launch_bounds__(WAVE * WROWS) void k_spgemm_wave(int32_t nrows, const int32_t *__restrict__ xrp,
+                                                            const int32_t *__restrict__ xci,
+                                                            const double *__restrict__ xv,
+                                                            const int32_t *__restrict__ yrp,
+                                                            const int32_t *__restrict__ yci,
+                                                            const double *__restrict__ yv,
+                                                            const int64_t *__restrict__ toff, int32_t *__restrict__ tkey,
+                                                            double *__restrict__ tval, int32_t *__restrict__ order,
+                                                            int32_t *__restrict__ cnt) {
+  const int lane = (int)(threadIdx.x % WAVE);
+  const int32_t i = (int32_t)(blockIdx.x * WROWS + threadIdx.x / WAVE);
+  if (i >= nrows) return;
+  const int32_t xb = xrp[i], lx = xrp[i + 1] - xb;
+  if (lx > WAVE) return;
+  int32_t ylen = 0, ystart = 0;
+  double x = 0.0;
+  if (lane < lx) {
+    const int32_t j = xci[xb + lane];
+    x = xv[xb + lane];
+    ystart = yrp[j];
+    ylen = yrp[j + 1] - ystart;
+  }
+  int32_t incl = ylen;
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const int32_t t = __shfl_up(incl, d);
+    if (lane >= d) incl += t;
+  }
+  const int32_t bound = __shfl(incl, WAVE - 1);
+  if (bound > WAVE) return;  // the per-row table kernel takes this row
+  if (bound == 0) {
+    if (lane == 0) cnt[i] = 0;
+    return;
+  }
+  // product `lane`: the X entry kk it belongs to, then its place in Y's row
+  int32_t kk = 0;
+  for (int32_t k = 0; k < lx; ++k) kk += (__shfl(incl, k) <= lane) ? 1 : 0;
+  kk = kk < WAVE ? kk : WAVE - 1;
+  const int32_t excl_k = __shfl(incl - ylen, kk);
+  const int32_t ystart_k = __shfl(ystart, kk);
+  const double x_k = __shfl(x, kk);
+  unsigned long long key = ~0ull;
+  double val = 0.0;
+  if (lane < bound) {
+    const int32_t q = ystart_k + (lane - excl_k);
+    key = ((unsigned long long)(uint32_t)yci[q] << 6) | (unsigned long long)lane;
+    val = x_k * yv[q];
+  }
+  for (int size = 2; size <= WAVE; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const unsigned long long ok = __shfl_xor(key, stride);
+      const double ov = __shfl_xor(val, stride);
+      const bool up = (lane & size) == 0, lower = (lane & stride) == 0;
+      const bool take = lower ? (up ? ok < key : ok > key) : (up ? ok > key : ok < key);
+      if (take) {
+        key = ok;
+        val = ov;
+      }
+    }
+  const unsigned long long prev = __shfl_up(key, 1);
+  const bool head = lane < bound && (lane == 0 || (prev >> 6) != (key >> 6));
+  double sum = val;
+  bool run = head;
+  for (int32_t m = 1; m < lx; ++m) {
+    const int src = lane + m < WAVE ? lane + m : WAVE - 1;
+    const unsigned long long km = __shfl(key, src);
+    const double vm = __shfl(val, src);
+    if (run && lane + m < bound && (km >> 6) == (key >> 6))
+      sum += vm;
+    else
+      run = false;
+  }
+  const unsigned long long heads = __ballot(head);
+  const int64_t base = toff[i];
+  if (head) {
+    const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (WAVE - lane));
+    const int32_t rank = (int32_t)__popcll(heads & below);
+    tkey[base + rank] = (int32_t)(key >> 6);
+    tval[base + rank] = sum;
+    order[base + rank] = rank;
+  }
+  if (lane == 0) cnt[i] = (int32_t)__popcll(heads);
+}
+
 // Row i of X Y accumulated into its own open-addressing table [toff[i], toff[i+1]) (keys cleared to -1
 // beforehand); the slot of each new column is appended to order[toff[i] + c], so the row's entries can be
 // read back without scanning the table; cnt[i] = distinct columns, cnt[nrows] = 0.
@@ -276,6 +383,7 @@ __global__ __launch_bounds__(TB) void k_spgemm_accumulate(int32_t nrows, const i
   const int32_t i = blockIdx.x * TB + threadIdx.x;
   if (i == nrows) cnt[nrows] = 0;
   if (i >= nrows) return;
+  if (wave_product_row(i, xrp, xci, yrp)) return;  // k_spgemm_wave's row
   const int64_t base = toff[i];
   const int64_t ts = toff[i + 1] - base;
   if (ts == 0) {
@@ -468,6 +576,12 @@ class Builder {
     DevBuf<int32_t> cnt((size_t)nr + 1, nullptr);
     // every key to -1 (all bytes 0xFF) in one coalesced pass
     hip_check(hipMemsetAsync(tkey.get(), 0xFF, (size_t)std::max<int64_t>(total, 1) * 4, s_), "memset");
+    if (nr > 0) {
+      hipLaunchKernelGGL(k_spgemm_wave, dim3((unsigned)(((int64_t)nr + WROWS - 1) / WROWS)), dim3(WAVE * WROWS), 0, s_,
+                         nr, X.rp.get(), X.ci.get(), X.v.get(), Y.rp.get(), Y.ci.get(), Y.v.get(), toff.get(),
+                         tkey.get(), tval.get(), order.get(), cnt.get());
+      check("k_spgemm_wave");
+    }
     hipLaunchKernelGGL(k_spgemm_accumulate, dim3(grid_for((int64_t)nr + 1)), dim3(TB), 0, s_, nr, X.rp.get(),
                        X.ci.get(), X.v.get(), Y.rp.get(), Y.ci.get(), Y.v.get(), toff.get(), tkey.get(), tval.get(),
                        order.get(), cnt.get());
