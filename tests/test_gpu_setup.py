@@ -64,6 +64,38 @@ def test_device_pmis_setup_edge_cases(namg):
     _compare(namg, one, 0)
 
 
+def _product_row_classes(G):
+    """Over the oracle hierarchy's products A P and R (A P): rows whose X row has more than 64 entries, rows
+    with at most 64 products, and the others (the device setup's three kernels' shares)."""
+    cls = {"le64": 0, "gt64": 0, "long_x": 0}
+
+    def count(Xrp, Xci, ylen):
+        for i in range(len(Xrp) - 1):
+            cols = Xci[Xrp[i]:Xrp[i + 1]]
+            key = "long_x" if len(cols) > 64 else ("le64" if ylen[cols].sum() <= 64 else "gt64")
+            cls[key] += 1
+
+    for l in range(G.levels - 1):
+        g = G.level(l)
+        P = g.P.tocsr()
+        count(g.A.rowptr, g.A.colind, np.diff(P.indptr))
+        R = P.T.tocsr()
+        AP = (g.A.to_scipy() @ P).tocsr()
+        count(R.indptr, R.indices, np.diff(AP.indptr))
+    return cls
+
+
+@pytest.mark.parametrize("n,per_row,seed", [(600, 24, 11), (800, 12, 4)])
+def test_device_sparse_products_all_row_classes(namg, n, per_row, seed):
+    """Random nonsymmetric matrices whose Galerkin products have rows of every kind the device setup
+    distinguishes (at most 64 products: one wavefront per row; more: a per-row table; more than 64 entries
+    in the left factor's row: the table too): every level still equals the oracle's bit for bit."""
+    A = random_csr(n, per_row, seed)
+    _, G, _ = _compare(namg, A, 9, max_coarse=10)
+    cls = _product_row_classes(G)
+    assert min(cls.values()) > 0, cls
+
+
 @pytest.mark.parametrize("name,N,kw", [("c2", 24, dict(smoother=1, inner_terms=3)),
                                        ("c3", 20, dict(smoother=0, inner_terms=2))])
 def test_solve_on_device_pmis_hierarchy(namg, name, N, kw):
