@@ -572,12 +572,9 @@ std::vector<double> dense_inverse(const HostCsr &A) {
 void smoother_data(HostLevel &L, bool with_ilu, const namg_setup_params &p, bool host_smoother) {
   const HostCsr &A = L.A;
   L.host_smoother = host_smoother;
-  if (host_smoother) {
-    pgs_data(A, L.dinv, L.dl1inv, L.pgs_lo, L.pgs_up);
-  } else {
-    for (int32_t i = 0; i < A.nr; ++i)
-      if (diagonal(A, i) == 0.0) fail(NAMG_E_ZERO_PIVOT, "zero diagonal in row " + std::to_string(i));
-  }
+  // without the host copy there is nothing to check either: the device setup has checked every diagonal,
+  // level 0's on import and each coarse operator's as it was built
+  if (host_smoother) pgs_data(A, L.dinv, L.dl1inv, L.pgs_lo, L.pgs_up);
   if (with_ilu) {
     // L \ U as one CSR: ILU(0) values in A's pattern, or the ILUT factor with its own fill
     HostCsr F;

@@ -69,8 +69,8 @@ HostHierarchy build_hierarchy(HostCsr &&A, const namg_setup_params &p);
 
 // Parameter checks shared by both setups, ||A||_inf, and the host part that completes a hierarchy whose
 // levels (A, P, R, C/F) are built: smoother data of every level but the coarsest, the coarse inverse.
-// host_smoother = false leaves the polynomial-GS data to a device packing (the ILU factors and the zero
-// diagonal check stay on the host).
+// host_smoother = false leaves the polynomial-GS data to a device packing (the ILU factors stay on the
+// host); the caller has then checked every level's diagonal (the device setup does, as it builds them).
 void validate_hierarchy_params(const namg_setup_params &p);
 double inf_norm(const HostCsr &A);
 void finish_hierarchy(HostHierarchy &H, const namg_setup_params &p, bool host_smoother = true);
