@@ -73,6 +73,8 @@ class PinnedPool {
 // DMA of one slice overlaps the host memcpy of another, and an event per slice says when it is reusable.
 constexpr int STAGE_SLOTS = 8;
 
+// Declared after the StageBuffer it guards: on every exit, errors included, it waits for the copies it has
+// recorded before the buffer goes back to the pool.
 struct StageEvents {
   hipEvent_t e[STAGE_SLOTS] = {};
   StageEvents() {
@@ -80,7 +82,10 @@ struct StageEvents {
   }
   ~StageEvents() {
     for (auto &x : e)
-      if (x) (void)hipEventDestroy(x);
+      if (x) {
+        (void)hipEventSynchronize(x);
+        (void)hipEventDestroy(x);
+      }
   }
 };
 
