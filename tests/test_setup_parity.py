@@ -325,7 +325,9 @@ def test_ilu_diagnostics_validation(namg):
 
 def test_nonnormality_study_host_only(namg):
     """bench.py's factor study runs without a GPU (host setup and diagnostics only) and reports the
-    Section 5.3.4 quantities per ordering and fill level, each within its theorem's bound."""
+    Sections 5.3.2 to 5.3.4 quantities per ordering and fill level, each within its theorem's bound; the
+    powers of U_s for ILU(0) of the 7-point stencil at 7^3 vanish one step past its longest chain, 3 (7 - 1)
+    edges, and ILUT's fill only lengthens the chains."""
     import importlib.util
 
     spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
@@ -339,3 +341,19 @@ def test_nonnormality_study_host_only(namg):
         assert 0.0 < r["jacobi5_res_L"] < 1.0 and "gmres_iters" not in r
     fills = [out["fill_sweep"][k]["nnz_upper"] for k in ("5", "10", "20", "50")]
     assert fills == sorted(fills)
+    pw = out["us_powers"]
+    assert pw["ilu0"]["vanishes_at_p"] == 3 * (7 - 1) + 1
+    assert pw["ilut_1e-3_20"]["vanishes_at_p"] >= pw["ilu0"]["vanishes_at_p"]
+    for seq in (pw["ilu0"], pw["ilut_1e-3_20"]):
+        assert len(seq["nnz"]) == seq["vanishes_at_p"] - 1 and min(seq["nnz"]) > 0
+        assert all(m <= n2 * (1 + 1e-3) for m, n2 in zip(seq["max_abs"], seq["norm2"]))
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU: --gpus above 1 exits with status 2 and says why, before touching a GPU."""
+    import subprocess
+    import sys
+
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU only" in r.stderr
