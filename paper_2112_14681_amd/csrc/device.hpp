@@ -95,9 +95,8 @@ struct StageBuffer {
   ~StageBuffer() { pool.release(b); }
 };
 
-// Copies of pageable memory on stream s (by default the calling thread's own stream, so that threads
-// uploading at the same time do not queue on the shared null stream); return when the copy is complete.
-inline void copy_to_device(void *dst, const void *src, size_t bytes, hipStream_t s = hipStreamPerThread) {
+// Copies of pageable memory on stream s (the null stream by default); return when the copy is complete.
+inline void copy_to_device(void *dst, const void *src, size_t bytes, hipStream_t s = nullptr) {
   if (bytes == 0) return;
   constexpr size_t SL = PinnedPool::CHUNK / STAGE_SLOTS;
   StageBuffer stage;

@@ -18,10 +18,6 @@
 namespace namg {
 namespace {
 
-// Each host thread packs on its own default stream, so setup threads packing at the same time do not queue
-// behind one another on the device's shared null stream.
-const hipStream_t PS = hipStreamPerThread;
-
 constexpr int PB = 256;
 inline unsigned pgrid(int64_t n) { return (unsigned)std::max<int64_t>((n + PB - 1) / PB, 1); }
 
@@ -166,28 +162,27 @@ void pack_device(DMat<T> &M, const DCsr &D, MemCounter *mc, int force_group) {
   M.nnz = D.nnz;
   M.mul = diag_mul(M.nrows, M.ncols);
   DevBuf<int32_t> bad(1, nullptr);
-  hip_check(hipMemsetAsync(bad.get(), 0, 4, PS), "hipMemsetAsync");
+  hip_check(hipMemset(bad.get(), 0, 4), "hipMemset");
   if (M.nrows > 0) {
-    hipLaunchKernelGGL(k_fits16, dim3(pgrid(M.nrows)), dim3(PB), 0, PS, M.nrows, D.rp.get(), D.ci.get(), M.mul,
+    hipLaunchKernelGGL(k_fits16, dim3(pgrid(M.nrows)), dim3(PB), 0, 0, M.nrows, D.rp.get(), D.ci.get(), M.mul,
                        bad.get());
     check("k_fits16");
   }
   int32_t hbad = 0;
-  hip_check(hipMemcpyAsync(&hbad, bad.get(), 4, hipMemcpyDeviceToHost, PS), "D2H");
-  hip_check(hipStreamSynchronize(PS), "hipStreamSynchronize");
+  hip_check(hipMemcpy(&hbad, bad.get(), 4, hipMemcpyDeviceToHost), "hipMemcpy D2H");
   M.narrow = hbad == 0;
   M.group = force_group > 0 ? force_group : choose_group(M.nrows, M.nnz);
   if (M.group > 1) {
     M.stored = M.nnz;
     M.ptr.alloc((size_t)M.nrows + 1, mc);
-    hip_check(hipMemcpyAsync(M.ptr.get(), D.rp.get(), ((size_t)M.nrows + 1) * 4, hipMemcpyDeviceToDevice, PS), "D2D");
+    hip_check(hipMemcpy(M.ptr.get(), D.rp.get(), ((size_t)M.nrows + 1) * 4, hipMemcpyDeviceToDevice), "hipMemcpy D2D");
     if (M.narrow)
       M.col16.alloc((size_t)M.stored, mc);
     else
       M.col.alloc((size_t)M.stored, mc);
     M.val.alloc((size_t)M.stored, mc);
     if (M.nrows > 0) {
-      hipLaunchKernelGGL(k_pack_csr<T>, dim3(pgrid(M.nrows)), dim3(PB), 0, PS, M.nrows, D.rp.get(), D.ci.get(),
+      hipLaunchKernelGGL(k_pack_csr<T>, dim3(pgrid(M.nrows)), dim3(PB), 0, 0, M.nrows, D.rp.get(), D.ci.get(),
                          D.v.get(), M.mul, (int32_t)M.narrow, M.col16.get(), M.col.get(), M.val.get());
       check("k_pack_csr");
     }
@@ -196,10 +191,9 @@ void pack_device(DMat<T> &M, const DCsr &D, MemCounter *mc, int force_group) {
     std::vector<int32_t> w(std::max(nslices, 1), 0);
     if (nslices > 0) {
       DevBuf<int32_t> dw((size_t)nslices, nullptr);
-      hipLaunchKernelGGL(k_slice_width, dim3(pgrid(nslices)), dim3(PB), 0, PS, M.nrows, D.rp.get(), dw.get());
+      hipLaunchKernelGGL(k_slice_width, dim3(pgrid(nslices)), dim3(PB), 0, 0, M.nrows, D.rp.get(), dw.get());
       check("k_slice_width");
-      hip_check(hipMemcpyAsync(w.data(), dw.get(), (size_t)nslices * 4, hipMemcpyDeviceToHost, PS), "D2H");
-      hip_check(hipStreamSynchronize(PS), "hipStreamSynchronize");
+      hip_check(hipMemcpy(w.data(), dw.get(), (size_t)nslices * 4, hipMemcpyDeviceToHost), "hipMemcpy D2H");
     }
     w.resize(nslices);
     const std::vector<int32_t> sptr = host_offsets(w);
@@ -212,7 +206,7 @@ void pack_device(DMat<T> &M, const DCsr &D, MemCounter *mc, int force_group) {
       M.col.alloc((size_t)M.stored, mc);
     M.val.alloc((size_t)M.stored, mc);
     if (nslices > 0) {
-      hipLaunchKernelGGL(k_pack_sell<T>, dim3(pgrid((int64_t)nslices * SELL_C)), dim3(PB), 0, PS, M.nrows, nslices,
+      hipLaunchKernelGGL(k_pack_sell<T>, dim3(pgrid((int64_t)nslices * SELL_C)), dim3(PB), 0, 0, M.nrows, nslices,
                          D.rp.get(), D.ci.get(), D.v.get(), M.ptr.get(), M.mul, (int32_t)M.narrow, M.col16.get(),
                          M.col.get(), M.val.get());
       check("k_pack_sell");
@@ -220,7 +214,7 @@ void pack_device(DMat<T> &M, const DCsr &D, MemCounter *mc, int force_group) {
   }
   // the caller may release D (its blocks return to the cache) right after: wait for this null-stream work
   // only (the solves and setups of other requests run on streams of their own)
-  hip_check(hipStreamSynchronize(PS), "hipStreamSynchronize");
+  hip_check(hipStreamSynchronize(nullptr), "hipStreamSynchronize");
 }
 
 template <class T>
@@ -228,15 +222,14 @@ void smoother_data_device(const DCsr &A, DCsr &lo, DCsr &up, DevBuf<T> &dinv, De
   const int32_t n = A.nr;
   DevBuf<int32_t> nlo((size_t)std::max(n, 1), nullptr), nup((size_t)std::max(n, 1), nullptr);
   if (n > 0) {
-    hipLaunchKernelGGL(k_strict_count, dim3(pgrid(n)), dim3(PB), 0, PS, n, A.rp.get(), A.ci.get(), nlo.get(),
+    hipLaunchKernelGGL(k_strict_count, dim3(pgrid(n)), dim3(PB), 0, 0, n, A.rp.get(), A.ci.get(), nlo.get(),
                        nup.get());
     check("k_strict_count");
   }
   std::vector<int32_t> cl(n), cu(n);
   if (n > 0) {
-    hip_check(hipMemcpyAsync(cl.data(), nlo.get(), (size_t)n * 4, hipMemcpyDeviceToHost, PS), "D2H");
-    hip_check(hipMemcpyAsync(cu.data(), nup.get(), (size_t)n * 4, hipMemcpyDeviceToHost, PS), "D2H");
-    hip_check(hipStreamSynchronize(PS), "hipStreamSynchronize");
+    hip_check(hipMemcpy(cl.data(), nlo.get(), (size_t)n * 4, hipMemcpyDeviceToHost), "hipMemcpy D2H");
+    hip_check(hipMemcpy(cu.data(), nup.get(), (size_t)n * 4, hipMemcpyDeviceToHost), "hipMemcpy D2H");
   }
   const std::vector<int32_t> lrp = host_offsets(cl), urp = host_offsets(cu);
   for (DCsr *tri : {&lo, &up}) {
@@ -256,12 +249,12 @@ void smoother_data_device(const DCsr &A, DCsr &lo, DCsr &up, DevBuf<T> &dinv, De
   dinv.alloc((size_t)std::max(n, 1), mc);
   dl1inv.alloc((size_t)std::max(n, 1), mc);
   if (n > 0) {
-    hipLaunchKernelGGL(k_smoother_data<T>, dim3(pgrid(n)), dim3(PB), 0, PS, n, A.rp.get(), A.ci.get(), A.v.get(),
+    hipLaunchKernelGGL(k_smoother_data<T>, dim3(pgrid(n)), dim3(PB), 0, 0, n, A.rp.get(), A.ci.get(), A.v.get(),
                        lo.rp.get(), up.rp.get(), lo.ci.get(), lo.v.get(), up.ci.get(), up.v.get(), dinv.get(),
                        dl1inv.get());
     check("k_smoother_data");
   }
-  hip_check(hipStreamSynchronize(PS), "hipStreamSynchronize");
+  hip_check(hipStreamSynchronize(nullptr), "hipStreamSynchronize");
 }
 
 template void pack_device<float>(DMat<float> &, const DCsr &, MemCounter *, int);

@@ -833,13 +833,8 @@ class Server final : public ServerBase {
     const int32_t n = r->slot.n;
     auto &sl = r->slot;
     r->x.assign(n, 0.0);
-    if (sl.status >= 0) {
-      // the solve's stream is past the slot's last tick; the finisher's own stream does not wait on others
-      hip_check(hipMemcpyAsync(r->x.data(), r->xd.get(), sizeof(double) * n, hipMemcpyDeviceToHost,
-                               hipStreamPerThread),
-                "D2H");
-      hip_check(hipStreamSynchronize(hipStreamPerThread), "hipStreamSynchronize");
-    }
+    if (sl.status >= 0)
+      hip_check(hipMemcpy(r->x.data(), r->xd.get(), sizeof(double) * n, hipMemcpyDeviceToHost), "hipMemcpy D2H");
     double xn = 0.0;
     for (double v : r->x) xn += v * v;
     xn = std::sqrt(xn);
