@@ -101,6 +101,67 @@ def test_rs_tie_break_smallest_index(oracle_lib):
     assert list(cf) == [1, 0, 1, 0, 1, 0, 1, 0, 1]
 
 
+def _graph_matrix(n, edges):
+    """Symmetric matrix with -1 on every edge and degree + 1 on the diagonal (isolated points: 1)."""
+    d = np.zeros((n, n))
+    for i, j in edges:
+        d[i, j] = d[j, i] = -1.0
+    np.fill_diagonal(d, np.abs(d).sum(axis=1) + 1.0)
+    return CSR.from_dense(d)
+
+
+def _rs_by_definition(n, edges, f_weight=2, largest_first=False):
+    """The first pass written from its definition for a symmetric graph: recompute every measure from
+    scratch after each decision (tiny inputs only)."""
+    nb = [set() for _ in range(n)]
+    for i, j in edges:
+        nb[i].add(j)
+        nb[j].add(i)
+    state = ["F" if not nb[i] else "U" for i in range(n)]
+    while "U" in state:
+        lam = {i: sum(1 if state[j] == "U" else (f_weight if state[j] == "F" else 0) for j in nb[i])
+               for i in range(n) if state[i] == "U"}
+        top = max(lam.values())
+        ties = [i for i in sorted(lam) if lam[i] == top]
+        i = ties[-1] if largest_first else ties[0]
+        state[i] = "C"
+        for j in nb[i]:
+            if state[j] == "U":
+                state[j] = "F"
+    return [1 if s == "C" else 0 for s in state]
+
+
+def test_rs_first_pass_hand_worked_golden(oracle_lib):
+    """Hand-worked RS first passes (tests/golden/rs_first_pass_hand.json): tridiag(4) fixes the
+    smallest-index tie-break (C = {1, 3}, not {0, 2}); the 11-point graph fixes the weight 2 on F
+    dependents (a weight of 1 or 0, or the largest-index tie-break, gives a different splitting)."""
+    g = json.load(open(os.path.join(GOLD, "rs_first_pass_hand.json")))
+    for case in g["cases"]:
+        A = _graph_matrix(case["n"], case["edges"])
+        cf = list(oracle_lib.coarsen(A, g["theta"]))
+        assert cf == case["cf"], case["name"]
+        # the golden's alternatives really differ, so the pin discriminates those readings
+        assert case["cf_if_largest_index_first"] != case["cf"]
+        assert _rs_by_definition(case["n"], case["edges"], largest_first=True) == case["cf_if_largest_index_first"]
+        assert _rs_by_definition(case["n"], case["edges"]) == case["cf"]
+        if "cf_if_f_weight_1" in case:
+            assert case["cf_if_f_weight_1"] != case["cf"]
+            assert _rs_by_definition(case["n"], case["edges"], f_weight=1) == case["cf_if_f_weight_1"]
+            assert _rs_by_definition(case["n"], case["edges"], f_weight=0) == case["cf_if_f_weight_1"]
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_rs_first_pass_matches_definition_on_random_graphs(oracle_lib, seed):
+    """The incremental first pass of the oracle against the definition (every measure recomputed after
+    each decision) on random symmetric graphs of 6-30 points with isolated points and ties."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(6, 31))
+    p = float(rng.uniform(0.08, 0.4))
+    edges = [(i, j) for i in range(n) for j in range(i + 1, n) if rng.random() < p]
+    A = _graph_matrix(n, edges)
+    assert list(oracle_lib.coarsen(A, 0.25)) == _rs_by_definition(n, edges)
+
+
 # ------------------------------------------------------------------------------ interpolation / RAP
 @pytest.mark.parametrize("maker", [lambda: poisson2d(16), lambda: poisson3d(8), lambda: varcoef3d(8, 1.0, 2, 100.0)[0]])
 def test_classical_interp_preserves_constants(oracle_lib, maker):

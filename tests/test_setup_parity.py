@@ -357,3 +357,19 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU only" in r.stderr
+
+
+def test_library_rs_first_pass_hand_worked_golden(namg):
+    """The library's own RS first pass (host setup) on the hand-worked splittings of
+    tests/golden/rs_first_pass_hand.json: the smallest-index tie-break and the weight 2 on F dependents."""
+    import json
+
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "rs_first_pass_hand.json")))
+    for case in g["cases"]:
+        n = case["n"]
+        d = np.zeros((n, n))
+        for i, j in case["edges"]:
+            d[i, j] = d[j, i] = -1.0
+        np.fill_diagonal(d, np.abs(d).sum(axis=1) + 1.0)
+        H = namg.Hierarchy(CSR.from_dense(d), device=-1, theta=g["theta"], max_levels=2, max_coarse=1)
+        assert list(H.export_level(0)["cf"]) == case["cf"], case["name"]
