@@ -44,6 +44,7 @@ enum { NAMG_T_NEUMANN = 0, NAMG_T_DIRECT = 1 };       /* namg_solve_params.gmres
 enum { NAMG_STOP_RELRES = 0, NAMG_STOP_NRBE = 1 };    /* namg_solve_params.stop_rule */
 enum { NAMG_ILU0 = 0, NAMG_ILUT = 1 };                /* namg_setup_params.ilu_kind  */
 enum { NAMG_COARSEN_RS = 0, NAMG_COARSEN_PMIS = 1 };  /* namg_setup_params.coarsen   */
+enum { NAMG_DIAG_LOSS_ORTH = 1, NAMG_DIAG_PHASE_TIMES = 2 }; /* namg_solve_params.diagnostics (bitmask) */
 
 #define NAMG_MAX_LEVELS 32
 #define NAMG_MAX_RESTART 128
@@ -101,6 +102,14 @@ typedef struct {
                       Section 3. Inside a restart cycle the residual norm is the Arnoldi estimate and ||x||
                       is that of the cycle's starting iterate (x is formed at the cycle's end); every cycle
                       starts with the true residual. The rule changes only when the iteration stops. */
+  int diagnostics; /* bitmask, default 0. NAMG_DIAG_LOSS_ORTH: at every cycle end the Gram matrix of the cycle's
+                      Krylov basis V_{k+1} (its last column normalised by its own norm) is reduced on the
+                      device and namg_solve_stats.loss_orth reports the largest ||I - V^T V||_F over the cycles
+                      (Section 3); costs k + 1 extra passes over V per cycle. NAMG_DIAG_PHASE_TIMES: hipEvents
+                      around each phase of every Arnoldi step fill ms_vcycle, ms_spmv and ms_ortho */
+  double *res_hist; /* optional host array (caller-owned, NULL = none): res_hist[j] receives the residual
+                       estimate |g_{j+1}| / ||b|| after iteration j + 1 of the solve, for j < res_hist_cap */
+  int res_hist_cap;
 } namg_solve_params;
 
 typedef struct {
@@ -110,6 +119,11 @@ typedef struct {
   double nrbe;        /* ||r|| / (||b|| + ||A||_inf ||x||), Section 3 */
   double ms_total;    /* wall time of the call on the stream (hipEvent) */
   double alg_bytes;   /* algorithmic HBM bytes moved by the solve's kernels */
+  double loss_orth;   /* largest ||I - V^T V||_F over the restart cycles; NaN unless NAMG_DIAG_LOSS_ORTH */
+  double ms_vcycle;   /* summed device time of the preconditioner applications (V-cycles) */
+  double ms_spmv;     /* summed device time of the FP64 products w = A z */
+  double ms_ortho;    /* summed device time of the orthogonalisation: fused reduction, small dense step,
+                         projection and column completion. The three are NaN unless NAMG_DIAG_PHASE_TIMES */
 } namg_solve_stats;
 
 typedef struct {
@@ -260,7 +274,8 @@ typedef struct {
   int setup_threads;   /* host threads running the AMG setup of queued requests */
   int device;          /* HIP device ordinal */
   int precision;       /* NAMG_FP64 or NAMG_FP32_PRECOND, for every request */
-  namg_solve_params solve; /* shared by every request; tri_mode must be NAMG_TRI_NEUMANN */
+  namg_solve_params solve; /* the default solve parameters of a request (namg_server_submit may give its
+                              own); tri_mode must be NAMG_TRI_NEUMANN, diagnostics 0 and res_hist NULL */
 } namg_server_params;
 
 typedef struct {
@@ -288,9 +303,13 @@ void namg_default_server_params(namg_server_params *p);
 int namg_server_create(const namg_server_params *p, namg_server **out);
 
 /* Queue one system A x = b (host CSR and b, copied; x0 = 0) with its setup parameters (precision and
- * device come from the server). Returns at once with a ticket. */
+ * device come from the server) and its solve parameters p (copied; NULL = the server's default). Requests
+ * with different smoothers, Neumann terms, restarts, tolerances or T forms are batched together: every
+ * batched launch carries each solve's own operands and parameters. p is validated as for namg_solve, and
+ * must keep tri_mode NAMG_TRI_NEUMANN, diagnostics 0 and res_hist NULL (NAMG_E_INVALID otherwise).
+ * Returns at once with a ticket. */
 int namg_server_submit(namg_server *s, int32_t n, const int32_t *rowptr, const int32_t *colind, const double *vals,
-                       const double *b, const namg_setup_params *sp, uint64_t *ticket);
+                       const double *b, const namg_setup_params *sp, const namg_solve_params *p, uint64_t *ticket);
 
 /* NAMG_PENDING while the request is queued or in flight. Once it has finished: copies x (n doubles,
  * host, may be NULL), its statistics and times, forgets the ticket and returns its status (NAMG_OK,

@@ -24,6 +24,7 @@ T_NEUMANN, T_DIRECT = 0, 1
 STOP_RELRES, STOP_NRBE = 0, 1
 ILU0, ILUT = 0, 1
 COARSEN_RS, COARSEN_PMIS = 0, 1
+DIAG_LOSS_ORTH, DIAG_PHASE_TIMES = 1, 2
 OP_SPMV, OP_RESIDUAL, OP_SMOOTH_PRE, OP_SMOOTH_POST, OP_RESTRICT, OP_PROLONG, OP_COARSE, OP_SPMV64 = range(8)
 MAX_LEVELS = 32
 
@@ -48,7 +49,8 @@ class SetupParams(C.Structure):
 class SolveParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int), ("max_iters", C.c_int), ("smoother", C.c_int),
                 ("tri_mode", C.c_int), ("inner_terms", C.c_int), ("gmres_T", C.c_int), ("pre_sweeps", C.c_int),
-                ("post_sweeps", C.c_int), ("t_degree", C.c_int), ("stop_rule", C.c_int)]
+                ("post_sweeps", C.c_int), ("t_degree", C.c_int), ("stop_rule", C.c_int), ("diagnostics", C.c_int),
+                ("res_hist", C.POINTER(C.c_double)), ("res_hist_cap", C.c_int)]
 
 
 class IluDiag(C.Structure):
@@ -64,7 +66,8 @@ class IluDiag(C.Structure):
 class SolveStats(C.Structure):
     _fields_ = [("status", C.c_int), ("iters", C.c_int), ("cycles", C.c_int), ("precond_apps", C.c_int),
                 ("relres_true", C.c_double), ("relres_est", C.c_double), ("nrbe", C.c_double),
-                ("ms_total", C.c_double), ("alg_bytes", C.c_double)]
+                ("ms_total", C.c_double), ("alg_bytes", C.c_double), ("loss_orth", C.c_double),
+                ("ms_vcycle", C.c_double), ("ms_spmv", C.c_double), ("ms_ortho", C.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -138,7 +141,7 @@ def _load():
     lib.namg_default_server_params.argtypes = [C.POINTER(ServerParams)]
     lib.namg_server_create.argtypes = [C.POINTER(ServerParams), C.POINTER(vp)]
     lib.namg_server_submit.argtypes = [vp, C.c_int32, i32p, i32p, f64p, f64p, C.POINTER(SetupParams),
-                                       C.POINTER(C.c_uint64)]
+                                       C.POINTER(SolveParams), C.POINTER(C.c_uint64)]
     lib.namg_server_poll.argtypes = [vp, C.c_uint64, f64p, C.POINTER(SolveStats), C.POINTER(RequestTimes)]
     lib.namg_server_wait.argtypes = [vp, C.c_uint64, f64p, C.POINTER(SolveStats), C.POINTER(RequestTimes)]
     lib.namg_server_stats.argtypes = [vp, C.POINTER(ServerCounters)]
@@ -298,14 +301,22 @@ class Hierarchy:
                                    _ptr(nz, C.c_int64)))
         return {"max_abs": ma, "norm2": n2, "nnz": nz}
 
-    def solve(self, b, x, stream=None, **params) -> dict:
-        """namg_solve on device tensors b (read) and x (initial guess in, solution out)."""
+    def solve(self, b, x, stream=None, history=False, **params) -> dict:
+        """namg_solve on device tensors b (read) and x (initial guess in, solution out). history=True also
+        returns the residual estimate after every iteration ("hist")."""
         p = solve_params(**params)
+        hist = None
+        if history:
+            hist = np.zeros(max(p.max_iters, 1))
+            p.res_hist = _ptr(hist, C.c_double)
+            p.res_hist_cap = hist.size
         st = SolveStats()
         code = _check(_lib.namg_solve(self.h, _dev_ptr(b, self.n), _dev_ptr(x, self.n), C.byref(p), _stream(stream),
                                       C.byref(st)))
         out = st.as_dict()
         out["status"] = code
+        if history:
+            out["hist"] = hist[: st.iters].copy()
         return out
 
     def vcycle(self, b, x, stream=None, **params):
@@ -360,15 +371,22 @@ class Server:
     def clock(self) -> float:
         return _lib.namg_server_clock(self.h)
 
-    def submit(self, A, b, **setup) -> int:
+    def submit(self, A, b, solve=None, **setup) -> int:
+        """Queue A x = b with setup parameters `setup`; `solve` (a dict of solve parameters) replaces the
+        server's default solve parameters for this request."""
         rp = np.ascontiguousarray(A.rowptr, dtype=np.int32)
         ci = np.ascontiguousarray(A.colind, dtype=np.int32)
         v = np.ascontiguousarray(A.vals, dtype=np.float64)
         bb = np.ascontiguousarray(b, dtype=np.float64)
         sp = setup_params(**setup)
+        sv = None
+        if solve is not None:
+            sv = SolveParams.from_buffer_copy(self.params.solve)
+            _set_fields(sv, solve)
         t = C.c_uint64()
         _check(_lib.namg_server_submit(self.h, int(A.n), _ptr(rp, C.c_int32), _ptr(ci, C.c_int32), _ptr(v, C.c_double),
-                                       _ptr(bb, C.c_double), C.byref(sp), C.byref(t)))
+                                       _ptr(bb, C.c_double), C.byref(sp), C.byref(sv) if sv is not None else None,
+                                       C.byref(t)))
         self._sizes[t.value] = int(A.n)
         return t.value
 

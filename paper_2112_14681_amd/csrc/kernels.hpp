@@ -856,12 +856,13 @@ struct KTask {
   KState *ks;
   int64_t ldv, ldz;
   int32_t n, i, ncols, has_w, last, k, nblk, rows_per_blk;
-  double beta, denom;
+  int32_t t_mode, pad;  // the solve's correction T (see step_body)
+  double beta, denom, tol;
 };
 
 template <int OP, class T>
 __global__ __launch_bounds__(BLK) void kb_krylov(const KTask<T> *__restrict__ tasks, const uint32_t *__restrict__ off,
-                                                 int ntasks, int32_t t_mode, double tol) {
+                                                 int ntasks) {
   uint32_t lb;
   const KTask<T> &t = tasks[find_task(off, ntasks, lb)];
   if constexpr (OP == KOP_RESIDUAL64) residual64_body(lb, t.A, t.b, t.x, t.V, t.vlow, t.partial);
@@ -871,9 +872,9 @@ __global__ __launch_bounds__(BLK) void kb_krylov(const KTask<T> *__restrict__ ta
     multidot_body<8>(lb, t.V, t.ldv, t.ncols, t.has_w ? t.w : (const double *)nullptr, t.n, t.rows_per_blk, t.partial,
                      t.nblk);
   if constexpr (OP == KOP_COLREDUCE) colreduce_body(lb, t.partial, t.nblk, t.cd);
-  if constexpr (OP == KOP_STEP) step_body(t.ks, t.cd, t.i, t_mode);
+  if constexpr (OP == KOP_STEP) step_body(t.ks, t.cd, t.i, t.t_mode);
   if constexpr (OP == KOP_PROJECT) project_body(lb, t.V, t.ldv, t.i, t.w, t.ks, t.n, t.vlow, t.partial);
-  if constexpr (OP == KOP_FINISH) finish_body(t.ks, t.partial, t.nblk, t.i, t.last, tol, t.beta, t.denom, t.host_out);
+  if constexpr (OP == KOP_FINISH) finish_body(t.ks, t.partial, t.nblk, t.i, t.last, t.tol, t.beta, t.denom, t.host_out);
   if constexpr (OP == KOP_BACKSOLVE) backsolve_body(t.ks, t.k);
   if constexpr (OP == KOP_UPDATE) update_x_body(lb, (const T *)t.Z, t.ldz, t.k, t.ks, t.x, t.n);
   if constexpr (OP == KOP_REDUCE) reduce_body(t.partial, t.nblk, t.host_out);

@@ -156,9 +156,11 @@ class BatchEngine {
     int iters = 0, cycles = 0, apps = 0;
     int status = NAMG_PENDING;
     std::string err;
+    namg_solve_params p{};  // this solve's parameters
+    CycleOpts o{};          // and its V-cycle options
   };
 
-  BatchEngine(int device, const namg_solve_params &p) : dev_(device), p_(p), o_(cycle_opts(p)) {
+  explicit BatchEngine(int device) : dev_(device) {
     DeviceGuard g(dev_);
     hip_check(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking), "hipStreamCreateWithFlags");
   }
@@ -267,12 +269,13 @@ class BatchEngine {
       add_krylov(KOP_SUMSQ, t, nb);
       add_krylov(KOP_REDUCE, t, ones);
     }
-    if (!resid.empty() && p_.stop_rule == NAMG_STOP_NRBE) {
+    if (!resid.empty()) {
       // ||x||^2 at the cycle's start for the backward-error denominator, before the residual pass
       // reuses the same partial-sum buffer
       std::vector<KTask<T>> t;
       std::vector<unsigned> nb, ones;
       for (Slot *sl : resid) {
+        if (sl->p.stop_rule != NAMG_STOP_NRBE) continue;
         KTask<T> k = base(sl);
         k.partial = sl->sv->red_.get();
         k.nblk = sl->sv->nblk_red_;
@@ -375,6 +378,8 @@ class BatchEngine {
     k.rows_per_blk = v.rows_per_dot_;
     k.beta = sl->beta;
     k.denom = sl->denom;
+    k.tol = sl->p.tol;
+    k.t_mode = t_mode(sl->p);
     return k;
   }
 
@@ -392,11 +397,11 @@ class BatchEngine {
       return;
     }
     sl->denom = sl->beta;
-    if (p_.stop_rule == NAMG_STOP_NRBE) sl->denom += sl->sv->anorm_inf_ * std::sqrt(sl->sv->pinned_[4]);
-    if (sl->rn / sl->denom <= p_.tol) {
+    if (sl->p.stop_rule == NAMG_STOP_NRBE) sl->denom += sl->sv->anorm_inf_ * std::sqrt(sl->sv->pinned_[4]);
+    if (sl->rn / sl->denom <= sl->p.tol) {
       sl->status = NAMG_OK;
       sl->phase = DONE;
-    } else if (sl->iters >= p_.max_iters) {
+    } else if (sl->iters >= sl->p.max_iters) {
       sl->status = NAMG_NOT_CONVERGED;
       sl->phase = DONE;
     } else {
@@ -404,7 +409,7 @@ class BatchEngine {
       sl->phase = STEP;
       sl->i = 0;
       sl->k = 0;
-      sl->me = std::min(p_.restart, p_.max_iters - sl->iters);
+      sl->me = std::min(sl->p.restart, sl->p.max_iters - sl->iters);
     }
   }
 
@@ -458,9 +463,9 @@ class BatchEngine {
       auto xl = [&](int l) -> T * { return l == 0 ? x0 : v.lv_[l].x.get(); };
       for (int l = 0; l + 1 < r.L; ++l) {
         v.record_ = &r.down[l];
-        v.level_down(l, bl(l), xl(l), o_, s_);
+        v.level_down(l, bl(l), xl(l), sl->o, s_);
         v.record_ = &r.up[l];
-        v.level_up(l, bl(l), xl(l), o_, s_);
+        v.level_up(l, bl(l), xl(l), sl->o, s_);
       }
       v.record_ = &r.coarse;
       v.coarse_solve(r.L - 1, bl(r.L - 1), xl(r.L - 1), s_);
@@ -507,7 +512,7 @@ class BatchEngine {
   }
 
   using RowKernel = void (*)(const RowTask<T> *, const uint32_t *, int);
-  using KKernel = void (*)(const KTask<T> *, const uint32_t *, int, int32_t, double);
+  using KKernel = void (*)(const KTask<T> *, const uint32_t *, int);
 
   template <int OP>
   static RowKernel row_kernel(int g) {
@@ -563,12 +568,11 @@ class BatchEngine {
     }
     std::memcpy(pinned_, stage_.data(), bytes);
     hip_check(hipMemcpyAsync(dbuf_, pinned_, bytes, hipMemcpyHostToDevice, s_), "hipMemcpyAsync");
-    const int32_t tm = t_mode(p_);
     for (const Group &gr : groups_) {
       const uint32_t *off = reinterpret_cast<const uint32_t *>(dbuf_ + gr.off_off);
       if (gr.krylov) {
         const KTask<T> *tasks = reinterpret_cast<const KTask<T> *>(dbuf_ + gr.task_off);
-        hipLaunchKernelGGL(krylov_kernel(gr.op), dim3(gr.grid), dim3(BLK), 0, s_, tasks, off, gr.ntasks, tm, p_.tol);
+        hipLaunchKernelGGL(krylov_kernel(gr.op), dim3(gr.grid), dim3(BLK), 0, s_, tasks, off, gr.ntasks);
       } else {
         const RowTask<T> *tasks = reinterpret_cast<const RowTask<T> *>(dbuf_ + gr.task_off);
         hipLaunchKernelGGL(row_kernel(gr.op, gr.g), dim3(gr.grid), dim3(BLK), 0, s_, tasks, off, gr.ntasks);
@@ -582,8 +586,6 @@ class BatchEngine {
   }
 
   int dev_;
-  namg_solve_params p_;
-  CycleOpts o_;
   hipStream_t s_ = nullptr;
   double sync_s_ = 0.0;
   std::vector<char> stage_;
@@ -596,7 +598,7 @@ class BatchEngine {
 class ServerBase {
  public:
   virtual ~ServerBase() = default;
-  virtual uint64_t submit(HostCsr &&A, const double *b, const namg_setup_params &sp) = 0;
+  virtual uint64_t submit(HostCsr &&A, const double *b, const namg_setup_params &sp, const namg_solve_params &p) = 0;
   virtual int poll(uint64_t ticket, bool wait, double *x, namg_solve_stats *st, namg_request_times *tm) = 0;
   virtual namg_server_counters stats() = 0;
   virtual double clock() const = 0;
@@ -610,6 +612,7 @@ class Server final : public ServerBase {
     HostCsr A;
     std::vector<double> b;
     namg_setup_params sp{};
+    namg_solve_params p{};
     std::unique_ptr<HostHierarchy> H;
     std::unique_ptr<Solver<T>> sv;
     DevBuf<double> bd, xd;
@@ -625,7 +628,7 @@ class Server final : public ServerBase {
   };
 
  public:
-  explicit Server(const namg_server_params &p) : p_(p), t0_(std::chrono::steady_clock::now()), eng_(p.device, p.solve) {
+  explicit Server(const namg_server_params &p) : p_(p), t0_(std::chrono::steady_clock::now()), eng_(p.device) {
     for (int q = 0; q < p_.setup_threads; ++q) setup_.emplace_back([this] { setup_loop(); });
     sched_ = std::thread([this] { sched_loop(); });
     finisher_ = std::thread([this] { finish_loop(); });
@@ -656,11 +659,12 @@ class Server final : public ServerBase {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0_).count();
   }
 
-  uint64_t submit(HostCsr &&A, const double *b, const namg_setup_params &sp) override {
+  uint64_t submit(HostCsr &&A, const double *b, const namg_setup_params &sp, const namg_solve_params &p) override {
     auto r = std::make_unique<Req>();
     r->b.assign(b, b + A.nr);
     r->A = std::move(A);
     r->sp = sp;
+    r->p = p;
     r->tm.submit = clock();
     std::lock_guard<std::mutex> lk(mu_);
     r->ticket = next_++;
@@ -732,7 +736,7 @@ class Server final : public ServerBase {
       try {
         if (r->sp.coarsen == NAMG_COARSEN_PMIS) r->sp.device = p_.device;  // device setup on the server's GPU
         r->H = std::make_unique<HostHierarchy>(build_hierarchy(std::move(r->A), r->sp));
-        r->footprint = solver_footprint<T>(*r->H, p_.solve.restart) + 16 * (int64_t)r->H->lv[0].A.nr;
+        r->footprint = solver_footprint<T>(*r->H, r->p.restart) + 16 * (int64_t)r->H->lv[0].A.nr;
         r->A = HostCsr{};
       } catch (const SetupError &e) {
         std::lock_guard<std::mutex> lk(mu_);
@@ -779,7 +783,7 @@ class Server final : public ServerBase {
         const int32_t n = r->H->lv[0].A.nr;
         r->sv = std::make_unique<Solver<T>>(*r->H, p_.device);
         r->H->device_levels.reset();  // packed into the solver's layouts; the blocks go back to the cache
-        r->sv->reserve_workspace(p_.solve.restart);
+        r->sv->reserve_workspace(r->p.restart);
         if (r->sv->device_bytes() + 16 * (int64_t)n != r->footprint) {
           std::lock_guard<std::mutex> lk(mu_);
           footprint_mismatches_++;
@@ -790,6 +794,8 @@ class Server final : public ServerBase {
         r->xd.alloc(n, nullptr);
         r->xd.upload(zero.data(), n);
         r->slot.sv = r->sv.get();
+        r->slot.p = r->p;
+        r->slot.o = cycle_opts(r->p);
         r->slot.b = r->bd.get();
         r->slot.x = r->xd.get();
         r->slot.n = n;
@@ -847,6 +853,7 @@ class Server final : public ServerBase {
     r->st.nrbe = sl.beta > 0.0 ? sl.rn / (sl.beta + r->H->anorm_inf * xn) : 0.0;
     r->st.ms_total = (clock() - r->tm.admitted) * 1e3;
     r->st.alg_bytes = sl.alg;
+    r->st.loss_orth = r->st.ms_vcycle = r->st.ms_spmv = r->st.ms_ortho = std::nan("");
     r->status = sl.status;
     r->err = sl.err;
     r->sv.reset();

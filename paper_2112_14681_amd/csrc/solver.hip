@@ -68,6 +68,20 @@ void validate_solve_params(const namg_solve_params &p) {
   if (p.t_degree < 1 || p.t_degree > NAMG_MAX_RESTART) throw SetupError{NAMG_E_INVALID, "t_degree out of range"};
   if (p.stop_rule != NAMG_STOP_RELRES && p.stop_rule != NAMG_STOP_NRBE)
     throw SetupError{NAMG_E_INVALID, "unknown stop_rule"};
+  if (p.diagnostics & ~(NAMG_DIAG_LOSS_ORTH | NAMG_DIAG_PHASE_TIMES))
+    throw SetupError{NAMG_E_INVALID, "unknown diagnostics flag"};
+  if (p.res_hist_cap < 0 || (p.res_hist_cap > 0 && !p.res_hist))
+    throw SetupError{NAMG_E_INVALID, "res_hist_cap > 0 needs a res_hist array"};
+}
+
+// A served request's solve parameters: batched launches cover the Neumann smoothers only, and a request
+// keeps no pointer into the caller's memory and reports no diagnostics.
+void validate_served_params(const namg_solve_params &p) {
+  validate_solve_params(p);
+  if (p.tri_mode != NAMG_TRI_NEUMANN)
+    throw SetupError{NAMG_E_INVALID, "serving batches the Neumann smoothers only (tri_mode must be NEUMANN)"};
+  if (p.diagnostics != 0 || p.res_hist || p.res_hist_cap != 0)
+    throw SetupError{NAMG_E_INVALID, "served requests take no diagnostics and no residual history"};
 }
 
 // One function pointer per lanes-per-row group for every row kernel.
@@ -222,6 +236,9 @@ class Solver final : public SolverBase {
       (void)hipEventDestroy(e.first);
       (void)hipEventDestroy(e.second);
     }
+    for (hipEvent_t e : phase_ev_) (void)hipEventDestroy(e);
+    if (wall_ev_[0]) (void)hipEventDestroy(wall_ev_[0]);
+    if (wall_ev_[1]) (void)hipEventDestroy(wall_ev_[1]);
     if (pinned_) (void)hipHostFree(pinned_);
   }
 
@@ -344,13 +361,19 @@ class Solver final : public SolverBase {
     const int m = p.restart;
     ensure_workspace(m);
     alg_ = 0.0;
-    hipEvent_t e0, e1;
-    hip_check(hipEventCreate(&e0), "hipEventCreate");
-    hip_check(hipEventCreate(&e1), "hipEventCreate");
-    hip_check(hipEventRecord(e0, s), "hipEventRecord");
+    if (!wall_ev_[0]) {
+      hip_check(hipEventCreate(&wall_ev_[0]), "hipEventCreate");
+      hip_check(hipEventCreate(&wall_ev_[1]), "hipEventCreate");
+    }
+    hip_check(hipEventRecord(wall_ev_[0], s), "hipEventRecord");
     const CycleOpts o = cycle_opts(p);
     if (o.tri_mode == NAMG_TRI_DIRECT) ensure_direct();
     const bool trace = std::getenv("NAMG_TRACE") != nullptr;
+    const bool timing = (p.diagnostics & NAMG_DIAG_PHASE_TIMES) != 0;
+    const bool orth = (p.diagnostics & NAMG_DIAG_LOSS_ORTH) != 0;
+    phase_used_ = 0;
+    std::vector<size_t> marks;  // four phase events per Arnoldi step (before the V-cycle, after it, after
+                                // the product, after the column completion)
     KState *ks = kst_.get();
     double *cd = cd_.get();
     double *V = V_.get();
@@ -361,6 +384,8 @@ class Solver final : public SolverBase {
 
     const double beta = std::sqrt(norm2sq(b, n, s));
     namg_solve_stats st{};
+    st.loss_orth = st.ms_vcycle = st.ms_spmv = st.ms_ortho = std::nan("");
+    if (orth) st.loss_orth = 0.0;
     int status = NAMG_OK;
     double rn = 0.0;
     if (!std::isfinite(beta)) throw SetupError{NAMG_E_NONFINITE, "non-finite right-hand side"};
@@ -399,11 +424,14 @@ class Solver final : public SolverBase {
             b0 = vi;
           else
             b0 = vin;
+          if (timing) marks.push_back(phase_mark(s));
           vcycle(0, b0, zi, o, s);
           st.precond_apps++;
+          if (timing) marks.push_back(phase_mark(s));
           launch(NAMG_KF_GMRES_SPMV, 0, A64_.bytes() + (S + 8.0) * n, sel_spmv<double, double, T, double>(1),
                  rows_grid(A64_), s, NAMG_HEAD_ARGS(M64), (const T *)zi, (const double *)nullptr, w, (double *)nullptr,
                  M64.mul);
+          if (timing) marks.push_back(phase_mark(s));
           const int32_t ncols = i + 1;
           launch(NAMG_KF_MULTIDOT, 0, 8.0 * n * (ncols + 1), &k_multidot<8>, nblk_dot_, s, (const double *)V, ldv_,
                  ncols, (const double *)w, n, rows_per_dot_, dot_.get(), nblk_dot_);
@@ -414,10 +442,12 @@ class Solver final : public SolverBase {
           // column i is complete once ||v_{i+2}|| is known: estimate and stop test before the next V-cycle
           launch_small(&k_finish, s, ks, (const double *)red_.get(), nblk_red_, i + 1, (int)(i + 1 == me), p.tol, beta,
                        denom, pinned_dev_);
+          if (timing) marks.push_back(phase_mark(s));
           hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
           const double est = pinned_[0];
           const int flag = (int)pinned_[1];
           if (flag < 0) throw SetupError{NAMG_E_NONFINITE, "non-finite value in the Arnoldi step"};
+          if (st.iters < p.res_hist_cap) p.res_hist[st.iters] = est;
           st.iters++;
           st.relres_est = est;
           if (trace) std::fprintf(stderr, "[namg]   iter %d est %.3e\n", st.iters, est);
@@ -426,18 +456,30 @@ class Solver final : public SolverBase {
             break;
           }
         }
+        if (orth) st.loss_orth = std::max(st.loss_orth, loss_of_orthogonality(k, s));
         launch_small(&k_backsolve, s, ks, k);
         launch(-1, 0, (double)n * (S * k + 16.0), &k_update_x<T>, blocks_for(n), s, (const T *)Z, ldz_, k,
                (const KState *)ks, x, n);
       }
     }
     const double xn = std::sqrt(norm2sq(x, n, s));
-    hip_check(hipEventRecord(e1, s), "hipEventRecord");
-    hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+    hip_check(hipEventRecord(wall_ev_[1], s), "hipEventRecord");
+    hip_check(hipEventSynchronize(wall_ev_[1]), "hipEventSynchronize");
     float ms = 0.f;
-    hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    hip_check(hipEventElapsedTime(&ms, wall_ev_[0], wall_ev_[1]), "hipEventElapsedTime");
+    if (timing) {
+      st.ms_vcycle = st.ms_spmv = st.ms_ortho = 0.0;
+      for (size_t q = 0; q + 3 < marks.size(); q += 4) {
+        const double tv = phase_ms(marks[q], marks[q + 1]), tm = phase_ms(marks[q + 1], marks[q + 2]),
+                     to = phase_ms(marks[q + 2], marks[q + 3]);
+        st.ms_vcycle += tv;
+        st.ms_spmv += tm;
+        st.ms_ortho += to;
+        if (trace)
+          std::fprintf(stderr, "[namg]   iter %zu: V-cycle %.3f ms, A z %.3f ms, orthogonalisation %.3f ms\n", q / 4 + 1,
+                       tv, tm, to);
+      }
+    }
     st.status = status;
     st.relres_true = beta > 0.0 ? rn / beta : 0.0;
     st.nrbe = (beta > 0.0) ? rn / (beta + anorm_inf_ * xn) : 0.0;
@@ -517,6 +559,58 @@ class Solver final : public SolverBase {
       prof_.total_ms += ms;
     }
     ev_used_ = 0;
+  }
+
+  // Record the next phase event of the pool on stream s; returns its index.
+  size_t phase_mark(hipStream_t s) {
+    end_run();
+    if (phase_used_ == phase_ev_.size()) {
+      hipEvent_t e;
+      hip_check(hipEventCreate(&e), "hipEventCreate");
+      phase_ev_.push_back(e);
+    }
+    hip_check(hipEventRecord(phase_ev_[phase_used_], s), "hipEventRecord");
+    return phase_used_++;
+  }
+
+  double phase_ms(size_t a, size_t b) {
+    hip_check(hipEventSynchronize(phase_ev_[b]), "hipEventSynchronize");
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, phase_ev_[a], phase_ev_[b]), "hipEventElapsedTime");
+    return ms;
+  }
+
+  // ||I - G||_F for the Gram matrix G of the cycle's basis V_{k+1} (Section 3's loss of orthogonality): column
+  // j's inner products with columns 0..j come from the fused reduction with ncols = j + 1 and no w. Columns
+  // 0..k-1 are normalised; column k (v_{k+1}, lagged) is scaled by its own reduced norm.
+  double loss_of_orthogonality(int k, hipStream_t s) {
+    const int32_t n = lv_[0].n;
+    const int ld = ws_m_ + 2;
+    if (gram_.size() < (size_t)ld * ld) gram_.alloc((size_t)ld * ld, &mc_);
+    for (int j = 0; j <= k; ++j) {
+      launch(-1, 0, 8.0 * n * (j + 1), &k_multidot<8>, nblk_dot_, s, (const double *)V_.get(), ldv_, (int32_t)(j + 1),
+             (const double *)nullptr, n, rows_per_dot_, dot_.get(), nblk_dot_);
+      launch(-1, 0, 0.0, &k_colreduce, (unsigned)(j + 1), s, (const double *)dot_.get(), nblk_dot_,
+             gram_.get() + (int64_t)j * ld);
+    }
+    std::vector<double> G((size_t)ld * ld);
+    hip_check(hipMemcpyAsync(G.data(), gram_.get(), sizeof(double) * ld * (k + 1), hipMemcpyDeviceToHost, s), "D2H");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    auto g = [&](int j, int i) -> double & { return G[(size_t)j * ld + i]; };  // i <= j
+    int cols = k + 1;
+    if (g(k, k) > 0.0) {
+      const double sc = 1.0 / std::sqrt(g(k, k));
+      for (int i = 0; i < k; ++i) g(k, i) *= sc;
+      g(k, k) *= sc * sc;
+    } else {
+      cols = k;  // lucky breakdown: v_{k+1} = 0
+    }
+    double acc = 0.0;
+    for (int j = 0; j < cols; ++j) {
+      acc += (1.0 - g(j, j)) * (1.0 - g(j, j));
+      for (int i = 0; i < j; ++i) acc += 2.0 * g(j, i) * g(j, i);
+    }
+    return std::sqrt(acc);
   }
 
   void upload_vec(DevBuf<T> &d, const std::vector<double> &h) {
@@ -881,7 +975,7 @@ class Solver final : public SolverBase {
   int32_t nc_ = 0;
   DMat<double> A64_;
   double anorm_inf_ = 0.0;
-  DevBuf<double> red_, V_, w_, dot_, cd_;
+  DevBuf<double> red_, V_, w_, dot_, cd_, gram_;
   DevBuf<T> Z_, vin_;
   DevBuf<KState> kst_;
   int ws_m_ = 0;
@@ -897,6 +991,9 @@ class Solver final : public SolverBase {
   namg_kernel_profile prof_{0, 0.0, 0.0};
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events_;
   size_t ev_used_ = 0;
+  std::vector<hipEvent_t> phase_ev_;  // phase timing (NAMG_DIAG_PHASE_TIMES), reused across solves
+  size_t phase_used_ = 0;
+  hipEvent_t wall_ev_[2] = {nullptr, nullptr};  // ms_total of every solve, created on the first one
 };
 
 }  // namespace namg
@@ -971,6 +1068,9 @@ void namg_default_solve_params(namg_solve_params *p) {
   p->post_sweeps = 1;
   p->t_degree = 1;
   p->stop_rule = NAMG_STOP_RELRES;
+  p->diagnostics = 0;
+  p->res_hist = nullptr;
+  p->res_hist_cap = 0;
 }
 
 int namg_setup(int32_t n, const int32_t *rowptr, const int32_t *colind, const double *vals,
@@ -1171,6 +1271,7 @@ const char *namg_last_error(void) { return namg::g_last_error.c_str(); }
 
 struct namg_server {
   std::unique_ptr<namg::ServerBase> impl;
+  namg_solve_params solve;  // the requests' default solve parameters
 };
 
 void namg_default_server_params(namg_server_params *p) {
@@ -1187,9 +1288,7 @@ int namg_server_create(const namg_server_params *p, namg_server **out) {
   return guarded([&]() -> int {
     if (!p || !out) throw namg::SetupError{NAMG_E_INVALID, "null argument"};
     *out = nullptr;
-    namg::validate_solve_params(p->solve);
-    if (p->solve.tri_mode != NAMG_TRI_NEUMANN)
-      throw namg::SetupError{NAMG_E_INVALID, "serving batches the Neumann smoothers only (tri_mode must be NEUMANN)"};
+    namg::validate_served_params(p->solve);
     if (p->max_inflight < 1 || p->max_inflight > namg::MAX_BATCH)
       throw namg::SetupError{NAMG_E_INVALID, "max_inflight out of range"};
     if (p->setup_threads < 1) throw namg::SetupError{NAMG_E_INVALID, "setup_threads must be >= 1"};
@@ -1207,6 +1306,7 @@ int namg_server_create(const namg_server_params *p, namg_server **out) {
       if (q.hbm_budget <= 0) q.hbm_budget = (int64_t)total_b / 2;
     }
     auto s = std::make_unique<namg_server>();
+    s->solve = q.solve;
     if (q.precision == NAMG_FP64)
       s->impl = std::make_unique<namg::Server<double>>(q);
     else
@@ -1217,10 +1317,12 @@ int namg_server_create(const namg_server_params *p, namg_server **out) {
 }
 
 int namg_server_submit(namg_server *s, int32_t n, const int32_t *rowptr, const int32_t *colind, const double *vals,
-                       const double *b, const namg_setup_params *sp, uint64_t *ticket) {
+                       const double *b, const namg_setup_params *sp, const namg_solve_params *p, uint64_t *ticket) {
   return guarded([&]() -> int {
     if (!s || !b || !sp || !ticket) throw namg::SetupError{NAMG_E_INVALID, "null argument"};
-    *ticket = s->impl->submit(namg::import_csr(n, rowptr, colind, vals), b, *sp);
+    const namg_solve_params q = p ? *p : s->solve;
+    namg::validate_served_params(q);
+    *ticket = s->impl->submit(namg::import_csr(n, rowptr, colind, vals), b, *sp, q);
     return NAMG_OK;
   });
 }

@@ -1,7 +1,10 @@
 """Write the full-size golden files: the CPU oracle's solves at the sizes the GPU tests check.
 
-    python tests/golden/make_golden.py c2   ->  c2_128_fp64_ilu0_t3.json   (about a minute)
-    python tests/golden/make_golden.py c3   ->  c3_192_fp64_pgs_t2.json    (a few minutes)
+    python tests/golden/make_golden.py c2    ->  c2_128_fp64_ilu0_t3.json        (about a minute)
+    python tests/golden/make_golden.py c3    ->  c3_192_fp64_pgs_t2.json         (a few minutes)
+    python tests/golden/make_golden.py c4n   ->  c4n_128_fp64_ilu0_t3_m50.json   (about a minute each)
+    python tests/golden/make_golden.py c4r   ->  c4r_128_fp64_ilu0_t3_m50.json
+    python tests/golden/make_golden.py c4rcm ->  c4rcm_128_fp64_ilu0_t3_m50.json
 
 Both use the benchmark's launch configuration: RS-AMG theta = 0.25 coarsened to <= 1000 rows (a dense
 direct solve on the coarsest level).
@@ -10,6 +13,10 @@ with 3 Neumann terms, low-sync MGS-GMRES(30) with T = I - L, tol 1e-8, FP64.
 c3: -div(k grad p), cell-centred, N = 192 (7 077 888 rows), lognormal k (sigma 1, seed 2), z spacing
 stretched 1:100; polynomial GS with 2 Neumann terms on every level, GMRES(30), tol 1e-8, FP64 (the
 reference for both the FP64 and the FP32-preconditioned GPU solves).
+c4n / c4r / c4rcm: first-order upwind convection-diffusion, N = 128, Peclet 10 (seed 3), in natural order,
+a random symmetric relabelling and reverse Cuthill-McKee of that; hybrid V-cycle with ILU(0) on level 0
+and 3 Neumann terms, GMRES(50), tol 1e-8, FP64 (the reference for the FP64 and FP32-preconditioned
+GPU solves). The orderings of Section 5.3.3.
 
 Calls only oracle/ (and the seeded generator). Stored: level sizes and a SHA-256 of every level's C/F
 array, the iteration count, the per-iteration residual estimates, the true relative residual, the max
@@ -39,6 +46,10 @@ CONFIGS = {
                desc={"workload": "3-D -div(k grad p), lognormal k sigma 1, z 1:100", "k_seed": 2,
                      "smoother": "polynomial GS", "inner_terms": 2}),
 }
+for _o, _d in (("c4n", "natural"), ("c4r", "random symmetric relabelling"), ("c4rcm", "RCM of the random order")):
+    CONFIGS[_o] = dict(file=f"{_o}_128_fp64_ilu0_t3_m50.json", smoother="ILU0", t=3, ilu_levels=1, restart=50,
+                       desc={"workload": f"3-D upwind convection-diffusion, Peclet 10, {_d}", "seed": 3,
+                             "smoother": "ILU0 hybrid", "inner_terms": 3})
 
 
 def main():
@@ -57,14 +68,15 @@ def main():
             entry["n_coarse"] = int(L.cf.sum())
         levels.append(entry)
     smoother = oracle.SMOOTH_ILU0 if cfg["smoother"] == "ILU0" else oracle.SMOOTH_PGS
-    r = H.solve(b, tol=1e-8, restart=30, smoother=smoother, tri_mode=oracle.TRI_NEUMANN, t=cfg["t"],
+    restart = cfg.get("restart", 30)
+    r = H.solve(b, tol=1e-8, restart=restart, smoother=smoother, tri_mode=oracle.TRI_NEUMANN, t=cfg["t"],
                 gmres_T=oracle.T_NEUMANN)
     t2 = time.time()
     x = r["x"]
     idx = np.sort(np.random.default_rng(2024).choice(A.n, 4096, replace=False))
     out = {
         "source": f"oracle/ (CPU FP64), written by tests/golden/make_golden.py {name}",
-        "config": dict(cfg["desc"], N=meta["N"], theta=0.25, max_coarse=MAX_COARSE, restart=30, gmres_T="I-L",
+        "config": dict(cfg["desc"], N=meta["N"], theta=0.25, max_coarse=MAX_COARSE, restart=restart, gmres_T="I-L",
                        tol=1e-8),
         "levels": levels,
         "iters": r["iters"],

@@ -1,11 +1,12 @@
 """GPU parity: the HIP library against the CPU oracle on the same seeded inputs.
 
 Component operators, single smoothing sweeps and whole V-cycles in FP64 must agree with the oracle to
-1e-12 relative (max-norm); whole FP64 solves take the same number of iterations and agree to 1e-10 in x
-(the iterate of a converged solve amplifies the ~1e-16 rounding difference of single operations by the
-conditioning of the Krylov least-squares problem; the measured gap is reported in the design notes).
-FP32-preconditioned solves must reach the same 1e-8 relative residual (checked with an independent
-FP64 SpMV) with an error against the FP64 oracle solution consistent with that residual.
+1e-12 relative (max-norm). Whole FP64 solves take the same number of iterations, their iterates agree
+to 1e-12 relative (max-norm over x, relative to max|x|) and their residual estimates after every
+iteration agree to 1e-12 relative, value by value. Every measured gap is printed on a line starting
+with PARITY-GAP. FP32-preconditioned solves must reach the same 1e-8 relative residual (checked with
+an independent FP64 SpMV) with an error against the FP64 oracle solution consistent with that
+residual.
 """
 import numpy as np
 import pytest
@@ -177,18 +178,30 @@ def test_vcycle_matches_oracle(namg, smoother, tri, t):
 
 
 # ----------------------------------------------------------------------------------------- solves
-def _check_solve(namg, A, b, H, G, x0=None, xtol=1e-10, **kw):
+def hist_gap(a, b):
+    """Largest relative difference between two residual histories, value by value."""
+    a, b = np.asarray(a), np.asarray(b)
+    assert a.shape == b.shape, (a.shape, b.shape)
+    if a.size == 0:
+        return 0.0
+    return float((np.abs(a - b) / np.maximum(np.abs(b), 1e-300)).max())
+
+
+def _check_solve(namg, A, b, H, G, x0=None, xtol=TOL64, htol=TOL64, label="", **kw):
     okw = dict(tol=kw.get("tol", 1e-8), restart=kw.get("restart", 30), max_iters=kw.get("max_iters", 1000),
                smoother=kw.get("smoother", 0), tri_mode=kw.get("tri_mode", 0), t=kw.get("inner_terms", 2),
                gmres_T=kw.get("gmres_T", 0), t_degree=kw.get("t_degree", 1),
                stop_rule=kw.get("stop_rule", O.STOP_RELRES))
     ref = G.solve(b, x0, **okw)
     xt = dev(np.zeros(A.n) if x0 is None else x0)
-    st = H.solve(dev(b), xt, **kw)
+    st = H.solve(dev(b), xt, history=True, **kw)
     x = host(xt)
+    gx, gh = relerr(x, ref["x"]), hist_gap(st["hist"], ref["hist"])
+    print(f"PARITY-GAP {label or 'solve'} n={A.n} {kw} iters={st['iters']} x={gx:.2e} hist={gh:.2e}")
     assert st["iters"] == ref["iters"], (st["iters"], ref["iters"])
     assert st["status"] == ref["status"]
-    assert relerr(x, ref["x"]) <= xtol, relerr(x, ref["x"])
+    assert gx <= xtol, gx
+    assert gh <= htol, gh
     res = np.linalg.norm(b - O.spmv(A, x)) / np.linalg.norm(b)
     if st["status"] == namg.OK and kw.get("stop_rule", namg.STOP_RELRES) == namg.STOP_RELRES:
         assert res <= kw.get("tol", 1e-8)
@@ -221,7 +234,7 @@ def test_solve_t_degree_parity(namg, t_degree):
     r = srv.wait(srv.submit(A, b))
     srv.close()
     ref = O.Hierarchy(A).solve(b, t=2, t_degree=t_degree)
-    assert r["iters"] == ref["iters"] and relerr(r["x"], ref["x"]) <= 1e-10
+    assert r["iters"] == ref["iters"] and relerr(r["x"], ref["x"]) <= TOL64
 
 
 def test_nrbe_stopping_rule_parity(namg):
@@ -244,7 +257,7 @@ def test_nrbe_stopping_rule_parity(namg):
     srv = namg.Server(solve=dict(kw, stop_rule=namg.STOP_NRBE), max_inflight=2, setup_threads=1, precision=0)
     r = srv.wait(srv.submit(A, b))
     srv.close()
-    assert r["iters"] == ref["iters"] and relerr(r["x"], ref["x"]) <= 1e-10
+    assert r["iters"] == ref["iters"] and relerr(r["x"], ref["x"]) <= TOL64
 
 
 @pytest.mark.parametrize("tri", [0, 1])
@@ -260,7 +273,7 @@ def test_ilut_sweeps_vcycle_and_solves(namg, droptol, lfil):
     """ILUT(droptol, lfil) factors (Algorithm 2 with row scaling) in place of ILU(0): single sweeps on the
     two finest levels (Neumann t = 1, 2, 3, 5 and direct substitution) match the oracle's ILUT sweep on
     the same level operator to 1e-12; the hybrid solve (ILUT on the finest level, polynomial GS below;
-    Neumann t = 3 and direct) takes the oracle's iterations with x within 1e-10. lfil = 0 leaves both
+    Neumann t = 3 and direct) takes the oracle's iterations with x within 1e-12. lfil = 0 leaves both
     strict triangles empty (the sweep is a Jacobi step)."""
     A, b, _ = config_system("c2", 23)
     setup = dict(ilu_kind=namg.ILUT, ilut_droptol=droptol, ilut_lfil=lfil)
@@ -299,12 +312,12 @@ def test_ilut_fp32_and_server(namg):
     srv = namg.Server(solve=dict(smoother=1, inner_terms=3), max_inflight=2, setup_threads=1, precision=0)
     r = srv.wait(srv.submit(A, b, **setup))
     srv.close()
-    assert r["status"] == namg.OK and r["iters"] == ref["iters"] and relerr(r["x"], ref["x"]) <= 1e-10
+    assert r["status"] == namg.OK and r["iters"] == ref["iters"] and relerr(r["x"], ref["x"]) <= TOL64
 
 
 def test_aggressive_coarsening_parity(namg):
     """Aggressive (A-1) coarsening on the first two levels (P = P_1 P_2, denser rows in P and R): V-cycle to
-    1e-12 and solves with the oracle's iterations and x within 1e-10, on C2 at 24^3 (ILU(0) hybrid) and
+    1e-12 and solves with the oracle's iterations and x within 1e-12, on C2 at 24^3 (ILU(0) hybrid) and
     C3 at 20^3 (polynomial GS); the FP32 preconditioner reaches the same residual."""
     for name, N, kw in (("c2", 24, dict(smoother=1, inner_terms=3)), ("c3", 20, dict(smoother=0, inner_terms=2))):
         A, b, _ = config_system(name, N)
@@ -425,3 +438,37 @@ def test_deterministic_bitwise(namg):
         H.solve(dev(b), xt, smoother=1, inner_terms=3)
         xs.append(host(xt))
     assert np.array_equal(xs[0], xs[1])
+
+
+def test_solve_diagnostics(namg):
+    """The opt-in diagnostics of namg_solve: the residual history equals the oracle's (checked in every
+    solve above); phase times are NaN unless requested and then add up to at most the solve's wall
+    time; the loss of orthogonality ||I - V^T V||_F (Section 3) of the cycle's basis is NaN unless
+    requested and then matches the oracle's, computed from its captured basis, where the loss is far
+    above the rounding of one vector (C1 at tol 1e-8: about 1e-7; C2 20^3 ILU(0) hybrid to 1e-12: about
+    3e-2). The loss is itself accumulated rounding, so two correct implementations that round
+    differently agree in magnitude, not digit for digit: the bound is a factor of 10."""
+    for name, N, kw in (("c1", None, dict(smoother=0, inner_terms=2, tol=1e-8)),
+                        ("c2", 20, dict(smoother=1, inner_terms=3, tol=1e-12))):
+        A, b, _ = config_system(name, N)
+        H, G = namg.Hierarchy(A, device=0), O.Hierarchy(A)
+        kw = dict(kw, restart=60, max_iters=60)
+        plain = H.solve(dev(b), dev(np.zeros(A.n)), **kw)
+        assert all(np.isnan(plain[k]) for k in ("loss_orth", "ms_vcycle", "ms_spmv", "ms_ortho"))
+        st = H.solve(dev(b), dev(np.zeros(A.n)), diagnostics=namg.DIAG_LOSS_ORTH | namg.DIAG_PHASE_TIMES, **kw)
+        assert st["iters"] == plain["iters"] and st["cycles"] == 1
+        phases = st["ms_vcycle"] + st["ms_spmv"] + st["ms_ortho"]
+        assert min(st["ms_vcycle"], st["ms_spmv"], st["ms_ortho"]) > 0.0 and phases <= st["ms_total"]
+        ref = G.solve(b, tol=kw["tol"], restart=60, max_iters=60, smoother=kw["smoother"], t=kw["inner_terms"],
+                      capture=True)
+        assert ref["iters"] == st["iters"]
+        loo = O.loss_orth(ref["V"])
+        ratio = st["loss_orth"] / loo
+        print(f"PARITY-GAP loss_orth {name} gpu={st['loss_orth']:.6e} oracle={loo:.6e} ratio={ratio:.4f}")
+        assert 0.1 <= ratio <= 10.0, (st["loss_orth"], loo)
+    with pytest.raises(namg.NamgError) as e:
+        H.solve(dev(b), dev(np.zeros(A.n)), res_hist_cap=4)
+    assert e.value.code == namg.E_INVALID
+    with pytest.raises(namg.NamgError) as e:
+        H.solve(dev(b), dev(np.zeros(A.n)), diagnostics=8)
+    assert e.value.code == namg.E_INVALID

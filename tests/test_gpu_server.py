@@ -178,3 +178,41 @@ def test_device_setup_requests_in_the_mix(namg):
         assert r["iters"] == st["iters"], (sp, r["iters"], st["iters"])
         assert np.array_equal(r["x"], xt.cpu().numpy()), sp
         assert r["nrbe"] <= 1e-8
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_per_request_solve_parameters(namg, precision):
+    """namg_server_submit with each request's own solve parameters (smoother, Neumann terms, restart,
+    tolerance, T form, stopping rule): requests of different kinds share ticks, and every one equals the
+    single-solve path with the same parameters bit for bit."""
+    systems = stream_systems(6, 12, 18, seed=23)
+    kinds = [dict(smoother=0, inner_terms=2, restart=30, tol=1e-8),
+             dict(smoother=1, inner_terms=3, restart=10, tol=1e-10),
+             dict(smoother=2, restart=20, tol=1e-8),
+             dict(smoother=0, inner_terms=3, restart=5, tol=1e-9, gmres_T=1),
+             dict(smoother=1, inner_terms=2, restart=30, tol=1e-8, t_degree=2),
+             dict(smoother=0, inner_terms=2, restart=4, tol=1e-8, stop_rule=1)]
+    srv = namg.Server(solve=SOLVE, max_inflight=6, setup_threads=3, precision=precision)
+    tickets = [srv.submit(A, b, solve=kw, ilu_levels=1) for (A, b), kw in zip(systems, kinds)]
+    res = [srv.wait(t) for t in tickets]
+    c = srv.stats()
+    srv.close()
+    assert c["peak_inflight"] > 1 and c["footprint_mismatches"] == 0
+    for (A, b), kw, r in zip(systems, kinds, res):
+        H = namg.Hierarchy(A, device=0, precision=precision, ilu_levels=1)
+        bt = torch.from_numpy(b).to("cuda:0")
+        xt = torch.zeros_like(bt)
+        st = H.solve(bt, xt, **kw)
+        torch.cuda.synchronize()
+        H.close()
+        assert r["status"] == st["status"] == namg.OK, kw
+        assert r["iters"] == st["iters"], kw
+        assert np.array_equal(r["x"], xt.cpu().numpy()), kw
+    # per-request parameters are validated at submission
+    A, b = systems[0]
+    srv = namg.Server(solve=SOLVE, max_inflight=2, setup_threads=1, precision=precision)
+    for bad in (dict(tri_mode=1), dict(diagnostics=1), dict(restart=0), dict(inner_terms=0)):
+        with pytest.raises(namg.NamgError) as e:
+            srv.submit(A, b, solve=bad)
+        assert e.value.code == namg.E_INVALID, bad
+    srv.close()

@@ -1,0 +1,293 @@
+"""CPU replay of the row kernels' memory accesses on the exact device layouts (no GPU).
+
+The sparse row kernels (SELL-64 with one or two rows per lane, CSR with G lanes per row) issue their
+index, value and gather loads before they know which slots of a chunk are real entries, so every slot
+must point at valid memory. This module restates the layouts the library packs (slices of 64 rows padded
+to their longest row, 16-bit column offsets from a scaled diagonal when every column fits, lane groups
+for long coarse rows) and the index arithmetic of the row kernels, lane by lane with numpy, and checks
+on the matrices of real hierarchies that
+
+  * every index and value load stays inside the stored arrays,
+  * every gather stays inside the gathered vector,
+  * the sums over the real entries equal the oracle's product: bit for bit with one lane per row (entry
+    order), to rounding with lane groups (lane j sums entries j, j + G, ..., then a fixed butterfly).
+
+A model of the two-rows-per-lane kernel with the base column of a lane's second row taken even when the
+lane has no second row (an earlier form of that kernel) must show an out-of-range gather on the ragged
+last slice, so the replay can tell the two apart.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+from workloads import CSR, config_system, varcoef3d
+
+SELL_C = 64
+BLK = 256
+U = 4
+COL_SHIFT = 20
+
+
+@pytest.fixture(scope="module")
+def namg():
+    import paper_2112_14681_amd as m
+
+    return m
+
+
+# --------------------------------------------------------------------------------------- layouts
+def diag_mul(nrows, ncols):
+    return (ncols << COL_SHIFT) // nrows if nrows > 0 else 0
+
+
+def diag_base(rows, mul):
+    return (rows.astype(np.int64) * mul) >> COL_SHIFT
+
+
+def choose_group(nrows, nnz, lane_entries=8, sell_min_rows=1 << 19):
+    avg = nnz / nrows if nrows > 0 else 0.0
+    if avg <= 10.0 or nrows >= sell_min_rows:
+        return 1
+    g = 2
+    while g < 64 and g * lane_entries < avg:
+        g <<= 1
+    return g
+
+
+class Layout:
+    """The device layout of one CSR matrix (nrows x ncols), as the library packs it."""
+
+    def __init__(self, rp, ci, vals, ncols, force_group=0):
+        self.nrows = len(rp) - 1
+        self.ncols = ncols
+        self.mul = diag_mul(self.nrows, ncols)
+        rows = np.repeat(np.arange(self.nrows), np.diff(rp))
+        off = ci.astype(np.int64) - diag_base(rows, self.mul)
+        self.narrow = bool(off.size == 0 or (off.min() >= -32768 and off.max() <= 32767))
+        self.group = force_group or choose_group(self.nrows, int(rp[-1]))
+        if self.group > 1:
+            self.ptr = rp.astype(np.int64)
+            self.idx = (off if self.narrow else ci).astype(np.int64)
+            self.val = vals.copy()
+            return
+        lens = np.diff(rp)
+        nsl = (self.nrows + SELL_C - 1) // SELL_C
+        padded = np.zeros(nsl * SELL_C, np.int64)
+        padded[: self.nrows] = lens
+        width = padded.reshape(nsl, SELL_C).max(axis=1)
+        self.ptr = np.zeros(nsl + 1, np.int64)
+        np.cumsum(width * SELL_C, out=self.ptr[1:])
+        stored = int(self.ptr[-1])
+        self.idx = np.zeros(max(stored, 1), np.int64)  # padding: offset 0 or column 0
+        self.val = np.zeros(max(stored, 1))
+        k_in_row = np.arange(rp[-1]) - np.repeat(rp[:-1], lens)
+        dst = self.ptr[rows // SELL_C] + SELL_C * k_in_row + (rows % SELL_C)
+        self.idx[dst] = off if self.narrow else ci
+        self.val[dst] = vals
+        self.stored = stored
+
+
+class Access:
+    """Collects every index/value load position and every gather column; checks their ranges."""
+
+    def __init__(self, layout):
+        self.L = layout
+        self.bad_loads = 0
+        self.bad_gathers = 0
+
+    def load(self, kk):
+        n_store = len(self.L.val) if self.L.group > 1 else max(self.L.stored, 1)
+        self.bad_loads += int(np.count_nonzero((kk < 0) | (kk >= n_store)))
+        return self.L.idx[np.clip(kk, 0, n_store - 1)], self.L.val[np.clip(kk, 0, n_store - 1)]
+
+    def gather(self, x, c):
+        self.bad_gathers += int(np.count_nonzero((c < 0) | (c >= self.L.ncols)))
+        return x[np.clip(c, 0, self.L.ncols - 1)]
+
+
+# ------------------------------------------------------------------------------- kernel replays
+def replay_one_row_per_lane(L, x):
+    """SELL-64 with one row per lane (8-byte values), or CSR with G lanes per row: row_dot_impl."""
+    acc_all = np.zeros(L.nrows)
+    a = Access(L)
+    G = L.group
+    nthreads = ((L.nrows * G + BLK - 1) // BLK) * BLK
+    g = np.arange(nthreads, dtype=np.int64)
+    row, sub = g // G, g % G
+    live = row < L.nrows
+    row, sub = row[live], sub[live]
+    step = SELL_C if G == 1 else G
+    if G == 1:
+        k = L.ptr[row >> 6] + (row & 63)
+        end = L.ptr[(row >> 6) + 1]
+    else:
+        k = L.ptr[row] + sub
+        end = L.ptr[row + 1]
+    base = diag_base(row, L.mul) if L.narrow else np.zeros_like(row)
+    acc = np.zeros(row.size)
+    while True:
+        act = k < end
+        if not act.any():
+            break
+        kk_list, ok_list = [], []
+        for u in range(U):
+            ok = act & (k + u * step < end)
+            kk = np.where(ok, k + u * step, k)
+            kk_list.append(kk[act])
+            ok_list.append(ok[act])
+        cols, vals = [], []
+        for kk in kk_list:
+            i, v = a.load(kk)
+            cols.append(base[act] + i if L.narrow else i)
+            vals.append(v)
+        xs = [a.gather(x, c) for c in cols]
+        part = acc[act]
+        for u in range(U):
+            part = np.where(ok_list[u], part + vals[u] * xs[u], part)
+        acc[act] = part
+        k = k + U * step
+    if G == 1:
+        acc_all[row] = acc
+    else:
+        # the xor butterfly over the group: lanes j and j ^ off pair up, in a fixed order
+        s = acc.reshape(-1, G)
+        off = G // 2
+        while off > 0:
+            s = s + s[:, np.arange(G) ^ off]
+            off //= 2
+        acc_all[row.reshape(-1, G)[:, 0]] = s[:, 0]
+    return acc_all, a
+
+
+def replay_two_rows_per_lane(L, x, second_base_always=False):
+    """SELL-64 with two rows per lane (4-byte values): sell_dot2_impl. Block lb covers rows
+    [512 lb, 512 lb + 512); wavefront w takes slices 2w and 2w + 1 of the block."""
+    a = Access(L)
+    nblocks = (L.nrows + 2 * BLK - 1) // (2 * BLK)
+    tid = np.arange(BLK, dtype=np.int64)
+    lb = np.repeat(np.arange(nblocks, dtype=np.int64), BLK)
+    t = np.tile(tid, nblocks)
+    r0 = lb * (2 * BLK) + (t >> 6) * (2 * SELL_C) + (t & 63)
+    live = r0 < L.nrows
+    r0 = r0[live]
+    has1 = r0 + SELL_C < L.nrows
+    s0, lane = r0 >> 6, r0 & 63
+    k0 = L.ptr[s0] + lane
+    e0 = L.ptr[s0 + 1]
+    k1 = np.where(has1, e0 + lane, 0)
+    e1 = np.where(has1, L.ptr[np.minimum(s0 + 2, len(L.ptr) - 1)], 0)
+    if L.narrow:
+        b0 = diag_base(r0, L.mul)
+        second = r0 + SELL_C if second_base_always else np.where(has1, r0 + SELL_C, r0)
+        b1 = diag_base(second, L.mul)
+    else:
+        b0 = b1 = np.zeros_like(r0)
+    a0, a1 = np.zeros(r0.size), np.zeros(r0.size)
+    while True:
+        act = (k0 < e0) | (k1 < e1)
+        if not act.any():
+            break
+        kb0 = np.where(k0 < e0, k0, k1)
+        kb1 = np.where(k1 < e1, k1, k0)
+        for u in range(U):
+            ok0 = act & (k0 + u * SELL_C < e0)
+            ok1 = act & (k1 + u * SELL_C < e1)
+            kk0 = np.where(ok0, k0 + u * SELL_C, kb0)[act]
+            kk1 = np.where(ok1, k1 + u * SELL_C, kb1)[act]
+            i0, v0 = a.load(kk0)
+            i1, v1 = a.load(kk1)
+            q0 = b0[act] + i0 if L.narrow else i0
+            q1 = b1[act] + i1 if L.narrow else i1
+            c0 = np.where(ok0[act], q0, b0[act])
+            c1 = np.where(ok1[act], q1, b1[act])
+            x0, x1 = a.gather(x, c0), a.gather(x, c1)
+            a0[act] = np.where(ok0[act], a0[act] + v0 * x0, a0[act])
+            a1[act] = np.where(ok1[act], a1[act] + v1 * x1, a1[act])
+        k0 = k0 + U * SELL_C
+        k1 = k1 + U * SELL_C
+    out = np.zeros(L.nrows)
+    out[r0] = a0
+    out[r0[has1] + SELL_C] = a1[has1]
+    return out, a
+
+
+# -------------------------------------------------------------------------------- the matrices
+def strict_part(rp, ci, vals, lower):
+    rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+    keep = ci < rows if lower else ci > rows
+    cnt = np.bincount(rows[keep], minlength=len(rp) - 1)
+    nrp = np.zeros(len(rp), np.int64)
+    np.cumsum(cnt, out=nrp[1:])
+    return nrp, ci[keep], vals[keep]
+
+
+def hierarchy_operators(namg, A, **kw):
+    """Every operator a V-cycle multiplies with, as (name, rowptr, colind, vals, ncols, force_group)."""
+    H = namg.Hierarchy(A, device=-1, **kw)
+    info = H.info()
+    ops = []
+    for l in range(info["levels"] - 1):
+        e = H.export_level(l)
+        Arp, Aci, Av = e["A"]
+        n = len(Arp) - 1
+        ops.append((f"A{l}", Arp, Aci, Av, n, 0))
+        if l == 0:
+            ops.append(("A0 fp64", Arp, Aci, Av, n, 1))
+        Prp, Pci, Pv, nc = e["P"]
+        ops.append((f"P{l}", Prp, Pci, Pv, nc, 0))
+        R = sp.csr_matrix((Pv, Pci, Prp), shape=(n, nc)).T.tocsr()
+        R.sort_indices()
+        ops.append((f"R{l}", R.indptr, R.indices, R.data, n, 0))
+        for lower in (True, False):
+            rp, ci, v = strict_part(Arp, Aci, Av, lower)
+            ops.append((f"A{l} {'lower' if lower else 'upper'}", rp, ci, v, n, 0))
+        if l == 0 and kw.get("ilu_levels", 1) != 0:
+            f = H.export_ilu(0)
+            ops.append(("ILU L_s", *f["L"], n, 0))
+            ops.append(("ILU U_s", *f["U"], n, 0))
+    H.close()
+    return ops
+
+
+def _systems():
+    yield "varcoef 33^3", varcoef3d(33, 0.5, 1001)[0]
+    yield "varcoef 47^3 stretched", varcoef3d(47, 1.0, 1002, 100.0)[0]
+    yield "varcoef 65^3", varcoef3d(65, 0.5, 1003)[0]
+    yield "permuted 34^3", config_system("c4r", 34)[0]
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_row_kernel_accesses_in_range(namg, case):
+    name, A = list(_systems())[case]
+    rng = np.random.default_rng(case)
+    for label, rp, ci, v, ncols, fg in hierarchy_operators(namg, A):
+        L = Layout(np.asarray(rp), np.asarray(ci), np.asarray(v), ncols, fg)
+        x = rng.standard_normal(ncols)
+        y, acc = replay_one_row_per_lane(L, x)
+        assert acc.bad_loads == 0 and acc.bad_gathers == 0, (name, label, "one row per lane", acc.bad_loads,
+                                                              acc.bad_gathers)
+        if ncols == len(rp) - 1 and L.group == 1:  # one lane per row sums in entry order: the oracle's bits
+            ref = O.spmv(CSR(ncols, np.asarray(rp, np.int32), np.asarray(ci, np.int32), np.asarray(v)), x)
+            assert np.array_equal(y, ref), (name, label)
+        else:
+            ref = sp.csr_matrix((v, ci, rp), shape=(len(rp) - 1, ncols)) @ x
+            np.testing.assert_allclose(y, ref, rtol=1e-13, atol=1e-13)
+        if L.group == 1:
+            y2, acc2 = replay_two_rows_per_lane(L, x)
+            assert acc2.bad_loads == 0 and acc2.bad_gathers == 0, (name, label, "two rows per lane",
+                                                                   acc2.bad_loads, acc2.bad_gathers)
+            assert np.array_equal(y2, y), (name, label)
+
+
+def test_replay_detects_second_row_base_past_the_end():
+    """On a ragged last slice (the row count not a multiple of 128) the earlier form of the two-rows kernel
+    gathers up to 64 columns past the end of x for lanes without a second row; the current form does not."""
+    A = varcoef3d(33, 0.5, 1001)[0]  # 35 937 rows: the last block has lanes without a second row
+    L = Layout(A.rowptr, A.colind, A.vals, A.n)
+    assert L.group == 1 and L.narrow and A.n % 128 != 0
+    x = np.random.default_rng(0).standard_normal(A.n)
+    _, old = replay_two_rows_per_lane(L, x, second_base_always=True)
+    _, new = replay_two_rows_per_lane(L, x)
+    assert old.bad_gathers > 0
+    assert new.bad_gathers == 0 and new.bad_loads == 0
