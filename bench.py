@@ -39,10 +39,13 @@ def _args():
                     help="coarsen to at most this many rows (dense direct solve on the coarsest level); default "
                          "50 for c1, whose configuration fixes it, 1000 otherwise")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-contract", action="store_true",
+                    help="skip the contract figures: C2 coarsened to 50 rows, and the FP32 preconditioner against "
+                         "all-FP64 at C2 and C3")
     ap.add_argument("--compare", action="store_true",
                     help="also time the direct-triangular, l1-Jacobi and FP32-preconditioner variants")
-    ap.add_argument("--serve-requests", type=int, default=200,
-                    help="requests of the served stream to replay (0: skip; 2000: the whole stream)")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests of the served stream to replay (0: skip; default: the whole stream)")
     ap.add_argument("--serve-inflight", type=int, default=64)
     ap.add_argument("--serve-setup-threads", type=int, default=14)
     ap.add_argument("--serve-only", action="store_true")
@@ -111,46 +114,84 @@ def _time_solves(torch, H, bt, xt, kw, steps, warmup):
     return (time.perf_counter() - t0) * 1e3 / steps, stats
 
 
-def _gen_request(args):
-    from workloads import varcoef3d
-
-    N, seed = args
-    return varcoef3d(N, 0.5, seed)
-
-
-def served_stream(namg, count, inflight, setup_threads, coarsen="pmis"):
+def served_stream(namg, count, inflight, setup_threads, coarsen="pmis", gen_threads=12, lead=256):
     """Replay the first `count` requests of the served stream (Poisson arrivals at 50/s, n log-uniform in
     [32, 160], variable-k pressure systems) against the continuous-batching server: FP32 AMG + FP64 GMRES(30),
     polynomial GS with 2 Neumann terms, tol 1e-8. Latency runs from each request's scheduled arrival to its
     completion on the server's clock. coarsen "rs": host setup (RS, classical interpolation); "pmis": the
-    device setup (PMIS, BAMG direct interpolation)."""
-    import multiprocessing as mp
-    from concurrent.futures import ProcessPoolExecutor, ThreadPoolExecutor
+    device setup (PMIS, BAMG direct interpolation).
 
-    from workloads import serve_stream
+    The systems are generated while the stream plays, by `gen_threads` threads, at most `lead` requests
+    ahead of the last one submitted (memory stays bounded); the clock starts once the first `lead`
+    requests exist. Four submitter threads submit request j at its scheduled arrival (or as soon as it
+    exists, if generation falls behind: such a request counts as late, and its lateness is part of its
+    latency)."""
+    import threading
+    from concurrent.futures import ThreadPoolExecutor
+
+    from workloads import serve_stream, varcoef3d
 
     reqs = serve_stream(2000, seed=5)[:count]
-    # fresh interpreters (spawn): the generator processes never inherit this process's GPU runtime
-    with ProcessPoolExecutor(max_workers=16, mp_context=mp.get_context("spawn")) as ex:
-        systems = list(ex.map(_gen_request, [(r["N"], r["seed"]) for r in reqs], chunksize=2))
+    ready = [threading.Event() for _ in range(count)]
+    systems = [None] * count
+    room = threading.Semaphore(lead)
+
+    def gen(j):
+        room.acquire()
+        systems[j] = varcoef3d(reqs[j]["N"], 0.5, reqs[j]["seed"])
+        ready[j].set()
+
+    gpool = ThreadPoolExecutor(max_workers=gen_threads)
+    gfuts = [gpool.submit(gen, j) for j in range(count)]
+    ready[min(lead, count) - 1].wait()
     srv = namg.Server(solve=dict(smoother=namg.SMOOTH_PGS, inner_terms=2, restart=30, tol=1e-8),
                       max_inflight=inflight, setup_threads=setup_threads, precision=namg.FP32_PRECOND)
     t0_srv = srv.clock()
     t0 = time.perf_counter()
+    tickets = [None] * count
+    late = np.zeros(count)
+    peak = {"waiting": 0, "inflight": 0, "queue": 0}
+    stop = threading.Event()
 
-    def submit(j):
-        delay = reqs[j]["arrival_s"] - (time.perf_counter() - t0)
-        if delay > 0:
-            time.sleep(delay)
-        A, b = systems[j]
-        # polynomial GS throughout: no ILU(0) factors to build
-        if coarsen == "pmis":
-            return srv.submit(A, b, ilu_levels=0, coarsen=namg.COARSEN_PMIS, seed=j)
-        return srv.submit(A, b, ilu_levels=0)
+    def monitor():
+        while not stop.wait(0.05):
+            c = srv.stats()
+            peak["waiting"] = max(peak["waiting"], c["waiting"])
+            peak["inflight"] = max(peak["inflight"], c["inflight"])
+            peak["queue"] = max(peak["queue"], c["submitted"] - c["completed"] - c["failed"])
 
-    with ThreadPoolExecutor(max_workers=4) as ex:
-        tickets = list(ex.map(submit, range(count)))
+    def submitter(k, nsub):
+        for j in range(k, count, nsub):
+            delay = reqs[j]["arrival_s"] - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            ready[j].wait()
+            late[j] = max(0.0, (time.perf_counter() - t0) - reqs[j]["arrival_s"])
+            A, b = systems[j]
+            # polynomial GS throughout: no ILU(0) factors to build
+            if coarsen == "pmis":
+                tickets[j] = srv.submit(A, b, ilu_levels=0, coarsen=namg.COARSEN_PMIS, seed=j)
+            else:
+                tickets[j] = srv.submit(A, b, ilu_levels=0)
+            systems[j] = None
+            room.release()
+            if (j + 1) % 250 == 0:
+                print(f"[served] submitted {j + 1}/{count} at {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                      flush=True)
+
+    mon = threading.Thread(target=monitor, daemon=True)
+    mon.start()
+    subs = [threading.Thread(target=submitter, args=(k, 4)) for k in range(4)]
+    for t in subs:
+        t.start()
+    for t in subs:
+        t.join()
+    for f in gfuts:
+        f.result()
+    gpool.shutdown()
     results = [srv.wait(t) for t in tickets]
+    stop.set()
+    mon.join()
     counters = srv.stats()
     srv.close()
     lat = np.array([r["times"]["done"] - (t0_srv + q["arrival_s"]) for r, q in zip(results, reqs)])
@@ -165,14 +206,66 @@ def served_stream(namg, count, inflight, setup_threads, coarsen="pmis"):
         "p50_s": round(float(np.percentile(lat, 50)), 4), "p99_s": round(float(np.percentile(lat, 99)), 4),
         "max_s": round(float(lat.max()), 4), "solves_per_s": round(count / span, 2),
         "arrival_span_s": round(reqs[-1]["arrival_s"] - reqs[0]["arrival_s"], 3),
+        "completion_span_s": round(float(span), 3),
+        "late_submissions": int(np.count_nonzero(late > 0.005)), "max_submit_lateness_s": round(float(late.max()), 4),
         "median_queue_s": round(float(np.median(queue_s)), 4), "median_setup_s": round(float(np.median(setup_s)), 4),
         "median_inflight_s": round(float(np.median(solve_s)), 4),
         "mean_iters": round(float(np.mean([r["iters"] for r in results])), 2),
         "alg_GBps_while_serving": round(sum(r["alg_bytes"] for r in results) / span / 1e9, 1),
-        "peak_inflight": counters["peak_inflight"], "ticks": counters["ticks"], "batched_launches": counters["launches"],
+        "peak_inflight": counters["peak_inflight"], "peak_waiting": peak["waiting"], "peak_outstanding": peak["queue"],
+        "ticks": counters["ticks"], "batched_launches": counters["launches"],
         "peak_device_GB": round(counters["peak_device_bytes"] / 1e9, 2),
         "setup_threads": setup_threads, "max_inflight": inflight, "setup": coarsen,
     }
+
+
+def contract_figures(namg, torch, steps):
+    """The figures the targets are stated on, next to the headline: C2 coarsened to <= 50 rows (the
+    library default and C1's configuration), and the FP32 preconditioner against all-FP64 at the same
+    1e-8 true residual on C2 (ILU(0) hybrid, t = 3) and on C3 (192^3 -div(k grad p), polynomial GS t = 2;
+    the configuration that states the 1.5x target). ms per solve, median of `steps` solves after one
+    warm-up."""
+    from workloads import config_system
+
+    out = {}
+    dev = torch.device("cuda:0")
+
+    def run(A, bt, prec, max_coarse, kw, ilu_levels):
+        H = namg.Hierarchy(A, device=0, precision=prec, ilu_levels=ilu_levels, max_coarse=max_coarse)
+        xt = torch.zeros_like(bt)
+        H.solve(bt, xt, **kw)
+        times, st = [], None
+        for _ in range(steps):
+            xt.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = H.solve(bt, xt, **kw)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+        info = H.info()
+        H.close()
+        return {"ms": round(float(np.median(times)), 4), "iters": st["iters"], "relres": st["relres_true"],
+                "levels": info["levels"], "status_ok": st["status"] == namg.OK}
+
+    A, b, _ = config_system("c2")
+    bt = torch.from_numpy(b).to(dev)
+    kw = dict(tol=1e-8, restart=30, smoother=namg.SMOOTH_ILU0, tri_mode=namg.TRI_NEUMANN, inner_terms=3)
+    out["c2_fp64_max_coarse_50"] = run(A, bt, namg.FP64, 50, kw, 1)
+    f64 = run(A, bt, namg.FP64, 1000, kw, 1)
+    f32 = run(A, bt, namg.FP32_PRECOND, 1000, kw, 1)
+    out["c2_fp64"], out["c2_fp32_precond"] = f64, f32
+    out["c2_fp32_speedup"] = round(f64["ms"] / f32["ms"], 3)
+    print("[contract] c2 done", file=sys.stderr, flush=True)
+    del bt
+    A, b, _ = config_system("c3")
+    bt = torch.from_numpy(b).to(dev)
+    kw = dict(tol=1e-8, restart=30, smoother=namg.SMOOTH_PGS, tri_mode=namg.TRI_NEUMANN, inner_terms=2)
+    f64 = run(A, bt, namg.FP64, 1000, kw, 0)
+    f32 = run(A, bt, namg.FP32_PRECOND, 1000, kw, 0)
+    out["c3_fp64"], out["c3_fp32_precond"] = f64, f32
+    out["c3_fp32_speedup"] = round(f64["ms"] / f32["ms"], 3)
+    print("[contract] c3 done", file=sys.stderr, flush=True)
+    return out
 
 
 def cpu_baseline(A, b, kw, gpu_iters, max_coarse):
@@ -412,6 +505,9 @@ def main():
             H_ilut.close()
         out["compare"] = cmp
 
+    if not args.no_contract and args.config == "c2" and args.N is None:
+        H.close()
+        out["contract"] = contract_figures(namg, torch, max(3, min(args.steps, 7)))
     if args.serve_requests > 0:
         H.close()
         out["served"] = served_stream(namg, args.serve_requests, args.serve_inflight, args.serve_setup_threads,

@@ -139,32 +139,84 @@ def varcoef3d(N: int, sigma: float, seed: int, stretch: float = 1.0):
 
     k = exp(sigma * xi) per cell with xi ~ N(0, 1); hx = hy = 1/N; z spacing geometric with
     hz_max/hz_min = stretch. Face transmissibility T = area / (h_c/(2k_c) + h_c'/(2k_c')); a boundary
-    face uses area / (h_c/(2k_c)). Row c: a_cc = sum of its face T, a_cc' = -T. SPD M-matrix.
-    Returns (A, b) with b ~ N(0, 1) drawn after k from the same generator.
+    face uses area / (h_c/(2k_c)). Row c: a_cc = sum of its face T (faces in the order -x, +x, -y, +y,
+    -z, +z), a_cc' = -T. SPD M-matrix. Returns (A, b) with b ~ N(0, 1) drawn after k from the same
+    generator.
+
+    Each interior face is computed once: both of its cells see the same area and the same two half-cell
+    resistances, whose sum does not depend on their order. The sparsity structure of an N^3 grid is
+    shared by every system of that size (cached).
     """
     rng = np.random.default_rng(seed)
     n = N ** 3
     kappa = np.exp(sigma * rng.standard_normal(n))
     b = rng.standard_normal(n)
-    h = [np.full(N, 1.0 / N), np.full(N, 1.0 / N), stretched_spacing(N, stretch)]
-    idx = np.arange(n, dtype=np.int64)
-    coord = [idx % N, (idx // N) % N, idx // (N * N)]
-    width = [h[a][coord[a]] for a in range(3)]
-    diag = np.zeros(n)
-    nbr = []
-    stride = [1, N, N * N]
+    hx = np.full(N, 1.0 / N)
+    hz = stretched_spacing(N, stretch)
+    two_k = 2.0 * kappa.reshape(N, N, N)  # [z, y, x]
+    # width of every cell along grid axis a (x, y, z), broadcast over [z, y, x]
+    width = [np.broadcast_to(hx[None, None, :], (N, N, N)), np.broadcast_to(hx[None, :, None], (N, N, N)),
+             np.broadcast_to(hz[:, None, None], (N, N, N))]
+    dim = [2, 1, 0]  # array dimension of grid axis a
+    diag = np.zeros((N, N, N))
+    coef = {}
     for a in range(3):
         area = width[(a + 1) % 3] * width[(a + 2) % 3]
-        half_own = width[a] / (2.0 * kappa)
-        for s in (-1, 1):
-            c = coord[a] + s
-            inside = (c >= 0) & (c < N)
-            other = np.where(inside, idx + s * stride[a], idx)
-            half_other = h[a][np.clip(c, 0, N - 1)] / (2.0 * kappa[other])
-            t = np.where(inside, area / (half_own + half_other), area / half_own)
-            diag += t
-            nbr.append((a, s, -t))
-    return _assemble((N, N, N), diag, nbr), b
+        half = width[a] / two_k
+        lo, hi, first, last = ([slice(None)] * 3 for _ in range(4))
+        lo[dim[a]], hi[dim[a]] = slice(0, N - 1), slice(1, N)
+        first[dim[a]], last[dim[a]] = slice(0, 1), slice(N - 1, N)
+        lo, hi, first, last = tuple(lo), tuple(hi), tuple(first), tuple(last)
+        face = area[lo] / (half[lo] + half[hi])  # between cell i and cell i + 1 along a
+        minus, plus = np.empty((N, N, N)), np.empty((N, N, N))
+        minus[first] = area[first] / half[first]
+        minus[hi] = face
+        plus[last] = area[last] / half[last]
+        plus[lo] = face
+        diag += minus
+        diag += plus
+        coef[(a, -1)], coef[(a, 1)] = minus, plus
+    rowptr, colind, keep = _grid7_structure(N)
+    slots = [coef[(2, -1)], coef[(1, -1)], coef[(0, -1)], None, coef[(0, 1)], coef[(1, 1)], coef[(2, 1)]]
+    vals = np.empty((n, 7))
+    for j, c in enumerate(slots):
+        if c is None:
+            vals[:, j] = diag.ravel()
+        else:
+            np.negative(c.ravel(), out=vals[:, j])
+    return CSR(n, rowptr, colind, np.ascontiguousarray(vals[keep])), b
+
+
+_GRID7_CACHE: dict = {}
+_GRID7_LOCK = __import__("threading").Lock()
+
+
+def _grid7_structure(N: int):
+    """Row pointers, column indices and the entry mask (n x 7, slots in ascending column order
+    -N^2, -N, -1, 0, +1, +N, +N^2) of the 7-point stencil on an N^3 grid with Dirichlet boundaries
+    eliminated. The few most recent sizes are kept."""
+    with _GRID7_LOCK:
+        hit = _GRID7_CACHE.get(N)
+    if hit is not None:
+        return hit
+    n = N ** 3
+    z, y, x = np.ogrid[0:N, 0:N, 0:N]
+    conds = [z > 0, y > 0, x > 0, np.ones((1, 1, 1), bool), x < N - 1, y < N - 1, z < N - 1]
+    keep = np.empty((n, 7), bool)
+    for j, c in enumerate(conds):
+        keep[:, j] = np.broadcast_to(c, (N, N, N)).ravel()
+    cols = np.arange(n, dtype=np.int32)[:, None] + np.array([-N * N, -N, -1, 0, 1, N, N * N], np.int32)[None, :]
+    colind = np.ascontiguousarray(cols[keep])
+    rowptr = np.zeros(n + 1, np.int64)
+    np.cumsum(keep.sum(axis=1), out=rowptr[1:])
+    if rowptr[-1] >= 2**31:
+        raise ValueError("nnz exceeds int32 range")
+    out = (rowptr.astype(np.int32), colind, keep)
+    with _GRID7_LOCK:
+        if len(_GRID7_CACHE) >= 4:
+            _GRID7_CACHE.pop(next(iter(_GRID7_CACHE)))
+        _GRID7_CACHE[N] = out
+    return out
 
 
 def convdiff3d(N: int, seed: int, peclet: float = 10.0):
