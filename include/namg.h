@@ -153,6 +153,7 @@ int namg_setup(int32_t n, const int32_t *rowptr, const int32_t *colind, const do
 int namg_solve(namg_hier *h, const double *b_dev, double *x_dev, const namg_solve_params *p, void *stream,
                namg_solve_stats *st);
 
+
 /* One preconditioner application x = M^{-1} b: one V-cycle with zero initial guess (Section 5).
  * b_dev, x_dev: n float64 device vectors (x written). */
 int namg_vcycle(namg_hier *h, const double *b_dev, double *x_dev, const namg_solve_params *p, void *stream);
@@ -269,7 +270,9 @@ int namg_us_powers(const namg_hier *h, int level, int pmax, int power_iters, dou
 typedef struct namg_server namg_server; /* opaque; owns its threads, stream and in-flight solves */
 
 typedef struct {
-  int64_t hbm_budget;  /* device bytes the in-flight solves may hold; <= 0: device memory - 16 GiB */
+  int64_t hbm_budget;  /* device bytes the in-flight solves may hold; <= 0: device memory less 48 GiB (16 GiB
+                          for other users of the device, 32 GiB for device setup memory, which admission
+                          does not count; see peak_setup_device_bytes) */
   int max_inflight;    /* solves advanced together per scheduler tick, 1..256 */
   int setup_threads;   /* host threads running the AMG setup of queued requests */
   int device;          /* HIP device ordinal */
@@ -282,13 +285,17 @@ typedef struct {
   double submit, setup_start, setup_done, admitted, done; /* seconds on the server's clock */
 } namg_request_times;
 
-/* device_bytes_in_use and peak_device_bytes count the footprints reserved at admission;
- * footprint_mismatches counts admitted requests whose solver allocated other than its reserved footprint
- * (0 when the admission estimate is exact). */
+/* device_bytes_in_use and peak_device_bytes count the footprints reserved at admission (every device
+ * buffer counted at the size it allocates, its block-cache size class); footprint_mismatches counts admitted
+ * requests whose solver allocated other than its reserved footprint (0 when the admission estimate is
+ * exact). peak_setup_device_bytes is the process-wide high-water mark of device setup memory, which no
+ * footprint covers: uploaded matrices, coarsening and sparse-product scratch, and the levels a set-up
+ * request keeps on the device until its solver is built. */
 typedef struct {
   int64_t submitted, completed, failed, inflight, waiting, ticks, launches;
   int64_t device_bytes_in_use, peak_device_bytes, peak_inflight;
   int64_t footprint_mismatches;
+  int64_t peak_setup_device_bytes;
 } namg_server_counters;
 
 void namg_default_server_params(namg_server_params *p);

@@ -98,7 +98,8 @@ class RequestTimes(C.Structure):
 class ServerCounters(C.Structure):
     _fields_ = [(name, C.c_int64) for name in ("submitted", "completed", "failed", "inflight", "waiting", "ticks",
                                                "launches", "device_bytes_in_use", "peak_device_bytes",
-                                               "peak_inflight", "footprint_mismatches")]
+                                               "peak_inflight", "footprint_mismatches",
+                                               "peak_setup_device_bytes")]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -304,6 +305,9 @@ class Hierarchy:
     def solve(self, b, x, stream=None, history=False, **params) -> dict:
         """namg_solve on device tensors b (read) and x (initial guess in, solution out). history=True also
         returns the residual estimate after every iteration ("hist")."""
+        return self._solve(_lib.namg_solve, b, x, stream, history, params)
+
+    def _solve(self, entry, b, x, stream, history, params) -> dict:
         p = solve_params(**params)
         hist = None
         if history:
@@ -311,8 +315,8 @@ class Hierarchy:
             p.res_hist = _ptr(hist, C.c_double)
             p.res_hist_cap = hist.size
         st = SolveStats()
-        code = _check(_lib.namg_solve(self.h, _dev_ptr(b, self.n), _dev_ptr(x, self.n), C.byref(p), _stream(stream),
-                                      C.byref(st)))
+        code = _check(entry(self.h, _dev_ptr(b, self.n), _dev_ptr(x, self.n), C.byref(p), _stream(stream),
+                            C.byref(st)))
         out = st.as_dict()
         out["status"] = code
         if history:

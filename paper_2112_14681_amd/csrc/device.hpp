@@ -5,9 +5,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
 #include <map>
 #include <mutex>
 #include <string>
@@ -30,10 +32,28 @@ inline void hip_check(hipError_t e, const char *what) {
   throw HipError{NAMG_E_HIP, std::string(what) + ": " + hipGetErrorString(e)};
 }
 
-// Counts the bytes every DevBuf of one hierarchy holds.
+// Counts the device bytes a set of DevBufs holds (one hierarchy, or every device setup of the process):
+// the size class each one allocated (see BlockCache), not the bytes it asked for; peak is the high-water
+// mark. Safe to share between threads.
 struct MemCounter {
-  int64_t bytes = 0;
+  std::atomic<int64_t> bytes{0}, peak{0};
+  void add(int64_t b) {
+    const int64_t now = bytes.fetch_add(b) + b;
+    int64_t p = peak.load();
+    while (now > p && !peak.compare_exchange_weak(p, now)) {
+    }
+  }
+  void sub(int64_t b) { bytes.fetch_sub(b); }
 };
+
+// Device memory of the device setup (uploaded A_0, scratch of coarsening and sparse products, the levels
+// kept for the solve-phase layouts, the temporaries of device packing): outside any solver's footprint.
+// The part of a server's default device budget left to it (peak_setup_device_bytes reports the measured need).
+constexpr int64_t SETUP_DEVICE_RESERVE = int64_t(32) << 30;
+inline MemCounter &setup_mem() {
+  static MemCounter m;
+  return m;
+}
 
 // Host<->device copies of pageable memory go through a pool of pinned staging buffers (64 MiB chunks):
 // the runtime's own pageable path shares one staging route among all threads, and many setup threads copy
@@ -198,6 +218,11 @@ class BlockCache {
   std::map<int, size_t> cached_;
 };
 
+// Device bytes that DevBuf::alloc(n) of elem-byte elements takes (its size class).
+inline int64_t alloc_bytes(int64_t n, int64_t elem) {
+  return (int64_t)BlockCache::size_class((size_t)std::max<int64_t>(n, 1) * (size_t)elem);
+}
+
 // One device allocation, returned to the block cache by the destructor (so a failed setup leaks nothing).
 template <class T>
 class DevBuf {
@@ -240,19 +265,27 @@ class DevBuf {
     }
     n_ = n;
     mc_ = mc;
-    if (mc_) mc_->bytes += (int64_t)(n * sizeof(T));
+    if (mc_) mc_->add((int64_t)cls_);
   }
   void upload(const T *h, size_t n) { copy_to_device(p_, h, n * sizeof(T)); }
   void release() {
     if (p_) {
-      if (!BlockCache::instance().put(dev_, cls_, p_)) {
+      // Released while an exception unwinds the stack (a failed setup, upload or solve): work queued before
+      // the error may still use the block, so the device drains before the block can be handed out again.
+      const bool unwinding = std::uncaught_exceptions() > 0;
+      const bool cached = !unwinding && BlockCache::instance().put(dev_, cls_, p_);
+      if (!cached) {
         int cur = -1;
         (void)hipGetDevice(&cur);
         if (cur != dev_) (void)hipSetDevice(dev_);
-        (void)hipFree(p_);
+        if (unwinding) {
+          (void)hipDeviceSynchronize();
+          (void)hipGetLastError();
+        }
+        if (!unwinding || !BlockCache::instance().put(dev_, cls_, p_)) (void)hipFree(p_);
         if (cur != dev_ && cur >= 0) (void)hipSetDevice(cur);
       }
-      if (mc_) mc_->bytes -= (int64_t)(n_ * sizeof(T));
+      if (mc_) mc_->sub((int64_t)cls_);
     }
     p_ = nullptr;
     n_ = 0;

@@ -525,7 +525,7 @@ class Builder {
     size_t bytes = 0;
     hip_check(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, (int)count, s_), "scan size");
     // a null temp pointer would turn the second call into another size query
-    if (bytes > temp_.size() || temp_.get() == nullptr) temp_.alloc(std::max<size_t>(bytes, 1), nullptr);
+    if (bytes > temp_.size() || temp_.get() == nullptr) temp_.alloc(std::max<size_t>(bytes, 1), &setup_mem());
     hip_check(hipcub::DeviceScan::ExclusiveSum(temp_.get(), bytes, in, out, (int)count, s_), "scan");
   }
 
@@ -541,9 +541,9 @@ class Builder {
     D.nr = A.nr;
     D.nc = A.nc;
     D.nnz = A.nnz();
-    D.rp.alloc(A.rp.size(), nullptr);
-    D.ci.alloc(A.ci.size(), nullptr);
-    D.v.alloc(A.v.size(), nullptr);
+    D.rp.alloc(A.rp.size(), &setup_mem());
+    D.ci.alloc(A.ci.size(), &setup_mem());
+    D.v.alloc(A.v.size(), &setup_mem());
     D.rp.upload(A.rp.data(), A.rp.size());
     D.ci.upload(A.ci.data(), A.ci.size());
     D.v.upload(A.v.data(), A.v.size());
@@ -561,7 +561,7 @@ class Builder {
   // C = X Y (X.nc == Y.nr), rows of C sorted by column
   void spgemm(const DCsr &X, const DCsr &Y, DCsr &C) {
     const int32_t nr = X.nr;
-    DevBuf<int64_t> tsize((size_t)nr + 1, nullptr), toff((size_t)nr + 1, nullptr);
+    DevBuf<int64_t> tsize((size_t)nr + 1, &setup_mem()), toff((size_t)nr + 1, &setup_mem());
     hipLaunchKernelGGL(k_spgemm_size, dim3(grid_for((int64_t)nr + 1)), dim3(TB), 0, s_, nr, X.rp.get(), X.ci.get(),
                        Y.rp.get(), tsize.get());
     check("k_spgemm_size");
@@ -570,10 +570,10 @@ class Builder {
     // every table is at least twice its row's entry count, so total / 2 bounds the product's entries,
     // whose row pointers are 32-bit
     if (total / 2 >= (int64_t)INT32_MAX) throw SetupError{NAMG_E_INVALID, "sparse product exceeds 2^31 entries"};
-    DevBuf<int32_t> tkey((size_t)std::max<int64_t>(total, 1), nullptr);
-    DevBuf<double> tval((size_t)std::max<int64_t>(total, 1), nullptr);
-    DevBuf<int32_t> order((size_t)std::max<int64_t>(total, 1), nullptr);
-    DevBuf<int32_t> cnt((size_t)nr + 1, nullptr);
+    DevBuf<int32_t> tkey((size_t)std::max<int64_t>(total, 1), &setup_mem());
+    DevBuf<double> tval((size_t)std::max<int64_t>(total, 1), &setup_mem());
+    DevBuf<int32_t> order((size_t)std::max<int64_t>(total, 1), &setup_mem());
+    DevBuf<int32_t> cnt((size_t)nr + 1, &setup_mem());
     // every key to -1 (all bytes 0xFF) in one coalesced pass
     hip_check(hipMemsetAsync(tkey.get(), 0xFF, (size_t)std::max<int64_t>(total, 1) * 4, s_), "memset");
     if (nr > 0) {
@@ -588,11 +588,11 @@ class Builder {
     check("k_spgemm_accumulate");
     C.nr = nr;
     C.nc = Y.nc;
-    C.rp.alloc((size_t)nr + 1, nullptr);
+    C.rp.alloc((size_t)nr + 1, &setup_mem());
     scan(cnt.get(), C.rp.get(), (int64_t)nr + 1);
     C.nnz = read_at(C.rp.get() + nr);
-    C.ci.alloc((size_t)std::max<int64_t>(C.nnz, 1), nullptr);
-    C.v.alloc((size_t)std::max<int64_t>(C.nnz, 1), nullptr);
+    C.ci.alloc((size_t)std::max<int64_t>(C.nnz, 1), &setup_mem());
+    C.v.alloc((size_t)std::max<int64_t>(C.nnz, 1), &setup_mem());
     const unsigned emit_grid = (unsigned)std::max<int64_t>(((int64_t)nr + EMIT_TB - 1) / EMIT_TB, 1);
     hipLaunchKernelGGL(k_spgemm_emit, dim3(emit_grid), dim3(EMIT_TB), 0, s_, nr, toff.get(), tkey.get(), tval.get(),
                        order.get(), C.rp.get(), C.ci.get(), C.v.get());
@@ -605,17 +605,17 @@ class Builder {
     R.nr = P.nc;
     R.nc = P.nr;
     R.nnz = P.nnz;
-    DevBuf<int32_t> cnt((size_t)P.nc + 1, nullptr), cursor((size_t)std::max(P.nc, 1), nullptr);
+    DevBuf<int32_t> cnt((size_t)P.nc + 1, &setup_mem()), cursor((size_t)std::max(P.nc, 1), &setup_mem());
     hip_check(hipMemsetAsync(cnt.get(), 0, ((size_t)P.nc + 1) * 4, s_), "memset");
     hip_check(hipMemsetAsync(cursor.get(), 0, (size_t)std::max(P.nc, 1) * 4, s_), "memset");
     if (P.nnz) {
       hipLaunchKernelGGL(k_col_count, dim3(grid_for(P.nnz)), dim3(TB), 0, s_, P.nnz, P.ci.get(), cnt.get());
       check("k_col_count");
     }
-    R.rp.alloc((size_t)P.nc + 1, nullptr);
+    R.rp.alloc((size_t)P.nc + 1, &setup_mem());
     scan(cnt.get(), R.rp.get(), (int64_t)P.nc + 1);
-    R.ci.alloc((size_t)std::max<int64_t>(P.nnz, 1), nullptr);
-    R.v.alloc((size_t)std::max<int64_t>(P.nnz, 1), nullptr);
+    R.ci.alloc((size_t)std::max<int64_t>(P.nnz, 1), &setup_mem());
+    R.v.alloc((size_t)std::max<int64_t>(P.nnz, 1), &setup_mem());
     hipLaunchKernelGGL(k_transpose_fill, dim3(grid_for(P.nr)), dim3(TB), 0, s_, P.nr, P.rp.get(), P.ci.get(),
                        P.v.get(), R.rp.get(), cursor.get(), R.ci.get(), R.v.get());
     check("k_transpose_fill");
@@ -628,8 +628,8 @@ class Builder {
   // point, or every point C). cf: 1 = C, 0 = F.
   bool coarsen(const DCsr &A, double theta, uint64_t seed, std::vector<int8_t> &cf, DCsr &P) {
     const int32_t n = A.nr;
-    DevBuf<uint8_t> flag((size_t)std::max<int64_t>(A.nnz, 1), nullptr);
-    DevBuf<int32_t> stcount((size_t)n + 1, nullptr), st_rp((size_t)n + 1, nullptr), cursor((size_t)n, nullptr);
+    DevBuf<uint8_t> flag((size_t)std::max<int64_t>(A.nnz, 1), &setup_mem());
+    DevBuf<int32_t> stcount((size_t)n + 1, &setup_mem()), st_rp((size_t)n + 1, &setup_mem()), cursor((size_t)n, &setup_mem());
     hip_check(hipMemsetAsync(stcount.get(), 0, ((size_t)n + 1) * 4, s_), "memset");
     hip_check(hipMemsetAsync(cursor.get(), 0, (size_t)n * 4, s_), "memset");
     hipLaunchKernelGGL(k_strength, dim3(grid_for(n)), dim3(TB), 0, s_, n, A.rp.get(), A.ci.get(), A.v.get(), theta,
@@ -637,14 +637,14 @@ class Builder {
     check("k_strength");
     scan(stcount.get(), st_rp.get(), (int64_t)n + 1);
     const int32_t nst = read_at(st_rp.get() + n);
-    DevBuf<int32_t> st_ci((size_t)std::max(nst, 1), nullptr);
+    DevBuf<int32_t> st_ci((size_t)std::max(nst, 1), &setup_mem());
     hipLaunchKernelGGL(k_st_fill, dim3(grid_for(n)), dim3(TB), 0, s_, n, A.rp.get(), A.ci.get(), flag.get(),
                        st_rp.get(), cursor.get(), st_ci.get());
     check("k_st_fill");
-    DevBuf<double> w((size_t)n, nullptr);
-    DevBuf<int8_t> state((size_t)n, nullptr);
-    DevBuf<uint8_t> newc((size_t)n, nullptr);
-    DevBuf<int32_t> remaining(1, nullptr);
+    DevBuf<double> w((size_t)n, &setup_mem());
+    DevBuf<int8_t> state((size_t)n, &setup_mem());
+    DevBuf<uint8_t> newc((size_t)n, &setup_mem());
+    DevBuf<int32_t> remaining(1, &setup_mem());
     hipLaunchKernelGGL(k_pmis_init, dim3(grid_for(n)), dim3(TB), 0, s_, n, stcount.get(), seed, w.get(), state.get());
     check("k_pmis_init");
     // every round makes the heaviest undecided point C, so n rounds always suffice
@@ -659,7 +659,7 @@ class Builder {
       check("k_pmis_apply");
       if (read_at(remaining.get()) == 0) break;
     }
-    DevBuf<int32_t> isc((size_t)n + 1, nullptr), cidx((size_t)n + 1, nullptr);
+    DevBuf<int32_t> isc((size_t)n + 1, &setup_mem()), cidx((size_t)n + 1, &setup_mem());
     hipLaunchKernelGGL(k_is_c, dim3(grid_for((int64_t)n + 1)), dim3(TB), 0, s_, n, state.get(), isc.get());
     check("k_is_c");
     scan(isc.get(), cidx.get(), (int64_t)n + 1);
@@ -670,17 +670,17 @@ class Builder {
     cf.resize(n);
     for (int32_t i = 0; i < n; ++i) cf[i] = st[i] == PT_C ? 1 : 0;
     if (nc == 0 || nc == n) return false;
-    DevBuf<int32_t> cnt((size_t)n + 1, nullptr);
+    DevBuf<int32_t> cnt((size_t)n + 1, &setup_mem());
     hipLaunchKernelGGL(k_interp_count, dim3(grid_for((int64_t)n + 1)), dim3(TB), 0, s_, n, A.rp.get(), A.ci.get(),
                        flag.get(), state.get(), cnt.get());
     check("k_interp_count");
     P.nr = n;
     P.nc = nc;
-    P.rp.alloc((size_t)n + 1, nullptr);
+    P.rp.alloc((size_t)n + 1, &setup_mem());
     scan(cnt.get(), P.rp.get(), (int64_t)n + 1);
     P.nnz = read_at(P.rp.get() + n);
-    P.ci.alloc((size_t)std::max<int64_t>(P.nnz, 1), nullptr);
-    P.v.alloc((size_t)std::max<int64_t>(P.nnz, 1), nullptr);
+    P.ci.alloc((size_t)std::max<int64_t>(P.nnz, 1), &setup_mem());
+    P.v.alloc((size_t)std::max<int64_t>(P.nnz, 1), &setup_mem());
     hipLaunchKernelGGL(k_interp_fill, dim3(grid_for(n)), dim3(TB), 0, s_, n, A.rp.get(), A.ci.get(), A.v.get(),
                        flag.get(), state.get(), cidx.get(), P.rp.get(), P.ci.get(), P.v.get());
     check("k_interp_fill");

@@ -161,7 +161,7 @@ void pack_device(DMat<T> &M, const DCsr &D, MemCounter *mc, int force_group) {
   M.ncols = D.nc;
   M.nnz = D.nnz;
   M.mul = diag_mul(M.nrows, M.ncols);
-  DevBuf<int32_t> bad(1, nullptr);
+  DevBuf<int32_t> bad(1, &setup_mem());
   hip_check(hipMemset(bad.get(), 0, 4), "hipMemset");
   if (M.nrows > 0) {
     hipLaunchKernelGGL(k_fits16, dim3(pgrid(M.nrows)), dim3(PB), 0, 0, M.nrows, D.rp.get(), D.ci.get(), M.mul,
@@ -190,7 +190,7 @@ void pack_device(DMat<T> &M, const DCsr &D, MemCounter *mc, int force_group) {
     const int32_t nslices = (M.nrows + SELL_C - 1) / SELL_C;
     std::vector<int32_t> w(std::max(nslices, 1), 0);
     if (nslices > 0) {
-      DevBuf<int32_t> dw((size_t)nslices, nullptr);
+      DevBuf<int32_t> dw((size_t)nslices, &setup_mem());
       hipLaunchKernelGGL(k_slice_width, dim3(pgrid(nslices)), dim3(PB), 0, 0, M.nrows, D.rp.get(), dw.get());
       check("k_slice_width");
       hip_check(hipMemcpy(w.data(), dw.get(), (size_t)nslices * 4, hipMemcpyDeviceToHost), "hipMemcpy D2H");
@@ -220,7 +220,7 @@ void pack_device(DMat<T> &M, const DCsr &D, MemCounter *mc, int force_group) {
 template <class T>
 void smoother_data_device(const DCsr &A, DCsr &lo, DCsr &up, DevBuf<T> &dinv, DevBuf<T> &dl1inv, MemCounter *mc) {
   const int32_t n = A.nr;
-  DevBuf<int32_t> nlo((size_t)std::max(n, 1), nullptr), nup((size_t)std::max(n, 1), nullptr);
+  DevBuf<int32_t> nlo((size_t)std::max(n, 1), &setup_mem()), nup((size_t)std::max(n, 1), &setup_mem());
   if (n > 0) {
     hipLaunchKernelGGL(k_strict_count, dim3(pgrid(n)), dim3(PB), 0, 0, n, A.rp.get(), A.ci.get(), nlo.get(),
                        nup.get());
@@ -238,14 +238,14 @@ void smoother_data_device(const DCsr &A, DCsr &lo, DCsr &up, DevBuf<T> &dinv, De
   }
   lo.nnz = lrp[n];
   up.nnz = urp[n];
-  lo.rp.alloc(lrp.size(), nullptr);
+  lo.rp.alloc(lrp.size(), &setup_mem());
   lo.rp.upload(lrp.data(), lrp.size());
-  up.rp.alloc(urp.size(), nullptr);
+  up.rp.alloc(urp.size(), &setup_mem());
   up.rp.upload(urp.data(), urp.size());
-  lo.ci.alloc((size_t)std::max<int64_t>(lo.nnz, 1), nullptr);
-  lo.v.alloc((size_t)std::max<int64_t>(lo.nnz, 1), nullptr);
-  up.ci.alloc((size_t)std::max<int64_t>(up.nnz, 1), nullptr);
-  up.v.alloc((size_t)std::max<int64_t>(up.nnz, 1), nullptr);
+  lo.ci.alloc((size_t)std::max<int64_t>(lo.nnz, 1), &setup_mem());
+  lo.v.alloc((size_t)std::max<int64_t>(lo.nnz, 1), &setup_mem());
+  up.ci.alloc((size_t)std::max<int64_t>(up.nnz, 1), &setup_mem());
+  up.v.alloc((size_t)std::max<int64_t>(up.nnz, 1), &setup_mem());
   dinv.alloc((size_t)std::max(n, 1), mc);
   dl1inv.alloc((size_t)std::max(n, 1), mc);
   if (n > 0) {

@@ -37,16 +37,16 @@ struct LayoutCount {
   void col(int64_t offset) {
     if (offset < -32768 || offset > 32767) narrow = false;
   }
-  // device bytes of the DMat<T> of nr rows (DMat::build's layout choice, DevBuf's rounding of empty buffers)
+  // device bytes of the DMat<T> of nr rows: DMat::build's layout choice, and the size class each of its
+  // three buffers (pointers, column indices, values) allocates
   template <class T>
   int64_t bytes(int32_t nr, int force_group = 0) const {
-    auto r1 = [](int64_t n) { return n == 0 ? (int64_t)1 : n; };
     const int group = force_group > 0 ? force_group : choose_group(nr, nnz);
     const int64_t ib = narrow ? 2 : 4;
-    if (group > 1) return 4 * r1((int64_t)nr + 1) + (ib + (int64_t)sizeof(T)) * r1(nnz);
+    if (group > 1) return alloc_bytes((int64_t)nr + 1, 4) + alloc_bytes(nnz, ib) + alloc_bytes(nnz, sizeof(T));
     const int64_t nslices = ((int64_t)nr + SELL_C - 1) / SELL_C;
     const int64_t stored = sell_stored + (int64_t)slice_w * SELL_C;  // the last, partial slice
-    return 4 * (nslices + 1) + (ib + (int64_t)sizeof(T)) * r1(stored);
+    return alloc_bytes(nslices + 1, 4) + alloc_bytes(stored, ib) + alloc_bytes(stored, sizeof(T));
   }
 };
 
@@ -117,28 +117,32 @@ int64_t solver_footprint(const HostHierarchy &H, int m) {
   for (int l = 0; l < nl; ++l) {
     const HostLevel &h = H.lv[l];
     const int64_t n = h.A.nr;
-    total += 2 * S * n;
+    total += 2 * alloc_bytes(n, S);  // b, x
     if (l == nl - 1) break;
     // A, its strict parts and (level 0) its FP64 copy from one pass; P and R from one pass over P
     const MatrixShape ms = matrix_shape(h.A);
     const auto pr = transfer_shape(h.P);
     if (l == 0) total += ms.all.bytes<double>(h.A.nr, 1);
-    total += ms.all.bytes<T>(h.A.nr) + pr.first.bytes<T>(h.P.nr) + 2 * S * n + 4 * S * n;
+    // A, P, then D^-1, D_l1^-1, r, f, g1, g2
+    total += ms.all.bytes<T>(h.A.nr) + pr.first.bytes<T>(h.P.nr) + 6 * alloc_bytes(n, S);
     total += h.host_restriction ? mat_alloc_bytes<T>(h.R) : pr.second.bytes<T>(h.P.nc);
     total += h.host_smoother ? mat_alloc_bytes<T>(h.pgs_lo) + mat_alloc_bytes<T>(h.pgs_up)
                              : ms.lo.bytes<T>(h.A.nr) + ms.up.bytes<T>(h.A.nr);
-    if (h.has_ilu) total += mat_alloc_bytes<T>(h.ilu_lo) + mat_alloc_bytes<T>(h.ilu_up) + S * n;
+    if (h.has_ilu) total += mat_alloc_bytes<T>(h.ilu_lo) + mat_alloc_bytes<T>(h.ilu_up) + alloc_bytes(n, S);
   }
   const int64_t nc = H.lv.back().A.nr;
   // dense inverse: CSR with 64 lanes per row (one SELL slice when nc == 1); columns always fit 16 bits
-  total += nc > 1 ? 4 * (nc + 1) + (2 + S) * nc * nc : 4 * 2 + (2 + S) * SELL_C;
+  total += nc > 1 ? alloc_bytes(nc + 1, 4) + alloc_bytes(nc * nc, 2) + alloc_bytes(nc * nc, S)
+                  : alloc_bytes(2, 4) + alloc_bytes(SELL_C, 2) + alloc_bytes(SELL_C, S);
   if (nl == 1) total += mat_alloc_bytes<double>(H.lv[0].A, 1);
   const int64_t n0 = H.lv[0].A.nr;
   const int64_t nred = blocks_for(n0);
-  total += 8 * (std::max<int64_t>(nred, 1) + 8) + (int64_t)sizeof(KState);
+  total += alloc_bytes(std::max<int64_t>(nred, 1) + 8, 8) + alloc_bytes(1, sizeof(KState));
+  // Krylov workspace: V, Z, w, the FP32 copy of v, the fused reduction's partial sums, its results
   const int64_t ld = (n0 + 63) / 64 * 64;
   const int64_t nblk = dot_blocks(n0);
-  total += 8 * ld * (m + 2) + S * ld * m + 8 * n0 + (S == 4 ? 4 * n0 : 0) + 8 * nblk * 2 * (m + 2) + 16 * (m + 2);
+  total += alloc_bytes(ld * (m + 2), 8) + alloc_bytes(ld * m, S) + alloc_bytes(n0, 8) +
+           (S == 4 ? alloc_bytes(n0, S) : 0) + alloc_bytes(nblk * 2 * (m + 2), 8) + alloc_bytes(2 * (m + 2), 8);
   return total;
 }
 
@@ -707,6 +711,7 @@ class Server final : public ServerBase {
     s.peak_device_bytes = peak_;
     s.peak_inflight = peak_inflight_;
     s.footprint_mismatches = footprint_mismatches_;
+    s.peak_setup_device_bytes = setup_mem().peak.load();
     return s;
   }
 
@@ -736,7 +741,8 @@ class Server final : public ServerBase {
       try {
         if (r->sp.coarsen == NAMG_COARSEN_PMIS) r->sp.device = p_.device;  // device setup on the server's GPU
         r->H = std::make_unique<HostHierarchy>(build_hierarchy(std::move(r->A), r->sp));
-        r->footprint = solver_footprint<T>(*r->H, r->p.restart) + 16 * (int64_t)r->H->lv[0].A.nr;
+        // the solver, and the request's b and x
+        r->footprint = solver_footprint<T>(*r->H, r->p.restart) + 2 * alloc_bytes(r->H->lv[0].A.nr, 8);
         r->A = HostCsr{};
       } catch (const SetupError &e) {
         std::lock_guard<std::mutex> lk(mu_);
@@ -784,7 +790,7 @@ class Server final : public ServerBase {
         r->sv = std::make_unique<Solver<T>>(*r->H, p_.device);
         r->H->device_levels.reset();  // packed into the solver's layouts; the blocks go back to the cache
         r->sv->reserve_workspace(r->p.restart);
-        if (r->sv->device_bytes() + 16 * (int64_t)n != r->footprint) {
+        if (r->sv->device_bytes() + 2 * alloc_bytes(n, 8) != r->footprint) {
           std::lock_guard<std::mutex> lk(mu_);
           footprint_mismatches_++;
         }
@@ -901,6 +907,10 @@ class Server final : public ServerBase {
       try {
         eng_.tick(slots);
       } catch (const HipError &e) {
+        // every in-flight solve shared the failed batch; launches queued before the error may still write
+        // to their buffers, so the stream drains before the finisher releases them
+        (void)hipStreamSynchronize(eng_.stream());
+        (void)hipGetLastError();
         for (auto *sl : slots) {
           sl->status = e.code;
           sl->err = e.msg;

@@ -242,7 +242,7 @@ class Solver final : public SolverBase {
     if (pinned_) (void)hipHostFree(pinned_);
   }
 
-  int64_t device_bytes() const override { return mc_.bytes; }
+  int64_t device_bytes() const override { return mc_.bytes.load(); }
 
   // Allocate the Krylov workspace for restart m ahead of the first solve (used by serving).
   void reserve_workspace(int m) {
@@ -1302,7 +1302,9 @@ int namg_server_create(const namg_server_params *p, namg_server **out) {
       namg::DeviceGuard g(q.device);
       size_t free_b = 0, total_b = 0;
       namg::hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
-      q.hbm_budget = (int64_t)total_b - ((int64_t)16 << 30);
+      // other users of the device, and device setup memory (uploads, scratch, kept levels), which
+      // admission does not count
+      q.hbm_budget = (int64_t)total_b - ((int64_t)16 << 30) - namg::SETUP_DEVICE_RESERVE;
       if (q.hbm_budget <= 0) q.hbm_budget = (int64_t)total_b / 2;
     }
     auto s = std::make_unique<namg_server>();

@@ -6,7 +6,10 @@ The expected values were written by tests/golden/make_golden.py, which calls onl
 every level's size and C/F splitting (SHA-256), the iteration count, the residual estimate after every
 iteration, and 4096 entries of the solution at seeded positions. The true residual of the GPU solution
 is recomputed here with an FP64 SpMV on the host. FP64 bounds: the sampled iterate within 1e-12 of
-max|x|, every residual estimate within 1e-12 relative; measured gaps are printed (PARITY-GAP lines).
+max|x|, every residual estimate within 1e-12 of the initial relative residual (1, from x0 = 0; the first
+estimate within 1e-12 relative); measured gaps are printed (PARITY-GAP lines), the largest value-by-value relative one too. The
+estimate |g_i|/||b|| is a relative residual: summation order perturbs it by about eps ||r_0|| however small
+|g_i| has become, so it is compared in the same max-norm sense as the iterate.
 Also at full size: C3 (192^3) and the three orderings of C4 (128^3, GMRES(50)).
 """
 import hashlib
@@ -76,14 +79,19 @@ def _check_fp64_against_golden(namg, label, A, b, st, x, golden):
     xmax = golden["x_max_abs"]
     gx = float(np.abs(x[idx] - np.asarray(golden["sample_x"])).max() / xmax)
     h, gh_ref = np.asarray(st["hist"]), np.asarray(golden["hist"])
-    gh = float((np.abs(h - gh_ref) / np.abs(gh_ref)).max()) if h.shape == gh_ref.shape else float("inf")
+    assert h.shape == gh_ref.shape, (h.shape, gh_ref.shape)
+    d = np.abs(h - gh_ref)
+    gh = float(d.max())  # the estimates are relative to ||b||, and x0 = 0: the initial one is 1
+    gh0 = float(d[0] / abs(gh_ref[0]))
+    ghv = float((d / np.abs(gh_ref)).max())
     gn = abs(np.linalg.norm(x) - golden["x_norm2"]) / golden["x_norm2"]
     res = np.linalg.norm(b - O.spmv(A, x)) / np.linalg.norm(b)
     print(f"PARITY-GAP {label} iters={st['iters']} (oracle {golden['iters']}) x_sample={gx:.2e} hist={gh:.2e} "
-          f"norm={gn:.2e} relres={res:.3e}")
+          f"hist_first={gh0:.2e} hist_value_by_value={ghv:.2e} norm={gn:.2e} relres={res:.3e}")
     assert st["status"] == namg.OK
     assert st["iters"] == golden["iters"] and st["cycles"] == golden["cycles"]
     assert gh <= 1e-12, gh
+    assert gh0 <= 1e-12, gh0
     assert gx <= 1e-12, gx
     assert gn <= 1e-12, gn
     assert np.abs(x).max() == pytest.approx(xmax, rel=1e-12)
@@ -104,7 +112,7 @@ def test_stop_after_k_iterations(namg, golden, system):
     for k in (1, golden["iters"] // 2, golden["iters"] - 1):
         st, _ = _solve(namg, H, b, max_iters=k)
         assert st["status"] == namg.NOT_CONVERGED and st["iters"] == k
-        assert st["relres_est"] == pytest.approx(golden["hist"][k - 1], rel=1e-12), k
+        assert abs(st["relres_est"] - golden["hist"][k - 1]) <= 1e-12, k
 
 
 def test_fp32_preconditioner_full_size(namg, golden, system):

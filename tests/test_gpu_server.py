@@ -165,8 +165,13 @@ def test_device_setup_requests_in_the_mix(namg):
               for j in range(len(systems))]
     tickets = [srv.submit(A, b, **sp) for (A, b), sp in zip(systems, setups)]
     results = [srv.wait(t) for t in tickets]
-    # the footprint of a device-built hierarchy (no host copy of the polynomial-GS data) is exact too
-    assert srv.stats()["footprint_mismatches"] == 0
+    # the footprint of a device-built hierarchy (no host copy of the polynomial-GS data) is exact too, and
+    # the device setups' own memory, which no footprint covers, is reported
+    c = srv.stats()
+    assert c["footprint_mismatches"] == 0
+    A0 = max((A for (A, _), sp in zip(systems, setups) if sp.get("coarsen") == namg.COARSEN_PMIS),
+             key=lambda A: A.n)
+    assert c["peak_setup_device_bytes"] >= 12 * len(A0.vals)  # at least one uploaded A_0 (columns + values)
     srv.close()
     for (A, b), sp, r in zip(systems, setups, results):
         H = namg.Hierarchy(A, device=0, **sp)
