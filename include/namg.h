@@ -153,6 +153,24 @@ int namg_setup(int32_t n, const int32_t *rowptr, const int32_t *colind, const do
 int namg_solve(namg_hier *h, const double *b_dev, double *x_dev, const namg_solve_params *p, void *stream,
                namg_solve_stats *st);
 
+/* For callers that cannot allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc): namg_solve with the same arguments, kernels and results (bit for bit),
+ * but its Krylov workspace comes from a static per-device array of NAMG_NOALLOC_SCRATCH_BYTES that the
+ * library holds on every device it runs on until the process ends, not from the hierarchy's own buffers;
+ * the call makes no hipMalloc, hipFree or other allocating call. The workspace for n rows and restart m,
+ * with ld = n rounded up to a multiple of 64, nb = the multi-dot's block count (at most 2048) and
+ * s = 8 (FP64) or 4 (FP32_PRECOND), is the sum of these parts, each rounded up to 256 bytes:
+ *   8 ld (m+2) [V], s ld m [Z], 8 n [w], (FP32_PRECOND only) 4 n, 16 nb (m+2), 16 (m+2).
+ * A larger workspace is refused with NAMG_E_INVALID before any work is issued (at m = 30 up to 531 520 rows
+ * fit in FP64, 690 048 with FP32_PRECOND), as are diagnostics != 0 and tri_mode NAMG_TRI_DIRECT on a
+ * hierarchy that has not yet run a direct solve through namg_solve (both allocate on first use). Every
+ * call on a device shares that device's array and leaves its contents behind (no part of it needs to start
+ * at zero): calls that overlap in time on one device, from two host threads or on two streams, race and
+ * corrupt each other's results. */
+#define NAMG_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int namg_solve_noalloc(namg_hier *h, const double *b_dev, double *x_dev, const namg_solve_params *p,
+                       void *stream, namg_solve_stats *st);
+
 
 /* One preconditioner application x = M^{-1} b: one V-cycle with zero initial guess (Section 5).
  * b_dev, x_dev: n float64 device vectors (x written). */

@@ -27,11 +27,13 @@ COARSEN_RS, COARSEN_PMIS = 0, 1
 DIAG_LOSS_ORTH, DIAG_PHASE_TIMES = 1, 2
 OP_SPMV, OP_RESIDUAL, OP_SMOOTH_PRE, OP_SMOOTH_POST, OP_RESTRICT, OP_PROLONG, OP_COARSE, OP_SPMV64 = range(8)
 MAX_LEVELS = 32
+NOALLOC_SCRATCH_BYTES = 256 << 20  # NAMG_NOALLOC_SCRATCH_BYTES
 
 KF_NONE, KF_NEUMANN, KF_RESIDUAL, KF_SPMV, KF_PROLONG, KF_GMRES_SPMV, KF_MULTIDOT, KF_PROJECT, KF_TRI = range(9)
 
 EXPORTED = (
-    "namg_default_setup_params", "namg_default_solve_params", "namg_setup", "namg_solve", "namg_vcycle",
+    "namg_default_setup_params", "namg_default_solve_params", "namg_setup", "namg_solve", "namg_solve_noalloc",
+    "namg_vcycle",
     "namg_apply", "namg_profile_kernel", "namg_profile_read", "namg_hier_info", "namg_level_sizes",
     "namg_export_level", "namg_export_ilu", "namg_ilu_diagnostics", "namg_tri_jacobi_residuals",
     "namg_us_powers", "namg_destroy", "namg_last_error", "namg_default_server_params", "namg_server_create",
@@ -127,6 +129,7 @@ def _load():
         C.POINTER(C.c_int64)
     lib.namg_setup.argtypes = [C.c_int32, i32p, i32p, f64p, C.POINTER(SetupParams), C.POINTER(vp)]
     lib.namg_solve.argtypes = [vp, vp, vp, C.POINTER(SolveParams), vp, C.POINTER(SolveStats)]
+    lib.namg_solve_noalloc.argtypes = [vp, vp, vp, C.POINTER(SolveParams), vp, C.POINTER(SolveStats)]
     lib.namg_vcycle.argtypes = [vp, vp, vp, C.POINTER(SolveParams), vp]
     lib.namg_apply.argtypes = [vp, C.c_int, C.c_int, C.POINTER(SolveParams), vp, vp, vp, vp]
     lib.namg_profile_kernel.argtypes = [vp, C.c_int, C.c_int, C.c_int]
@@ -306,6 +309,11 @@ class Hierarchy:
         """namg_solve on device tensors b (read) and x (initial guess in, solution out). history=True also
         returns the residual estimate after every iteration ("hist")."""
         return self._solve(_lib.namg_solve, b, x, stream, history, params)
+
+    def solve_noalloc(self, b, x, stream=None, history=False, **params) -> dict:
+        """namg_solve_noalloc: the same solve with the Krylov workspace in the library's static per-device
+        array (NOALLOC_SCRATCH_BYTES); no device allocation."""
+        return self._solve(_lib.namg_solve_noalloc, b, x, stream, history, params)
 
     def _solve(self, entry, b, x, stream, history, params) -> dict:
         p = solve_params(**params)

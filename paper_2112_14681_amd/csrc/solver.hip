@@ -13,6 +13,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <type_traits>
@@ -122,6 +123,8 @@ class SolverBase {
  public:
   virtual ~SolverBase() = default;
   virtual int solve(const double *b, double *x, const namg_solve_params &p, hipStream_t s, namg_solve_stats *st) = 0;
+  virtual int solve_in(const double *b, double *x, const namg_solve_params &p, hipStream_t s, namg_solve_stats *st,
+                       void *scratch, size_t scratch_bytes) = 0;
   virtual void vcycle64(const double *b, double *x, const namg_solve_params &p, hipStream_t s) = 0;
   virtual void apply(int level, int op, const namg_solve_params &p, const double *in1, const double *in2, double *out,
                      hipStream_t s) = 0;
@@ -223,6 +226,12 @@ class Solver final : public SolverBase {
     anorm_inf_ = H.anorm_inf;
     const int32_t n = lv_[0].n;
     nblk_red_ = (int32_t)blocks_for(n);
+    ldv_ = ((int64_t)n + 63) / 64 * 64;
+    ldz_ = ldv_;
+    nblk_dot_ = dot_blocks(n);
+    rows_per_dot_ = dot_rows_per_block(n);
+    hip_check(hipEventCreate(&wall_ev_[0]), "hipEventCreate");
+    hip_check(hipEventCreate(&wall_ev_[1]), "hipEventCreate");
     red_.alloc(std::max<int32_t>(nblk_red_, 1) + 8, &mc_);
     kst_.alloc(1, &mc_);
     hip_check(hipHostMalloc((void **)&pinned_, 64, hipHostMallocMapped), "hipHostMalloc");
@@ -357,14 +366,70 @@ class Solver final : public SolverBase {
   // ------------------------------------------------------------------------------------------- solve
   int solve(const double *b, double *x, const namg_solve_params &p, hipStream_t s, namg_solve_stats *stats) override {
     DeviceGuard g(dev_);
+    ensure_workspace(p.restart);
+    const Workspace ws{V_.get(), w_.get(), dot_.get(), cd_.get(), Z_.get(), vin_.get()};
+    return run(b, x, p, s, stats, ws);
+  }
+
+  // The same solve with its Krylov workspace carved out of caller-provided device memory of scratch_bytes
+  // bytes instead of the hierarchy's own buffers: nothing is allocated on the device. The options that
+  // allocate on first use (the direct comparators' schedules and graphs, the Gram matrix and phase events
+  // of the diagnostics) are refused before any work is issued.
+  int solve_in(const double *b, double *x, const namg_solve_params &p, hipStream_t s, namg_solve_stats *stats,
+               void *scratch, size_t scratch_bytes) override {
+    DeviceGuard g(dev_);
+    if (p.tri_mode == NAMG_TRI_DIRECT && !direct_ready_)
+      throw SetupError{NAMG_E_INVALID, "the direct comparators allocate their level schedules on first use; run "
+                                       "one namg_solve with tri_mode DIRECT on this hierarchy first"};
+    if (p.diagnostics != 0) throw SetupError{NAMG_E_INVALID, "diagnostics allocate on first use; pass 0"};
+    size_t off[7];
+    const size_t need = workspace_layout(p.restart, off);
+    if (need > scratch_bytes)
+      throw SetupError{NAMG_E_INVALID, "the Krylov workspace needs " + std::to_string(need) +
+                                           " bytes (n = " + std::to_string(lv_[0].n) + ", restart " +
+                                           std::to_string(p.restart) + "); the static workspace holds " +
+                                           std::to_string(scratch_bytes)};
+    char *base = static_cast<char *>(scratch);
+    const Workspace ws{reinterpret_cast<double *>(base + off[0]), reinterpret_cast<double *>(base + off[2]),
+                       reinterpret_cast<double *>(base + off[4]), reinterpret_cast<double *>(base + off[5]),
+                       reinterpret_cast<T *>(base + off[1]),
+                       std::is_same<T, double>::value ? nullptr : reinterpret_cast<T *>(base + off[3])};
+    return run(b, x, p, s, stats, ws);
+  }
+
+ private:
+  // The Krylov workspace of one solve: basis V (m + 2 columns of ldv_), w = A z, the multi-dot partials,
+  // the reduced inner products, the preconditioned vectors Z (m columns of ldz_) and, in FP32 mode, the
+  // low-precision copy of the V-cycle's input.
+  struct Workspace {
+    double *V, *w, *dot, *cd;
+    T *Z, *vin;
+  };
+
+  // Byte offsets of the workspace parts for restart m in one block (V, Z, w, vin, dot partials, cd; each
+  // part starts on a 256-byte boundary); off[6] and the return value are the total size.
+  size_t workspace_layout(int m, size_t off[7]) const {
+    const int32_t n = lv_[0].n;
+    const size_t part[6] = {8 * (size_t)ldv_ * (m + 2),
+                            sizeof(T) * (size_t)ldz_ * m,
+                            8 * (size_t)n,
+                            std::is_same<T, double>::value ? 0 : sizeof(T) * (size_t)n,
+                            8 * (size_t)nblk_dot_ * 2 * (m + 2),
+                            8 * (size_t)2 * (m + 2)};
+    size_t at = 0;
+    for (int q = 0; q < 6; ++q) {
+      off[q] = at;
+      at += (part[q] + 255) / 256 * 256;
+    }
+    off[6] = at;
+    return at;
+  }
+
+  int run(const double *b, double *x, const namg_solve_params &p, hipStream_t s, namg_solve_stats *stats,
+          const Workspace &ws) {
     const int32_t n = lv_[0].n;
     const int m = p.restart;
-    ensure_workspace(m);
     alg_ = 0.0;
-    if (!wall_ev_[0]) {
-      hip_check(hipEventCreate(&wall_ev_[0]), "hipEventCreate");
-      hip_check(hipEventCreate(&wall_ev_[1]), "hipEventCreate");
-    }
     hip_check(hipEventRecord(wall_ev_[0], s), "hipEventRecord");
     const CycleOpts o = cycle_opts(p);
     if (o.tri_mode == NAMG_TRI_DIRECT) ensure_direct();
@@ -375,11 +440,11 @@ class Solver final : public SolverBase {
     std::vector<size_t> marks;  // four phase events per Arnoldi step (before the V-cycle, after it, after
                                 // the product, after the column completion)
     KState *ks = kst_.get();
-    double *cd = cd_.get();
-    double *V = V_.get();
-    T *Z = Z_.get();
-    double *w = w_.get();
-    T *vin = std::is_same<T, double>::value ? nullptr : vin_.get();
+    double *cd = ws.cd;
+    double *V = ws.V;
+    T *Z = ws.Z;
+    double *w = ws.w;
+    T *vin = std::is_same<T, double>::value ? nullptr : ws.vin;
     const MatView<double> M64 = A64_.view();
 
     const double beta = std::sqrt(norm2sq(b, n, s));
@@ -434,8 +499,8 @@ class Solver final : public SolverBase {
           if (timing) marks.push_back(phase_mark(s));
           const int32_t ncols = i + 1;
           launch(NAMG_KF_MULTIDOT, 0, 8.0 * n * (ncols + 1), &k_multidot<8>, nblk_dot_, s, (const double *)V, ldv_,
-                 ncols, (const double *)w, n, rows_per_dot_, dot_.get(), nblk_dot_);
-          launch(-1, 0, 0.0, &k_colreduce, (unsigned)(2 * ncols), s, (const double *)dot_.get(), nblk_dot_, cd);
+                 ncols, (const double *)w, n, rows_per_dot_, ws.dot, nblk_dot_);
+          launch(-1, 0, 0.0, &k_colreduce, (unsigned)(2 * ncols), s, (const double *)ws.dot, nblk_dot_, cd);
           launch_small(&k_step, s, ks, (const double *)cd, i, t_mode(p));
           launch(NAMG_KF_PROJECT, 0, 8.0 * n * (i + 4) + (vin ? S * n : 0.0), &k_project<T>, blocks_for(n), s, V,
                  ldv_, i, (const double *)w, (const KState *)ks, n, vin, red_.get());
@@ -456,7 +521,7 @@ class Solver final : public SolverBase {
             break;
           }
         }
-        if (orth) st.loss_orth = std::max(st.loss_orth, loss_of_orthogonality(k, s));
+        if (orth) st.loss_orth = std::max(st.loss_orth, loss_of_orthogonality(k, m, ws, s));
         launch_small(&k_backsolve, s, ks, k);
         launch(-1, 0, (double)n * (S * k + 16.0), &k_update_x<T>, blocks_for(n), s, (const T *)Z, ldz_, k,
                (const KState *)ks, x, n);
@@ -583,14 +648,14 @@ class Solver final : public SolverBase {
   // ||I - G||_F for the Gram matrix G of the cycle's basis V_{k+1} (Section 3's loss of orthogonality): column
   // j's inner products with columns 0..j come from the fused reduction with ncols = j + 1 and no w. Columns
   // 0..k-1 are normalised; column k (v_{k+1}, lagged) is scaled by its own reduced norm.
-  double loss_of_orthogonality(int k, hipStream_t s) {
+  double loss_of_orthogonality(int k, int m, const Workspace &ws, hipStream_t s) {
     const int32_t n = lv_[0].n;
-    const int ld = ws_m_ + 2;
+    const int ld = m + 2;
     if (gram_.size() < (size_t)ld * ld) gram_.alloc((size_t)ld * ld, &mc_);
     for (int j = 0; j <= k; ++j) {
-      launch(-1, 0, 8.0 * n * (j + 1), &k_multidot<8>, nblk_dot_, s, (const double *)V_.get(), ldv_, (int32_t)(j + 1),
-             (const double *)nullptr, n, rows_per_dot_, dot_.get(), nblk_dot_);
-      launch(-1, 0, 0.0, &k_colreduce, (unsigned)(j + 1), s, (const double *)dot_.get(), nblk_dot_,
+      launch(-1, 0, 8.0 * n * (j + 1), &k_multidot<8>, nblk_dot_, s, (const double *)ws.V, ldv_, (int32_t)(j + 1),
+             (const double *)nullptr, n, rows_per_dot_, ws.dot, nblk_dot_);
+      launch(-1, 0, 0.0, &k_colreduce, (unsigned)(j + 1), s, (const double *)ws.dot, nblk_dot_,
              gram_.get() + (int64_t)j * ld);
     }
     std::vector<double> G((size_t)ld * ld);
@@ -628,14 +693,10 @@ class Solver final : public SolverBase {
   void ensure_workspace(int m) {
     if (ws_m_ >= m) return;
     const int32_t n = lv_[0].n;
-    ldv_ = ((int64_t)n + 63) / 64 * 64;
-    ldz_ = ldv_;
     V_.alloc((size_t)ldv_ * (m + 2), &mc_);
     Z_.alloc((size_t)ldz_ * m, &mc_);
     w_.alloc(n, &mc_);
     if (!std::is_same<T, double>::value) vin_.alloc(n, &mc_);
-    nblk_dot_ = dot_blocks(n);
-    rows_per_dot_ = dot_rows_per_block(n);
     dot_.alloc((size_t)nblk_dot_ * 2 * (m + 2), &mc_);
     cd_.alloc((size_t)2 * (m + 2), &mc_);
     ws_m_ = m;
@@ -1000,6 +1061,31 @@ class Solver final : public SolverBase {
 
 #include "server.hpp"
 
+// Krylov workspace of namg_solve_noalloc: one static array per device, held from the library's load until
+// the process ends. Host code never passes the array's name to a kernel (on the host it names a host-side
+// stand-in); it uses the device address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[NAMG_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;  // device ordinal -> address of that device's copy of `scratch`
+
+// The device address of `scratch` on device dev, resolved once per device with dev current.
+void *scratch_on(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) return it->second;
+  namg::DeviceGuard g(dev);
+  void *ptr = nullptr;
+  namg::hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+  if (!ptr) throw namg::HipError{NAMG_E_HIP, "hipGetSymbolAddress(scratch) returned a null address"};
+  g_scratch_ptr.emplace(dev, ptr);
+  return ptr;
+}
+
+}  // namespace
+
 struct namg_hier {
   namg::HostHierarchy host;
   int precision = NAMG_FP64;
@@ -1110,6 +1196,16 @@ int namg_solve(namg_hier *h, const double *b_dev, double *x_dev, const namg_solv
     if (!p || !b_dev || !x_dev) throw namg::SetupError{NAMG_E_INVALID, "null argument"};
     namg::validate_solve_params(*p);
     return device_of(h)->solve(b_dev, x_dev, *p, (hipStream_t)stream, st);
+  });
+}
+
+int namg_solve_noalloc(namg_hier *h, const double *b_dev, double *x_dev, const namg_solve_params *p, void *stream,
+                       namg_solve_stats *st) {
+  return guarded([&]() -> int {
+    if (!p || !b_dev || !x_dev) throw namg::SetupError{NAMG_E_INVALID, "null argument"};
+    namg::validate_solve_params(*p);
+    namg::SolverBase *sv = device_of(h);
+    return sv->solve_in(b_dev, x_dev, *p, (hipStream_t)stream, st, scratch_on(h->device), NAMG_NOALLOC_SCRATCH_BYTES);
   });
 }
 
