@@ -54,7 +54,9 @@ def _args():
     ap.add_argument("--nonnormality", action="store_true",
                     help="the factor study of Sections 5.3.2 to 5.3.4 instead of the benchmark: orderings of C4 (Table 2) "
                          "and an ILUT fill sweep (Tables 3-5), with GMRES iterations when a GPU is present")
-    ap.add_argument("--nn-N", type=int, default=128, help="grid size of the ordering study")
+    ap.add_argument("--nn-N", type=int, default=128, help="grid size of the ordering studies")
+    ap.add_argument("--orderings", action="store_true",
+                    help="only the convection-diffusion orderings: iterations, ms and GMRES-product bandwidth")
     ap.add_argument("--nn-fill-N", type=int, default=64, help="grid size of the fill sweep")
     return ap.parse_args()
 
@@ -268,6 +270,35 @@ def contract_figures(namg, torch, steps):
     return out
 
 
+def orderings_study(namg, torch, N, steps):
+    """The convection-diffusion system (Peclet 10, N^3) in natural, random and RCM-of-random order with its
+    configuration (ILU(0) Neumann t = 3 on the finest level, FP32 preconditioner, FP64 GMRES(50), tol 1e-8):
+    iterations, ms per solve and the achieved bandwidth of the GMRES product w = A z (FP64 A, FP32 z; the
+    kernel's own bytes over its live hipEvent time) and of the finest level's Neumann terms, per ordering."""
+    from workloads import config_system
+
+    out = {}
+    kw = dict(tol=1e-8, restart=50, smoother=namg.SMOOTH_ILU0, tri_mode=namg.TRI_NEUMANN, inner_terms=3)
+    for name in ("c4n", "c4r", "c4rcm"):
+        A, b, _ = config_system(name, N)
+        H = namg.Hierarchy(A, device=0, precision=namg.FP32_PRECOND, ilu_levels=1, max_coarse=1000)
+        bt = torch.from_numpy(b).to("cuda:0")
+        xt = torch.zeros_like(bt)
+        ms, st = _time_solves(torch, H, bt, xt, kw, steps, 1)
+        rates = {}
+        for key, family in (("gmres_spmv_GBps", namg.KF_GMRES_SPMV), ("level0_neumann_GBps", namg.KF_NEUMANN)):
+            H.profile_kernel(family, 0, 1)
+            _time_solves(torch, H, bt, xt, kw, 1, 0)
+            pr = H.profile_read()
+            H.profile_kernel(namg.KF_NONE)
+            rates[key] = round(pr["alg_bytes"] / (pr["total_ms"] * 1e-3) / 1e9, 1) if pr["launches"] else None
+        out[name] = {"ms": round(ms, 3), "iters": st[-1]["iters"], "relres": st[-1]["relres_true"], **rates}
+        H.close()
+        print(f"[orderings] {name} done", file=sys.stderr, flush=True)
+    return {"metric": "convection-diffusion orderings: iterations, ms and bandwidth",
+            "workload": f"c4 {N}^3 Peclet 10, ILU(0) t = 3, FP32 preconditioner, GMRES(50)", **out}
+
+
 def cpu_baseline(A, b, kw, gpu_iters, max_coarse):
     """The oracle (single-threaded FP64 C++) on the same system and hierarchy configuration: setup
     excluded, full solve timed."""
@@ -379,6 +410,10 @@ def main():
         print(json.dumps(nonnormality_study(namg, torch, args.nn_N, args.nn_fill_N)), flush=True)
         return
 
+    if args.orderings:
+        print(json.dumps(orderings_study(namg, torch, args.nn_N, args.steps)), flush=True)
+        return
+
     if args.serve_only:
         print(json.dumps({"metric": "served latency of the pressure-system request stream",
                           "served": served_stream(namg, args.serve_requests, args.serve_inflight,
@@ -445,9 +480,14 @@ def main():
         "alg_GBps": round(gbs, 1),
     }
     if prof["launches"]:
-        per_launch_bytes = prof["alg_bytes"] / prof["launches"]
+        # one launch is one pass of a Neumann inner term over a strict half of the finest operator; its
+        # algorithmic bytes per pass: ((nnz - n) / 2) (s + 4) + 4 (n + 1) + 4 s n (s = 8 or 4; the strict
+        # half's values with int32 indices, its row pointers, and the vectors r, D^-1, g_in, g_out)
+        s_val = 8 if prec == namg.FP64 else 4
+        pass_bytes = (A.nnz - A.n) / 2 * (s_val + 4) + 4 * (A.n + 1) + 4 * s_val * A.n
+        kernel_bytes = prof["alg_bytes"] / prof["launches"]  # what the kernel itself moves (16-bit offsets)
         per_launch_ms = prof["total_ms"] / prof["launches"]
-        achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
+        achieved = pass_bytes / (per_launch_ms * 1e-3) / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                            "frac": round(achieved / HBM_PEAK_GBPS, 4),
                            "traffic": DOMINANT_TRAFFIC_BYTES.get((meta["name"], meta["N"], args.precision,
@@ -457,14 +497,16 @@ def main():
                            "launches_timed": prof["launches"],
                            "timing": f"hipEvents around every {PROFILE_EVERY}th run of consecutive dispatches",
                            "avg_us": round(per_launch_ms * 1e3, 3),
-                           "alg_MB_per_launch": round(per_launch_bytes / 1e6, 3)}
+                           "alg_MB_per_launch": round(pass_bytes / 1e6, 3),
+                           "kernel_MB_per_launch": round(kernel_bytes / 1e6, 3),
+                           "kernel_GBps": round(kernel_bytes / (per_launch_ms * 1e-3) / 1e9, 1)}
     out["copy_ceiling_GBps"] = round(copy_ceiling(torch), 1)
     out["read_ceiling_GBps"] = round(read_ceiling(torch), 1)
 
     if args.compare:
         # the Table 7 family on this workload: ILUT(1e-2, 5) on the finest level with Jacobi (Neumann) or
         # direct triangular solves next to ILU(0), plus the Table 6 comparator, aggressive coarsening on
-        # the first two levels and the other precision
+        # the first two levels, the other precision and one more Neumann term (t + 1)
         cmp = {}
         ilut = dict(ilu_kind=namg.ILUT, ilut_droptol=1e-2, ilut_lfil=5)
         H_ilut = None
@@ -475,7 +517,8 @@ def main():
                                             prec, ilut),
                                            ("aggressive2", {}, prec, dict(agg_levels=2)),
                                            ("pmis_device_setup", {}, prec, dict(coarsen=namg.COARSEN_PMIS)),
-                                           ("fp32_precond", {}, namg.FP32_PRECOND, None), ("fp64", {}, namg.FP64, None)):
+                                           ("fp32_precond", {}, namg.FP32_PRECOND, None), ("fp64", {}, namg.FP64, None),
+                                           ("inner_terms_4", dict(inner_terms=4), prec, None)):
             if setup2 is ilut:
                 if H_ilut is None:
                     t0 = time.perf_counter()

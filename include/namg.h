@@ -158,11 +158,11 @@ int namg_solve(namg_hier *h, const double *b_dev, double *x_dev, const namg_solv
  * but its Krylov workspace comes from a static per-device array of NAMG_NOALLOC_SCRATCH_BYTES that the
  * library holds on every device it runs on until the process ends, not from the hierarchy's own buffers;
  * the call makes no hipMalloc, hipFree or other allocating call. The workspace for n rows and restart m,
- * with ld = n rounded up to a multiple of 64, nb = the multi-dot's block count (at most 2048) and
+ * with ld = n rounded up to a multiple of 64, nb = the multi-dot's block count (at most 512) and
  * s = 8 (FP64) or 4 (FP32_PRECOND), is the sum of these parts, each rounded up to 256 bytes:
  *   8 ld (m+2) [V], s ld m [Z], 8 n [w], (FP32_PRECOND only) 4 n, 16 nb (m+2), 16 (m+2).
- * A larger workspace is refused with NAMG_E_INVALID before any work is issued (at m = 30 up to 531 520 rows
- * fit in FP64, 690 048 with FP32_PRECOND), as are diagnostics != 0 and tri_mode NAMG_TRI_DIRECT on a
+ * A larger workspace is refused with NAMG_E_INVALID before any work is issued (at m = 30 up to 532 032 rows
+ * fit in FP64, 691 136 with FP32_PRECOND), as are diagnostics != 0 and tri_mode NAMG_TRI_DIRECT on a
  * hierarchy that has not yet run a direct solve through namg_solve (both allocate on first use). Every
  * call on a device shares that device's array and leaves its contents behind (no part of it needs to start
  * at zero): calls that overlap in time on one device, from two host threads or on two streams, race and

@@ -332,6 +332,7 @@ struct DeviceLevels {
 // carry offset 0 (column base(r)) or column 0.
 // Row order and the order of entries within a row are those of the CSR input.
 constexpr int SELL_C = 64;
+constexpr int SELL_C_UNIT = SELL_C;
 constexpr int COL_SHIFT = 20;
 
 __host__ __device__ inline int32_t diag_base(int32_t row, int64_t mul) {
@@ -359,17 +360,73 @@ struct MatView {
   const int32_t *col = nullptr;    // 32-bit columns, or null when col16 is used
   const int16_t *col16 = nullptr;  // 16-bit offsets from diag_base(row, mul), or null
   const T *val = nullptr;
+  const uint64_t *umask = nullptr;  // unit-row SELL (prolongations): per slice, bit l = row 64 s + l is a unit row
+  const int32_t *smeta = nullptr;   // unit-row SELL: per slice, unit rows before it and explicit rows in it
   int64_t mul = 0;
   int32_t nrows = 0;
+  int32_t ncols = 0;   // set by DMat::view (and for the prolongation kernels)
+  int32_t unroll = 4;  // unit-row layout: entries per chunk of the prolongation loop (4 or 8)
 };
+
+// Unit rows of a prolongation. The row of a C point is the unit vector of its coarse index (one entry of
+// value exactly 1), and coarse indices number the C points in fine order. The unit-row SELL layout stores no
+// entries for those rows: within slice s, the l-th explicit row (rank l among the slice's F rows) keeps entry
+// k at ptr[s] + k * m_s + l (m_s explicit rows, padded to the slice's longest explicit row), and the column
+// of a unit row is the number of C points before it. Built from P and its level's C/F splitting cf; it
+// applies when there is a C point and every C row has that form (always, for P of a C/F splitting), else
+// the matrix keeps the plain SELL-64 layout.
+struct UnitRows {
+  bool ok = false;
+  std::vector<uint64_t> mask;   // per slice: bit l set when row 64 s + l is a C point
+  std::vector<int32_t> width;   // per slice: longest explicit row
+  std::vector<int32_t> count;   // per slice: explicit rows
+  std::vector<int32_t> before;  // per slice: C points before it
+  std::vector<int32_t> ptr;     // per slice: first stored slot (nslices + 1 entries)
+  int64_t stored = 0;           // sum over slices of width * count
+};
+
+inline UnitRows unit_rows_of(const HostCsr &P, const std::vector<int8_t> &cf) {
+  UnitRows u;
+  if ((int64_t)cf.size() != (int64_t)P.nr) return u;
+  const int32_t nslices = (P.nr + SELL_C_UNIT - 1) / SELL_C_UNIT;
+  u.mask.assign(nslices, 0);
+  u.width.assign(nslices, 0);
+  u.count.assign(nslices, 0);
+  u.before.assign(nslices, 0);
+  u.ptr.assign(nslices + 1, 0);
+  int64_t units = 0;
+  for (int32_t s = 0; s < nslices; ++s) {
+    u.before[s] = (int32_t)units;
+    for (int32_t r = s * SELL_C_UNIT; r < std::min(P.nr, (s + 1) * SELL_C_UNIT); ++r) {
+      const int32_t len = P.rp[r + 1] - P.rp[r];
+      if (cf[r] == 1) {
+        if (len != 1 || P.v[P.rp[r]] != 1.0 || P.ci[P.rp[r]] != units) return UnitRows{};
+        u.mask[s] |= uint64_t(1) << (r - s * SELL_C_UNIT);
+        ++units;
+      } else {
+        u.width[s] = std::max(u.width[s], len);
+        u.count[s]++;
+      }
+    }
+    u.stored += (int64_t)u.width[s] * u.count[s];
+    if (u.stored > INT32_MAX) return UnitRows{};
+    u.ptr[s + 1] = (int32_t)u.stored;
+  }
+  u.ok = units > 0;
+  return u;
+}
 
 // Layout tuning, read once from the environment (defaults in parentheses):
 //   NAMG_LANE_ENTRIES (8): CSR lane groups are sized so that a lane takes about this many entries;
 //   NAMG_SELL_MIN_ROWS (524288): a matrix with at least this many rows uses SELL-64 whatever its row
-//   length (one lane per row already fills the device).
+//   length (one lane per row already fills the device);
+//   NAMG_WIDE_ROWS (off): SELL-64 matrices whose rows average more entries load them in chunks of eight;
+//   NAMG_UNIT_UNROLL (by row length): 4 or 8 entries per chunk for prolongations in the unit-row layout.
 struct LayoutTuning {
   int lane_entries = 8;
   int64_t sell_min_rows = int64_t(1) << 19;
+  double wide_rows = 1e9;
+  int unit_unroll = 0;  // 0: by the F rows' average length
 };
 
 inline const LayoutTuning &layout_tuning() {
@@ -377,9 +434,17 @@ inline const LayoutTuning &layout_tuning() {
     LayoutTuning v;
     if (const char *e = std::getenv("NAMG_LANE_ENTRIES")) v.lane_entries = std::max(1, std::atoi(e));
     if (const char *e = std::getenv("NAMG_SELL_MIN_ROWS")) v.sell_min_rows = std::max<int64_t>(1, std::atoll(e));
+    if (const char *e = std::getenv("NAMG_WIDE_ROWS")) v.wide_rows = std::atof(e);
+    if (const char *e = std::getenv("NAMG_UNIT_UNROLL")) v.unit_unroll = std::atoi(e) == 8 ? 8 : 4;
     return v;
   }();
   return t;
+}
+
+// Entries per chunk of the row kernels for a matrix in the given layout: 8 for a SELL-64 matrix whose rows
+// average more than NAMG_WIDE_ROWS entries (fewer dependent load rounds per row), else 4.
+inline int choose_unroll(int group, int64_t nrows, int64_t nnz) {
+  return group == 1 && nrows > 0 && (double)nnz > layout_tuning().wide_rows * (double)nrows ? 8 : 4;
 }
 
 // Lanes per row for a matrix with the given shape: one lane when rows are short or the matrix is large
@@ -394,37 +459,72 @@ inline int choose_group(int64_t nrows, int64_t nnz) {
   return g;
 }
 
+// Per-slice (C points before the slice, explicit rows in it) pairs of the unit-row layout.
+inline std::vector<int32_t> unit_meta(const UnitRows &u) {
+  std::vector<int32_t> m(2 * std::max<size_t>(u.mask.size(), 1), 0);
+  for (size_t s = 0; s < u.mask.size(); ++s) {
+    m[2 * s] = u.before[s];
+    m[2 * s + 1] = u.count[s];
+  }
+  return m;
+}
+
 template <class T>
 struct DMat {
   int32_t nrows = 0, ncols = 0, group = 1;
   int64_t nnz = 0, stored = 0, mul = 0;
+  int64_t explicit_nnz = 0, explicit_rows = 0;  // unit-row layout: the entries and count of the explicit rows
   bool narrow = false;
+  bool unit = false;  // the unit-row SELL layout (prolongations, see UnitRows)
+  int unroll = 4;     // entries per chunk of the row kernels (choose_unroll; unit-row layout: see view())
   DevBuf<int32_t> ptr, col;
   DevBuf<int16_t> col16;
   DevBuf<T> val;
+  DevBuf<uint64_t> umask;
+  DevBuf<int32_t> smeta;
   MatView<T> view() const {
     MatView<T> v;
     v.ptr = ptr.get();
     v.col = narrow ? nullptr : col.get();
     v.col16 = narrow ? col16.get() : nullptr;
     v.val = val.get();
+    v.umask = unit ? umask.get() : nullptr;
+    v.smeta = unit ? smeta.get() : nullptr;
     v.mul = mul;
     v.nrows = nrows;
+    v.ncols = ncols;
+    v.unroll = unit ? (layout_tuning().unit_unroll ? layout_tuning().unit_unroll
+                                                   : (explicit_nnz > 4 * explicit_rows ? 8 : 4))
+                    : unroll;
     return v;
   }
-  // algorithmic bytes of one pass over the matrix (entries once, row/slice pointers once)
+  // algorithmic bytes of one pass over the matrix (entries once, row/slice pointers once; in the unit-row
+  // layout the explicit rows' entries and the per-slice mask and counts, unit rows carry no entries)
   double bytes() const {
-    const double nptr = group > 1 ? (double)nrows + 1.0 : (double)((nrows + SELL_C - 1) / SELL_C) + 1.0;
+    const double nslices = (double)((nrows + SELL_C - 1) / SELL_C);
+    if (unit) return (double)explicit_nnz * (sizeof(T) + (narrow ? 2.0 : 4.0)) + 4.0 * (nslices + 1.0) + 16.0 * nslices;
+    const double nptr = group > 1 ? (double)nrows + 1.0 : nslices + 1.0;
     return (double)nnz * (sizeof(T) + (narrow ? 2.0 : 4.0)) + 4.0 * nptr;
   }
 
-  void build(const HostCsr &A, MemCounter *mc, int force_group = 0) {
+  // unit_cf: A is a prolongation and unit_cf its level's C/F splitting; packed in the unit-row layout when
+  // it applies (see UnitRows)
+  void build(const HostCsr &A, MemCounter *mc, int force_group = 0, const std::vector<int8_t> *unit_cf = nullptr) {
     nrows = A.nr;
     ncols = A.nc;
     nnz = A.nnz();
     mul = diag_mul(nrows, ncols);
     narrow = fits_col16(A);
     group = force_group > 0 ? force_group : choose_group(nrows, nnz);
+    unroll = choose_unroll(group, nrows, nnz);
+    unit = false;
+    if (unit_cf && group == 1) {
+      const UnitRows u = unit_rows_of(A, *unit_cf);
+      if (u.ok) {
+        build_unit(A, u, mc);
+        return;
+      }
+    }
     std::vector<int32_t> hptr;
     std::vector<int32_t> hcol;  // wide columns (padding: column 0)
     std::vector<int16_t> h16;   // narrow offsets from the owning row's base (padding: offset 0)
@@ -479,6 +579,61 @@ struct DMat {
     }
     ptr.alloc(hptr.size(), mc);
     ptr.upload(hptr.data(), hptr.size());
+    if (narrow) {
+      col16.alloc(h16.size(), mc);
+      col16.upload(h16.data(), h16.size());
+    } else {
+      col.alloc(hcol.size(), mc);
+      col.upload(hcol.data(), hcol.size());
+    }
+    val.alloc(hval.size(), mc);
+    val.upload(hval.data(), hval.size());
+  }
+
+  // The unit-row SELL layout of A (u = unit_rows_of(A), u.ok): per slice the explicit rows' entries, entry k
+  // of the l-th explicit row at ptr[s] + k * count_s + l; padding value 0 with offset 0 or column 0.
+  void build_unit(const HostCsr &A, const UnitRows &u, MemCounter *mc) {
+    unit = true;
+    group = 1;
+    const int32_t nslices = (int32_t)u.mask.size();
+    const std::vector<int32_t> &hptr = u.ptr;
+    const std::vector<int32_t> hmeta = unit_meta(u);
+    stored = u.stored;
+    explicit_nnz = 0;
+    explicit_rows = 0;
+    for (int32_t c : u.count) explicit_rows += c;
+    std::vector<T> hval(stored);
+    std::vector<int32_t> hcol;
+    std::vector<int16_t> h16;
+    if (narrow)
+      h16.assign(stored, 0);
+    else
+      hcol.assign(stored, 0);
+    for (int32_t s = 0; s < nslices; ++s) {
+      int32_t l = 0;
+      for (int32_t r = s * SELL_C; r < std::min(nrows, (s + 1) * SELL_C); ++r) {
+        if ((u.mask[s] >> (r - s * SELL_C)) & 1) continue;
+        const int32_t len = A.rp[r + 1] - A.rp[r];
+        const int32_t base = diag_base(r, mul);
+        explicit_nnz += len;
+        for (int32_t k = 0; k < u.width[s]; ++k) {
+          const int64_t d = (int64_t)hptr[s] + (int64_t)k * u.count[s] + l;
+          const bool has = k < len;
+          hval[d] = has ? (T)A.v[A.rp[r] + k] : T(0);
+          if (narrow)
+            h16[d] = has ? (int16_t)(A.ci[A.rp[r] + k] - base) : (int16_t)0;
+          else
+            hcol[d] = has ? A.ci[A.rp[r] + k] : 0;
+        }
+        ++l;
+      }
+    }
+    ptr.alloc(hptr.size(), mc);
+    ptr.upload(hptr.data(), hptr.size());
+    umask.alloc(std::max<size_t>(u.mask.size(), 1), mc);
+    umask.upload(u.mask.data(), u.mask.size());
+    smeta.alloc(hmeta.size(), mc);
+    smeta.upload(hmeta.data(), hmeta.size());
     if (narrow) {
       col16.alloc(h16.size(), mc);
       col16.upload(h16.data(), h16.size());

@@ -62,14 +62,13 @@ __device__ __forceinline__ double strided_sum(const double *__restrict__ p, int3
 // Row `row` of a sparse matrix times x, reduced over the G lanes of the row's group (every lane of the
 // group returns the full sum). G == 1: SELL-64, one lane per row. G > 1: CSR, lane `sub` takes entries
 // sub, sub + G, ...; groups are aligned inside the wavefront, so the butterfly never leaves the group.
-// Entries go in chunks of U: the chunk's index and value loads are all issued, then all its gathers,
-// then the multiply-adds in entry order. A short row thus waits on two dependent memory latencies per
+// Entries go in chunks of U (4; 8 for SELL matrices whose rows are long, see DMat::unroll): the chunk's
+// index and value loads are all issued, then all its gathers, then the multiply-adds in entry order. A short row thus waits on two dependent memory latencies per
 // chunk rather than two per entry. Slots past the row's end reload the chunk's first entry (in bounds)
 // and are not added, so the sum is the plain in-order one. NARROW: columns are 16-bit offsets from the
 // row's scaled diagonal (the matrix-wide choice is a uniform branch in row_dot).
-template <int G, bool NARROW, class Acc, class TM, class TX>
+template <int G, bool NARROW, int U, class Acc, class TM, class TX>
 __device__ __forceinline__ Acc row_dot_impl(const MatView<TM> &A, const TX *__restrict__ x, int32_t row, int sub) {
-  constexpr int U = 4;
   constexpr int32_t STEP = G == 1 ? SELL_C : G;
   int32_t k, end;
   if constexpr (G == 1) {
@@ -108,10 +107,10 @@ __device__ __forceinline__ Acc row_dot_impl(const MatView<TM> &A, const TX *__re
   return acc;
 }
 
-template <int G, class Acc, class TM, class TX>
+template <int G, class Acc, int U = 4, class TM, class TX>
 __device__ __forceinline__ Acc row_dot(const MatView<TM> &A, const TX *__restrict__ x, int32_t row, int sub) {
-  if (A.col16) return row_dot_impl<G, true, Acc>(A, x, row, sub);
-  return row_dot_impl<G, false, Acc>(A, x, row, sub);
+  if (A.col16) return row_dot_impl<G, true, U, Acc>(A, x, row, sub);
+  return row_dot_impl<G, false, U, Acc>(A, x, row, sub);
 }
 
 // SELL-64 rows r0 and r0 + 64 (the same lane of two adjacent slices) of one thread, interleaved so that
@@ -119,10 +118,9 @@ __device__ __forceinline__ Acc row_dot(const MatView<TM> &A, const TX *__restric
 // exists. There is no branch between the loads (a branch would make the compiler wait for every load
 // issued before it): a slot past its row's end loads an in-bounds entry of the chunk, gathers from a
 // valid column (an existing row's base, or column 0) and is not added.
-template <bool NARROW, class Acc, class TM, class TX>
+template <bool NARROW, int U, class Acc, class TM, class TX>
 __device__ __forceinline__ void sell_dot2_impl(const MatView<TM> &A, const TX *__restrict__ x, int32_t r0, bool has1,
                                                Acc &a0, Acc &a1) {
-  constexpr int U = 4;
   const int32_t s0 = r0 >> 6, lane = r0 & 63;
   int32_t k0 = A.ptr[s0] + lane;
   const int32_t e0 = A.ptr[s0 + 1];
@@ -212,16 +210,16 @@ inline unsigned row_blocks(int64_t nrows, int group, int val_bytes) {
 }
 
 // The row sums of this thread's rows (every lane of a CSR group gets its row's full sum).
-template <int G, class Acc, class TM, class TX>
+template <int G, class Acc, int U = 4, class TM, class TX>
 __device__ __forceinline__ void row_dots(const MatView<TM> &A, const TX *__restrict__ x, const ThreadRows<G, TM> &t,
                                          Acc (&out)[ThreadRows<G, TM>::R]) {
   if constexpr (ThreadRows<G, TM>::R == 2) {
     if (A.col16)
-      sell_dot2_impl<true, Acc>(A, x, t.row[0], t.ok[1], out[0], out[1]);
+      sell_dot2_impl<true, U, Acc>(A, x, t.row[0], t.ok[1], out[0], out[1]);
     else
-      sell_dot2_impl<false, Acc>(A, x, t.row[0], t.ok[1], out[0], out[1]);
+      sell_dot2_impl<false, U, Acc>(A, x, t.row[0], t.ok[1], out[0], out[1]);
   } else {
-    out[0] = row_dot<G, Acc>(A, x, t.row[0], t.sub);
+    out[0] = row_dot<G, Acc, U>(A, x, t.row[0], t.sub);
   }
 }
 
@@ -230,7 +228,7 @@ __device__ __forceinline__ void row_dots(const MatView<TM> &A, const TX *__restr
 // y = A x  (restriction R r, the GMRES product w = A z with z promoted on load, the coarse inverse),
 // optionally f = d .* y as well: the restriction also produces the first term f = D^{-1} b of the
 // coarse level's polynomial Gauss-Seidel sweep (same product as the residual pass with x = 0).
-template <int G, class Acc, class TM, class TX, class TY>
+template <int G, class Acc, int U = 4, class TM, class TX, class TY>
 __device__ __forceinline__ void spmv_body(uint32_t lb, const MatView<TM> &A, const TX *__restrict__ x,
                                           TY *__restrict__ y, const TY *__restrict__ d, TY *__restrict__ f) {
   constexpr int R = ThreadRows<G, TM>::R;
@@ -240,7 +238,7 @@ __device__ __forceinline__ void spmv_body(uint32_t lb, const MatView<TM> &A, con
 #pragma unroll
   for (int q = 0; q < R; ++q) dv[q] = (f && t.ok[q]) ? d[t.row[q]] : TY(0);
   Acc v[R];
-  row_dots<G, Acc>(A, x, t, v);
+  row_dots<G, Acc, U>(A, x, t, v);
   if (t.sub != 0) return;
 #pragma unroll
   for (int q = 0; q < R; ++q) {
@@ -252,7 +250,7 @@ __device__ __forceinline__ void spmv_body(uint32_t lb, const MatView<TM> &A, con
 }
 
 // r = b - A x (x == nullptr means x = 0), optionally f = d .* r. One pass: SpMV, subtract, scale.
-template <int G, class T>
+template <int G, class T, int U = 4>
 __device__ __forceinline__ void residual_body(uint32_t lb, const MatView<T> &A, const T *__restrict__ b,
                                               const T *__restrict__ x, const T *__restrict__ d, T *__restrict__ r,
                                               T *__restrict__ f) {
@@ -266,7 +264,7 @@ __device__ __forceinline__ void residual_body(uint32_t lb, const MatView<T> &A, 
     dv[q] = (f && t.ok[q]) ? d[t.row[q]] : T(0);
     acc[q] = T(0);
   }
-  if (x) row_dots<G, T>(A, x, t, acc);
+  if (x) row_dots<G, T, U>(A, x, t, acc);
   if (t.sub != 0) return;
 #pragma unroll
   for (int q = 0; q < R; ++q) {
@@ -281,7 +279,7 @@ __device__ __forceinline__ void residual_body(uint32_t lb, const MatView<T> &A, 
 //   out = [acc +] [scale .*] (f - S in)
 // Polynomial GS: S = D^{-1}L (or D^{-1}U), f = D^{-1} r; ILU: S = L_s with f = r, or S = U_s with
 // f = D_U^{-1} y. `acc` may alias `out` (x += ...); `in` never aliases `out`.
-template <int G, class T>
+template <int G, class T, int U = 4>
 __device__ __forceinline__ void neumann_body(uint32_t lb, const MatView<T> &S, const T *__restrict__ f,
                                              const T *__restrict__ in, const T *__restrict__ scale, const T *acc,
                                              T *out) {
@@ -296,7 +294,7 @@ __device__ __forceinline__ void neumann_body(uint32_t lb, const MatView<T> &S, c
     sc[q] = scale ? scale[row] : T(1);
     av[q] = acc ? acc[row] : T(0);
   }
-  row_dots<G, T>(S, in, t, sv);
+  row_dots<G, T, U>(S, in, t, sv);
   if (t.sub != 0) return;
 #pragma unroll
   for (int q = 0; q < R; ++q) {
@@ -308,9 +306,112 @@ __device__ __forceinline__ void neumann_body(uint32_t lb, const MatView<T> &S, c
   }
 }
 
+// x += P e for P in the unit-row SELL layout (device.hpp, UnitRows), on the rows of ThreadRows<1, T> (one
+// row per lane in FP64, rows r and r + 64 in FP32). A C point's row adds e[c], c = the C points before it,
+// as a virtual first entry of value 1 (0 + 1 * e[c] is e[c] exactly); an F row of rank l among its slice's m
+// F rows sums the slots ptr[s] + l, ptr[s] + l + m, ... (padding: value 0 at a valid column) in order. Both
+// go through one loop: entries in chunks of U, every index and value load of a chunk issued before its
+// gathers, as in row_dot; a slot past its row's end loads an in-bounds entry, gathers a valid column and is
+// not added.
+template <bool NARROW, int U, class T>
+__device__ __forceinline__ void prolong_unit_rows(const MatView<T> &P, const T *__restrict__ e, T *x,
+                                                  const ThreadRows<1, T> &t) {
+  constexpr int R = ThreadRows<1, T>::R;
+  int32_t k[R], lim[R], end[R], m[R], cu[R], base[R];
+  bool virt[R];
+  T xv[R], acc[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int32_t row = t.ok[q] ? t.row[q] : t.row[0];
+    // a wavefront's rows q are one slice (ThreadRows): the slice's mask, counts and pointers are loaded
+    // once per wavefront through the scalar unit
+    const int32_t s = __builtin_amdgcn_readfirstlane(row >> 6), lane = row & 63;
+    const uint64_t um = P.umask[s];
+    const int32_t before = P.smeta[2 * s], mm = P.smeta[2 * s + 1];
+    const int32_t p0 = P.ptr[s], p1 = P.ptr[s + 1];
+    xv[q] = x[row];
+    const int32_t below = __popcll(um & ((uint64_t(1) << lane) - 1));
+    const bool unit = (um >> lane) & 1;
+    virt[q] = t.ok[q] && unit;
+    // the load cursor: an F row's own slots; a C point's lane follows the F row of rank `below` (its
+    // neighbour), so that every lane of a wavefront loads from the same cache lines
+    k[q] = p0 + (unit ? (mm > 0 ? min(below, mm - 1) : 0) : lane - below);
+    lim[q] = p1;
+    end[q] = (unit || !t.ok[q]) ? p0 : p1;  // the slots whose entries this row adds
+    m[q] = mm > 0 ? mm : 1;
+    cu[q] = before + below;
+    base[q] = NARROW ? diag_base(row, P.mul) : 0;
+    acc[q] = T(0);
+  }
+  while (true) {
+    bool more = false;
+#pragma unroll
+    for (int q = 0; q < R; ++q) more = more || virt[q] || k[q] < end[q];
+    if (!more) break;
+    bool ok[R][U];
+    int32_t c[R][U];
+    T v[R][U], ev[R][U];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      // an in-bounds slot for loads past the slice's end (the buffers hold at least one)
+      const int32_t kb = k[q] < lim[q] ? k[q] : (lim[q] > 0 ? lim[q] - 1 : 0);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t kk = k[q] + u * m[q] < lim[q] ? k[q] + u * m[q] : kb;
+        ok[q][u] = k[q] + u * m[q] < end[q];
+        // every loaded index is used, so the loads are issued unconditionally, as one batch; a slot that is
+        // not this row's decodes another row's offset, so columns are clamped into [0, ncols)
+        const int32_t col = NARROW ? base[q] + (int32_t)P.col16[kk] : P.col[kk];
+        c[q][u] = min(max(col, 0), P.ncols - 1);
+        v[q][u] = P.val[kk];
+      }
+      if (virt[q]) {  // the unit row's virtual entry takes slot 0 (its row has no stored slots)
+        ok[q][0] = true;
+        c[q][0] = cu[q];
+        v[q][0] = T(1);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+#pragma unroll
+      for (int u = 0; u < U; ++u) ev[q][u] = e[c[q][u]];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (ok[q][u]) acc[q] += v[q][u] * ev[q][u];
+      virt[q] = false;
+      k[q] += U * m[q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q)
+    if (t.ok[q]) x[t.row[q]] = xv[q] + acc[q];
+}
+
 // x += P e  (prolongation and correction in one pass)
 template <int G, class T>
 __device__ __forceinline__ void prolong_body(uint32_t lb, const MatView<T> &P, const T *__restrict__ e, T *x) {
+  if constexpr (G == 1) {
+    if (P.umask) {
+      const ThreadRows<1, T> t(lb, P.nrows);
+      if (!t.ok[0]) return;
+      // chunks of eight when the F rows average more than four entries (one dependent round instead of two
+      // for the six-entry rows of a stencil's P)
+      if (P.unroll == 8) {
+        if (P.col16)
+          prolong_unit_rows<true, 8>(P, e, x, t);
+        else
+          prolong_unit_rows<false, 8>(P, e, x, t);
+      } else {
+        if (P.col16)
+          prolong_unit_rows<true, 4>(P, e, x, t);
+        else
+          prolong_unit_rows<false, 4>(P, e, x, t);
+      }
+      return;
+    }
+  }
   constexpr int R = ThreadRows<G, T>::R;
   const ThreadRows<G, T> t(lb, P.nrows);
   if (!t.ok[0]) return;
@@ -361,28 +462,39 @@ __device__ __forceinline__ MatView<T> make_view(const int32_t *ptr, const void *
 }
 #define NAMG_MAT_VIEW(T) make_view<T>(m_ptr, m_idx, m_val, m_nrows, m_narrow, m_mul)
 
-template <int G, class Acc, class TM, class TX, class TY>
+template <int G, class Acc, class TM, class TX, class TY, int U = 4>
 __global__ __launch_bounds__(BLK) void k_spmv(NAMG_MAT_HEAD(TM), const TX *__restrict__ x, const TY *__restrict__ d,
                                               TY *__restrict__ y, TY *__restrict__ f, int64_t m_mul) {
-  spmv_body<G, Acc>(blockIdx.x, NAMG_MAT_VIEW(TM), x, y, d, f);
+  spmv_body<G, Acc, U>(blockIdx.x, NAMG_MAT_VIEW(TM), x, y, d, f);
 }
 
-template <int G, class T>
+template <int G, class T, int U = 4>
 __global__ __launch_bounds__(BLK) void k_residual(NAMG_MAT_HEAD(T), const T *__restrict__ b, const T *__restrict__ d,
                                                   const T *__restrict__ x, T *__restrict__ r, T *__restrict__ f,
                                                   int64_t m_mul) {
-  residual_body<G>(blockIdx.x, NAMG_MAT_VIEW(T), b, x, d, r, f);
+  residual_body<G, T, U>(blockIdx.x, NAMG_MAT_VIEW(T), b, x, d, r, f);
 }
 
-template <int G, class T>
+template <int G, class T, int U = 4>
 __global__ __launch_bounds__(BLK) void k_neumann(NAMG_MAT_HEAD(T), const T *__restrict__ f, const T *__restrict__ scale,
                                                  const T *acc, const T *__restrict__ in, T *out, int64_t m_mul) {
-  neumann_body<G>(blockIdx.x, NAMG_MAT_VIEW(T), f, in, scale, acc, out);
+  neumann_body<G, T, U>(blockIdx.x, NAMG_MAT_VIEW(T), f, in, scale, acc, out);
 }
 
+// A prolongation may be packed in the unit-row layout: its per-slice masks and counts (null for the plain
+// layout) complete the view, and prolong_body dispatches on them. The other row kernels never receive a
+// unit-row matrix (the host refuses to launch them on one).
 template <int G, class T>
-__global__ __launch_bounds__(BLK) void k_prolong(NAMG_MAT_HEAD(T), T *x, const T *__restrict__ e, int64_t m_mul) {
-  prolong_body<G>(blockIdx.x, NAMG_MAT_VIEW(T), e, x);
+__global__ __launch_bounds__(BLK) void k_prolong(NAMG_MAT_HEAD(T), T *x, const T *__restrict__ e, int64_t m_mul,
+                                                 const uint64_t *__restrict__ m_umask,
+                                                 const int32_t *__restrict__ m_smeta, int32_t m_ncols,
+                                                 int32_t m_unroll) {
+  MatView<T> P = NAMG_MAT_VIEW(T);
+  P.umask = m_umask;
+  P.smeta = m_smeta;
+  P.ncols = m_ncols;
+  P.unroll = m_unroll;
+  prolong_body<G>(blockIdx.x, P, e, x);
 }
 
 template <class T>
@@ -484,9 +596,11 @@ __device__ __forceinline__ void colreduce_body(uint32_t lb, const double *__rest
 // The single fused reduction of an Arnoldi step (Algorithm 1, the global synchronisation):
 // c = V_{i+1}^T v_{i+1} and d = V_{i+1}^T w in one pass over V. Block lb owns the contiguous row range
 // [lb * rows_per_blk, (lb + 1) * rows_per_blk) (rows_per_blk even); each thread takes row pairs with
-// 16-byte loads, so every wavefront load moves 1 KiB. Partial sums are written value-major:
+// 16-byte loads, so every wavefront load moves 1 KiB, and PAIRS row pairs per iteration with all their
+// loads issued before the multiply-adds (the sums stay in row order). Columns go in chunks of CH (slots past
+// ncols repeat the last column and are discarded). Partial sums are written value-major:
 // partial[v * nblk + lb], v < ncols for c, ncols + v for d.
-template <int CH>
+template <int CH, int PAIRS = 1>
 __device__ __forceinline__ void multidot_body(uint32_t lb, const double *__restrict__ V, int64_t ldv, int32_t ncols,
                                               const double *__restrict__ w, int32_t n, int32_t rows_per_blk,
                                               double *__restrict__ partial, int32_t nblk) {
@@ -500,11 +614,32 @@ __device__ __forceinline__ void multidot_body(uint32_t lb, const double *__restr
 #pragma unroll
     for (int c = 0; c < CH; ++c) ac[c] = ad[c] = 0.0;
     // every slot loads a valid column (slots past ncols repeat the last one and are discarded below), so
-    // there is no branch between the loads and all CH + 2 of them are in flight together
+    // there is no branch between the loads and all of them are in flight together
     const double *cols[CH];
 #pragma unroll
     for (int c = 0; c < CH; ++c) cols[c] = V + (int64_t)min(j0 + c, ncols - 1) * ldv;
-    for (int32_t r = r0 + 2 * (int32_t)threadIdx.x; r < r1; r += 2 * BLK) {
+    int32_t r = r0 + 2 * (int32_t)threadIdx.x;
+    for (; r + 2 * BLK * (PAIRS - 1) + 1 < r1; r += 2 * BLK * PAIRS) {
+      double2 vr[PAIRS], wr[PAIRS], vj[PAIRS][CH];
+#pragma unroll
+      for (int p = 0; p < PAIRS; ++p) {
+        const int32_t rr = r + 2 * BLK * p;
+        vr[p] = *reinterpret_cast<const double2 *>(v + rr);
+        wr[p] = w ? *reinterpret_cast<const double2 *>(w + rr) : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < CH; ++c) vj[p][c] = *reinterpret_cast<const double2 *>(cols[c] + rr);
+      }
+#pragma unroll
+      for (int p = 0; p < PAIRS; ++p)
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          ac[c] += vj[p][c].x * vr[p].x;
+          ac[c] += vj[p][c].y * vr[p].y;
+          ad[c] += vj[p][c].x * wr[p].x;
+          ad[c] += vj[p][c].y * wr[p].y;
+        }
+    }
+    for (; r < r1; r += 2 * BLK) {
       if (r + 1 < r1) {
         const double2 vr = *reinterpret_cast<const double2 *>(v + r);
         const double2 wr = w ? *reinterpret_cast<const double2 *>(w + r) : make_double2(0.0, 0.0);
@@ -556,10 +691,11 @@ __device__ __forceinline__ void multidot_body(uint32_t lb, const double *__restr
   }
 }
 
-// Partition of the fused reduction over n rows: at most 2048 blocks of an even number of rows (at least
-// 512), so that a thread takes one or a few row pairs.
+// Partition of the fused reduction over n rows: at most 512 blocks (two per compute unit) of an even
+// number of rows (at least 512), so that a thread takes several row pairs and the block-level reduction of
+// the 2 (i + 1) sums is paid once per 512 rows or more.
 inline int32_t dot_rows_per_block(int64_t n) {
-  const int64_t nb = std::min<int64_t>(2048, std::max<int64_t>(1, (n + 511) / 512));
+  const int64_t nb = std::min<int64_t>(512, std::max<int64_t>(1, (n + 511) / 512));
   const int64_t rows = (n + nb - 1) / nb;
   return (int32_t)std::max<int64_t>(2, (rows + 1) / 2 * 2);
 }
@@ -753,11 +889,27 @@ __global__ __launch_bounds__(BLK) void k_colreduce(const double *__restrict__ pa
   colreduce_body(blockIdx.x, partial, nblk, out);
 }
 
-template <int CH>
+template <int CH, int PAIRS = 1>
 __global__ __launch_bounds__(BLK) void k_multidot(const double *__restrict__ V, int64_t ldv, int32_t ncols,
                                                   const double *__restrict__ w, int32_t n, int32_t rows_per_blk,
                                                   double *__restrict__ partial, int32_t nblk) {
-  multidot_body<CH>(blockIdx.x, V, ldv, ncols, w, n, rows_per_blk, partial, nblk);
+  multidot_body<CH, PAIRS>(blockIdx.x, V, ldv, ncols, w, n, rows_per_blk, partial, nblk);
+}
+
+// The fused reduction's kernel for ncols columns: one chunk of exactly ncols columns up to eight (two row
+// pairs per iteration up to four columns, where registers allow), else chunks of eight.
+using MultidotKernel = void (*)(const double *, int64_t, int32_t, const double *, int32_t, int32_t, double *, int32_t);
+inline MultidotKernel multidot_kernel(int32_t ncols) {
+  switch (ncols) {
+    case 1: return &k_multidot<1, 2>;
+    case 2: return &k_multidot<2, 2>;
+    case 3: return &k_multidot<3, 2>;
+    case 4: return &k_multidot<4, 2>;
+    case 5: return &k_multidot<5>;
+    case 6: return &k_multidot<6>;
+    case 7: return &k_multidot<7>;
+    default: return &k_multidot<8>;
+  }
 }
 
 __global__ __launch_bounds__(BLK) void k_finish(KState *__restrict__ st, const double *__restrict__ partial, int32_t nblk,
@@ -824,14 +976,14 @@ struct RowTask {
   int32_t n, pad;
 };
 
-template <int OP, int G, class T>
+template <int OP, int G, class T, int U = 4>
 __global__ __launch_bounds__(BLK) void kb_rows(const RowTask<T> *__restrict__ tasks, const uint32_t *__restrict__ off,
                                                int ntasks) {
   uint32_t lb;
   const RowTask<T> &t = tasks[find_task(off, ntasks, lb)];
-  if constexpr (OP == ROP_RESIDUAL) residual_body<G>(lb, t.M, t.a, t.b, t.c, t.o0, t.o1);
-  if constexpr (OP == ROP_NEUMANN) neumann_body<G>(lb, t.M, t.a, t.b, t.c, t.d, t.o0);
-  if constexpr (OP == ROP_SPMV) spmv_body<G, T>(lb, t.M, t.b, t.o0, t.c, t.o1);
+  if constexpr (OP == ROP_RESIDUAL) residual_body<G, T, U>(lb, t.M, t.a, t.b, t.c, t.o0, t.o1);
+  if constexpr (OP == ROP_NEUMANN) neumann_body<G, T, U>(lb, t.M, t.a, t.b, t.c, t.d, t.o0);
+  if constexpr (OP == ROP_SPMV) spmv_body<G, T, U>(lb, t.M, t.b, t.o0, t.c, t.o1);
   if constexpr (OP == ROP_PROLONG) prolong_body<G>(lb, t.M, t.b, t.o0);
   if constexpr (OP == ROP_AXPY) axpy_body(lb, t.a, t.c, t.d, t.o0, t.n);
   if constexpr (OP == ROP_FILL) {

@@ -74,6 +74,37 @@ __global__ __launch_bounds__(PB) void k_pack_sell(int32_t nrows, int32_t nslices
   }
 }
 
+// Unit-row layout (device.hpp, UnitRows), one thread per row: an explicit row of rank l in slice s writes
+// entry k (or padding: value 0, offset 0 or column 0) at ptr[s] + k * meta[2 s + 1] + l for k < the slice's
+// width; a C point's row writes nothing
+template <class T>
+__global__ __launch_bounds__(PB) void k_pack_unit(int32_t nrows, const int32_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                                  const int32_t *__restrict__ sptr, const uint64_t *__restrict__ mask,
+                                                  const int32_t *__restrict__ meta, int64_t mul, int32_t narrow,
+                                                  int16_t *__restrict__ col16, int32_t *__restrict__ col,
+                                                  T *__restrict__ val) {
+  const int32_t r = blockIdx.x * PB + threadIdx.x;
+  if (r >= nrows) return;
+  const int32_t s = r / SELL_C, lane = r % SELL_C;
+  const uint64_t mk = mask[s];
+  if ((mk >> lane) & 1) return;
+  const int32_t l = lane - __popcll(mk & ((uint64_t(1) << lane) - 1));
+  const int32_t m = meta[2 * s + 1];
+  const int32_t width = (sptr[s + 1] - sptr[s]) / m;
+  const int32_t len = rp[r + 1] - rp[r], beg = rp[r];
+  const int32_t base = diag_base(r, mul);
+  for (int32_t k = 0; k < width; ++k) {
+    const int64_t d = (int64_t)sptr[s] + (int64_t)k * m + l;
+    const bool has = k < len;
+    val[d] = has ? (T)v[beg + k] : T(0);
+    if (narrow)
+      col16[d] = has ? (int16_t)(ci[beg + k] - base) : (int16_t)0;
+    else
+      col[d] = has ? ci[beg + k] : 0;
+  }
+}
+
 // CSR with lane groups: the CSR arrays themselves, columns as offsets when narrow, values cast to T
 template <class T>
 __global__ __launch_bounds__(PB) void k_pack_csr(int32_t nrows, const int32_t *__restrict__ rp,
@@ -155,8 +186,41 @@ std::vector<int32_t> host_offsets(const std::vector<int32_t> &counts) {
 
 bool device_packing_enabled() { return std::getenv("NAMG_HOST_PACK") == nullptr; }
 
+// The unit-row layout u of the prolongation D into M, as DMat::build_unit packs it (u computed on the host
+// from the host copy of P and the level's C/F splitting).
 template <class T>
-void pack_device(DMat<T> &M, const DCsr &D, MemCounter *mc, int force_group) {
+void pack_unit_device(DMat<T> &M, const DCsr &D, const UnitRows &u, MemCounter *mc) {
+  const int32_t nslices = (int32_t)u.mask.size();
+  const std::vector<int32_t> meta = unit_meta(u);
+  M.unit = true;
+  M.group = 1;
+  M.stored = u.stored;
+  M.explicit_nnz = M.nnz;
+  for (uint64_t mk : u.mask) M.explicit_nnz -= __builtin_popcountll(mk);
+  M.explicit_rows = 0;
+  for (int32_t c : u.count) M.explicit_rows += c;
+  M.ptr.alloc(u.ptr.size(), mc);
+  M.ptr.upload(u.ptr.data(), u.ptr.size());
+  M.umask.alloc(std::max<size_t>(u.mask.size(), 1), mc);
+  M.umask.upload(u.mask.data(), u.mask.size());
+  M.smeta.alloc(meta.size(), mc);
+  M.smeta.upload(meta.data(), meta.size());
+  if (M.narrow)
+    M.col16.alloc((size_t)M.stored, mc);
+  else
+    M.col.alloc((size_t)M.stored, mc);
+  M.val.alloc((size_t)M.stored, mc);
+  if (nslices > 0) {
+    hipLaunchKernelGGL(k_pack_unit<T>, dim3(pgrid(M.nrows)), dim3(PB), 0, 0, M.nrows, D.rp.get(), D.ci.get(),
+                       D.v.get(), M.ptr.get(), M.umask.get(), M.smeta.get(), M.mul, (int32_t)M.narrow, M.col16.get(),
+                       M.col.get(), M.val.get());
+    check("k_pack_unit");
+  }
+}
+
+template <class T>
+void pack_device(DMat<T> &M, const DCsr &D, MemCounter *mc, int force_group, const UnitRows *unit) {
+  M.unit = false;
   M.nrows = D.nr;
   M.ncols = D.nc;
   M.nnz = D.nnz;
@@ -172,7 +236,10 @@ void pack_device(DMat<T> &M, const DCsr &D, MemCounter *mc, int force_group) {
   hip_check(hipMemcpy(&hbad, bad.get(), 4, hipMemcpyDeviceToHost), "hipMemcpy D2H");
   M.narrow = hbad == 0;
   M.group = force_group > 0 ? force_group : choose_group(M.nrows, M.nnz);
-  if (M.group > 1) {
+  M.unroll = choose_unroll(M.group, M.nrows, M.nnz);
+  if (unit && unit->ok && M.group == 1) {
+    pack_unit_device(M, D, *unit, mc);
+  } else if (M.group > 1) {
     M.stored = M.nnz;
     M.ptr.alloc((size_t)M.nrows + 1, mc);
     hip_check(hipMemcpy(M.ptr.get(), D.rp.get(), ((size_t)M.nrows + 1) * 4, hipMemcpyDeviceToDevice), "hipMemcpy D2D");
@@ -257,8 +324,8 @@ void smoother_data_device(const DCsr &A, DCsr &lo, DCsr &up, DevBuf<T> &dinv, De
   hip_check(hipStreamSynchronize(nullptr), "hipStreamSynchronize");
 }
 
-template void pack_device<float>(DMat<float> &, const DCsr &, MemCounter *, int);
-template void pack_device<double>(DMat<double> &, const DCsr &, MemCounter *, int);
+template void pack_device<float>(DMat<float> &, const DCsr &, MemCounter *, int, const UnitRows *);
+template void pack_device<double>(DMat<double> &, const DCsr &, MemCounter *, int, const UnitRows *);
 template void smoother_data_device<float>(const DCsr &, DCsr &, DCsr &, DevBuf<float> &, DevBuf<float> &,
                                           MemCounter *);
 template void smoother_data_device<double>(const DCsr &, DCsr &, DCsr &, DevBuf<double> &, DevBuf<double> &,

@@ -107,6 +107,21 @@ inline std::pair<LayoutCount, LayoutCount> transfer_shape(const HostCsr &P) {
   return {lp, lr};
 }
 
+// Device bytes of the DMat<T> that packs prolongation P of C/F splitting cf (lp = its LayoutCount): the
+// unit-row layout when it applies (pointers, masks, per-slice counts, the explicit rows' entries), else lp's layout.
+template <class T>
+int64_t prolong_alloc_bytes(const HostCsr &P, const std::vector<int8_t> &cf, const LayoutCount &lp) {
+  if (choose_group(P.nr, lp.nnz) == 1) {
+    const UnitRows u = unit_rows_of(P, cf);
+    if (u.ok) {
+      const int64_t ns = (int64_t)u.mask.size();
+      return alloc_bytes(ns + 1, 4) + alloc_bytes(ns, 8) + alloc_bytes(2 * ns, 4) +
+             alloc_bytes(u.stored, lp.narrow ? 2 : 4) + alloc_bytes(u.stored, sizeof(T));
+    }
+  }
+  return lp.bytes<T>(P.nr);
+}
+
 // Device bytes of Solver<T>(H) with its Krylov workspace for restart m (the direct comparators' level
 // schedules, which serving never builds, excluded).
 template <class T>
@@ -124,7 +139,7 @@ int64_t solver_footprint(const HostHierarchy &H, int m) {
     const auto pr = transfer_shape(h.P);
     if (l == 0) total += ms.all.bytes<double>(h.A.nr, 1);
     // A, P, then D^-1, D_l1^-1, r, f, g1, g2
-    total += ms.all.bytes<T>(h.A.nr) + pr.first.bytes<T>(h.P.nr) + 6 * alloc_bytes(n, S);
+    total += ms.all.bytes<T>(h.A.nr) + prolong_alloc_bytes<T>(h.P, h.cf, pr.first) + 6 * alloc_bytes(n, S);
     total += h.host_restriction ? mat_alloc_bytes<T>(h.R) : pr.second.bytes<T>(h.P.nc);
     total += h.host_smoother ? mat_alloc_bytes<T>(h.pgs_lo) + mat_alloc_bytes<T>(h.pgs_up)
                              : ms.lo.bytes<T>(h.A.nr) + ms.up.bytes<T>(h.A.nr);
@@ -493,7 +508,9 @@ class BatchEngine {
           const std::vector<Op> *ops = pick(q);
           if (!ops || k >= ops->size()) continue;
           const Op &op = (*ops)[k];
-          const std::pair<int, int> key{op.kind, op.group};
+          // a SELL matrix loaded in chunks of eight has kernels of its own (row_kernel, WIDE)
+          const bool wide = op.group == 1 && op.t.M.unroll == 8 && op.kind != ROP_PROLONG;
+          const std::pair<int, int> key{op.kind, op.group | (wide ? WIDE : 0)};
           size_t j = 0;
           while (j < keys.size() && keys[j] != key) ++j;
           if (j == keys.size()) {
@@ -518,9 +535,13 @@ class BatchEngine {
   using RowKernel = void (*)(const RowTask<T> *, const uint32_t *, int);
   using KKernel = void (*)(const KTask<T> *, const uint32_t *, int);
 
+  // Group code of a SELL matrix whose row kernels load entries in chunks of eight.
+  static constexpr int WIDE = 0x100;
+
   template <int OP>
   static RowKernel row_kernel(int g) {
     switch (g) {
+      case 1 | WIDE: return &kb_rows<OP, 1, T, 8>;
       case 1: return &kb_rows<OP, 1, T>;
       case 2: return &kb_rows<OP, 2, T>;
       case 4: return &kb_rows<OP, 4, T>;

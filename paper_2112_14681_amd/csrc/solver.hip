@@ -96,12 +96,22 @@ void validate_served_params(const namg_solve_params &p) {
     case 32: return &NAME<32, __VA_ARGS__>;               \
     default: return &NAME<64, __VA_ARGS__>;               \
   }
+// Chunks of eight (unroll == 8) exist for one lane per row only (SELL-64, see choose_unroll).
 template <class Acc, class TM, class TX, class TY>
-auto sel_spmv(int g) { NAMG_GROUP_SWITCH(k_spmv, Acc, TM, TX, TY) }
+auto sel_spmv(int g, int unroll = 4) {
+  if (g == 1 && unroll == 8) return &k_spmv<1, Acc, TM, TX, TY, 8>;
+  NAMG_GROUP_SWITCH(k_spmv, Acc, TM, TX, TY)
+}
 template <class T>
-auto sel_residual(int g) { NAMG_GROUP_SWITCH(k_residual, T) }
+auto sel_residual(int g, int unroll = 4) {
+  if (g == 1 && unroll == 8) return &k_residual<1, T, 8>;
+  NAMG_GROUP_SWITCH(k_residual, T)
+}
 template <class T>
-auto sel_neumann(int g) { NAMG_GROUP_SWITCH(k_neumann, T) }
+auto sel_neumann(int g, int unroll = 4) {
+  if (g == 1 && unroll == 8) return &k_neumann<1, T, 8>;
+  NAMG_GROUP_SWITCH(k_neumann, T)
+}
 template <class T>
 auto sel_prolong(int g) { NAMG_GROUP_SWITCH(k_prolong, T) }
 #undef NAMG_GROUP_SWITCH
@@ -169,7 +179,8 @@ class Solver final : public SolverBase {
       if (l == nl - 1) break;
       if (dl) {
         pack_device(d.A, dl->A[l], &mc_);
-        pack_device(d.P, dl->P[l], &mc_);
+        const UnitRows pu = unit_rows_of(h.P, h.cf);
+        pack_device(d.P, dl->P[l], &mc_, 0, &pu);
         pack_device(d.R, dl->R[l], &mc_);
         DCsr lo, up;
         smoother_data_device(dl->A[l], lo, up, d.dinv, d.dl1inv, &mc_);
@@ -177,7 +188,7 @@ class Solver final : public SolverBase {
         pack_device(d.pgs_up, up, &mc_);
       } else {
         d.A.build(h.A, &mc_);
-        d.P.build(h.P, &mc_);
+        d.P.build(h.P, &mc_, 0, &h.cf);
         if (h.host_restriction)
           d.R.build(h.R, &mc_);
         else
@@ -234,7 +245,9 @@ class Solver final : public SolverBase {
     hip_check(hipEventCreate(&wall_ev_[1]), "hipEventCreate");
     red_.alloc(std::max<int32_t>(nblk_red_, 1) + 8, &mc_);
     kst_.alloc(1, &mc_);
-    hip_check(hipHostMalloc((void **)&pinned_, 64, hipHostMallocMapped), "hipHostMalloc");
+    hip_check(hipHostMalloc((void **)&pinned_, sizeof(double) * (size_t)step_slot(NAMG_MAX_RESTART + 1),
+                            hipHostMallocMapped),
+              "hipHostMalloc");
     hip_check(hipHostGetDevicePointer((void **)&pinned_dev_, pinned_, 0), "hipHostGetDevicePointer");
   }
 
@@ -327,7 +340,7 @@ class Solver final : public SolverBase {
         cast(in1, d.x.get(), n, s);
       {
         const MatView<T> M = d.A.view();
-        launch(NAMG_KF_SPMV, level, d.A.bytes() + 2 * S * n, sel_spmv<T, T, T, T>(d.A.group), rows_grid(d.A), s,
+        launch(NAMG_KF_SPMV, level, d.A.bytes() + 2 * S * n, sel_spmv<T, T, T, T>(d.A.group, d.A.unroll), rows_grid(d.A), s,
                NAMG_HEAD_ARGS(M), (const T *)d.x.get(), (const T *)nullptr, d.b.get(), (T *)nullptr, M.mul);
       }
         cast(d.b.get(), out, n, s);
@@ -480,8 +493,17 @@ class Solver final : public SolverBase {
         // column completion of step 0: rho_0 = ||r|| from the residual pass's partial sums
         launch_small(&k_finish, s, ks, (const double *)red_.get(), nblk_red_, 0, 0, p.tol, beta, denom,
                      pinned_dev_);
-        int k = 0;
-        for (int i = 0; i < me; ++i) {
+        // The host reads each step's (estimate, stop flag) from its own host-mapped slot. It waits for the
+        // device after a step only when that step might be the last: from the last two estimates read, the
+        // steps ahead are issued without waiting while even a convergence twice as fast as the last step's
+        // (per step) would not reach the stopping level (at most PLAN_AHEAD steps at a time). Every step
+        // issued past the stopping one only writes workspace columns and Hessenberg entries beyond it, so
+        // the iterate is the one of the step-by-step loop; the waits saved are the device's idle time.
+        const double stop_level = p.tol * denom / beta;  // estimate |g| / ||b|| at which the flag is raised
+        int k = 0, first_unread = 0, sync_at = 0;
+        double e_prev = -1.0, e_last = -1.0;
+        bool stop = false;
+        for (int i = 0; i < me && !stop; ++i) {
           double *vi = V + (int64_t)i * ldv_;
           T *zi = Z + (int64_t)i * ldz_;
           const T *b0;
@@ -498,28 +520,46 @@ class Solver final : public SolverBase {
                  M64.mul);
           if (timing) marks.push_back(phase_mark(s));
           const int32_t ncols = i + 1;
-          launch(NAMG_KF_MULTIDOT, 0, 8.0 * n * (ncols + 1), &k_multidot<8>, nblk_dot_, s, (const double *)V, ldv_,
-                 ncols, (const double *)w, n, rows_per_dot_, ws.dot, nblk_dot_);
+          launch(NAMG_KF_MULTIDOT, 0, 8.0 * n * (ncols + 1), multidot_kernel(ncols), nblk_dot_, s, (const double *)V,
+                 ldv_, ncols, (const double *)w, n, rows_per_dot_, ws.dot, nblk_dot_);
           launch(-1, 0, 0.0, &k_colreduce, (unsigned)(2 * ncols), s, (const double *)ws.dot, nblk_dot_, cd);
           launch_small(&k_step, s, ks, (const double *)cd, i, t_mode(p));
           launch(NAMG_KF_PROJECT, 0, 8.0 * n * (i + 4) + (vin ? S * n : 0.0), &k_project<T>, blocks_for(n), s, V,
                  ldv_, i, (const double *)w, (const KState *)ks, n, vin, red_.get());
           // column i is complete once ||v_{i+2}|| is known: estimate and stop test before the next V-cycle
           launch_small(&k_finish, s, ks, (const double *)red_.get(), nblk_red_, i + 1, (int)(i + 1 == me), p.tol, beta,
-                       denom, pinned_dev_);
+                       denom, pinned_dev_ + step_slot(i));
           if (timing) marks.push_back(phase_mark(s));
-          hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
-          const double est = pinned_[0];
-          const int flag = (int)pinned_[1];
-          if (flag < 0) throw SetupError{NAMG_E_NONFINITE, "non-finite value in the Arnoldi step"};
-          if (st.iters < p.res_hist_cap) p.res_hist[st.iters] = est;
-          st.iters++;
-          st.relres_est = est;
-          if (trace) std::fprintf(stderr, "[namg]   iter %d est %.3e\n", st.iters, est);
-          if (flag == 1) {
-            k = i + 1;
-            break;
+          if (i < sync_at && i + 1 < me) continue;
+          wait_stream(s);
+          for (int j = first_unread; j <= i; ++j) {
+            const double est = pinned_[step_slot(j)];
+            const int flag = (int)pinned_[step_slot(j) + 1];
+            if (flag < 0) throw SetupError{NAMG_E_NONFINITE, "non-finite value in the Arnoldi step"};
+            if (st.iters < p.res_hist_cap) p.res_hist[st.iters] = est;
+            st.iters++;
+            st.relres_est = est;
+            if (trace) std::fprintf(stderr, "[namg]   iter %d est %.3e\n", st.iters, est);
+            if (flag == 1) {
+              k = j + 1;
+              stop = true;
+              break;
+            }
+            e_prev = e_last;
+            e_last = est;
           }
+          first_unread = i + 1;
+          int ahead = 1;
+          if (!timing && e_prev > 0.0 && e_last > 0.0) {
+            const double rate = 0.5 * e_last / e_prev;
+            double pred = e_last;
+            while (ahead < PLAN_AHEAD && i + ahead + 1 < me) {
+              pred *= rate;
+              if (!(pred > stop_level)) break;
+              ++ahead;
+            }
+          }
+          sync_at = i + ahead;
         }
         if (orth) st.loss_orth = std::max(st.loss_orth, loss_of_orthogonality(k, m, ws, s));
         launch_small(&k_backsolve, s, ks, k);
@@ -711,8 +751,23 @@ class Solver final : public SolverBase {
   // Deterministic final reduction written straight into host-mapped memory, then read by the host.
   double reduce_read(const double *partial, int32_t nb, hipStream_t s) {
     launch_small(&k_reduce, s, partial, nb, pinned_dev_ + 2);
-    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    wait_stream(s);
     return pinned_[2];
+  }
+
+  // Steps issued ahead of the host's reading of their stop flags (see run).
+  static constexpr int PLAN_AHEAD = 4;
+  static constexpr int step_slot(int i) { return 4 + 2 * i; }
+
+  // Waits until stream s is idle by polling it: the solve waits once per Arnoldi step, for a few
+  // microseconds of work at a time, and a blocking wait adds its wake-up latency to each of those waits.
+  // Errors as hipStreamSynchronize.
+  static void wait_stream(hipStream_t s) {
+    while (true) {
+      const hipError_t e = hipStreamQuery(s);
+      if (e == hipSuccess) return;
+      if (e != hipErrorNotReady) hip_check(e, "hipStreamQuery");
+    }
   }
 
   // ------------------------------------------------------------------ V-cycle row operations
@@ -758,6 +813,10 @@ class Solver final : public SolverBase {
   }
 
   void emit(const RowOp &op, hipStream_t s) {
+    // a unit-row matrix (a prolongation's layout) is only read by the prolongation kernels, which receive
+    // its masks; any other row kernel would read its entries as plain SELL-64 and gather out of range
+    if (op.t.M.umask && op.kind != ROP_PROLONG)
+      throw SetupError{NAMG_E_INVALID, "internal: unit-row layout passed to a row kernel other than prolongation"};
     if (record_) {
       record_->push_back(op);
       return;
@@ -765,20 +824,20 @@ class Solver final : public SolverBase {
     const RowTask<T> &t = op.t;
     switch (op.kind) {
       case ROP_RESIDUAL:
-        launch(op.family, op.level, op.bytes, sel_residual<T>(op.group), op.grid, s, NAMG_HEAD_ARGS(t.M), t.a, t.c, t.b,
+        launch(op.family, op.level, op.bytes, sel_residual<T>(op.group, t.M.unroll), op.grid, s, NAMG_HEAD_ARGS(t.M), t.a, t.c, t.b,
                t.o0, t.o1, t.M.mul);
         break;
       case ROP_NEUMANN:
-        launch(op.family, op.level, op.bytes, sel_neumann<T>(op.group), op.grid, s, NAMG_HEAD_ARGS(t.M), t.a, t.c, t.d,
+        launch(op.family, op.level, op.bytes, sel_neumann<T>(op.group, t.M.unroll), op.grid, s, NAMG_HEAD_ARGS(t.M), t.a, t.c, t.d,
                t.b, t.o0, t.M.mul);
         break;
       case ROP_SPMV:
-        launch(op.family, op.level, op.bytes, sel_spmv<T, T, T, T>(op.group), op.grid, s, NAMG_HEAD_ARGS(t.M), t.b, t.c,
+        launch(op.family, op.level, op.bytes, sel_spmv<T, T, T, T>(op.group, t.M.unroll), op.grid, s, NAMG_HEAD_ARGS(t.M), t.b, t.c,
                t.o0, t.o1, t.M.mul);
         break;
       case ROP_PROLONG:
         launch(op.family, op.level, op.bytes, sel_prolong<T>(op.group), op.grid, s, NAMG_HEAD_ARGS(t.M), t.o0, t.b,
-               t.M.mul);
+               t.M.mul, t.M.umask, t.M.smeta, t.M.ncols, t.M.unroll);
         break;
       case ROP_AXPY:
         launch(op.family, op.level, op.bytes, &k_axpy<T>, op.grid, s, t.a, t.c, t.d, t.o0, t.n);
@@ -1042,7 +1101,9 @@ class Solver final : public SolverBase {
   int ws_m_ = 0;
   int64_t ldv_ = 0, ldz_ = 0;
   int32_t nblk_red_ = 0, nblk_dot_ = 0, rows_per_dot_ = 0;
-  double *pinned_ = nullptr;      // host-mapped scalars: [0] estimate, [1] flag, [2] reductions
+  // host-mapped scalars: [0] estimate, [1] flag (column 0, and the serving engine's steps), [2] reductions,
+  // then (estimate, flag) of Arnoldi step i at step_slot(i)
+  double *pinned_ = nullptr;
   double *pinned_dev_ = nullptr;  // the same memory as seen from the device
   double alg_ = 0.0;
   int prof_family_ = NAMG_KF_NONE, prof_level_ = -1, prof_every_ = 1;

@@ -10,7 +10,9 @@ on the matrices of real hierarchies that
   * every index and value load stays inside the stored arrays,
   * every gather stays inside the gathered vector,
   * the sums over the real entries equal the oracle's product: bit for bit with one lane per row (entry
-    order), to rounding with lane groups (lane j sums entries j, j + G, ..., then a fixed butterfly).
+    order), to rounding with lane groups (lane j sums entries j, j + G, ..., then a fixed butterfly);
+  * the prolongations' unit-row layout (a C point's row stores no entry) loads and gathers in range and
+    gives the plain layout's bits.
 
 A model of the two-rows-per-lane kernel with the base column of a lane's second row taken even when the
 lane has no second row (an earlier form of that kernel) must show an out-of-range gather on the ragged
@@ -86,6 +88,105 @@ class Layout:
         self.idx[dst] = off if self.narrow else ci
         self.val[dst] = vals
         self.stored = stored
+
+
+class UnitLayout:
+    """The unit-row SELL layout of a prolongation, as the library packs it: the rows of C points (cf == 1)
+    store nothing (each must be the unit vector of its coarse index, the number of C points before it, else
+    `ok` is False and the plain layout is used); within slice s the l-th F row keeps entry k at
+    ptr[s] + k m_s + l, padded to the slice's longest F row."""
+
+    def __init__(self, rp, ci, vals, ncols, cf):
+        self.nrows = len(rp) - 1
+        self.ncols = ncols
+        self.mul = diag_mul(self.nrows, ncols)
+        rows = np.repeat(np.arange(self.nrows), np.diff(rp))
+        off = ci.astype(np.int64) - diag_base(rows, self.mul)
+        self.narrow = bool(off.size == 0 or (off.min() >= -32768 and off.max() <= 32767))
+        self.group = 1
+        lens = np.diff(rp)
+        unit = np.asarray(cf) == 1
+        nunits = int(unit.sum())
+        first = rp[:-1][unit]
+        self.ok = (nunits > 0 and bool(np.all(lens[unit] == 1)) and bool(np.all(vals[first] == 1.0))
+                   and bool(np.array_equal(ci[first], np.arange(nunits))))
+        nsl = (self.nrows + SELL_C - 1) // SELL_C
+        upad = np.zeros(nsl * SELL_C, bool)
+        upad[: self.nrows] = unit
+        bits = upad.reshape(nsl, SELL_C)
+        self.mask_bits = bits
+        self.before = np.concatenate([[0], np.cumsum(bits.sum(axis=1))[:-1]]).astype(np.int64)
+        lpad = np.zeros(nsl * SELL_C, np.int64)
+        lpad[: self.nrows] = np.where(unit, 0, lens)
+        expl = np.zeros(nsl * SELL_C, bool)
+        expl[: self.nrows] = ~unit
+        self.count = expl.reshape(nsl, SELL_C).sum(axis=1).astype(np.int64)
+        width = lpad.reshape(nsl, SELL_C).max(axis=1)
+        self.ptr = np.zeros(nsl + 1, np.int64)
+        np.cumsum(width * self.count, out=self.ptr[1:])
+        stored = int(self.ptr[-1])
+        self.stored = stored
+        self.idx = np.zeros(max(stored, 1), np.int64)
+        self.val = np.zeros(max(stored, 1))
+        # rank of each explicit row among its slice's explicit rows
+        rank = np.cumsum(expl.reshape(nsl, SELL_C), axis=1).reshape(-1)[: self.nrows] - 1
+        er = ~unit[rows]
+        k_in_row = np.arange(rp[-1]) - np.repeat(rp[:-1], lens)
+        dst = self.ptr[rows // SELL_C] + k_in_row * self.count[rows // SELL_C] + rank[rows]
+        self.idx[dst[er]] = (off if self.narrow else ci)[er]
+        self.val[dst[er]] = vals[er]
+
+
+def replay_prolong_unit(L, e, U=U):
+    """prolong_unit_rows's loads and gathers, row by row (a thread's second row, in FP32, runs the same index
+    stream): an F row walks its slots in chunks of U (4, or 8 where F rows average more than four entries);
+    a C point's row takes a virtual first entry (column = C points before it, value 1) in its one chunk,
+    whose loads follow the slots of the F row of rank `below` (columns clamped into range, not added).
+    Returns P e and the access record."""
+    a = Access(L)
+    row = np.arange(L.nrows, dtype=np.int64)
+    s, lane = row >> 6, row & 63
+    bits = L.mask_bits
+    is_unit = bits.reshape(-1)[row]
+    below = np.cumsum(bits, axis=1).reshape(-1)[row] - is_unit  # C points before this lane in its slice
+    mm = L.count[s]
+    m = np.maximum(mm, 1)
+    p0, lim = L.ptr[s], L.ptr[s + 1]
+    k = p0 + np.where(is_unit, np.where(mm > 0, np.minimum(below, mm - 1), 0), lane - below)
+    end = np.where(is_unit, p0, lim)
+    cu = L.before[s] + below
+    base = diag_base(row, L.mul) if L.narrow else np.zeros_like(row)
+    virt = is_unit.copy()
+    acc = np.zeros(L.nrows)
+    while True:
+        act = virt | (k < end)
+        if not act.any():
+            break
+        kb = np.where(k < lim, k, np.where(lim > 0, lim - 1, 0))
+        oks, cs, vs = [], [], []
+        for q in range(U):
+            kk = np.where(k + q * m < lim, k + q * m, kb)
+            ok = k + q * m < end
+            i, v = a.load(kk[act])
+            col = base[act] + i if L.narrow else i
+            c = np.clip(col, 0, L.ncols - 1)  # a slot that is not this row's decodes another row's offset
+            if q == 0:
+                va = virt[act]
+                ok = ok.copy()
+                ok[act] = ok[act] | va
+                c = np.where(va, cu[act], c)
+                v = np.where(va, 1.0, v)
+            oks.append(ok[act])
+            cs.append(c)
+            vs.append(v)
+        xs = [a.gather(e, c) for c in cs]
+        part = acc[act]
+        for q in range(U):
+            part = np.where(oks[q], part + vs[q] * xs[q], part)
+        acc[act] = part
+        virt[:] = False
+        k = k + U * m
+    return acc, a
 
 
 class Access:
@@ -223,7 +324,8 @@ def strict_part(rp, ci, vals, lower):
 
 
 def hierarchy_operators(namg, A, **kw):
-    """Every operator a V-cycle multiplies with, as (name, rowptr, colind, vals, ncols, force_group)."""
+    """Every operator a V-cycle multiplies with, as (name, rowptr, colind, vals, ncols, force_group, cf); cf is
+    the level's C/F splitting for a prolongation, else None."""
     H = namg.Hierarchy(A, device=-1, **kw)
     info = H.info()
     ops = []
@@ -231,21 +333,21 @@ def hierarchy_operators(namg, A, **kw):
         e = H.export_level(l)
         Arp, Aci, Av = e["A"]
         n = len(Arp) - 1
-        ops.append((f"A{l}", Arp, Aci, Av, n, 0))
+        ops.append((f"A{l}", Arp, Aci, Av, n, 0, None))
         if l == 0:
-            ops.append(("A0 fp64", Arp, Aci, Av, n, 1))
+            ops.append(("A0 fp64", Arp, Aci, Av, n, 1, None))
         Prp, Pci, Pv, nc = e["P"]
-        ops.append((f"P{l}", Prp, Pci, Pv, nc, 0))
+        ops.append((f"P{l}", Prp, Pci, Pv, nc, 0, e["cf"]))
         R = sp.csr_matrix((Pv, Pci, Prp), shape=(n, nc)).T.tocsr()
         R.sort_indices()
-        ops.append((f"R{l}", R.indptr, R.indices, R.data, n, 0))
+        ops.append((f"R{l}", R.indptr, R.indices, R.data, n, 0, None))
         for lower in (True, False):
             rp, ci, v = strict_part(Arp, Aci, Av, lower)
-            ops.append((f"A{l} {'lower' if lower else 'upper'}", rp, ci, v, n, 0))
+            ops.append((f"A{l} {'lower' if lower else 'upper'}", rp, ci, v, n, 0, None))
         if l == 0 and kw.get("ilu_levels", 1) != 0:
             f = H.export_ilu(0)
-            ops.append(("ILU L_s", *f["L"], n, 0))
-            ops.append(("ILU U_s", *f["U"], n, 0))
+            ops.append(("ILU L_s", *f["L"], n, 0, None))
+            ops.append(("ILU U_s", *f["U"], n, 0, None))
     H.close()
     return ops
 
@@ -261,7 +363,7 @@ def _systems():
 def test_row_kernel_accesses_in_range(namg, case):
     name, A = list(_systems())[case]
     rng = np.random.default_rng(case)
-    for label, rp, ci, v, ncols, fg in hierarchy_operators(namg, A):
+    for label, rp, ci, v, ncols, fg, cf in hierarchy_operators(namg, A):
         L = Layout(np.asarray(rp), np.asarray(ci), np.asarray(v), ncols, fg)
         x = rng.standard_normal(ncols)
         y, acc = replay_one_row_per_lane(L, x)
@@ -273,6 +375,17 @@ def test_row_kernel_accesses_in_range(namg, case):
         else:
             ref = sp.csr_matrix((v, ci, rp), shape=(len(rp) - 1, ncols)) @ x
             np.testing.assert_allclose(y, ref, rtol=1e-13, atol=1e-13)
+        if cf is not None:
+            Lu = UnitLayout(np.asarray(rp), np.asarray(ci), np.asarray(v), ncols, cf)
+            assert Lu.ok, (name, label)  # a C/F splitting's P always has the unit-row form
+            assert Lu.stored < L.stored, (name, label)
+            for unroll in (4, 8):
+                yu, accu = replay_prolong_unit(Lu, x, unroll)
+                assert accu.bad_loads == 0 and accu.bad_gathers == 0, (name, label, "unit rows", unroll,
+                                                                      accu.bad_loads, accu.bad_gathers)
+                ref = sp.csr_matrix((v, ci, rp), shape=(len(rp) - 1, ncols)) @ x
+                np.testing.assert_allclose(yu, ref, rtol=1e-14, atol=1e-14)
+                assert np.array_equal(yu, y), (name, label, unroll)  # entry order kept: the plain layout's bits
         if L.group == 1:
             y2, acc2 = replay_two_rows_per_lane(L, x)
             assert acc2.bad_loads == 0 and acc2.bad_gathers == 0, (name, label, "two rows per lane",
@@ -291,3 +404,30 @@ def test_replay_detects_second_row_base_past_the_end():
     _, new = replay_two_rows_per_lane(L, x)
     assert old.bad_gathers > 0
     assert new.bad_gathers == 0 and new.bad_loads == 0
+
+
+def test_unit_layout_needs_its_masks():
+    """The unit-row layout stores each F row's entries with the stride of its slice's F-row count, and a 16-bit
+    offset relative to that row's own diagonal base. Read as plain SELL-64 (the masks not reaching the
+    kernel), lanes decode other rows' offsets against their own base and gather outside e; with the masks
+    every access stays in range."""
+    A = config_system("c2", 24)[0]
+    found = 0
+    for label, rp, ci, v, ncols, fg, cf in hierarchy_operators(namg_module(), A):
+        if cf is None:
+            continue
+        Lu = UnitLayout(np.asarray(rp), np.asarray(ci), np.asarray(v), ncols, cf)
+        plain = Layout(np.asarray(rp), np.asarray(ci), np.asarray(v), ncols)
+        plain.ptr, plain.idx, plain.val, plain.stored = Lu.ptr, Lu.idx, Lu.val, Lu.stored
+        x = np.random.default_rng(1).standard_normal(ncols)
+        _, wrong = replay_one_row_per_lane(plain, x)
+        _, right = replay_prolong_unit(Lu, x)
+        found += wrong.bad_gathers
+        assert right.bad_gathers == 0 and right.bad_loads == 0, label
+    assert found > 0
+
+
+def namg_module():
+    import paper_2112_14681_amd as m
+
+    return m
