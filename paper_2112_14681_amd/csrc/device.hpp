@@ -418,12 +418,16 @@ inline UnitRows unit_rows_of(const HostCsr &P, const std::vector<int8_t> &cf) {
 
 // Layout tuning, read once from the environment (defaults in parentheses):
 //   NAMG_LANE_ENTRIES (8): CSR lane groups are sized so that a lane takes about this many entries;
+//   NAMG_LANE_ENTRIES_SMALL, NAMG_SMALL_ROWS (as NAMG_LANE_ENTRIES, 65536): the same for matrices of fewer
+//   rows, whose kernels are latency-bound (shorter chains per lane);
 //   NAMG_SELL_MIN_ROWS (524288): a matrix with at least this many rows uses SELL-64 whatever its row
 //   length (one lane per row already fills the device);
 //   NAMG_WIDE_ROWS (off): SELL-64 matrices whose rows average more entries load them in chunks of eight;
 //   NAMG_UNIT_UNROLL (by row length): 4 or 8 entries per chunk for prolongations in the unit-row layout.
 struct LayoutTuning {
   int lane_entries = 8;
+  int lane_entries_small = 8;            // the same for matrices of fewer than small_rows rows
+  int64_t small_rows = int64_t(1) << 16;
   int64_t sell_min_rows = int64_t(1) << 19;
   double wide_rows = 1e9;
   int unit_unroll = 0;  // 0: by the F rows' average length
@@ -432,7 +436,9 @@ struct LayoutTuning {
 inline const LayoutTuning &layout_tuning() {
   static const LayoutTuning t = [] {
     LayoutTuning v;
-    if (const char *e = std::getenv("NAMG_LANE_ENTRIES")) v.lane_entries = std::max(1, std::atoi(e));
+    if (const char *e = std::getenv("NAMG_LANE_ENTRIES")) v.lane_entries = v.lane_entries_small = std::max(1, std::atoi(e));
+    if (const char *e = std::getenv("NAMG_LANE_ENTRIES_SMALL")) v.lane_entries_small = std::max(1, std::atoi(e));
+    if (const char *e = std::getenv("NAMG_SMALL_ROWS")) v.small_rows = std::max<int64_t>(1, std::atoll(e));
     if (const char *e = std::getenv("NAMG_SELL_MIN_ROWS")) v.sell_min_rows = std::max<int64_t>(1, std::atoll(e));
     if (const char *e = std::getenv("NAMG_WIDE_ROWS")) v.wide_rows = std::atof(e);
     if (const char *e = std::getenv("NAMG_UNIT_UNROLL")) v.unit_unroll = std::atoi(e) == 8 ? 8 : 4;
@@ -454,8 +460,9 @@ inline int choose_group(int64_t nrows, int64_t nnz) {
   const LayoutTuning &t = layout_tuning();
   const double avg = nrows > 0 ? (double)nnz / (double)nrows : 0.0;
   if (avg <= 10.0 || nrows >= t.sell_min_rows) return 1;
+  const int per_lane = nrows < t.small_rows ? t.lane_entries_small : t.lane_entries;
   int g = 2;
-  while (g < 64 && g * t.lane_entries < avg) g <<= 1;
+  while (g < 64 && g * per_lane < avg) g <<= 1;
   return g;
 }
 
