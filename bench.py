@@ -68,7 +68,7 @@ PROFILE_EVERY = 3  # time every 3rd run of consecutive dominant-kernel dispatche
 # Measured HBM traffic of the dominant kernel (bytes per launch): rocprofv3 FETCH_SIZE x 2.000 plus
 # WRITE_SIZE x 1.000, factors from a 2 GiB copy (profiles/k_neumann_level0_c2_128cubed_traffic.md).
 # Valid for the kernel version it was taken on; None when the kernel has changed since.
-DOMINANT_TRAFFIC_BYTES = {("c2", 128, "fp64", "ilu0"): 120.2e6}
+DOMINANT_TRAFFIC_BYTES = {}
 
 
 def copy_ceiling(torch, nbytes=2 << 30, reps=10):
@@ -485,13 +485,19 @@ def main():
         # half's values with int32 indices, its row pointers, and the vectors r, D^-1, g_in, g_out)
         s_val = 8 if prec == namg.FP64 else 4
         pass_bytes = (A.nnz - A.n) / 2 * (s_val + 4) + 4 * (A.n + 1) + 4 * s_val * A.n
-        kernel_bytes = prof["alg_bytes"] / prof["launches"]  # what the kernel itself moves (16-bit offsets)
+        # what the kernel itself moves: at 128^3 the triangle is in the slice-diagonal form (8 or 4 B per entry
+        # and 4 B per 64 entries, no per-entry column), so the per-unit figure above, which counts int32
+        # columns, exceeds it and `frac` can pass 1; `kernel_GBps` and `traffic_GBps` are the rates of the
+        # bytes actually moved
+        kernel_bytes = prof["alg_bytes"] / prof["launches"]
         per_launch_ms = prof["total_ms"] / prof["launches"]
         achieved = pass_bytes / (per_launch_ms * 1e-3) / 1e9
+        traffic = DOMINANT_TRAFFIC_BYTES.get((meta["name"], meta["N"], args.precision, args.smoother))
         out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                            "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                           "traffic": DOMINANT_TRAFFIC_BYTES.get((meta["name"], meta["N"], args.precision,
-                                                                  args.smoother)),
+                           "traffic": traffic,
+                           # measured HBM bytes per launch over the same live time: what the memory system moved
+                           "traffic_GBps": round(traffic / (per_launch_ms * 1e-3) / 1e9, 1) if traffic else None,
                            "kernel": f"k_neumann<1,{'double' if prec == namg.FP64 else 'float'}> on level 0 "
                                      f"({'ILU(0)' if args.smoother == 'ilu0' else 'poly-GS'} Neumann term)",
                            "launches_timed": prof["launches"],

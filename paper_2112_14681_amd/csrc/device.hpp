@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <exception>
+#include <iterator>
 #include <map>
 #include <mutex>
 #include <string>
@@ -324,6 +325,13 @@ struct DeviceLevels {
 //    j, j+G, ...; the G partial sums are combined by a fixed xor-butterfly. Used for the long rows of
 //    the Galerkin operators on coarse levels, where one lane per row would walk 30-100 dependent
 //    entries.
+//  * slice-diagonal SELL-64: a square SELL-64 matrix whose rows within each slice share a few column
+//    offsets from the diagonal (stencil operators in natural order and their red-black coarsenings)
+//    stores no per-entry column at all. Slot k of slice s holds, for all 64 rows, the entries at one
+//    offset d(s, k) from the row's diagonal (value 0 where a row has no entry there); the slots of a
+//    slice are the union of its rows' offsets in increasing order, so each row's entries keep their CSR
+//    order. One int32 offset per slot (64 entries) replaces the 2- or 4-byte column of every entry, and
+//    a slot's gathers are 64 consecutive elements of x. Chosen per matrix, see LayoutCount.
 // Column indices are stored in one of two widths, also chosen per matrix: as 16-bit offsets from the
 // row's scaled diagonal, base(r) = (r * mul) >> 20 with mul = (ncols << 20) / nrows, when every column
 // of the matrix lies within [-32768, 32767] of its row's base (stencil operators and their Galerkin
@@ -359,6 +367,7 @@ struct MatView {
   const int32_t *ptr = nullptr;    // SELL slice pointers (group 1) or CSR row pointers (group > 1)
   const int32_t *col = nullptr;    // 32-bit columns, or null when col16 is used
   const int16_t *col16 = nullptr;  // 16-bit offsets from diag_base(row, mul), or null
+  const int32_t *dia = nullptr;    // slice-diagonal form: [ncols - 1, then one offset per stored slot], or null
   const T *val = nullptr;
   const uint64_t *umask = nullptr;  // unit-row SELL (prolongations): per slice, bit l = row 64 s + l is a unit row
   const int32_t *smeta = nullptr;   // unit-row SELL: per slice, unit rows before it and explicit rows in it
@@ -423,7 +432,8 @@ inline UnitRows unit_rows_of(const HostCsr &P, const std::vector<int8_t> &cf) {
 //   NAMG_SELL_MIN_ROWS (524288): a matrix with at least this many rows uses SELL-64 whatever its row
 //   length (one lane per row already fills the device);
 //   NAMG_WIDE_ROWS (off): SELL-64 matrices whose rows average more entries load them in chunks of eight;
-//   NAMG_UNIT_UNROLL (by row length): 4 or 8 entries per chunk for prolongations in the unit-row layout.
+//   NAMG_UNIT_UNROLL (by row length): 4 or 8 entries per chunk for prolongations in the unit-row layout;
+//   NAMG_DIA (1): 0 keeps every matrix out of the slice-diagonal form.
 struct LayoutTuning {
   int lane_entries = 8;
   int lane_entries_small = 8;            // the same for matrices of fewer than small_rows rows
@@ -431,6 +441,7 @@ struct LayoutTuning {
   int64_t sell_min_rows = int64_t(1) << 19;
   double wide_rows = 1e9;
   int unit_unroll = 0;  // 0: by the F rows' average length
+  bool dia = true;
 };
 
 inline const LayoutTuning &layout_tuning() {
@@ -442,6 +453,7 @@ inline const LayoutTuning &layout_tuning() {
     if (const char *e = std::getenv("NAMG_SELL_MIN_ROWS")) v.sell_min_rows = std::max<int64_t>(1, std::atoll(e));
     if (const char *e = std::getenv("NAMG_WIDE_ROWS")) v.wide_rows = std::atof(e);
     if (const char *e = std::getenv("NAMG_UNIT_UNROLL")) v.unit_unroll = std::atoi(e) == 8 ? 8 : 4;
+    if (const char *e = std::getenv("NAMG_DIA")) v.dia = std::atoi(e) != 0;
     return v;
   }();
   return t;
@@ -466,6 +478,106 @@ inline int choose_group(int64_t nrows, int64_t nnz) {
   return g;
 }
 
+// The slice-diagonal form (see the layout notes above) is taken by a square matrix of group 1 that is not a
+// unit-row prolongation when
+//   * every row's columns strictly increase (so the slots' offset order is each row's entry order),
+//   * no slice's union of offsets exceeds dia_cap(its longest row), and
+//   * it stores fewer bytes than SELL-64: slots x 64 x value bytes + 4 per slot, against SELL-64's
+//     entries x (value bytes + column bytes).
+// DMat::build, pack_device and the serving footprint all decide through LayoutCount or these functions.
+__host__ __device__ inline int64_t dia_cap(int64_t longest_row) { return 2 * longest_row + 8; }
+inline bool dia_wins(int64_t sell_stored, int64_t dia_stored, bool narrow, int64_t val_bytes) {
+  if (!layout_tuning().dia) return false;
+  const int64_t sell = sell_stored * (val_bytes + (narrow ? 2 : 4));
+  const int64_t dia = dia_stored * val_bytes + 4 * (dia_stored / SELL_C + 1);
+  return dia < sell;
+}
+
+// Sizes of one DMat layout, counted row by row in increasing row order (each row's col() calls, in its
+// entry order, then row()): the entries, the SELL-64 storage (each slice as wide as its longest row),
+// whether every column fits the 16-bit offset form, and the slice-diagonal storage (each slice as wide as
+// the union of its rows' offsets) with whether that form is allowed.
+struct LayoutCount {
+  int64_t nnz = 0, sell_stored = 0, dia_stored = 0;
+  int32_t slice_w = 0;
+  bool narrow = true;
+  bool square = true;  // the matrix is square (the slice-diagonal form needs it)
+  bool dia_ok = true;  // rows strictly increasing and every completed slice within its cap
+  std::vector<int32_t> row_off, prev_off, uni, merged;  // prev_off: the slice's last row that was merged
+
+  void col(int64_t offset) {
+    if (offset < -32768 || offset > 32767) narrow = false;
+    if (!dia_ok) return;
+    if (!row_off.empty() && offset <= row_off.back()) {
+      dia_ok = false;
+      return;
+    }
+    row_off.push_back((int32_t)offset);
+  }
+  void row(int32_t r, int32_t len) {
+    nnz += len;
+    slice_w = std::max(slice_w, len);
+    // a row with the offsets of the slice's previous row adds nothing to the union (the stencil case)
+    if (dia_ok && !row_off.empty() && row_off != prev_off) {
+      merged.clear();
+      std::set_union(uni.begin(), uni.end(), row_off.begin(), row_off.end(), std::back_inserter(merged));
+      uni.swap(merged);
+      prev_off.swap(row_off);
+    }
+    row_off.clear();
+    if ((r + 1) % SELL_C == 0) {
+      sell_stored += (int64_t)slice_w * SELL_C;
+      if (dia_ok) {
+        if ((int64_t)uni.size() > dia_cap(slice_w))
+          dia_ok = false;
+        else
+          dia_stored += (int64_t)uni.size() * SELL_C;
+      }
+      uni.clear();
+      prev_off.clear();
+      slice_w = 0;
+    }
+  }
+  // the storage with the last, partial slice (nr rows counted)
+  int64_t sell_total() const { return sell_stored + (int64_t)slice_w * SELL_C; }
+  int64_t dia_total() const { return dia_stored + (int64_t)uni.size() * SELL_C; }
+  // the slice-diagonal choice for a DMat<T> of group `group`
+  template <class T>
+  bool use_dia(int group) const {
+    return group == 1 && square && dia_ok && (int64_t)uni.size() <= dia_cap(slice_w) &&
+           dia_wins(sell_total(), dia_total(), narrow, sizeof(T));
+  }
+  // device bytes of the DMat<T> of nr rows: DMat::build's layout choice, and the size class each of its
+  // buffers (pointers, column indices or slot offsets, values) allocates
+  template <class T>
+  int64_t bytes(int32_t nr, int force_group = 0) const {
+    const int group = force_group > 0 ? force_group : choose_group(nr, nnz);
+    const int64_t ib = narrow ? 2 : 4;
+    if (group > 1) return alloc_bytes((int64_t)nr + 1, 4) + alloc_bytes(nnz, ib) + alloc_bytes(nnz, sizeof(T));
+    const int64_t nslices = ((int64_t)nr + SELL_C - 1) / SELL_C;
+    if (use_dia<T>(group)) {
+      const int64_t st = dia_total();
+      return alloc_bytes(nslices + 1, 4) + alloc_bytes(st / SELL_C + 1, 4) + alloc_bytes(st, sizeof(T));
+    }
+    const int64_t stored = sell_total();
+    return alloc_bytes(nslices + 1, 4) + alloc_bytes(stored, ib) + alloc_bytes(stored, sizeof(T));
+  }
+};
+
+// LayoutCount of every entry of A (allow_dia false: the slice-diagonal form is not considered, nor counted).
+inline LayoutCount layout_count(const HostCsr &A, bool allow_dia = true) {
+  LayoutCount c;
+  c.square = A.nr == A.nc;
+  c.dia_ok = allow_dia;
+  const int64_t mul = diag_mul(A.nr, A.nc);
+  for (int32_t r = 0; r < A.nr; ++r) {
+    const int32_t base = diag_base(r, mul);
+    for (int32_t k = A.rp[r]; k < A.rp[r + 1]; ++k) c.col((int64_t)A.ci[k] - base);
+    c.row(r, A.rp[r + 1] - A.rp[r]);
+  }
+  return c;
+}
+
 // Per-slice (C points before the slice, explicit rows in it) pairs of the unit-row layout.
 inline std::vector<int32_t> unit_meta(const UnitRows &u) {
   std::vector<int32_t> m(2 * std::max<size_t>(u.mask.size(), 1), 0);
@@ -483,17 +595,20 @@ struct DMat {
   int64_t explicit_nnz = 0, explicit_rows = 0;  // unit-row layout: the entries and count of the explicit rows
   bool narrow = false;
   bool unit = false;  // the unit-row SELL layout (prolongations, see UnitRows)
+  bool dia = false;   // the slice-diagonal SELL layout (see LayoutCount)
   int unroll = 4;     // entries per chunk of the row kernels (choose_unroll; unit-row layout: see view())
   DevBuf<int32_t> ptr, col;
   DevBuf<int16_t> col16;
   DevBuf<T> val;
   DevBuf<uint64_t> umask;
   DevBuf<int32_t> smeta;
+  DevBuf<int32_t> doff;  // slice-diagonal form: ncols - 1, then the offset of every stored slot
   MatView<T> view() const {
     MatView<T> v;
     v.ptr = ptr.get();
-    v.col = narrow ? nullptr : col.get();
-    v.col16 = narrow ? col16.get() : nullptr;
+    v.col = (narrow || dia) ? nullptr : col.get();
+    v.col16 = (narrow && !dia) ? col16.get() : nullptr;
+    v.dia = dia ? doff.get() : nullptr;
     v.val = val.get();
     v.umask = unit ? umask.get() : nullptr;
     v.smeta = unit ? smeta.get() : nullptr;
@@ -510,13 +625,15 @@ struct DMat {
   double bytes() const {
     const double nslices = (double)((nrows + SELL_C - 1) / SELL_C);
     if (unit) return (double)explicit_nnz * (sizeof(T) + (narrow ? 2.0 : 4.0)) + 4.0 * (nslices + 1.0) + 16.0 * nslices;
+    if (dia) return (double)stored * sizeof(T) + 4.0 * ((double)stored / SELL_C + 1.0) + 4.0 * (nslices + 1.0);
     const double nptr = group > 1 ? (double)nrows + 1.0 : nslices + 1.0;
     return (double)nnz * (sizeof(T) + (narrow ? 2.0 : 4.0)) + 4.0 * nptr;
   }
 
   // unit_cf: A is a prolongation and unit_cf its level's C/F splitting; packed in the unit-row layout when
-  // it applies (see UnitRows)
-  void build(const HostCsr &A, MemCounter *mc, int force_group = 0, const std::vector<int8_t> *unit_cf = nullptr) {
+  // it applies (see UnitRows). allow_dia false: the slice-diagonal form is not considered.
+  void build(const HostCsr &A, MemCounter *mc, int force_group = 0, const std::vector<int8_t> *unit_cf = nullptr,
+             bool allow_dia = true) {
     nrows = A.nr;
     ncols = A.nc;
     nnz = A.nnz();
@@ -525,12 +642,17 @@ struct DMat {
     group = force_group > 0 ? force_group : choose_group(nrows, nnz);
     unroll = choose_unroll(group, nrows, nnz);
     unit = false;
+    dia = false;
     if (unit_cf && group == 1) {
       const UnitRows u = unit_rows_of(A, *unit_cf);
       if (u.ok) {
         build_unit(A, u, mc);
         return;
       }
+    }
+    if (allow_dia && group == 1 && nrows == ncols && layout_count(A).use_dia<T>(group)) {
+      build_dia(A, mc);
+      return;
     }
     std::vector<int32_t> hptr;
     std::vector<int32_t> hcol;  // wide columns (padding: column 0)
@@ -593,6 +715,49 @@ struct DMat {
       col.alloc(hcol.size(), mc);
       col.upload(hcol.data(), hcol.size());
     }
+    val.alloc(hval.size(), mc);
+    val.upload(hval.data(), hval.size());
+  }
+
+  // The slice-diagonal layout of the square matrix A (LayoutCount::use_dia holds): slice s stores its union
+  // of offsets in increasing order, slot k at ptr[s] + 64 k (entries) and doff[1 + ptr[s] / 64 + k] (offset);
+  void build_dia(const HostCsr &A, MemCounter *mc) {
+    dia = true;
+    group = 1;
+    unroll = 4;  // not used by the slice-diagonal kernels (they chunk by the slice's width)
+    const int32_t nslices = (nrows + SELL_C - 1) / SELL_C;
+    std::vector<int32_t> hptr(nslices + 1, 0);
+    std::vector<int32_t> hoff(1, ncols - 1);
+    std::vector<int32_t> uni, merged, ro;
+    for (int32_t s = 0; s < nslices; ++s) {
+      uni.clear();
+      for (int32_t r = s * SELL_C; r < std::min(nrows, (s + 1) * SELL_C); ++r) {
+        merged.clear();
+        ro.clear();
+        for (int32_t k = A.rp[r]; k < A.rp[r + 1]; ++k) ro.push_back(A.ci[k] - r);
+        std::set_union(uni.begin(), uni.end(), ro.begin(), ro.end(), std::back_inserter(merged));
+        uni.swap(merged);
+      }
+      hptr[s + 1] = hptr[s] + (int32_t)uni.size() * SELL_C;
+      hoff.insert(hoff.end(), uni.begin(), uni.end());
+    }
+    stored = hptr[nslices];
+    std::vector<T> hval(stored, T(0));
+    for (int32_t s = 0; s < nslices; ++s) {
+      const int32_t *o = hoff.data() + 1 + hptr[s] / SELL_C;
+      const int32_t w = (hptr[s + 1] - hptr[s]) / SELL_C;
+      for (int32_t r = s * SELL_C; r < std::min(nrows, (s + 1) * SELL_C); ++r) {
+        int32_t j = 0;
+        for (int32_t k = A.rp[r]; k < A.rp[r + 1]; ++k) {
+          while (j < w && o[j] != A.ci[k] - r) ++j;
+          hval[(int64_t)hptr[s] + (int64_t)j * SELL_C + (r - s * SELL_C)] = (T)A.v[k];
+        }
+      }
+    }
+    ptr.alloc(hptr.size(), mc);
+    ptr.upload(hptr.data(), hptr.size());
+    doff.alloc(hoff.size(), mc);
+    doff.upload(hoff.data(), hoff.size());
     val.alloc(hval.size(), mc);
     val.upload(hval.data(), hval.size());
   }

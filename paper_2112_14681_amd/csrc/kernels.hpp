@@ -43,6 +43,12 @@ __device__ __forceinline__ double block_sum(double v, double *lds) {
   return t;
 }
 
+// acc + v x with one rounding. The row kernels add every product this way, so that the rounding of a row sum
+// does not depend on whether the compiler keeps a product and its sum in one basic block (it fuses them only
+// then): every layout gives the same bits for the same row.
+__device__ __forceinline__ double mul_add(double v, double x, double acc) { return __builtin_fma(v, x, acc); }
+__device__ __forceinline__ float mul_add(float v, float x, float acc) { return __builtin_fmaf(v, x, acc); }
+
 // This thread's share of sum(p[0..n)): p[tid] + p[tid + BLK] + ..., added in that order. Loads go in
 // groups of eight so that a long sum waits on one memory latency per group, not per element.
 __device__ __forceinline__ double strided_sum(const double *__restrict__ p, int32_t n) {
@@ -98,7 +104,7 @@ __device__ __forceinline__ Acc row_dot_impl(const MatView<TM> &A, const TX *__re
     for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (k + u * STEP < end) acc += (Acc)v[u] * (Acc)xv[u];
+      if (k + u * STEP < end) acc = mul_add((Acc)v[u], (Acc)xv[u], acc);
   }
   if constexpr (G > 1) {
 #pragma unroll
@@ -107,8 +113,129 @@ __device__ __forceinline__ Acc row_dot_impl(const MatView<TM> &A, const TX *__re
   return acc;
 }
 
+// K slots j .. j + K - 1 of one slice-diagonal row (all of them exist): the K offsets (wave-uniform, one
+// merged scalar load), then K value loads and K gathers, none waiting on another, then the K products in
+// slot order. A padding slot (value 0) adds 0 times an in-range element of x: the sum is the row's CSR-order
+// sum whenever x is finite (a -0 sum may come out +0).
+template <int K, class Acc, class TM, class TX>
+__device__ __forceinline__ void dia_slots(const TM *__restrict__ vp, const int32_t *__restrict__ off,
+                                          const TX *__restrict__ x, int32_t row, int32_t cmax, int32_t j, Acc &acc) {
+  int32_t o[K];
+  TM v[K];
+  TX xv[K];
+#pragma unroll
+  for (int u = 0; u < K; ++u) o[u] = off[j + u];
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    v[u] = vp[(int64_t)(j + u) * SELL_C];
+    xv[u] = x[min(max(row + o[u], 0), cmax)];
+  }
+  // every product is added, padding slots included (value 0 times an element of x, which is finite in any
+  // solve that has not already failed its non-finite check): with no condition, no gather can be sunk
+  // behind a wait
+#pragma unroll
+  for (int u = 0; u < K; ++u) acc = mul_add((Acc)v[u], (Acc)xv[u], acc);
+}
+
+// The same for two rows (r0 of one slice, r1 of the next) whose slices both have slots j .. j + K - 1.
+template <int K, class Acc, class TM, class TX>
+__device__ __forceinline__ void dia_slots2(const TM *__restrict__ vp0, const int32_t *__restrict__ off0,
+                                           const TM *__restrict__ vp1, const int32_t *__restrict__ off1,
+                                           const TX *__restrict__ x, int32_t r0, int32_t r1, int32_t cmax, int32_t j,
+                                           Acc &a0, Acc &a1) {
+  int32_t o0[K], o1[K];
+  TM v0[K], v1[K];
+  TX x0[K], x1[K];
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    o0[u] = off0[j + u];
+    o1[u] = off1[j + u];
+  }
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    v0[u] = vp0[(int64_t)(j + u) * SELL_C];
+    v1[u] = vp1[(int64_t)(j + u) * SELL_C];
+    x0[u] = x[min(max(r0 + o0[u], 0), cmax)];
+    x1[u] = x[min(max(r1 + o1[u], 0), cmax)];
+  }
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    a0 = mul_add((Acc)v0[u], (Acc)x0[u], a0);
+    a1 = mul_add((Acc)v1[u], (Acc)x1[u], a1);
+  }
+}
+
+// Slots j .. w - 1 of one row: chunks of eight, then one chunk of exactly the rest (a wave-uniform switch), so
+// no slot past the slice's end is loaded and a row of w slots waits on ceil(w / 8) rounds of loads.
+template <class Acc, class TM, class TX>
+__device__ __forceinline__ void dia_row_from(const TM *__restrict__ vp, const int32_t *__restrict__ off,
+                                             const TX *__restrict__ x, int32_t row, int32_t cmax, int32_t j, int32_t w,
+                                             Acc &acc) {
+  for (; j + 8 <= w; j += 8) dia_slots<8>(vp, off, x, row, cmax, j, acc);
+  switch (w - j) {
+    case 7: dia_slots<7>(vp, off, x, row, cmax, j, acc); break;
+    case 6: dia_slots<6>(vp, off, x, row, cmax, j, acc); break;
+    case 5: dia_slots<5>(vp, off, x, row, cmax, j, acc); break;
+    case 4: dia_slots<4>(vp, off, x, row, cmax, j, acc); break;
+    case 3: dia_slots<3>(vp, off, x, row, cmax, j, acc); break;
+    case 2: dia_slots<2>(vp, off, x, row, cmax, j, acc); break;
+    case 1: dia_slots<1>(vp, off, x, row, cmax, j, acc); break;
+    default: break;
+  }
+}
+
+// Row `row` of a slice-diagonal matrix (device.hpp) times x, one lane per row and a wavefront per slice: the
+// slice's pointers and slot offsets are wave-uniform and come through the scalar unit.
+template <class Acc, class TM, class TX>
+__device__ __forceinline__ Acc dia_dot(const MatView<TM> &A, const TX *__restrict__ x, int32_t row) {
+  const int32_t s = __builtin_amdgcn_readfirstlane(row >> 6), lane = row & 63;
+  const int32_t p0 = A.ptr[s], p1 = A.ptr[s + 1];
+  Acc acc = Acc(0);
+  dia_row_from(A.val + p0 + lane, A.dia + 1 + (p0 >> 6), x, row, A.dia[0], 0, (p1 - p0) >> 6, acc);
+  return acc;
+}
+
+// Rows r0 and r0 + 64 (the same lane of slices s and s + 1): the slots both slices have go together, in
+// chunks of eight and one exact rest; the longer slice's further slots (slices at the matrix's faces) follow
+// for its row alone. Slice s + 1 may not exist (then only row r0 is summed).
+template <class Acc, class TM, class TX>
+__device__ __forceinline__ void dia_dot2(const MatView<TM> &A, const TX *__restrict__ x, int32_t r0, Acc &a0,
+                                         Acc &a1) {
+  const int32_t s0 = __builtin_amdgcn_readfirstlane(r0 >> 6), lane = r0 & 63;
+  const bool two = (s0 + 1) * SELL_C < A.nrows;  // uniform
+  const int32_t p0 = A.ptr[s0], p1 = A.ptr[s0 + 1];
+  const int32_t p2 = two ? A.ptr[s0 + 2] : p1;
+  const int32_t w0 = (p1 - p0) >> 6, w1 = (p2 - p1) >> 6;
+  const TM *__restrict__ vp0 = A.val + p0 + lane;
+  const TM *__restrict__ vp1 = A.val + p1 + lane;
+  const int32_t *__restrict__ off0 = A.dia + 1 + (p0 >> 6);
+  const int32_t *__restrict__ off1 = A.dia + 1 + (p1 >> 6);
+  const int32_t cmax = A.dia[0];
+  const int32_t r1 = r0 + SELL_C;
+  a0 = Acc(0);
+  a1 = Acc(0);
+  const int32_t wm = min(w0, w1);
+  int32_t j = 0;
+  for (; j + 8 <= wm; j += 8) dia_slots2<8>(vp0, off0, vp1, off1, x, r0, r1, cmax, j, a0, a1);
+  switch (wm - j) {
+    case 7: dia_slots2<7>(vp0, off0, vp1, off1, x, r0, r1, cmax, j, a0, a1); break;
+    case 6: dia_slots2<6>(vp0, off0, vp1, off1, x, r0, r1, cmax, j, a0, a1); break;
+    case 5: dia_slots2<5>(vp0, off0, vp1, off1, x, r0, r1, cmax, j, a0, a1); break;
+    case 4: dia_slots2<4>(vp0, off0, vp1, off1, x, r0, r1, cmax, j, a0, a1); break;
+    case 3: dia_slots2<3>(vp0, off0, vp1, off1, x, r0, r1, cmax, j, a0, a1); break;
+    case 2: dia_slots2<2>(vp0, off0, vp1, off1, x, r0, r1, cmax, j, a0, a1); break;
+    case 1: dia_slots2<1>(vp0, off0, vp1, off1, x, r0, r1, cmax, j, a0, a1); break;
+    default: break;
+  }
+  if (w0 > wm) dia_row_from(vp0, off0, x, r0, cmax, wm, w0, a0);
+  if (w1 > wm) dia_row_from(vp1, off1, x, r1, cmax, wm, w1, a1);
+}
+
 template <int G, class Acc, int U = 4, class TM, class TX>
 __device__ __forceinline__ Acc row_dot(const MatView<TM> &A, const TX *__restrict__ x, int32_t row, int sub) {
+  if constexpr (G == 1) {
+    if (A.dia) return dia_dot<Acc>(A, x, row);
+  }
   if (A.col16) return row_dot_impl<G, true, U, Acc>(A, x, row, sub);
   return row_dot_impl<G, false, U, Acc>(A, x, row, sub);
 }
@@ -168,8 +295,8 @@ __device__ __forceinline__ void sell_dot2_impl(const MatView<TM> &A, const TX *_
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (ok0[u]) a0 += (Acc)v0[u] * (Acc)x0[u];
-      if (ok1[u]) a1 += (Acc)v1[u] * (Acc)x1[u];
+      if (ok0[u]) a0 = mul_add((Acc)v0[u], (Acc)x0[u], a0);
+      if (ok1[u]) a1 = mul_add((Acc)v1[u], (Acc)x1[u], a1);
     }
     k0 += U * SELL_C;
     k1 += U * SELL_C;
@@ -214,7 +341,9 @@ template <int G, class Acc, int U = 4, class TM, class TX>
 __device__ __forceinline__ void row_dots(const MatView<TM> &A, const TX *__restrict__ x, const ThreadRows<G, TM> &t,
                                          Acc (&out)[ThreadRows<G, TM>::R]) {
   if constexpr (ThreadRows<G, TM>::R == 2) {
-    if (A.col16)
+    if (A.dia)
+      dia_dot2<Acc>(A, x, t.row[0], out[0], out[1]);
+    else if (A.col16)
       sell_dot2_impl<true, U, Acc>(A, x, t.row[0], t.ok[1], out[0], out[1]);
     else
       sell_dot2_impl<false, U, Acc>(A, x, t.row[0], t.ok[1], out[0], out[1]);
@@ -379,7 +508,7 @@ __device__ __forceinline__ void prolong_unit_rows(const MatView<T> &P, const T *
     for (int q = 0; q < R; ++q) {
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (ok[q][u]) acc[q] += v[q][u] * ev[q][u];
+        if (ok[q][u]) acc[q] = mul_add(v[q][u], ev[q][u], acc[q]);
       virt[q] = false;
       k[q] += U * m[q];
     }
@@ -446,21 +575,23 @@ __device__ __forceinline__ void axpy_body(uint32_t lb, const T *__restrict__ f, 
 // kernel-argument load. The bodies get the MatView rebuilt in registers.
 #define NAMG_MAT_HEAD(T) \
   const int32_t *__restrict__ m_ptr, const void *__restrict__ m_idx, const T *__restrict__ m_val, int32_t m_nrows, \
-      int32_t m_narrow
+      int32_t m_form
 
+// form: 0 = 32-bit columns, 1 = 16-bit offsets, 2 = slice-diagonal (idx = the slot offsets)
 template <class T>
 __device__ __forceinline__ MatView<T> make_view(const int32_t *ptr, const void *idx, const T *val, int32_t nrows,
-                                                int32_t narrow, int64_t mul) {
+                                                int32_t form, int64_t mul) {
   MatView<T> v;
   v.ptr = ptr;
-  v.col = narrow ? nullptr : static_cast<const int32_t *>(idx);
-  v.col16 = narrow ? static_cast<const int16_t *>(idx) : nullptr;
+  v.col = form == 0 ? static_cast<const int32_t *>(idx) : nullptr;
+  v.col16 = form == 1 ? static_cast<const int16_t *>(idx) : nullptr;
+  v.dia = form == 2 ? static_cast<const int32_t *>(idx) : nullptr;
   v.val = val;
   v.mul = mul;
   v.nrows = nrows;
   return v;
 }
-#define NAMG_MAT_VIEW(T) make_view<T>(m_ptr, m_idx, m_val, m_nrows, m_narrow, m_mul)
+#define NAMG_MAT_VIEW(T) make_view<T>(m_ptr, m_idx, m_val, m_nrows, m_form, m_mul)
 
 template <int G, class Acc, class TM, class TX, class TY, int U = 4>
 __global__ __launch_bounds__(BLK) void k_spmv(NAMG_MAT_HEAD(TM), const TX *__restrict__ x, const TY *__restrict__ d,

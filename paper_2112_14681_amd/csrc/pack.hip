@@ -32,6 +32,78 @@ __global__ __launch_bounds__(PB) void k_slice_width(int32_t nrows, const int32_t
   w[s] = m * SELL_C;
 }
 
+// The slice-diagonal form of a square matrix (see LayoutCount), one wavefront per slice s, lane l on row
+// 64 s + l: each round takes the smallest pending column offset (column - row) over the wavefront, which is
+// the slice's next slot, and the lanes whose row has that offset advance past it.
+// uw[s] = the slice's number of distinct offsets, counted up to dia_cap(its longest row) + 1;
+// *unsorted = 1 when some row's columns do not strictly increase (integer atomic only).
+__global__ __launch_bounds__(PB) void k_dia_width(int32_t nrows, const int32_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ ci, int32_t *__restrict__ uw,
+                                                  int32_t *unsorted) {
+  const int64_t t = (int64_t)blockIdx.x * PB + threadIdx.x;
+  const int32_t s = (int32_t)(t >> 6), lane = (int32_t)(t & 63);
+  if (s >= (nrows + SELL_C - 1) / SELL_C) return;  // whole wavefronts
+  const int32_t r = s * SELL_C + lane;
+  int32_t k = 0, end = 0;
+  if (r < nrows) {
+    k = rp[r];
+    end = rp[r + 1];
+  }
+  for (int32_t q = k + 1; q < end; ++q)
+    if (ci[q] <= ci[q - 1]) {
+      atomicOr(unsorted, 1);
+      break;
+    }
+  int32_t len = end - k;
+  for (int off = 32; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
+  const int64_t cap = dia_cap(len);
+  int32_t cnt = 0;
+  while (true) {
+    const int32_t cur = k < end ? ci[k] - r : INT32_MAX;
+    int32_t m = cur;
+    for (int off = 32; off > 0; off >>= 1) m = min(m, __shfl_xor(m, off, 64));
+    if (m == INT32_MAX || cnt > cap) break;
+    ++cnt;
+    if (cur == m) ++k;
+  }
+  if (lane == 0) uw[s] = cnt;
+}
+
+// Packs the slice-diagonal form with the rounds of k_dia_width (run only when every slice was counted in
+// full and every row is sorted, so slice s fills exactly its slots [sptr[s], sptr[s + 1]) / 64 ...):
+// slot j of slice s takes offset doff[1 + sptr[s] / 64 + j] and, lane by lane, the row's entry at that offset
+// or 0; doff[0] = ncols - 1.
+template <class T>
+__global__ __launch_bounds__(PB) void k_pack_dia(int32_t nrows, int32_t ncols, const int32_t *__restrict__ rp,
+                                                 const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                                 const int32_t *__restrict__ sptr, int32_t *__restrict__ doff,
+                                                 T *__restrict__ val) {
+  const int64_t t = (int64_t)blockIdx.x * PB + threadIdx.x;
+  const int32_t s = (int32_t)(t >> 6), lane = (int32_t)(t & 63);
+  if (s >= (nrows + SELL_C - 1) / SELL_C) return;
+  const int32_t r = s * SELL_C + lane;
+  int32_t k = 0, end = 0;
+  if (r < nrows) {
+    k = rp[r];
+    end = rp[r + 1];
+  }
+  const int32_t p0 = sptr[s], p1 = sptr[s + 1];
+  int32_t j = 0;
+  while (true) {
+    const int32_t cur = k < end ? ci[k] - r : INT32_MAX;
+    int32_t m = cur;
+    for (int off = 32; off > 0; off >>= 1) m = min(m, __shfl_xor(m, off, 64));
+    const int64_t d = (int64_t)p0 + (int64_t)j * SELL_C + lane;
+    if (m == INT32_MAX || d >= p1) break;  // the second test never fires for a slice counted in full
+    const bool has = cur == m;
+    val[d] = has ? (T)v[k] : T(0);
+    if (lane == 0) doff[1 + p0 / SELL_C + j] = m;
+    if (has) ++k;
+    ++j;
+  }
+  if (s == 0 && lane == 0) doff[0] = ncols - 1;
+}
+
 // *bad = 1 when a column lies outside [-32768, 32767] of its row's base (integer atomic only)
 __global__ __launch_bounds__(PB) void k_fits16(int32_t nrows, const int32_t *__restrict__ rp,
                                                const int32_t *__restrict__ ci, int64_t mul, int32_t *bad) {
@@ -219,8 +291,9 @@ void pack_unit_device(DMat<T> &M, const DCsr &D, const UnitRows &u, MemCounter *
 }
 
 template <class T>
-void pack_device(DMat<T> &M, const DCsr &D, MemCounter *mc, int force_group, const UnitRows *unit) {
+void pack_device(DMat<T> &M, const DCsr &D, MemCounter *mc, int force_group, const UnitRows *unit, bool allow_dia) {
   M.unit = false;
+  M.dia = false;
   M.nrows = D.nr;
   M.ncols = D.nc;
   M.nnz = D.nnz;
@@ -263,6 +336,43 @@ void pack_device(DMat<T> &M, const DCsr &D, MemCounter *mc, int force_group, con
       hip_check(hipMemcpy(w.data(), dw.get(), (size_t)nslices * 4, hipMemcpyDeviceToHost), "hipMemcpy D2H");
     }
     w.resize(nslices);
+    if (allow_dia && nslices > 0 && M.nrows == M.ncols && layout_tuning().dia) {
+      // the slice-diagonal choice, by the rule LayoutCount applies on the host
+      std::vector<int32_t> uw(nslices, 0);
+      int32_t unsorted = 0;
+      {
+        DevBuf<int32_t> duw((size_t)nslices, &setup_mem()), dflag(1, &setup_mem());
+        hip_check(hipMemset(dflag.get(), 0, 4), "hipMemset");
+        hipLaunchKernelGGL(k_dia_width, dim3(pgrid((int64_t)nslices * SELL_C)), dim3(PB), 0, 0, M.nrows, D.rp.get(),
+                           D.ci.get(), duw.get(), dflag.get());
+        check("k_dia_width");
+        hip_check(hipMemcpy(uw.data(), duw.get(), (size_t)nslices * 4, hipMemcpyDeviceToHost), "hipMemcpy D2H");
+        hip_check(hipMemcpy(&unsorted, dflag.get(), 4, hipMemcpyDeviceToHost), "hipMemcpy D2H");
+      }
+      bool ok = unsorted == 0;
+      int64_t sell_stored = 0, dia_stored = 0;
+      for (int32_t q = 0; q < nslices; ++q) {
+        ok = ok && uw[q] <= dia_cap(w[q] / SELL_C);
+        sell_stored += w[q];
+        dia_stored += (int64_t)uw[q] * SELL_C;
+      }
+      if (ok && dia_wins(sell_stored, dia_stored, M.narrow, sizeof(T))) {
+        for (int32_t &q : uw) q *= SELL_C;
+        const std::vector<int32_t> sptr = host_offsets(uw);
+        M.dia = true;
+        M.stored = sptr[nslices];
+        M.unroll = 4;  // not used by the slice-diagonal kernels
+        M.ptr.alloc(sptr.size(), mc);
+        M.ptr.upload(sptr.data(), sptr.size());
+        M.doff.alloc((size_t)(M.stored / SELL_C + 1), mc);
+        M.val.alloc((size_t)M.stored, mc);
+        hipLaunchKernelGGL(k_pack_dia<T>, dim3(pgrid((int64_t)nslices * SELL_C)), dim3(PB), 0, 0, M.nrows, M.ncols,
+                           D.rp.get(), D.ci.get(), D.v.get(), M.ptr.get(), M.doff.get(), M.val.get());
+        check("k_pack_dia");
+        hip_check(hipStreamSynchronize(nullptr), "hipStreamSynchronize");
+        return;
+      }
+    }
     const std::vector<int32_t> sptr = host_offsets(w);
     M.stored = sptr[nslices];
     M.ptr.alloc(sptr.size(), mc);
@@ -324,8 +434,8 @@ void smoother_data_device(const DCsr &A, DCsr &lo, DCsr &up, DevBuf<T> &dinv, De
   hip_check(hipStreamSynchronize(nullptr), "hipStreamSynchronize");
 }
 
-template void pack_device<float>(DMat<float> &, const DCsr &, MemCounter *, int, const UnitRows *);
-template void pack_device<double>(DMat<double> &, const DCsr &, MemCounter *, int, const UnitRows *);
+template void pack_device<float>(DMat<float> &, const DCsr &, MemCounter *, int, const UnitRows *, bool);
+template void pack_device<double>(DMat<double> &, const DCsr &, MemCounter *, int, const UnitRows *, bool);
 template void smoother_data_device<float>(const DCsr &, DCsr &, DCsr &, DevBuf<float> &, DevBuf<float> &,
                                           MemCounter *);
 template void smoother_data_device<double>(const DCsr &, DCsr &, DCsr &, DevBuf<double> &, DevBuf<double> &,

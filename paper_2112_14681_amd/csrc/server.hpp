@@ -20,44 +20,16 @@
 
 namespace namg {
 
-// Sizes of one DMat layout, counted row by row in increasing row order: the entries, the SELL-64 storage
-// (each slice as wide as its longest row) and whether every column fits the 16-bit offset form.
-struct LayoutCount {
-  int64_t nnz = 0, sell_stored = 0;
-  int32_t slice_w = 0;
-  bool narrow = true;
-  void row(int32_t r, int32_t len) {
-    nnz += len;
-    slice_w = std::max(slice_w, len);
-    if ((r + 1) % SELL_C == 0) {
-      sell_stored += (int64_t)slice_w * SELL_C;
-      slice_w = 0;
-    }
-  }
-  void col(int64_t offset) {
-    if (offset < -32768 || offset > 32767) narrow = false;
-  }
-  // device bytes of the DMat<T> of nr rows: DMat::build's layout choice, and the size class each of its
-  // three buffers (pointers, column indices, values) allocates
-  template <class T>
-  int64_t bytes(int32_t nr, int force_group = 0) const {
-    const int group = force_group > 0 ? force_group : choose_group(nr, nnz);
-    const int64_t ib = narrow ? 2 : 4;
-    if (group > 1) return alloc_bytes((int64_t)nr + 1, 4) + alloc_bytes(nnz, ib) + alloc_bytes(nnz, sizeof(T));
-    const int64_t nslices = ((int64_t)nr + SELL_C - 1) / SELL_C;
-    const int64_t stored = sell_stored + (int64_t)slice_w * SELL_C;  // the last, partial slice
-    return alloc_bytes(nslices + 1, 4) + alloc_bytes(stored, ib) + alloc_bytes(stored, sizeof(T));
-  }
-};
-
 // One pass over a level matrix: its own layout and those of its strict lower and upper parts (the scaled
 // triangles of polynomial GS, which have A's rows and columns and so A's column offsets).
 struct MatrixShape {
   LayoutCount all, lo, up;
 };
 
-inline MatrixShape matrix_shape(const HostCsr &A) {
+inline MatrixShape matrix_shape(const HostCsr &A, bool allow_dia = true) {
   MatrixShape m;
+  m.all.square = m.lo.square = m.up.square = A.nr == A.nc;
+  m.all.dia_ok = m.lo.dia_ok = m.up.dia_ok = allow_dia;
   const int64_t mul = diag_mul(A.nr, A.nc);
   for (int32_t r = 0; r < A.nr; ++r) {
     const int32_t base = diag_base(r, mul);
@@ -83,14 +55,17 @@ inline MatrixShape matrix_shape(const HostCsr &A) {
 
 // Device bytes one DMat<T>::build of A allocates.
 template <class T>
-int64_t mat_alloc_bytes(const HostCsr &A, int force_group = 0) {
-  return matrix_shape(A).all.bytes<T>(A.nr, force_group);
+int64_t mat_alloc_bytes(const HostCsr &A, int force_group = 0, bool allow_dia = true) {
+  return layout_count(A, allow_dia).bytes<T>(A.nr, force_group);
 }
 
 // One pass over P for the layouts of P and of R = P^T (R's rows are P's columns; entry (c, i) of R takes its
 // column offset from R's own diagonal base).
 inline std::pair<LayoutCount, LayoutCount> transfer_shape(const HostCsr &P) {
   LayoutCount lp, lr;
+  // rectangular: neither takes the slice-diagonal form (and lr's columns arrive out of row order)
+  lp.square = lr.square = false;
+  lp.dia_ok = lr.dia_ok = false;
   const int64_t mul_p = diag_mul(P.nr, P.nc), mul_r = diag_mul(P.nc, P.nr);
   std::vector<int32_t> rlen(P.nc, 0);
   for (int32_t i = 0; i < P.nr; ++i) {
@@ -122,10 +97,10 @@ int64_t prolong_alloc_bytes(const HostCsr &P, const std::vector<int8_t> &cf, con
   return lp.bytes<T>(P.nr);
 }
 
-// Device bytes of Solver<T>(H) with its Krylov workspace for restart m (the direct comparators' level
-// schedules, which serving never builds, excluded).
+// Device bytes of Solver<T>(H, device, allow_dia) with its Krylov workspace for restart m (the direct
+// comparators' level schedules, which serving never builds, excluded).
 template <class T>
-int64_t solver_footprint(const HostHierarchy &H, int m) {
+int64_t solver_footprint(const HostHierarchy &H, int m, bool allow_dia = true) {
   const int64_t S = sizeof(T);
   const int nl = (int)H.lv.size();
   int64_t total = 0;
@@ -135,21 +110,29 @@ int64_t solver_footprint(const HostHierarchy &H, int m) {
     total += 2 * alloc_bytes(n, S);  // b, x
     if (l == nl - 1) break;
     // A, its strict parts and (level 0) its FP64 copy from one pass; P and R from one pass over P
-    const MatrixShape ms = matrix_shape(h.A);
+    const MatrixShape ms = matrix_shape(h.A, allow_dia);
     const auto pr = transfer_shape(h.P);
     if (l == 0) total += ms.all.bytes<double>(h.A.nr, 1);
     // A, P, then D^-1, D_l1^-1, r, f, g1, g2
     total += ms.all.bytes<T>(h.A.nr) + prolong_alloc_bytes<T>(h.P, h.cf, pr.first) + 6 * alloc_bytes(n, S);
-    total += h.host_restriction ? mat_alloc_bytes<T>(h.R) : pr.second.bytes<T>(h.P.nc);
-    total += h.host_smoother ? mat_alloc_bytes<T>(h.pgs_lo) + mat_alloc_bytes<T>(h.pgs_up)
+    total += h.host_restriction ? mat_alloc_bytes<T>(h.R, 0, allow_dia) : pr.second.bytes<T>(h.P.nc);
+    total += h.host_smoother ? mat_alloc_bytes<T>(h.pgs_lo, 0, allow_dia) + mat_alloc_bytes<T>(h.pgs_up, 0, allow_dia)
                              : ms.lo.bytes<T>(h.A.nr) + ms.up.bytes<T>(h.A.nr);
-    if (h.has_ilu) total += mat_alloc_bytes<T>(h.ilu_lo) + mat_alloc_bytes<T>(h.ilu_up) + alloc_bytes(n, S);
+    if (h.has_ilu)
+      total += mat_alloc_bytes<T>(h.ilu_lo, 0, allow_dia) + mat_alloc_bytes<T>(h.ilu_up, 0, allow_dia) + alloc_bytes(n, S);
   }
   const int64_t nc = H.lv.back().A.nr;
-  // dense inverse: CSR with 64 lanes per row (one SELL slice when nc == 1); columns always fit 16 bits
-  total += nc > 1 ? alloc_bytes(nc + 1, 4) + alloc_bytes(nc * nc, 2) + alloc_bytes(nc * nc, S)
-                  : alloc_bytes(2, 4) + alloc_bytes(SELL_C, 2) + alloc_bytes(SELL_C, S);
-  if (nl == 1) total += mat_alloc_bytes<double>(H.lv[0].A, 1);
+  // dense inverse: CSR with 64 lanes per row, columns always fit 16 bits; one row: group 1, counted as such
+  if (nc > 1) {
+    total += alloc_bytes(nc + 1, 4) + alloc_bytes(nc * nc, 2) + alloc_bytes(nc * nc, S);
+  } else {
+    LayoutCount one;
+    one.dia_ok = allow_dia;
+    one.col(0);
+    one.row(0, 1);
+    total += one.bytes<T>(1, 1);
+  }
+  if (nl == 1) total += mat_alloc_bytes<double>(H.lv[0].A, 1, allow_dia);
   const int64_t n0 = H.lv[0].A.nr;
   const int64_t nred = blocks_for(n0);
   total += alloc_bytes(std::max<int64_t>(nred, 1) + 8, 8) + alloc_bytes(1, sizeof(KState));
@@ -763,7 +746,7 @@ class Server final : public ServerBase {
         if (r->sp.coarsen == NAMG_COARSEN_PMIS) r->sp.device = p_.device;  // device setup on the server's GPU
         r->H = std::make_unique<HostHierarchy>(build_hierarchy(std::move(r->A), r->sp));
         // the solver, and the request's b and x
-        r->footprint = solver_footprint<T>(*r->H, r->p.restart) + 2 * alloc_bytes(r->H->lv[0].A.nr, 8);
+        r->footprint = solver_footprint<T>(*r->H, r->p.restart, false) + 2 * alloc_bytes(r->H->lv[0].A.nr, 8);
         r->A = HostCsr{};
       } catch (const SetupError &e) {
         std::lock_guard<std::mutex> lk(mu_);
@@ -808,7 +791,7 @@ class Server final : public ServerBase {
       }
       try {
         const int32_t n = r->H->lv[0].A.nr;
-        r->sv = std::make_unique<Solver<T>>(*r->H, p_.device);
+        r->sv = std::make_unique<Solver<T>>(*r->H, p_.device, false);  // SELL-64 only: see Solver
         r->H->device_levels.reset();  // packed into the solver's layouts; the blocks go back to the cache
         r->sv->reserve_workspace(r->p.restart);
         if (r->sv->device_bytes() + 2 * alloc_bytes(n, 8) != r->footprint) {

@@ -119,9 +119,14 @@ auto sel_prolong(int g) { NAMG_GROUP_SWITCH(k_prolong, T) }
 // The leading kernel arguments of a sparse operator (see NAMG_MAT_HEAD in kernels.hpp).
 template <class T>
 const void *mat_idx(const MatView<T> &M) {
+  if (M.dia) return static_cast<const void *>(M.dia);
   return M.col16 ? static_cast<const void *>(M.col16) : static_cast<const void *>(M.col);
 }
-#define NAMG_HEAD_ARGS(M) (M).ptr, mat_idx(M), (M).val, (M).nrows, (int32_t)((M).col16 != nullptr)
+template <class T>
+int32_t mat_form(const MatView<T> &M) {
+  return M.dia ? 2 : M.col16 ? 1 : 0;
+}
+#define NAMG_HEAD_ARGS(M) (M).ptr, mat_idx(M), (M).val, (M).nrows, mat_form(M)
 
 template <class T>
 unsigned rows_grid(const DMat<T> &M) {
@@ -162,8 +167,11 @@ class Solver final : public SolverBase {
   friend class BatchEngine<T>;
 
  public:
-  Solver(const HostHierarchy &H, int device) : dev_(device), host_(&H) {
+  // allow_dia false: no operator takes the slice-diagonal form (the served requests: their setup, not their
+  // solve, bounds the stream, and the form's device analysis would lengthen every setup)
+  Solver(const HostHierarchy &H, int device, bool allow_dia = true) : dev_(device), host_(&H) {
     DeviceGuard g(dev_);
+    const bool ad = allow_dia;
     const int nl = (int)H.lv.size();
     lv_.resize(nl);
     // levels built on the device are packed there (same bytes as the host packing below)
@@ -178,40 +186,40 @@ class Solver final : public SolverBase {
       d.x.alloc(d.n, &mc_);
       if (l == nl - 1) break;
       if (dl) {
-        pack_device(d.A, dl->A[l], &mc_);
+        pack_device(d.A, dl->A[l], &mc_, 0, nullptr, ad);
         const UnitRows pu = unit_rows_of(h.P, h.cf);
         pack_device(d.P, dl->P[l], &mc_, 0, &pu);
         pack_device(d.R, dl->R[l], &mc_);
         DCsr lo, up;
         smoother_data_device(dl->A[l], lo, up, d.dinv, d.dl1inv, &mc_);
-        pack_device(d.pgs_lo, lo, &mc_);
-        pack_device(d.pgs_up, up, &mc_);
+        pack_device(d.pgs_lo, lo, &mc_, 0, nullptr, ad);
+        pack_device(d.pgs_up, up, &mc_, 0, nullptr, ad);
       } else {
-        d.A.build(h.A, &mc_);
+        d.A.build(h.A, &mc_, 0, nullptr, ad);
         d.P.build(h.P, &mc_, 0, &h.cf);
         if (h.host_restriction)
           d.R.build(h.R, &mc_);
         else
           d.R.build(restriction_of(h.P), &mc_);
         if (h.host_smoother) {
-          d.pgs_lo.build(h.pgs_lo, &mc_);
-          d.pgs_up.build(h.pgs_up, &mc_);
+          d.pgs_lo.build(h.pgs_lo, &mc_, 0, nullptr, ad);
+          d.pgs_up.build(h.pgs_up, &mc_, 0, nullptr, ad);
           upload_vec(d.dinv, h.dinv);
           upload_vec(d.dl1inv, h.dl1inv);
         } else {
           std::vector<double> dinv, dl1inv;
           HostCsr lo, up;
           pgs_data(h.A, dinv, dl1inv, lo, up);
-          d.pgs_lo.build(lo, &mc_);
-          d.pgs_up.build(up, &mc_);
+          d.pgs_lo.build(lo, &mc_, 0, nullptr, ad);
+          d.pgs_up.build(up, &mc_, 0, nullptr, ad);
           upload_vec(d.dinv, dinv);
           upload_vec(d.dl1inv, dl1inv);
         }
       }
       d.has_ilu = h.has_ilu;
       if (h.has_ilu) {
-        d.ilu_lo.build(h.ilu_lo, &mc_);
-        d.ilu_up.build(h.ilu_up, &mc_);
+        d.ilu_lo.build(h.ilu_lo, &mc_, 0, nullptr, ad);
+        d.ilu_up.build(h.ilu_up, &mc_, 0, nullptr, ad);
         upload_vec(d.ilu_dinv, h.ilu_dinv);
       }
       d.r.alloc(d.n, &mc_);
@@ -229,11 +237,11 @@ class Solver final : public SolverBase {
     for (int32_t i = 0; i < nc_; ++i)
       for (int32_t j = 0; j < nc_; ++j) inv.ci[(size_t)i * nc_ + j] = j;
     inv.v = H.coarse_inv;
-    coarse_inv_.build(inv, &mc_, nc_ > 1 ? 64 : 1);
+    coarse_inv_.build(inv, &mc_, nc_ > 1 ? 64 : 1, nullptr, ad);
     if (dl)
-      pack_device(A64_, dl->A[0], &mc_, 1);
+      pack_device(A64_, dl->A[0], &mc_, 1, nullptr, ad);
     else
-      A64_.build(H.lv[0].A, &mc_, 1);
+      A64_.build(H.lv[0].A, &mc_, 1, nullptr, ad);
     anorm_inf_ = H.anorm_inf;
     const int32_t n = lv_[0].n;
     nblk_red_ = (int32_t)blocks_for(n);
@@ -316,7 +324,7 @@ class Solver final : public SolverBase {
     if (op == NAMG_OP_SPMV64) {
       if (level != 0) throw SetupError{NAMG_E_INVALID, "SPMV64 is defined on level 0 only"};
       const MatView<double> M = A64_.view();
-      launch(NAMG_KF_GMRES_SPMV, 0, A64_.bytes() + 16.0 * A64_.nrows, sel_spmv<double, double, double, double>(1),
+      launch(NAMG_KF_GMRES_SPMV, 0, A64_.bytes() + 16.0 * A64_.nrows, sel_spmv<double, double, double, double>(1, A64_.unroll),
              rows_grid(A64_), s, NAMG_HEAD_ARGS(M), in1, (const double *)nullptr, out, (double *)nullptr, M.mul);
       return;
     }
@@ -515,7 +523,7 @@ class Solver final : public SolverBase {
           vcycle(0, b0, zi, o, s);
           st.precond_apps++;
           if (timing) marks.push_back(phase_mark(s));
-          launch(NAMG_KF_GMRES_SPMV, 0, A64_.bytes() + (S + 8.0) * n, sel_spmv<double, double, T, double>(1),
+          launch(NAMG_KF_GMRES_SPMV, 0, A64_.bytes() + (S + 8.0) * n, sel_spmv<double, double, T, double>(1, A64_.unroll),
                  rows_grid(A64_), s, NAMG_HEAD_ARGS(M64), (const T *)zi, (const double *)nullptr, w, (double *)nullptr,
                  M64.mul);
           if (timing) marks.push_back(phase_mark(s));

@@ -12,7 +12,10 @@ on the matrices of real hierarchies that
   * the sums over the real entries equal the oracle's product: bit for bit with one lane per row (entry
     order), to rounding with lane groups (lane j sums entries j, j + G, ..., then a fixed butterfly);
   * the prolongations' unit-row layout (a C point's row stores no entry) loads and gathers in range and
-    gives the plain layout's bits.
+    gives the plain layout's bits;
+  * the slice-diagonal layout (one column offset per slot of 64 rows, no per-entry columns) is chosen where
+    the library's rule takes it, reads its offsets, values and gathers in range with one and with two rows
+    per lane (chunks of eight slots and one exact rest), and gives the plain layout's bits.
 
 A model of the two-rows-per-lane kernel with the base column of a lane's second row taken even when the
 lane has no second row (an earlier form of that kernel) must show an out-of-range gather on the ragged
@@ -135,6 +138,166 @@ class UnitLayout:
         dst = self.ptr[rows // SELL_C] + k_in_row * self.count[rows // SELL_C] + rank[rows]
         self.idx[dst[er]] = (off if self.narrow else ci)[er]
         self.val[dst[er]] = vals[er]
+
+
+def dia_cap(longest_row):
+    return 2 * longest_row + 8
+
+
+class DiaLayout:
+    """The slice-diagonal layout of a square matrix, as the library packs it, and the library's rule for taking
+    it (`use(val_bytes)`): rows with strictly increasing columns, no slice whose union of offsets (column -
+    row) exceeds dia_cap(its longest row), and fewer bytes than SELL-64 (slots x 64 x value bytes + 4 per slot
+    against SELL-64's stored entries x (value + column bytes)). Slice s keeps its union in increasing order:
+    slot k's entries at ptr[s] + 64 k, its offset at off[1 + ptr[s] / 64 + k]; off[0] is ncols - 1."""
+
+    def __init__(self, rp, ci, vals, ncols):
+        rp = np.asarray(rp, np.int64)
+        ci = np.asarray(ci, np.int64)
+        self.nrows = n = len(rp) - 1
+        self.ncols = ncols
+        self.square = n == ncols
+        lens = np.diff(rp)
+        rows = np.repeat(np.arange(n), lens)
+        off = ci - rows
+        nsl = (n + SELL_C - 1) // SELL_C
+        same_row = rows[1:] == rows[:-1]
+        self.sorted = bool(np.all(ci[1:][same_row] > ci[:-1][same_row]))
+        sl = rows >> 6
+        key = np.unique(sl * (1 << 33) + (off + (1 << 32)))
+        ksl = key >> 33
+        koff = (key & ((1 << 33) - 1)) - (1 << 32)
+        width = np.bincount(ksl, minlength=nsl)
+        lpad = np.zeros(nsl * SELL_C, np.int64)
+        lpad[:n] = lens
+        self.longest = lpad.reshape(nsl, SELL_C).max(axis=1) if nsl else np.zeros(0, np.int64)
+        self.width = width
+        self.ptr = np.zeros(nsl + 1, np.int64)
+        np.cumsum(width * SELL_C, out=self.ptr[1:])
+        self.stored = int(self.ptr[-1])
+        self.sell_stored = int((self.longest * SELL_C).sum())
+        # offsets: slice by slice in increasing order (np.unique sorted the keys that way)
+        self.off = np.concatenate([[ncols - 1], koff]).astype(np.int64)
+        self.val = np.zeros(max(self.stored, 1))
+        # the slot of each entry: its rank among its slice's offsets
+        first = np.searchsorted(ksl, np.arange(nsl))
+        slot = np.searchsorted(key, sl * (1 << 33) + (off + (1 << 32))) - first[sl]
+        self.val[self.ptr[sl] + slot * SELL_C + (rows & 63)] = vals
+        self.narrow = bool(off.size == 0 or (off.min() >= -32768 and off.max() <= 32767))
+
+    def use(self, val_bytes, group=1):
+        if not (group == 1 and self.square and self.sorted and self.nrows > 0):
+            return False
+        if np.any(self.width > dia_cap(self.longest)):
+            return False
+        sell = self.sell_stored * (val_bytes + (2 if self.narrow else 4))
+        dia = self.stored * val_bytes + 4 * (self.stored // SELL_C + 1)
+        return dia < sell
+
+
+class DiaAccess:
+    """Range checks of the slice-diagonal kernels' reads: offsets, values, gathers."""
+
+    def __init__(self, L):
+        self.L = L
+        self.bad = {"offsets": 0, "values": 0, "gathers": 0}
+
+    def offset(self, i):
+        self.bad["offsets"] += int(np.count_nonzero((i < 0) | (i >= len(self.L.off))))
+        return self.L.off[np.clip(i, 0, len(self.L.off) - 1)]
+
+    def value(self, k):
+        n = max(self.L.stored, 1)
+        self.bad["values"] += int(np.count_nonzero((k < 0) | (k >= n)))
+        return self.L.val[np.clip(k, 0, n - 1)]
+
+    def gather(self, x, c):
+        self.bad["gathers"] += int(np.count_nonzero((c < 0) | (c >= self.L.ncols)))
+        return x[np.clip(c, 0, self.L.ncols - 1)]
+
+    def clean(self):
+        return all(v == 0 for v in self.bad.values())
+
+
+def _dia_exact_chunks(w):
+    """The chunks dia_row_from walks for a row of w slots: eights, then one chunk of exactly the rest."""
+    j, out = 0, []
+    while j + 8 <= w:
+        out.append((j, 8))
+        j += 8
+    if w - j > 0:
+        out.append((j, w - j))
+    return out
+
+
+def replay_dia_exact(L, x):
+    """dia_dot in its exact-chunk form (one row per lane, a wavefront per slice): every chunk's slots exist, so
+    offsets and values are read inside the slice; every product is added, padding (value 0) included."""
+    a = DiaAccess(L)
+    cmax = int(a.offset(np.array([0]))[0])
+    acc = np.zeros(L.nrows)
+    for s in range(len(L.ptr) - 1):
+        rows = np.arange(s * SELL_C, min(L.nrows, (s + 1) * SELL_C), dtype=np.int64)
+        lane = rows & 63
+        p0, p1 = int(L.ptr[s]), int(L.ptr[s + 1])
+        w = (p1 - p0) >> 6
+        part = np.zeros(rows.size)
+        for j, k in _dia_exact_chunks(w):
+            for u in range(k):
+                o = int(a.offset(np.array([1 + (p0 >> 6) + j + u]))[0])
+                v = a.value(p0 + (j + u) * SELL_C + lane)
+                part = part + v * a.gather(x, np.clip(rows + o, 0, cmax))
+        acc[rows] = part
+    return acc, a
+
+
+def replay_dia_exact_two_rows(L, x):
+    """dia_dot2 in its exact-chunk form: the slots both slices have go together (rows r0 of slice s and r0 + 64
+    of slice s + 1, all 64 lanes of each, past-the-end rows included), then the longer slice's rest alone."""
+    a = DiaAccess(L)
+    cmax = int(a.offset(np.array([0]))[0])
+    out = np.zeros(L.nrows)
+    nsl = len(L.ptr) - 1
+    lane = np.arange(SELL_C, dtype=np.int64)
+    for s0 in range(0, nsl, 2):
+        two = (s0 + 1) * SELL_C < L.nrows
+        p0, p1 = int(L.ptr[s0]), int(L.ptr[s0 + 1])
+        p2 = int(L.ptr[s0 + 2]) if two else p1
+        w0, w1 = (p1 - p0) >> 6, (p2 - p1) >> 6
+        r0 = s0 * SELL_C + lane
+        r1 = r0 + SELL_C
+        a0, a1 = np.zeros(SELL_C), np.zeros(SELL_C)
+
+        def slots(p, r, part, j0, w):
+            for j, k in _dia_exact_chunks(w - j0):
+                for u in range(k):
+                    q = j0 + j + u
+                    o = int(a.offset(np.array([1 + (p >> 6) + q]))[0])
+                    v = a.value(p + q * SELL_C + lane)
+                    part = part + v * a.gather(x, np.clip(r + o, 0, cmax))
+            return part
+
+        wm = min(w0, w1)
+        for j, k in _dia_exact_chunks(wm):  # joint part: the two rows' products interleave, each in slot order
+            for u in range(k):
+                q = j + u
+                for p, r, which in ((p0, r0, 0), (p1, r1, 1)):
+                    o = int(a.offset(np.array([1 + (p >> 6) + q]))[0])
+                    v = a.value(p + q * SELL_C + lane)
+                    prod = v * a.gather(x, np.clip(r + o, 0, cmax))
+                    if which == 0:
+                        a0 = a0 + prod
+                    else:
+                        a1 = a1 + prod
+        if w0 > wm:
+            a0 = slots(p0, r0, a0, wm, w0)
+        if w1 > wm:
+            a1 = slots(p1, r1, a1, wm, w1)
+        keep0 = r0 < L.nrows
+        out[r0[keep0]] = a0[keep0]
+        keep1 = r1 < L.nrows
+        out[r1[keep1]] = a1[keep1]
+    return out, a
 
 
 def replay_prolong_unit(L, e, U=U):
@@ -363,6 +526,7 @@ def _systems():
 def test_row_kernel_accesses_in_range(namg, case):
     name, A = list(_systems())[case]
     rng = np.random.default_rng(case)
+    dia_used = set()
     for label, rp, ci, v, ncols, fg, cf in hierarchy_operators(namg, A):
         L = Layout(np.asarray(rp), np.asarray(ci), np.asarray(v), ncols, fg)
         x = rng.standard_normal(ncols)
@@ -391,6 +555,24 @@ def test_row_kernel_accesses_in_range(namg, case):
             assert acc2.bad_loads == 0 and acc2.bad_gathers == 0, (name, label, "two rows per lane",
                                                                    acc2.bad_loads, acc2.bad_gathers)
             assert np.array_equal(y2, y), (name, label)
+        if ncols == len(rp) - 1:
+            D = DiaLayout(rp, ci, v, ncols)
+            for vb in (4, 8):
+                if not D.use(vb, L.group):
+                    continue
+                dia_used.add(label)
+                ye, ae = replay_dia_exact(D, x)
+                assert ae.clean(), (name, label, "slice-diagonal exact chunks, one row", ae.bad)
+                assert np.array_equal(ye, y), (name, label, "exact")  # the plain layout's bits (up to the sign of 0)
+                ye2, ae2 = replay_dia_exact_two_rows(D, x)
+                assert ae2.clean(), (name, label, "slice-diagonal exact chunks, two rows", ae2.bad)
+                assert np.array_equal(ye2, y), (name, label, "exact, two rows")
+    # the natural-order stencils take the form on level 0 (A, its strict parts, its FP64 copy); a random
+    # relabelling scatters the offsets and keeps SELL-64
+    if name.startswith("permuted"):
+        assert not any(lbl.startswith("A0") for lbl in dia_used), dia_used
+    else:
+        assert {"A0", "A0 fp64", "A0 lower", "A0 upper"} <= dia_used, dia_used
 
 
 def test_replay_detects_second_row_base_past_the_end():
