@@ -578,6 +578,19 @@ inline LayoutCount layout_count(const HostCsr &A, bool allow_dia = true) {
   return c;
 }
 
+// Flag in MatView::unroll of a unit-row prolongation whose kernel takes a pair of slices per wavefront, its
+// lanes first on the pair's F rows, then on its C points' rows (prolong_unit_pairs), instead of one lane per
+// row (prolong_unit_rows).
+constexpr int UNIT_PAIRS = 16;
+
+// The pair form pays where a slice's F rows are about half its rows (a red-black splitting: with one lane per
+// row half the lanes of the F loop idle) and the matrix fills the device; with more F rows a pair takes two
+// passes of 64 lanes, and on small levels half as many wavefronts run (measured at 128^3: level 0, 50 % F
+// rows, 30.4 -> 22.7 us; level 1, 83 % F rows, 14.0 -> 15.7 us; levels 2-4 2-3 us slower each).
+inline bool unit_pairs_for(int64_t nrows, int64_t explicit_rows) {
+  return nrows >= (int64_t(1) << 19) && 32 * explicit_rows <= 17 * nrows;
+}
+
 // Per-slice (C points before the slice, explicit rows in it) pairs of the unit-row layout.
 inline std::vector<int32_t> unit_meta(const UnitRows &u) {
   std::vector<int32_t> m(2 * std::max<size_t>(u.mask.size(), 1), 0);
@@ -595,6 +608,7 @@ struct DMat {
   int64_t explicit_nnz = 0, explicit_rows = 0;  // unit-row layout: the entries and count of the explicit rows
   bool narrow = false;
   bool unit = false;  // the unit-row SELL layout (prolongations, see UnitRows)
+  bool unit_pairs = false;  // its kernel in the pair form (unit_pairs_for)
   bool dia = false;   // the slice-diagonal SELL layout (see LayoutCount)
   int unroll = 4;     // entries per chunk of the row kernels (choose_unroll; unit-row layout: see view())
   DevBuf<int32_t> ptr, col;
@@ -616,7 +630,8 @@ struct DMat {
     v.nrows = nrows;
     v.ncols = ncols;
     v.unroll = unit ? (layout_tuning().unit_unroll ? layout_tuning().unit_unroll
-                                                   : (explicit_nnz > 4 * explicit_rows ? 8 : 4))
+                                                   : (explicit_nnz > 4 * explicit_rows ? 8 : 4)) |
+                          (unit_pairs ? UNIT_PAIRS : 0)
                     : unroll;
     return v;
   }
@@ -642,6 +657,7 @@ struct DMat {
     group = force_group > 0 ? force_group : choose_group(nrows, nnz);
     unroll = choose_unroll(group, nrows, nnz);
     unit = false;
+    unit_pairs = false;
     dia = false;
     if (unit_cf && group == 1) {
       const UnitRows u = unit_rows_of(A, *unit_cf);
@@ -774,6 +790,7 @@ struct DMat {
     explicit_nnz = 0;
     explicit_rows = 0;
     for (int32_t c : u.count) explicit_rows += c;
+    unit_pairs = unit_pairs_for(nrows, explicit_rows);
     std::vector<T> hval(stored);
     std::vector<int32_t> hcol;
     std::vector<int16_t> h16;

@@ -518,16 +518,137 @@ __device__ __forceinline__ void prolong_unit_rows(const MatView<T> &P, const T *
     if (t.ok[q]) x[t.row[q]] = xv[q] + acc[q];
 }
 
+// Rows of a block of the pair form of the unit-row prolongation kernel: a wavefront per pair of 64-row slices.
+constexpr int UNIT_PAIR_ROWS = 2 * SELL_C;
+constexpr int UNIT_BLOCK_ROWS = WAVES * UNIT_PAIR_ROWS;
+
+
+// x += P e for P in the unit-row SELL layout (device.hpp, UnitRows). Wavefront w of block lb takes slices
+// s = 2 (4 lb + w) and s + 1. Its lanes first take the pair's F rows (those of slice s, then of slice s + 1,
+// each in rank order), 64 at a time, then its C points' rows the same way, so every lane of a pass has a row
+// of the kind the pass computes (a red-black splitting puts about 32 of each kind in a slice: one lane per
+// row left half the lanes of the F loop idle). The position of a lane's row comes from a table in LDS that
+// the wavefront builds from the two slices' masks.
+//   F row of rank l in slice q: entries k at ptr[s_q] + k m_q + l, in chunks of U (every index, value and
+//   gather of a chunk issued before its products); a slot past the row's end loads a stored slot of the
+//   pair and adds 0 times a gathered element (its column clamped into [0, ncols)), which leaves the sum as
+//   it is: acc starts at +0 and so is never -0, and e is finite.
+//   C point of rank l in slice q: its coarse index is the C points before slice q plus l, and its row adds
+//   0 + 1 e[c] (that is e[c], +0 for -0), as the virtual first entry of the layout's definition.
+// Each row's sum is its entries' in-order sum, so the result is the plain layout's, bit for bit.
+template <bool NARROW, int U, class T>
+__device__ __forceinline__ void prolong_unit_pairs(uint32_t lb, const MatView<T> &P, const T *__restrict__ e, T *x) {
+  __shared__ int16_t tab[WAVES][2][UNIT_PAIR_ROWS];  // per wavefront: [F or C][rank in the pair] = row in the pair
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int32_t nslices = (P.nrows + SELL_C - 1) / SELL_C;
+  const int32_t s0 = ((int32_t)lb * WAVES + wave) * 2;
+  uint64_t um[2] = {0, 0};
+  int32_t before[2] = {0, 0}, m[2] = {0, 0}, p[2] = {0, 0}, w[2] = {0, 0}, nc[2] = {0, 0}, nr[2] = {0, 0};
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int32_t s = s0 + q;
+    if (s < nslices) {  // uniform
+      um[q] = P.umask[s];
+      before[q] = P.smeta[2 * s];
+      m[q] = P.smeta[2 * s + 1];
+      p[q] = P.ptr[s];
+      w[q] = m[q] > 0 ? (P.ptr[s + 1] - p[q]) / m[q] : 0;
+      nr[q] = min(SELL_C, P.nrows - s * SELL_C);
+      nc[q] = __popcll(um[q]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    if (lane < nr[q]) {
+      const uint64_t below = (uint64_t(1) << lane) - 1;
+      if ((um[q] >> lane) & 1)
+        tab[wave][1][q * nc[0] + __popcll(um[q] & below)] = (int16_t)(q * SELL_C + lane);
+      else
+        tab[wave][0][q * m[0] + __popcll(~um[q] & below)] = (int16_t)(q * SELL_C + lane);
+    }
+  }
+  __syncthreads();
+  const int32_t row0 = s0 * SELL_C;
+  // F rows
+  const int32_t nf = m[0] + m[1];
+  const int32_t wmax = max(m[0] > 0 ? w[0] : 0, m[1] > 0 ? w[1] : 0);
+  const int32_t safe = (m[0] > 0 && w[0] > 0) ? p[0] : p[1];  // a stored slot of the pair (used when wmax > 0)
+  for (int32_t f0 = 0; f0 < nf; f0 += SELL_C) {
+    const int32_t f = f0 + lane;
+    const bool act = f < nf;
+    const bool second = f >= m[0];
+    const int32_t rank = second ? f - m[0] : f;
+    const int32_t mq = second ? m[1] : m[0], pq = second ? p[1] : p[0];
+    const int32_t wl = act ? (second ? w[1] : w[0]) : 0;
+    const int32_t row = row0 + (act ? (int32_t)tab[wave][0][f] : 0);
+    const T xv = act ? x[row] : T(0);
+    const int32_t base = NARROW ? diag_base(row, P.mul) : 0;
+    T acc = T(0);
+    for (int32_t k = 0; k < wmax; k += U) {
+      int32_t c[U];
+      T v[U], ev[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool ok = k + u < wl;
+        const int32_t kk = ok ? pq + (k + u) * mq + rank : safe;
+        const int32_t col = NARROW ? base + (int32_t)P.col16[kk] : P.col[kk];
+        const T vv = P.val[kk];  // loaded unconditionally (kk is a stored slot), then selected
+        c[u] = min(max(col, 0), P.ncols - 1);
+        v[u] = ok ? vv : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) ev[u] = e[c[u]];
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc = mul_add(v[u], ev[u], acc);
+    }
+    if (act) x[row] = xv + acc;
+  }
+  // C points' rows: at most two passes of 64 (a pair has at most 128), both passes' loads issued first
+  const int32_t ncp = nc[0] + nc[1];
+  int32_t crow[2];
+  T cev[2], cxv[2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int32_t c = r * SELL_C + lane;
+    crow[r] = -1;
+    if (c < ncp) {
+      const int32_t col = c >= nc[0] ? before[1] + (c - nc[0]) : before[0] + c;
+      crow[r] = row0 + (int32_t)tab[wave][1][c];
+      cev[r] = e[col];
+      cxv[r] = x[crow[r]];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+    if (crow[r] >= 0) x[crow[r]] = cxv[r] + mul_add(T(1), cev[r], T(0));
+}
+
 // x += P e  (prolongation and correction in one pass)
 template <int G, class T>
 __device__ __forceinline__ void prolong_body(uint32_t lb, const MatView<T> &P, const T *__restrict__ e, T *x) {
   if constexpr (G == 1) {
     if (P.umask) {
+      // chunks of eight when the F rows average more than four entries (one dependent round instead of two
+      // for the six-entry rows of a stencil's P); UNIT_PAIRS: the kernel of a wavefront per pair of slices
+      // (DMat::unit_pairs), whose every thread reaches the kernel's barrier
+      const int chunk = P.unroll & ~UNIT_PAIRS;
+      if (P.unroll & UNIT_PAIRS) {
+        if (chunk == 8) {
+          if (P.col16)
+            prolong_unit_pairs<true, 8>(lb, P, e, x);
+          else
+            prolong_unit_pairs<false, 8>(lb, P, e, x);
+        } else {
+          if (P.col16)
+            prolong_unit_pairs<true, 4>(lb, P, e, x);
+          else
+            prolong_unit_pairs<false, 4>(lb, P, e, x);
+        }
+        return;
+      }
       const ThreadRows<1, T> t(lb, P.nrows);
       if (!t.ok[0]) return;
-      // chunks of eight when the F rows average more than four entries (one dependent round instead of two
-      // for the six-entry rows of a stencil's P)
-      if (P.unroll == 8) {
+      if (chunk == 8) {
         if (P.col16)
           prolong_unit_rows<true, 8>(P, e, x, t);
         else

@@ -271,6 +271,7 @@ void pack_unit_device(DMat<T> &M, const DCsr &D, const UnitRows &u, MemCounter *
   for (uint64_t mk : u.mask) M.explicit_nnz -= __builtin_popcountll(mk);
   M.explicit_rows = 0;
   for (int32_t c : u.count) M.explicit_rows += c;
+  M.unit_pairs = unit_pairs_for(M.nrows, M.explicit_rows);
   M.ptr.alloc(u.ptr.size(), mc);
   M.ptr.upload(u.ptr.data(), u.ptr.size());
   M.umask.alloc(std::max<size_t>(u.mask.size(), 1), mc);
@@ -293,6 +294,7 @@ void pack_unit_device(DMat<T> &M, const DCsr &D, const UnitRows &u, MemCounter *
 template <class T>
 void pack_device(DMat<T> &M, const DCsr &D, MemCounter *mc, int force_group, const UnitRows *unit, bool allow_dia) {
   M.unit = false;
+  M.unit_pairs = false;
   M.dia = false;
   M.nrows = D.nr;
   M.ncols = D.nc;

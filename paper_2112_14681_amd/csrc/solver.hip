@@ -130,6 +130,7 @@ int32_t mat_form(const MatView<T> &M) {
 
 template <class T>
 unsigned rows_grid(const DMat<T> &M) {
+  if (M.unit && M.unit_pairs) return (unsigned)((M.nrows + UNIT_BLOCK_ROWS - 1) / UNIT_BLOCK_ROWS);
   return row_blocks(M.nrows, M.group, (int)sizeof(T));
 }
 }  // namespace

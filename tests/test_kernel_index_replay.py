@@ -300,7 +300,7 @@ def replay_dia_exact_two_rows(L, x):
     return out, a
 
 
-def replay_prolong_unit(L, e, U=U):
+def replay_prolong_unit_rows(L, e, U=U):
     """prolong_unit_rows's loads and gathers, row by row (a thread's second row, in FP32, runs the same index
     stream): an F row walks its slots in chunks of U (4, or 8 where F rows average more than four entries);
     a C point's row takes a virtual first entry (column = C points before it, value 1) in its one chunk,
@@ -349,6 +349,87 @@ def replay_prolong_unit(L, e, U=U):
         acc[act] = part
         virt[:] = False
         k = k + U * m
+    return acc, a
+
+
+def replay_prolong_unit_pairs(L, e, U=U):
+    """prolong_unit_pairs, wavefront by wavefront: a wavefront takes slices 2w and 2w + 1; its lanes take the
+    pair's F rows (slice 2w's in rank order, then slice 2w + 1's), 64 at a time, then its C points' rows the
+    same way; a lane's row comes from the table the wavefront builds from the two masks. An F row of rank l in
+    slice q walks slots ptr + k m_q + l in chunks of U up to the pair's widest F row; a slot past its own end
+    loads the pair's first stored slot (a slice with F rows and entries), its column clamped into range, and
+    adds 0 times the gathered element. A C point of rank l in slice q reads e[before_q + l]. Returns P e (the
+    amount each row adds to x) and the access record; also checks the table's indices and every row written."""
+    a = Access(L)
+    acc = np.zeros(L.nrows)
+    written = np.zeros(L.nrows, np.int64)
+    nsl = len(L.ptr) - 1
+    lane = np.arange(SELL_C, dtype=np.int64)
+    a.bad_table = 0
+    for s0 in range(0, nsl, 2):
+        qs = [q for q in (0, 1) if s0 + q < nsl]
+        um = [L.mask_bits[s0 + q] if q in qs else np.zeros(SELL_C, bool) for q in (0, 1)]
+        m = [int(L.count[s0 + q]) if q in qs else 0 for q in (0, 1)]
+        p = [int(L.ptr[s0 + q]) if q in qs else 0 for q in (0, 1)]
+        w = [(int(L.ptr[s0 + q + 1]) - p[q]) // m[q] if q in qs and m[q] > 0 else 0 for q in (0, 1)]
+        nr = [min(SELL_C, L.nrows - (s0 + q) * SELL_C) if q in qs else 0 for q in (0, 1)]
+        nc = [int(um[q][: nr[q]].sum()) for q in (0, 1)]
+        before = [int(L.before[s0 + q]) if q in qs else 0 for q in (0, 1)]
+        ftab = np.full(2 * SELL_C, -1, np.int64)
+        ctab = np.full(2 * SELL_C, -1, np.int64)
+        for q in (0, 1):
+            live = lane < nr[q]
+            isc = um[q] & live
+            isf = ~um[q] & live
+            crank = np.cumsum(um[q]) - um[q]
+            frank = np.cumsum(~um[q]) - (~um[q])
+            ci_ = q * nc[0] + crank[isc]
+            fi_ = q * m[0] + frank[isf]
+            a.bad_table += int(np.count_nonzero((ci_ < 0) | (ci_ >= 2 * SELL_C)))
+            a.bad_table += int(np.count_nonzero((fi_ < 0) | (fi_ >= 2 * SELL_C)))
+            ctab[np.clip(ci_, 0, 2 * SELL_C - 1)] = q * SELL_C + lane[isc]
+            ftab[np.clip(fi_, 0, 2 * SELL_C - 1)] = q * SELL_C + lane[isf]
+        row0 = s0 * SELL_C
+        nf = m[0] + m[1]
+        wmax = max(w[0] if m[0] > 0 else 0, w[1] if m[1] > 0 else 0)
+        safe = p[0] if (m[0] > 0 and w[0] > 0) else p[1]
+        for f0 in range(0, nf, SELL_C):
+            f = f0 + lane
+            act = f < nf
+            second = f >= m[0]
+            rank = np.where(second, f - m[0], f)
+            mq = np.where(second, m[1], m[0])
+            pq = np.where(second, p[1], p[0])
+            wl = np.where(act, np.where(second, w[1], w[0]), 0)
+            pos = np.where(act, ftab[np.clip(f, 0, 2 * SELL_C - 1)], 0)
+            a.bad_table += int(np.count_nonzero(act & (pos < 0)))
+            row = row0 + pos
+            base = diag_base(row, L.mul) if L.narrow else np.zeros_like(row)
+            part = np.zeros(SELL_C)
+            for k in range(0, wmax, U):
+                for u in range(U):
+                    ok = k + u < wl
+                    kk = np.where(ok, pq + (k + u) * mq + rank, safe)
+                    i, v = a.load(kk)
+                    col = base + i if L.narrow else i
+                    c = np.clip(col, 0, L.ncols - 1)
+                    ev = a.gather(e, c)
+                    part = part + np.where(ok, v, 0.0) * ev
+            rows = row[act]
+            written[rows] += 1
+            acc[rows] = part[act]
+        ncp = nc[0] + nc[1]
+        for c0 in range(0, ncp, SELL_C):
+            c = c0 + lane
+            act = c < ncp
+            second = c >= nc[0]
+            col = np.where(second, before[1] + (c - nc[0]), before[0] + c)[act]
+            pos = ctab[np.clip(c, 0, 2 * SELL_C - 1)][act]
+            a.bad_table += int(np.count_nonzero(pos < 0))
+            rows = row0 + pos
+            written[rows] += 1
+            acc[rows] = 0.0 + 1.0 * a.gather(e, col)
+    a.bad_rows = int(np.count_nonzero(written != 1))  # every row written exactly once
     return acc, a
 
 
@@ -544,9 +625,15 @@ def test_row_kernel_accesses_in_range(namg, case):
             assert Lu.ok, (name, label)  # a C/F splitting's P always has the unit-row form
             assert Lu.stored < L.stored, (name, label)
             for unroll in (4, 8):
-                yu, accu = replay_prolong_unit(Lu, x, unroll)
+                yu, accu = replay_prolong_unit_rows(Lu, x, unroll)
                 assert accu.bad_loads == 0 and accu.bad_gathers == 0, (name, label, "unit rows", unroll,
                                                                       accu.bad_loads, accu.bad_gathers)
+                yp, accp = replay_prolong_unit_pairs(Lu, x, unroll)
+                assert accp.bad_loads == 0 and accp.bad_gathers == 0, (name, label, "unit pairs", unroll,
+                                                                      accp.bad_loads, accp.bad_gathers)
+                assert accp.bad_table == 0 and accp.bad_rows == 0, (name, label, "unit pairs", unroll,
+                                                                    accp.bad_table, accp.bad_rows)
+                assert np.array_equal(yp, yu), (name, label, "pairs", unroll)
                 ref = sp.csr_matrix((v, ci, rp), shape=(len(rp) - 1, ncols)) @ x
                 np.testing.assert_allclose(yu, ref, rtol=1e-14, atol=1e-14)
                 assert np.array_equal(yu, y), (name, label, unroll)  # entry order kept: the plain layout's bits
@@ -603,9 +690,11 @@ def test_unit_layout_needs_its_masks():
         plain.ptr, plain.idx, plain.val, plain.stored = Lu.ptr, Lu.idx, Lu.val, Lu.stored
         x = np.random.default_rng(1).standard_normal(ncols)
         _, wrong = replay_one_row_per_lane(plain, x)
-        _, right = replay_prolong_unit(Lu, x)
+        _, right = replay_prolong_unit_rows(Lu, x)
+        _, pairs = replay_prolong_unit_pairs(Lu, x)
         found += wrong.bad_gathers
         assert right.bad_gathers == 0 and right.bad_loads == 0, label
+        assert pairs.bad_gathers == 0 and pairs.bad_loads == 0 and pairs.bad_table == 0 and pairs.bad_rows == 0, label
     assert found > 0
 
 
