@@ -325,12 +325,12 @@ struct DeviceLevels {
 //    j, j+G, ...; the G partial sums are combined by a fixed xor-butterfly. Used for the long rows of
 //    the Galerkin operators on coarse levels, where one lane per row would walk 30-100 dependent
 //    entries.
-//  * slice-diagonal SELL-64: a square SELL-64 matrix whose rows within each slice share a few column
-//    offsets from the diagonal (stencil operators in natural order and their red-black coarsenings)
-//    stores no per-entry column at all. Slot k of slice s holds, for all 64 rows, the entries at one
-//    offset d(s, k) from the row's diagonal (value 0 where a row has no entry there); the slots of a
-//    slice are the union of its rows' offsets in increasing order, so each row's entries keep their CSR
-//    order. One int32 offset per slot (64 entries) replaces the 2- or 4-byte column of every entry, and
+//  * slice-diagonal SELL-64: a SELL-64 matrix whose rows within each slice share a few column offsets
+//    from their scaled diagonal base(r) below (stencil operators in natural order, their red-black
+//    coarsenings and the restrictions between them) stores no per-entry column at all. Slot k of slice s
+//    holds, for all 64 rows, the entries at column base(r) + d(s, k) (value 0 where a row has no entry
+//    there); the slots of a slice are the union of its rows' offsets in increasing order, so each row's
+//    entries keep their CSR order. One int32 offset per slot (64 entries) replaces the 2- or 4-byte column of every entry, and
 //    a slot's gathers are 64 consecutive elements of x. Chosen per matrix, see LayoutCount.
 // Column indices are stored in one of two widths, also chosen per matrix: as 16-bit offsets from the
 // row's scaled diagonal, base(r) = (r * mul) >> 20 with mul = (ncols << 20) / nrows, when every column
@@ -478,8 +478,8 @@ inline int choose_group(int64_t nrows, int64_t nnz) {
   return g;
 }
 
-// The slice-diagonal form (see the layout notes above) is taken by a square matrix of group 1 that is not a
-// unit-row prolongation when
+// The slice-diagonal form (see the layout notes above) is taken by a matrix of group 1 that is not a unit-row
+// prolongation when
 //   * every row's columns strictly increase (so the slots' offset order is each row's entry order),
 //   * no slice's union of offsets exceeds dia_cap(its longest row), and
 //   * it stores fewer bytes than SELL-64: slots x 64 x value bytes + 4 per slot, against SELL-64's
@@ -501,7 +501,6 @@ struct LayoutCount {
   int64_t nnz = 0, sell_stored = 0, dia_stored = 0;
   int32_t slice_w = 0;
   bool narrow = true;
-  bool square = true;  // the matrix is square (the slice-diagonal form needs it)
   bool dia_ok = true;  // rows strictly increasing and every completed slice within its cap
   std::vector<int32_t> row_off, prev_off, uni, merged;  // prev_off: the slice's last row that was merged
 
@@ -544,7 +543,7 @@ struct LayoutCount {
   // the slice-diagonal choice for a DMat<T> of group `group`
   template <class T>
   bool use_dia(int group) const {
-    return group == 1 && square && dia_ok && (int64_t)uni.size() <= dia_cap(slice_w) &&
+    return group == 1 && dia_ok && (int64_t)uni.size() <= dia_cap(slice_w) &&
            dia_wins(sell_total(), dia_total(), narrow, sizeof(T));
   }
   // device bytes of the DMat<T> of nr rows: DMat::build's layout choice, and the size class each of its
@@ -567,7 +566,6 @@ struct LayoutCount {
 // LayoutCount of every entry of A (allow_dia false: the slice-diagonal form is not considered, nor counted).
 inline LayoutCount layout_count(const HostCsr &A, bool allow_dia = true) {
   LayoutCount c;
-  c.square = A.nr == A.nc;
   c.dia_ok = allow_dia;
   const int64_t mul = diag_mul(A.nr, A.nc);
   for (int32_t r = 0; r < A.nr; ++r) {
@@ -666,7 +664,7 @@ struct DMat {
         return;
       }
     }
-    if (allow_dia && group == 1 && nrows == ncols && layout_count(A).use_dia<T>(group)) {
+    if (allow_dia && group == 1 && layout_count(A).use_dia<T>(group)) {
       build_dia(A, mc);
       return;
     }
@@ -735,7 +733,7 @@ struct DMat {
     val.upload(hval.data(), hval.size());
   }
 
-  // The slice-diagonal layout of the square matrix A (LayoutCount::use_dia holds): slice s stores its union
+  // The slice-diagonal layout of A (LayoutCount::use_dia holds): slice s stores its union
   // of offsets in increasing order, slot k at ptr[s] + 64 k (entries) and doff[1 + ptr[s] / 64 + k] (offset);
   void build_dia(const HostCsr &A, MemCounter *mc) {
     dia = true;
@@ -750,7 +748,8 @@ struct DMat {
       for (int32_t r = s * SELL_C; r < std::min(nrows, (s + 1) * SELL_C); ++r) {
         merged.clear();
         ro.clear();
-        for (int32_t k = A.rp[r]; k < A.rp[r + 1]; ++k) ro.push_back(A.ci[k] - r);
+        const int32_t base = diag_base(r, mul);
+        for (int32_t k = A.rp[r]; k < A.rp[r + 1]; ++k) ro.push_back(A.ci[k] - base);
         std::set_union(uni.begin(), uni.end(), ro.begin(), ro.end(), std::back_inserter(merged));
         uni.swap(merged);
       }
@@ -765,7 +764,7 @@ struct DMat {
       for (int32_t r = s * SELL_C; r < std::min(nrows, (s + 1) * SELL_C); ++r) {
         int32_t j = 0;
         for (int32_t k = A.rp[r]; k < A.rp[r + 1]; ++k) {
-          while (j < w && o[j] != A.ci[k] - r) ++j;
+          while (j < w && o[j] != A.ci[k] - diag_base(r, mul)) ++j;
           hval[(int64_t)hptr[s] + (int64_t)j * SELL_C + (r - s * SELL_C)] = (T)A.v[k];
         }
       }

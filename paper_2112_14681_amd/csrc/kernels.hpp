@@ -115,11 +115,12 @@ __device__ __forceinline__ Acc row_dot_impl(const MatView<TM> &A, const TX *__re
 
 // K slots j .. j + K - 1 of one slice-diagonal row (all of them exist): the K offsets (wave-uniform, one
 // merged scalar load), then K value loads and K gathers, none waiting on another, then the K products in
-// slot order. A padding slot (value 0) adds 0 times an in-range element of x: the sum is the row's CSR-order
-// sum whenever x is finite (a -0 sum may come out +0).
+// slot order. A slot's column is the row's scaled diagonal `base` (the row itself in a square matrix) plus the
+// slot's offset. A padding slot (value 0) adds 0 times an in-range element of x: the sum is the row's
+// CSR-order sum whenever x is finite (a -0 sum may come out +0).
 template <int K, class Acc, class TM, class TX>
 __device__ __forceinline__ void dia_slots(const TM *__restrict__ vp, const int32_t *__restrict__ off,
-                                          const TX *__restrict__ x, int32_t row, int32_t cmax, int32_t j, Acc &acc) {
+                                          const TX *__restrict__ x, int32_t base, int32_t cmax, int32_t j, Acc &acc) {
   int32_t o[K];
   TM v[K];
   TX xv[K];
@@ -128,7 +129,7 @@ __device__ __forceinline__ void dia_slots(const TM *__restrict__ vp, const int32
 #pragma unroll
   for (int u = 0; u < K; ++u) {
     v[u] = vp[(int64_t)(j + u) * SELL_C];
-    xv[u] = x[min(max(row + o[u], 0), cmax)];
+    xv[u] = x[min(max(base + o[u], 0), cmax)];
   }
   // every product is added, padding slots included (value 0 times an element of x, which is finite in any
   // solve that has not already failed its non-finite check): with no condition, no gather can be sunk
@@ -137,11 +138,12 @@ __device__ __forceinline__ void dia_slots(const TM *__restrict__ vp, const int32
   for (int u = 0; u < K; ++u) acc = mul_add((Acc)v[u], (Acc)xv[u], acc);
 }
 
-// The same for two rows (r0 of one slice, r1 of the next) whose slices both have slots j .. j + K - 1.
+// The same for two rows (of bases b0 and b1, in one slice and the next) whose slices both have slots
+// j .. j + K - 1.
 template <int K, class Acc, class TM, class TX>
 __device__ __forceinline__ void dia_slots2(const TM *__restrict__ vp0, const int32_t *__restrict__ off0,
                                            const TM *__restrict__ vp1, const int32_t *__restrict__ off1,
-                                           const TX *__restrict__ x, int32_t r0, int32_t r1, int32_t cmax, int32_t j,
+                                           const TX *__restrict__ x, int32_t b0, int32_t b1, int32_t cmax, int32_t j,
                                            Acc &a0, Acc &a1) {
   int32_t o0[K], o1[K];
   TM v0[K], v1[K];
@@ -155,8 +157,8 @@ __device__ __forceinline__ void dia_slots2(const TM *__restrict__ vp0, const int
   for (int u = 0; u < K; ++u) {
     v0[u] = vp0[(int64_t)(j + u) * SELL_C];
     v1[u] = vp1[(int64_t)(j + u) * SELL_C];
-    x0[u] = x[min(max(r0 + o0[u], 0), cmax)];
-    x1[u] = x[min(max(r1 + o1[u], 0), cmax)];
+    x0[u] = x[min(max(b0 + o0[u], 0), cmax)];
+    x1[u] = x[min(max(b1 + o1[u], 0), cmax)];
   }
 #pragma unroll
   for (int u = 0; u < K; ++u) {
@@ -169,17 +171,17 @@ __device__ __forceinline__ void dia_slots2(const TM *__restrict__ vp0, const int
 // no slot past the slice's end is loaded and a row of w slots waits on ceil(w / 8) rounds of loads.
 template <class Acc, class TM, class TX>
 __device__ __forceinline__ void dia_row_from(const TM *__restrict__ vp, const int32_t *__restrict__ off,
-                                             const TX *__restrict__ x, int32_t row, int32_t cmax, int32_t j, int32_t w,
+                                             const TX *__restrict__ x, int32_t base, int32_t cmax, int32_t j, int32_t w,
                                              Acc &acc) {
-  for (; j + 8 <= w; j += 8) dia_slots<8>(vp, off, x, row, cmax, j, acc);
+  for (; j + 8 <= w; j += 8) dia_slots<8>(vp, off, x, base, cmax, j, acc);
   switch (w - j) {
-    case 7: dia_slots<7>(vp, off, x, row, cmax, j, acc); break;
-    case 6: dia_slots<6>(vp, off, x, row, cmax, j, acc); break;
-    case 5: dia_slots<5>(vp, off, x, row, cmax, j, acc); break;
-    case 4: dia_slots<4>(vp, off, x, row, cmax, j, acc); break;
-    case 3: dia_slots<3>(vp, off, x, row, cmax, j, acc); break;
-    case 2: dia_slots<2>(vp, off, x, row, cmax, j, acc); break;
-    case 1: dia_slots<1>(vp, off, x, row, cmax, j, acc); break;
+    case 7: dia_slots<7>(vp, off, x, base, cmax, j, acc); break;
+    case 6: dia_slots<6>(vp, off, x, base, cmax, j, acc); break;
+    case 5: dia_slots<5>(vp, off, x, base, cmax, j, acc); break;
+    case 4: dia_slots<4>(vp, off, x, base, cmax, j, acc); break;
+    case 3: dia_slots<3>(vp, off, x, base, cmax, j, acc); break;
+    case 2: dia_slots<2>(vp, off, x, base, cmax, j, acc); break;
+    case 1: dia_slots<1>(vp, off, x, base, cmax, j, acc); break;
     default: break;
   }
 }
@@ -191,7 +193,8 @@ __device__ __forceinline__ Acc dia_dot(const MatView<TM> &A, const TX *__restric
   const int32_t s = __builtin_amdgcn_readfirstlane(row >> 6), lane = row & 63;
   const int32_t p0 = A.ptr[s], p1 = A.ptr[s + 1];
   Acc acc = Acc(0);
-  dia_row_from(A.val + p0 + lane, A.dia + 1 + (p0 >> 6), x, row, A.dia[0], 0, (p1 - p0) >> 6, acc);
+  dia_row_from(A.val + p0 + lane, A.dia + 1 + (p0 >> 6), x, diag_base(row, A.mul), A.dia[0], 0, (p1 - p0) >> 6,
+               acc);
   return acc;
 }
 
@@ -211,24 +214,24 @@ __device__ __forceinline__ void dia_dot2(const MatView<TM> &A, const TX *__restr
   const int32_t *__restrict__ off0 = A.dia + 1 + (p0 >> 6);
   const int32_t *__restrict__ off1 = A.dia + 1 + (p1 >> 6);
   const int32_t cmax = A.dia[0];
-  const int32_t r1 = r0 + SELL_C;
+  const int32_t b0 = diag_base(r0, A.mul), b1 = diag_base(r0 + SELL_C, A.mul);
   a0 = Acc(0);
   a1 = Acc(0);
   const int32_t wm = min(w0, w1);
   int32_t j = 0;
-  for (; j + 8 <= wm; j += 8) dia_slots2<8>(vp0, off0, vp1, off1, x, r0, r1, cmax, j, a0, a1);
+  for (; j + 8 <= wm; j += 8) dia_slots2<8>(vp0, off0, vp1, off1, x, b0, b1, cmax, j, a0, a1);
   switch (wm - j) {
-    case 7: dia_slots2<7>(vp0, off0, vp1, off1, x, r0, r1, cmax, j, a0, a1); break;
-    case 6: dia_slots2<6>(vp0, off0, vp1, off1, x, r0, r1, cmax, j, a0, a1); break;
-    case 5: dia_slots2<5>(vp0, off0, vp1, off1, x, r0, r1, cmax, j, a0, a1); break;
-    case 4: dia_slots2<4>(vp0, off0, vp1, off1, x, r0, r1, cmax, j, a0, a1); break;
-    case 3: dia_slots2<3>(vp0, off0, vp1, off1, x, r0, r1, cmax, j, a0, a1); break;
-    case 2: dia_slots2<2>(vp0, off0, vp1, off1, x, r0, r1, cmax, j, a0, a1); break;
-    case 1: dia_slots2<1>(vp0, off0, vp1, off1, x, r0, r1, cmax, j, a0, a1); break;
+    case 7: dia_slots2<7>(vp0, off0, vp1, off1, x, b0, b1, cmax, j, a0, a1); break;
+    case 6: dia_slots2<6>(vp0, off0, vp1, off1, x, b0, b1, cmax, j, a0, a1); break;
+    case 5: dia_slots2<5>(vp0, off0, vp1, off1, x, b0, b1, cmax, j, a0, a1); break;
+    case 4: dia_slots2<4>(vp0, off0, vp1, off1, x, b0, b1, cmax, j, a0, a1); break;
+    case 3: dia_slots2<3>(vp0, off0, vp1, off1, x, b0, b1, cmax, j, a0, a1); break;
+    case 2: dia_slots2<2>(vp0, off0, vp1, off1, x, b0, b1, cmax, j, a0, a1); break;
+    case 1: dia_slots2<1>(vp0, off0, vp1, off1, x, b0, b1, cmax, j, a0, a1); break;
     default: break;
   }
-  if (w0 > wm) dia_row_from(vp0, off0, x, r0, cmax, wm, w0, a0);
-  if (w1 > wm) dia_row_from(vp1, off1, x, r1, cmax, wm, w1, a1);
+  if (w0 > wm) dia_row_from(vp0, off0, x, b0, cmax, wm, w0, a0);
+  if (w1 > wm) dia_row_from(vp1, off1, x, b1, cmax, wm, w1, a1);
 }
 
 template <int G, class Acc, int U = 4, class TM, class TX>

@@ -32,18 +32,19 @@ __global__ __launch_bounds__(PB) void k_slice_width(int32_t nrows, const int32_t
   w[s] = m * SELL_C;
 }
 
-// The slice-diagonal form of a square matrix (see LayoutCount), one wavefront per slice s, lane l on row
-// 64 s + l: each round takes the smallest pending column offset (column - row) over the wavefront, which is
-// the slice's next slot, and the lanes whose row has that offset advance past it.
+// The slice-diagonal form (see LayoutCount), one wavefront per slice s, lane l on row 64 s + l: each round
+// takes the smallest pending column offset (column - the row's scaled diagonal base) over the wavefront,
+// which is the slice's next slot, and the lanes whose row has that offset advance past it.
 // uw[s] = the slice's number of distinct offsets, counted up to dia_cap(its longest row) + 1;
 // *unsorted = 1 when some row's columns do not strictly increase (integer atomic only).
 __global__ __launch_bounds__(PB) void k_dia_width(int32_t nrows, const int32_t *__restrict__ rp,
-                                                  const int32_t *__restrict__ ci, int32_t *__restrict__ uw,
-                                                  int32_t *unsorted) {
+                                                  const int32_t *__restrict__ ci, int64_t mul,
+                                                  int32_t *__restrict__ uw, int32_t *unsorted) {
   const int64_t t = (int64_t)blockIdx.x * PB + threadIdx.x;
   const int32_t s = (int32_t)(t >> 6), lane = (int32_t)(t & 63);
   if (s >= (nrows + SELL_C - 1) / SELL_C) return;  // whole wavefronts
   const int32_t r = s * SELL_C + lane;
+  const int32_t base = diag_base(r, mul);
   int32_t k = 0, end = 0;
   if (r < nrows) {
     k = rp[r];
@@ -59,7 +60,7 @@ __global__ __launch_bounds__(PB) void k_dia_width(int32_t nrows, const int32_t *
   const int64_t cap = dia_cap(len);
   int32_t cnt = 0;
   while (true) {
-    const int32_t cur = k < end ? ci[k] - r : INT32_MAX;
+    const int32_t cur = k < end ? ci[k] - base : INT32_MAX;
     int32_t m = cur;
     for (int off = 32; off > 0; off >>= 1) m = min(m, __shfl_xor(m, off, 64));
     if (m == INT32_MAX || cnt > cap) break;
@@ -74,14 +75,16 @@ __global__ __launch_bounds__(PB) void k_dia_width(int32_t nrows, const int32_t *
 // slot j of slice s takes offset doff[1 + sptr[s] / 64 + j] and, lane by lane, the row's entry at that offset
 // or 0; doff[0] = ncols - 1.
 template <class T>
-__global__ __launch_bounds__(PB) void k_pack_dia(int32_t nrows, int32_t ncols, const int32_t *__restrict__ rp,
-                                                 const int32_t *__restrict__ ci, const double *__restrict__ v,
+__global__ __launch_bounds__(PB) void k_pack_dia(int32_t nrows, int32_t ncols, int64_t mul,
+                                                 const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                 const double *__restrict__ v,
                                                  const int32_t *__restrict__ sptr, int32_t *__restrict__ doff,
                                                  T *__restrict__ val) {
   const int64_t t = (int64_t)blockIdx.x * PB + threadIdx.x;
   const int32_t s = (int32_t)(t >> 6), lane = (int32_t)(t & 63);
   if (s >= (nrows + SELL_C - 1) / SELL_C) return;
   const int32_t r = s * SELL_C + lane;
+  const int32_t base = diag_base(r, mul);
   int32_t k = 0, end = 0;
   if (r < nrows) {
     k = rp[r];
@@ -90,7 +93,7 @@ __global__ __launch_bounds__(PB) void k_pack_dia(int32_t nrows, int32_t ncols, c
   const int32_t p0 = sptr[s], p1 = sptr[s + 1];
   int32_t j = 0;
   while (true) {
-    const int32_t cur = k < end ? ci[k] - r : INT32_MAX;
+    const int32_t cur = k < end ? ci[k] - base : INT32_MAX;
     int32_t m = cur;
     for (int off = 32; off > 0; off >>= 1) m = min(m, __shfl_xor(m, off, 64));
     const int64_t d = (int64_t)p0 + (int64_t)j * SELL_C + lane;
@@ -338,7 +341,7 @@ void pack_device(DMat<T> &M, const DCsr &D, MemCounter *mc, int force_group, con
       hip_check(hipMemcpy(w.data(), dw.get(), (size_t)nslices * 4, hipMemcpyDeviceToHost), "hipMemcpy D2H");
     }
     w.resize(nslices);
-    if (allow_dia && nslices > 0 && M.nrows == M.ncols && layout_tuning().dia) {
+    if (allow_dia && nslices > 0 && layout_tuning().dia) {
       // the slice-diagonal choice, by the rule LayoutCount applies on the host
       std::vector<int32_t> uw(nslices, 0);
       int32_t unsorted = 0;
@@ -346,7 +349,7 @@ void pack_device(DMat<T> &M, const DCsr &D, MemCounter *mc, int force_group, con
         DevBuf<int32_t> duw((size_t)nslices, &setup_mem()), dflag(1, &setup_mem());
         hip_check(hipMemset(dflag.get(), 0, 4), "hipMemset");
         hipLaunchKernelGGL(k_dia_width, dim3(pgrid((int64_t)nslices * SELL_C)), dim3(PB), 0, 0, M.nrows, D.rp.get(),
-                           D.ci.get(), duw.get(), dflag.get());
+                           D.ci.get(), M.mul, duw.get(), dflag.get());
         check("k_dia_width");
         hip_check(hipMemcpy(uw.data(), duw.get(), (size_t)nslices * 4, hipMemcpyDeviceToHost), "hipMemcpy D2H");
         hip_check(hipMemcpy(&unsorted, dflag.get(), 4, hipMemcpyDeviceToHost), "hipMemcpy D2H");
@@ -369,7 +372,7 @@ void pack_device(DMat<T> &M, const DCsr &D, MemCounter *mc, int force_group, con
         M.doff.alloc((size_t)(M.stored / SELL_C + 1), mc);
         M.val.alloc((size_t)M.stored, mc);
         hipLaunchKernelGGL(k_pack_dia<T>, dim3(pgrid((int64_t)nslices * SELL_C)), dim3(PB), 0, 0, M.nrows, M.ncols,
-                           D.rp.get(), D.ci.get(), D.v.get(), M.ptr.get(), M.doff.get(), M.val.get());
+                           M.mul, D.rp.get(), D.ci.get(), D.v.get(), M.ptr.get(), M.doff.get(), M.val.get());
         check("k_pack_dia");
         hip_check(hipStreamSynchronize(nullptr), "hipStreamSynchronize");
         return;

@@ -28,7 +28,6 @@ struct MatrixShape {
 
 inline MatrixShape matrix_shape(const HostCsr &A, bool allow_dia = true) {
   MatrixShape m;
-  m.all.square = m.lo.square = m.up.square = A.nr == A.nc;
   m.all.dia_ok = m.lo.dia_ok = m.up.dia_ok = allow_dia;
   const int64_t mul = diag_mul(A.nr, A.nc);
   for (int32_t r = 0; r < A.nr; ++r) {
@@ -63,8 +62,8 @@ int64_t mat_alloc_bytes(const HostCsr &A, int force_group = 0, bool allow_dia = 
 // column offset from R's own diagonal base).
 inline std::pair<LayoutCount, LayoutCount> transfer_shape(const HostCsr &P) {
   LayoutCount lp, lr;
-  // rectangular: neither takes the slice-diagonal form (and lr's columns arrive out of row order)
-  lp.square = lr.square = false;
+  // neither is counted for the slice-diagonal form (served requests never take it, and lr's columns arrive
+  // out of row order)
   lp.dia_ok = lr.dia_ok = false;
   const int64_t mul_p = diag_mul(P.nr, P.nc), mul_r = diag_mul(P.nc, P.nr);
   std::vector<int32_t> rlen(P.nc, 0);

@@ -189,19 +189,19 @@ class Solver final : public SolverBase {
       if (dl) {
         pack_device(d.A, dl->A[l], &mc_, 0, nullptr, ad);
         const UnitRows pu = unit_rows_of(h.P, h.cf);
-        pack_device(d.P, dl->P[l], &mc_, 0, &pu);
-        pack_device(d.R, dl->R[l], &mc_);
+        pack_device(d.P, dl->P[l], &mc_, 0, &pu, ad);
+        pack_device(d.R, dl->R[l], &mc_, 0, nullptr, ad);
         DCsr lo, up;
         smoother_data_device(dl->A[l], lo, up, d.dinv, d.dl1inv, &mc_);
         pack_device(d.pgs_lo, lo, &mc_, 0, nullptr, ad);
         pack_device(d.pgs_up, up, &mc_, 0, nullptr, ad);
       } else {
         d.A.build(h.A, &mc_, 0, nullptr, ad);
-        d.P.build(h.P, &mc_, 0, &h.cf);
+        d.P.build(h.P, &mc_, 0, &h.cf, ad);
         if (h.host_restriction)
-          d.R.build(h.R, &mc_);
+          d.R.build(h.R, &mc_, 0, nullptr, ad);
         else
-          d.R.build(restriction_of(h.P), &mc_);
+          d.R.build(restriction_of(h.P), &mc_, 0, nullptr, ad);
         if (h.host_smoother) {
           d.pgs_lo.build(h.pgs_lo, &mc_, 0, nullptr, ad);
           d.pgs_up.build(h.pgs_up, &mc_, 0, nullptr, ad);

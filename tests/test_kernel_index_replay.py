@@ -145,10 +145,10 @@ def dia_cap(longest_row):
 
 
 class DiaLayout:
-    """The slice-diagonal layout of a square matrix, as the library packs it, and the library's rule for taking
-    it (`use(val_bytes)`): rows with strictly increasing columns, no slice whose union of offsets (column -
-    row) exceeds dia_cap(its longest row), and fewer bytes than SELL-64 (slots x 64 x value bytes + 4 per slot
-    against SELL-64's stored entries x (value + column bytes)). Slice s keeps its union in increasing order:
+    """The slice-diagonal layout of a matrix, as the library packs it, and the library's rule for taking it
+    (`use(val_bytes)`): rows with strictly increasing columns, no slice whose union of offsets (column - the
+    row's scaled diagonal base) exceeds dia_cap(its longest row), and fewer bytes than SELL-64 (slots x 64 x
+    value bytes + 4 per slot against SELL-64's stored entries x (value + column bytes)). Slice s keeps its union in increasing order:
     slot k's entries at ptr[s] + 64 k, its offset at off[1 + ptr[s] / 64 + k]; off[0] is ncols - 1."""
 
     def __init__(self, rp, ci, vals, ncols):
@@ -156,10 +156,10 @@ class DiaLayout:
         ci = np.asarray(ci, np.int64)
         self.nrows = n = len(rp) - 1
         self.ncols = ncols
-        self.square = n == ncols
+        self.mul = diag_mul(n, ncols)
         lens = np.diff(rp)
         rows = np.repeat(np.arange(n), lens)
-        off = ci - rows
+        off = ci - diag_base(rows, self.mul)
         nsl = (n + SELL_C - 1) // SELL_C
         same_row = rows[1:] == rows[:-1]
         self.sorted = bool(np.all(ci[1:][same_row] > ci[:-1][same_row]))
@@ -186,7 +186,7 @@ class DiaLayout:
         self.narrow = bool(off.size == 0 or (off.min() >= -32768 and off.max() <= 32767))
 
     def use(self, val_bytes, group=1):
-        if not (group == 1 and self.square and self.sorted and self.nrows > 0):
+        if not (group == 1 and self.sorted and self.nrows > 0):
             return False
         if np.any(self.width > dia_cap(self.longest)):
             return False
@@ -246,7 +246,7 @@ def replay_dia_exact(L, x):
             for u in range(k):
                 o = int(a.offset(np.array([1 + (p0 >> 6) + j + u]))[0])
                 v = a.value(p0 + (j + u) * SELL_C + lane)
-                part = part + v * a.gather(x, np.clip(rows + o, 0, cmax))
+                part = part + v * a.gather(x, np.clip(diag_base(rows, L.mul) + o, 0, cmax))
         acc[rows] = part
     return acc, a
 
@@ -274,7 +274,7 @@ def replay_dia_exact_two_rows(L, x):
                     q = j0 + j + u
                     o = int(a.offset(np.array([1 + (p >> 6) + q]))[0])
                     v = a.value(p + q * SELL_C + lane)
-                    part = part + v * a.gather(x, np.clip(r + o, 0, cmax))
+                    part = part + v * a.gather(x, np.clip(diag_base(r, L.mul) + o, 0, cmax))
             return part
 
         wm = min(w0, w1)
@@ -284,7 +284,7 @@ def replay_dia_exact_two_rows(L, x):
                 for p, r, which in ((p0, r0, 0), (p1, r1, 1)):
                     o = int(a.offset(np.array([1 + (p >> 6) + q]))[0])
                     v = a.value(p + q * SELL_C + lane)
-                    prod = v * a.gather(x, np.clip(r + o, 0, cmax))
+                    prod = v * a.gather(x, np.clip(diag_base(r, L.mul) + o, 0, cmax))
                     if which == 0:
                         a0 = a0 + prod
                     else:
@@ -642,7 +642,7 @@ def test_row_kernel_accesses_in_range(namg, case):
             assert acc2.bad_loads == 0 and acc2.bad_gathers == 0, (name, label, "two rows per lane",
                                                                    acc2.bad_loads, acc2.bad_gathers)
             assert np.array_equal(y2, y), (name, label)
-        if ncols == len(rp) - 1:
+        if cf is None:  # every operator but the prolongations (whose unit-row layout comes first)
             D = DiaLayout(rp, ci, v, ncols)
             for vb in (4, 8):
                 if not D.use(vb, L.group):
