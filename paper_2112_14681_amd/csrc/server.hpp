@@ -32,6 +32,30 @@ inline MatrixShape matrix_shape(const HostCsr &A, bool allow_dia = true) {
   const int64_t mul = diag_mul(A.nr, A.nc);
   for (int32_t r = 0; r < A.nr; ++r) {
     const int32_t base = diag_base(r, mul);
+    if (!allow_dia) {
+      // one tight pass: the row's counts and the range of each part's offsets (row_span)
+      int64_t mn = INT64_MAX, mx = INT64_MIN, lmn = INT64_MAX, lmx = INT64_MIN, umn = INT64_MAX, umx = INT64_MIN;
+      int32_t nlo = 0, nup = 0;
+      for (int32_t k = A.rp[r]; k < A.rp[r + 1]; ++k) {
+        const int32_t c = A.ci[k];
+        const int64_t d = (int64_t)c - base;
+        mn = std::min(mn, d);
+        mx = std::max(mx, d);
+        if (c < r) {
+          ++nlo;
+          lmn = std::min(lmn, d);
+          lmx = std::max(lmx, d);
+        } else if (c > r) {
+          ++nup;
+          umn = std::min(umn, d);
+          umx = std::max(umx, d);
+        }
+      }
+      m.all.row_span(r, A.rp[r + 1] - A.rp[r], mn, mx);
+      m.lo.row_span(r, nlo, lmn, lmx);
+      m.up.row_span(r, nup, umn, umx);
+      continue;
+    }
     int32_t nlo = 0, nup = 0;
     for (int32_t k = A.rp[r]; k < A.rp[r + 1]; ++k) {
       const int32_t c = A.ci[k];
@@ -67,17 +91,22 @@ inline std::pair<LayoutCount, LayoutCount> transfer_shape(const HostCsr &P) {
   lp.dia_ok = lr.dia_ok = false;
   const int64_t mul_p = diag_mul(P.nr, P.nc), mul_r = diag_mul(P.nc, P.nr);
   std::vector<int32_t> rlen(P.nc, 0);
+  int64_t rmn = INT64_MAX, rmx = INT64_MIN;  // R's offsets, over all its entries (its 16-bit test is global)
   for (int32_t i = 0; i < P.nr; ++i) {
     const int32_t base = diag_base(i, mul_p);
+    int64_t mn = INT64_MAX, mx = INT64_MIN;
     for (int32_t k = P.rp[i]; k < P.rp[i + 1]; ++k) {
       const int32_t c = P.ci[k];
-      lp.col((int64_t)c - base);
-      lr.col((int64_t)i - diag_base(c, mul_r));
+      const int64_t d = (int64_t)c - base, dr = (int64_t)i - diag_base(c, mul_r);
+      mn = std::min(mn, d);
+      mx = std::max(mx, d);
+      rmn = std::min(rmn, dr);
+      rmx = std::max(rmx, dr);
       rlen[c]++;
     }
-    lp.row(i, P.rp[i + 1] - P.rp[i]);
+    lp.row_span(i, P.rp[i + 1] - P.rp[i], mn, mx);
   }
-  for (int32_t c = 0; c < P.nc; ++c) lr.row(c, rlen[c]);
+  for (int32_t c = 0; c < P.nc; ++c) lr.row_span(c, rlen[c], rmn, rmx);
   return {lp, lr};
 }
 
@@ -85,7 +114,7 @@ inline std::pair<LayoutCount, LayoutCount> transfer_shape(const HostCsr &P) {
 // unit-row layout when it applies (pointers, masks, per-slice counts, the explicit rows' entries), else lp's layout.
 template <class T>
 int64_t prolong_alloc_bytes(const HostCsr &P, const std::vector<int8_t> &cf, const LayoutCount &lp) {
-  if (choose_group(P.nr, lp.nnz) == 1) {
+  if (choose_group(P.nr, lp.nnz, (int)sizeof(T)) == 1) {
     const UnitRows u = unit_rows_of(P, cf);
     if (u.ok) {
       const int64_t ns = (int64_t)u.mask.size();

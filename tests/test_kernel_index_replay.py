@@ -637,6 +637,13 @@ def test_row_kernel_accesses_in_range(namg, case):
                 ref = sp.csr_matrix((v, ci, rp), shape=(len(rp) - 1, ncols)) @ x
                 np.testing.assert_allclose(yu, ref, rtol=1e-14, atol=1e-14)
                 assert np.array_equal(yu, y), (name, label, unroll)  # entry order kept: the plain layout's bits
+        if L.group > 1 and not fg:
+            # 8-byte values take SELL-64 from fewer rows on (choose_group): the same matrix one row per lane
+            L1 = Layout(np.asarray(rp), np.asarray(ci), np.asarray(v), ncols, 1)
+            y1, acc1 = replay_one_row_per_lane(L1, x)
+            assert acc1.bad_loads == 0 and acc1.bad_gathers == 0, (name, label, "SELL-64", acc1.bad_loads,
+                                                                  acc1.bad_gathers)
+            np.testing.assert_allclose(y1, y, rtol=1e-13, atol=1e-13)
         if L.group == 1:
             y2, acc2 = replay_two_rows_per_lane(L, x)
             assert acc2.bad_loads == 0 and acc2.bad_gathers == 0, (name, label, "two rows per lane",
