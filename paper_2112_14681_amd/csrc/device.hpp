@@ -429,8 +429,8 @@ inline UnitRows unit_rows_of(const HostCsr &P, const std::vector<int8_t> &cf) {
 //   NAMG_LANE_ENTRIES (8): CSR lane groups are sized so that a lane takes about this many entries;
 //   NAMG_LANE_ENTRIES_SMALL, NAMG_SMALL_ROWS (as NAMG_LANE_ENTRIES, 65536): the same for matrices of fewer
 //   rows, whose kernels are latency-bound (shorter chains per lane);
-//   NAMG_SELL_MIN_ROWS (524288; for 8-byte values NAMG_SELL_MIN_ROWS_FP64, 131072): a matrix with at least this
-//   many rows uses SELL-64 whatever its row length (one lane per row already fills the device);
+//   NAMG_SELL_MIN_ROWS (131072): a matrix with at least this many rows uses SELL-64 whatever its row
+//   length (one lane per row already fills the device);
 //   NAMG_WIDE_ROWS (off): SELL-64 matrices whose rows average more entries load them in chunks of eight;
 //   NAMG_UNIT_UNROLL (by row length): 4 or 8 entries per chunk for prolongations in the unit-row layout;
 //   NAMG_DIA (1): 0 keeps every matrix out of the slice-diagonal form.
@@ -438,8 +438,7 @@ struct LayoutTuning {
   int lane_entries = 8;
   int lane_entries_small = 8;            // the same for matrices of fewer than small_rows rows
   int64_t small_rows = int64_t(1) << 16;
-  int64_t sell_min_rows = int64_t(1) << 19;       // 4-byte values
-  int64_t sell_min_rows_fp64 = int64_t(1) << 17;  // 8-byte values
+  int64_t sell_min_rows = int64_t(1) << 17;
   double wide_rows = 1e9;
   int unit_unroll = 0;  // 0: by the F rows' average length
   bool dia = true;
@@ -451,9 +450,7 @@ inline const LayoutTuning &layout_tuning() {
     if (const char *e = std::getenv("NAMG_LANE_ENTRIES")) v.lane_entries = v.lane_entries_small = std::max(1, std::atoi(e));
     if (const char *e = std::getenv("NAMG_LANE_ENTRIES_SMALL")) v.lane_entries_small = std::max(1, std::atoi(e));
     if (const char *e = std::getenv("NAMG_SMALL_ROWS")) v.small_rows = std::max<int64_t>(1, std::atoll(e));
-    if (const char *e = std::getenv("NAMG_SELL_MIN_ROWS"))
-      v.sell_min_rows = v.sell_min_rows_fp64 = std::max<int64_t>(1, std::atoll(e));
-    if (const char *e = std::getenv("NAMG_SELL_MIN_ROWS_FP64")) v.sell_min_rows_fp64 = std::max<int64_t>(1, std::atoll(e));
+    if (const char *e = std::getenv("NAMG_SELL_MIN_ROWS")) v.sell_min_rows = std::max<int64_t>(1, std::atoll(e));
     if (const char *e = std::getenv("NAMG_WIDE_ROWS")) v.wide_rows = std::atof(e);
     if (const char *e = std::getenv("NAMG_UNIT_UNROLL")) v.unit_unroll = std::atoi(e) == 8 ? 8 : 4;
     if (const char *e = std::getenv("NAMG_DIA")) v.dia = std::atoi(e) != 0;
@@ -468,15 +465,15 @@ inline int choose_unroll(int group, int64_t nrows, int64_t nnz) {
   return group == 1 && nrows > 0 && (double)nnz > layout_tuning().wide_rows * (double)nrows ? 8 : 4;
 }
 
-// Lanes per row for a matrix with the given shape and value size: one lane when rows are short or the matrix
-// is large enough to fill the device with one lane per row (NAMG_SELL_MIN_ROWS rows, fewer for 8-byte values:
-// there one row per lane of a 175 K-row, 34-entry level measured 0.25 ms per solve faster than lane groups,
-// while 4-byte values, two rows per lane, were 0.12 ms slower); otherwise a power of two up to 64 that gives
-// each lane about NAMG_LANE_ENTRIES entries.
-inline int choose_group(int64_t nrows, int64_t nnz, int val_bytes) {
+// Lanes per row for a matrix with the given shape: one lane when rows are short or the matrix is large enough
+// to fill the device with one lane per row (NAMG_SELL_MIN_ROWS rows: at C2 one row per lane of the 175 K-row,
+// 34-entry level 2 measured 0.25 ms per FP64 solve and 0.1 ms per FP32 solve faster than lane groups; from
+// 16 K rows down it was slower); otherwise a power of two up to 64 that gives each lane about
+// NAMG_LANE_ENTRIES entries.
+inline int choose_group(int64_t nrows, int64_t nnz) {
   const LayoutTuning &t = layout_tuning();
   const double avg = nrows > 0 ? (double)nnz / (double)nrows : 0.0;
-  if (avg <= 10.0 || nrows >= (val_bytes >= 8 ? t.sell_min_rows_fp64 : t.sell_min_rows)) return 1;
+  if (avg <= 10.0 || nrows >= t.sell_min_rows) return 1;
   const int per_lane = nrows < t.small_rows ? t.lane_entries_small : t.lane_entries;
   int g = 2;
   while (g < 64 && g * per_lane < avg) g <<= 1;
@@ -566,7 +563,7 @@ struct LayoutCount {
   // buffers (pointers, column indices or slot offsets, values) allocates
   template <class T>
   int64_t bytes(int32_t nr, int force_group = 0) const {
-    const int group = force_group > 0 ? force_group : choose_group(nr, nnz, (int)sizeof(T));
+    const int group = force_group > 0 ? force_group : choose_group(nr, nnz);
     const int64_t ib = narrow ? 2 : 4;
     if (group > 1) return alloc_bytes((int64_t)nr + 1, 4) + alloc_bytes(nnz, ib) + alloc_bytes(nnz, sizeof(T));
     const int64_t nslices = ((int64_t)nr + SELL_C - 1) / SELL_C;
@@ -679,7 +676,7 @@ struct DMat {
     nnz = A.nnz();
     mul = diag_mul(nrows, ncols);
     narrow = fits_col16(A);
-    group = force_group > 0 ? force_group : choose_group(nrows, nnz, (int)sizeof(T));
+    group = force_group > 0 ? force_group : choose_group(nrows, nnz);
     unroll = choose_unroll(group, nrows, nnz);
     unit = false;
     unit_pairs = false;

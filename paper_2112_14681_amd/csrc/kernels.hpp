@@ -138,35 +138,6 @@ __device__ __forceinline__ void dia_slots(const TM *__restrict__ vp, const int32
   for (int u = 0; u < K; ++u) acc = mul_add((Acc)v[u], (Acc)xv[u], acc);
 }
 
-// The same for two rows (of bases b0 and b1, in one slice and the next) whose slices both have slots
-// j .. j + K - 1.
-template <int K, class Acc, class TM, class TX>
-__device__ __forceinline__ void dia_slots2(const TM *__restrict__ vp0, const int32_t *__restrict__ off0,
-                                           const TM *__restrict__ vp1, const int32_t *__restrict__ off1,
-                                           const TX *__restrict__ x, int32_t b0, int32_t b1, int32_t cmax, int32_t j,
-                                           Acc &a0, Acc &a1) {
-  int32_t o0[K], o1[K];
-  TM v0[K], v1[K];
-  TX x0[K], x1[K];
-#pragma unroll
-  for (int u = 0; u < K; ++u) {
-    o0[u] = off0[j + u];
-    o1[u] = off1[j + u];
-  }
-#pragma unroll
-  for (int u = 0; u < K; ++u) {
-    v0[u] = vp0[(int64_t)(j + u) * SELL_C];
-    v1[u] = vp1[(int64_t)(j + u) * SELL_C];
-    x0[u] = x[min(max(b0 + o0[u], 0), cmax)];
-    x1[u] = x[min(max(b1 + o1[u], 0), cmax)];
-  }
-#pragma unroll
-  for (int u = 0; u < K; ++u) {
-    a0 = mul_add((Acc)v0[u], (Acc)x0[u], a0);
-    a1 = mul_add((Acc)v1[u], (Acc)x1[u], a1);
-  }
-}
-
 // Slots j .. w - 1 of one row: chunks of eight, then one chunk of exactly the rest (a wave-uniform switch), so
 // no slot past the slice's end is loaded and a row of w slots waits on ceil(w / 8) rounds of loads.
 template <class Acc, class TM, class TX>
@@ -198,42 +169,6 @@ __device__ __forceinline__ Acc dia_dot(const MatView<TM> &A, const TX *__restric
   return acc;
 }
 
-// Rows r0 and r0 + 64 (the same lane of slices s and s + 1): the slots both slices have go together, in
-// chunks of eight and one exact rest; the longer slice's further slots (slices at the matrix's faces) follow
-// for its row alone. Slice s + 1 may not exist (then only row r0 is summed).
-template <class Acc, class TM, class TX>
-__device__ __forceinline__ void dia_dot2(const MatView<TM> &A, const TX *__restrict__ x, int32_t r0, Acc &a0,
-                                         Acc &a1) {
-  const int32_t s0 = __builtin_amdgcn_readfirstlane(r0 >> 6), lane = r0 & 63;
-  const bool two = (s0 + 1) * SELL_C < A.nrows;  // uniform
-  const int32_t p0 = A.ptr[s0], p1 = A.ptr[s0 + 1];
-  const int32_t p2 = two ? A.ptr[s0 + 2] : p1;
-  const int32_t w0 = (p1 - p0) >> 6, w1 = (p2 - p1) >> 6;
-  const TM *__restrict__ vp0 = A.val + p0 + lane;
-  const TM *__restrict__ vp1 = A.val + p1 + lane;
-  const int32_t *__restrict__ off0 = A.dia + 1 + (p0 >> 6);
-  const int32_t *__restrict__ off1 = A.dia + 1 + (p1 >> 6);
-  const int32_t cmax = A.dia[0];
-  const int32_t b0 = diag_base(r0, A.mul), b1 = diag_base(r0 + SELL_C, A.mul);
-  a0 = Acc(0);
-  a1 = Acc(0);
-  const int32_t wm = min(w0, w1);
-  int32_t j = 0;
-  for (; j + 8 <= wm; j += 8) dia_slots2<8>(vp0, off0, vp1, off1, x, b0, b1, cmax, j, a0, a1);
-  switch (wm - j) {
-    case 7: dia_slots2<7>(vp0, off0, vp1, off1, x, b0, b1, cmax, j, a0, a1); break;
-    case 6: dia_slots2<6>(vp0, off0, vp1, off1, x, b0, b1, cmax, j, a0, a1); break;
-    case 5: dia_slots2<5>(vp0, off0, vp1, off1, x, b0, b1, cmax, j, a0, a1); break;
-    case 4: dia_slots2<4>(vp0, off0, vp1, off1, x, b0, b1, cmax, j, a0, a1); break;
-    case 3: dia_slots2<3>(vp0, off0, vp1, off1, x, b0, b1, cmax, j, a0, a1); break;
-    case 2: dia_slots2<2>(vp0, off0, vp1, off1, x, b0, b1, cmax, j, a0, a1); break;
-    case 1: dia_slots2<1>(vp0, off0, vp1, off1, x, b0, b1, cmax, j, a0, a1); break;
-    default: break;
-  }
-  if (w0 > wm) dia_row_from(vp0, off0, x, b0, cmax, wm, w0, a0);
-  if (w1 > wm) dia_row_from(vp1, off1, x, b1, cmax, wm, w1, a1);
-}
-
 template <int G, class Acc, int U = 4, class TM, class TX>
 __device__ __forceinline__ Acc row_dot(const MatView<TM> &A, const TX *__restrict__ x, int32_t row, int sub) {
   if constexpr (G == 1) {
@@ -243,116 +178,32 @@ __device__ __forceinline__ Acc row_dot(const MatView<TM> &A, const TX *__restric
   return row_dot_impl<G, false, U, Acc>(A, x, row, sub);
 }
 
-// SELL-64 rows r0 and r0 + 64 (the same lane of two adjacent slices) of one thread, interleaved so that
-// both rows' loads are in flight together. Each row's sum is row_dot's in-order sum. has1: row r0 + 64
-// exists. There is no branch between the loads (a branch would make the compiler wait for every load
-// issued before it): a slot past its row's end loads an in-bounds entry of the chunk, gathers from a
-// valid column (an existing row's base, or column 0) and is not added.
-template <bool NARROW, int U, class Acc, class TM, class TX>
-__device__ __forceinline__ void sell_dot2_impl(const MatView<TM> &A, const TX *__restrict__ x, int32_t r0, bool has1,
-                                               Acc &a0, Acc &a1) {
-  const int32_t s0 = r0 >> 6, lane = r0 & 63;
-  int32_t k0 = A.ptr[s0] + lane;
-  const int32_t e0 = A.ptr[s0 + 1];
-  int32_t k1 = 0, e1 = 0;
-  if (has1) {
-    k1 = e0 + lane;
-    e1 = A.ptr[s0 + 2];
-  }
-  // the column an inactive slot gathers from: its row's base, which is < ncols for an existing row; a lane
-  // without a second row uses the first row's base (the second row's would lie past the end of x)
-  const int32_t b0 = NARROW ? diag_base(r0, A.mul) : 0;
-  const int32_t b1 = NARROW ? diag_base(has1 ? r0 + SELL_C : r0, A.mul) : 0;
-  a0 = Acc(0);
-  a1 = Acc(0);
-  while (k0 < e0 || k1 < e1) {
-    const int32_t kb0 = k0 < e0 ? k0 : k1;  // an entry of this chunk that exists
-    const int32_t kb1 = k1 < e1 ? k1 : k0;
-    bool ok0[U], ok1[U];
-    int32_t c0[U], c1[U];
-    TM v0[U], v1[U];
-    TX x0[U], x1[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      ok0[u] = k0 + u * SELL_C < e0;
-      ok1[u] = k1 + u * SELL_C < e1;
-      const int32_t kk0 = ok0[u] ? k0 + u * SELL_C : kb0;
-      const int32_t kk1 = ok1[u] ? k1 + u * SELL_C : kb1;
-      int32_t q0, q1;
-      if constexpr (NARROW) {
-        q0 = b0 + (int32_t)A.col16[kk0];
-        q1 = b1 + (int32_t)A.col16[kk1];
-      } else {
-        q0 = A.col[kk0];
-        q1 = A.col[kk1];
-      }
-      c0[u] = ok0[u] ? q0 : b0;
-      c1[u] = ok1[u] ? q1 : b1;
-      v0[u] = A.val[kk0];
-      v1[u] = A.val[kk1];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      x0[u] = x[c0[u]];
-      x1[u] = x[c1[u]];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (ok0[u]) a0 = mul_add((Acc)v0[u], (Acc)x0[u], a0);
-      if (ok1[u]) a1 = mul_add((Acc)v1[u], (Acc)x1[u], a1);
-    }
-    k0 += U * SELL_C;
-    k1 += U * SELL_C;
-  }
-}
-
-// The rows one thread of a row kernel computes. SELL-64 (G == 1) with 4-byte values: two rows, r and
-// r + 64, the same lane of a pair of adjacent slices (block lb covers rows [512 lb, 512 lb + 512);
-// wavefront w takes slices 2w and 2w + 1 of the block), so that each lane keeps two independent load
-// chains in flight. SELL-64 with 8-byte values: one row per lane (its loads are wide enough; measured
-// faster). CSR lane groups (G > 1): lane `sub` of the group of one row.
+// The row one thread of a row kernel computes: SELL-64 (G == 1), one row per lane; CSR lane groups (G > 1),
+// lane `sub` of the group of one row. (Two rows per lane, the same lane of two adjacent slices, measured
+// slower once the slice-diagonal form and SELL-64 for the 175 K-row level were in place: 4.62-4.68 against
+// 4.55-4.56 ms per FP32 C2 solve, 4.47 with SELL-64 from 2^17 rows.) R is kept as the bodies' row count.
 template <int G, class TM>
 struct ThreadRows {
-  static constexpr int R = (G == 1 && sizeof(TM) == 4) ? 2 : 1;
+  static constexpr int R = 1;
   int32_t row[R];
   bool ok[R];
   int sub;
   __device__ __forceinline__ ThreadRows(uint32_t lb, int32_t nrows) {
-    if constexpr (R == 2) {
-      row[0] = (int32_t)lb * (2 * BLK) + (int32_t)(threadIdx.x >> 6) * (2 * SELL_C) + (int32_t)(threadIdx.x & 63);
-      row[1] = row[0] + SELL_C;
-      ok[0] = row[0] < nrows;
-      ok[1] = row[1] < nrows;
-      sub = 0;
-    } else {
-      const int64_t g = (int64_t)lb * BLK + threadIdx.x;
-      row[0] = (int32_t)(g / G);
-      sub = (int)(g % G);
-      ok[0] = row[0] < nrows;
-    }
+    const int64_t g = (int64_t)lb * BLK + threadIdx.x;
+    row[0] = (int32_t)(g / G);
+    sub = (int)(g % G);
+    ok[0] = row[0] < nrows;
   }
 };
 
-// Blocks of a row kernel over nrows rows with `group` lanes per row and val_bytes-byte matrix values.
-inline unsigned row_blocks(int64_t nrows, int group, int val_bytes) {
-  if (group == 1 && val_bytes == 4) return (unsigned)((nrows + 2 * BLK - 1) / (2 * BLK));
-  return blocks_for(nrows * group);
-}
+// Blocks of a row kernel over nrows rows with `group` lanes per row.
+inline unsigned row_blocks(int64_t nrows, int group) { return blocks_for(nrows * group); }
 
 // The row sums of this thread's rows (every lane of a CSR group gets its row's full sum).
 template <int G, class Acc, int U = 4, class TM, class TX>
 __device__ __forceinline__ void row_dots(const MatView<TM> &A, const TX *__restrict__ x, const ThreadRows<G, TM> &t,
                                          Acc (&out)[ThreadRows<G, TM>::R]) {
-  if constexpr (ThreadRows<G, TM>::R == 2) {
-    if (A.dia)
-      dia_dot2<Acc>(A, x, t.row[0], out[0], out[1]);
-    else if (A.col16)
-      sell_dot2_impl<true, U, Acc>(A, x, t.row[0], t.ok[1], out[0], out[1]);
-    else
-      sell_dot2_impl<false, U, Acc>(A, x, t.row[0], t.ok[1], out[0], out[1]);
-  } else {
-    out[0] = row_dot<G, Acc, U>(A, x, t.row[0], t.sub);
-  }
+  out[0] = row_dot<G, Acc, U>(A, x, t.row[0], t.sub);
 }
 
 // ---------------------------------------------------------------------------------------- row bodies
@@ -439,7 +290,7 @@ __device__ __forceinline__ void neumann_body(uint32_t lb, const MatView<T> &S, c
 }
 
 // x += P e for P in the unit-row SELL layout (device.hpp, UnitRows), on the rows of ThreadRows<1, T> (one
-// row per lane in FP64, rows r and r + 64 in FP32). A C point's row adds e[c], c = the C points before it,
+// row per lane). A C point's row adds e[c], c = the C points before it,
 // as a virtual first entry of value 1 (0 + 1 * e[c] is e[c] exactly); an F row of rank l among its slice's m
 // F rows sums the slots ptr[s] + l, ptr[s] + l + m, ... (padding: value 0 at a valid column) in order. Both
 // go through one loop: entries in chunks of U, every index and value load of a chunk issued before its

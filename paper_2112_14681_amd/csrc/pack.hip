@@ -313,7 +313,7 @@ void pack_device(DMat<T> &M, const DCsr &D, MemCounter *mc, int force_group, con
   int32_t hbad = 0;
   hip_check(hipMemcpy(&hbad, bad.get(), 4, hipMemcpyDeviceToHost), "hipMemcpy D2H");
   M.narrow = hbad == 0;
-  M.group = force_group > 0 ? force_group : choose_group(M.nrows, M.nnz, (int)sizeof(T));
+  M.group = force_group > 0 ? force_group : choose_group(M.nrows, M.nnz);
   M.unroll = choose_unroll(M.group, M.nrows, M.nnz);
   if (unit && unit->ok && M.group == 1) {
     pack_unit_device(M, D, *unit, mc);

@@ -114,7 +114,7 @@ inline std::pair<LayoutCount, LayoutCount> transfer_shape(const HostCsr &P) {
 // unit-row layout when it applies (pointers, masks, per-slice counts, the explicit rows' entries), else lp's layout.
 template <class T>
 int64_t prolong_alloc_bytes(const HostCsr &P, const std::vector<int8_t> &cf, const LayoutCount &lp) {
-  if (choose_group(P.nr, lp.nnz, (int)sizeof(T)) == 1) {
+  if (choose_group(P.nr, lp.nnz) == 1) {
     const UnitRows u = unit_rows_of(P, cf);
     if (u.ok) {
       const int64_t ns = (int64_t)u.mask.size();
@@ -229,7 +229,7 @@ class BatchEngine {
         KTask<T> k = base(sl);
         k.zin = sl->sv->Z_.get() + (int64_t)sl->i * sl->sv->ldz_;
         t.push_back(k);
-        nb.push_back(row_blocks(sl->n, 1, 8));
+        nb.push_back(row_blocks(sl->n, 1));
         sl->alg += sl->sv->A64_.bytes() + (sizeof(T) + 8.0) * sl->n;
       }
       add_krylov(KOP_SPMV64, t, nb);

@@ -131,7 +131,7 @@ int32_t mat_form(const MatView<T> &M) {
 template <class T>
 unsigned rows_grid(const DMat<T> &M) {
   if (M.unit && M.unit_pairs) return (unsigned)((M.nrows + UNIT_BLOCK_ROWS - 1) / UNIT_BLOCK_ROWS);
-  return row_blocks(M.nrows, M.group, (int)sizeof(T));
+  return row_blocks(M.nrows, M.group);
 }
 }  // namespace
 
@@ -862,7 +862,7 @@ class Solver final : public SolverBase {
     const DevLevel<T> &L = lv_[l];
     const int32_t n = L.n;
     const double bytes = (x ? L.A.bytes() + S * n : 0.0) + S * n * (1 + (r ? 1 : 0) + (f ? 2 : 0));
-    const unsigned grid = x ? rows_grid(L.A) : row_blocks(n, 1, (int)sizeof(T));
+    const unsigned grid = x ? rows_grid(L.A) : row_blocks(n, 1);
     emit(row_op(ROP_RESIDUAL, NAMG_KF_RESIDUAL, l, L.A.view(), x ? L.A.group : 1, grid, bytes, b, x, d, nullptr, r, f,
                 n),
          s);

@@ -1,6 +1,6 @@
 """CPU replay of the row kernels' memory accesses on the exact device layouts (no GPU).
 
-The sparse row kernels (SELL-64 with one or two rows per lane, CSR with G lanes per row) issue their
+The sparse row kernels (SELL-64 with one row per lane, CSR with G lanes per row) issue their
 index, value and gather loads before they know which slots of a chunk are real entries, so every slot
 must point at valid memory. This module restates the layouts the library packs (slices of 64 rows padded
 to their longest row, 16-bit column offsets from a scaled diagonal when every column fits, lane groups
@@ -14,12 +14,13 @@ on the matrices of real hierarchies that
   * the prolongations' unit-row layout (a C point's row stores no entry) loads and gathers in range and
     gives the plain layout's bits;
   * the slice-diagonal layout (one column offset per slot of 64 rows, no per-entry columns) is chosen where
-    the library's rule takes it, reads its offsets, values and gathers in range with one and with two rows
-    per lane (chunks of eight slots and one exact rest), and gives the plain layout's bits.
+    the library's rule takes it, reads its offsets, values and gathers in range (chunks of eight slots and
+    one exact rest), and gives the plain layout's bits;
+  * both forms of the unit-row prolongation kernel (one lane per row; a wavefront per pair of slices, F
+    rows first) load, gather and write in range and give the same bits.
 
-A model of the two-rows-per-lane kernel with the base column of a lane's second row taken even when the
-lane has no second row (an earlier form of that kernel) must show an out-of-range gather on the ragged
-last slice, so the replay can tell the two apart.
+A model of the unit-row kernel that reads the layout as plain SELL-64 (its masks not reaching the kernel)
+must show out-of-range gathers, so the replay can tell the two apart.
 """
 import numpy as np
 import pytest
@@ -50,7 +51,7 @@ def diag_base(rows, mul):
     return (rows.astype(np.int64) * mul) >> COL_SHIFT
 
 
-def choose_group(nrows, nnz, lane_entries=8, sell_min_rows=1 << 19):
+def choose_group(nrows, nnz, lane_entries=8, sell_min_rows=1 << 17):
     avg = nnz / nrows if nrows > 0 else 0.0
     if avg <= 10.0 or nrows >= sell_min_rows:
         return 1
@@ -249,55 +250,6 @@ def replay_dia_exact(L, x):
                 part = part + v * a.gather(x, np.clip(diag_base(rows, L.mul) + o, 0, cmax))
         acc[rows] = part
     return acc, a
-
-
-def replay_dia_exact_two_rows(L, x):
-    """dia_dot2 in its exact-chunk form: the slots both slices have go together (rows r0 of slice s and r0 + 64
-    of slice s + 1, all 64 lanes of each, past-the-end rows included), then the longer slice's rest alone."""
-    a = DiaAccess(L)
-    cmax = int(a.offset(np.array([0]))[0])
-    out = np.zeros(L.nrows)
-    nsl = len(L.ptr) - 1
-    lane = np.arange(SELL_C, dtype=np.int64)
-    for s0 in range(0, nsl, 2):
-        two = (s0 + 1) * SELL_C < L.nrows
-        p0, p1 = int(L.ptr[s0]), int(L.ptr[s0 + 1])
-        p2 = int(L.ptr[s0 + 2]) if two else p1
-        w0, w1 = (p1 - p0) >> 6, (p2 - p1) >> 6
-        r0 = s0 * SELL_C + lane
-        r1 = r0 + SELL_C
-        a0, a1 = np.zeros(SELL_C), np.zeros(SELL_C)
-
-        def slots(p, r, part, j0, w):
-            for j, k in _dia_exact_chunks(w - j0):
-                for u in range(k):
-                    q = j0 + j + u
-                    o = int(a.offset(np.array([1 + (p >> 6) + q]))[0])
-                    v = a.value(p + q * SELL_C + lane)
-                    part = part + v * a.gather(x, np.clip(diag_base(r, L.mul) + o, 0, cmax))
-            return part
-
-        wm = min(w0, w1)
-        for j, k in _dia_exact_chunks(wm):  # joint part: the two rows' products interleave, each in slot order
-            for u in range(k):
-                q = j + u
-                for p, r, which in ((p0, r0, 0), (p1, r1, 1)):
-                    o = int(a.offset(np.array([1 + (p >> 6) + q]))[0])
-                    v = a.value(p + q * SELL_C + lane)
-                    prod = v * a.gather(x, np.clip(diag_base(r, L.mul) + o, 0, cmax))
-                    if which == 0:
-                        a0 = a0 + prod
-                    else:
-                        a1 = a1 + prod
-        if w0 > wm:
-            a0 = slots(p0, r0, a0, wm, w0)
-        if w1 > wm:
-            a1 = slots(p1, r1, a1, wm, w1)
-        keep0 = r0 < L.nrows
-        out[r0[keep0]] = a0[keep0]
-        keep1 = r1 < L.nrows
-        out[r1[keep1]] = a1[keep1]
-    return out, a
 
 
 def replay_prolong_unit_rows(L, e, U=U):
@@ -505,58 +457,6 @@ def replay_one_row_per_lane(L, x):
     return acc_all, a
 
 
-def replay_two_rows_per_lane(L, x, second_base_always=False):
-    """SELL-64 with two rows per lane (4-byte values): sell_dot2_impl. Block lb covers rows
-    [512 lb, 512 lb + 512); wavefront w takes slices 2w and 2w + 1 of the block."""
-    a = Access(L)
-    nblocks = (L.nrows + 2 * BLK - 1) // (2 * BLK)
-    tid = np.arange(BLK, dtype=np.int64)
-    lb = np.repeat(np.arange(nblocks, dtype=np.int64), BLK)
-    t = np.tile(tid, nblocks)
-    r0 = lb * (2 * BLK) + (t >> 6) * (2 * SELL_C) + (t & 63)
-    live = r0 < L.nrows
-    r0 = r0[live]
-    has1 = r0 + SELL_C < L.nrows
-    s0, lane = r0 >> 6, r0 & 63
-    k0 = L.ptr[s0] + lane
-    e0 = L.ptr[s0 + 1]
-    k1 = np.where(has1, e0 + lane, 0)
-    e1 = np.where(has1, L.ptr[np.minimum(s0 + 2, len(L.ptr) - 1)], 0)
-    if L.narrow:
-        b0 = diag_base(r0, L.mul)
-        second = r0 + SELL_C if second_base_always else np.where(has1, r0 + SELL_C, r0)
-        b1 = diag_base(second, L.mul)
-    else:
-        b0 = b1 = np.zeros_like(r0)
-    a0, a1 = np.zeros(r0.size), np.zeros(r0.size)
-    while True:
-        act = (k0 < e0) | (k1 < e1)
-        if not act.any():
-            break
-        kb0 = np.where(k0 < e0, k0, k1)
-        kb1 = np.where(k1 < e1, k1, k0)
-        for u in range(U):
-            ok0 = act & (k0 + u * SELL_C < e0)
-            ok1 = act & (k1 + u * SELL_C < e1)
-            kk0 = np.where(ok0, k0 + u * SELL_C, kb0)[act]
-            kk1 = np.where(ok1, k1 + u * SELL_C, kb1)[act]
-            i0, v0 = a.load(kk0)
-            i1, v1 = a.load(kk1)
-            q0 = b0[act] + i0 if L.narrow else i0
-            q1 = b1[act] + i1 if L.narrow else i1
-            c0 = np.where(ok0[act], q0, b0[act])
-            c1 = np.where(ok1[act], q1, b1[act])
-            x0, x1 = a.gather(x, c0), a.gather(x, c1)
-            a0[act] = np.where(ok0[act], a0[act] + v0 * x0, a0[act])
-            a1[act] = np.where(ok1[act], a1[act] + v1 * x1, a1[act])
-        k0 = k0 + U * SELL_C
-        k1 = k1 + U * SELL_C
-    out = np.zeros(L.nrows)
-    out[r0] = a0
-    out[r0[has1] + SELL_C] = a1[has1]
-    return out, a
-
-
 # -------------------------------------------------------------------------------- the matrices
 def strict_part(rp, ci, vals, lower):
     rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
@@ -644,11 +544,6 @@ def test_row_kernel_accesses_in_range(namg, case):
             assert acc1.bad_loads == 0 and acc1.bad_gathers == 0, (name, label, "SELL-64", acc1.bad_loads,
                                                                   acc1.bad_gathers)
             np.testing.assert_allclose(y1, y, rtol=1e-13, atol=1e-13)
-        if L.group == 1:
-            y2, acc2 = replay_two_rows_per_lane(L, x)
-            assert acc2.bad_loads == 0 and acc2.bad_gathers == 0, (name, label, "two rows per lane",
-                                                                   acc2.bad_loads, acc2.bad_gathers)
-            assert np.array_equal(y2, y), (name, label)
         if cf is None:  # every operator but the prolongations (whose unit-row layout comes first)
             D = DiaLayout(rp, ci, v, ncols)
             for vb in (4, 8):
@@ -658,28 +553,12 @@ def test_row_kernel_accesses_in_range(namg, case):
                 ye, ae = replay_dia_exact(D, x)
                 assert ae.clean(), (name, label, "slice-diagonal exact chunks, one row", ae.bad)
                 assert np.array_equal(ye, y), (name, label, "exact")  # the plain layout's bits (up to the sign of 0)
-                ye2, ae2 = replay_dia_exact_two_rows(D, x)
-                assert ae2.clean(), (name, label, "slice-diagonal exact chunks, two rows", ae2.bad)
-                assert np.array_equal(ye2, y), (name, label, "exact, two rows")
     # the natural-order stencils take the form on level 0 (A, its strict parts, its FP64 copy); a random
     # relabelling scatters the offsets and keeps SELL-64
     if name.startswith("permuted"):
         assert not any(lbl.startswith("A0") for lbl in dia_used), dia_used
     else:
         assert {"A0", "A0 fp64", "A0 lower", "A0 upper"} <= dia_used, dia_used
-
-
-def test_replay_detects_second_row_base_past_the_end():
-    """On a ragged last slice (the row count not a multiple of 128) the earlier form of the two-rows kernel
-    gathers up to 64 columns past the end of x for lanes without a second row; the current form does not."""
-    A = varcoef3d(33, 0.5, 1001)[0]  # 35 937 rows: the last block has lanes without a second row
-    L = Layout(A.rowptr, A.colind, A.vals, A.n)
-    assert L.group == 1 and L.narrow and A.n % 128 != 0
-    x = np.random.default_rng(0).standard_normal(A.n)
-    _, old = replay_two_rows_per_lane(L, x, second_base_always=True)
-    _, new = replay_two_rows_per_lane(L, x)
-    assert old.bad_gathers > 0
-    assert new.bad_gathers == 0 and new.bad_loads == 0
 
 
 def test_unit_layout_needs_its_masks():
