@@ -68,7 +68,7 @@ PROFILE_EVERY = 3  # time every 3rd run of consecutive dominant-kernel dispatche
 # Measured HBM traffic of the dominant kernel (bytes per launch): rocprofv3 FETCH_SIZE x 2.000 plus
 # WRITE_SIZE x 1.000, factors from a 2 GiB copy (profiles/k_neumann_level0_c2_128cubed_traffic.md).
 # Valid for the kernel version it was taken on; None when the kernel has changed since.
-DOMINANT_TRAFFIC_BYTES = {("c2", 128, "fp64", "ilu0"): 109.79e6, ("c2", 128, "fp32", "ilu0"): 56.52e6}
+DOMINANT_TRAFFIC_BYTES = {("c2", 128, "fp64", "ilu0"): 109.79e6, ("c2", 128, "fp32", "ilu0"): None}
 
 
 def copy_ceiling(torch, nbytes=2 << 30, reps=10):
@@ -498,7 +498,8 @@ def main():
                            "traffic": traffic,
                            # measured HBM bytes per launch over the same live time: what the memory system moved
                            "traffic_GBps": round(traffic / (per_launch_ms * 1e-3) / 1e9, 1) if traffic else None,
-                           "kernel": f"k_neumann<1,{'double' if prec == namg.FP64 else 'float'}> on level 0 "
+                           "kernel": ("k_neumann<1,double>" if prec == namg.FP64 or os.environ.get("NAMG_DIA_PAIRS") == "0"
+                                      else "k_neumann_pairs (FP32, two rows per lane)") + " on level 0 "
                                      f"({'ILU(0)' if args.smoother == 'ilu0' else 'poly-GS'} Neumann term)",
                            "launches_timed": prof["launches"],
                            "timing": f"hipEvents around every {PROFILE_EVERY}th run of consecutive dispatches",

@@ -13,6 +13,7 @@
 #include <iterator>
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <string>
 #include <utility>
 #include <vector>
@@ -375,6 +376,7 @@ struct MatView {
   int32_t nrows = 0;
   int32_t ncols = 0;   // set by DMat::view (and for the prolongation kernels)
   int32_t unroll = 4;  // unit-row layout: entries per chunk of the prolongation loop (4 or 8)
+  bool pairs = false;  // the host launches this matrix's Neumann terms as k_neumann_pairs (set by DMat::view)
 };
 
 // Unit rows of a prolongation. The row of a C point is the unit vector of its coarse index (one entry of
@@ -442,6 +444,11 @@ struct LayoutTuning {
   double wide_rows = 1e9;
   int unit_unroll = 0;  // 0: by the F rows' average length
   bool dia = true;
+  // two rows per lane (DMat::pairs_ok) for triangles of at most this many slots per slice on average: at C2
+  // in FP32 the level-0 triangles (3 slots) gain 11.6 -> 10.5 us per term; the level-1 triangles (about 10)
+  // lose, and with them the solve reads 4.66-4.67 ms against 4.51-4.54 with one row per lane and 4.44-4.47
+  // with this bound
+  double dia_pairs_maxw = 4.0;
 };
 
 inline const LayoutTuning &layout_tuning() {
@@ -454,9 +461,17 @@ inline const LayoutTuning &layout_tuning() {
     if (const char *e = std::getenv("NAMG_WIDE_ROWS")) v.wide_rows = std::atof(e);
     if (const char *e = std::getenv("NAMG_UNIT_UNROLL")) v.unit_unroll = std::atoi(e) == 8 ? 8 : 4;
     if (const char *e = std::getenv("NAMG_DIA")) v.dia = std::atoi(e) != 0;
+    if (const char *e = std::getenv("NAMG_DIA_PAIRS_MAXW")) v.dia_pairs_maxw = std::atof(e);
     return v;
   }();
   return t;
+}
+
+// FP32 Neumann terms on square slice-diagonal triangles with two rows per lane (k_neumann_pairs): on unless
+// NAMG_DIA_PAIRS=0, read each time a matrix is laid out, so that one process can hold both forms.
+inline bool dia_pairs_enabled() {
+  const char *e = std::getenv("NAMG_DIA_PAIRS");
+  return !e || std::atoi(e) != 0;
 }
 
 // Entries per chunk of the row kernels for a matrix in the given layout: 8 for a SELL-64 matrix whose rows
@@ -632,6 +647,7 @@ struct DMat {
   bool unit = false;  // the unit-row SELL layout (prolongations, see UnitRows)
   bool unit_pairs = false;  // its kernel in the pair form (unit_pairs_for)
   bool dia = false;   // the slice-diagonal SELL layout (see LayoutCount)
+  bool pairs_ok = false;  // dia_pairs_enabled() when the matrix was laid out
   int unroll = 4;     // entries per chunk of the row kernels (choose_unroll; unit-row layout: see view())
   DevBuf<int32_t> ptr, col;
   DevBuf<int16_t> col16;
@@ -655,6 +671,10 @@ struct DMat {
                                                    : (explicit_nnz > 4 * explicit_rows ? 8 : 4)) |
                           (unit_pairs ? UNIT_PAIRS : 0)
                     : unroll;
+    // two rows per lane for FP32 square slice-diagonal matrices (k_neumann_pairs)
+    const int64_t nslices = ((int64_t)nrows + SELL_C - 1) / SELL_C;
+    v.pairs = dia && std::is_same<T, float>::value && nrows == ncols && ncols >= 2 && pairs_ok &&
+              (double)stored <= layout_tuning().dia_pairs_maxw * SELL_C * (double)nslices;
     return v;
   }
   // algorithmic bytes of one pass over the matrix (entries once, row/slice pointers once; in the unit-row
@@ -681,6 +701,7 @@ struct DMat {
     unit = false;
     unit_pairs = false;
     dia = false;
+    pairs_ok = dia_pairs_enabled();
     if (unit_cf && group == 1) {
       const UnitRows u = unit_rows_of(A, *unit_cf);
       if (u.ok) {

@@ -587,6 +587,123 @@ __global__ __launch_bounds__(BLK) void k_neumann(NAMG_MAT_HEAD(T), const T *__re
   neumann_body<G, T, U>(blockIdx.x, NAMG_MAT_VIEW(T), f, in, scale, acc, out);
 }
 
+// ------------------------------------------------- one Neumann term, FP32 slice-diagonal, two rows per lane
+
+// In a slice-diagonal matrix rows 2h and 2h + 1 of a slice keep their values side by side in every slot
+// (ptr[s] + 64 k + 2h and + 1). K slots j .. j + K - 1 of that pair: the offsets o (one merged scalar load
+// per slice; the lane takes its half-wavefront's slice), one 8-byte value load, and the two gathers
+// x[r + o] and x[r + 1 + o] as one 8-byte load at the pair's first column clamped into [0, cmax - 1], from
+// which the select below gives in[clamp(r + o)] and in[clamp(r + 1 + o)] exactly (clamp to [0, cmax]).
+template <int K>
+__device__ __forceinline__ void dia_pair_slots(const float *__restrict__ vp, const int32_t *__restrict__ offA,
+                                               const int32_t *__restrict__ offB, bool second,
+                                               const float *__restrict__ x, int32_t r, int32_t cmax, int32_t j,
+                                               float &acc0, float &acc1) {
+  typedef float pair_u __attribute__((ext_vector_type(2), aligned(4)));
+  int32_t oa[K], ob[K];
+  float2 v[K];
+  pair_u g[K];
+  int32_t c[K];
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    oa[u] = offA[j + u];
+    ob[u] = offB[j + u];
+  }
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    c[u] = r + (second ? ob[u] : oa[u]);
+    v[u] = *reinterpret_cast<const float2 *>(vp + (int64_t)(j + u) * SELL_C);
+    g[u] = *reinterpret_cast<const pair_u *>(x + min(max(c[u], 0), cmax - 1));
+  }
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    acc0 = mul_add(v[u].x, c[u] >= cmax ? g[u].y : g[u].x, acc0);
+    acc1 = mul_add(v[u].y, c[u] < 0 ? g[u].x : g[u].y, acc1);
+  }
+}
+
+// One Neumann term out = [acc +] [scale .*] (f - S in), as k_neumann, on a square slice-diagonal FP32
+// triangle with at least two columns: a wavefront takes slices 2w and 2w + 1 (lanes 0-31 and 32-63) and lane
+// h of a half takes rows 2h and 2h + 1 of its slice, so values and the row vectors move as 8-byte pairs: with
+// 4-byte values one row per lane moves half the bytes per load of the FP64 kernel, and this term is bound by
+// its loads in flight, not by HBM. Each row still sums its own slice's slots in slot order, padding included,
+// with the same operations as the one-row kernel, so every output has the same bits. Wavefronts whose two
+// slices differ in width, or that reach the matrix's last (possibly partial) slice, take the rows one at a
+// time with the lane's own slice data.
+__global__ __launch_bounds__(BLK) void k_neumann_pairs(NAMG_MAT_HEAD(float), const float *__restrict__ f,
+                                                       const float *__restrict__ scale, const float *acc,
+                                                       const float *__restrict__ in, float *out) {
+  const int32_t nrows = m_nrows;
+  const int32_t *__restrict__ dia = static_cast<const int32_t *>(m_idx);
+  const int32_t nslices = (nrows + SELL_C - 1) / SELL_C;
+  // wave-uniform (readfirstlane), so the slices' pointers and offsets come through the scalar unit
+  const int32_t sA = __builtin_amdgcn_readfirstlane(2 * (int32_t)(blockIdx.x * WAVES + (threadIdx.x >> 6)));
+  if (sA >= nslices) return;
+  const int32_t lane = threadIdx.x & 63;
+  const bool second = lane >= 32;
+  const int32_t r = (sA + (second ? 1 : 0)) * SELL_C + 2 * (lane & 31);
+  const int32_t cmax = dia[0];
+  const bool full = (sA + 2) * SELL_C <= nrows;  // both slices exist and hold 64 rows each
+  if (full) {
+    const int32_t pA = m_ptr[sA], pB = m_ptr[sA + 1], pE = m_ptr[sA + 2];
+    const int32_t w = (pB - pA) >> 6;
+    if (w == (pE - pB) >> 6) {
+      const int32_t p = second ? pB : pA;
+      const float2 fv = *reinterpret_cast<const float2 *>(f + r);
+      const float2 sc = scale ? *reinterpret_cast<const float2 *>(scale + r) : make_float2(1.f, 1.f);
+      const float2 av = acc ? *reinterpret_cast<const float2 *>(acc + r) : make_float2(0.f, 0.f);
+      const float *vp = m_val + p + 2 * (lane & 31);
+      const int32_t *offA = dia + 1 + (pA >> 6), *offB = dia + 1 + (pB >> 6);
+      float s0 = 0.f, s1 = 0.f;
+      int32_t j = 0;
+      for (; j + 8 <= w; j += 8) dia_pair_slots<8>(vp, offA, offB, second, in, r, cmax, j, s0, s1);
+      switch (w - j) {
+        case 7: dia_pair_slots<7>(vp, offA, offB, second, in, r, cmax, j, s0, s1); break;
+        case 6: dia_pair_slots<6>(vp, offA, offB, second, in, r, cmax, j, s0, s1); break;
+        case 5: dia_pair_slots<5>(vp, offA, offB, second, in, r, cmax, j, s0, s1); break;
+        case 4: dia_pair_slots<4>(vp, offA, offB, second, in, r, cmax, j, s0, s1); break;
+        case 3: dia_pair_slots<3>(vp, offA, offB, second, in, r, cmax, j, s0, s1); break;
+        case 2: dia_pair_slots<2>(vp, offA, offB, second, in, r, cmax, j, s0, s1); break;
+        case 1: dia_pair_slots<1>(vp, offA, offB, second, in, r, cmax, j, s0, s1); break;
+        default: break;
+      }
+      float v0 = fv.x - s0, v1 = fv.y - s1;
+      if (scale) {
+        v0 *= sc.x;
+        v1 *= sc.y;
+      }
+      if (acc) {
+        v0 += av.x;
+        v1 += av.y;
+      }
+      *reinterpret_cast<float2 *>(out + r) = make_float2(v0, v1);
+      return;
+    }
+  }
+  // the rows one at a time, each with its own slice's pointers and offsets
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int32_t row = r + q;
+    if (row >= nrows) continue;
+    const int32_t s = row >> 6;
+    const int32_t p0 = m_ptr[s], w = (m_ptr[s + 1] - p0) >> 6;
+    const float *vp = m_val + p0 + (row & 63);
+    const int32_t *off = dia + 1 + (p0 >> 6);
+    float sv = 0.f;
+    for (int32_t k = 0; k < w; ++k) sv = mul_add(vp[(int64_t)k * SELL_C], in[min(max(row + off[k], 0), cmax)], sv);
+    float v = f[row] - sv;
+    if (scale) v *= scale[row];
+    if (acc) v += acc[row];
+    out[row] = v;
+  }
+}
+
+// Blocks of k_neumann_pairs for nrows rows: two 64-row slices per wavefront.
+inline unsigned neumann_pairs_blocks(int32_t nrows) {
+  const int64_t nslices = ((int64_t)nrows + SELL_C - 1) / SELL_C;
+  return (unsigned)((nslices + 2 * WAVES - 1) / (2 * WAVES));
+}
+
 // A prolongation may be packed in the unit-row layout: its per-slice masks and counts (null for the plain
 // layout) complete the view, and prolong_body dispatches on them. The other row kernels never receive a
 // unit-row matrix (the host refuses to launch them on one).

@@ -299,6 +299,7 @@ void pack_device(DMat<T> &M, const DCsr &D, MemCounter *mc, int force_group, con
   M.unit = false;
   M.unit_pairs = false;
   M.dia = false;
+  M.pairs_ok = dia_pairs_enabled();
   M.nrows = D.nr;
   M.ncols = D.nc;
   M.nnz = D.nnz;

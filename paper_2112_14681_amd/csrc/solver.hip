@@ -837,6 +837,16 @@ class Solver final : public SolverBase {
                t.o0, t.o1, t.M.mul);
         break;
       case ROP_NEUMANN:
+        if constexpr (std::is_same<T, float>::value) {
+          // two rows per lane (8-byte pairs of every row vector; never with both scale and acc, so that the
+          // output expression is the one-row kernel's without a fused multiply-add to choose)
+          auto al8 = [](const void *p) { return ((uintptr_t)p & 7) == 0; };
+          if (t.M.pairs && !(t.c && t.d) && al8(t.a) && al8(t.c) && al8(t.d) && al8(t.o0)) {
+            launch(op.family, op.level, op.bytes, &k_neumann_pairs, neumann_pairs_blocks(t.M.nrows), s,
+                   NAMG_HEAD_ARGS(t.M), t.a, t.c, t.d, t.b, t.o0);
+            break;
+          }
+        }
         launch(op.family, op.level, op.bytes, sel_neumann<T>(op.group, t.M.unroll), op.grid, s, NAMG_HEAD_ARGS(t.M), t.a, t.c, t.d,
                t.b, t.o0, t.M.mul);
         break;

@@ -382,6 +382,37 @@ def test_solve_fp32_preconditioner(namg):
         assert relerr(x, ref["x"]) <= 1e-6
 
 
+def test_fp32_neumann_two_rows_per_lane(namg, monkeypatch):
+    """FP32 Neumann terms on square slice-diagonal triangles run with two rows per lane (k_neumann_pairs) unless
+    NAMG_DIA_PAIRS=0; the V-cycle and the solve are the same bit for bit either way, for ILU(0) and polynomial
+    GS, host- and device-packed, on sizes whose last pair of slices is partial or single (41^3: 1077 slices,
+    37^3: 792 slices, the last one partial)."""
+    import torch
+
+    cases = (("c2", 41, dict(smoother=1, inner_terms=3), dict(ilu_levels=1)),
+             ("c3", 37, dict(smoother=0, inner_terms=2), dict(ilu_levels=0)),
+             ("c2", 41, dict(smoother=1, inner_terms=3), dict(ilu_levels=1, coarsen=namg.COARSEN_PMIS, seed=2)))
+    for name, N, kw, setup in cases:
+        A, b, _ = config_system(name, N)
+        bt = dev(b)
+        out = []
+        for pairs in ("0", "1"):
+            monkeypatch.setenv("NAMG_DIA_PAIRS", pairs)
+            H = namg.Hierarchy(A, device=0, precision=namg.FP32_PRECOND, **setup)
+            monkeypatch.delenv("NAMG_DIA_PAIRS", raising=False)  # the layout keeps the choice made at setup
+            zt = torch.empty_like(bt)
+            H.vcycle(bt, zt, **kw)
+            xt = torch.zeros_like(bt)
+            st = H.solve(bt, xt, **kw)
+            torch.cuda.synchronize()
+            out.append((host(zt), host(xt), st["iters"], st["status"]))
+            H.close()
+        (z0, x0, i0, s0), (z1, x1, i1, s1) = out
+        assert s0 == s1 == namg.OK, (name, N, setup)
+        assert np.array_equal(z0, z1), (name, N, setup)
+        assert np.array_equal(x0, x1) and i0 == i1, (name, N, setup)
+
+
 def test_restart_x0_and_not_converged(namg):
     A, b, _ = config_system("c1")
     H, G = namg.Hierarchy(A, device=0), O.Hierarchy(A)

@@ -252,6 +252,50 @@ def replay_dia_exact(L, x):
     return acc, a
 
 
+def replay_dia_pairs(L, x):
+    """k_neumann_pairs's row sums (FP32 square slice-diagonal triangles, two rows per lane): a wavefront takes
+    slices 2w and 2w + 1 (lanes 0-31 and 32-63) and lane h of a half rows 2h and 2h + 1 of its slice. When both
+    slices hold 64 rows and have the same width, slot k's two values are one 8-byte read at ptr + 64 k + 2h
+    and the two gathers one 8-byte read at the pair's first column clamped into [0, cmax - 1], from which a
+    select gives x[clamp(r + o)] and x[clamp(r + 1 + o)]; otherwise each row runs alone on its own slice's
+    pointers and offsets. Every row sums its slice's slots in slot order, padding included."""
+    a = DiaAccess(L)
+    n, nsl = L.nrows, len(L.ptr) - 1
+    cmax = int(a.offset(np.array([0]))[0])
+    acc = np.zeros(n)
+    for sA in range(0, nsl, 2):
+        if (sA + 2) * SELL_C <= n and (int(L.ptr[sA + 1]) - int(L.ptr[sA])) == (int(L.ptr[sA + 2]) - int(L.ptr[sA + 1])):
+            w = (int(L.ptr[sA + 1]) - int(L.ptr[sA])) >> 6
+            for s in (sA, sA + 1):
+                p = int(L.ptr[s])
+                h = np.arange(32, dtype=np.int64)
+                r = s * SELL_C + 2 * h
+                s0, s1 = np.zeros(32), np.zeros(32)
+                for j, k in _dia_exact_chunks(w):
+                    for u in range(k):
+                        o = int(a.offset(np.array([1 + (p >> 6) + j + u]))[0])
+                        vi = p + (j + u) * SELL_C + 2 * h
+                        v0, v1 = a.value(vi), a.value(vi + 1)
+                        c = r + o
+                        cc = np.clip(c, 0, cmax - 1)
+                        g0, g1 = a.gather(x, cc), a.gather(x, cc + 1)
+                        s0 = s0 + v0 * np.where(c >= cmax, g1, g0)
+                        s1 = s1 + v1 * np.where(c < 0, g0, g1)
+                acc[r], acc[r + 1] = s0, s1
+        else:
+            for row in range(sA * SELL_C, min(n, (sA + 2) * SELL_C)):
+                s = row >> 6
+                p0 = int(L.ptr[s])
+                w = (int(L.ptr[s + 1]) - p0) >> 6
+                t = 0.0
+                for k in range(w):
+                    o = int(a.offset(np.array([1 + (p0 >> 6) + k]))[0])
+                    t = t + float(a.value(np.array([p0 + k * SELL_C + (row & 63)]))[0]) * float(
+                        a.gather(x, np.array([min(max(row + o, 0), cmax)]))[0])
+                acc[row] = t
+    return acc, a
+
+
 def replay_prolong_unit_rows(L, e, U=U):
     """prolong_unit_rows's loads and gathers, row by row (a thread's second row, in FP32, runs the same index
     stream): an F row walks its slots in chunks of U (4, or 8 where F rows average more than four entries);
@@ -507,7 +551,7 @@ def _systems():
 def test_row_kernel_accesses_in_range(namg, case):
     name, A = list(_systems())[case]
     rng = np.random.default_rng(case)
-    dia_used = set()
+    dia_used, pairs_used = set(), set()
     for label, rp, ci, v, ncols, fg, cf in hierarchy_operators(namg, A):
         L = Layout(np.asarray(rp), np.asarray(ci), np.asarray(v), ncols, fg)
         x = rng.standard_normal(ncols)
@@ -553,12 +597,18 @@ def test_row_kernel_accesses_in_range(namg, case):
                 ye, ae = replay_dia_exact(D, x)
                 assert ae.clean(), (name, label, "slice-diagonal exact chunks, one row", ae.bad)
                 assert np.array_equal(ye, y), (name, label, "exact")  # the plain layout's bits (up to the sign of 0)
+                if vb == 4 and ncols == len(rp) - 1 and ncols >= 2:  # FP32 square: the two-rows-per-lane kernel
+                    yp, ap = replay_dia_pairs(D, x)
+                    assert ap.clean(), (name, label, "slice-diagonal, two rows per lane", ap.bad)
+                    assert np.array_equal(yp, ye), (name, label, "two rows per lane")
+                    pairs_used.add(label)
     # the natural-order stencils take the form on level 0 (A, its strict parts, its FP64 copy); a random
     # relabelling scatters the offsets and keeps SELL-64
     if name.startswith("permuted"):
         assert not any(lbl.startswith("A0") for lbl in dia_used), dia_used
     else:
         assert {"A0", "A0 fp64", "A0 lower", "A0 upper"} <= dia_used, dia_used
+        assert {"A0 lower", "A0 upper"} <= pairs_used, pairs_used
 
 
 def test_unit_layout_needs_its_masks():
