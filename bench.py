@@ -66,9 +66,10 @@ PROFILE_EVERY = 3  # time every 3rd run of consecutive dominant-kernel dispatche
 # odd, so pre- and post-smoothing runs alternate in the sample)
 
 # Measured HBM traffic of the dominant kernel (bytes per launch): rocprofv3 FETCH_SIZE x 2.000 plus
-# WRITE_SIZE x 1.000, factors from a 2 GiB copy (profiles/k_neumann_level0_c2_128cubed_traffic.md).
+# WRITE_SIZE x 1.000, factors from a 2 GiB copy (profiles/k_neumann_level0_c2_128cubed_traffic.md for FP64,
+# profiles/hbm_traffic_c2_128cubed_kernels.md for both; in FP32 the term runs as k_neumann_pairs).
 # Valid for the kernel version it was taken on; None when the kernel has changed since.
-DOMINANT_TRAFFIC_BYTES = {("c2", 128, "fp64", "ilu0"): 109.79e6, ("c2", 128, "fp32", "ilu0"): None}
+DOMINANT_TRAFFIC_BYTES = {("c2", 128, "fp64", "ilu0"): 109.79e6, ("c2", 128, "fp32", "ilu0"): 53.37e6}
 
 
 def copy_ceiling(torch, nbytes=2 << 30, reps=10):
