@@ -628,19 +628,6 @@ inline bool unit_pairs_for(int64_t nrows, int64_t explicit_rows) {
   return nrows >= (int64_t(1) << 19) && 32 * explicit_rows <= 17 * nrows;
 }
 
-// Flag in MatView::unroll of a unit-row prolongation whose kernel takes the same lane of two adjacent slices
-// per thread (TwoSliceRows), for a large level that does not take the pair form: one lane per row leaves the
-// loads of a thread's one short row (a slice's mask and counts, its entries, their gathers) waiting on each
-// other with half the wavefronts of the level queued behind the resident ones.
-constexpr int UNIT_ROWS2 = 32;
-inline bool unit_rows2_for(int64_t nrows, bool pairs) {
-  static const int64_t min_rows = [] {
-    const char *e = std::getenv("NAMG_UNIT_ROWS2_MIN");
-    return e ? std::max<int64_t>(1, std::atoll(e)) : int64_t(1) << 19;
-  }();
-  return !pairs && nrows >= min_rows;
-}
-
 // Per-slice (C points before the slice, explicit rows in it) pairs of the unit-row layout.
 inline std::vector<int32_t> unit_meta(const UnitRows &u) {
   std::vector<int32_t> m(2 * std::max<size_t>(u.mask.size(), 1), 0);
@@ -659,7 +646,6 @@ struct DMat {
   bool narrow = false;
   bool unit = false;  // the unit-row SELL layout (prolongations, see UnitRows)
   bool unit_pairs = false;  // its kernel in the pair form (unit_pairs_for)
-  bool unit_rows2 = false;  // its kernel with two slices per thread (unit_rows2_for)
   bool dia = false;   // the slice-diagonal SELL layout (see LayoutCount)
   bool pairs_ok = false;  // dia_pairs_enabled() when the matrix was laid out
   int unroll = 4;     // entries per chunk of the row kernels (choose_unroll; unit-row layout: see view())
@@ -683,7 +669,7 @@ struct DMat {
     v.ncols = ncols;
     v.unroll = unit ? (layout_tuning().unit_unroll ? layout_tuning().unit_unroll
                                                    : (explicit_nnz > 4 * explicit_rows ? 8 : 4)) |
-                          (unit_pairs ? UNIT_PAIRS : 0) | (unit_rows2 ? UNIT_ROWS2 : 0)
+                          (unit_pairs ? UNIT_PAIRS : 0)
                     : unroll;
     // two rows per lane for FP32 square slice-diagonal matrices (k_neumann_pairs)
     const int64_t nslices = ((int64_t)nrows + SELL_C - 1) / SELL_C;
@@ -714,7 +700,6 @@ struct DMat {
     unroll = choose_unroll(group, nrows, nnz);
     unit = false;
     unit_pairs = false;
-    unit_rows2 = false;
     dia = false;
     pairs_ok = dia_pairs_enabled();
     if (unit_cf && group == 1) {
@@ -850,7 +835,6 @@ struct DMat {
     explicit_rows = 0;
     for (int32_t c : u.count) explicit_rows += c;
     unit_pairs = unit_pairs_for(nrows, explicit_rows);
-    unit_rows2 = unit_rows2_for(nrows, unit_pairs);
     std::vector<T> hval(stored);
     std::vector<int32_t> hcol;
     std::vector<int16_t> h16;

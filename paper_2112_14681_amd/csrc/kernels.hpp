@@ -196,24 +196,6 @@ struct ThreadRows {
   }
 };
 
-// The rows of a thread of the unit-row prolongation in its two-slice form (UNIT_ROWS2): wavefront w of the
-// grid takes slices 2w and 2w + 1 and lane l rows 64 (2w) + l and 64 (2w + 1) + l, so a large level runs
-// half as many wavefronts, each with two independent chains of loads in flight.
-struct TwoSliceRows {
-  static constexpr int R = 2;
-  int32_t row[R];
-  bool ok[R];
-  int sub = 0;
-  __device__ __forceinline__ TwoSliceRows(uint32_t lb, int32_t nrows) {
-    const int64_t s0 = 2 * ((int64_t)lb * WAVES + (threadIdx.x >> 6));
-    const int64_t r0 = s0 * SELL_C + (threadIdx.x & 63);
-    row[0] = (int32_t)min(r0, (int64_t)INT32_MAX);
-    row[1] = (int32_t)min(r0 + SELL_C, (int64_t)INT32_MAX);
-    ok[0] = r0 < nrows;
-    ok[1] = r0 + SELL_C < nrows;
-  }
-};
-
 // Blocks of a row kernel over nrows rows with `group` lanes per row.
 inline unsigned row_blocks(int64_t nrows, int group) { return blocks_for(nrows * group); }
 
@@ -314,9 +296,10 @@ __device__ __forceinline__ void neumann_body(uint32_t lb, const MatView<T> &S, c
 // go through one loop: entries in chunks of U, every index and value load of a chunk issued before its
 // gathers, as in row_dot; a slot past its row's end loads an in-bounds entry, gathers a valid column and is
 // not added.
-template <bool NARROW, int U, class T, class TR>
-__device__ __forceinline__ void prolong_unit_rows(const MatView<T> &P, const T *__restrict__ e, T *x, const TR &t) {
-  constexpr int R = TR::R;
+template <bool NARROW, int U, class T>
+__device__ __forceinline__ void prolong_unit_rows(const MatView<T> &P, const T *__restrict__ e, T *x,
+                                                  const ThreadRows<1, T> &t) {
+  constexpr int R = ThreadRows<1, T>::R;
   int32_t k[R], lim[R], end[R], m[R], cu[R], base[R];
   bool virt[R];
   T xv[R], acc[R];
@@ -502,23 +485,7 @@ __device__ __forceinline__ void prolong_body(uint32_t lb, const MatView<T> &P, c
       // chunks of eight when the F rows average more than four entries (one dependent round instead of two
       // for the six-entry rows of a stencil's P); UNIT_PAIRS: the kernel of a wavefront per pair of slices
       // (DMat::unit_pairs), whose every thread reaches the kernel's barrier
-      const int chunk = P.unroll & ~(UNIT_PAIRS | UNIT_ROWS2);
-      if (P.unroll & UNIT_ROWS2) {
-        const TwoSliceRows t(lb, P.nrows);
-        if (!t.ok[0]) return;
-        if (chunk == 8) {
-          if (P.col16)
-            prolong_unit_rows<true, 8>(P, e, x, t);
-          else
-            prolong_unit_rows<false, 8>(P, e, x, t);
-        } else {
-          if (P.col16)
-            prolong_unit_rows<true, 4>(P, e, x, t);
-          else
-            prolong_unit_rows<false, 4>(P, e, x, t);
-        }
-        return;
-      }
+      const int chunk = P.unroll & ~UNIT_PAIRS;
       if (P.unroll & UNIT_PAIRS) {
         if (chunk == 8) {
           if (P.col16)

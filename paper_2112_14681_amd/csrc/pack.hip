@@ -275,7 +275,6 @@ void pack_unit_device(DMat<T> &M, const DCsr &D, const UnitRows &u, MemCounter *
   M.explicit_rows = 0;
   for (int32_t c : u.count) M.explicit_rows += c;
   M.unit_pairs = unit_pairs_for(M.nrows, M.explicit_rows);
-  M.unit_rows2 = unit_rows2_for(M.nrows, M.unit_pairs);
   M.ptr.alloc(u.ptr.size(), mc);
   M.ptr.upload(u.ptr.data(), u.ptr.size());
   M.umask.alloc(std::max<size_t>(u.mask.size(), 1), mc);
@@ -299,7 +298,6 @@ template <class T>
 void pack_device(DMat<T> &M, const DCsr &D, MemCounter *mc, int force_group, const UnitRows *unit, bool allow_dia) {
   M.unit = false;
   M.unit_pairs = false;
-  M.unit_rows2 = false;
   M.dia = false;
   M.pairs_ok = dia_pairs_enabled();
   M.nrows = D.nr;

@@ -131,7 +131,6 @@ int32_t mat_form(const MatView<T> &M) {
 template <class T>
 unsigned rows_grid(const DMat<T> &M) {
   if (M.unit && M.unit_pairs) return (unsigned)((M.nrows + UNIT_BLOCK_ROWS - 1) / UNIT_BLOCK_ROWS);
-  if (M.unit && M.unit_rows2) return (unsigned)((M.nrows + 2 * BLK - 1) / (2 * BLK));  // two slices per wavefront
   return row_blocks(M.nrows, M.group);
 }
 }  // namespace

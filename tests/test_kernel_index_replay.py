@@ -348,48 +348,6 @@ def replay_prolong_unit_rows(L, e, U=U):
     return acc, a
 
 
-def replay_prolong_tail_lanes(L, U=U):
-    """With two slices per thread (TwoSliceRows) the lanes whose second row lies past the matrix's end, in a
-    last slice that other lanes of the wavefront still own, run that slice's loop without adding anything:
-    no mask bit (an F row's cursor at rank lane - below), end = the slice's start, and each round's loads
-    clamped into the slice (or to the stored arrays' first entry) as long as any lane of the wavefront has
-    slots left. Returns the access record of those loads."""
-    a = Access(L)
-    n = L.nrows
-    if n % SELL_C == 0:
-        return a
-    s = n >> 6
-    bits = L.mask_bits[s]
-    assert not bits[n & 63:].any()  # rows past the end are no C points
-    lanes = np.arange(n & 63, SELL_C, dtype=np.int64)
-    below = np.cumsum(bits)[lanes] - bits[lanes]
-    m = max(int(L.count[s]), 1)
-    p0, lim = int(L.ptr[s]), int(L.ptr[s + 1])
-    k = p0 + lanes - below
-    # the wavefront loops while a valid row of the slice has slots left: at most its widest F row's rounds
-    rounds = -(-((lim - p0) // m) // U) + 1 if lim > p0 else 1
-    for _ in range(rounds):
-        kb = np.where(k < lim, k, lim - 1 if lim > 0 else 0)
-        for q in range(U):
-            a.load(np.where(k + q * m < lim, k + q * m, kb))
-        k = k + U * m
-    return a
-
-
-def test_two_slice_rows_cover_each_row_once():
-    """TwoSliceRows with the grid rows_grid gives it (blocks of 2 * 256 rows): wavefront w of block b takes
-    slices 2 (4 b + w) and 2 (4 b + w) + 1; every row of any size is taken by exactly one lane."""
-    for n in (1, 63, 64, 65, 511, 512, 513, 1000, 4097):
-        seen = np.zeros(n, np.int64)
-        for b in range((n + 2 * BLK - 1) // (2 * BLK)):
-            for t in range(BLK):
-                s0 = 2 * (b * (BLK // 64) + t // 64)
-                for r in (s0 * SELL_C + t % 64, (s0 + 1) * SELL_C + t % 64):
-                    if r < n:
-                        seen[r] += 1
-        assert np.all(seen == 1), n
-
-
 def replay_prolong_unit_pairs(L, e, U=U):
     """prolong_unit_pairs, wavefront by wavefront: a wavefront takes slices 2w and 2w + 1; its lanes take the
     pair's F rows (slice 2w's in rank order, then slice 2w + 1's), 64 at a time, then its C points' rows the
@@ -620,8 +578,6 @@ def test_row_kernel_accesses_in_range(namg, case):
                 assert accp.bad_table == 0 and accp.bad_rows == 0, (name, label, "unit pairs", unroll,
                                                                     accp.bad_table, accp.bad_rows)
                 assert np.array_equal(yp, yu), (name, label, "pairs", unroll)
-                at = replay_prolong_tail_lanes(Lu, unroll)
-                assert at.bad_loads == 0, (name, label, "two slices per thread, lanes past the end", unroll)
                 ref = sp.csr_matrix((v, ci, rp), shape=(len(rp) - 1, ncols)) @ x
                 np.testing.assert_allclose(yu, ref, rtol=1e-14, atol=1e-14)
                 assert np.array_equal(yu, y), (name, label, unroll)  # entry order kept: the plain layout's bits
