@@ -423,6 +423,23 @@ __device__ __forceinline__ void prolong_unit_pairs(uint32_t lb, const MatView<T>
   }
   __syncthreads();
   const int32_t row0 = s0 * SELL_C;
+  // C points' rows (at most two passes of 64: a pair has at most 128): their loads go out first, ahead of the
+  // F rows' chains (a C row's x and e are no F row's, so the order of their loads and the F rows' stores does
+  // not matter); their stores come last
+  const int32_t ncp = nc[0] + nc[1];
+  int32_t crow[2];
+  T cev[2], cxv[2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int32_t c = r * SELL_C + lane;
+    crow[r] = -1;
+    if (c < ncp) {
+      const int32_t col = c >= nc[0] ? before[1] + (c - nc[0]) : before[0] + c;
+      crow[r] = row0 + (int32_t)tab[wave][1][c];
+      cev[r] = e[col];
+      cxv[r] = x[crow[r]];
+    }
+  }
   // F rows
   const int32_t nf = m[0] + m[1];
   const int32_t wmax = max(m[0] > 0 ? w[0] : 0, m[1] > 0 ? w[1] : 0);
@@ -456,21 +473,6 @@ __device__ __forceinline__ void prolong_unit_pairs(uint32_t lb, const MatView<T>
       for (int u = 0; u < U; ++u) acc = mul_add(v[u], ev[u], acc);
     }
     if (act) x[row] = xv + acc;
-  }
-  // C points' rows: at most two passes of 64 (a pair has at most 128), both passes' loads issued first
-  const int32_t ncp = nc[0] + nc[1];
-  int32_t crow[2];
-  T cev[2], cxv[2];
-#pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int32_t c = r * SELL_C + lane;
-    crow[r] = -1;
-    if (c < ncp) {
-      const int32_t col = c >= nc[0] ? before[1] + (c - nc[0]) : before[0] + c;
-      crow[r] = row0 + (int32_t)tab[wave][1][c];
-      cev[r] = e[col];
-      cxv[r] = x[crow[r]];
-    }
   }
 #pragma unroll
   for (int r = 0; r < 2; ++r)
